@@ -1,0 +1,206 @@
+"""ctypes front-end of the FP64 oracle (``oracle.c``).
+
+TEST INFRASTRUCTURE ONLY -- see the package docstring.  State lives in numpy arrays
+owned by the caller, so a run can be continued, inspected step by step, or saved.
+
+Each class follows the step order of the paper's coupled model (section 5.2):
+H update -> F1 update driven by E^n -> current moment J -> E update (Ampere's
+law with -J, eq. (1)) -> absorbing boundary -> soft source at t^{n+1}.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from .build import LIB, build
+
+_lib = None
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        L.oracle_vgrid.argtypes = [C.c_int, C.c_double, C.c_double, _dp, _dp, _dp, _dp, _dp]
+        L.oracle_nu_shape.argtypes = [C.c_int, C.c_int, _dp, _dp, C.c_double, C.c_int, _dp]
+        L.oracle_collision1v.argtypes = [C.c_int, _dp, _dp, _dp]
+        L.oracle_constants.argtypes = [_dp]
+        L.oracle_cpml_profile.argtypes = [C.c_int, C.c_int] + [C.c_double] * 7 + [_dp] * 6
+        L.oracle_run1d.argtypes = (
+            [C.c_int, C.c_double, C.c_double, C.c_int,
+             C.c_int, C.c_double, C.c_double, C.c_int,
+             _dp, _dp,
+             C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
+             C.c_longlong, C.c_longlong,
+             _dp, _dp, _dp, _dp,
+             C.c_int, _ip, _dp, C.c_int, _dp])
+        L.oracle_run2d.argtypes = (
+            [C.c_int, C.c_int, C.c_double, C.c_double,
+             C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
+             C.c_int, C.c_double, C.c_double, C.c_int,
+             _dp, _dp,
+             C.c_int, C.c_int, C.c_int,
+             C.c_double, C.c_double, C.c_double, C.c_double,
+             C.c_longlong, C.c_longlong,
+             _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+             C.c_int, _ip, _dp])
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    assert a.flags["C_CONTIGUOUS"]
+    if a.dtype == np.float64:
+        return a.ctypes.data_as(_dp)
+    if a.dtype == np.int32:
+        return a.ctypes.data_as(_ip)
+    raise TypeError(a.dtype)
+
+
+def constants():
+    out = np.zeros(4)
+    lib().oracle_constants(_p(out))
+    return dict(c=out[0], eps0=out[1], e=out[2], me=out[3])
+
+
+def vgrid(nv, vmax_over_vth, te_ev):
+    """Velocity grid and Maxwellian tables (see ``oracle_vgrid``)."""
+    v, fh, gh = np.zeros(nv), np.zeros(nv), np.zeros(nv)
+    dv, vth = C.c_double(), C.c_double()
+    rc = lib().oracle_vgrid(nv, vmax_over_vth, te_ev, _p(v), _p(fh), _p(gh), C.byref(dv), C.byref(vth))
+    if rc:
+        raise ValueError("bad velocity grid")
+    return v, fh, gh, dv.value, vth.value
+
+
+def nu_shape(dims, nv, vmax_over_vth, te_ev, model):
+    v, fh, gh, dv, vth = vgrid(nv, vmax_over_vth, te_ev)
+    s = np.zeros(nv if dims == 1 else nv * nv)
+    lib().oracle_nu_shape(dims, nv, _p(v), _p(fh), dv, model, _p(s))
+    return s
+
+
+def collision1v(nu, f):
+    nu = np.ascontiguousarray(nu, dtype=np.float64)
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.zeros_like(f)
+    lib().oracle_collision1v(len(f), _p(nu), _p(f), _p(out))
+    return out
+
+
+def cpml_profile(n, ncpml, dx, dt, order=3.0, sigma_factor=1.0, kappa_max=5.0,
+                 alpha_min=0.0, alpha_max=0.05):
+    be, ae, ke = np.zeros(n + 1), np.zeros(n + 1), np.zeros(n + 1)
+    bh, ah, kh = np.zeros(n), np.zeros(n), np.zeros(n)
+    lib().oracle_cpml_profile(n, ncpml, dx, dt, order, sigma_factor, kappa_max, alpha_min,
+                              alpha_max, _p(be), _p(ae), _p(ke), _p(bh), _p(ah), _p(kh))
+    return dict(be=be, ae=ae, ke=ke, bh=bh, ah=ah, kh=kh)
+
+
+class Oracle1D:
+    """1D (Ez, Hy) Yee grid coupled to a 1V kinetic F1 in every plasma node.
+
+    ``ne``/``nubar`` are per E node (nx+1 values).  ``bc`` is ``"mur"`` or ``"pec"``.
+    """
+
+    def __init__(self, nx, dx, courant, ne, nubar, nv=64, vmax_over_vth=6.0, te_ev=2.0,
+                 nu_model="hard_sphere", bc="mur", src_node=0, src_amp=0.0, src_f=0.0,
+                 src_tau=1.0, src_t0=0.0):
+        self.nx, self.dx, self.courant = int(nx), float(dx), float(courant)
+        self.ne = np.ascontiguousarray(ne, dtype=np.float64)
+        self.nubar = np.ascontiguousarray(nubar, dtype=np.float64)
+        assert self.ne.shape == (nx + 1,) and self.nubar.shape == (nx + 1,)
+        self.nv, self.vmax, self.te = int(nv), float(vmax_over_vth), float(te_ev)
+        self.nu_model = {"hard_sphere": 0, "const": 1}[nu_model]
+        self.bc = {"pec": 0, "mur": 1}[bc]
+        self.src = (int(src_node), float(src_amp), float(src_f), float(src_tau), float(src_t0))
+        self.cells = np.nonzero(self.ne > 0)[0].astype(np.int32)
+        self.E = np.zeros(nx + 1)
+        self.H = np.zeros(nx)
+        self.J = np.zeros(nx + 1)
+        self.df = np.zeros(len(self.cells) * self.nv)
+        self.step = 0
+        self.dt = self.courant * self.dx / constants()["c"]
+
+    def run(self, nsteps, probes=(), snap_every=0):
+        probes = np.ascontiguousarray(probes, dtype=np.int32)
+        pout = np.zeros(max(1, nsteps * len(probes)))
+        nsnap = nsteps // snap_every if snap_every > 0 else 0
+        sout = np.zeros(max(1, nsnap * (self.nx + 1)))
+        rc = lib().oracle_run1d(
+            self.nx, self.dx, self.courant, self.bc,
+            self.nv, self.vmax, self.te, self.nu_model,
+            _p(self.ne), _p(self.nubar),
+            *self.src,
+            self.step, int(nsteps),
+            _p(self.E), _p(self.H), _p(self.J), _p(self.df),
+            len(probes), _p(probes) if len(probes) else None, _p(pout),
+            int(snap_every), _p(sout))
+        if rc:
+            raise ValueError("oracle_run1d rejected its arguments")
+        self.step += int(nsteps)
+        return (pout[: nsteps * len(probes)].reshape(nsteps, len(probes)),
+                sout[: nsnap * (self.nx + 1)].reshape(nsnap, self.nx + 1))
+
+    def df_rows(self):
+        return self.df.reshape(len(self.cells), self.nv)
+
+
+class Oracle2D:
+    """2D TEz (Ex, Ey, Hz) Yee grid with CPML and a 2V kinetic F1 per plasma cell.
+
+    ``ne``/``nubar`` are per cell, shape (ny, nx).  ``src_kind``: 0 none, 1 Ey line at
+    column ``src_i``, 2 Ey point at (src_i, src_j).
+    """
+
+    def __init__(self, nx, ny, dx, courant, ne, nubar, nv=32, vmax_over_vth=6.0, te_ev=5.0,
+                 nu_model="hard_sphere", ncpml=8, cpml_order=3.0, sigma_factor=1.0,
+                 kappa_max=5.0, alpha_min=0.0, alpha_max=0.05,
+                 src_kind=0, src_i=0, src_j=0, src_amp=0.0, src_f=0.0, src_tau=1.0, src_t0=0.0):
+        self.nx, self.ny, self.dx, self.courant = int(nx), int(ny), float(dx), float(courant)
+        self.ne = np.ascontiguousarray(ne, dtype=np.float64).reshape(-1)
+        self.nubar = np.ascontiguousarray(nubar, dtype=np.float64).reshape(-1)
+        assert self.ne.shape == (nx * ny,)
+        self.nv, self.vmax, self.te = int(nv), float(vmax_over_vth), float(te_ev)
+        self.nu_model = {"hard_sphere": 0, "const": 1}[nu_model]
+        self.cpml = (int(ncpml), float(cpml_order), float(sigma_factor), float(kappa_max),
+                     float(alpha_min), float(alpha_max))
+        self.src = (int(src_kind), int(src_i), int(src_j), float(src_amp), float(src_f),
+                    float(src_tau), float(src_t0))
+        self.cells = np.nonzero(self.ne > 0)[0].astype(np.int32)
+        self.Ex = np.zeros((ny + 1, nx))
+        self.Ey = np.zeros((ny, nx + 1))
+        self.Hz = np.zeros((ny, nx))
+        self.Jx = np.zeros((ny + 1, nx))
+        self.Jy = np.zeros((ny, nx + 1))
+        self.psi = np.zeros(self.Ex.size + self.Ey.size + 2 * self.Hz.size)
+        self.df = np.zeros(len(self.cells) * self.nv * self.nv)
+        self.step = 0
+        self.dt = self.courant * self.dx / constants()["c"]
+
+    def run(self, nsteps, probes=()):
+        """``probes`` are (i, j) Ey indices; returns Ey at them after every step."""
+        idx = np.ascontiguousarray([j * (self.nx + 1) + i for (i, j) in probes], dtype=np.int32)
+        pout = np.zeros(max(1, nsteps * len(idx)))
+        rc = lib().oracle_run2d(
+            self.nx, self.ny, self.dx, self.courant, *self.cpml,
+            self.nv, self.vmax, self.te, self.nu_model,
+            _p(self.ne), _p(self.nubar), *self.src,
+            self.step, int(nsteps),
+            _p(self.Ex), _p(self.Ey), _p(self.Hz), _p(self.Jx), _p(self.Jy),
+            _p(self.psi), _p(self.df),
+            len(idx), _p(idx) if len(idx) else None, _p(pout))
+        if rc:
+            raise ValueError("oracle_run2d rejected its arguments")
+        self.step += int(nsteps)
+        return pout[: nsteps * len(idx)].reshape(nsteps, len(idx))
+
+    def df_cells(self):
+        return self.df.reshape(len(self.cells), self.nv, self.nv)

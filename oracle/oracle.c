@@ -1,0 +1,424 @@
+/*
+ * oracle.c -- plain FP64 CPU oracle of the coupled Yee-FDTD / two-term kinetic
+ * plasma model of Dodge, Shafiee & Shokri (arXiv 2211.05647).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path links, loads or calls
+ * this file; only the test-suite, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no code, header, table or constant with the
+ * HIP library: it builds its own velocity tables, collision frequencies, CPML
+ * profiles and source samples from the paper's definitions, in double
+ * precision, on the FULL signed velocity grid (the GPU path stores only half
+ * of it).  It is deliberately unblocked and unfused: every step is written in
+ * the order the method states it, so that it can be checked against the paper
+ * by eye.  OpenMP only splits independent loop iterations.
+ *
+ * Readings of the paper taken here (the paper is silent or garbled):
+ *   - Ampere's law subtracts J (Maxwell's equations, eq. (1), second line);
+ *     the printed C_J coefficient has no sign, we use -dt/eps0 * J.
+ *   - electrons carry charge -e with e > 0; the F1 equation of the numerical
+ *     model (section 5.2) is used as printed: dF1/dt - (e/m) E dF0/dv = -nu F1.
+ *   - order inside one step: H -> F1 (driven by E^n) -> J -> E -> boundary ->
+ *     soft source (the flowchart figure is missing; the F1 update's factor 2*E
+ *     puts F1 and J on half-integer time levels, which the E update needs).
+ *   - F0 is a Maxwellian at T_e (the workloads fix it), normalised on the
+ *     discrete grid; dF0/dv is the analytic derivative -v F0 / v_th^2.
+ *   - v_th = sqrt(e T_e / m_e); bins are cell-centred and symmetric,
+ *     v_j = (j - (Nv-1)/2) dv, dv = 2 vmax / Nv, with no v = 0 bin.
+ *   - the 1V (2V) Cartesian analogue of the current moment of section 5.2 is
+ *     J = -e dv sum_j v_j f_j  (J = -e dv^2 sum_ab v_ab f_ab).
+ *   - collision frequency nu(v) = N s v with the constant N s fixed so that
+ *     the Maxwellian mean of nu equals the prescribed mean frequency
+ *     ("hard sphere"), or nu = const (the test mode).
+ *   - CPML (section 2, eq. (4) and the b, a, sigma_max, alpha formulas):
+ *     psi at the new level is b * psi(old) + a * (field difference); kappa is
+ *     graded like sigma with the same power; E-side profiles are sampled at
+ *     integer depth, H-side at half-cell depth; the outer wall is PEC.
+ *   - 2D TEz: F1 lives at plasma cell centres; E is averaged from the two
+ *     bounding edges to the centre and J is averaged back to each edge with
+ *     the transposed weights, so field-to-plasma work is exchanged exactly.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include <stdint.h>
+
+/* CODATA 2018 */
+static const double K_C0 = 299792458.0;
+static const double K_EPS0 = 8.8541878128e-12;
+static const double K_QE = 1.602176634e-19;
+static const double K_ME = 9.1093837015e-31;
+static const double K_PI = 3.14159265358979323846;
+
+static double k_mu0(void) { return 1.0 / (K_EPS0 * K_C0 * K_C0); }
+
+int oracle_constants(double *out4)
+{
+    out4[0] = K_C0; out4[1] = K_EPS0; out4[2] = K_QE; out4[3] = K_ME;
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Velocity grid and the frozen isotropic part F0 (section 5.2: F0 is held
+ * fixed, F1 starts at zero).  Maxwellian at T_e, discretely normalised so that
+ * sum_j fhat_j dv = 1; ghat_j = dfhat/dv = -v_j fhat_j / v_th^2.
+ * ------------------------------------------------------------------------- */
+int oracle_vgrid(int nv, double vmax_over_vth, double te_ev,
+                 double *v, double *fhat, double *ghat,
+                 double *dv_out, double *vth_out)
+{
+    if (nv < 2 || (nv % 2) != 0 || te_ev <= 0.0 || vmax_over_vth <= 0.0)
+        return -1;
+    double vth = sqrt(K_QE * te_ev / K_ME);
+    double dv = 2.0 * vmax_over_vth * vth / (double)nv;
+    double norm = 0.0;
+    for (int j = 0; j < nv; ++j) {
+        v[j] = ((double)j - 0.5 * (double)(nv - 1)) * dv;
+        fhat[j] = exp(-v[j] * v[j] / (2.0 * vth * vth));
+        norm += fhat[j] * dv;
+    }
+    for (int j = 0; j < nv; ++j) {
+        fhat[j] = fhat[j] / norm;
+        ghat[j] = -v[j] * fhat[j] / (vth * vth);
+    }
+    *dv_out = dv;
+    *vth_out = vth;
+    return 0;
+}
+
+/* Collision-frequency shape s_j with nu_j = nubar * s_j (section 5.2,
+ * nu(v) = N s v).  model 0: hard sphere, s_j = |v_j| / <|v|>; model 1: const.
+ * dims = 1 uses |v_j|; dims = 2 uses |(vx_a, vy_b)| over the nv*nv grid. */
+int oracle_nu_shape(int dims, int nv, const double *v, const double *fhat,
+                    double dv, int model, double *s)
+{
+    if (dims == 1) {
+        double mean = 0.0;
+        for (int j = 0; j < nv; ++j) mean += fabs(v[j]) * fhat[j] * dv;
+        for (int j = 0; j < nv; ++j) s[j] = (model == 0) ? fabs(v[j]) / mean : 1.0;
+        return 0;
+    }
+    if (dims == 2) {
+        double mean = 0.0;
+        for (int a = 0; a < nv; ++a)
+            for (int b = 0; b < nv; ++b)
+                mean += sqrt(v[a] * v[a] + v[b] * v[b]) * fhat[a] * fhat[b] * dv * dv;
+        for (int a = 0; a < nv; ++a)
+            for (int b = 0; b < nv; ++b)
+                s[a * nv + b] = (model == 0)
+                    ? sqrt(v[a] * v[a] + v[b] * v[b]) / mean : 1.0;
+        return 0;
+    }
+    return -1;
+}
+
+/* Elastic collision operator acting on an arbitrary distribution sampled on
+ * the signed 1V grid, in mirror form: C(f)_j = -(nu_j / 2) (f_j - f_{mirror j}).
+ * Elastic scattering only randomises direction (section 5.1: only elastic
+ * collisions), so the isotropic part is untouched and, for the odd part, this
+ * reduces to -nu_j f_j, the right-hand side of the F1 equation. */
+int oracle_collision1v(int nv, const double *nu, const double *f, double *out)
+{
+    for (int j = 0; j < nv; ++j)
+        out[j] = -0.5 * nu[j] * (f[j] - f[nv - 1 - j]);
+    return 0;
+}
+
+/* Gaussian-modulated sine (section 5.2 table): A sin(2 pi f (t - t0)) exp(-((t - t0)/tau)^2). */
+static double source_wave(double t, double amp, double f, double tau, double t0)
+{
+    double x = (t - t0) / tau;
+    return amp * sin(2.0 * K_PI * f * (t - t0)) * exp(-x * x);
+}
+
+/* ---------------------------------------------------------------------------
+ * 1D: Ez at integer nodes i = 0..nx, Hy at i + 1/2 (i = 0..nx-1), SI units.
+ * bc: 0 = PEC ends, 1 = first-order Mur ends.
+ * ne, nubar: [nx+1] electron density (m^-3, 0 = vacuum) and mean collision
+ *   frequency (1/s) per E node.  Plasma nodes are those with ne > 0, in
+ *   increasing order; df holds their F1 rows, df[c * nv + j].
+ * State (in/out): E[nx+1], H[nx], J[nx+1] (J^{n-1/2}), df.
+ * Probes: E at probe nodes after every step, probe_E[s * nprobe + p].
+ * Snapshots: E after every snap_every-th step, snap_E[k * (nx+1) + i].
+ * Returns 0, or -1 on bad arguments.
+ * ------------------------------------------------------------------------- */
+int oracle_run1d(int nx, double dx, double courant, int bc,
+                 int nv, double vmax_over_vth, double te_ev, int nu_model,
+                 const double *ne, const double *nubar,
+                 int src_node, double src_amp, double src_f, double src_tau, double src_t0,
+                 long long step0, long long nsteps,
+                 double *E, double *H, double *J, double *df,
+                 int nprobe, const int *probe_node, double *probe_E,
+                 int snap_every, double *snap_E)
+{
+    if (nx < 2 || nv < 2 || dx <= 0.0 || courant <= 0.0 || courant > 1.0) return -1;
+    if (ne[0] > 0.0 || ne[nx] > 0.0) return -1;
+    double dt = courant * dx / K_C0;
+
+    double *v = malloc(sizeof(double) * nv), *fh = malloc(sizeof(double) * nv);
+    double *gh = malloc(sizeof(double) * nv), *sh = malloc(sizeof(double) * nv);
+    double dv, vth;
+    if (oracle_vgrid(nv, vmax_over_vth, te_ev, v, fh, gh, &dv, &vth) != 0) {
+        free(v); free(fh); free(gh); free(sh); return -1;
+    }
+    oracle_nu_shape(1, nv, v, fh, dv, nu_model, sh);
+
+    int ncell = 0;
+    for (int i = 0; i <= nx; ++i) if (ne[i] > 0.0) ++ncell;
+    int *cell_node = malloc(sizeof(int) * (ncell > 0 ? ncell : 1));
+    for (int i = 0, c = 0; i <= nx; ++i) if (ne[i] > 0.0) cell_node[c++] = i;
+
+    const double ch = dt / (k_mu0() * dx);   /* C_H^E-like coefficient of the H update   */
+    const double ce = dt / (K_EPS0 * dx);    /* C_H^E of the E update (sigma = 0)         */
+    const double cj = dt / K_EPS0;           /* C_J^E (subtracted, see header)            */
+    const double q = (K_C0 * dt - dx) / (K_C0 * dt + dx);   /* Mur-1 coefficient          */
+
+    for (long long s = 0; s < nsteps; ++s) {
+        long long n = step0 + s;
+        /* 1. Faraday: H^{n+1/2} = H^{n-1/2} + dt/(mu0 dx) (E_{i+1} - E_i) */
+        for (int i = 0; i < nx; ++i) H[i] += ch * (E[i + 1] - E[i]);
+
+        /* 2-3. F1 update driven by E^n (section 5.2 update of f_1x), then the
+         *      current moment J^{n+1/2} = -e dv sum_j v_j F1_j. */
+        #pragma omp parallel for schedule(static)
+        for (int c = 0; c < ncell; ++c) {
+            int i = cell_node[c];
+            double *f = df + (size_t)c * nv;
+            double acc = 0.0;
+            for (int j = 0; j < nv; ++j) {
+                double nu = nubar[i] * sh[j];
+                f[j] = ((2.0 - dt * nu) * f[j]
+                        + 2.0 * dt * (K_QE / K_ME) * ne[i] * gh[j] * E[i]) / (2.0 + dt * nu);
+                acc += v[j] * f[j];
+            }
+            J[i] = -K_QE * dv * acc;
+        }
+
+        /* 4. Ampere: E^{n+1} = E^n + dt/(eps0 dx)(H_{i+1/2} - H_{i-1/2}) - dt/eps0 J^{n+1/2} */
+        double e0 = E[0], e1 = E[1], en1 = E[nx - 1], en = E[nx];
+        for (int i = 1; i < nx; ++i) E[i] += ce * (H[i] - H[i - 1]) - cj * J[i];
+
+        /* 5. boundaries */
+        if (bc == 1) {
+            E[0] = e1 + q * (E[1] - e0);
+            E[nx] = en1 + q * (E[nx - 1] - en);
+        } else {
+            E[0] = 0.0; E[nx] = 0.0;
+        }
+
+        /* 6. soft source at t^{n+1} */
+        if (src_amp != 0.0 && src_node > 0 && src_node < nx)
+            E[src_node] += source_wave((double)(n + 1) * dt, src_amp, src_f, src_tau, src_t0);
+
+        for (int p = 0; p < nprobe; ++p) probe_E[s * nprobe + p] = E[probe_node[p]];
+        if (snap_every > 0 && ((s + 1) % snap_every) == 0)
+            memcpy(snap_E + ((s + 1) / snap_every - 1) * (size_t)(nx + 1), E, sizeof(double) * (nx + 1));
+    }
+    free(v); free(fh); free(gh); free(sh); free(cell_node);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * CPML profile along one axis (section 2, eq. (4) and the following formulas).
+ * For each sample point the depth rho into the layer is given; returns b, the
+ * coefficient a_raw = a / delta_cell multiplying the raw field difference, and
+ * kappa.  Points outside the layer (rho <= 0) get b = 0, a_raw = 0, kappa = 1.
+ * ------------------------------------------------------------------------- */
+static void cpml_coeff(double rho, double thick, double dx, double dt,
+                       double order, double sigma_factor, double kappa_max,
+                       double alpha_min, double alpha_max,
+                       double *b, double *a_raw, double *kappa)
+{
+    if (rho <= 0.0) { *b = 0.0; *a_raw = 0.0; *kappa = 1.0; return; }
+    double sigma_max = sigma_factor * (order + 1.0) / (150.0 * K_PI * dx);
+    double r = rho / thick;
+    double sig = sigma_max * pow(r, order);
+    double kap = 1.0 + (kappa_max - 1.0) * pow(r, order);
+    double alp = alpha_min + (alpha_max - alpha_min) * (1.0 - r);
+    double bb = exp(-(sig / kap + alp) * dt / K_EPS0);
+    double aa = sig * (bb - 1.0) / (sig * kap + alp * kap * kap);
+    *b = bb; *a_raw = aa / dx; *kappa = kap;
+}
+
+/* Profiles along an axis with n cells and an ncpml-cell layer at both ends.
+ * e-side samples at integer positions 0..n (n+1 values), h-side at i + 1/2
+ * (n values). */
+int oracle_cpml_profile(int n, int ncpml, double dx, double dt, double order,
+                        double sigma_factor, double kappa_max, double alpha_min,
+                        double alpha_max,
+                        double *be, double *ae, double *ke,
+                        double *bh, double *ah, double *kh)
+{
+    double thick = ncpml * dx;
+    for (int i = 0; i <= n; ++i) {
+        double rho = 0.0;
+        if (i < ncpml) rho = (ncpml - i) * dx;
+        if (i > n - ncpml) rho = (i - (n - ncpml)) * dx;
+        if (ncpml == 0) rho = 0.0;
+        cpml_coeff(rho, thick, dx, dt, order, sigma_factor, kappa_max, alpha_min,
+                   alpha_max, &be[i], &ae[i], &ke[i]);
+    }
+    for (int i = 0; i < n; ++i) {
+        double x = i + 0.5, rho = 0.0;
+        if (x < ncpml) rho = (ncpml - x) * dx;
+        if (x > n - ncpml) rho = (x - (n - ncpml)) * dx;
+        if (ncpml == 0) rho = 0.0;
+        cpml_coeff(rho, thick, dx, dt, order, sigma_factor, kappa_max, alpha_min,
+                   alpha_max, &bh[i], &ah[i], &kh[i]);
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * 2D TEz: Ex at (i+1/2, j)   Ex[j*nx + i],      i < nx, j <= ny
+ *         Ey at (i, j+1/2)   Ey[j*(nx+1) + i],  i <= nx, j < ny
+ *         Hz at (i+1/2,j+1/2) Hz[j*nx + i],     i < nx, j < ny
+ * Per-cell inputs ne, nubar [j*nx + i].  Plasma cells are those with ne > 0
+ * in increasing linear index; df[(c*nv + a)*nv + b], a = vx bin, b = vy bin.
+ * psi: 4 arrays packed back to back: psi_exy (Ex size), psi_eyx (Ey size),
+ *      psi_hzx (Hz size), psi_hzy (Hz size).
+ * Jx, Jy: edge currents (Ex, Ey sizes).
+ * src_kind: 0 none, 1 soft Ey line at column src_i (all j), 2 soft Ey point
+ * at (src_i, src_j).  ncpml = 0 gives a closed PEC box.
+ * Probes record Ey at probe index (into the Ey array) after every step.
+ * ------------------------------------------------------------------------- */
+int oracle_run2d(int nx, int ny, double dx, double courant,
+                 int ncpml, double cpml_order, double sigma_factor, double kappa_max,
+                 double alpha_min, double alpha_max,
+                 int nv, double vmax_over_vth, double te_ev, int nu_model,
+                 const double *ne, const double *nubar,
+                 int src_kind, int src_i, int src_j,
+                 double src_amp, double src_f, double src_tau, double src_t0,
+                 long long step0, long long nsteps,
+                 double *Ex, double *Ey, double *Hz, double *Jx, double *Jy,
+                 double *psi, double *df,
+                 int nprobe, const int *probe_idx, double *probe_out)
+{
+    if (nx < 2 || ny < 2 || nv < 2 || dx <= 0.0) return -1;
+    if (courant <= 0.0 || courant > 1.0 / sqrt(2.0)) return -1;
+    if (2 * ncpml >= nx || 2 * ncpml >= ny) return -1;
+    const double dt = courant * dx / K_C0;
+    const size_t nEx = (size_t)nx * (ny + 1), nEy = (size_t)(nx + 1) * ny, nHz = (size_t)nx * ny;
+    double *psi_exy = psi, *psi_eyx = psi + nEx, *psi_hzx = psi + nEx + nEy, *psi_hzy = psi_hzx + nHz;
+
+    /* velocity tables */
+    double *v = malloc(sizeof(double) * nv), *fh = malloc(sizeof(double) * nv);
+    double *gh = malloc(sizeof(double) * nv), *sh = malloc(sizeof(double) * nv * nv);
+    double dv, vth;
+    if (oracle_vgrid(nv, vmax_over_vth, te_ev, v, fh, gh, &dv, &vth) != 0) {
+        free(v); free(fh); free(gh); free(sh); return -1;
+    }
+    oracle_nu_shape(2, nv, v, fh, dv, nu_model, sh);
+    const int nv2 = nv * nv;
+    double *gx = malloc(sizeof(double) * nv2), *gy = malloc(sizeof(double) * nv2);
+    for (int a = 0; a < nv; ++a)
+        for (int b = 0; b < nv; ++b) {
+            double f2 = fh[a] * fh[b];
+            gx[a * nv + b] = -v[a] * f2 / (vth * vth);
+            gy[a * nv + b] = -v[b] * f2 / (vth * vth);
+        }
+
+    /* CPML profiles */
+    double *bex = malloc(sizeof(double) * (nx + 1)), *aex = malloc(sizeof(double) * (nx + 1)), *kex = malloc(sizeof(double) * (nx + 1));
+    double *bhx = malloc(sizeof(double) * nx), *ahx = malloc(sizeof(double) * nx), *khx = malloc(sizeof(double) * nx);
+    double *bey = malloc(sizeof(double) * (ny + 1)), *aey = malloc(sizeof(double) * (ny + 1)), *key = malloc(sizeof(double) * (ny + 1));
+    double *bhy = malloc(sizeof(double) * ny), *ahy = malloc(sizeof(double) * ny), *khy = malloc(sizeof(double) * ny);
+    oracle_cpml_profile(nx, ncpml, dx, dt, cpml_order, sigma_factor, kappa_max, alpha_min, alpha_max, bex, aex, kex, bhx, ahx, khx);
+    oracle_cpml_profile(ny, ncpml, dx, dt, cpml_order, sigma_factor, kappa_max, alpha_min, alpha_max, bey, aey, key, bhy, ahy, khy);
+
+    /* plasma cells */
+    int ncell = 0;
+    for (size_t k = 0; k < nHz; ++k) if (ne[k] > 0.0) ++ncell;
+    int *cell_idx = malloc(sizeof(int) * (ncell > 0 ? ncell : 1));
+    for (size_t k = 0, c = 0; k < nHz; ++k) if (ne[k] > 0.0) cell_idx[c++] = (int)k;
+    double *jbx = calloc(nHz, sizeof(double)), *jby = calloc(nHz, sizeof(double));
+
+    const double ch = dt / k_mu0();
+    const double ce = dt / K_EPS0;
+
+    for (long long s = 0; s < nsteps; ++s) {
+        long long n = step0 + s;
+        /* 1. Hz^{n+1/2} with CPML psi at the H side */
+        #pragma omp parallel for schedule(static)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t k = (size_t)j * nx + i;
+                double dEx = Ex[(size_t)(j + 1) * nx + i] - Ex[(size_t)j * nx + i];
+                double dEy = Ey[(size_t)j * (nx + 1) + i + 1] - Ey[(size_t)j * (nx + 1) + i];
+                psi_hzx[k] = bhx[i] * psi_hzx[k] + ahx[i] * dEy;
+                psi_hzy[k] = bhy[j] * psi_hzy[k] + ahy[j] * dEx;
+                Hz[k] += ch * (dEx / (khy[j] * dx) - dEy / (khx[i] * dx) + psi_hzy[k] - psi_hzx[k]);
+            }
+
+        /* 2-3. F1 update with E^n averaged to the cell centre, then the cell
+         *      current moments (Jx, Jy)^{n+1/2} */
+        #pragma omp parallel for schedule(static)
+        for (int c = 0; c < ncell; ++c) {
+            int k = cell_idx[c], i = k % nx, j = k / nx;
+            double exc = 0.5 * (Ex[(size_t)j * nx + i] + Ex[(size_t)(j + 1) * nx + i]);
+            double eyc = 0.5 * (Ey[(size_t)j * (nx + 1) + i] + Ey[(size_t)j * (nx + 1) + i + 1]);
+            double *f = df + (size_t)c * nv2;
+            double accx = 0.0, accy = 0.0;
+            for (int a = 0; a < nv; ++a)
+                for (int b = 0; b < nv; ++b) {
+                    int q = a * nv + b;
+                    double nu = nubar[k] * sh[q];
+                    f[q] = ((2.0 - dt * nu) * f[q]
+                            + 2.0 * dt * (K_QE / K_ME) * ne[k] * (gx[q] * exc + gy[q] * eyc))
+                           / (2.0 + dt * nu);
+                    accx += v[a] * f[q];
+                    accy += v[b] * f[q];
+                }
+            jbx[k] = -K_QE * dv * dv * accx;
+            jby[k] = -K_QE * dv * dv * accy;
+        }
+
+        /* 4. edge currents: mean of the two adjacent cell-centre currents */
+        for (int j = 0; j <= ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                double lo = (j > 0) ? jbx[(size_t)(j - 1) * nx + i] : 0.0;
+                double hi = (j < ny) ? jbx[(size_t)j * nx + i] : 0.0;
+                Jx[(size_t)j * nx + i] = 0.5 * (lo + hi);
+            }
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i <= nx; ++i) {
+                double lo = (i > 0) ? jby[(size_t)j * nx + i - 1] : 0.0;
+                double hi = (i < nx) ? jby[(size_t)j * nx + i] : 0.0;
+                Jy[(size_t)j * (nx + 1) + i] = 0.5 * (lo + hi);
+            }
+
+        /* 5. E^{n+1} with CPML psi at the E side; PEC walls keep the
+         *    tangential E on the outer boundary at zero */
+        #pragma omp parallel for schedule(static)
+        for (int j = 1; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t k = (size_t)j * nx + i;
+                double dHz = Hz[(size_t)j * nx + i] - Hz[(size_t)(j - 1) * nx + i];
+                psi_exy[k] = bey[j] * psi_exy[k] + aey[j] * dHz;
+                Ex[k] += ce * (dHz / (key[j] * dx) + psi_exy[k] - Jx[k]);
+            }
+        #pragma omp parallel for schedule(static)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 1; i < nx; ++i) {
+                size_t k = (size_t)j * (nx + 1) + i;
+                double dHz = Hz[(size_t)j * nx + i] - Hz[(size_t)j * nx + i - 1];
+                psi_eyx[k] = bex[i] * psi_eyx[k] + aex[i] * dHz;
+                Ey[k] += ce * (-dHz / (kex[i] * dx) - psi_eyx[k] - Jy[k]);
+            }
+
+        /* 6. soft source at t^{n+1} */
+        if (src_amp != 0.0 && src_kind != 0) {
+            double g = source_wave((double)(n + 1) * dt, src_amp, src_f, src_tau, src_t0);
+            if (src_kind == 1 && src_i > 0 && src_i < nx)
+                for (int j = 0; j < ny; ++j) Ey[(size_t)j * (nx + 1) + src_i] += g;
+            if (src_kind == 2 && src_i > 0 && src_i < nx && src_j >= 0 && src_j < ny)
+                Ey[(size_t)src_j * (nx + 1) + src_i] += g;
+        }
+        for (int p = 0; p < nprobe; ++p) probe_out[s * nprobe + p] = Ey[probe_idx[p]];
+    }
+
+    free(v); free(fh); free(gh); free(sh); free(gx); free(gy);
+    free(bex); free(aex); free(kex); free(bhx); free(ahx); free(khx);
+    free(bey); free(aey); free(key); free(bhy); free(ahy); free(khy);
+    free(cell_idx); free(jbx); free(jby);
+    return 0;
+}

@@ -1,0 +1,226 @@
+"""Seeded synthetic workloads shaped like the paper's plasma-slab problem (section 5).
+
+This module only draws inputs: grids, density and collision-rate profiles, source
+parameters.  It holds none of the method's arithmetic and is shared by the oracle
+tests and the HIP path.  Everything is derived from ``numpy.random.default_rng``
+seeded with 221105647, one spawned sub-stream per workload, so a workload is a pure
+function of its name (and the run index for the batched set).
+
+Common frame (a reading of the paper's pulse table in section 5.2):
+  * reference frequency f_ref = 20 GHz (the pulse centre frequency), cell size
+    dx = lambda_ref / 40, Courant number S = c dt / dx = 0.5;
+  * Gaussian-modulated sine source, tau = 0.966 / f_src and t0 = 4.5 tau (this
+    reproduces the table's 48 ps / 217 ps at 20 GHz), amplitude 1 V/m;
+  * densities are given through the plasma-to-source frequency ratio
+    r = omega_p / omega_src and converted to m^-3 here:
+    n = eps0 m_e (r omega_src)^2 / e^2 (CODATA 2018 constants);
+  * collision rates are given as nu_mean / omega_src and converted to 1/s.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SEED = 221105647
+F_REF = 20e9
+
+# CODATA 2018 (input conversion only)
+_C = 299792458.0
+_EPS0 = 8.8541878128e-12
+_QE = 1.602176634e-19
+_ME = 9.1093837015e-31
+
+DX_REF = _C / F_REF / 40.0
+COURANT_1D = 0.5
+COURANT_2D = 0.5
+
+_STREAMS = {"c0": 0, "c1": 1, "c2": 2, "c3": 3, "c4": 4, "c1l": 5, "mlp": 6, "misc": 7}
+
+
+def rng(name: str) -> np.random.Generator:
+    """Independent, reproducible sub-stream for workload ``name``."""
+    ss = np.random.SeedSequence(SEED).spawn(len(_STREAMS))[_STREAMS[name]]
+    return np.random.default_rng(ss)
+
+
+def density_from_ratio(r, f_src):
+    w = 2.0 * math.pi * f_src
+    return _EPS0 * _ME * (np.asarray(r, dtype=np.float64) * w) ** 2 / _QE ** 2
+
+
+def pulse(f_src):
+    tau = 0.966 / f_src
+    return dict(src_amp=1.0, src_f=f_src, src_tau=tau, src_t0=4.5 * tau)
+
+
+@dataclass
+class Run1D:
+    """One 1D (Ez, Hy) run with a 1V kinetic plasma: per-node inputs of length nx+1."""
+    name: str
+    nx: int
+    nv: int
+    ne: np.ndarray
+    nubar: np.ndarray
+    src_node: int
+    src_amp: float
+    src_f: float
+    src_tau: float
+    src_t0: float
+    steps: int
+    dx: float = DX_REF
+    courant: float = COURANT_1D
+    te_ev: float = 2.0
+    vmax_over_vth: float = 6.0
+    nu_model: str = "hard_sphere"
+    bc: str = "mur"
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def plasma_cells(self) -> int:
+        return int(np.count_nonzero(self.ne > 0))
+
+
+@dataclass
+class Run2D:
+    """One 2D TEz run with a 2V kinetic plasma: per-cell inputs of shape (ny, nx)."""
+    name: str
+    nx: int
+    ny: int
+    nv: int
+    ne: np.ndarray
+    nubar: np.ndarray
+    src_kind: int
+    src_i: int
+    src_j: int
+    src_amp: float
+    src_f: float
+    src_tau: float
+    src_t0: float
+    steps: int
+    dx: float = DX_REF
+    courant: float = COURANT_2D
+    te_ev: float = 5.0
+    vmax_over_vth: float = 6.0
+    nu_model: str = "hard_sphere"
+    ncpml: int = 8
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def plasma_cells(self) -> int:
+        return int(np.count_nonzero(self.ne > 0))
+
+
+def slab_1d(nx, nv, lo, hi, ratio, nu_ratio, f_src, src_node, steps, name="slab",
+            te_ev=2.0, nu_model="hard_sphere", bc="mur", f_grid=F_REF) -> Run1D:
+    ne = np.zeros(nx + 1)
+    nub = np.zeros(nx + 1)
+    ne[lo:hi] = density_from_ratio(ratio, f_src)
+    nub[lo:hi] = nu_ratio * 2.0 * math.pi * f_src
+    return Run1D(name=name, nx=nx, nv=nv, ne=ne, nubar=nub, src_node=src_node,
+                 steps=steps, te_ev=te_ev, nu_model=nu_model, bc=bc,
+                 dx=_C / f_grid / 40.0, **pulse(f_src))
+
+
+def c0() -> Run1D:
+    """Small FP64 case: Nx=1000, slab [400, 600), omega_p/omega=0.8, nu/omega=0.1,
+    Nv=64 on +-6 v_th, Te=2 eV, source at node 100, Mur ends, 1000 steps."""
+    return slab_1d(1000, 64, 400, 600, 0.8, 0.1, F_REF, 100, 1000, name="c0")
+
+
+def smoothed_uniform(g: np.random.Generator, n: int, sigma: float) -> np.ndarray:
+    """White noise -> periodic Gaussian filter (width ``sigma`` samples) -> map through
+    the normal CDF of its own spread, giving a smooth field with uniform marginals."""
+    from scipy.ndimage import gaussian_filter1d
+    from scipy.special import ndtr
+    w = gaussian_filter1d(g.standard_normal(n), sigma, mode="wrap")
+    return ndtr(w / w.std())
+
+
+def c1(nx: int = 65536, steps: int = 20000, name: str = "c1", stream: str = "c1") -> Run1D:
+    """Large 1D case: Nx=65536, Nv=512, plasma over nodes [400, Nx-100) with a smoothed
+    random profile omega_p/omega in [0.2, 2] and log-uniform nu/omega in [0.01, 1]."""
+    g = rng(stream)
+    lo, hi = 400, nx - 100
+    u = smoothed_uniform(g, hi - lo, 64.0)
+    u2 = smoothed_uniform(g, hi - lo, 64.0)
+    w = 2.0 * math.pi * F_REF
+    ne = np.zeros(nx + 1)
+    nub = np.zeros(nx + 1)
+    ne[lo:hi] = density_from_ratio(0.2 + 1.8 * u, F_REF)
+    nub[lo:hi] = 10.0 ** (-2.0 + 2.0 * u2) * w
+    return Run1D(name=name, nx=nx, nv=512, ne=ne, nubar=nub, src_node=100, steps=steps,
+                 **pulse(F_REF))
+
+
+def c1_large() -> Run1D:
+    """C1 with Nx = 2^20 and 2000 steps: F1 (1.07 GB half grid in FP32) exceeds every cache."""
+    return c1(nx=1 << 20, steps=2000, name="c1l", stream="c1l")
+
+
+def c2(n: int = 512, radius: float = 100.0, steps: int = 4000) -> Run2D:
+    """2D TEz 512x512, 32x32 velocity grid, CPML 8, plasma column of radius 100 cells
+    at the centre (omega_p/omega=1.2, nu/omega=0.05, Te=5 eV), Ey line source at i=20."""
+    ii, jj = np.meshgrid(np.arange(n) + 0.5, np.arange(n) + 0.5)
+    inside = (ii - n / 2) ** 2 + (jj - n / 2) ** 2 < radius ** 2
+    ne = np.where(inside, density_from_ratio(1.2, F_REF), 0.0)
+    nub = np.where(inside, 0.05 * 2.0 * math.pi * F_REF, 0.0)
+    return Run2D(name="c2", nx=n, ny=n, nv=32, ne=ne, nubar=nub, src_kind=1, src_i=20,
+                 src_j=0, steps=steps, **pulse(F_REF))
+
+
+def c3(nruns: int = 256) -> list:
+    """Batched set: Nx ~ U[500, 20000], Nv in {64, 128, 256}, slab [0.4 Nx, 0.6 Nx) with
+    omega_p/omega ~ U[0.2, 2], nu/omega log-U[0.01, 1], f_src = f_ref (1 + U[-0.3, 0.3])
+    on the fixed f_ref grid, source at 0.1 Nx, 2 Nx steps per run."""
+    g = rng("c3")
+    runs = []
+    for r in range(nruns):
+        nx = int(g.integers(500, 20001))
+        nv = int(g.choice([64, 128, 256]))
+        ratio = float(g.uniform(0.2, 2.0))
+        nu_ratio = float(10.0 ** g.uniform(-2.0, 0.0))
+        f_src = F_REF * (1.0 + float(g.uniform(-0.3, 0.3)))
+        run = slab_1d(nx, nv, int(0.4 * nx), int(0.6 * nx), ratio, nu_ratio, f_src,
+                      int(0.1 * nx), 2 * nx, name=f"c3_{r}")
+        run.meta = dict(ratio=ratio, nu_ratio=nu_ratio, f_src=f_src)
+        runs.append(run)
+    return runs
+
+
+def blobs_2d(n: int, nblobs: int, g: np.random.Generator, ratio_lo=0.2, ratio_hi=1.5,
+             r_lo=40.0, r_hi=200.0, margin=208, extra_hot: int = 0):
+    """Random circular plasma blobs; where blobs overlap the one with the larger
+    omega_p wins (with its own nu)."""
+    ratio = np.zeros((n, n))
+    nur = np.zeros((n, n))
+    specs = []
+    for b in range(nblobs + extra_hot):
+        cx, cy = g.uniform(margin, n - margin, size=2)
+        rad = g.uniform(r_lo, r_hi) * n / 4096.0
+        rr = g.uniform(ratio_lo, ratio_hi) if b < nblobs else g.uniform(2.0, 2.5)
+        nn = 10.0 ** g.uniform(-2.0, 0.0)
+        specs.append((cx, cy, rad, rr, nn))
+    for (cx, cy, rad, rr, nn) in specs:
+        i0, i1 = max(0, int(cx - rad) - 1), min(n, int(cx + rad) + 2)
+        j0, j1 = max(0, int(cy - rad) - 1), min(n, int(cy + rad) + 2)
+        ii, jj = np.meshgrid(np.arange(i0, i1) + 0.5, np.arange(j0, j1) + 0.5)
+        m = (ii - cx) ** 2 + (jj - cy) ** 2 < rad ** 2
+        sub_r = ratio[j0:j1, i0:i1]
+        sub_n = nur[j0:j1, i0:i1]
+        take = m & (rr > sub_r)
+        sub_r[take] = rr
+        sub_n[take] = nn
+    return ratio, nur, specs
+
+
+def c4(n: int = 4096, nblobs: int = 48, extra_hot: int = 0, steps: int = 2000) -> Run2D:
+    """2D TEz 4096x4096 with 48 random plasma blobs (omega_p/omega in [0.2, 1.5],
+    nu/omega log-U[0.01, 1], radii U[40, 200] cells), Te=5 eV, Ey line source."""
+    g = rng("c4")
+    ratio, nur, specs = blobs_2d(n, nblobs, g, extra_hot=extra_hot)
+    ne = np.where(ratio > 0, density_from_ratio(ratio, F_REF), 0.0)
+    nub = nur * 2.0 * math.pi * F_REF
+    return Run2D(name="c4", nx=n, ny=n, nv=32, ne=ne, nubar=nub, src_kind=1, src_i=20,
+                 src_j=0, steps=steps, meta=dict(blobs=specs), **pulse(F_REF))
