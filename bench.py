@@ -1,0 +1,137 @@
+#!/usr/bin/env python3
+"""Throughput of the kinetic-FDTD step on one MI355X.
+
+One benchmark step is one leap-frog time step of the whole coupled path (H update,
+F1 update driven by E, FP64 current moment, E update with -J, Mur ends, soft source) on
+the large 1D workload: Nx = 65536 cells, Nv = 512 velocity bins, plasma over nodes
+[400, Nx-100) with a smoothed random density (omega_p/omega in [0.2, 2]) and
+log-uniform collision rates, FP32 storage with FP64 moments.  Inputs are synthetic and
+seeded.  The metric counts phase-space updates (plasma cell x signed velocity bin x
+step) per second.
+
+Prints one JSON line.  ``--gpus N`` with N > 1 exits: this path runs on one GPU.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in ("common.h", "kernels1d.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2211_05647_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def pmc_traffic(bytes_alg):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
+    on the kernel as it is now (else None)."""
+    p = os.path.join(ROOT, "profiles", "k_step1d_c1_pmc.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(run, budget_s=15.0):
+    """The FP64 oracle on the host cores, on a bounded sample of the same workload:
+    the full line (all plasma cells, full signed grid) for as many steps as fit the
+    time budget.  Returns phase-space updates/s."""
+    sys.path.insert(0, ROOT)
+    from oracle.core import Oracle1D, threads
+    o = Oracle1D(run.nx, run.dx, run.courant, run.ne, run.nubar, nv=run.nv,
+                 vmax_over_vth=run.vmax_over_vth, te_ev=run.te_ev, nu_model=run.nu_model,
+                 bc=run.bc, src_node=run.src_node, src_amp=run.src_amp, src_f=run.src_f,
+                 src_tau=run.src_tau, src_t0=run.src_t0)
+    t0 = time.perf_counter()
+    o.run(2)
+    per = (time.perf_counter() - t0) / 2
+    n = max(2, int(budget_s / max(per, 1e-6)))
+    t0 = time.perf_counter()
+    o.run(n)
+    t = time.perf_counter() - t0
+    ups = run.plasma_cells * run.nv * n / t
+    return dict(value=ups, unit="phase-space updates/s", cores=threads(), kind="oracle",
+                sample=f"large 1D workload, full line (Nx={run.nx}, Nv={run.nv}), {n} steps "
+                       f"from the zero state, FP64 on the full signed grid, {t:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the kinetic-FDTD path here runs on a single "
+              "MI355X (multi-GPU sharding is a design note only)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    sys.path.insert(0, ROOT)
+    from paper_2211_05647_amd import binding as B
+    from paper_2211_05647_amd import workloads as W
+
+    run = W.c1()
+    print(f"[bench] workload c1: Nx={run.nx} Nv={run.nv} plasma cells={run.plasma_cells}",
+          file=sys.stderr, flush=True)
+    sim = B.Sim(run, precision=B.FP32, tile=args.tile)
+    sim.run(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.run(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_dev = sim.last_run_ms()          # HIP events on the launch stream, per step
+    # sanity: the run must have stayed finite
+    sim.read(B.F_E)
+
+    ncell, nv, half, nx = run.plasma_cells, run.nv, run.nv // 2, run.nx
+    updates = ncell * nv * args.steps
+    value = updates / wall
+    # algorithmic bytes of one launch of the fused step kernel: F1 read + write
+    # (half grid, FP32), per-cell scalars (node index, dt*nu, density), fields
+    # (E and H read + written, J written) over the whole line
+    bytes_alg = ncell * half * 4 * 2 + ncell * 12 + (nx + 1) * 4 * 5
+    achieved = bytes_alg / (ms_dev * 1e-3) / 1e9
+    traffic = pmc_traffic(bytes_alg)
+    out = {
+        "metric": "kinetic-FDTD phase-space updates/s",
+        "value": value,
+        "unit": "phase-space updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (f64 moments)",
+        "data": "synthetic, seeded",
+        "config": {"workload": "1D Yee + 1V kinetic, Nx=65536, Nv=512, FP32",
+                   "nx": nx, "nv": nv, "plasma_cells": ncell, "steps": args.steps},
+        "stored_bin_updates_per_s": ncell * half * args.steps / wall,
+        "roofline": {"bound": "hbm", "kernel": "k_step1d<float>", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "bytes_per_launch": bytes_alg,
+                     "launch_ms": ms_dev},
+        "context": "paper: MATLAB plasma code ~20x GPU (GTX 1050) over serial CPU (i7-7700HQ)",
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(run)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,196 @@
+/*
+ * fdtd_plasma.h -- C ABI of the MI355X (gfx950) kinetic-FDTD plasma library.
+ *
+ * The library advances Maxwell's curl equations on a Yee grid (arXiv 2211.05647,
+ * section 2, eq. (1)-(5); CPML of eq. (4) and the b, a, sigma_max, alpha formulas
+ * that follow it), coupled every time step to the two-term kinetic model of the
+ * electrons in every plasma cell (section 5.2, eq. for dF1/dt with nu(v) = N s v and
+ * J = -e \int v F d^3v, and the Crank-Nicolson style update of f_1x and the Jx sum).
+ * The problem is stated the way the paper states it: a grid (cells, cell size,
+ * Courant number, absorbing layer), a plasma profile (electron density, collision
+ * frequency, temperature, velocity bins), a Gaussian-modulated source (section 5.2
+ * table) and a number of time steps.
+ *
+ * Conventions (all entry points):
+ *   - every call returns int: FDTD_OK (0) or a negative fdtd_status; nothing throws
+ *     across the ABI.  fdtd_plasma_strerror() names a code; fdtd_plasma_last_error()
+ *     gives the thread's last message.
+ *   - host pointers are plain host memory; device pointers are HIP device memory.
+ *   - input arrays are copied during create; the caller may free them on return.
+ *   - if fdtd_device.workspace is non-NULL, the library never allocates device memory:
+ *     every device array lives inside that caller-owned buffer, which must stay valid
+ *     until fdtd_plasma_destroy.  If it is NULL the library allocates (hipMalloc) and
+ *     frees on destroy.
+ *   - work is enqueued on fdtd_device.hip_stream (NULL = the null stream); step/run
+ *     return once enqueued.  read_* synchronise that stream.
+ *   - after k steps, E is at t = k dt while H and J are at t = (k - 1/2) dt.
+ *   - a read into a short buffer returns FDTD_ERANGE and writes nothing.
+ *   - invalid arguments return FDTD_EINVAL with no side effect; HIP errors return
+ *     FDTD_EDEVICE; a non-finite field returns FDTD_ENUMERIC from read_fields.
+ *   - handles are not thread-safe; calls on one handle must be serialised.
+ */
+#ifndef FDTD_PLASMA_H
+#define FDTD_PLASMA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fdtd_plasma fdtd_plasma;   /* opaque: one run or one batch of runs */
+
+enum fdtd_status {
+  FDTD_OK = 0,
+  FDTD_EINVAL = -1,   /* bad argument, shape or configuration            */
+  FDTD_ENOMEM = -2,   /* workspace too small or allocation failed        */
+  FDTD_EDEVICE = -3,  /* HIP runtime error                               */
+  FDTD_ERANGE = -4,   /* destination buffer too short / index out of range */
+  FDTD_ENUMERIC = -5, /* non-finite value found in the fields            */
+  FDTD_ESTATE = -6    /* call not allowed in the handle's current state   */
+};
+
+enum fdtd_precision { FDTD_FP64 = 0, FDTD_FP32 = 1 };
+enum fdtd_boundary { FDTD_BC_PEC = 0, FDTD_BC_MUR1 = 1, FDTD_BC_CPML = 2 };
+enum fdtd_nu_model { FDTD_NU_HARD_SPHERE = 0, FDTD_NU_CONST = 1 };
+enum fdtd_closure { FDTD_CLOSURE_KINETIC = 0, FDTD_CLOSURE_MLP = 1 };
+enum fdtd_source_kind { FDTD_SRC_NONE = 0, FDTD_SRC_LINE_SOFT = 1, FDTD_SRC_POINT_SOFT = 2 };
+
+/* Field selectors for read_fields / add_probe.
+ * 1D grids (Ez at nodes i = 0..nx, Hy at i + 1/2):
+ *   FDTD_F_E  Ez [nx+1] V/m,  FDTD_F_H Hy [nx] A/m,  FDTD_F_J Jz [nx+1] A/m^2,
+ *   FDTD_F_DF F1 on the full signed velocity grid, [ncell][nv] (s/m^4), plasma nodes
+ *             in increasing order (mirror bins reconstructed from the stored half).
+ * 2D TEz grids (Ex at (i+1/2, j), Ey at (i, j+1/2), Hz at (i+1/2, j+1/2)):
+ *   FDTD_F_EX [ny+1][nx], FDTD_F_EY [ny][nx+1], FDTD_F_HZ [ny][nx] (A/m),
+ *   FDTD_F_JX [ny+1][nx], FDTD_F_JY [ny][nx+1] (edge currents, A/m^2),
+ *   FDTD_F_DF [ncell][nv][nv] (vx index, vy index), plasma cells in row-major order. */
+enum fdtd_field {
+  FDTD_F_E = 0, FDTD_F_H = 1, FDTD_F_J = 2, FDTD_F_DF = 3,
+  FDTD_F_EX = 4, FDTD_F_EY = 5, FDTD_F_HZ = 6, FDTD_F_JX = 7, FDTD_F_JY = 8
+};
+
+/* Grid (section 2): dims 1 = (Ez, Hy) line, 2 = TEz plane.  nx (and ny) in cells,
+ * dx in metres (dy = dx), courant = c dt / dx (rejected above 1 in 1D, 1/sqrt(2) in 2D).
+ * boundary: 1D takes PEC or MUR1, 2D takes PEC or CPML.  The CPML parameters follow
+ * the paper's ranges (thickness 8 cells, order 2-4, sigma factor 0.7-1.5, kappa_max
+ * 5-11, alpha_max 0-0.05 S/m). */
+typedef struct {
+  int32_t dims;
+  int32_t nx, ny;
+  double dx;
+  double courant;
+  int32_t precision;
+  int32_t boundary;
+  int32_t cpml_cells;
+  double cpml_order, cpml_sigma_factor, cpml_kappa_max, cpml_alpha_min, cpml_alpha_max;
+} fdtd_grid;
+
+/* Plasma profile (section 5.2).  ne / nu_mean: host arrays, 1D: [nx+1] per E node,
+ * 2D: [ny][nx] per cell; ne = 0 marks vacuum.  F0 is a Maxwellian at te_ev, F1 starts
+ * at zero.  nv bins per velocity axis (a power of two, >= 8), cell-centred on
+ * +-vmax_over_vth * v_th.  nu_model HARD_SPHERE: nu(v) = N s |v| scaled so its
+ * Maxwellian mean is nu_mean; CONST: nu = nu_mean.  closure: KINETIC, or MLP with the
+ * network blob `mlp` (fdtd_mlp_blob) and the kinetic step as fallback. */
+typedef struct {
+  const double *ne;
+  const double *nu_mean;
+  double te_ev;
+  int32_t nv;
+  double vmax_over_vth;
+  int32_t nu_model;
+  int32_t closure;
+  const void *mlp;
+} fdtd_profile;
+
+/* Soft source (section 5.2 table): adds amplitude * sin(2 pi f (t - t0))
+ * exp(-((t - t0)/tau)^2) to E at t^{n+1} after each E update.  1D: node i (POINT).
+ * 2D: LINE adds to every Ey(i, j + 1/2) of column i; POINT adds to Ey(i, j + 1/2). */
+typedef struct {
+  int32_t kind;
+  int32_t i, j;
+  double amplitude, f_hz, tau_s, t0_s;
+} fdtd_source;
+
+/* Device binding.  hip_stream: a hipStream_t (NULL = null stream).  workspace: device
+ * memory of workspace_bytes (see fdtd_plasma_workspace_size) or NULL.  max_probes /
+ * probe_capacity reserve room for time-series probes (steps kept per probe). */
+typedef struct {
+  int32_t device;
+  void *hip_stream;
+  void *workspace;
+  size_t workspace_bytes;
+  int32_t max_probes;
+  int32_t probe_capacity;
+} fdtd_device;
+
+/* Bytes of device workspace a single run needs.  EINVAL on a bad configuration. */
+int fdtd_plasma_workspace_size(const fdtd_grid *grid, const fdtd_profile *profile,
+                               const fdtd_device *dev, size_t *bytes);
+
+/* Validate, build the FP64 tables on the host (velocity grid, F0 and dF0/dv, collision
+ * frequencies, CPML profiles), round them once to the storage precision, copy them and
+ * the zero initial state to the device.  *out receives the handle. */
+int fdtd_plasma_create(const fdtd_grid *grid, const fdtd_profile *profile,
+                       const fdtd_source *source, const fdtd_device *dev, fdtd_plasma **out);
+
+/* Batch of nruns independent 1D FP32 runs of uneven size sharing one launch (arrays of
+ * nruns structs).  steps[r] is the step count of run r: fdtd_plasma_run advances every
+ * run to min(its own count, the batch step).  Workspace size via
+ * fdtd_plasma_workspace_size_batch. */
+int fdtd_plasma_workspace_size_batch(int32_t nruns, const fdtd_grid *grids,
+                                     const fdtd_profile *profiles, const fdtd_device *dev,
+                                     size_t *bytes);
+int fdtd_plasma_create_batch(int32_t nruns, const fdtd_grid *grids,
+                             const fdtd_profile *profiles, const fdtd_source *sources,
+                             const int64_t *steps, const fdtd_device *dev,
+                             fdtd_plasma **out);
+
+/* One leap-frog step (H, F1 and J, E, boundary, source), enqueued. */
+int fdtd_plasma_step(fdtd_plasma *h);
+/* nsteps leap-frog steps, enqueued on the handle's stream. */
+int fdtd_plasma_run(fdtd_plasma *h, int64_t nsteps);
+/* Steps taken so far (batch: the batch step counter). */
+int fdtd_plasma_steps(const fdtd_plasma *h, int64_t *steps);
+
+/* Number of doubles read_fields writes for (run, field). */
+int fdtd_plasma_field_size(const fdtd_plasma *h, int32_t run, int32_t field, size_t *n);
+/* Synchronise, copy one field of run `run` (0 for a single run) to host as doubles in
+ * SI units, layout as documented at enum fdtd_field.  *step_out (optional) receives the
+ * step count of that run.  FDTD_ENUMERIC if the copied field holds a NaN or Inf. */
+int fdtd_plasma_read_fields(fdtd_plasma *h, int32_t run, int32_t field, double *dst,
+                            size_t dst_len, int64_t *step_out);
+
+/* Record `field` at grid index (i, j) after every step (1D: j ignored).  Only before
+ * the first step; at most fdtd_device.max_probes.  *id receives the probe id. */
+int fdtd_plasma_add_probe(fdtd_plasma *h, int32_t run, int32_t field, int32_t i, int32_t j,
+                          int32_t *id);
+/* Copy the last min(steps, probe_capacity) samples of probe `id` (oldest first). */
+int fdtd_plasma_read_probe(fdtd_plasma *h, int32_t id, double *dst, size_t dst_len,
+                           size_t *n_out);
+
+/* Whole evolving state (fields, F1, CPML memory, step counter, probe rings) as an
+ * opaque host blob; load requires a handle created with the same configuration and
+ * resumes bitwise-identically. */
+int fdtd_plasma_state_size(const fdtd_plasma *h, size_t *bytes);
+int fdtd_plasma_save_state(fdtd_plasma *h, void *dst, size_t len);
+int fdtd_plasma_load_state(fdtd_plasma *h, const void *src, size_t len);
+
+/* Launch shape (autotuner hook): nodes (1D) or cells (2D) per tile, and plasma cells
+ * per work-group for the kinetic kernels; 0 keeps the current value.  Only before the
+ * first step. */
+int fdtd_plasma_set_tiling(fdtd_plasma *h, int32_t tile, int32_t cells_per_group);
+
+/* Average device time per step of the last fdtd_plasma_run, measured with HIP events
+ * on the handle's stream (synchronises). */
+int fdtd_plasma_last_run_ms(fdtd_plasma *h, double *ms_per_step);
+
+void fdtd_plasma_destroy(fdtd_plasma *h);
+const char *fdtd_plasma_strerror(int code);
+const char *fdtd_plasma_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDTD_PLASMA_H */

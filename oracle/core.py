@@ -30,6 +30,7 @@ def lib():
         L.oracle_nu_shape.argtypes = [C.c_int, C.c_int, _dp, _dp, C.c_double, C.c_int, _dp]
         L.oracle_collision1v.argtypes = [C.c_int, _dp, _dp, _dp]
         L.oracle_constants.argtypes = [_dp]
+        L.oracle_threads.argtypes = []
         L.oracle_cpml_profile.argtypes = [C.c_int, C.c_int] + [C.c_double] * 7 + [_dp] * 6
         L.oracle_run1d.argtypes = (
             [C.c_int, C.c_double, C.c_double, C.c_int,
@@ -62,6 +63,11 @@ def _p(a):
     if a.dtype == np.int32:
         return a.ctypes.data_as(_ip)
     raise TypeError(a.dtype)
+
+
+def threads():
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().oracle_threads())
 
 
 def constants():

@@ -41,6 +41,9 @@
 #include <stdlib.h>
 #include <string.h>
 #include <stdint.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* CODATA 2018 */
 static const double K_C0 = 299792458.0;
@@ -50,6 +53,15 @@ static const double K_ME = 9.1093837015e-31;
 static const double K_PI = 3.14159265358979323846;
 
 static double k_mu0(void) { return 1.0 / (K_EPS0 * K_C0 * K_C0); }
+
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 int oracle_constants(double *out4)
 {

@@ -1,0 +1,247 @@
+"""ctypes binding of ``libfdtdplasma.so`` (the C ABI of ``include/fdtd_plasma.h``).
+
+Argument marshalling only: every step of the method runs in the HIP kernels.  PyTorch
+supplies the device workspace (a uint8 tensor) and the stream.  The library must be
+built in-tree (``paper_2211_05647_amd/build.py``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfdtdplasma.so")
+
+FP64, FP32 = 0, 1
+BC_PEC, BC_MUR1, BC_CPML = 0, 1, 2
+NU_HARD_SPHERE, NU_CONST = 0, 1
+CLOSURE_KINETIC, CLOSURE_MLP = 0, 1
+SRC_NONE, SRC_LINE, SRC_POINT = 0, 1, 2
+F_E, F_H, F_J, F_DF, F_EX, F_EY, F_HZ, F_JX, F_JY = range(9)
+
+OK, EINVAL, ENOMEM, EDEVICE, ERANGE, ENUMERIC, ESTATE = 0, -1, -2, -3, -4, -5, -6
+
+_dp = C.POINTER(C.c_double)
+
+
+class Grid(C.Structure):
+    _fields_ = [("dims", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("dx", C.c_double), ("courant", C.c_double),
+                ("precision", C.c_int32), ("boundary", C.c_int32),
+                ("cpml_cells", C.c_int32), ("cpml_order", C.c_double),
+                ("cpml_sigma_factor", C.c_double), ("cpml_kappa_max", C.c_double),
+                ("cpml_alpha_min", C.c_double), ("cpml_alpha_max", C.c_double)]
+
+
+class Profile(C.Structure):
+    _fields_ = [("ne", _dp), ("nu_mean", _dp), ("te_ev", C.c_double), ("nv", C.c_int32),
+                ("vmax_over_vth", C.c_double), ("nu_model", C.c_int32),
+                ("closure", C.c_int32), ("mlp", C.c_void_p)]
+
+
+class Source(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("i", C.c_int32), ("j", C.c_int32),
+                ("amplitude", C.c_double), ("f_hz", C.c_double), ("tau_s", C.c_double),
+                ("t0_s", C.c_double)]
+
+
+class Device(C.Structure):
+    _fields_ = [("device", C.c_int32), ("hip_stream", C.c_void_p), ("workspace", C.c_void_p),
+                ("workspace_bytes", C.c_size_t), ("max_probes", C.c_int32),
+                ("probe_capacity", C.c_int32)]
+
+
+# every symbol the header declares, with its ctypes signature
+_SIGS = {
+    "fdtd_plasma_workspace_size": ([C.POINTER(Grid), C.POINTER(Profile), C.POINTER(Device), C.POINTER(C.c_size_t)], C.c_int),
+    "fdtd_plasma_create": ([C.POINTER(Grid), C.POINTER(Profile), C.POINTER(Source), C.POINTER(Device), C.POINTER(C.c_void_p)], C.c_int),
+    "fdtd_plasma_workspace_size_batch": ([C.c_int32, C.POINTER(Grid), C.POINTER(Profile), C.POINTER(Device), C.POINTER(C.c_size_t)], C.c_int),
+    "fdtd_plasma_create_batch": ([C.c_int32, C.POINTER(Grid), C.POINTER(Profile), C.POINTER(Source), C.POINTER(C.c_int64), C.POINTER(Device), C.POINTER(C.c_void_p)], C.c_int),
+    "fdtd_plasma_step": ([C.c_void_p], C.c_int),
+    "fdtd_plasma_run": ([C.c_void_p, C.c_int64], C.c_int),
+    "fdtd_plasma_steps": ([C.c_void_p, C.POINTER(C.c_int64)], C.c_int),
+    "fdtd_plasma_field_size": ([C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)], C.c_int),
+    "fdtd_plasma_read_fields": ([C.c_void_p, C.c_int32, C.c_int32, _dp, C.c_size_t, C.POINTER(C.c_int64)], C.c_int),
+    "fdtd_plasma_add_probe": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
+    "fdtd_plasma_read_probe": ([C.c_void_p, C.c_int32, _dp, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
+    "fdtd_plasma_state_size": ([C.c_void_p, C.POINTER(C.c_size_t)], C.c_int),
+    "fdtd_plasma_save_state": ([C.c_void_p, C.c_void_p, C.c_size_t], C.c_int),
+    "fdtd_plasma_load_state": ([C.c_void_p, C.c_void_p, C.c_size_t], C.c_int),
+    "fdtd_plasma_set_tiling": ([C.c_void_p, C.c_int32, C.c_int32], C.c_int),
+    "fdtd_plasma_last_run_ms": ([C.c_void_p, C.POINTER(C.c_double)], C.c_int),
+    "fdtd_plasma_destroy": ([C.c_void_p], None),
+    "fdtd_plasma_strerror": ([C.c_int], C.c_char_p),
+    "fdtd_plasma_last_error": ([], C.c_char_p),
+}
+
+_lib = None
+
+
+def lib():
+    """Load the built library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2211_05647_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+class FdtdError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        msg = lib().fdtd_plasma_last_error().decode()
+        super().__init__(f"{what}: {lib().fdtd_plasma_strerror(code).decode()} ({code}): {msg}")
+
+
+def check(rc, what):
+    if rc != OK:
+        raise FdtdError(rc, what)
+
+
+def _arr(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+def make_grid(dims, nx, ny, dx, courant, precision, boundary, cpml_cells=8, cpml_order=3.0,
+              sigma_factor=1.0, kappa_max=5.0, alpha_min=0.0, alpha_max=0.05):
+    return Grid(dims, nx, ny, dx, courant, precision, boundary, cpml_cells, cpml_order,
+                sigma_factor, kappa_max, alpha_min, alpha_max)
+
+
+class Sim:
+    """One run (or a batch of 1D runs) on the GPU through the C ABI.
+
+    ``workload``: a ``workloads.Run1D`` / ``Run2D`` (or a list of Run1D for a batch).
+    The workspace is a torch uint8 tensor on ``cuda:device``; work goes on torch's
+    current stream of that device.
+    """
+
+    def __init__(self, workload, precision=FP32, device=0, max_probes=0, probe_capacity=0,
+                 closure=CLOSURE_KINETIC, mlp_blob=None, tile=0, cells_per_group=0):
+        import torch
+        self.torch = torch
+        L = lib()
+        self.device = device
+        self.stream = torch.cuda.current_stream(device)
+        self.batch = isinstance(workload, (list, tuple))
+        runs = list(workload) if self.batch else [workload]
+        self.runs = runs
+        self._keep = []
+        grids, profs, srcs = [], [], []
+        for w in runs:
+            if hasattr(w, "ny"):
+                g = make_grid(2, w.nx, w.ny, w.dx, w.courant, precision, BC_CPML, w.ncpml)
+                if w.ncpml == 0:
+                    g.boundary = BC_PEC
+                src = Source(w.src_kind, w.src_i, w.src_j, w.src_amp, w.src_f, w.src_tau, w.src_t0)
+            else:
+                g = make_grid(1, w.nx, 1, w.dx, w.courant, precision,
+                              BC_MUR1 if w.bc == "mur" else BC_PEC, 0)
+                src = Source(SRC_POINT if w.src_amp != 0 else SRC_NONE, w.src_node, 0,
+                             w.src_amp, w.src_f, w.src_tau, w.src_t0)
+            ne, pne = _arr(w.ne)
+            nu, pnu = _arr(w.nubar)
+            self._keep += [ne, nu]
+            mlp_ptr = None
+            if mlp_blob is not None:
+                self._keep.append(mlp_blob)
+                mlp_ptr = mlp_blob.ctypes.data_as(C.c_void_p)
+            p = Profile(pne, pnu, w.te_ev, w.nv, w.vmax_over_vth,
+                        NU_HARD_SPHERE if w.nu_model == "hard_sphere" else NU_CONST,
+                        closure, mlp_ptr)
+            grids.append(g)
+            profs.append(p)
+            srcs.append(src)
+        dev = Device(device, C.c_void_p(self.stream.cuda_stream), None, 0, max_probes, probe_capacity)
+        nbytes = C.c_size_t()
+        if self.batch:
+            GA, PA = Grid * len(runs), Profile * len(runs)
+            self._ga, self._pa = GA(*grids), PA(*profs)
+            self._sa = (Source * len(runs))(*srcs)
+            check(L.fdtd_plasma_workspace_size_batch(len(runs), self._ga, self._pa, C.byref(dev), C.byref(nbytes)),
+                  "workspace_size_batch")
+        else:
+            check(L.fdtd_plasma_workspace_size(C.byref(grids[0]), C.byref(profs[0]), C.byref(dev), C.byref(nbytes)),
+                  "workspace_size")
+        self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=f"cuda:{device}")
+        dev.workspace = C.c_void_p(self.workspace.data_ptr())
+        dev.workspace_bytes = self.workspace.numel()
+        h = C.c_void_p()
+        if self.batch:
+            steps = (C.c_int64 * len(runs))(*[int(w.steps) for w in runs])
+            self._steps = steps
+            check(L.fdtd_plasma_create_batch(len(runs), self._ga, self._pa, self._sa, steps, C.byref(dev), C.byref(h)),
+                  "create_batch")
+        else:
+            check(L.fdtd_plasma_create(C.byref(grids[0]), C.byref(profs[0]), C.byref(srcs[0]), C.byref(dev), C.byref(h)),
+                  "create")
+        self.h = h
+        if tile or cells_per_group:
+            check(L.fdtd_plasma_set_tiling(self.h, tile, cells_per_group), "set_tiling")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fdtd_plasma_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, nsteps):
+        check(lib().fdtd_plasma_run(self.h, int(nsteps)), "run")
+
+    def step(self):
+        check(lib().fdtd_plasma_step(self.h), "step")
+
+    @property
+    def steps(self):
+        s = C.c_int64()
+        check(lib().fdtd_plasma_steps(self.h, C.byref(s)), "steps")
+        return s.value
+
+    def read(self, field, run=0):
+        n = C.c_size_t()
+        check(lib().fdtd_plasma_field_size(self.h, run, field, C.byref(n)), "field_size")
+        out = np.empty(n.value, dtype=np.float64)
+        st = C.c_int64()
+        check(lib().fdtd_plasma_read_fields(self.h, run, field, out.ctypes.data_as(_dp), out.size, C.byref(st)),
+              "read_fields")
+        return out
+
+    def add_probe(self, field, i, j=0, run=0):
+        pid = C.c_int32()
+        check(lib().fdtd_plasma_add_probe(self.h, run, field, i, j, C.byref(pid)), "add_probe")
+        return pid.value
+
+    def read_probe(self, pid, n):
+        out = np.empty(n, dtype=np.float64)
+        got = C.c_size_t()
+        check(lib().fdtd_plasma_read_probe(self.h, pid, out.ctypes.data_as(_dp), n, C.byref(got)), "read_probe")
+        return out[: got.value]
+
+    def save_state(self):
+        n = C.c_size_t()
+        check(lib().fdtd_plasma_state_size(self.h, C.byref(n)), "state_size")
+        buf = np.empty(n.value, dtype=np.uint8)
+        check(lib().fdtd_plasma_save_state(self.h, buf.ctypes.data_as(C.c_void_p), buf.size), "save_state")
+        return buf
+
+    def load_state(self, buf):
+        check(lib().fdtd_plasma_load_state(self.h, buf.ctypes.data_as(C.c_void_p), buf.size), "load_state")
+
+    def last_run_ms(self):
+        ms = C.c_double()
+        check(lib().fdtd_plasma_last_run_ms(self.h, C.byref(ms)), "last_run_ms")
+        return ms.value

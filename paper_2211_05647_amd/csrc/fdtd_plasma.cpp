@@ -1,0 +1,823 @@
+// fdtd_plasma.cpp -- host side of the C ABI declared in include/fdtd_plasma.h.
+//
+// Validates the problem statement, builds every table in FP64 (velocity grid, the
+// frozen Maxwellian F0 and its derivative, collision-frequency shapes, moment weights,
+// CPML profiles), rounds each table once to the storage precision, carves the device
+// workspace, and enqueues the step kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fdtd_plasma.h"
+#include "common.h"
+#include "host_internal.h"
+
+using namespace fdtdp;
+
+namespace fdtdp {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(FDTD_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+VTable build_vtable(int dims, int nv, double vmax_over_vth, double te_ev, int nu_model,
+                    double dt) {
+  VTable t;
+  t.nv = nv;
+  t.vth = std::sqrt(kQe * te_ev / kMe);
+  t.dv = 2.0 * vmax_over_vth * t.vth / nv;
+  t.v.resize(nv);
+  t.f.resize(nv);
+  double norm = 0.0;
+  for (int j = 0; j < nv; ++j) {
+    t.v[j] = (j - 0.5 * (nv - 1)) * t.dv;
+    t.f[j] = std::exp(-t.v[j] * t.v[j] / (2.0 * t.vth * t.vth));
+    norm += t.f[j];
+  }
+  norm *= t.dv;
+  for (int j = 0; j < nv; ++j) t.f[j] /= norm;
+  // mean speed over the Maxwellian (1V: |v|, 2V: |(vx, vy)|)
+  double mean = 0.0;
+  if (dims == 1) {
+    for (int j = 0; j < nv; ++j) mean += std::fabs(t.v[j]) * t.f[j] * t.dv;
+  } else {
+    for (int a = 0; a < nv; ++a)
+      for (int b = 0; b < nv; ++b)
+        mean += std::sqrt(t.v[a] * t.v[a] + t.v[b] * t.v[b]) * t.f[a] * t.f[b] * t.dv * t.dv;
+  }
+  t.mean_speed = mean;
+  t.nu_model = nu_model;
+  t.dt = dt;
+  return t;
+}
+
+size_t Carver::take(size_t bytes) {
+  size_t off = (size_ + 255) & ~size_t(255);
+  size_ = off + bytes;
+  return off;
+}
+
+}  // namespace fdtdp
+
+// ----------------------------------------------------------------------------------
+// 1D layout: state arrays of every run first (contiguous, saved/loaded as one blob),
+// then probe rings, then read-only tables, run descriptors and tiles.
+// ----------------------------------------------------------------------------------
+namespace {
+
+struct RunSpec1D {
+  fdtd_grid g;
+  fdtd_profile p;          // p.ne / p.nu_mean point into the owned copies below
+  fdtd_source s;
+  int64_t steps;
+  std::vector<double> ne, nu;
+};
+
+int validate_1d(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s, bool batch) {
+  if (!g || !p) return fail(FDTD_EINVAL, "null grid or profile");
+  if (g->dims != 1) return fail(FDTD_EINVAL, "dims must be 1 here");
+  if (g->nx < 8 || g->nx > (1 << 28)) return fail(FDTD_EINVAL, "nx out of range: %d", g->nx);
+  if (!(g->dx > 0.0) || !std::isfinite(g->dx)) return fail(FDTD_EINVAL, "dx must be > 0");
+  if (!(g->courant > 0.0) || g->courant > 1.0)
+    return fail(FDTD_EINVAL, "1D Courant number must lie in (0, 1], got %g", g->courant);
+  if (g->precision != FDTD_FP32 && g->precision != FDTD_FP64)
+    return fail(FDTD_EINVAL, "unknown precision %d", g->precision);
+  if (batch && g->precision != FDTD_FP32)
+    return fail(FDTD_EINVAL, "batched runs are FP32");
+  if (g->boundary != FDTD_BC_PEC && g->boundary != FDTD_BC_MUR1)
+    return fail(FDTD_EINVAL, "1D boundary must be PEC or MUR1");
+  if (!is_pow2(p->nv) || p->nv < 8 || p->nv > 1024)
+    return fail(FDTD_EINVAL, "nv must be a power of two in [8, 1024], got %d", p->nv);
+  if (!(p->te_ev > 0.0) || !(p->vmax_over_vth > 0.0))
+    return fail(FDTD_EINVAL, "te_ev and vmax_over_vth must be > 0");
+  if (p->nu_model != FDTD_NU_HARD_SPHERE && p->nu_model != FDTD_NU_CONST)
+    return fail(FDTD_EINVAL, "unknown nu_model %d", p->nu_model);
+  if (p->closure != FDTD_CLOSURE_KINETIC)
+    return fail(FDTD_EINVAL, "1D runs take the kinetic closure");
+  if (!p->ne || !p->nu_mean) return fail(FDTD_EINVAL, "null ne or nu_mean");
+  const int nx = g->nx;
+  for (int i = 0; i <= nx; ++i) {
+    if (!(p->ne[i] >= 0.0) || !std::isfinite(p->ne[i]))
+      return fail(FDTD_EINVAL, "ne[%d] must be finite and >= 0", i);
+    if (!(p->nu_mean[i] >= 0.0) || !std::isfinite(p->nu_mean[i]))
+      return fail(FDTD_EINVAL, "nu_mean[%d] must be finite and >= 0", i);
+  }
+  if (p->ne[0] > 0 || p->ne[1] > 0 || p->ne[nx - 1] > 0 || p->ne[nx] > 0)
+    return fail(FDTD_EINVAL, "the two end nodes on each side must be vacuum");
+  if (s && s->kind != FDTD_SRC_NONE) {
+    if (s->kind != FDTD_SRC_POINT_SOFT)
+      return fail(FDTD_EINVAL, "1D source must be a point source");
+    if (s->i < 2 || s->i > nx - 2) return fail(FDTD_EINVAL, "source node out of [2, nx-2]");
+    if (!(s->tau_s > 0.0) || !std::isfinite(s->amplitude) || !std::isfinite(s->f_hz) ||
+        !std::isfinite(s->t0_s))
+      return fail(FDTD_EINVAL, "bad source parameters");
+  }
+  return FDTD_OK;
+}
+
+template <class T>
+size_t sz(size_t n) { return n * sizeof(T); }
+
+int default_tile_1d(int half, int elem, int nx, int ncell) {
+  // about 32 KB of F1 per tile, at least 32 nodes, and enough tiles to fill the chip
+  int row = half * elem;
+  int t = std::max(32, std::min(kMaxTile1D, 32768 / std::max(row, 1)));
+  (void)nx;
+  (void)ncell;
+  int p = 32;
+  while (p * 2 <= t) p *= 2;
+  return p;
+}
+
+}  // namespace
+
+struct fdtd_plasma {
+  int dims = 1;
+  int precision = FDTD_FP32;
+  int nruns = 1;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool owns_ws = false;
+  int64_t step = 0;
+  bool started = false;
+  int tile = 0;
+  int cells_per_group = 0;
+  // state region
+  size_t state_off = 0, state_bytes = 0;
+  // 1D
+  std::vector<RunSpec1D> specs;
+  std::vector<Host1D> h1;
+  size_t runs_off = 0, tiles_off = 0;
+  int ntiles = 0;
+  std::vector<int64_t> tile_limit;   // step limit of each tile, non-increasing
+  // probes
+  int max_probes = 0, probe_cap = 0;
+  size_t probe_off = 0;
+  std::vector<ProbeInfo> probes;
+  // 2D
+  Host2D* h2 = nullptr;
+  // timing
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  int64_t last_n = 0;
+};
+
+namespace {
+
+int elem_size(int precision) { return precision == FDTD_FP64 ? 8 : 4; }
+
+// Compute the 1D layout; with h != nullptr also fill in device pointers (ws base).
+size_t layout_1d(fdtd_plasma* h, const std::vector<RunSpec1D>& specs, int precision,
+                 int max_probes, int probe_cap, std::vector<Host1D>* out) {
+  Carver cv;
+  const int es = elem_size(precision);
+  std::vector<Host1D> hs(specs.size());
+  for (size_t r = 0; r < specs.size(); ++r) {
+    const auto& sp = specs[r];
+    Host1D& x = hs[r];
+    x.nx = sp.g.nx;
+    x.nv = sp.p.nv;
+    x.half = sp.p.nv / 2;
+    x.ncell = 0;
+    for (int i = 0; i <= x.nx; ++i) if (sp.p.ne[i] > 0) ++x.ncell;
+    for (int b = 0; b < 2; ++b) x.off_E[b] = cv.take((size_t)(x.nx + 1) * es);
+    for (int b = 0; b < 2; ++b) x.off_H[b] = cv.take((size_t)(x.nx + 1) * es);
+    x.off_J = cv.take((size_t)(x.nx + 1) * es);
+    x.off_df = cv.take((size_t)std::max(x.ncell, 1) * x.half * es);
+  }
+  const size_t state_end = cv.size();
+  const size_t probe_off = cv.take((size_t)std::max(max_probes, 1) * std::max(probe_cap, 1) * es);
+  for (size_t r = 0; r < specs.size(); ++r) {
+    Host1D& x = hs[r];
+    x.off_cell_node = cv.take(sz<int32_t>(std::max(x.ncell, 1)));
+    x.off_tau = cv.take((size_t)std::max(x.ncell, 1) * es);
+    x.off_dens = cv.take((size_t)std::max(x.ncell, 1) * es);
+    x.off_s = cv.take((size_t)x.half * es);
+    x.off_b = cv.take((size_t)x.half * es);
+    x.off_w = cv.take(sz<double>(x.half));
+  }
+  const size_t runs_off = cv.take(specs.size() * (precision == FDTD_FP64 ? sizeof(Run1D<double>)
+                                                                          : sizeof(Run1D<float>)));
+  // tiles: worst case every node its own 32-node tile
+  size_t max_tiles = 0;
+  for (auto& x : hs) max_tiles += (size_t)(x.nx + 1 + 31) / 32;
+  const size_t tiles_off = cv.take(max_tiles * sizeof(Tile1D));
+  if (h) {
+    h->state_off = 0;
+    h->state_bytes = state_end;
+    h->probe_off = probe_off;
+    h->runs_off = runs_off;
+    h->tiles_off = tiles_off;
+  }
+  if (out) *out = hs;
+  return cv.size() + 256;
+}
+
+template <class T>
+int upload_1d(fdtd_plasma* h) {
+  std::vector<Run1D<T>> rd(h->nruns);
+  for (int r = 0; r < h->nruns; ++r) {
+    const RunSpec1D& sp = h->specs[r];
+    Host1D& x = h->h1[r];
+    const double dt = sp.g.courant * sp.g.dx / kC0;
+    x.dt = dt;
+    VTable vt = build_vtable(1, sp.p.nv, sp.p.vmax_over_vth, sp.p.te_ev, sp.p.nu_model, dt);
+    x.vt = vt;
+    const int half = x.half;
+    std::vector<T> s(half), b(half);
+    std::vector<double> w(half);
+    for (int k = 0; k < half; ++k) {
+      const int j = half + k;  // v_j > 0
+      const double g = -vt.v[j] * vt.f[j] / (vt.vth * vt.vth);       // dF0/dv per unit density
+      s[k] = (T)(sp.p.nu_model == FDTD_NU_HARD_SPHERE ? std::fabs(vt.v[j]) / vt.mean_speed : 1.0);
+      b[k] = (T)(2.0 * dt * (kQe / kMe) * g);
+      w[k] = (dt / kEps0) * (-2.0 * kQe * vt.dv) * vt.v[j];
+    }
+    std::vector<int32_t> cn;
+    std::vector<T> tau, dens;
+    for (int i = 0; i <= x.nx; ++i) {
+      if (sp.p.ne[i] > 0) {
+        cn.push_back(i);
+        tau.push_back((T)(dt * sp.p.nu_mean[i]));
+        dens.push_back((T)sp.p.ne[i]);
+      }
+    }
+    x.cell_node = cn;
+    hipError_t e;
+    char* base = h->ws;
+    if (x.ncell > 0) {
+      if ((e = hipMemcpyAsync(base + x.off_cell_node, cn.data(), cn.size() * 4, hipMemcpyHostToDevice, h->stream)) ||
+          (e = hipMemcpyAsync(base + x.off_tau, tau.data(), tau.size() * sizeof(T), hipMemcpyHostToDevice, h->stream)) ||
+          (e = hipMemcpyAsync(base + x.off_dens, dens.data(), dens.size() * sizeof(T), hipMemcpyHostToDevice, h->stream)))
+        return hip_fail(e, "upload cell tables");
+    }
+    if ((e = hipMemcpyAsync(base + x.off_s, s.data(), half * sizeof(T), hipMemcpyHostToDevice, h->stream)) ||
+        (e = hipMemcpyAsync(base + x.off_b, b.data(), half * sizeof(T), hipMemcpyHostToDevice, h->stream)) ||
+        (e = hipMemcpyAsync(base + x.off_w, w.data(), half * sizeof(double), hipMemcpyHostToDevice, h->stream)))
+      return hip_fail(e, "upload velocity tables");
+
+    Run1D<T>& R = rd[r];
+    std::memset(&R, 0, sizeof R);
+    for (int k = 0; k < 2; ++k) {
+      R.E[k] = reinterpret_cast<T*>(base + x.off_E[k]);
+      R.H[k] = reinterpret_cast<T*>(base + x.off_H[k]);
+    }
+    R.J = reinterpret_cast<T*>(base + x.off_J);
+    R.df = reinterpret_cast<T*>(base + x.off_df);
+    R.cell_node = reinterpret_cast<const int32_t*>(base + x.off_cell_node);
+    R.tau = reinterpret_cast<const T*>(base + x.off_tau);
+    R.dens = reinterpret_cast<const T*>(base + x.off_dens);
+    R.s_bin = reinterpret_cast<const T*>(base + x.off_s);
+    R.b_bin = reinterpret_cast<const T*>(base + x.off_b);
+    R.w_bin = reinterpret_cast<const double*>(base + x.off_w);
+    R.nx = x.nx;
+    R.ncell = x.ncell;
+    R.half = half;
+    R.bc = sp.g.boundary == FDTD_BC_MUR1 ? 1 : 0;
+    R.S = (T)sp.g.courant;
+    R.q = (T)((sp.g.courant - 1.0) / (sp.g.courant + 1.0));
+    R.src_node = (sp.s.kind == FDTD_SRC_POINT_SOFT && sp.s.amplitude != 0.0) ? sp.s.i : -1;
+    R.src_amp = sp.s.amplitude;
+    R.src_w = 2.0 * M_PI * sp.s.f_hz;
+    R.src_tau = sp.s.kind != FDTD_SRC_NONE ? sp.s.tau_s : 1.0;
+    R.src_t0 = sp.s.t0_s;
+    R.dt = dt;
+    R.step_limit = sp.steps;
+    R.nprobe = 0;
+    R.probe_cap = std::max(h->probe_cap, 1);
+    R.probe_buf = reinterpret_cast<T*>(base + h->probe_off);
+  }
+  // probes
+  for (size_t p = 0; p < h->probes.size(); ++p) {
+    const ProbeInfo& pi = h->probes[p];
+    Run1D<T>& R = rd[pi.run];
+    R.probe_node[R.nprobe] = pi.i;
+    R.probe_field[R.nprobe] = pi.field == FDTD_F_E ? 0 : (pi.field == FDTD_F_H ? 1 : 2);
+    R.nprobe++;
+  }
+  // probe rings are per handle: shift each run's buffer to its first probe id
+  for (int r = 0; r < h->nruns; ++r) {
+    int first = -1;
+    for (size_t p = 0; p < h->probes.size(); ++p)
+      if (h->probes[p].run == r) { first = (int)p; break; }
+    if (first >= 0) rd[r].probe_buf += (size_t)first * rd[r].probe_cap;
+  }
+  hipError_t e = hipMemcpyAsync(h->ws + h->runs_off, rd.data(), rd.size() * sizeof(Run1D<T>),
+                                hipMemcpyHostToDevice, h->stream);
+  if (e) return hip_fail(e, "upload run descriptors");
+  return FDTD_OK;
+}
+
+int build_tiles_1d(fdtd_plasma* h) {
+  std::vector<std::pair<int64_t, Tile1D>> all;
+  for (int r = 0; r < h->nruns; ++r) {
+    const Host1D& x = h->h1[r];
+    const int es = elem_size(h->precision);
+    int tile = h->tile > 0 ? h->tile : default_tile_1d(x.half, es, x.nx, x.ncell);
+    tile = std::max(32, std::min(kMaxTile1D, tile));
+    int c = 0;
+    for (int n0 = 0; n0 <= x.nx; n0 += tile) {
+      Tile1D t;
+      t.run = r;
+      t.node0 = n0;
+      t.node1 = std::min(x.nx + 1, n0 + tile);
+      t.cell0 = c;
+      while (c < x.ncell && x.cell_node[c] < t.node1) ++c;
+      t.cell1 = c;
+      all.push_back({h->specs[r].steps, t});
+    }
+  }
+  // longest runs first: at batch step s the active tiles are a prefix
+  std::stable_sort(all.begin(), all.end(),
+                   [](const auto& a, const auto& b) { return a.first > b.first; });
+  std::vector<Tile1D> tiles;
+  h->tile_limit.clear();
+  for (auto& pr : all) {
+    tiles.push_back(pr.second);
+    h->tile_limit.push_back(pr.first);
+  }
+  h->ntiles = (int)tiles.size();
+  hipError_t e = hipMemcpyAsync(h->ws + h->tiles_off, tiles.data(), tiles.size() * sizeof(Tile1D),
+                                hipMemcpyHostToDevice, h->stream);
+  if (e) return hip_fail(e, "upload tiles");
+  return FDTD_OK;
+}
+
+int finish_upload(fdtd_plasma* h) {
+  int rc;
+  if (h->dims == 1) {
+    rc = h->precision == FDTD_FP64 ? upload_1d<double>(h) : upload_1d<float>(h);
+    if (rc) return rc;
+    rc = build_tiles_1d(h);
+    if (rc) return rc;
+  } else {
+    rc = upload_2d(h->h2, h->ws, h->stream, h->probes, h->probe_off, h->probe_cap);
+    if (rc) return rc;
+  }
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e) return hip_fail(e, "synchronise after upload");
+  return FDTD_OK;
+}
+
+int attach_workspace(fdtd_plasma* h, const fdtd_device* dev, size_t need) {
+  if (dev->workspace) {
+    if (dev->workspace_bytes < need)
+      return fail(FDTD_ENOMEM, "workspace has %zu bytes, need %zu", dev->workspace_bytes, need);
+    h->ws = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(dev->workspace) + 255) & ~uintptr_t(255));
+    h->ws_bytes = dev->workspace_bytes;
+    h->owns_ws = false;
+  } else {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, need);
+    if (e) return fail(FDTD_ENOMEM, "hipMalloc(%zu): %s", need, hipGetErrorString(e));
+    h->ws = reinterpret_cast<char*>(p);
+    h->ws_bytes = need;
+    h->owns_ws = true;
+  }
+  // zero the evolving state (fields, F1, CPML memory) and the probe rings
+  hipError_t e = hipMemsetAsync(h->ws + h->state_off, 0, h->state_bytes, h->stream);
+  if (e) return hip_fail(e, "clear state");
+  return FDTD_OK;
+}
+
+int check_device(const fdtd_device* dev) {
+  if (!dev) return fail(FDTD_EINVAL, "null device binding");
+  if (dev->max_probes < 0 || dev->max_probes > kMaxProbes)
+    return fail(FDTD_EINVAL, "max_probes must lie in [0, %d]", kMaxProbes);
+  if (dev->probe_capacity < 0) return fail(FDTD_EINVAL, "probe_capacity < 0");
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e || n <= 0) return fail(FDTD_EDEVICE, "no HIP device");
+  if (dev->device < 0 || dev->device >= n) return fail(FDTD_EINVAL, "device %d out of range", dev->device);
+  e = hipSetDevice(dev->device);
+  if (e) return hip_fail(e, "hipSetDevice");
+  return FDTD_OK;
+}
+
+int create_1d(int nruns, const fdtd_grid* grids, const fdtd_profile* profiles,
+              const fdtd_source* sources, const int64_t* steps, const fdtd_device* dev,
+              fdtd_plasma** out, bool batch) {
+  int rc = check_device(dev);
+  if (rc) return rc;
+  fdtd_plasma* h = new (std::nothrow) fdtd_plasma();
+  if (!h) return fail(FDTD_ENOMEM, "host allocation");
+  h->dims = 1;
+  h->nruns = nruns;
+  h->precision = grids[0].precision;
+  h->device = dev->device;
+  h->stream = reinterpret_cast<hipStream_t>(dev->hip_stream);
+  h->max_probes = dev->max_probes;
+  h->probe_cap = dev->probe_capacity;
+  h->specs.resize(nruns);
+  for (int r = 0; r < nruns; ++r) {
+    h->specs[r].g = grids[r];
+    h->specs[r].p = profiles[r];
+    // inputs are copied: the caller may free its arrays once create returns
+    const size_t n = (size_t)grids[r].nx + 1;
+    h->specs[r].ne.assign(profiles[r].ne, profiles[r].ne + n);
+    h->specs[r].nu.assign(profiles[r].nu_mean, profiles[r].nu_mean + n);
+    h->specs[r].p.ne = h->specs[r].ne.data();
+    h->specs[r].p.nu_mean = h->specs[r].nu.data();
+    fdtd_source none{};
+    h->specs[r].s = sources ? sources[r] : none;
+    h->specs[r].steps = (batch && steps) ? steps[r] : INT64_MAX;
+  }
+  const size_t need = layout_1d(h, h->specs, h->precision, h->max_probes, h->probe_cap, &h->h1);
+  rc = attach_workspace(h, dev, need);
+  if (!rc) rc = finish_upload(h);
+  if (!rc) {
+    hipError_t e = hipEventCreate(&h->ev0);
+    if (!e) e = hipEventCreate(&h->ev1);
+    if (e) rc = hip_fail(e, "hipEventCreate");
+  }
+  if (rc) {
+    fdtd_plasma_destroy(h);
+    return rc;
+  }
+  *out = h;
+  return FDTD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fdtd_plasma_workspace_size(const fdtd_grid* grid, const fdtd_profile* profile,
+                               const fdtd_device* dev, size_t* bytes) {
+  if (!grid || !profile || !bytes) return fail(FDTD_EINVAL, "null argument");
+  const int mp = dev ? dev->max_probes : 0, pc = dev ? dev->probe_capacity : 0;
+  if (grid->dims == 2) {
+    int rc = validate_2d(grid, profile, nullptr);
+    if (rc) return rc;
+    *bytes = workspace_2d(grid, profile, mp, pc);
+    return FDTD_OK;
+  }
+  int rc = validate_1d(grid, profile, nullptr, false);
+  if (rc) return rc;
+  std::vector<RunSpec1D> specs(1);
+  specs[0].g = *grid;
+  specs[0].p = *profile;
+  *bytes = layout_1d(nullptr, specs, grid->precision, mp, pc, nullptr);
+  return FDTD_OK;
+}
+
+int fdtd_plasma_workspace_size_batch(int32_t nruns, const fdtd_grid* grids,
+                                     const fdtd_profile* profiles, const fdtd_device* dev,
+                                     size_t* bytes) {
+  if (nruns <= 0 || !grids || !profiles || !bytes) return fail(FDTD_EINVAL, "bad batch arguments");
+  std::vector<RunSpec1D> specs(nruns);
+  for (int r = 0; r < nruns; ++r) {
+    int rc = validate_1d(&grids[r], &profiles[r], nullptr, true);
+    if (rc) return rc;
+    specs[r].g = grids[r];
+    specs[r].p = profiles[r];
+  }
+  *bytes = layout_1d(nullptr, specs, FDTD_FP32, dev ? dev->max_probes : 0,
+                     dev ? dev->probe_capacity : 0, nullptr);
+  return FDTD_OK;
+}
+
+int fdtd_plasma_create(const fdtd_grid* grid, const fdtd_profile* profile,
+                       const fdtd_source* source, const fdtd_device* dev, fdtd_plasma** out) {
+  if (!grid || !profile || !out) return fail(FDTD_EINVAL, "null argument");
+  if (grid->dims == 2) {
+    int rc = validate_2d(grid, profile, source);
+    if (rc) return rc;
+    rc = check_device(dev);
+    if (rc) return rc;
+    fdtd_plasma* h = new (std::nothrow) fdtd_plasma();
+    if (!h) return fail(FDTD_ENOMEM, "host allocation");
+    h->dims = 2;
+    h->nruns = 1;
+    h->precision = grid->precision;
+    h->device = dev->device;
+    h->stream = reinterpret_cast<hipStream_t>(dev->hip_stream);
+    h->max_probes = dev->max_probes;
+    h->probe_cap = dev->probe_capacity;
+    size_t state_bytes = 0, probe_off = 0;
+    h->h2 = make_2d(grid, profile, source, dev->max_probes, dev->probe_capacity, &state_bytes,
+                    &probe_off);
+    if (!h->h2) {
+      delete h;
+      return fail(FDTD_ENOMEM, "host allocation (2D)");
+    }
+    h->state_off = 0;
+    h->state_bytes = state_bytes;
+    h->probe_off = probe_off;
+    int rc2 = attach_workspace(h, dev, workspace_2d(grid, profile, dev->max_probes, dev->probe_capacity));
+    if (!rc2) rc2 = finish_upload(h);
+    if (!rc2) {
+      hipError_t e = hipEventCreate(&h->ev0);
+      if (!e) e = hipEventCreate(&h->ev1);
+      if (e) rc2 = hip_fail(e, "hipEventCreate");
+    }
+    if (rc2) {
+      fdtd_plasma_destroy(h);
+      return rc2;
+    }
+    *out = h;
+    return FDTD_OK;
+  }
+  int rc = validate_1d(grid, profile, source, false);
+  if (rc) return rc;
+  return create_1d(1, grid, profile, source, nullptr, dev, out, false);
+}
+
+int fdtd_plasma_create_batch(int32_t nruns, const fdtd_grid* grids, const fdtd_profile* profiles,
+                             const fdtd_source* sources, const int64_t* steps,
+                             const fdtd_device* dev, fdtd_plasma** out) {
+  if (nruns <= 0 || !grids || !profiles || !steps || !out)
+    return fail(FDTD_EINVAL, "bad batch arguments");
+  for (int r = 0; r < nruns; ++r) {
+    int rc = validate_1d(&grids[r], &profiles[r], sources ? &sources[r] : nullptr, true);
+    if (rc) return fail(rc, "run %d: %s", r, g_last_error.c_str());
+    if (steps[r] < 0) return fail(FDTD_EINVAL, "run %d: negative step count", r);
+  }
+  return create_1d(nruns, grids, profiles, sources, steps, dev, out, true);
+}
+
+int fdtd_plasma_step(fdtd_plasma* h) { return fdtd_plasma_run(h, 1); }
+
+int fdtd_plasma_run(fdtd_plasma* h, int64_t nsteps) {
+  if (!h) return fail(FDTD_EINVAL, "null handle");
+  if (nsteps < 0) return fail(FDTD_EINVAL, "negative step count");
+  hipError_t e = hipSetDevice(h->device);
+  if (e) return hip_fail(e, "hipSetDevice");
+  h->started = true;
+  if ((e = hipEventRecord(h->ev0, h->stream))) return hip_fail(e, "hipEventRecord");
+  for (int64_t k = 0; k < nsteps; ++k) {
+    const int64_t s = h->step + k;
+    if (h->dims == 1) {
+      // active tiles: those whose run still has steps left (limits are non-increasing)
+      int n = h->ntiles;
+      if (h->nruns > 1) {
+        n = (int)(std::upper_bound(h->tile_limit.begin(), h->tile_limit.end(), s,
+                                   [](int64_t v, int64_t lim) { return v >= lim; }) -
+                  h->tile_limit.begin());
+      }
+      e = h->precision == FDTD_FP64
+              ? launch_step1d<double>(h->ws + h->runs_off, h->ws + h->tiles_off, n, s, h->stream)
+              : launch_step1d<float>(h->ws + h->runs_off, h->ws + h->tiles_off, n, s, h->stream);
+    } else {
+      e = launch_step2d(h->h2, s, h->stream);
+    }
+    if (e) return hip_fail(e, "launch step kernel");
+  }
+  if ((e = hipEventRecord(h->ev1, h->stream))) return hip_fail(e, "hipEventRecord");
+  h->step += nsteps;
+  h->last_n = nsteps;
+  return FDTD_OK;
+}
+
+int fdtd_plasma_steps(const fdtd_plasma* h, int64_t* steps) {
+  if (!h || !steps) return fail(FDTD_EINVAL, "null argument");
+  *steps = h->step;
+  return FDTD_OK;
+}
+
+int fdtd_plasma_last_run_ms(fdtd_plasma* h, double* ms) {
+  if (!h || !ms) return fail(FDTD_EINVAL, "null argument");
+  if (h->last_n <= 0) return fail(FDTD_ESTATE, "no run recorded");
+  hipError_t e = hipEventSynchronize(h->ev1);
+  if (e) return hip_fail(e, "hipEventSynchronize");
+  float t = 0.f;
+  e = hipEventElapsedTime(&t, h->ev0, h->ev1);
+  if (e) return hip_fail(e, "hipEventElapsedTime");
+  *ms = (double)t / (double)h->last_n;
+  return FDTD_OK;
+}
+
+int fdtd_plasma_field_size(const fdtd_plasma* h, int32_t run, int32_t field, size_t* n) {
+  if (!h || !n) return fail(FDTD_EINVAL, "null argument");
+  if (run < 0 || run >= h->nruns) return fail(FDTD_ERANGE, "run %d out of range", run);
+  if (h->dims == 2) return field_size_2d(h->h2, field, n);
+  const Host1D& x = h->h1[run];
+  switch (field) {
+    case FDTD_F_E: case FDTD_F_J: *n = x.nx + 1; return FDTD_OK;
+    case FDTD_F_H: *n = x.nx; return FDTD_OK;
+    case FDTD_F_DF: *n = (size_t)x.ncell * x.nv; return FDTD_OK;
+    default: return fail(FDTD_EINVAL, "field %d not defined on a 1D grid", field);
+  }
+}
+
+int fdtd_plasma_read_fields(fdtd_plasma* h, int32_t run, int32_t field, double* dst,
+                            size_t dst_len, int64_t* step_out) {
+  size_t n = 0;
+  int rc = fdtd_plasma_field_size(h, run, field, &n);
+  if (rc) return rc;
+  if (!dst) return fail(FDTD_EINVAL, "null destination");
+  if (dst_len < n) return fail(FDTD_ERANGE, "destination holds %zu values, need %zu", dst_len, n);
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e) return hip_fail(e, "synchronise");
+  if (h->dims == 2) {
+    rc = read_2d(h->h2, h->ws, field, h->step, dst);
+    if (rc) return rc;
+  } else {
+    const Host1D& x = h->h1[run];
+    const int es = elem_size(h->precision);
+    const int64_t srun = std::min<int64_t>(h->step, h->specs[run].steps);
+    const int par = (int)(srun & 1);
+    size_t off = 0, cnt = 0;
+    double scale = 1.0;
+    switch (field) {
+      case FDTD_F_E: off = x.off_E[par]; cnt = x.nx + 1; break;
+      case FDTD_F_H: off = x.off_H[par]; cnt = x.nx; scale = 1.0 / kEta0; break;
+      case FDTD_F_J: off = x.off_J; cnt = x.nx + 1; scale = kEps0 / x.dt; break;
+      case FDTD_F_DF: off = x.off_df; cnt = (size_t)x.ncell * x.half; break;
+    }
+    std::vector<char> buf(std::max<size_t>(cnt, 1) * es);
+    if (cnt) {
+      e = hipMemcpy(buf.data(), h->ws + off, cnt * es, hipMemcpyDeviceToHost);
+      if (e) return hip_fail(e, "copy field");
+    }
+    auto val = [&](size_t k) -> double {
+      return es == 8 ? reinterpret_cast<double*>(buf.data())[k] : reinterpret_cast<float*>(buf.data())[k];
+    };
+    if (field == FDTD_F_DF) {
+      for (int c = 0; c < x.ncell; ++c)
+        for (int k = 0; k < x.half; ++k) {
+          const double f = val((size_t)c * x.half + k);
+          dst[(size_t)c * x.nv + x.half + k] = f;
+          dst[(size_t)c * x.nv + x.half - 1 - k] = -f;
+        }
+    } else {
+      for (size_t k = 0; k < cnt; ++k) dst[k] = val(k) * scale;
+    }
+    if (step_out) *step_out = srun;
+  }
+  if (step_out && h->dims == 2) *step_out = h->step;
+  for (size_t k = 0; k < n; ++k)
+    if (!std::isfinite(dst[k])) return fail(FDTD_ENUMERIC, "non-finite value at index %zu", k);
+  return FDTD_OK;
+}
+
+int fdtd_plasma_add_probe(fdtd_plasma* h, int32_t run, int32_t field, int32_t i, int32_t j,
+                          int32_t* id) {
+  if (!h || !id) return fail(FDTD_EINVAL, "null argument");
+  if (h->started) return fail(FDTD_ESTATE, "probes must be added before the first step");
+  if ((int)h->probes.size() >= h->max_probes) return fail(FDTD_ERANGE, "no probe slot left");
+  if (h->probe_cap <= 0) return fail(FDTD_ERANGE, "probe_capacity is 0");
+  if (run < 0 || run >= h->nruns) return fail(FDTD_ERANGE, "run out of range");
+  if (h->dims == 1) {
+    const Host1D& x = h->h1[run];
+    if (field != FDTD_F_E && field != FDTD_F_H && field != FDTD_F_J)
+      return fail(FDTD_EINVAL, "1D probes record E, H or J");
+    if (i < 0 || i > x.nx || (field == FDTD_F_H && i >= x.nx)) return fail(FDTD_ERANGE, "probe index out of range");
+    // a run's probes must be consecutive ids (one ring block per run)
+    if (!h->probes.empty() && h->probes.back().run != run) {
+      for (auto& p : h->probes)
+        if (p.run == run) return fail(FDTD_EINVAL, "add all probes of a run consecutively");
+    }
+  } else {
+    int rc = check_probe_2d(h->h2, field, i, j);
+    if (rc) return rc;
+  }
+  ProbeInfo p{run, field, i, j};
+  h->probes.push_back(p);
+  *id = (int)h->probes.size() - 1;
+  return finish_upload(h) ? FDTD_EDEVICE : FDTD_OK;
+}
+
+int fdtd_plasma_read_probe(fdtd_plasma* h, int32_t id, double* dst, size_t dst_len, size_t* n_out) {
+  if (!h || !dst) return fail(FDTD_EINVAL, "null argument");
+  if (id < 0 || id >= (int)h->probes.size()) return fail(FDTD_ERANGE, "probe id out of range");
+  const ProbeInfo& p = h->probes[id];
+  int64_t steps = h->step;
+  if (h->dims == 1) steps = std::min<int64_t>(steps, h->specs[p.run].steps);
+  const size_t n = (size_t)std::min<int64_t>(steps, h->probe_cap);
+  if (dst_len < n) return fail(FDTD_ERANGE, "destination holds %zu values, need %zu", dst_len, n);
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e) return hip_fail(e, "synchronise");
+  const int es = elem_size(h->precision);
+  std::vector<char> buf((size_t)h->probe_cap * es);
+  e = hipMemcpy(buf.data(), h->ws + h->probe_off + (size_t)id * h->probe_cap * es,
+                buf.size(), hipMemcpyDeviceToHost);
+  if (e) return hip_fail(e, "copy probe");
+  double scale = 1.0;
+  if (h->dims == 1) {
+    const Host1D& x = h->h1[p.run];
+    if (p.field == FDTD_F_H) scale = 1.0 / kEta0;
+    if (p.field == FDTD_F_J) scale = kEps0 / x.dt;
+  } else {
+    scale = probe_scale_2d(h->h2, p.field);
+  }
+  for (size_t k = 0; k < n; ++k) {
+    const size_t s = (size_t)((steps - (int64_t)n + (int64_t)k) % h->probe_cap);
+    dst[k] = scale * (es == 8 ? reinterpret_cast<double*>(buf.data())[s] : reinterpret_cast<float*>(buf.data())[s]);
+  }
+  if (n_out) *n_out = n;
+  return FDTD_OK;
+}
+
+int fdtd_plasma_state_size(const fdtd_plasma* h, size_t* bytes) {
+  if (!h || !bytes) return fail(FDTD_EINVAL, "null argument");
+  *bytes = 16 + h->state_bytes + (size_t)h->max_probes * h->probe_cap * elem_size(h->precision);
+  return FDTD_OK;
+}
+
+int fdtd_plasma_save_state(fdtd_plasma* h, void* dst, size_t len) {
+  size_t need = 0;
+  int rc = fdtd_plasma_state_size(h, &need);
+  if (rc) return rc;
+  if (!dst || len < need) return fail(FDTD_ERANGE, "state buffer holds %zu bytes, need %zu", len, need);
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e) return hip_fail(e, "synchronise");
+  char* d = reinterpret_cast<char*>(dst);
+  const int64_t magic = 0x46445444504c534dLL;
+  std::memcpy(d, &magic, 8);
+  std::memcpy(d + 8, &h->step, 8);
+  e = hipMemcpy(d + 16, h->ws + h->state_off, h->state_bytes, hipMemcpyDeviceToHost);
+  if (!e && need > 16 + h->state_bytes)
+    e = hipMemcpy(d + 16 + h->state_bytes, h->ws + h->probe_off, need - 16 - h->state_bytes,
+                  hipMemcpyDeviceToHost);
+  if (e) return hip_fail(e, "copy state");
+  return FDTD_OK;
+}
+
+int fdtd_plasma_load_state(fdtd_plasma* h, const void* src, size_t len) {
+  size_t need = 0;
+  int rc = fdtd_plasma_state_size(h, &need);
+  if (rc) return rc;
+  if (!src || len != need) return fail(FDTD_ERANGE, "state blob has %zu bytes, need %zu", len, need);
+  const char* s = reinterpret_cast<const char*>(src);
+  int64_t magic = 0, step = 0;
+  std::memcpy(&magic, s, 8);
+  std::memcpy(&step, s + 8, 8);
+  if (magic != 0x46445444504c534dLL || step < 0) return fail(FDTD_EINVAL, "not a state blob");
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e) return hip_fail(e, "synchronise");
+  e = hipMemcpy(h->ws + h->state_off, s + 16, h->state_bytes, hipMemcpyHostToDevice);
+  if (!e && need > 16 + h->state_bytes)
+    e = hipMemcpy(h->ws + h->probe_off, s + 16 + h->state_bytes, need - 16 - h->state_bytes,
+                  hipMemcpyHostToDevice);
+  if (e) return hip_fail(e, "copy state");
+  h->step = step;
+  h->started = true;
+  return FDTD_OK;
+}
+
+int fdtd_plasma_set_tiling(fdtd_plasma* h, int32_t tile, int32_t cells_per_group) {
+  if (!h) return fail(FDTD_EINVAL, "null handle");
+  if (h->started) return fail(FDTD_ESTATE, "tiling must be set before the first step");
+  if (tile < 0 || cells_per_group < 0) return fail(FDTD_EINVAL, "negative tiling");
+  if (h->dims == 1) {
+    if (tile && (tile < 32 || tile > kMaxTile1D))
+      return fail(FDTD_EINVAL, "1D tile must lie in [32, %d]", kMaxTile1D);
+    if (tile) h->tile = tile;
+    if (cells_per_group) h->cells_per_group = cells_per_group;
+    int rc = build_tiles_1d(h);
+    if (rc) return rc;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    return e ? hip_fail(e, "synchronise") : FDTD_OK;
+  }
+  return set_tiling_2d(h->h2, h->ws, h->stream, tile, cells_per_group);
+}
+
+void fdtd_plasma_destroy(fdtd_plasma* h) {
+  if (!h) return;
+  hipSetDevice(h->device);
+  if (h->stream) hipStreamSynchronize(h->stream);
+  if (h->ev0) hipEventDestroy(h->ev0);
+  if (h->ev1) hipEventDestroy(h->ev1);
+  if (h->owns_ws && h->ws) hipFree(h->ws);
+  if (h->h2) destroy_2d(h->h2);
+  delete h;
+}
+
+const char* fdtd_plasma_strerror(int code) {
+  switch (code) {
+    case FDTD_OK: return "ok";
+    case FDTD_EINVAL: return "invalid argument";
+    case FDTD_ENOMEM: return "out of memory or workspace too small";
+    case FDTD_EDEVICE: return "HIP device error";
+    case FDTD_ERANGE: return "out of range";
+    case FDTD_ENUMERIC: return "non-finite value in the fields";
+    case FDTD_ESTATE: return "call not allowed in the current state";
+    default: return "unknown error";
+  }
+}
+
+const char* fdtd_plasma_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

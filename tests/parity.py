@@ -1,0 +1,54 @@
+"""Helpers shared by the GPU parity tests: run a workload through the C ABI and through
+the oracle on the same seeded inputs, and compare."""
+import numpy as np
+
+from oracle.core import Oracle1D
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = np.sqrt(np.sum(b * b))
+    return float(np.sqrt(np.sum((a - b) ** 2)) / (den if den > 0 else 1.0))
+
+
+def oracle_1d(run, nx=None):
+    """Oracle for a Run1D, optionally on the prefix [0, nx] of the line (exact as long as
+    the field has not reached the cut: the Yee stencil moves information one node per step)."""
+    n = run.nx if nx is None else nx
+    ne = run.ne[: n + 1].copy()
+    if nx is not None:
+        ne[n - 1:] = 0.0     # the oracle's line ends in vacuum; the field never gets there
+    return Oracle1D(n, run.dx, run.courant, ne, run.nubar[: n + 1].copy(),
+                    nv=run.nv, vmax_over_vth=run.vmax_over_vth, te_ev=run.te_ev,
+                    nu_model=run.nu_model, bc=run.bc, src_node=run.src_node,
+                    src_amp=run.src_amp, src_f=run.src_f, src_tau=run.src_tau,
+                    src_t0=run.src_t0)
+
+
+def space_time_1d(sim, orc, nsteps, every, probes, df_snaps=None):
+    """Advance both sides ``nsteps`` in chunks of ``every``; collect E snapshots (and the
+    probe series) from both.  Returns (gpu, oracle) stacked arrays.  With a list
+    ``df_snaps``, (gpu, oracle) F1 pairs of the oracle's cells are appended after each
+    chunk (a late single snapshot of F1 can be a small residual of a zero-mean drive,
+    so F1 is compared over space and time like the fields)."""
+    from paper_2211_05647_amd import binding as B
+    g_snap, o_snap = [], []
+    g_pr, o_pr = [], []
+    pids = [sim.add_probe(B.F_E, p) for p in probes] if probes else []
+    done = 0
+    while done < nsteps:
+        k = min(every, nsteps - done)
+        sim.run(k)
+        pr, _ = orc.run(k, probes=probes)
+        o_pr.append(pr)
+        done += k
+        g_snap.append(sim.read(B.F_E)[: orc.nx + 1])
+        o_snap.append(orc.E.copy())
+        if df_snaps is not None:
+            gd = sim.read(B.F_DF)[: orc.df.size]
+            df_snaps.append((gd, orc.df.copy()))
+    if pids:
+        g_pr = np.stack([sim.read_probe(p, nsteps) for p in pids], axis=1)
+        o_pr = np.concatenate(o_pr, axis=0)
+    return np.array(g_snap), np.array(o_snap), g_pr, o_pr

@@ -1,0 +1,116 @@
+"""CPU-side checks of the C ABI: the library loads, exports every entry point the
+headers declare, and rejects bad problem statements without touching a device."""
+import ctypes as C
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2211_05647_amd import binding as B
+from paper_2211_05647_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names |= set(re.findall(r"\b(fdtd_\w+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    names = _declared()
+    assert len(names) >= 15
+    for n in sorted(names):
+        assert hasattr(L, n), n
+    # and the binding declares a signature for each of them
+    assert names <= set(B._SIGS), names - set(B._SIGS)
+
+
+def _grid_profile(run, precision=B.FP32):
+    g = B.make_grid(1, run.nx, 1, run.dx, run.courant, precision, B.BC_MUR1, 0)
+    ne = np.ascontiguousarray(run.ne)
+    nu = np.ascontiguousarray(run.nubar)
+    p = B.Profile(ne.ctypes.data_as(C.POINTER(C.c_double)), nu.ctypes.data_as(C.POINTER(C.c_double)),
+                  run.te_ev, run.nv, run.vmax_over_vth, 0, 0, None)
+    return g, p, (ne, nu)
+
+
+def test_workspace_size_scales_with_problem():
+    L = B.lib()
+    run = W.c0()
+    g, p, keep = _grid_profile(run, B.FP64)
+    n64 = C.c_size_t()
+    assert L.fdtd_plasma_workspace_size(C.byref(g), C.byref(p), None, C.byref(n64)) == 0
+    g.precision = B.FP32
+    n32 = C.c_size_t()
+    assert L.fdtd_plasma_workspace_size(C.byref(g), C.byref(p), None, C.byref(n32)) == 0
+    # F1 dominates: 200 nodes x 32 stored bins x 8 or 4 bytes
+    assert n64.value > n32.value > 200 * 32 * 4
+
+
+@pytest.mark.parametrize("mutate", [
+    lambda g, p: setattr(g, "courant", 1.5),
+    lambda g, p: setattr(g, "courant", 0.0),
+    lambda g, p: setattr(g, "nx", 4),
+    lambda g, p: setattr(g, "dx", -1.0),
+    lambda g, p: setattr(g, "precision", 7),
+    lambda g, p: setattr(g, "boundary", B.BC_CPML),
+    lambda g, p: setattr(p, "nv", 48),
+    lambda g, p: setattr(p, "nv", 4),
+    lambda g, p: setattr(p, "te_ev", 0.0),
+    lambda g, p: setattr(p, "nu_model", 9),
+    lambda g, p: setattr(p, "closure", B.CLOSURE_MLP),
+])
+def test_bad_problem_statements_are_rejected(mutate):
+    L = B.lib()
+    run = W.c0()
+    g, p, keep = _grid_profile(run)
+    mutate(g, p)
+    n = C.c_size_t(12345)
+    rc = L.fdtd_plasma_workspace_size(C.byref(g), C.byref(p), None, C.byref(n))
+    assert rc == B.EINVAL
+    assert n.value == 12345
+    assert len(L.fdtd_plasma_last_error()) > 0
+
+
+def test_plasma_at_the_ends_is_rejected():
+    L = B.lib()
+    run = W.c0()
+    run.ne[1] = 1e18
+    g, p, keep = _grid_profile(run)
+    n = C.c_size_t()
+    assert L.fdtd_plasma_workspace_size(C.byref(g), C.byref(p), None, C.byref(n)) == B.EINVAL
+
+
+def test_negative_density_is_rejected():
+    L = B.lib()
+    run = W.c0()
+    run.ne[500] = -1.0
+    g, p, keep = _grid_profile(run)
+    n = C.c_size_t()
+    assert L.fdtd_plasma_workspace_size(C.byref(g), C.byref(p), None, C.byref(n)) == B.EINVAL
+
+
+def test_strerror_names_every_code():
+    L = B.lib()
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert L.fdtd_plasma_strerror(code).decode() != "unknown error"
+    assert L.fdtd_plasma_strerror(-99).decode() == "unknown error"
+
+
+def test_seeded_workloads_are_reproducible():
+    a, b = W.c1(nx=4096, steps=10), W.c1(nx=4096, steps=10)
+    assert np.array_equal(a.ne, b.ne) and np.array_equal(a.nubar, b.nubar)
+    r = a.ne[400:a.nx - 100]
+    ratio = np.sqrt(r * W._QE ** 2 / (W._EPS0 * W._ME)) / (2 * np.pi * W.F_REF)
+    assert 0.2 <= ratio.min() and ratio.max() <= 2.0
+    runs = W.c3()
+    assert len(runs) == 256 and {x.nv for x in runs} == {64, 128, 256}
+    assert all(500 <= x.nx <= 20000 and x.steps == 2 * x.nx for x in runs)
