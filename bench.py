@@ -85,7 +85,10 @@ def main():
     run = W.c1()
     print(f"[bench] workload c1: Nx={run.nx} Nv={run.nv} plasma cells={run.plasma_cells}",
           file=sys.stderr, flush=True)
-    sim = B.Sim(run, precision=B.FP32, tile=args.tile)
+    from paper_2211_05647_amd import autotune
+    tile = args.tile or autotune.lookup(run, B.FP32)
+    print(f"[bench] tile={tile or 'default'}", file=sys.stderr, flush=True)
+    sim = B.Sim(run, precision=B.FP32, tile=tile)
     sim.run(args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -119,7 +122,8 @@ def main():
         "dtype": "f32 (f64 moments)",
         "data": "synthetic, seeded",
         "config": {"workload": "1D Yee + 1V kinetic, Nx=65536, Nv=512, FP32",
-                   "nx": nx, "nv": nv, "plasma_cells": ncell, "steps": args.steps},
+                   "nx": nx, "nv": nv, "plasma_cells": ncell, "steps": args.steps,
+                   "tile": tile},
         "stored_bin_updates_per_s": ncell * half * args.steps / wall,
         "roofline": {"bound": "hbm", "kernel": "k_step1d<float>", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

@@ -6,8 +6,8 @@
 namespace fdtdp {
 
 constexpr int kMaxProbes = 16;
-constexpr int kMaxTile1D = 1024;   // nodes per 1D tile (LDS holds the tile's J)
 constexpr int kBlock = 256;        // threads per work-group of the step kernels
+constexpr int kMaxTile1D = 256;    // nodes per 1D tile: one node per thread
 
 // 16-byte vector of the storage type: 4 floats or 2 doubles per lane per chunk.
 template <class T> struct Vec;

@@ -3,38 +3,95 @@
 //
 // One work-group owns a tile of E nodes [node0, node1) and the plasma nodes inside
 // it [cell0, cell1).  Per step it
-//   1. advances F1 of its plasma nodes with E^n (Crank-Nicolson in the collision term,
+//   1. loads E^n and H^{n-1/2} around its nodes into registers (and E^n into LDS);
+//   2. advances F1 of its plasma nodes with E^n (Crank-Nicolson in the collision term,
 //      the f_1x update of section 5.2) and reduces the current moment
 //      J = -e dv sum_j v_j F1_j in FP64 (half grid: F1 is odd in v, so the sum over
 //      v > 0 bins counts twice), keeping the tile's J in LDS;
-//   2. updates H^{n+1/2} and E^{n+1} of its nodes (Ampere's law minus J), with the
+//   3. updates H^{n+1/2} and E^{n+1} of its nodes (Ampere's law minus J), with the
 //      first-order Mur ends and the soft source.
 // E and H are double-buffered, so halo values are re-derived from the previous
 // buffers and no work-group ever waits for another inside a step.
 //
-// Memory layout of F1: [cell][v > 0 bin], contiguous in the bin index; a wavefront
-// covers one or more cells per pass with 16-byte loads per lane (coalesced rows).
+// F1 layout: [cell][v > 0 bin], contiguous in the bin index.  A group of `lpc` lanes
+// covers one cell row with 16-byte loads (64 lanes x 16 B = one 1 KB row per wave
+// instruction at Nv = 512); each lane group keeps U rows in flight, and the U FP64
+// partial moments are reduced with a reduce-scatter butterfly (log2(U) exchange
+// rounds that halve the values each lane carries, then plain xor rounds).
 #include "common.h"
 
 namespace fdtdp {
 
-template <class T>
-__device__ __forceinline__ void kinetic_tile(const Run1D<T>& R, const T* __restrict__ Ec,
+// Sum U per-lane values over the lpc lanes of each lane group (lpc >= U).  On return,
+// lane `li` of a group holds the total of value index `which`.
+template <int U>
+__device__ __forceinline__ double group_reduce(double (&a)[U], int lpc, int li, int& which) {
+  if constexpr (U == 1) {
+    double s = a[0];
+    for (int o = lpc >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    which = 0;
+    return s;
+  } else {
+    // requires lpc >= U (the caller handles narrower groups)
+    // reduce-scatter rounds: at each round a lane keeps half of its values and sends
+    // the other half to its partner
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = a[u];
+    int n = U, o = lpc >> 1, sel = 0;
+#pragma unroll
+    for (int r = 0; (1 << r) < U; ++r) {
+      const bool hi = (li & o) != 0;
+      const int h = n >> 1;
+#pragma unroll
+      for (int k = 0; k < U / 2; ++k) {
+        if (k < h) {
+          const double send = hi ? v[k] : v[k + h];
+          const double got = __shfl_xor(send, o);
+          v[k] = (hi ? v[k + h] : v[k]) + got;
+        }
+      }
+      sel = sel * 2 + (hi ? 1 : 0);
+      n = h;
+      o >>= 1;
+    }
+    double s = v[0];
+    for (; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    which = sel;
+    return s;
+  }
+}
+
+// Lane index (within a group) that reports value u after group_reduce<U>.
+template <int U>
+__device__ __forceinline__ int reporter(int u, int lpc) {
+  if (U == 1) return u;
+  int li = 0, o = lpc >> 1;
+  for (int b = U >> 1; b > 0; b >>= 1) {
+    if (u & b) li += o;
+    o >>= 1;
+  }
+  return li;
+}
+
+template <class T, int U>
+__device__ __forceinline__ void kinetic_tile(const Run1D<T>& R, const T* eloc,
                                              const Tile1D& tile, T* jloc) {
   using V = typename Vec<T>::type;
   constexpr int VPL = Vec<T>::n;
   constexpr int kWaves = kBlock / 64;
+  constexpr int CPL = 4 / U;              // chunks per lane this instance handles
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ch = R.half / VPL;            // 16-byte chunks per cell row
   const int lpc = ch < 64 ? ch : 64;      // lanes per cell
-  const int cpl = ch / lpc;               // chunks per lane (<= 4)
-  const int cpw = 64 / lpc;               // cells per wavefront pass
+  const int cpl = ch / lpc;               // chunks per lane (<= CPL by dispatch)
+  const int cpw = 64 / lpc;               // lane groups per wavefront
   const int sub = lane / lpc, li = lane - sub * lpc;
 
-  V s[4], b[4];
-  double w[4][VPL];
+  V s[CPL], b[CPL];
+  double w[CPL][VPL];
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
+  for (int m = 0; m < CPL; ++m) {
     if (m < cpl) {
       const int k = li + m * lpc;
       s[m] = reinterpret_cast<const V*>(R.s_bin)[k];
@@ -44,37 +101,75 @@ __device__ __forceinline__ void kinetic_tile(const Run1D<T>& R, const T* __restr
     }
   }
   V* __restrict__ dfv = reinterpret_cast<V*>(R.df);
-  for (int base = tile.cell0 + wave * cpw; base < tile.cell1; base += kWaves * cpw) {
-    const int c = base + sub;
-    const bool act = c < tile.cell1;
-    double acc = 0.0;
-    int node = 0;
-    if (act) {
-      node = R.cell_node[c];
-      const T ne = R.dens[c] * Ec[node];
-      const T tau = R.tau[c];
-      V* __restrict__ row = dfv + (size_t)c * ch;
+  const int stride = kWaves * cpw * U;
+  for (int base = tile.cell0 + wave * cpw * U; base < tile.cell1; base += stride) {
+    V f[U][CPL];
+    T ne[U], tau[U];
+    int loc[U];
+    // issue every load of the U rows before any arithmetic
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        if (m < cpl) {
-          V f = row[li + m * lpc];
+    for (int u = 0; u < U; ++u) {
+      const int c = base + u * cpw + sub;
+      loc[u] = -1;
+      if (c < tile.cell1) {
+        loc[u] = R.cell_node[c] - tile.node0;
+        tau[u] = R.tau[c];
+        ne[u] = R.dens[c];
+        const V* row = dfv + (size_t)c * ch;
 #pragma unroll
-          for (int v = 0; v < VPL; ++v) {
-            const T x = tau * lane_at(s[m], v);          // dt * nu_j
-            const T r = cn_recip(T(2) + x);
-            const T fv = lane_at(f, v);
-            // F1' = ((2 - x) F1 + 2 dt (e/m) n dF0/dv E) / (2 + x), as an increment of F1
-            const T t = fma(-(x + x), fv, lane_at(b[m], v) * ne);
-            const T fn = fma(t, r, fv);
-            lane_at(f, v) = fn;
-            acc = fma(w[m][v], (double)fn, acc);
+        for (int m = 0; m < CPL; ++m)
+          if (m < cpl) f[u][m] = row[li + m * lpc];
+      }
+    }
+    double acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      acc[u] = 0.0;
+      if (loc[u] >= 0) {
+        const T nE = ne[u] * eloc[loc[u]];
+#pragma unroll
+        for (int m = 0; m < CPL; ++m) {
+          if (m < cpl) {
+#pragma unroll
+            for (int v = 0; v < VPL; ++v) {
+              const T x = tau[u] * lane_at(s[m], v);       // dt * nu_j
+              const T r = cn_recip(T(2) + x);
+              const T fv = lane_at(f[u][m], v);
+              // F1' = ((2 - x) F1 + 2 dt (e/m) n dF0/dv E) / (2 + x), as an increment
+              const T t = fma(-(x + x), fv, lane_at(b[m], v) * nE);
+              const T fn = fma(t, r, fv);
+              lane_at(f[u][m], v) = fn;
+              acc[u] = fma(w[m][v], (double)fn, acc[u]);
+            }
           }
-          row[li + m * lpc] = f;
         }
       }
     }
-    for (int o = lpc >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    if (act && li == 0) jloc[node - tile.node0] = (T)acc;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (loc[u] >= 0) {
+        const int c = base + u * cpw + sub;
+        V* row = dfv + (size_t)c * ch;
+#pragma unroll
+        for (int m = 0; m < CPL; ++m)
+          if (m < cpl) row[li + m * lpc] = f[u][m];
+      }
+    }
+    if (U > 1 && lpc < U) {
+      // tiny rows (fewer lanes than rows in flight): plain all-reduce per row
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        double s = acc[u];
+        for (int o = lpc >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o);
+        if (li == 0 && loc[u] >= 0) jloc[loc[u]] = (T)s;
+      }
+    } else {
+      int which = 0;
+      const double tot = group_reduce<U>(acc, lpc, li, which);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (which == u && li == reporter<U>(u, lpc) && loc[u] >= 0) jloc[loc[u]] = (T)tot;
+    }
   }
 }
 
@@ -83,6 +178,7 @@ __global__ __launch_bounds__(kBlock) void k_step1d(const Run1D<T>* __restrict__ 
                                                    const Tile1D* __restrict__ tiles,
                                                    int64_t step) {
   __shared__ T jloc[kMaxTile1D];
+  __shared__ T eloc[kMaxTile1D];
   const Tile1D tile = tiles[blockIdx.x];
   const Run1D<T>& R = runs[tile.run];
   if (step >= R.step_limit) return;
@@ -91,43 +187,64 @@ __global__ __launch_bounds__(kBlock) void k_step1d(const Run1D<T>* __restrict__ 
   T* __restrict__ En = R.E[par ^ 1];
   const T* __restrict__ Hc = R.H[par];
   T* __restrict__ Hn = R.H[par ^ 1];
-  const int tid = threadIdx.x;
+  const int k = threadIdx.x;
   const int nloc = tile.node1 - tile.node0;
-  for (int k = tid; k < nloc; k += kBlock) jloc[k] = T(0);
-  __syncthreads();
-  if (tile.cell1 > tile.cell0) kinetic_tile<T>(R, Ec, tile, jloc);
+  const int nx = R.nx;
+  const int i = tile.node0 + k;
+  const bool own = k < nloc;
+
+  // 1. this thread's node: E^n at i-1, i, i+1 (and i+2 / i-2 at the ends), H^{n-1/2}
+  T em = T(0), e0 = T(0), ep = T(0), hm = T(0), h0 = T(0), ex = T(0), hx = T(0);
+  if (own) {
+    e0 = Ec[i];
+    if (i > 0) { em = Ec[i - 1]; hm = Hc[i - 1]; }
+    if (i < nx) { ep = Ec[i + 1]; h0 = Hc[i]; }
+    if (i == 0) { ex = Ec[2]; hx = Hc[1]; }
+    if (i == nx) { ex = Ec[nx - 2]; hx = Hc[nx - 2]; }
+    eloc[k] = e0;
+    jloc[k] = T(0);
+  }
   __syncthreads();
 
-  const int nx = R.nx;
-  const T S = R.S;
-  for (int k = tid; k < nloc; k += kBlock) {
-    const int i = tile.node0 + k;
-    T en, hn = T(0);
+  // 2. kinetic F1 update and FP64 current moment of the tile's plasma nodes
+  if (tile.cell1 > tile.cell0) {
+    const int ch = R.half / Vec<T>::n;
+    const int cpl = ch < 64 ? 1 : ch / 64;
+    if (cpl == 1) kinetic_tile<T, 4>(R, eloc, tile, jloc);
+    else if (cpl == 2) kinetic_tile<T, 2>(R, eloc, tile, jloc);
+    else kinetic_tile<T, 1>(R, eloc, tile, jloc);
+  }
+  __syncthreads();
+
+  // 3. H^{n+1/2} and E^{n+1}
+  if (own) {
+    const T S = R.S;
     const T jv = jloc[k];
+    T en, hn = T(0);
     if (i == 0) {
-      hn = h_update(Hc[0], S, Ec[1], Ec[0]);
+      hn = h_update(h0, S, ep, e0);
       if (R.bc == 1) {
-        const T h1 = h_update(Hc[1], S, Ec[2], Ec[1]);
-        const T e1 = e_update(Ec[1], S, h1, hn, T(0));
-        en = fma(R.q, e1 - Ec[0], Ec[1]);
+        const T h1 = h_update(hx, S, ex, ep);
+        const T e1 = e_update(ep, S, h1, hn, T(0));
+        en = fma(R.q, e1 - e0, ep);
       } else {
         en = T(0);
       }
       Hn[0] = hn;
     } else if (i == nx) {
       if (R.bc == 1) {
-        const T ha = h_update(Hc[nx - 1], S, Ec[nx], Ec[nx - 1]);
-        const T hb = h_update(Hc[nx - 2], S, Ec[nx - 1], Ec[nx - 2]);
-        const T e = e_update(Ec[nx - 1], S, ha, hb, T(0));
-        en = fma(R.q, e - Ec[nx], Ec[nx - 1]);
+        const T ha = h_update(hm, S, e0, em);
+        const T hb = h_update(hx, S, em, ex);
+        const T e = e_update(em, S, ha, hb, T(0));
+        en = fma(R.q, e - e0, em);
       } else {
         en = T(0);
       }
     } else {
-      const T hm = h_update(Hc[i - 1], S, Ec[i], Ec[i - 1]);
-      hn = h_update(Hc[i], S, Ec[i + 1], Ec[i]);
+      const T hl = h_update(hm, S, e0, em);
+      hn = h_update(h0, S, ep, e0);
       Hn[i] = hn;
-      en = e_update(Ec[i], S, hn, hm, jv);
+      en = e_update(e0, S, hn, hl, jv);
       if (i == R.src_node)
         en += (T)source_wave((double)(step + 1) * R.dt, R.src_amp, R.src_w, R.src_tau,
                              R.src_t0);
