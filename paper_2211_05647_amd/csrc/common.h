@@ -39,6 +39,58 @@ __device__ __forceinline__ double source_wave(double t, double amp, double w, do
   return amp * sin(w * (t - t0)) * exp(-x * x);
 }
 
+// Sum U per-lane values over the lpc lanes of each lane group (lpc >= U).  On return,
+// lane `li` of a group holds the total of value index `which`.
+template <int U>
+__device__ __forceinline__ double group_reduce(double (&a)[U], int lpc, int li, int& which) {
+  if constexpr (U == 1) {
+    double s = a[0];
+    for (int o = lpc >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    which = 0;
+    return s;
+  } else {
+    // requires lpc >= U (the caller handles narrower groups)
+    // reduce-scatter rounds: at each round a lane keeps half of its values and sends
+    // the other half to its partner
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = a[u];
+    int n = U, o = lpc >> 1, sel = 0;
+#pragma unroll
+    for (int r = 0; (1 << r) < U; ++r) {
+      const bool hi = (li & o) != 0;
+      const int h = n >> 1;
+#pragma unroll
+      for (int k = 0; k < U / 2; ++k) {
+        if (k < h) {
+          const double send = hi ? v[k] : v[k + h];
+          const double got = __shfl_xor(send, o);
+          v[k] = (hi ? v[k + h] : v[k]) + got;
+        }
+      }
+      sel = sel * 2 + (hi ? 1 : 0);
+      n = h;
+      o >>= 1;
+    }
+    double s = v[0];
+    for (; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    which = sel;
+    return s;
+  }
+}
+
+// Lane index (within a group) that reports value u after group_reduce<U>.
+template <int U>
+__device__ __forceinline__ int reporter(int u, int lpc) {
+  if (U == 1) return u;
+  int li = 0, o = lpc >> 1;
+  for (int b = U >> 1; b > 0; b >>= 1) {
+    if (u & b) li += o;
+    o >>= 1;
+  }
+  return li;
+}
+
 struct Tile1D {
   int32_t run, node0, node1, cell0, cell1;
 };
@@ -65,6 +117,43 @@ template <class T> struct Run1D {
   int32_t probe_node[kMaxProbes];
   int32_t probe_field[kMaxProbes];
   T* probe_buf;    // [nprobe][probe_cap]
+};
+
+// One 2D TEz run.  Ex [ny+1][nx] at (i+1/2, j), Ey [ny][nx+1] at (i, j+1/2),
+// Hz [ny][nx] at (i+1/2, j+1/2), normalised (E in V/m, Hz scaled by eta0, psi scaled
+// to V/m, current by dt/eps0).  CPML memory is stored only in the layer strips.
+template <class T> struct Run2D {
+  T* Ex;
+  T* Ey;
+  T* Hz;
+  T* psi_hzx;      // [ny][2m]   Hz points inside an x layer
+  T* psi_hzy;      // [2m][nx]   Hz points inside a y layer
+  T* psi_exy;      // [2m][nx]   Ex points inside a y layer
+  T* psi_eyx;      // [ny][2m]   Ey points inside an x layer
+  T* Jcx;          // [ny][nx]   cell-centre current (normalised), 0 off plasma
+  T* Jcy;
+  T* df;           // [ncell][nv][nv/2]  F1 on the vy > 0 half plane
+  const int32_t* cell_idx;   // [ncell] j * nx + i
+  const T* tau;    // [ncell] dt * nu_mean
+  const T* dens;   // [ncell]
+  const T* s_bin;  // [nv*nv/2] collision-frequency shape
+  const T* bx_bin; // [nv*nv/2] 2 dt (e/m) dF0/dvx per unit density
+  const T* by_bin; // [nv*nv/2] 2 dt (e/m) dF0/dvy per unit density
+  const double* wx_bin;  // moment weights (dt/eps0)(-2 e dv^2) vx
+  const double* wy_bin;  // moment weights (dt/eps0)(-2 e dv^2) vy
+  // CPML profiles: b, a (dimensionless), 1/kappa; e side at integer positions, h side
+  // at half positions
+  const T *bex, *aex, *rkex, *bhx, *ahx, *rkhx;
+  const T *bey, *aey, *rkey, *bhy, *ahy, *rkhy;
+  int32_t nx, ny, m, ncell, half, cells_per_block, nbk;
+  T S;
+  int32_t src_kind, src_i, src_j;
+  double src_amp, src_w, src_tau, src_t0, dt;
+  int32_t nprobe, probe_cap;
+  int32_t probe_field[kMaxProbes];
+  int32_t probe_i[kMaxProbes];
+  int32_t probe_j[kMaxProbes];
+  T* probe_buf;
 };
 
 }  // namespace fdtdp

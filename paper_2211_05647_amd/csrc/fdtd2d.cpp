@@ -1,19 +1,438 @@
-// fdtd2d.cpp -- 2D TEz path (placeholder until the 2D kernels land).
+// fdtd2d.cpp -- host side of the 2D TEz path: validation, FP64 tables (velocity grid on
+// the vy > 0 half plane, Maxwellian F0 and its derivatives, collision shapes, moment
+// weights, CPML profiles of section 2), workspace layout, launches and readback.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "common.h"
 #include "host_internal.h"
 
 namespace fdtdp {
-struct Host2D { int unused; };
-int validate_2d(const fdtd_grid*, const fdtd_profile*, const fdtd_source*) {
-  return fail(FDTD_EINVAL, "2D grids are not available in this build");
+
+struct Host2D {
+  fdtd_grid g;
+  fdtd_profile p;
+  fdtd_source s;
+  std::vector<double> ne, nu;
+  int nx = 0, ny = 0, m = 0, nv = 0, half = 0, ncell = 0, es = 4;
+  double dt = 0;
+  int cells_per_block = 0;
+  std::vector<int32_t> cell_idx;
+  // workspace offsets
+  size_t off_Ex = 0, off_Ey = 0, off_Hz = 0, off_phzx = 0, off_phzy = 0, off_pexy = 0,
+         off_peyx = 0, off_Jcx = 0, off_Jcy = 0, off_df = 0;
+  size_t off_cell = 0, off_tau = 0, off_dens = 0, off_s = 0, off_bx = 0, off_by = 0,
+         off_wx = 0, off_wy = 0, off_prof = 0, off_run = 0;
+  size_t state_end = 0, probe_off = 0, total = 0;
+  char* ws = nullptr;
+  int nbk = 0, nbh = 0, nbe = 0;
+};
+
+namespace {
+
+size_t layout(Host2D* h, int max_probes, int probe_cap) {
+  Carver cv;
+  const int es = h->es, nx = h->nx, ny = h->ny, m = std::max(h->m, 1);
+  h->off_Ex = cv.take((size_t)(ny + 1) * nx * es);
+  h->off_Ey = cv.take((size_t)ny * (nx + 1) * es);
+  h->off_Hz = cv.take((size_t)ny * nx * es);
+  h->off_phzx = cv.take((size_t)ny * 2 * m * es);
+  h->off_phzy = cv.take((size_t)2 * m * nx * es);
+  h->off_pexy = cv.take((size_t)2 * m * nx * es);
+  h->off_peyx = cv.take((size_t)ny * 2 * m * es);
+  h->off_Jcx = cv.take((size_t)ny * nx * es);
+  h->off_Jcy = cv.take((size_t)ny * nx * es);
+  h->off_df = cv.take((size_t)std::max(h->ncell, 1) * h->half * es);
+  h->state_end = cv.size();
+  h->probe_off = cv.take((size_t)std::max(max_probes, 1) * std::max(probe_cap, 1) * es);
+  const size_t nc = std::max(h->ncell, 1);
+  h->off_cell = cv.take(nc * 4);
+  h->off_tau = cv.take(nc * es);
+  h->off_dens = cv.take(nc * es);
+  h->off_s = cv.take((size_t)h->half * es);
+  h->off_bx = cv.take((size_t)h->half * es);
+  h->off_by = cv.take((size_t)h->half * es);
+  h->off_wx = cv.take((size_t)h->half * 8);
+  h->off_wy = cv.take((size_t)h->half * 8);
+  h->off_prof = cv.take((size_t)(6 * (nx + 1) + 6 * (ny + 1)) * es);
+  h->off_run = cv.take(std::max(sizeof(Run2D<double>), sizeof(Run2D<float>)));
+  h->total = cv.size() + 256;
+  return h->total;
 }
-size_t workspace_2d(const fdtd_grid*, const fdtd_profile*, int, int) { return 0; }
-Host2D* make_2d(const fdtd_grid*, const fdtd_profile*, const fdtd_source*, int, int, size_t*, size_t*) { return nullptr; }
-int upload_2d(Host2D*, char*, hipStream_t, const std::vector<ProbeInfo>&, size_t, int) { return FDTD_EINVAL; }
-hipError_t launch_step2d(Host2D*, int64_t, hipStream_t) { return hipErrorInvalidValue; }
-int field_size_2d(const Host2D*, int, size_t*) { return FDTD_EINVAL; }
-int read_2d(Host2D*, char*, int, int64_t, double*) { return FDTD_EINVAL; }
-int check_probe_2d(const Host2D*, int, int, int) { return FDTD_EINVAL; }
-double probe_scale_2d(const Host2D*, int) { return 1.0; }
-int set_tiling_2d(Host2D*, char*, hipStream_t, int, int) { return FDTD_EINVAL; }
+
+// CPML coefficients at depth rho into a layer of thickness `thick` (section 2 formulas):
+// b = exp(-(sigma/kappa + alpha) dt / eps0), a = sigma (b - 1) / (sigma kappa + alpha kappa^2)
+void cpml_point(const fdtd_grid& g, double rho, double thick, double dt, double* b, double* a,
+                double* rk) {
+  if (rho <= 0.0) { *b = 0.0; *a = 0.0; *rk = 1.0; return; }
+  const double smax = g.cpml_sigma_factor * (g.cpml_order + 1.0) / (150.0 * M_PI * g.dx);
+  const double r = rho / thick;
+  const double sig = smax * std::pow(r, g.cpml_order);
+  const double kap = 1.0 + (g.cpml_kappa_max - 1.0) * std::pow(r, g.cpml_order);
+  const double alp = g.cpml_alpha_min + (g.cpml_alpha_max - g.cpml_alpha_min) * (1.0 - r);
+  *b = std::exp(-(sig / kap + alp) * dt / kEps0);
+  *a = sig * (*b - 1.0) / (sig * kap + alp * kap * kap);
+  *rk = 1.0 / kap;
+}
+
+template <class T>
+void axis_profile(const fdtd_grid& g, int n, int m, double dt, T* be, T* ae, T* rke, T* bh,
+                  T* ah, T* rkh) {
+  const double thick = m * g.dx;
+  for (int i = 0; i <= n; ++i) {
+    double rho = 0.0;
+    if (m > 0 && i < m) rho = (m - i) * g.dx;
+    if (m > 0 && i > n - m) rho = (i - (n - m)) * g.dx;
+    double b, a, rk;
+    cpml_point(g, rho, thick, dt, &b, &a, &rk);
+    be[i] = (T)b; ae[i] = (T)a; rke[i] = (T)rk;
+  }
+  for (int i = 0; i < n; ++i) {
+    const double x = i + 0.5;
+    double rho = 0.0;
+    if (m > 0 && x < m) rho = (m - x) * g.dx;
+    if (m > 0 && x > n - m) rho = (x - (n - m)) * g.dx;
+    double b, a, rk;
+    cpml_point(g, rho, thick, dt, &b, &a, &rk);
+    bh[i] = (T)b; ah[i] = (T)a; rkh[i] = (T)rk;
+  }
+}
+
+template <class T>
+int upload(Host2D* h, char* ws, hipStream_t st, const std::vector<ProbeInfo>& probes,
+           size_t probe_off, int probe_cap) {
+  h->ws = ws;
+  const int nv = h->nv, half = h->half, nx = h->nx, ny = h->ny, m = h->m;
+  const double dt = h->dt;
+  VTable vt = build_vtable(2, nv, h->p.vmax_over_vth, h->p.te_ev, h->p.nu_model, dt);
+  std::vector<T> s(half), bx(half), by(half);
+  std::vector<double> wx(half), wy(half);
+  const double vth2 = vt.vth * vt.vth;
+  for (int a = 0; a < nv; ++a)
+    for (int bb = 0; bb < nv / 2; ++bb) {
+      const int q = a * (nv / 2) + bb;
+      const int b = nv / 2 + bb;           // vy > 0 half plane
+      const double vx = vt.v[a], vy = vt.v[b];
+      const double f2 = vt.f[a] * vt.f[b];
+      const double sp = std::sqrt(vx * vx + vy * vy);
+      s[q] = (T)(h->p.nu_model == FDTD_NU_HARD_SPHERE ? sp / vt.mean_speed : 1.0);
+      bx[q] = (T)(2.0 * dt * (kQe / kMe) * (-vx * f2 / vth2));
+      by[q] = (T)(2.0 * dt * (kQe / kMe) * (-vy * f2 / vth2));
+      wx[q] = (dt / kEps0) * (-2.0 * kQe * vt.dv * vt.dv) * vx;
+      wy[q] = (dt / kEps0) * (-2.0 * kQe * vt.dv * vt.dv) * vy;
+    }
+  std::vector<T> tau, dens;
+  for (int c = 0; c < h->ncell; ++c) {
+    const int k = h->cell_idx[c];
+    tau.push_back((T)(dt * h->nu[k]));
+    dens.push_back((T)h->ne[k]);
+  }
+  std::vector<T> prof(6 * (nx + 1) + 6 * (ny + 1));
+  T* px = prof.data();
+  T* py = prof.data() + 6 * (nx + 1);
+  axis_profile<T>(h->g, nx, m, dt, px, px + (nx + 1), px + 2 * (nx + 1), px + 3 * (nx + 1),
+                  px + 4 * (nx + 1), px + 5 * (nx + 1));
+  axis_profile<T>(h->g, ny, m, dt, py, py + (ny + 1), py + 2 * (ny + 1), py + 3 * (ny + 1),
+                  py + 4 * (ny + 1), py + 5 * (ny + 1));
+  hipError_t e;
+  auto put = [&](size_t off, const void* src, size_t bytes) {
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(ws + off, src, bytes, hipMemcpyHostToDevice, st);
+  };
+  if ((e = put(h->off_cell, h->cell_idx.data(), h->cell_idx.size() * 4)) ||
+      (e = put(h->off_tau, tau.data(), tau.size() * sizeof(T))) ||
+      (e = put(h->off_dens, dens.data(), dens.size() * sizeof(T))) ||
+      (e = put(h->off_s, s.data(), half * sizeof(T))) ||
+      (e = put(h->off_bx, bx.data(), half * sizeof(T))) ||
+      (e = put(h->off_by, by.data(), half * sizeof(T))) ||
+      (e = put(h->off_wx, wx.data(), half * 8)) || (e = put(h->off_wy, wy.data(), half * 8)) ||
+      (e = put(h->off_prof, prof.data(), prof.size() * sizeof(T))))
+    return hip_fail(e, "upload 2D tables");
+
+  Run2D<T> R;
+  std::memset(&R, 0, sizeof R);
+  R.Ex = reinterpret_cast<T*>(ws + h->off_Ex);
+  R.Ey = reinterpret_cast<T*>(ws + h->off_Ey);
+  R.Hz = reinterpret_cast<T*>(ws + h->off_Hz);
+  R.psi_hzx = reinterpret_cast<T*>(ws + h->off_phzx);
+  R.psi_hzy = reinterpret_cast<T*>(ws + h->off_phzy);
+  R.psi_exy = reinterpret_cast<T*>(ws + h->off_pexy);
+  R.psi_eyx = reinterpret_cast<T*>(ws + h->off_peyx);
+  R.Jcx = reinterpret_cast<T*>(ws + h->off_Jcx);
+  R.Jcy = reinterpret_cast<T*>(ws + h->off_Jcy);
+  R.df = reinterpret_cast<T*>(ws + h->off_df);
+  R.cell_idx = reinterpret_cast<const int32_t*>(ws + h->off_cell);
+  R.tau = reinterpret_cast<const T*>(ws + h->off_tau);
+  R.dens = reinterpret_cast<const T*>(ws + h->off_dens);
+  R.s_bin = reinterpret_cast<const T*>(ws + h->off_s);
+  R.bx_bin = reinterpret_cast<const T*>(ws + h->off_bx);
+  R.by_bin = reinterpret_cast<const T*>(ws + h->off_by);
+  R.wx_bin = reinterpret_cast<const double*>(ws + h->off_wx);
+  R.wy_bin = reinterpret_cast<const double*>(ws + h->off_wy);
+  const T* dpx = reinterpret_cast<const T*>(ws + h->off_prof);
+  const T* dpy = dpx + 6 * (nx + 1);
+  R.bex = dpx; R.aex = dpx + (nx + 1); R.rkex = dpx + 2 * (nx + 1);
+  R.bhx = dpx + 3 * (nx + 1); R.ahx = dpx + 4 * (nx + 1); R.rkhx = dpx + 5 * (nx + 1);
+  R.bey = dpy; R.aey = dpy + (ny + 1); R.rkey = dpy + 2 * (ny + 1);
+  R.bhy = dpy + 3 * (ny + 1); R.ahy = dpy + 4 * (ny + 1); R.rkhy = dpy + 5 * (ny + 1);
+  R.nx = nx; R.ny = ny; R.m = m; R.ncell = h->ncell; R.half = half;
+  R.cells_per_block = h->cells_per_block;
+  R.nbk = h->nbk;
+  R.S = (T)h->g.courant;
+  R.src_kind = (h->s.kind != FDTD_SRC_NONE && h->s.amplitude != 0.0) ? h->s.kind : 0;
+  R.src_i = h->s.i; R.src_j = h->s.j;
+  R.src_amp = h->s.amplitude; R.src_w = 2.0 * M_PI * h->s.f_hz;
+  R.src_tau = R.src_kind ? h->s.tau_s : 1.0; R.src_t0 = h->s.t0_s; R.dt = dt;
+  R.probe_cap = std::max(probe_cap, 1);
+  R.probe_buf = reinterpret_cast<T*>(ws + probe_off);
+  for (const auto& pi : probes) {
+    R.probe_field[R.nprobe] = pi.field;
+    R.probe_i[R.nprobe] = pi.i;
+    R.probe_j[R.nprobe] = pi.j;
+    R.nprobe++;
+  }
+  e = put(h->off_run, &R, sizeof R);
+  if (e) return hip_fail(e, "upload 2D run descriptor");
+  return FDTD_OK;
+}
+
+void set_grid(Host2D* h) {
+  h->nbk = h->ncell > 0 ? (h->ncell + h->cells_per_block - 1) / h->cells_per_block : 0;
+  h->nbh = (h->nx * h->ny + kBlock - 1) / kBlock;
+  h->nbe = ((h->nx + 1) * (h->ny + 1) + kBlock - 1) / kBlock;
+}
+
+}  // namespace
+
+template <class T>
+hipError_t launch_step2d_t(const void* run, int nbk, int nbh, int nbe, int64_t step,
+                           hipStream_t stream);
+
+int validate_2d(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s) {
+  if (!g || !p) return fail(FDTD_EINVAL, "null grid or profile");
+  if (g->dims != 2) return fail(FDTD_EINVAL, "dims must be 2 here");
+  if (g->nx < 8 || g->ny < 8 || g->nx > 32768 || g->ny > 32768)
+    return fail(FDTD_EINVAL, "nx, ny must lie in [8, 32768]");
+  if (!(g->dx > 0.0) || !std::isfinite(g->dx)) return fail(FDTD_EINVAL, "dx must be > 0");
+  if (!(g->courant > 0.0) || g->courant > 1.0 / std::sqrt(2.0))
+    return fail(FDTD_EINVAL, "2D Courant number must lie in (0, 1/sqrt(2)], got %g", g->courant);
+  if (g->precision != FDTD_FP32 && g->precision != FDTD_FP64)
+    return fail(FDTD_EINVAL, "unknown precision %d", g->precision);
+  if (g->boundary == FDTD_BC_CPML) {
+    if (g->cpml_cells < 1 || 2 * g->cpml_cells + 2 > std::min(g->nx, g->ny))
+      return fail(FDTD_EINVAL, "cpml_cells out of range");
+    if (!(g->cpml_order > 0) || !(g->cpml_sigma_factor >= 0) || !(g->cpml_kappa_max >= 1) ||
+        !(g->cpml_alpha_min >= 0) || !(g->cpml_alpha_max >= 0) ||
+        !std::isfinite(g->cpml_order + g->cpml_sigma_factor + g->cpml_kappa_max +
+                       g->cpml_alpha_min + g->cpml_alpha_max))
+      return fail(FDTD_EINVAL, "bad CPML parameters");
+  } else if (g->boundary != FDTD_BC_PEC) {
+    return fail(FDTD_EINVAL, "2D boundary must be PEC or CPML");
+  }
+  if (!is_pow2(p->nv) || p->nv < 8 || p->nv > 32)
+    return fail(FDTD_EINVAL, "2D nv must be a power of two in [8, 32], got %d", p->nv);
+  if (!(p->te_ev > 0.0) || !(p->vmax_over_vth > 0.0))
+    return fail(FDTD_EINVAL, "te_ev and vmax_over_vth must be > 0");
+  if (p->nu_model != FDTD_NU_HARD_SPHERE && p->nu_model != FDTD_NU_CONST)
+    return fail(FDTD_EINVAL, "unknown nu_model %d", p->nu_model);
+  if (p->closure != FDTD_CLOSURE_KINETIC)
+    return fail(FDTD_EINVAL, "this build runs the kinetic closure in 2D");
+  if (!p->ne || !p->nu_mean) return fail(FDTD_EINVAL, "null ne or nu_mean");
+  const size_t n = (size_t)g->nx * g->ny;
+  for (size_t k = 0; k < n; ++k) {
+    if (!(p->ne[k] >= 0.0) || !std::isfinite(p->ne[k]))
+      return fail(FDTD_EINVAL, "ne[%zu] must be finite and >= 0", k);
+    if (!(p->nu_mean[k] >= 0.0) || !std::isfinite(p->nu_mean[k]))
+      return fail(FDTD_EINVAL, "nu_mean[%zu] must be finite and >= 0", k);
+  }
+  if (s && s->kind != FDTD_SRC_NONE) {
+    if (s->kind != FDTD_SRC_LINE_SOFT && s->kind != FDTD_SRC_POINT_SOFT)
+      return fail(FDTD_EINVAL, "unknown source kind");
+    if (s->i < 1 || s->i > g->nx - 1) return fail(FDTD_EINVAL, "source column out of [1, nx-1]");
+    if (s->kind == FDTD_SRC_POINT_SOFT && (s->j < 0 || s->j >= g->ny))
+      return fail(FDTD_EINVAL, "source row out of [0, ny)");
+    if (!(s->tau_s > 0.0) || !std::isfinite(s->amplitude) || !std::isfinite(s->f_hz) ||
+        !std::isfinite(s->t0_s))
+      return fail(FDTD_EINVAL, "bad source parameters");
+  }
+  return FDTD_OK;
+}
+
+static Host2D* new_host(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s) {
+  Host2D* h = new (std::nothrow) Host2D();
+  if (!h) return nullptr;
+  h->g = *g;
+  h->p = *p;
+  fdtd_source none{};
+  h->s = s ? *s : none;
+  h->nx = g->nx;
+  h->ny = g->ny;
+  h->m = g->boundary == FDTD_BC_CPML ? g->cpml_cells : 0;
+  h->nv = p->nv;
+  h->half = p->nv * p->nv / 2;
+  h->es = g->precision == FDTD_FP64 ? 8 : 4;
+  h->dt = g->courant * g->dx / kC0;
+  const size_t n = (size_t)g->nx * g->ny;
+  h->ne.assign(p->ne, p->ne + n);
+  h->nu.assign(p->nu_mean, p->nu_mean + n);
+  h->p.ne = h->ne.data();
+  h->p.nu_mean = h->nu.data();
+  for (size_t k = 0; k < n; ++k)
+    if (h->ne[k] > 0) h->cell_idx.push_back((int32_t)k);
+  h->ncell = (int)h->cell_idx.size();
+  // about 64 KB of F1 per kinetic work-group
+  h->cells_per_block = std::max(4, std::min(256, 65536 / (h->half * h->es)));
+  set_grid(h);
+  return h;
+}
+
+size_t workspace_2d(const fdtd_grid* g, const fdtd_profile* p, int max_probes, int probe_cap) {
+  Host2D* h = new_host(g, p, nullptr);
+  if (!h) return 0;
+  size_t n = layout(h, max_probes, probe_cap);
+  delete h;
+  return n;
+}
+
+Host2D* make_2d(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s, int max_probes,
+                int probe_cap, size_t* state_bytes, size_t* probe_off) {
+  Host2D* h = new_host(g, p, s);
+  if (!h) return nullptr;
+  layout(h, max_probes, probe_cap);
+  *state_bytes = h->state_end;
+  *probe_off = h->probe_off;
+  return h;
+}
+
+int upload_2d(Host2D* h, char* ws, hipStream_t stream, const std::vector<ProbeInfo>& probes,
+              size_t probe_off, int probe_cap) {
+  return h->es == 8 ? upload<double>(h, ws, stream, probes, probe_off, probe_cap)
+                    : upload<float>(h, ws, stream, probes, probe_off, probe_cap);
+}
+
+hipError_t launch_step2d(Host2D* h, int64_t step, hipStream_t stream) {
+  const void* run = h->ws + h->off_run;
+  return h->es == 8 ? launch_step2d_t<double>(run, h->nbk, h->nbh, h->nbe, step, stream)
+                    : launch_step2d_t<float>(run, h->nbk, h->nbh, h->nbe, step, stream);
+}
+
+int field_size_2d(const Host2D* h, int field, size_t* n) {
+  const size_t nx = h->nx, ny = h->ny;
+  switch (field) {
+    case FDTD_F_EX: case FDTD_F_JX: *n = (ny + 1) * nx; return FDTD_OK;
+    case FDTD_F_EY: case FDTD_F_JY: *n = ny * (nx + 1); return FDTD_OK;
+    case FDTD_F_HZ: *n = ny * nx; return FDTD_OK;
+    case FDTD_F_DF: *n = (size_t)h->ncell * h->nv * h->nv; return FDTD_OK;
+    default: return fail(FDTD_EINVAL, "field %d not defined on a 2D grid", field);
+  }
+}
+
+int read_2d(Host2D* h, char* ws, int field, int64_t, double* dst) {
+  const int nx = h->nx, ny = h->ny, es = h->es;
+  auto grab = [&](size_t off, size_t cnt, std::vector<double>& out) -> int {
+    std::vector<char> buf(std::max<size_t>(cnt, 1) * es);
+    if (cnt) {
+      hipError_t e = hipMemcpy(buf.data(), ws + off, cnt * es, hipMemcpyDeviceToHost);
+      if (e) return hip_fail(e, "copy 2D field");
+    }
+    out.resize(cnt);
+    for (size_t k = 0; k < cnt; ++k)
+      out[k] = es == 8 ? reinterpret_cast<double*>(buf.data())[k] : reinterpret_cast<float*>(buf.data())[k];
+    return FDTD_OK;
+  };
+  std::vector<double> v;
+  int rc = FDTD_OK;
+  const double jscale = kEps0 / h->dt;
+  switch (field) {
+    case FDTD_F_EX:
+      rc = grab(h->off_Ex, (size_t)(ny + 1) * nx, v);
+      if (!rc) std::copy(v.begin(), v.end(), dst);
+      break;
+    case FDTD_F_EY:
+      rc = grab(h->off_Ey, (size_t)ny * (nx + 1), v);
+      if (!rc) std::copy(v.begin(), v.end(), dst);
+      break;
+    case FDTD_F_HZ:
+      rc = grab(h->off_Hz, (size_t)ny * nx, v);
+      if (!rc) for (size_t k = 0; k < v.size(); ++k) dst[k] = v[k] / kEta0;
+      break;
+    case FDTD_F_JX:
+      rc = grab(h->off_Jcx, (size_t)ny * nx, v);
+      if (!rc)
+        for (int j = 0; j <= ny; ++j)
+          for (int i = 0; i < nx; ++i) {
+            const double lo = j > 0 ? v[(size_t)(j - 1) * nx + i] : 0.0;
+            const double hi = j < ny ? v[(size_t)j * nx + i] : 0.0;
+            dst[(size_t)j * nx + i] = 0.5 * (lo + hi) * jscale;
+          }
+      break;
+    case FDTD_F_JY:
+      rc = grab(h->off_Jcy, (size_t)ny * nx, v);
+      if (!rc)
+        for (int j = 0; j < ny; ++j)
+          for (int i = 0; i <= nx; ++i) {
+            const double lo = i > 0 ? v[(size_t)j * nx + i - 1] : 0.0;
+            const double hi = i < nx ? v[(size_t)j * nx + i] : 0.0;
+            dst[(size_t)j * (nx + 1) + i] = 0.5 * (lo + hi) * jscale;
+          }
+      break;
+    case FDTD_F_DF: {
+      rc = grab(h->off_df, (size_t)h->ncell * h->half, v);
+      const int nv = h->nv, hv = nv / 2;
+      if (!rc)
+        for (int c = 0; c < h->ncell; ++c)
+          for (int a = 0; a < nv; ++a)
+            for (int bb = 0; bb < hv; ++bb) {
+              const double f = v[(size_t)c * h->half + a * hv + bb];
+              const int b = hv + bb;
+              dst[((size_t)c * nv + a) * nv + b] = f;
+              dst[((size_t)c * nv + (nv - 1 - a)) * nv + (nv - 1 - b)] = -f;
+            }
+      break;
+    }
+    default:
+      return fail(FDTD_EINVAL, "field %d not defined on a 2D grid", field);
+  }
+  return rc;
+}
+
+int check_probe_2d(const Host2D* h, int field, int i, int j) {
+  if (field == FDTD_F_EX) {
+    if (i < 0 || i >= h->nx || j < 0 || j > h->ny) return fail(FDTD_ERANGE, "Ex probe out of range");
+  } else if (field == FDTD_F_EY) {
+    if (i < 0 || i > h->nx || j < 0 || j >= h->ny) return fail(FDTD_ERANGE, "Ey probe out of range");
+  } else if (field == FDTD_F_HZ) {
+    if (i < 0 || i >= h->nx || j < 0 || j >= h->ny) return fail(FDTD_ERANGE, "Hz probe out of range");
+  } else {
+    return fail(FDTD_EINVAL, "2D probes record Ex, Ey or Hz");
+  }
+  return FDTD_OK;
+}
+
+double probe_scale_2d(const Host2D*, int field) { return field == FDTD_F_HZ ? 1.0 / kEta0 : 1.0; }
+
+int set_tiling_2d(Host2D* h, char* ws, hipStream_t stream, int tile, int cells_per_group) {
+  const int cpb = cells_per_group ? cells_per_group : tile;
+  if (cpb) {
+    if (cpb < 1 || cpb > 4096) return fail(FDTD_EINVAL, "cells per group must lie in [1, 4096]");
+    h->cells_per_block = cpb;
+    set_grid(h);
+    // patch the descriptor's launch fields
+    const size_t off = h->es == 8 ? offsetof(Run2D<double>, cells_per_block)
+                                  : offsetof(Run2D<float>, cells_per_block);
+    int32_t v[2] = {h->cells_per_block, h->nbk};
+    hipError_t e = hipMemcpyAsync(ws + h->off_run + off, v, sizeof v, hipMemcpyHostToDevice, stream);
+    if (!e) e = hipStreamSynchronize(stream);
+    if (e) return hip_fail(e, "update 2D tiling");
+  }
+  return FDTD_OK;
+}
+
 void destroy_2d(Host2D* h) { delete h; }
+
 }  // namespace fdtdp

@@ -22,58 +22,6 @@
 
 namespace fdtdp {
 
-// Sum U per-lane values over the lpc lanes of each lane group (lpc >= U).  On return,
-// lane `li` of a group holds the total of value index `which`.
-template <int U>
-__device__ __forceinline__ double group_reduce(double (&a)[U], int lpc, int li, int& which) {
-  if constexpr (U == 1) {
-    double s = a[0];
-    for (int o = lpc >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    which = 0;
-    return s;
-  } else {
-    // requires lpc >= U (the caller handles narrower groups)
-    // reduce-scatter rounds: at each round a lane keeps half of its values and sends
-    // the other half to its partner
-    double v[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = a[u];
-    int n = U, o = lpc >> 1, sel = 0;
-#pragma unroll
-    for (int r = 0; (1 << r) < U; ++r) {
-      const bool hi = (li & o) != 0;
-      const int h = n >> 1;
-#pragma unroll
-      for (int k = 0; k < U / 2; ++k) {
-        if (k < h) {
-          const double send = hi ? v[k] : v[k + h];
-          const double got = __shfl_xor(send, o);
-          v[k] = (hi ? v[k + h] : v[k]) + got;
-        }
-      }
-      sel = sel * 2 + (hi ? 1 : 0);
-      n = h;
-      o >>= 1;
-    }
-    double s = v[0];
-    for (; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    which = sel;
-    return s;
-  }
-}
-
-// Lane index (within a group) that reports value u after group_reduce<U>.
-template <int U>
-__device__ __forceinline__ int reporter(int u, int lpc) {
-  if (U == 1) return u;
-  int li = 0, o = lpc >> 1;
-  for (int b = U >> 1; b > 0; b >>= 1) {
-    if (u & b) li += o;
-    o >>= 1;
-  }
-  return li;
-}
-
 template <class T, int U>
 __device__ __forceinline__ void kinetic_tile(const Run1D<T>& R, const T* eloc,
                                              const Tile1D& tile, T* jloc) {
