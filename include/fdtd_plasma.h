@@ -135,17 +135,34 @@ int fdtd_plasma_workspace_size(const fdtd_grid *grid, const fdtd_profile *profil
 int fdtd_plasma_create(const fdtd_grid *grid, const fdtd_profile *profile,
                        const fdtd_source *source, const fdtd_device *dev, fdtd_plasma **out);
 
-/* Batch of nruns independent 1D FP32 runs of uneven size sharing one launch (arrays of
- * nruns structs).  steps[r] is the step count of run r: fdtd_plasma_run advances every
- * run to min(its own count, the batch step).  Workspace size via
- * fdtd_plasma_workspace_size_batch. */
+/* Batch of nruns independent 1D FP32 runs of uneven size (arrays of nruns structs),
+ * advanced together.  steps[r] is the step count of run r: fdtd_plasma_run advances
+ * every run to min(its own count, the batch step).  ntap (0..8) training-pair taps per
+ * run record (E^n, J^{n+1/2}) at the plasma nodes tap_nodes[r * ntap + k] after every
+ * step of that run (NULL when ntap = 0).  Default launch: one persistent launch per
+ * fdtd_plasma_run, work-groups pulling whole runs longest-first from a queue
+ * (see fdtd_plasma_set_batch_mode).  Workspace size via fdtd_plasma_workspace_size_batch. */
 int fdtd_plasma_workspace_size_batch(int32_t nruns, const fdtd_grid *grids,
-                                     const fdtd_profile *profiles, const fdtd_device *dev,
-                                     size_t *bytes);
+                                     const fdtd_profile *profiles, const int64_t *steps,
+                                     int32_t ntap, const fdtd_device *dev, size_t *bytes);
 int fdtd_plasma_create_batch(int32_t nruns, const fdtd_grid *grids,
                              const fdtd_profile *profiles, const fdtd_source *sources,
-                             const int64_t *steps, const fdtd_device *dev,
-                             fdtd_plasma **out);
+                             const int64_t *steps, int32_t ntap, const int32_t *tap_nodes,
+                             const fdtd_device *dev, fdtd_plasma **out);
+
+/* Batch launch form: mode 0 = persistent work-queue launch with `groups` work-groups
+ * (0 = one per run, capped by the device's resident capacity); mode 1 = one launch per
+ * step over the tiles of the runs still active.  Only before the first step. */
+int fdtd_plasma_set_batch_mode(fdtd_plasma *h, int32_t mode, int32_t groups);
+
+/* Copy the taps of run `run`: [ntap][steps taken by that run][2] doubles, (E in V/m,
+ * J in A/m^2), oldest first.  FDTD_ERANGE if dst_len is short. */
+int fdtd_plasma_read_taps(fdtd_plasma *h, int32_t run, double *dst, size_t dst_len,
+                          size_t *n_out);
+
+/* Per-run status after the last run: 0, or FDTD_ENUMERIC if that run produced a
+ * non-finite E value (other runs of the batch are unaffected). */
+int fdtd_plasma_run_status(fdtd_plasma *h, int32_t run, int32_t *status);
 
 /* One leap-frog step (H, F1 and J, E, boundary, source), enqueued. */
 int fdtd_plasma_step(fdtd_plasma *h);

@@ -57,8 +57,11 @@ class Device(C.Structure):
 _SIGS = {
     "fdtd_plasma_workspace_size": ([C.POINTER(Grid), C.POINTER(Profile), C.POINTER(Device), C.POINTER(C.c_size_t)], C.c_int),
     "fdtd_plasma_create": ([C.POINTER(Grid), C.POINTER(Profile), C.POINTER(Source), C.POINTER(Device), C.POINTER(C.c_void_p)], C.c_int),
-    "fdtd_plasma_workspace_size_batch": ([C.c_int32, C.POINTER(Grid), C.POINTER(Profile), C.POINTER(Device), C.POINTER(C.c_size_t)], C.c_int),
-    "fdtd_plasma_create_batch": ([C.c_int32, C.POINTER(Grid), C.POINTER(Profile), C.POINTER(Source), C.POINTER(C.c_int64), C.POINTER(Device), C.POINTER(C.c_void_p)], C.c_int),
+    "fdtd_plasma_workspace_size_batch": ([C.c_int32, C.POINTER(Grid), C.POINTER(Profile), C.POINTER(C.c_int64), C.c_int32, C.POINTER(Device), C.POINTER(C.c_size_t)], C.c_int),
+    "fdtd_plasma_create_batch": ([C.c_int32, C.POINTER(Grid), C.POINTER(Profile), C.POINTER(Source), C.POINTER(C.c_int64), C.c_int32, C.POINTER(C.c_int32), C.POINTER(Device), C.POINTER(C.c_void_p)], C.c_int),
+    "fdtd_plasma_set_batch_mode": ([C.c_void_p, C.c_int32, C.c_int32], C.c_int),
+    "fdtd_plasma_read_taps": ([C.c_void_p, C.c_int32, _dp, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
+    "fdtd_plasma_run_status": ([C.c_void_p, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
     "fdtd_plasma_step": ([C.c_void_p], C.c_int),
     "fdtd_plasma_run": ([C.c_void_p, C.c_int64], C.c_int),
     "fdtd_plasma_steps": ([C.c_void_p, C.POINTER(C.c_int64)], C.c_int),
@@ -126,7 +129,8 @@ class Sim:
     """
 
     def __init__(self, workload, precision=FP32, device=0, max_probes=0, probe_capacity=0,
-                 closure=CLOSURE_KINETIC, mlp_blob=None, tile=0, cells_per_group=0):
+                 closure=CLOSURE_KINETIC, mlp_blob=None, tile=0, cells_per_group=0,
+                 taps=None, batch_mode=0, groups=0):
         import torch
         self.torch = torch
         L = lib()
@@ -167,7 +171,13 @@ class Sim:
             GA, PA = Grid * len(runs), Profile * len(runs)
             self._ga, self._pa = GA(*grids), PA(*profs)
             self._sa = (Source * len(runs))(*srcs)
-            check(L.fdtd_plasma_workspace_size_batch(len(runs), self._ga, self._pa, C.byref(dev), C.byref(nbytes)),
+            self._steps = (C.c_int64 * len(runs))(*[int(w.steps) for w in runs])
+            self.ntap = 0 if taps is None else int(np.asarray(taps).shape[1])
+            self._taps = None
+            if self.ntap:
+                self._taps = np.ascontiguousarray(taps, dtype=np.int32)
+            check(L.fdtd_plasma_workspace_size_batch(len(runs), self._ga, self._pa, self._steps, self.ntap,
+                                                     C.byref(dev), C.byref(nbytes)),
                   "workspace_size_batch")
         else:
             check(L.fdtd_plasma_workspace_size(C.byref(grids[0]), C.byref(profs[0]), C.byref(dev), C.byref(nbytes)),
@@ -177,14 +187,16 @@ class Sim:
         dev.workspace_bytes = self.workspace.numel()
         h = C.c_void_p()
         if self.batch:
-            steps = (C.c_int64 * len(runs))(*[int(w.steps) for w in runs])
-            self._steps = steps
-            check(L.fdtd_plasma_create_batch(len(runs), self._ga, self._pa, self._sa, steps, C.byref(dev), C.byref(h)),
+            tp = self._taps.ctypes.data_as(C.POINTER(C.c_int32)) if self.ntap else None
+            check(L.fdtd_plasma_create_batch(len(runs), self._ga, self._pa, self._sa, self._steps, self.ntap, tp,
+                                             C.byref(dev), C.byref(h)),
                   "create_batch")
         else:
             check(L.fdtd_plasma_create(C.byref(grids[0]), C.byref(profs[0]), C.byref(srcs[0]), C.byref(dev), C.byref(h)),
                   "create")
         self.h = h
+        if self.batch and (batch_mode or groups):
+            check(L.fdtd_plasma_set_batch_mode(self.h, batch_mode, groups), "set_batch_mode")
         if tile or cells_per_group:
             check(L.fdtd_plasma_set_tiling(self.h, tile, cells_per_group), "set_tiling")
 
@@ -240,6 +252,19 @@ class Sim:
 
     def load_state(self, buf):
         check(lib().fdtd_plasma_load_state(self.h, buf.ctypes.data_as(C.c_void_p), buf.size), "load_state")
+
+    def read_taps(self, run):
+        """(ntap, steps, 2) array of (E^n in V/m, J^{n+1/2} in A/m^2) at the run's taps."""
+        n = self.ntap * max(0, min(self.steps, int(self.runs[run].steps))) * 2
+        out = np.empty(max(n, 1), dtype=np.float64)
+        got = C.c_size_t()
+        check(lib().fdtd_plasma_read_taps(self.h, run, out.ctypes.data_as(_dp), out.size, C.byref(got)), "read_taps")
+        return out[: got.value].reshape(self.ntap, -1, 2)
+
+    def run_status(self, run):
+        st = C.c_int32()
+        check(lib().fdtd_plasma_run_status(self.h, run, C.byref(st)), "run_status")
+        return st.value
 
     def last_run_ms(self):
         ms = C.c_double()

@@ -8,6 +8,8 @@ namespace fdtdp {
 constexpr int kMaxProbes = 16;
 constexpr int kBlock = 256;        // threads per work-group of the step kernels
 constexpr int kMaxTile1D = 256;    // nodes per 1D tile: one node per thread
+constexpr int kBatchBlock = 1024;  // threads (and nodes per chunk) of the persistent batch kernel
+constexpr int kMaxTaps = 8;        // training-pair taps per 1D run
 
 // 16-byte vector of the storage type: 4 floats or 2 doubles per lane per chunk.
 template <class T> struct Vec;
@@ -117,6 +119,13 @@ template <class T> struct Run1D {
   int32_t probe_node[kMaxProbes];
   int32_t probe_field[kMaxProbes];
   T* probe_buf;    // [nprobe][probe_cap]
+  // training-pair taps: (E^n, J^{n+1/2}) at chosen plasma nodes after every step
+  int32_t ntap;
+  int32_t tap_node[kMaxTaps];
+  T* tap_buf;      // [ntap][tap_cap][2]
+  int64_t tap_cap;
+  int32_t* status; // bit 0: a non-finite E value was produced
+  const int32_t* chunk_cell;  // [nchunk + 1] first plasma cell of each kBatchBlock-node chunk
 };
 
 // One 2D TEz run.  Ex [ny+1][nx] at (i+1/2, j), Ey [ny][nx+1] at (i, j+1/2),

@@ -91,6 +91,7 @@ struct RunSpec1D {
   fdtd_source s;
   int64_t steps;
   std::vector<double> ne, nu;
+  std::vector<int32_t> taps;   // training-pair tap nodes of this run
 };
 
 int validate_1d(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s, bool batch) {
@@ -172,6 +173,8 @@ struct fdtd_plasma {
   size_t runs_off = 0, tiles_off = 0;
   int ntiles = 0;
   std::vector<int64_t> tile_limit;   // step limit of each tile, non-increasing
+  size_t order_off = 0, queue_off = 0, status_off = 0;
+  int batch_mode = 0, batch_groups = 0, ntap = 0;
   // probes
   int max_probes = 0, probe_cap = 0;
   size_t probe_off = 0;
@@ -210,6 +213,10 @@ size_t layout_1d(fdtd_plasma* h, const std::vector<RunSpec1D>& specs, int precis
   const size_t probe_off = cv.take((size_t)std::max(max_probes, 1) * std::max(probe_cap, 1) * es);
   for (size_t r = 0; r < specs.size(); ++r) {
     Host1D& x = hs[r];
+    x.ntap = (int)specs[r].taps.size();
+    x.tap_cap = specs[r].steps == INT64_MAX ? 0 : specs[r].steps;
+    x.off_tap = cv.take((size_t)std::max<int64_t>(x.ntap * x.tap_cap, 1) * 2 * es);
+    x.off_chunk = cv.take(sz<int32_t>((x.nx + kBatchBlock) / kBatchBlock + 1));
     x.off_cell_node = cv.take(sz<int32_t>(std::max(x.ncell, 1)));
     x.off_tau = cv.take((size_t)std::max(x.ncell, 1) * es);
     x.off_dens = cv.take((size_t)std::max(x.ncell, 1) * es);
@@ -223,7 +230,13 @@ size_t layout_1d(fdtd_plasma* h, const std::vector<RunSpec1D>& specs, int precis
   size_t max_tiles = 0;
   for (auto& x : hs) max_tiles += (size_t)(x.nx + 1 + 31) / 32;
   const size_t tiles_off = cv.take(max_tiles * sizeof(Tile1D));
+  const size_t order_off = cv.take(sz<int32_t>(specs.size()));
+  const size_t queue_off = cv.take(sz<int32_t>(1));
+  const size_t status_off = cv.take(sz<int32_t>(specs.size()));
   if (h) {
+    h->order_off = order_off;
+    h->queue_off = queue_off;
+    h->status_off = status_off;
     h->state_off = 0;
     h->state_bytes = state_end;
     h->probe_off = probe_off;
@@ -264,8 +277,20 @@ int upload_1d(fdtd_plasma* h) {
       }
     }
     x.cell_node = cn;
+    // first plasma cell of every kBatchBlock-node chunk (persistent batch kernel)
+    std::vector<int32_t> chunk;
+    {
+      int c = 0;
+      for (int n0 = 0; n0 <= x.nx; n0 += kBatchBlock) {
+        chunk.push_back(c);
+        while (c < x.ncell && cn[c] < std::min(x.nx + 1, n0 + kBatchBlock)) ++c;
+      }
+      chunk.push_back(c);
+    }
     hipError_t e;
     char* base = h->ws;
+    if ((e = hipMemcpyAsync(base + x.off_chunk, chunk.data(), chunk.size() * 4, hipMemcpyHostToDevice, h->stream)))
+      return hip_fail(e, "upload chunk offsets");
     if (x.ncell > 0) {
       if ((e = hipMemcpyAsync(base + x.off_cell_node, cn.data(), cn.size() * 4, hipMemcpyHostToDevice, h->stream)) ||
           (e = hipMemcpyAsync(base + x.off_tau, tau.data(), tau.size() * sizeof(T), hipMemcpyHostToDevice, h->stream)) ||
@@ -307,6 +332,12 @@ int upload_1d(fdtd_plasma* h) {
     R.nprobe = 0;
     R.probe_cap = std::max(h->probe_cap, 1);
     R.probe_buf = reinterpret_cast<T*>(base + h->probe_off);
+    R.ntap = x.ntap;
+    for (int t = 0; t < x.ntap; ++t) R.tap_node[t] = sp.taps[t];
+    R.tap_buf = reinterpret_cast<T*>(base + x.off_tap);
+    R.tap_cap = x.tap_cap;
+    R.status = reinterpret_cast<int32_t*>(base + h->status_off) + r;
+    R.chunk_cell = reinterpret_cast<const int32_t*>(base + x.off_chunk);
   }
   // probes
   for (size_t p = 0; p < h->probes.size(); ++p) {
@@ -361,12 +392,33 @@ int build_tiles_1d(fdtd_plasma* h) {
   hipError_t e = hipMemcpyAsync(h->ws + h->tiles_off, tiles.data(), tiles.size() * sizeof(Tile1D),
                                 hipMemcpyHostToDevice, h->stream);
   if (e) return hip_fail(e, "upload tiles");
+  // run queue of the persistent batch kernel: most work first (steps x (F1 row bytes + node))
+  std::vector<int32_t> order(h->nruns);
+  for (int r = 0; r < h->nruns; ++r) order[r] = r;
+  auto work = [&](int r) {
+    const Host1D& x = h->h1[r];
+    const double st = h->specs[r].steps == INT64_MAX ? 1.0 : (double)h->specs[r].steps;
+    return st * ((double)x.ncell * x.half + 5.0 * (x.nx + 1));
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+  e = hipMemcpyAsync(h->ws + h->order_off, order.data(), order.size() * 4, hipMemcpyHostToDevice,
+                     h->stream);
+  if (e) return hip_fail(e, "upload run order");
   return FDTD_OK;
+}
+
+int batch_groups(const fdtd_plasma* h) {
+  if (h->batch_groups > 0) return std::min(h->batch_groups, h->nruns);
+  int cus = 256;
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
+  return std::max(1, std::min(h->nruns, 2 * cus));
 }
 
 int finish_upload(fdtd_plasma* h) {
   int rc;
   if (h->dims == 1) {
+    hipError_t ez = hipMemsetAsync(h->ws + h->status_off, 0, sizeof(int32_t) * h->nruns, h->stream);
+    if (ez) return hip_fail(ez, "clear run status");
     rc = h->precision == FDTD_FP64 ? upload_1d<double>(h) : upload_1d<float>(h);
     if (rc) return rc;
     rc = build_tiles_1d(h);
@@ -416,8 +468,9 @@ int check_device(const fdtd_device* dev) {
 }
 
 int create_1d(int nruns, const fdtd_grid* grids, const fdtd_profile* profiles,
-              const fdtd_source* sources, const int64_t* steps, const fdtd_device* dev,
-              fdtd_plasma** out, bool batch) {
+              const fdtd_source* sources, const int64_t* steps, int ntap,
+              const int32_t* tap_nodes, const fdtd_device* dev, fdtd_plasma** out,
+              bool batch) {
   int rc = check_device(dev);
   if (rc) return rc;
   fdtd_plasma* h = new (std::nothrow) fdtd_plasma();
@@ -442,7 +495,9 @@ int create_1d(int nruns, const fdtd_grid* grids, const fdtd_profile* profiles,
     fdtd_source none{};
     h->specs[r].s = sources ? sources[r] : none;
     h->specs[r].steps = (batch && steps) ? steps[r] : INT64_MAX;
+    for (int t = 0; t < ntap; ++t) h->specs[r].taps.push_back(tap_nodes[(size_t)r * ntap + t]);
   }
+  h->ntap = ntap;
   const size_t need = layout_1d(h, h->specs, h->precision, h->max_probes, h->probe_cap, &h->h1);
   rc = attach_workspace(h, dev, need);
   if (!rc) rc = finish_upload(h);
@@ -483,15 +538,20 @@ int fdtd_plasma_workspace_size(const fdtd_grid* grid, const fdtd_profile* profil
 }
 
 int fdtd_plasma_workspace_size_batch(int32_t nruns, const fdtd_grid* grids,
-                                     const fdtd_profile* profiles, const fdtd_device* dev,
-                                     size_t* bytes) {
-  if (nruns <= 0 || !grids || !profiles || !bytes) return fail(FDTD_EINVAL, "bad batch arguments");
+                                     const fdtd_profile* profiles, const int64_t* steps,
+                                     int32_t ntap, const fdtd_device* dev, size_t* bytes) {
+  if (nruns <= 0 || !grids || !profiles || !steps || !bytes)
+    return fail(FDTD_EINVAL, "bad batch arguments");
+  if (ntap < 0 || ntap > kMaxTaps) return fail(FDTD_EINVAL, "ntap must lie in [0, %d]", kMaxTaps);
   std::vector<RunSpec1D> specs(nruns);
   for (int r = 0; r < nruns; ++r) {
     int rc = validate_1d(&grids[r], &profiles[r], nullptr, true);
     if (rc) return rc;
+    if (steps[r] < 0) return fail(FDTD_EINVAL, "run %d: negative step count", r);
     specs[r].g = grids[r];
     specs[r].p = profiles[r];
+    specs[r].steps = steps[r];
+    specs[r].taps.assign(ntap, 0);
   }
   *bytes = layout_1d(nullptr, specs, FDTD_FP32, dev ? dev->max_probes : 0,
                      dev ? dev->probe_capacity : 0, nullptr);
@@ -541,20 +601,28 @@ int fdtd_plasma_create(const fdtd_grid* grid, const fdtd_profile* profile,
   }
   int rc = validate_1d(grid, profile, source, false);
   if (rc) return rc;
-  return create_1d(1, grid, profile, source, nullptr, dev, out, false);
+  return create_1d(1, grid, profile, source, nullptr, 0, nullptr, dev, out, false);
 }
 
 int fdtd_plasma_create_batch(int32_t nruns, const fdtd_grid* grids, const fdtd_profile* profiles,
-                             const fdtd_source* sources, const int64_t* steps,
-                             const fdtd_device* dev, fdtd_plasma** out) {
+                             const fdtd_source* sources, const int64_t* steps, int32_t ntap,
+                             const int32_t* tap_nodes, const fdtd_device* dev,
+                             fdtd_plasma** out) {
   if (nruns <= 0 || !grids || !profiles || !steps || !out)
     return fail(FDTD_EINVAL, "bad batch arguments");
+  if (ntap < 0 || ntap > kMaxTaps || (ntap > 0 && !tap_nodes))
+    return fail(FDTD_EINVAL, "ntap must lie in [0, %d] with tap_nodes given", kMaxTaps);
   for (int r = 0; r < nruns; ++r) {
     int rc = validate_1d(&grids[r], &profiles[r], sources ? &sources[r] : nullptr, true);
     if (rc) return fail(rc, "run %d: %s", r, g_last_error.c_str());
     if (steps[r] < 0) return fail(FDTD_EINVAL, "run %d: negative step count", r);
+    for (int t = 0; t < ntap; ++t) {
+      const int32_t nd = tap_nodes[(size_t)r * ntap + t];
+      if (nd < 0 || nd > grids[r].nx || !(profiles[r].ne[nd] > 0))
+        return fail(FDTD_EINVAL, "run %d: tap %d is not a plasma node", r, t);
+    }
   }
-  return create_1d(nruns, grids, profiles, sources, steps, dev, out, true);
+  return create_1d(nruns, grids, profiles, sources, steps, ntap, tap_nodes, dev, out, true);
 }
 
 int fdtd_plasma_step(fdtd_plasma* h) { return fdtd_plasma_run(h, 1); }
@@ -565,8 +633,17 @@ int fdtd_plasma_run(fdtd_plasma* h, int64_t nsteps) {
   hipError_t e = hipSetDevice(h->device);
   if (e) return hip_fail(e, "hipSetDevice");
   h->started = true;
+  int64_t nsteps_loop = nsteps;
   if ((e = hipEventRecord(h->ev0, h->stream))) return hip_fail(e, "hipEventRecord");
-  for (int64_t k = 0; k < nsteps; ++k) {
+  if (h->dims == 1 && h->nruns > 1 && h->batch_mode == 0) {
+    e = launch_batch1d_persistent(h->ws + h->runs_off,
+                                  reinterpret_cast<const int32_t*>(h->ws + h->order_off), h->nruns,
+                                  reinterpret_cast<int32_t*>(h->ws + h->queue_off), h->step,
+                                  h->step + nsteps, batch_groups(h), h->stream);
+    if (e) return hip_fail(e, "launch persistent batch kernel");
+    nsteps_loop = 0;
+  }
+  for (int64_t k = 0; k < nsteps_loop; ++k) {
     const int64_t s = h->step + k;
     if (h->dims == 1) {
       // active tiles: those whose run still has steps left (limits are non-increasing)
@@ -774,6 +851,57 @@ int fdtd_plasma_load_state(fdtd_plasma* h, const void* src, size_t len) {
   if (e) return hip_fail(e, "copy state");
   h->step = step;
   h->started = true;
+  return FDTD_OK;
+}
+
+int fdtd_plasma_set_batch_mode(fdtd_plasma* h, int32_t mode, int32_t groups) {
+  if (!h) return fail(FDTD_EINVAL, "null handle");
+  if (h->started) return fail(FDTD_ESTATE, "batch mode must be set before the first step");
+  if (h->dims != 1) return fail(FDTD_EINVAL, "batch modes apply to 1D handles");
+  if (mode != 0 && mode != 1) return fail(FDTD_EINVAL, "mode must be 0 or 1");
+  if (groups < 0 || groups > 65536) return fail(FDTD_EINVAL, "groups out of range");
+  h->batch_mode = mode;
+  h->batch_groups = groups;
+  return FDTD_OK;
+}
+
+int fdtd_plasma_read_taps(fdtd_plasma* h, int32_t run, double* dst, size_t dst_len, size_t* n_out) {
+  if (!h || !dst) return fail(FDTD_EINVAL, "null argument");
+  if (h->dims != 1) return fail(FDTD_EINVAL, "taps exist on 1D handles");
+  if (run < 0 || run >= h->nruns) return fail(FDTD_ERANGE, "run out of range");
+  const Host1D& x = h->h1[run];
+  const int64_t steps = std::min<int64_t>(std::min<int64_t>(h->step, h->specs[run].steps), x.tap_cap);
+  const size_t n = (size_t)x.ntap * steps * 2;
+  if (dst_len < n) return fail(FDTD_ERANGE, "destination holds %zu values, need %zu", dst_len, n);
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e) return hip_fail(e, "synchronise");
+  std::vector<float> buf((size_t)std::max<int64_t>(x.ntap * x.tap_cap, 1) * 2);
+  if (n) {
+    e = hipMemcpy(buf.data(), h->ws + x.off_tap, (size_t)x.ntap * x.tap_cap * 2 * 4, hipMemcpyDeviceToHost);
+    if (e) return hip_fail(e, "copy taps");
+  }
+  const double js = kEps0 / x.dt;
+  for (int t = 0; t < x.ntap; ++t)
+    for (int64_t s = 0; s < steps; ++s) {
+      const size_t src = ((size_t)t * x.tap_cap + s) * 2;
+      const size_t d = ((size_t)t * steps + s) * 2;
+      dst[d] = buf[src];
+      dst[d + 1] = buf[src + 1] * js;
+    }
+  if (n_out) *n_out = n;
+  return FDTD_OK;
+}
+
+int fdtd_plasma_run_status(fdtd_plasma* h, int32_t run, int32_t* status) {
+  if (!h || !status) return fail(FDTD_EINVAL, "null argument");
+  if (h->dims != 1) { *status = 0; return FDTD_OK; }
+  if (run < 0 || run >= h->nruns) return fail(FDTD_ERANGE, "run out of range");
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e) return hip_fail(e, "synchronise");
+  int32_t v = 0;
+  e = hipMemcpy(&v, h->ws + h->status_off + 4 * (size_t)run, 4, hipMemcpyDeviceToHost);
+  if (e) return hip_fail(e, "copy status");
+  *status = v ? FDTD_ENUMERIC : FDTD_OK;
   return FDTD_OK;
 }
 

@@ -55,12 +55,19 @@ struct Host1D {
   std::vector<int32_t> cell_node;
   size_t off_E[2] = {0, 0}, off_H[2] = {0, 0}, off_J = 0, off_df = 0;
   size_t off_cell_node = 0, off_tau = 0, off_dens = 0, off_s = 0, off_b = 0, off_w = 0;
+  int ntap = 0;
+  int64_t tap_cap = 0;
+  size_t off_tap = 0, off_chunk = 0;
 };
 
 // 1D launch (kernels1d.hip)
 template <class T>
 hipError_t launch_step1d(const void* runs, const void* tiles, int ntiles, int64_t step,
                          hipStream_t stream);
+
+hipError_t launch_batch1d_persistent(const void* runs, const int32_t* order, int nruns,
+                                     int32_t* queue, int64_t s0, int64_t s1, int groups,
+                                     hipStream_t stream);
 
 // 2D TEz (fdtd2d.cpp / kernels2d.hip)
 struct Host2D;

@@ -1,8 +1,8 @@
 // kernels1d.hip -- one leap-frog step of the 1D (Ez, Hy) Yee line coupled to the 1V
 // kinetic F1 of every plasma node (arXiv 2211.05647, section 2 and section 5.2).
 //
-// One work-group owns a tile of E nodes [node0, node1) and the plasma nodes inside
-// it [cell0, cell1).  Per step it
+// A work-group of NT threads owns a tile of at most NT E nodes [node0, node1) and the
+// plasma nodes inside it [cell0, cell1).  Per step it
 //   1. loads E^n and H^{n-1/2} around its nodes into registers (and E^n into LDS);
 //   2. advances F1 of its plasma nodes with E^n (Crank-Nicolson in the collision term,
 //      the f_1x update of section 5.2) and reduces the current moment
@@ -13,21 +13,28 @@
 // E and H are double-buffered, so halo values are re-derived from the previous
 // buffers and no work-group ever waits for another inside a step.
 //
+// Two launch forms share that step body:
+//   k_step1d             one launch per step, one work-group per tile (any number of
+//                        runs; tiles of finished runs are left out of the launch);
+//   k_batch1d_persistent one launch for a range of steps of a whole batch of runs: each
+//                        work-group pulls the next run from a longest-first queue (one
+//                        atomic add) and takes it through every step on its own, so no
+//                        work-group ever waits for another.
+//
 // F1 layout: [cell][v > 0 bin], contiguous in the bin index.  A group of `lpc` lanes
 // covers one cell row with 16-byte loads (64 lanes x 16 B = one 1 KB row per wave
 // instruction at Nv = 512); each lane group keeps U rows in flight, and the U FP64
-// partial moments are reduced with a reduce-scatter butterfly (log2(U) exchange
-// rounds that halve the values each lane carries, then plain xor rounds).
+// partial moments are reduced with a reduce-scatter butterfly.
 #include "common.h"
 
 namespace fdtdp {
 
-template <class T, int U>
+template <class T, int U, int NT>
 __device__ __forceinline__ void kinetic_tile(const Run1D<T>& R, const T* eloc,
                                              const Tile1D& tile, T* jloc) {
   using V = typename Vec<T>::type;
   constexpr int VPL = Vec<T>::n;
-  constexpr int kWaves = kBlock / 64;
+  constexpr int kWaves = NT / 64;
   constexpr int CPL = 4 / U;              // chunks per lane this instance handles
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ch = R.half / VPL;            // 16-byte chunks per cell row
@@ -107,9 +114,9 @@ __device__ __forceinline__ void kinetic_tile(const Run1D<T>& R, const T* eloc,
       // tiny rows (fewer lanes than rows in flight): plain all-reduce per row
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        double s = acc[u];
-        for (int o = lpc >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o);
-        if (li == 0 && loc[u] >= 0) jloc[loc[u]] = (T)s;
+        double sm = acc[u];
+        for (int o = lpc >> 1; o > 0; o >>= 1) sm += __shfl_xor(sm, o);
+        if (li == 0 && loc[u] >= 0) jloc[loc[u]] = (T)sm;
       }
     } else {
       int which = 0;
@@ -121,15 +128,11 @@ __device__ __forceinline__ void kinetic_tile(const Run1D<T>& R, const T* eloc,
   }
 }
 
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_step1d(const Run1D<T>* __restrict__ runs,
-                                                   const Tile1D* __restrict__ tiles,
-                                                   int64_t step) {
-  __shared__ T jloc[kMaxTile1D];
-  __shared__ T eloc[kMaxTile1D];
-  const Tile1D tile = tiles[blockIdx.x];
-  const Run1D<T>& R = runs[tile.run];
-  if (step >= R.step_limit) return;
+// One step of one tile by a work-group of NT threads (tile.node1 - tile.node0 <= NT).
+// jloc / eloc: LDS arrays of NT values.  The caller synchronises before reusing them.
+template <class T, int NT>
+__device__ __forceinline__ void step_tile(const Run1D<T>& R, const Tile1D& tile, int64_t step,
+                                          T* jloc, T* eloc) {
   const int par = (int)(step & 1);
   const T* __restrict__ Ec = R.E[par];
   T* __restrict__ En = R.E[par ^ 1];
@@ -158,9 +161,9 @@ __global__ __launch_bounds__(kBlock) void k_step1d(const Run1D<T>* __restrict__ 
   if (tile.cell1 > tile.cell0) {
     const int ch = R.half / Vec<T>::n;
     const int cpl = ch < 64 ? 1 : ch / 64;
-    if (cpl == 1) kinetic_tile<T, 4>(R, eloc, tile, jloc);
-    else if (cpl == 2) kinetic_tile<T, 2>(R, eloc, tile, jloc);
-    else kinetic_tile<T, 1>(R, eloc, tile, jloc);
+    if (cpl == 1) kinetic_tile<T, 4, NT>(R, eloc, tile, jloc);
+    else if (cpl == 2) kinetic_tile<T, 2, NT>(R, eloc, tile, jloc);
+    else kinetic_tile<T, 1, NT>(R, eloc, tile, jloc);
   }
   __syncthreads();
 
@@ -199,11 +202,67 @@ __global__ __launch_bounds__(kBlock) void k_step1d(const Run1D<T>* __restrict__ 
     }
     En[i] = en;
     R.J[i] = jv;
+    if (!isfinite(en)) atomicOr(R.status, 1);
     for (int p = 0; p < R.nprobe; ++p) {
       if (R.probe_node[p] == i) {
         const int f = R.probe_field[p];
         const T val = (f == 0) ? en : (f == 1 ? hn : jv);
         R.probe_buf[(size_t)p * R.probe_cap + (size_t)(step % R.probe_cap)] = val;
+      }
+    }
+    for (int t = 0; t < R.ntap; ++t) {
+      if (R.tap_node[t] == i && step < R.tap_cap) {
+        T* dst = R.tap_buf + ((size_t)t * R.tap_cap + (size_t)step) * 2;
+        dst[0] = e0;   // E^n, the drive of this step's F1 update
+        dst[1] = jv;   // J^{n+1/2}
+      }
+    }
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_step1d(const Run1D<T>* __restrict__ runs,
+                                                   const Tile1D* __restrict__ tiles,
+                                                   int64_t step) {
+  __shared__ T jloc[kMaxTile1D];
+  __shared__ T eloc[kMaxTile1D];
+  const Tile1D tile = tiles[blockIdx.x];
+  const Run1D<T>& R = runs[tile.run];
+  if (step >= R.step_limit) return;
+  step_tile<T, kBlock>(R, tile, step, jloc, eloc);
+}
+
+// Persistent batch: steps [s0, s1) of every run, runs taken longest first from `order`
+// through the counter `*queue` (zero at launch).  Every work-group leaves the loop once
+// the counter passes nruns.
+template <class T>
+__global__ __launch_bounds__(kBatchBlock) void k_batch1d_persistent(
+    const Run1D<T>* __restrict__ runs, const int32_t* __restrict__ order, int nruns,
+    int32_t* queue, int64_t s0, int64_t s1) {
+  __shared__ T jloc[kBatchBlock];
+  __shared__ T eloc[kBatchBlock];
+  __shared__ int32_t next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(queue, 1);
+    __syncthreads();
+    const int qi = next;
+    __syncthreads();
+    if (qi >= nruns) break;
+    const Run1D<T>& R = runs[order[qi]];
+    const int64_t end = s1 < R.step_limit ? s1 : R.step_limit;
+    const int nchunk = (R.nx + kBatchBlock) / kBatchBlock;
+    for (int64_t s = s0; s < end; ++s) {
+      for (int c = 0; c < nchunk; ++c) {
+        Tile1D tile;
+        tile.run = 0;
+        tile.node0 = c * kBatchBlock;
+        tile.node1 = min(R.nx + 1, tile.node0 + kBatchBlock);
+        tile.cell0 = R.chunk_cell[c];
+        tile.cell1 = R.chunk_cell[c + 1];
+        // the barrier at the end of each chunk also orders this step's global stores
+        // before the next step's loads: the whole run lives on one work-group
+        step_tile<T, kBatchBlock>(R, tile, s, jloc, eloc);
+        __syncthreads();
       }
     }
   }
@@ -216,6 +275,17 @@ hipError_t launch_step1d(const void* runs, const void* tiles, int ntiles, int64_
   hipLaunchKernelGGL(k_step1d<T>, dim3(ntiles), dim3(kBlock), 0, stream,
                      static_cast<const Run1D<T>*>(runs), static_cast<const Tile1D*>(tiles),
                      step);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch1d_persistent(const void* runs, const int32_t* order, int nruns,
+                                     int32_t* queue, int64_t s0, int64_t s1, int groups,
+                                     hipStream_t stream) {
+  if (nruns <= 0 || s1 <= s0) return hipSuccess;
+  hipError_t e = hipMemsetAsync(queue, 0, sizeof(int32_t), stream);
+  if (e) return e;
+  hipLaunchKernelGGL(k_batch1d_persistent<float>, dim3(groups), dim3(kBatchBlock), 0, stream,
+                     static_cast<const Run1D<float>*>(runs), order, nruns, queue, s0, s1);
   return hipGetLastError();
 }
 

@@ -1,0 +1,137 @@
+"""GPU tests of the batched 1D path: many independent runs of uneven size in one
+persistent launch (work-groups pull whole runs longest-first from a queue), the per-step
+alternative, the training-pair taps, per-run status, and parity with solo runs and with
+the FP64 oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2211_05647_amd import binding as B
+from paper_2211_05647_amd import workloads as W
+from parity import oracle_1d, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _banner(msg):
+    print(f"[gpu-batch] {msg}", flush=True)
+
+
+def small_batch(n=10, seed=3, nx_hi=1500):
+    g = np.random.default_rng(seed)
+    runs = []
+    for r in range(n):
+        nx = int(g.integers(300, nx_hi))
+        nv = int(g.choice([64, 128, 256]))
+        f_src = W.F_REF * (1 + g.uniform(-0.3, 0.3))
+        run = W.slab_1d(nx, nv, int(0.4 * nx), int(0.6 * nx), g.uniform(0.2, 2.0),
+                        10 ** g.uniform(-2, 0), f_src, int(0.1 * nx), 2 * nx,
+                        name=f"b{r}")
+        runs.append(run)
+    return runs
+
+
+def tap_nodes(runs, ntap, seed=9):
+    g = np.random.default_rng(seed)
+    out = np.zeros((len(runs), ntap), dtype=np.int32)
+    for r, run in enumerate(runs):
+        cells = np.nonzero(run.ne > 0)[0]
+        out[r] = g.choice(cells, size=ntap, replace=False)
+    return out
+
+
+FIELDS = (B.F_E, B.F_H, B.F_J, B.F_DF)
+
+
+@pytest.mark.parametrize("mode,groups", [(0, 0), (0, 3), (1, 0)])
+def test_batch_equals_solo_bitwise(gpu_lib, mode, groups):
+    """Run r of a batch ends bitwise equal to run r simulated alone, whatever the launch
+    form (persistent queue with one or fewer work-groups per run, or one launch per step)."""
+    runs = small_batch()
+    _banner(f"batch == solo, mode={mode} groups={groups}")
+    bat = B.Sim(runs, batch_mode=mode, groups=groups)
+    bat.run(max(r.steps for r in runs) + 5)
+    for r, run in enumerate(runs):
+        solo = B.Sim(run)
+        solo.run(run.steps)
+        for f in FIELDS:
+            assert np.array_equal(bat.read(f, run=r), solo.read(f)), (r, f)
+        solo.close()
+
+
+def test_batch_in_chunks_equals_one_call(gpu_lib):
+    runs = small_batch(6, seed=11)
+    _banner("batch in chunks")
+    a = B.Sim(runs)
+    a.run(max(r.steps for r in runs))
+    b = B.Sim(runs)
+    for k in (1, 7, 250, 999, 4000):
+        b.run(k)
+    for r in range(len(runs)):
+        for f in FIELDS:
+            assert np.array_equal(a.read(f, run=r), b.read(f, run=r))
+
+
+def test_batch_parity_with_oracle(gpu_lib):
+    runs = small_batch(5, seed=21, nx_hi=900)
+    _banner("batch vs oracle")
+    bat = B.Sim(runs)
+    snaps_g, snaps_o = [[] for _ in runs], [[] for _ in runs]
+    orcs = [oracle_1d(run) for run in runs]
+    done = 0
+    total = max(r.steps for r in runs)
+    while done < total:
+        bat.run(200)
+        done += 200
+        for r, run in enumerate(runs):
+            k = min(done, run.steps) - orcs[r].step
+            if k > 0:
+                orcs[r].run(k)
+            snaps_g[r].append(bat.read(B.F_E, run=r))
+            snaps_o[r].append(orcs[r].E.copy())
+    for r in range(len(runs)):
+        err = rel_l2(np.array(snaps_g[r]), np.array(snaps_o[r]))
+        _banner(f"run {r}: space-time rel L2 {err:.2e}")
+        assert err <= 1e-5
+
+
+def test_taps_record_drive_and_current(gpu_lib):
+    """Taps hold (E^n, J^{n+1/2}) at their nodes for every step: checked against the
+    oracle stepped one step at a time."""
+    runs = small_batch(3, seed=31, nx_hi=500)
+    taps = tap_nodes(runs, 4)
+    _banner("taps")
+    bat = B.Sim(runs, taps=taps)
+    bat.run(max(r.steps for r in runs))
+    for r, run in enumerate(runs):
+        got = bat.read_taps(r)
+        assert got.shape == (4, run.steps, 2)
+        o = oracle_1d(run)
+        E = np.zeros((run.steps, 4))
+        J = np.zeros((run.steps, 4))
+        for s in range(run.steps):
+            E[s] = o.E[taps[r]]
+            o.run(1)
+            J[s] = o.J[taps[r]]
+        assert rel_l2(got[:, :, 0].T, E) <= 1e-5
+        assert rel_l2(got[:, :, 1].T, J) <= 1e-5
+
+
+def test_nonfinite_run_is_flagged_alone(gpu_lib):
+    """A run whose density overflows FP32 storage turns non-finite; only that run is
+    flagged and the others stay bitwise equal to their solo runs."""
+    runs = small_batch(4, seed=41)
+    runs[2].ne[runs[2].ne > 0] = 1e39
+    _banner("non-finite run")
+    bat = B.Sim(runs)
+    bat.run(max(r.steps for r in runs))
+    assert bat.run_status(2) == B.ENUMERIC
+    with pytest.raises(B.FdtdError) as ei:
+        bat.read(B.F_E, run=2)
+    assert ei.value.code == B.ENUMERIC
+    for r in (0, 1, 3):
+        assert bat.run_status(r) == B.OK
+        solo = B.Sim(runs[r])
+        solo.run(runs[r].steps)
+        assert np.array_equal(bat.read(B.F_E, run=r), solo.read(B.F_E))
