@@ -9,7 +9,11 @@ log-uniform collision rates, FP32 storage with FP64 moments.  Inputs are synthet
 seeded.  The metric counts phase-space updates (plasma cell x signed velocity bin x
 step) per second.
 
-Prints one JSON line.  ``--gpus N`` with N > 1 exits: this path runs on one GPU.
+Prints one JSON line.  The other workloads (Nx = 2^20 line, the 2D column, the batch of
+256 runs) are timed too and reported under "extra" unless --quick is given.
+``--calibrate-copy`` only runs a plain device copy of known size (the reference kernel
+for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE).  ``--gpus N`` with N > 1 exits: this
+path runs on one GPU.
 """
 import argparse
 import hashlib
@@ -29,7 +33,7 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def pmc_traffic(bytes_alg):
+def pmc_traffic():
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
     on the kernel as it is now (else None)."""
     p = os.path.join(ROOT, "profiles", "k_step1d_c1_pmc.json")
@@ -39,6 +43,22 @@ def pmc_traffic(bytes_alg):
     if d.get("kernel_hash") != kernel_hash():
         return None
     return d.get("hbm_bytes_per_launch")
+
+
+def bytes_1d(run):
+    """Algorithmic bytes of one launch of the 1D step kernel: F1 read + write (half grid,
+    FP32), per-cell scalars (node index, dt*nu, density), fields (E and H read and
+    written, J written) over the whole line."""
+    ncell, half, nx = run.plasma_cells, run.nv // 2, run.nx
+    return ncell * half * 4 * 2 + ncell * 12 + (nx + 1) * 4 * 5
+
+
+def bytes_2d(run):
+    """Algorithmic bytes of one 2D step (both launches): F1 read + write, per-cell
+    scalars and E gather, Ex/Ey/Hz read + written, cell currents written and read."""
+    ncell, half, nx, ny = run.plasma_cells, run.nv * run.nv // 2, run.nx, run.ny
+    npt = nx * ny
+    return ncell * half * 4 * 2 + ncell * (12 + 16 + 8) + npt * 4 * (6 + 4)
 
 
 def cpu_baseline(run, budget_s=15.0):
@@ -64,13 +84,92 @@ def cpu_baseline(run, budget_s=15.0):
                        f"from the zero state, FP64 on the full signed grid, {t:.1f} s")
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def time_single(run, B, torch, steps, warmup, tile=0):
+    sim = B.Sim(run, precision=B.FP32, tile=tile)
+    sim.run(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.run(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = sim.last_run_ms()
+    if hasattr(run, "ny"):
+        sim.read(B.F_EY)
+    else:
+        sim.read(B.F_E)
+    sim.close()
+    return wall, ms
+
+
+def extra_workloads(B, W, torch, autotune):
+    out = {}
+    # 1D line with Nx = 2^20: F1 (1.07 GB) far above every cache
+    run = W.c1_large()
+    log(f"c1l: Nx={run.nx} plasma cells={run.plasma_cells}")
+    tile = autotune.lookup(run, B.FP32) or autotune.lookup(W.c1(nx=4096, steps=1), B.FP32)
+    wall, ms = time_single(run, B, torch, run.steps, 50, tile)
+    by = bytes_1d(run)
+    out["c1_nx2e20"] = dict(workload="1D Yee + 1V kinetic, Nx=1048576, Nv=512, FP32, 2000 steps",
+                            updates_per_s=run.plasma_cells * run.nv * run.steps / wall,
+                            ms_per_step=wall / run.steps * 1e3, kernel_ms=ms,
+                            hbm_gbs=by / (ms * 1e-3) / 1e9,
+                            hbm_frac=by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+    # 2D column
+    run = W.c2()
+    log(f"c2: {run.nx}x{run.ny} plasma cells={run.plasma_cells}")
+    tile = autotune.lookup(run, B.FP32)
+    wall, ms = time_single(run, B, torch, run.steps, 100, tile)
+    by = bytes_2d(run)
+    out["c2"] = dict(workload="2D TEz 512x512 + 2V kinetic 32x32, FP32, 4000 steps",
+                     updates_per_s=run.plasma_cells * run.nv ** 2 * run.steps / wall,
+                     ms_per_step=wall / run.steps * 1e3, step_ms=ms,
+                     hbm_gbs=by / (ms * 1e-3) / 1e9,
+                     hbm_frac=by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+    # batch of 256 uneven runs, one persistent launch
+    runs = W.c3()
+    work = sum(r.plasma_cells * r.nv * r.steps for r in runs)
+    by = sum(bytes_1d(r) * r.steps for r in runs)
+    tot = max(r.steps for r in runs)
+    log(f"c3: {len(runs)} runs, {tot} steps max")
+    sim = B.Sim(runs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.run(tot)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sim.close()
+    out["c3"] = dict(workload="256 independent 1D runs, Nx in [500, 20000], Nv in {64,128,256}, "
+                              "2 Nx steps each, one persistent launch",
+                     updates_per_s=work / wall, seconds=wall, hbm_gbs=by / wall / 1e9,
+                     hbm_frac=by / wall / 1e9 / HBM_PEAK_GBS)
+    return out
+
+
+def calibrate_copy(torch):
+    """Plain device copies of known size: 5 x 1 GiB read + 1 GiB written."""
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read_per_launch": n * 4, "copy_bytes_written_per_launch": n * 4,
+                      "launches": 5}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="only the headline workload")
     ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the kinetic-FDTD path here runs on a single "
@@ -79,35 +178,23 @@ def main():
 
     import torch
     sys.path.insert(0, ROOT)
+    if args.calibrate_copy:
+        calibrate_copy(torch)
+        return
+    from paper_2211_05647_amd import autotune
     from paper_2211_05647_amd import binding as B
     from paper_2211_05647_amd import workloads as W
 
     run = W.c1()
-    print(f"[bench] workload c1: Nx={run.nx} Nv={run.nv} plasma cells={run.plasma_cells}",
-          file=sys.stderr, flush=True)
-    from paper_2211_05647_amd import autotune
+    log(f"workload c1: Nx={run.nx} Nv={run.nv} plasma cells={run.plasma_cells}")
     tile = args.tile or autotune.lookup(run, B.FP32)
-    print(f"[bench] tile={tile or 'default'}", file=sys.stderr, flush=True)
-    sim = B.Sim(run, precision=B.FP32, tile=tile)
-    sim.run(args.warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.run(args.steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_dev = sim.last_run_ms()          # HIP events on the launch stream, per step
-    # sanity: the run must have stayed finite
-    sim.read(B.F_E)
+    log(f"tile={tile or 'default'}")
+    wall, ms_dev = time_single(run, B, torch, args.steps, args.warmup, tile)
 
     ncell, nv, half, nx = run.plasma_cells, run.nv, run.nv // 2, run.nx
-    updates = ncell * nv * args.steps
-    value = updates / wall
-    # algorithmic bytes of one launch of the fused step kernel: F1 read + write
-    # (half grid, FP32), per-cell scalars (node index, dt*nu, density), fields
-    # (E and H read + written, J written) over the whole line
-    bytes_alg = ncell * half * 4 * 2 + ncell * 12 + (nx + 1) * 4 * 5
+    value = ncell * nv * args.steps / wall
+    bytes_alg = bytes_1d(run)
     achieved = bytes_alg / (ms_dev * 1e-3) / 1e9
-    traffic = pmc_traffic(bytes_alg)
     out = {
         "metric": "kinetic-FDTD phase-space updates/s",
         "value": value,
@@ -127,12 +214,14 @@ def main():
         "stored_bin_updates_per_s": ncell * half * args.steps / wall,
         "roofline": {"bound": "hbm", "kernel": "k_step1d<float>", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "bytes_per_launch": bytes_alg,
+                     "traffic": pmc_traffic(), "bytes_per_launch": bytes_alg,
                      "launch_ms": ms_dev},
         "context": "paper: MATLAB plasma code ~20x GPU (GTX 1050) over serial CPU (i7-7700HQ)",
     }
+    if not args.quick:
+        out["extra"] = extra_workloads(B, W, torch, autotune)
     if not args.no_cpu_baseline:
-        print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
+        log("timing the FP64 oracle on the host")
         out["cpu_baseline"] = cpu_baseline(run)
     print(json.dumps(out), flush=True)
 

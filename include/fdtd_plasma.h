@@ -139,9 +139,9 @@ int fdtd_plasma_create(const fdtd_grid *grid, const fdtd_profile *profile,
  * advanced together.  steps[r] is the step count of run r: fdtd_plasma_run advances
  * every run to min(its own count, the batch step).  ntap (0..8) training-pair taps per
  * run record (E^n, J^{n+1/2}) at the plasma nodes tap_nodes[r * ntap + k] after every
- * step of that run (NULL when ntap = 0).  Default launch: one persistent launch per
- * fdtd_plasma_run, work-groups pulling whole runs longest-first from a queue
- * (see fdtd_plasma_set_batch_mode).  Workspace size via fdtd_plasma_workspace_size_batch. */
+ * step of that run (NULL when ntap = 0).  Default launch: one launch per step over the
+ * tiles of the runs still active (see fdtd_plasma_set_batch_mode for the persistent
+ * form).  Workspace size via fdtd_plasma_workspace_size_batch. */
 int fdtd_plasma_workspace_size_batch(int32_t nruns, const fdtd_grid *grids,
                                      const fdtd_profile *profiles, const int64_t *steps,
                                      int32_t ntap, const fdtd_device *dev, size_t *bytes);
@@ -150,9 +150,11 @@ int fdtd_plasma_create_batch(int32_t nruns, const fdtd_grid *grids,
                              const int64_t *steps, int32_t ntap, const int32_t *tap_nodes,
                              const fdtd_device *dev, fdtd_plasma **out);
 
-/* Batch launch form: mode 0 = persistent work-queue launch with `groups` work-groups
- * (0 = one per run, capped by the device's resident capacity); mode 1 = one launch per
- * step over the tiles of the runs still active.  Only before the first step. */
+/* Batch launch form: mode 0 = one persistent launch per fdtd_plasma_run, `groups`
+ * work-groups (0 = one per run, at most two per compute unit) each pulling whole runs
+ * longest-first from a queue and taking them through every step alone; mode 1 (default)
+ * = one launch per step over the tiles of the runs still active.  Both give bitwise
+ * identical results.  Only before the first step. */
 int fdtd_plasma_set_batch_mode(fdtd_plasma *h, int32_t mode, int32_t groups);
 
 /* Copy the taps of run `run`: [ntap][steps taken by that run][2] doubles, (E in V/m,

@@ -130,7 +130,7 @@ class Sim:
 
     def __init__(self, workload, precision=FP32, device=0, max_probes=0, probe_capacity=0,
                  closure=CLOSURE_KINETIC, mlp_blob=None, tile=0, cells_per_group=0,
-                 taps=None, batch_mode=0, groups=0):
+                 taps=None, batch_mode=None, groups=0):
         import torch
         self.torch = torch
         L = lib()
@@ -195,8 +195,9 @@ class Sim:
             check(L.fdtd_plasma_create(C.byref(grids[0]), C.byref(profs[0]), C.byref(srcs[0]), C.byref(dev), C.byref(h)),
                   "create")
         self.h = h
-        if self.batch and (batch_mode or groups):
-            check(L.fdtd_plasma_set_batch_mode(self.h, batch_mode, groups), "set_batch_mode")
+        if self.batch and (batch_mode is not None or groups):
+            mode = 1 if batch_mode is None else batch_mode
+            check(L.fdtd_plasma_set_batch_mode(self.h, mode, groups), "set_batch_mode")
         if tile or cells_per_group:
             check(L.fdtd_plasma_set_tiling(self.h, tile, cells_per_group), "set_tiling")
 

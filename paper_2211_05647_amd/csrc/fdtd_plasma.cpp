@@ -174,7 +174,7 @@ struct fdtd_plasma {
   int ntiles = 0;
   std::vector<int64_t> tile_limit;   // step limit of each tile, non-increasing
   size_t order_off = 0, queue_off = 0, status_off = 0;
-  int batch_mode = 0, batch_groups = 0, ntap = 0;
+  int batch_mode = 1, batch_groups = 0, ntap = 0;   // batch default: per-step launches
   // probes
   int max_probes = 0, probe_cap = 0;
   size_t probe_off = 0;
