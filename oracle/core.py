@@ -50,6 +50,10 @@ def lib():
              C.c_longlong, C.c_longlong,
              _dp, _dp, _dp, _dp, _dp, _dp, _dp,
              C.c_int, _ip, _dp])
+        L.oracle_replay1v.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, C.c_double,
+                                      C.c_double, C.c_double, C.c_longlong, _dp, _dp]
+        L.oracle_replay2v.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, C.c_double,
+                                      C.c_double, C.c_double, C.c_longlong, _dp, _dp, _dp, _dp]
         _lib = L
     return _lib
 
@@ -108,6 +112,29 @@ def cpml_profile(n, ncpml, dx, dt, order=3.0, sigma_factor=1.0, kappa_max=5.0,
     lib().oracle_cpml_profile(n, ncpml, dx, dt, order, sigma_factor, kappa_max, alpha_min,
                               alpha_max, _p(be), _p(ae), _p(ke), _p(bh), _p(ah), _p(kh))
     return dict(be=be, ae=ae, ke=ke, bh=bh, ah=ah, kh=kh)
+
+
+def replay1v(E, ne, nubar, dt, nv=64, vmax_over_vth=6.0, te_ev=2.0, nu_model="hard_sphere"):
+    """One isolated 1V cell driven by the series E[n] = E^n; returns J^{n+1/2} (A/m^2)."""
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    J = np.zeros_like(E)
+    rc = lib().oracle_replay1v(nv, vmax_over_vth, te_ev, {"hard_sphere": 0, "const": 1}[nu_model],
+                               ne, nubar, dt, len(E), _p(E), _p(J))
+    if rc:
+        raise ValueError("bad replay arguments")
+    return J
+
+
+def replay2v(Ex, Ey, ne, nubar, dt, nv=32, vmax_over_vth=6.0, te_ev=5.0, nu_model="hard_sphere"):
+    """One isolated 2V cell driven by (Ex, Ey)[n]; returns (Jx, Jy)^{n+1/2} (A/m^2)."""
+    Ex = np.ascontiguousarray(Ex, dtype=np.float64)
+    Ey = np.ascontiguousarray(Ey, dtype=np.float64)
+    Jx, Jy = np.zeros_like(Ex), np.zeros_like(Ex)
+    rc = lib().oracle_replay2v(nv, vmax_over_vth, te_ev, {"hard_sphere": 0, "const": 1}[nu_model],
+                               ne, nubar, dt, len(Ex), _p(Ex), _p(Ey), _p(Jx), _p(Jy))
+    if rc:
+        raise ValueError("bad replay arguments")
+    return Jx, Jy
 
 
 class Oracle1D:

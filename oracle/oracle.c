@@ -434,3 +434,67 @@ int oracle_run2d(int nx, int ny, double dx, double courant,
     free(cell_idx); free(jbx); free(jby);
     return 0;
 }
+
+/* ---------------------------------------------------------------------------
+ * Isolated plasma cells driven by a prescribed field (training data for the
+ * learned closure and its checks).  The F1 update and current moment are those
+ * of the coupled runs above (section 5.2), with E^n taken from the input series
+ * instead of a grid.  Returns J^{n+1/2} (SI) for every n.
+ * ------------------------------------------------------------------------- */
+int oracle_replay1v(int nv, double vmax_over_vth, double te_ev, int nu_model,
+                    double ne, double nubar, double dt, long long nsteps,
+                    const double *E, double *J)
+{
+    double *v = malloc(sizeof(double) * nv), *fh = malloc(sizeof(double) * nv);
+    double *gh = malloc(sizeof(double) * nv), *sh = malloc(sizeof(double) * nv);
+    double *f = calloc(nv, sizeof(double));
+    double dv, vth;
+    if (oracle_vgrid(nv, vmax_over_vth, te_ev, v, fh, gh, &dv, &vth) != 0) {
+        free(v); free(fh); free(gh); free(sh); free(f); return -1;
+    }
+    oracle_nu_shape(1, nv, v, fh, dv, nu_model, sh);
+    for (long long n = 0; n < nsteps; ++n) {
+        double acc = 0.0;
+        for (int j = 0; j < nv; ++j) {
+            double nu = nubar * sh[j];
+            f[j] = ((2.0 - dt * nu) * f[j] + 2.0 * dt * (K_QE / K_ME) * ne * gh[j] * E[n])
+                   / (2.0 + dt * nu);
+            acc += v[j] * f[j];
+        }
+        J[n] = -K_QE * dv * acc;
+    }
+    free(v); free(fh); free(gh); free(sh); free(f);
+    return 0;
+}
+
+int oracle_replay2v(int nv, double vmax_over_vth, double te_ev, int nu_model,
+                    double ne, double nubar, double dt, long long nsteps,
+                    const double *Ex, const double *Ey, double *Jx, double *Jy)
+{
+    double *v = malloc(sizeof(double) * nv), *fh = malloc(sizeof(double) * nv);
+    double *gh = malloc(sizeof(double) * nv), *sh = malloc(sizeof(double) * nv * nv);
+    double *f = calloc((size_t)nv * nv, sizeof(double));
+    double dv, vth;
+    if (oracle_vgrid(nv, vmax_over_vth, te_ev, v, fh, gh, &dv, &vth) != 0) {
+        free(v); free(fh); free(gh); free(sh); free(f); return -1;
+    }
+    oracle_nu_shape(2, nv, v, fh, dv, nu_model, sh);
+    for (long long n = 0; n < nsteps; ++n) {
+        double ax = 0.0, ay = 0.0;
+        for (int a = 0; a < nv; ++a)
+            for (int b = 0; b < nv; ++b) {
+                int q = a * nv + b;
+                double f2 = fh[a] * fh[b];
+                double gx = -v[a] * f2 / (vth * vth), gy = -v[b] * f2 / (vth * vth);
+                double nu = nubar * sh[q];
+                f[q] = ((2.0 - dt * nu) * f[q]
+                        + 2.0 * dt * (K_QE / K_ME) * ne * (gx * Ex[n] + gy * Ey[n])) / (2.0 + dt * nu);
+                ax += v[a] * f[q];
+                ay += v[b] * f[q];
+            }
+        Jx[n] = -K_QE * dv * dv * ax;
+        Jy[n] = -K_QE * dv * dv * ay;
+    }
+    free(v); free(fh); free(gh); free(sh); free(f);
+    return 0;
+}
