@@ -54,7 +54,7 @@ enum fdtd_status {
 enum fdtd_precision { FDTD_FP64 = 0, FDTD_FP32 = 1 };
 enum fdtd_boundary { FDTD_BC_PEC = 0, FDTD_BC_MUR1 = 1, FDTD_BC_CPML = 2 };
 enum fdtd_nu_model { FDTD_NU_HARD_SPHERE = 0, FDTD_NU_CONST = 1 };
-enum fdtd_closure { FDTD_CLOSURE_KINETIC = 0, FDTD_CLOSURE_MLP = 1 };
+enum fdtd_closure_kind { FDTD_CLOSURE_KINETIC = 0, FDTD_CLOSURE_MLP = 1 };
 enum fdtd_source_kind { FDTD_SRC_NONE = 0, FDTD_SRC_LINE_SOFT = 1, FDTD_SRC_POINT_SOFT = 2 };
 
 /* Field selectors for read_fields / add_probe.

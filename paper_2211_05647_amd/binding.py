@@ -75,6 +75,19 @@ _SIGS = {
     "fdtd_plasma_set_tiling": ([C.c_void_p, C.c_int32, C.c_int32], C.c_int),
     "fdtd_plasma_last_run_ms": ([C.c_void_p, C.POINTER(C.c_double)], C.c_int),
     "fdtd_plasma_destroy": ([C.c_void_p], None),
+    "fdtd_plasma_tap_buffer": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.POINTER(C.c_int32)], C.c_int),
+    "fdtd_closure_workspace_size": ([C.c_int32, C.c_int32, C.POINTER(C.c_size_t)], C.c_int),
+    "fdtd_closure_create": ([C.POINTER(Device), C.c_int32, C.c_int32, C.POINTER(C.c_void_p)], C.c_int),
+    "fdtd_closure_set_params": ([C.c_void_p, C.POINTER(C.c_float), C.c_size_t], C.c_int),
+    "fdtd_closure_get_params": ([C.c_void_p, C.POINTER(C.c_float), C.c_size_t], C.c_int),
+    "fdtd_closure_forward": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
+    "fdtd_closure_grad": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_float)], C.c_int),
+    "fdtd_closure_adam": ([C.c_void_p, C.c_float, C.c_float, C.c_float, C.c_float], C.c_int),
+    "fdtd_closure_train_step": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float, C.POINTER(C.c_float)], C.c_int),
+    "fdtd_closure_single_pole": ([C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_double, C.c_double, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
+    "fdtd_closure_replay2v": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int32, C.c_int64, _dp, _dp, C.c_double, C.c_double, C.c_int32, C.c_double, C.c_void_p, C.c_int64], C.c_int),
+    "fdtd_closure_make_pairs": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_int64), C.c_int32, C.c_void_p, C.c_void_p], C.c_int),
+    "fdtd_closure_destroy": ([C.c_void_p], None),
     "fdtd_plasma_strerror": ([C.c_int], C.c_char_p),
     "fdtd_plasma_last_error": ([], C.c_char_p),
 }
@@ -267,7 +280,108 @@ class Sim:
         check(lib().fdtd_plasma_run_status(self.h, run, C.byref(st)), "run_status")
         return st.value
 
+    def tap_buffer(self, run):
+        """(device pointer, capacity, ntap) of a batch run's tap buffer [ntap][cap][2] FP32."""
+        ptr, cap, nt = C.c_void_p(), C.c_int64(), C.c_int32()
+        check(lib().fdtd_plasma_tap_buffer(self.h, run, C.byref(ptr), C.byref(cap), C.byref(nt)), "tap_buffer")
+        return ptr.value, cap.value, nt.value
+
     def last_run_ms(self):
         ms = C.c_double()
         check(lib().fdtd_plasma_last_run_ms(self.h, C.byref(ms)), "last_run_ms")
         return ms.value
+
+
+NPARAM = 19073
+NIN = 18
+
+
+def single_pole(dims, nv, te_ev, nu_model, ne, nu_mean, dt, vmax_over_vth=6.0):
+    """(alpha, beta) of the single-pole recurrence of a kinetic cell (library routine)."""
+    a, b = C.c_double(), C.c_double()
+    check(lib().fdtd_closure_single_pole(dims, nv, vmax_over_vth, te_ev,
+                                         NU_HARD_SPHERE if nu_model == "hard_sphere" else NU_CONST,
+                                         ne, nu_mean, dt, C.byref(a), C.byref(b)), "single_pole")
+    return a.value, b.value
+
+
+class Closure:
+    """The learned closure's trainer/evaluator on the GPU (argument marshalling only).
+    Feature rows, targets and outputs are torch float32 tensors on the device."""
+
+    def __init__(self, max_rows=4096, max_series=4096, device=0):
+        import torch
+        self.torch = torch
+        self.stream = torch.cuda.current_stream(device)
+        n = C.c_size_t()
+        check(lib().fdtd_closure_workspace_size(max_rows, max_series, C.byref(n)), "closure_workspace_size")
+        self.workspace = torch.empty(n.value + 256, dtype=torch.uint8, device=f"cuda:{device}")
+        dev = Device(device, C.c_void_p(self.stream.cuda_stream), C.c_void_p(self.workspace.data_ptr()),
+                     self.workspace.numel(), 0, 0)
+        h = C.c_void_p()
+        check(lib().fdtd_closure_create(C.byref(dev), max_rows, max_series, C.byref(h)), "closure_create")
+        self.h = h
+        self.max_rows = max_rows
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fdtd_closure_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        check(lib().fdtd_closure_set_params(self.h, p.ctypes.data_as(C.POINTER(C.c_float)), p.size), "set_params")
+
+    def get_params(self):
+        p = np.empty(NPARAM, dtype=np.float32)
+        check(lib().fdtd_closure_get_params(self.h, p.ctypes.data_as(C.POINTER(C.c_float)), p.size), "get_params")
+        return p
+
+    def forward(self, X):
+        Y = self.torch.empty(X.shape[0], dtype=self.torch.float32, device=X.device)
+        check(lib().fdtd_closure_forward(self.h, X.data_ptr(), X.shape[0], Y.data_ptr()), "forward")
+        return Y
+
+    def grad(self, X, T):
+        g = np.empty(NPARAM, dtype=np.float32)
+        loss = C.c_float()
+        check(lib().fdtd_closure_grad(self.h, X.data_ptr(), T.data_ptr(), X.shape[0],
+                                      g.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss)), "grad")
+        return loss.value, g
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        check(lib().fdtd_closure_adam(self.h, lr, beta1, beta2, eps), "adam")
+
+    def train_step(self, X, T, lr, want_loss=False):
+        loss = C.c_float()
+        check(lib().fdtd_closure_train_step(self.h, X.data_ptr(), T.data_ptr(), X.shape[0], lr,
+                                            C.byref(loss) if want_loss else None), "train_step")
+        return loss.value if want_loss else None
+
+    def replay2v(self, E_ptr, e_stride, e_series_stride, nseries, nsteps, ne, nu, te_ev, dt, J,
+                 j_series_stride, nu_model="hard_sphere", vmax_over_vth=6.0):
+        ne, pne = _arr(ne)
+        nu, pnu = _arr(nu)
+        check(lib().fdtd_closure_replay2v(self.h, E_ptr, e_stride, e_series_stride, nseries, nsteps,
+                                          pne, pnu, te_ev, vmax_over_vth,
+                                          NU_HARD_SPHERE if nu_model == "hard_sphere" else NU_CONST,
+                                          dt, J.data_ptr(), j_series_stride), "replay2v")
+
+    def make_pairs(self, E_ptr, e_stride, e_series_stride, J, j_series_stride, series4, idx):
+        series4 = np.ascontiguousarray(series4, dtype=np.float32)
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        n = idx.size
+        X = self.torch.empty((n, NIN), dtype=self.torch.float32, device=J.device)
+        T = self.torch.empty(n, dtype=self.torch.float32, device=J.device)
+        check(lib().fdtd_closure_make_pairs(self.h, E_ptr, e_stride, e_series_stride, J.data_ptr(),
+                                            j_series_stride, series4.shape[0],
+                                            series4.ctypes.data_as(C.POINTER(C.c_float)),
+                                            idx.ctypes.data_as(C.POINTER(C.c_int64)), n,
+                                            X.data_ptr(), T.data_ptr()), "make_pairs")
+        return X, T

@@ -14,6 +14,7 @@
 #include <string>
 #include <vector>
 
+#include "../../include/fdtd_closure.h"
 #include "../../include/fdtd_plasma.h"
 #include "common.h"
 #include "host_internal.h"
@@ -889,6 +890,18 @@ int fdtd_plasma_read_taps(fdtd_plasma* h, int32_t run, double* dst, size_t dst_l
       dst[d + 1] = buf[src + 1] * js;
     }
   if (n_out) *n_out = n;
+  return FDTD_OK;
+}
+
+int fdtd_plasma_tap_buffer(fdtd_plasma* h, int32_t run, const float** dev, int64_t* cap,
+                           int32_t* ntap) {
+  if (!h || !dev || !cap || !ntap) return fail(FDTD_EINVAL, "null argument");
+  if (h->dims != 1 || h->precision != FDTD_FP32) return fail(FDTD_EINVAL, "taps exist on FP32 1D handles");
+  if (run < 0 || run >= h->nruns) return fail(FDTD_ERANGE, "run out of range");
+  const Host1D& x = h->h1[run];
+  *dev = reinterpret_cast<const float*>(h->ws + x.off_tap);
+  *cap = x.tap_cap;
+  *ntap = x.ntap;
   return FDTD_OK;
 }
 

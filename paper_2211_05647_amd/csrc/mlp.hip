@@ -1,0 +1,478 @@
+// mlp.hip -- the learned closure: an 18 -> 128 -> 128 -> 1 network (tanh-form GELU) that
+// corrects the single-pole recurrence of a plasma cell's current,
+//     J^{n+1/2} = alpha J^{n-1/2} + beta (E^n + s y),   y = MLP([E^n..E^{n-15}]/s, p1, p2),
+// trained on currents of the kinetic model of section 5.2 (arXiv 2211.05647).
+//
+// GEMM operands are bfloat16 (round to nearest even), accumulation FP32, on the matrix
+// cores (v_mfma_f32_16x16x16_bf16).  One wavefront owns 16 rows; a work-group of 4
+// wavefronts owns 64 rows and keeps the bf16 weights in LDS (rows padded by 8 elements so
+// the 16 lanes of a fragment load hit distinct banks).
+//
+// MFMA 16x16x16 fragment layout (lane l, r0 = l % 16, kq = l / 16):
+//   A (16 x 16, rows x k):  A[r0][4 kq + e], e = 0..3
+//   B (16 x 16, k x cols):  B[4 kq + e][r0]
+//   D (16 x 16):            D[4 kq + e][r0]
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mlp_common.h"
+
+namespace fdtdp {
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);      // round to nearest, ties to even
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ float gelu_f(float x) {
+  const float k = 0.7978845608028654f;   // sqrt(2/pi)
+  return 0.5f * x * (1.0f + tanhf(k * (x + 0.044715f * x * x * x)));
+}
+__device__ __forceinline__ float gelu_grad_f(float x) {
+  const float k = 0.7978845608028654f;
+  const float t = tanhf(k * (x + 0.044715f * x * x * x));
+  return 0.5f * (1.0f + t) + 0.5f * x * (1.0f - t * t) * k * (1.0f + 3.0f * 0.044715f * x * x);
+}
+
+__device__ __forceinline__ f4 mfma(s4 a, s4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// --- weights in LDS -----------------------------------------------------------------
+struct MlpLds {
+  uint16_t W1[kNH * kK1P];     // W1[n][k], k < 18 real, rest zero
+  uint16_t W2[kNH * kK2P];     // W2[n][k]
+  float b1[kNH], b2[kNH], w3[kNH];
+  float b3;
+};
+
+__device__ void load_weights(MlpLds& L, const MlpWeights& W, bool transposed_w2) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  const uint16_t* src2 = transposed_w2 ? W.W2T : W.W2;
+  for (int i = t; i < kNH * kK1P / 4; i += nt)
+    reinterpret_cast<uint2*>(L.W1)[i] = reinterpret_cast<const uint2*>(W.W1)[i];
+  for (int i = t; i < kNH * kK2P / 4; i += nt)
+    reinterpret_cast<uint2*>(L.W2)[i] = reinterpret_cast<const uint2*>(src2)[i];
+  for (int i = t; i < kNH; i += nt) {
+    L.b1[i] = W.b1[i];
+    L.b2[i] = W.b2[i];
+    L.w3[i] = W.w3q[i];
+  }
+  if (t == 0) L.b3 = W.b3[0];
+}
+
+// Forward pass of the 16 rows of this wave.  Xs: [16][kK1P] bf16 features (LDS).
+// A1s: [16][kK2P] bf16 scratch (LDS) that receives GELU(Z1).  On return z1/z2 hold the
+// pre-activations in D layout and y[e] the output of row 4 kq + e.
+__device__ __forceinline__ void wave_forward(const MlpLds& L, const uint16_t* Xs, uint16_t* A1s,
+                                             f4 (&z1)[8], f4 (&z2)[8], float (&y)[4]) {
+  const int l = threadIdx.x & 63, r0 = l & 15, kq = l >> 4;
+#pragma unroll
+  for (int nt = 0; nt < 8; ++nt) {
+    f4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < kK1 / 16; ++kk) {
+      const s4 a = *reinterpret_cast<const s4*>(Xs + r0 * kK1P + kk * 16 + kq * 4);
+      const s4 b = *reinterpret_cast<const s4*>(L.W1 + (nt * 16 + r0) * kK1P + kk * 16 + kq * 4);
+      c = mfma(a, b, c);
+    }
+    const float bias = L.b1[nt * 16 + r0];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      c[e] += bias;
+      A1s[(kq * 4 + e) * kK2P + nt * 16 + r0] = to_bf16(gelu_f(c[e]));
+    }
+    z1[nt] = c;
+  }
+  __syncthreads();
+  float yp[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int nt = 0; nt < 8; ++nt) {
+    f4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < kNH / 16; ++kk) {
+      const s4 a = *reinterpret_cast<const s4*>(A1s + r0 * kK2P + kk * 16 + kq * 4);
+      const s4 b = *reinterpret_cast<const s4*>(L.W2 + (nt * 16 + r0) * kK2P + kk * 16 + kq * 4);
+      c = mfma(a, b, c);
+    }
+    const float bias = L.b2[nt * 16 + r0], w = L.w3[nt * 16 + r0];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      c[e] += bias;
+      yp[e] = fmaf(gelu_f(c[e]), w, yp[e]);
+    }
+    z2[nt] = c;
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    float v = yp[e];
+    for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o);
+    y[e] = v + L.b3;
+  }
+}
+
+// --- inference on rows in global memory ----------------------------------------------
+__global__ __launch_bounds__(256) void k_mlp_rows(MlpWeights W, const float* __restrict__ X,
+                                                  int n, float* __restrict__ Y) {
+  __shared__ MlpLds L;
+  __shared__ uint16_t Xs[4][16 * kK1P];
+  __shared__ uint16_t A1s[4][16 * kK2P];
+  load_weights(L, W, false);
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+  for (int base = blockIdx.x * 64; base < n; base += gridDim.x * 64) {
+    __syncthreads();
+    // stage this wave's 16 feature rows as bf16 (zero padding beyond 18 and n)
+    for (int q = l; q < 16 * kK1; q += 64) {
+      const int r = q / kK1, k = q - r * kK1;
+      const int row = base + wave * 16 + r;
+      const float v = (row < n && k < kNIn) ? X[(size_t)row * kNIn + k] : 0.f;
+      Xs[wave][r * kK1P + k] = to_bf16(v);
+    }
+    __syncthreads();
+    f4 z1[8], z2[8];
+    float y[4];
+    wave_forward(L, Xs[wave], A1s[wave], z1, z2, y);
+    const int r0 = l & 15, kq = l >> 4;
+    if (r0 == 0) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = base + wave * 16 + kq * 4 + e;
+        if (row < n) Y[row] = y[e];
+      }
+    }
+  }
+}
+
+// --- training: forward + backward of one 64-row block, partial gradients --------------
+// Partial gradients of block b go to P[b][kNParam] in the parameter order
+// W1[128][18], b1, W2[128][128], b2, w3, b3; the block's summed squared error to lossp[b].
+__global__ __launch_bounds__(256) void k_mlp_grad(MlpWeights W, const float* __restrict__ X,
+                                                  const float* __restrict__ T, int n,
+                                                  float* __restrict__ P, float* __restrict__ lossp) {
+  __shared__ MlpLds L;                      // W2 slot holds W2 (forward)
+  __shared__ uint16_t W2T[kNH * kK2P];      // W2 transposed (backward, dA1 = dZ2 W2)
+  __shared__ uint16_t Xs[64 * kK1P];
+  __shared__ uint16_t A1s[64 * kK2P];
+  __shared__ uint16_t dZ2s[64 * kK2P];
+  __shared__ uint16_t dZ1s[64 * kK2P];
+  __shared__ float red[4][3 * kNH + 2];     // per-wave column sums: db1, db2, dw3, db3, loss
+  load_weights(L, W, false);
+  for (int i = threadIdx.x; i < kNH * kK2P / 4; i += blockDim.x)
+    reinterpret_cast<uint2*>(W2T)[i] = reinterpret_cast<const uint2*>(W.W2T)[i];
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, r0 = l & 15, kq = l >> 4;
+  const int base = blockIdx.x * 64;
+  for (int q = l; q < 16 * kK1; q += 64) {
+    const int r = q / kK1, k = q - r * kK1;
+    const int row = base + wave * 16 + r;
+    const float v = (row < n && k < kNIn) ? X[(size_t)row * kNIn + k] : 0.f;
+    Xs[(wave * 16 + r) * kK1P + k] = to_bf16(v);
+  }
+  __syncthreads();
+  f4 z1[8], z2[8];
+  float y[4];
+  wave_forward(L, Xs + wave * 16 * kK1P, A1s + wave * 16 * kK2P, z1, z2, y);
+
+  // output error: dy = 2 (y - t) / n for real rows
+  float dy[4], se = 0.f;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int row = base + wave * 16 + kq * 4 + e;
+    const float err = row < n ? (y[e] - T[row]) : 0.f;
+    dy[e] = 2.0f * err / (float)n;
+    se += err * err;
+  }
+  // dZ2, column sums for db2 / dw3, and dZ2 in bf16 for the backward GEMMs
+  float cb2[8], cw3[8];
+#pragma unroll
+  for (int nt = 0; nt < 8; ++nt) {
+    const float w = L.w3[nt * 16 + r0];
+    float sb = 0.f, sw = 0.f;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float a2 = gelu_f(z2[nt][e]);
+      const float d = dy[e] * w * gelu_grad_f(z2[nt][e]);
+      sb += d;
+      sw = fmaf(a2, dy[e], sw);
+      dZ2s[(wave * 16 + kq * 4 + e) * kK2P + nt * 16 + r0] = to_bf16(d);
+    }
+    cb2[nt] = sb;
+    cw3[nt] = sw;
+  }
+  __syncthreads();
+  // dA1 = dZ2 W2  (B[k][j] = W2[k][j] = W2T[j][k]), then dZ1 = dA1 * GELU'(Z1)
+  float cb1[8];
+#pragma unroll
+  for (int nt = 0; nt < 8; ++nt) {
+    f4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < kNH / 16; ++kk) {
+      const s4 a = *reinterpret_cast<const s4*>(dZ2s + (wave * 16 + r0) * kK2P + kk * 16 + kq * 4);
+      const s4 b = *reinterpret_cast<const s4*>(W2T + (nt * 16 + r0) * kK2P + kk * 16 + kq * 4);
+      c = mfma(a, b, c);
+    }
+    float sb = 0.f;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float d = c[e] * gelu_grad_f(z1[nt][e]);
+      sb += d;
+      dZ1s[(wave * 16 + kq * 4 + e) * kK2P + nt * 16 + r0] = to_bf16(d);
+    }
+    cb1[nt] = sb;
+  }
+  // reduce the column sums over the 4 row groups of the wave, then over waves via LDS
+#pragma unroll
+  for (int nt = 0; nt < 8; ++nt) {
+    float a = cb1[nt], b = cb2[nt], c = cw3[nt];
+    a += __shfl_xor(a, 16); a += __shfl_xor(a, 32);
+    b += __shfl_xor(b, 16); b += __shfl_xor(b, 32);
+    c += __shfl_xor(c, 16); c += __shfl_xor(c, 32);
+    if (kq == 0) {
+      red[wave][nt * 16 + r0] = a;
+      red[wave][kNH + nt * 16 + r0] = b;
+      red[wave][2 * kNH + nt * 16 + r0] = c;
+    }
+  }
+  float sdy = dy[0] + dy[1] + dy[2] + dy[3];
+  for (int o = 16; o < 64; o <<= 1) sdy += __shfl_xor(sdy, o);   // distinct rows per kq group
+  for (int o = 16; o < 64; o <<= 1) se += __shfl_xor(se, o);
+  if (l == 0) {
+    red[wave][3 * kNH] = sdy;
+    red[wave][3 * kNH + 1] = se;
+  }
+  __syncthreads();
+  float* Pb = P + (size_t)blockIdx.x * kNParam;
+  for (int i = threadIdx.x; i < 3 * kNH + 2; i += blockDim.x) {
+    const float v = red[0][i] + red[1][i] + red[2][i] + red[3][i];
+    if (i < kNH) Pb[kOffB1 + i] = v;
+    else if (i < 2 * kNH) Pb[kOffB2 + i - kNH] = v;
+    else if (i < 3 * kNH) Pb[kOffW3 + i - 2 * kNH] = v;
+    else if (i == 3 * kNH) Pb[kOffB3] = v;
+    else lossp[blockIdx.x] = v;
+  }
+  // dW2 = dZ2^T A1 over the block's 64 rows: 64 tiles of 16x16, 16 per wave
+  for (int t = wave; t < 64; t += 4) {
+    const int it = t >> 3, jt = t & 7;
+    f4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      s4 a, b;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = kk * 16 + kq * 4 + e;
+        a[e] = (short)dZ2s[row * kK2P + it * 16 + r0];
+        b[e] = (short)A1s[row * kK2P + jt * 16 + r0];
+      }
+      c = mfma(a, b, c);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      Pb[kOffW2 + (it * 16 + kq * 4 + e) * kNH + jt * 16 + r0] = c[e];
+  }
+  // dW1 = dZ1^T X: 8 x 2 tiles (columns >= 18 are padding), 4 per wave
+  for (int t = wave; t < 16; t += 4) {
+    const int it = t >> 1, jt = t & 1;
+    f4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      s4 a, b;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = kk * 16 + kq * 4 + e;
+        a[e] = (short)dZ1s[row * kK2P + it * 16 + r0];
+        b[e] = (short)Xs[row * kK1P + jt * 16 + r0];
+      }
+      c = mfma(a, b, c);
+    }
+    const int col = jt * 16 + r0;
+    if (col < kNIn) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) Pb[kOffW1 + (it * 16 + kq * 4 + e) * kNIn + col] = c[e];
+    }
+  }
+}
+
+// Sum the per-block partial gradients in block order (deterministic) into G, and the
+// loss partials into *loss (mean squared error).
+__global__ void k_mlp_reduce(const float* __restrict__ P, const float* __restrict__ lossp,
+                             int nblocks, int n, float* __restrict__ G, float* __restrict__ loss) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < kNParam) {
+    float s = 0.f;
+    for (int b = 0; b < nblocks; ++b) s += P[(size_t)b * kNParam + p];
+    G[p] = s;
+  }
+  if (p == 0) {
+    float s = 0.f;
+    for (int b = 0; b < nblocks; ++b) s += lossp[b];
+    *loss = s / (float)n;
+  }
+}
+
+// Adam on the FP32 master weights, then the bf16 copies the GEMM kernels read.
+__global__ void k_mlp_adam(float* __restrict__ master, float* __restrict__ m, float* __restrict__ v,
+                           const float* __restrict__ G, float lr, float b1, float b2, float eps,
+                           float c1, float c2) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kNParam) return;
+  const float g = G[p];
+  const float mm = b1 * m[p] + (1.f - b1) * g;
+  const float vv = b2 * v[p] + (1.f - b2) * g * g;
+  m[p] = mm;
+  v[p] = vv;
+  const float mh = mm / c1, vh = vv / c2;
+  master[p] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+// bf16 (padded) copies of W1, W2, W2^T and the rounded w3 from the FP32 master vector.
+__global__ void k_mlp_pack(const float* __restrict__ master, MlpWeights W) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < kNH * kK1P) {
+    const int nrow = t / kK1P, k = t - nrow * kK1P;
+    W.W1[t] = k < kNIn ? to_bf16(master[kOffW1 + nrow * kNIn + k]) : (uint16_t)0;
+  }
+  if (t < kNH * kK2P) {
+    const int nrow = t / kK2P, k = t - nrow * kK2P;
+    W.W2[t] = k < kNH ? to_bf16(master[kOffW2 + nrow * kNH + k]) : (uint16_t)0;
+    W.W2T[t] = k < kNH ? to_bf16(master[kOffW2 + k * kNH + nrow]) : (uint16_t)0;
+  }
+  if (t < kNH) {
+    W.b1[t] = master[kOffB1 + t];
+    W.b2[t] = master[kOffB2 + t];
+    W.w3q[t] = from_bf16(to_bf16(master[kOffW3 + t]));
+  }
+  if (t == 0) W.b3[0] = master[kOffB3];
+}
+
+// --- training data ----------------------------------------------------------------
+// Replay: each wavefront integrates one isolated 2V kinetic cell (vy > 0 half plane of an
+// nv x nv grid, nv = 32) driven along x by a prescribed series E[k * stride], and writes
+// the normalised x current (dt/eps0 * Jx)^{n+1/2} for every step.  Same F1 update and
+// FP64 moment as the 2D step kernel.
+__global__ __launch_bounds__(256) void k_replay2v(const float* __restrict__ E, int64_t e_stride,
+                                                  int64_t e_series_stride, int nseries,
+                                                  int64_t nsteps, const ReplayCell* __restrict__ cells,
+                                                  const float* __restrict__ s_bin,
+                                                  const float* __restrict__ bx_bin,
+                                                  const double* __restrict__ wx_bin,
+                                                  float* __restrict__ J, int64_t j_series_stride) {
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int l = threadIdx.x & 63;
+  if (wave >= nseries) return;
+  const ReplayCell cell = cells[wave];
+  constexpr int PER = kReplayHalf / 64;        // bins per lane
+  float s[PER], bx[PER], f[PER];
+  double w[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int q = l * PER + k;
+    s[k] = s_bin[q];
+    bx[k] = bx_bin[q] * cell.dens;
+    w[k] = wx_bin[q];
+    f[k] = 0.f;
+  }
+  const float* Es = E + (size_t)wave * e_series_stride;
+  float* Js = J + (size_t)wave * j_series_stride;
+  for (int64_t n = 0; n < nsteps; ++n) {
+    const float e = Es[n * e_stride];
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const float x = cell.tau * s[k];
+      const float r = __builtin_amdgcn_rcpf(2.f + x);
+      const float t = fmaf(-(x + x), f[k], bx[k] * e);
+      f[k] = fmaf(t, r, f[k]);
+      acc = fma(w[k], (double)f[k], acc);
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (l == 0) Js[n] = (float)acc;
+  }
+}
+
+// Training pairs: for each (series, step n >= 15) index build the 18 features
+// [E^n .. E^{n-15}] / s, p1, p2 and the target ((J^{n+1/2} - a J^{n-1/2}) / b - E^n) / s.
+__global__ void k_make_pairs(const float* __restrict__ E, int64_t e_stride, int64_t e_series_stride,
+                             const float* __restrict__ J, int64_t j_series_stride,
+                             const PairSeries* __restrict__ ser, const int64_t* __restrict__ idx,
+                             int npairs, float* __restrict__ X, float* __restrict__ Tt) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npairs) return;
+  const int64_t code = idx[p];
+  const int si = (int)(code >> 32);
+  const int64_t n = code & 0xFFFFFFFFLL;
+  const PairSeries S = ser[si];
+  const float* Es = E + (size_t)si * e_series_stride;
+  const float* Js = J + (size_t)si * j_series_stride;
+  float h[kHist];
+  float sc = 0.f;
+#pragma unroll
+  for (int k = 0; k < kHist; ++k) {
+    h[k] = (n - k >= 0) ? Es[(n - k) * e_stride] : 0.f;
+    sc = fmaxf(sc, fabsf(h[k]));
+  }
+  sc = fmaxf(sc, 1e-30f);
+  float* x = X + (size_t)p * kNIn;
+#pragma unroll
+  for (int k = 0; k < kHist; ++k) x[k] = h[k] / sc;
+  x[kHist] = S.q1;
+  x[kHist + 1] = S.q2;
+  const float jn = Js[n], jp = n > 0 ? Js[n - 1] : 0.f;
+  Tt[p] = ((jn - S.alpha * jp) / S.beta - h[0]) / sc;
+}
+
+// --- host wrappers ---------------------------------------------------------------
+hipError_t mlp_launch_rows(const MlpWeights& W, const float* X, int n, float* Y, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = (n + 63) / 64 < 2048 ? (n + 63) / 64 : 2048;
+  hipLaunchKernelGGL(k_mlp_rows, dim3(blocks), dim3(256), 0, st, W, X, n, Y);
+  return hipGetLastError();
+}
+
+hipError_t mlp_launch_grad(const MlpWeights& W, const float* X, const float* T, int n, float* P,
+                           float* lossp, float* G, float* loss, hipStream_t st) {
+  const int nb = (n + 63) / 64;
+  hipLaunchKernelGGL(k_mlp_grad, dim3(nb), dim3(256), 0, st, W, X, T, n, P, lossp);
+  hipError_t e = hipGetLastError();
+  if (e) return e;
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((kNParam + 255) / 256), dim3(256), 0, st, P, lossp, nb, n,
+                     G, loss);
+  return hipGetLastError();
+}
+
+hipError_t mlp_launch_adam(float* master, float* m, float* v, const float* G, float lr, float b1,
+                           float b2, float eps, float c1, float c2, hipStream_t st) {
+  hipLaunchKernelGGL(k_mlp_adam, dim3((kNParam + 255) / 256), dim3(256), 0, st, master, m, v, G,
+                     lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t mlp_launch_pack(const float* master, const MlpWeights& W, hipStream_t st) {
+  hipLaunchKernelGGL(k_mlp_pack, dim3((kNH * kK2P + 255) / 256), dim3(256), 0, st, master, W);
+  return hipGetLastError();
+}
+
+hipError_t mlp_launch_replay2v(const float* E, int64_t e_stride, int64_t e_series_stride,
+                               int nseries, int64_t nsteps, const ReplayCell* cells,
+                               const float* s_bin, const float* bx_bin, const double* wx_bin,
+                               float* J, int64_t j_series_stride, hipStream_t st) {
+  if (nseries <= 0 || nsteps <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_replay2v, dim3((nseries + 3) / 4), dim3(256), 0, st, E, e_stride,
+                     e_series_stride, nseries, nsteps, cells, s_bin, bx_bin, wx_bin, J,
+                     j_series_stride);
+  return hipGetLastError();
+}
+
+hipError_t mlp_launch_pairs(const float* E, int64_t e_stride, int64_t e_series_stride,
+                            const float* J, int64_t j_series_stride, const PairSeries* ser,
+                            const int64_t* idx, int npairs, float* X, float* T, hipStream_t st) {
+  if (npairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_make_pairs, dim3((npairs + 255) / 256), dim3(256), 0, st, E, e_stride,
+                     e_series_stride, J, j_series_stride, ser, idx, npairs, X, T);
+  return hipGetLastError();
+}
+
+}  // namespace fdtdp
