@@ -49,7 +49,10 @@ def lib():
              C.c_double, C.c_double, C.c_double, C.c_double,
              C.c_longlong, C.c_longlong,
              _dp, _dp, _dp, _dp, _dp, _dp, _dp,
-             C.c_int, _ip, _dp])
+             C.c_int, _ip, _dp,
+             _ip, _dp, _dp, C.c_int, _dp, _dp])
+        L.oracle_mlp.argtypes = [_dp, _dp, C.c_int]
+        L.oracle_mlp.restype = C.c_double
         L.oracle_replay1v.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, C.c_double,
                                       C.c_double, C.c_double, C.c_longlong, _dp, _dp]
         L.oracle_replay2v.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, C.c_double,
@@ -112,6 +115,13 @@ def cpml_profile(n, ncpml, dx, dt, order=3.0, sigma_factor=1.0, kappa_max=5.0,
     lib().oracle_cpml_profile(n, ncpml, dx, dt, order, sigma_factor, kappa_max, alpha_min,
                               alpha_max, _p(be), _p(ae), _p(ke), _p(bh), _p(ah), _p(kh))
     return dict(be=be, ae=ae, ke=ke, bh=bh, ah=ah, kh=kh)
+
+
+def mlp(params, x, emulate_bf16=False):
+    """The closure network on one feature row (plain C, FP64)."""
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    return lib().oracle_mlp(_p(params), _p(x), int(bool(emulate_bf16)))
 
 
 def replay1v(E, ne, nubar, dt, nv=64, vmax_over_vth=6.0, te_ev=2.0, nu_model="hard_sphere"):
@@ -217,6 +227,16 @@ class Oracle2D:
         self.df = np.zeros(len(self.cells) * self.nv * self.nv)
         self.step = 0
         self.dt = self.courant * self.dx / constants()["c"]
+        self.closure = None
+
+    def set_closure(self, mode, coef, params, emulate_bf16=True):
+        """Learned closure on the plasma cells with mode 1: coef [ncell][4] = (alpha, beta,
+        q1, q2), params the 19073 network parameters (FP64)."""
+        n = len(self.cells)
+        self.closure = dict(mode=np.ascontiguousarray(mode, dtype=np.int32),
+                            coef=np.ascontiguousarray(coef, dtype=np.float64).reshape(n * 4),
+                            params=np.ascontiguousarray(params, dtype=np.float64),
+                            bf=int(bool(emulate_bf16)), hist=np.zeros(n * 32), J=np.zeros(n * 2))
 
     def run(self, nsteps, probes=()):
         """``probes`` are (i, j) Ey indices; returns Ey at them after every step."""
@@ -229,7 +249,10 @@ class Oracle2D:
             self.step, int(nsteps),
             _p(self.Ex), _p(self.Ey), _p(self.Hz), _p(self.Jx), _p(self.Jy),
             _p(self.psi), _p(self.df),
-            len(idx), _p(idx) if len(idx) else None, _p(pout))
+            len(idx), _p(idx) if len(idx) else None, _p(pout),
+            *((_p(self.closure["mode"]), _p(self.closure["coef"]), _p(self.closure["params"]),
+               self.closure["bf"], _p(self.closure["hist"]), _p(self.closure["J"]))
+              if self.closure else (None, None, None, 0, None, None)))
         if rc:
             raise ValueError("oracle_run2d rejected its arguments")
         self.step += int(nsteps)

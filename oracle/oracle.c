@@ -281,6 +281,68 @@ int oracle_cpml_profile(int n, int ncpml, double dx, double dt, double order,
 }
 
 /* ---------------------------------------------------------------------------
+ * Learned closure of a cell's current (used by oracle_run2d for closure cells):
+ * J^{n+1/2} = alpha J^{n-1/2} + beta (E^n + s y), y = MLP([E^n..E^{n-15}]/s, q1, q2),
+ * s = max |E window| (floor 1e-30); network 18 -> 128 -> 128 -> 1 with tanh-form GELU,
+ * parameters W1[128][18], b1, W2[128][128], b2, w3, b3.  With bf != 0 the GEMM operands
+ * (features, weights, first-layer activations) are rounded to bfloat16 (ties to even).
+ * ------------------------------------------------------------------------- */
+static double o_bf16(double x)
+{
+    float f = (float)x;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    u &= 0xFFFF0000u;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+static double o_gelu(double x)
+{
+    return 0.5 * x * (1.0 + tanh(sqrt(2.0 / K_PI) * (x + 0.044715 * x * x * x)));
+}
+
+double oracle_mlp(const double *p, const double *x, int bf)
+{
+    const double *W1 = p, *b1 = p + 2304, *W2 = p + 2432, *b2 = p + 18816, *w3 = p + 18944;
+    const double b3 = p[19072];
+    double xq[18], a1[128];
+    for (int k = 0; k < 18; ++k) xq[k] = bf ? o_bf16(x[k]) : x[k];
+    for (int n = 0; n < 128; ++n) {
+        double z = 0.0;
+        for (int k = 0; k < 18; ++k) z += (bf ? o_bf16(W1[n * 18 + k]) : W1[n * 18 + k]) * xq[k];
+        z += b1[n];
+        a1[n] = bf ? o_bf16(o_gelu(z)) : o_gelu(z);
+    }
+    double y = 0.0;
+    for (int n = 0; n < 128; ++n) {
+        double z = 0.0;
+        for (int k = 0; k < 128; ++k) z += (bf ? o_bf16(W2[n * 128 + k]) : W2[n * 128 + k]) * a1[k];
+        z += b2[n];
+        y += o_gelu(z) * (bf ? o_bf16(w3[n]) : w3[n]);
+    }
+    return y + b3;
+}
+
+/* one closure step of one current component; hist[0..15] newest first, shifted in place */
+static double closure_step(double *hist, double e, double jprev, const double *coef,
+                           const double *params, int bf)
+{
+    for (int k = 15; k > 0; --k) hist[k] = hist[k - 1];
+    hist[0] = e;
+    double s = 0.0;
+    for (int k = 0; k < 16; ++k) s = fmax(s, fabs(hist[k]));
+    s = fmax(s, 1e-30);
+    double x[18];
+    for (int k = 0; k < 16; ++k) x[k] = hist[k] / s;
+    x[16] = coef[2];
+    x[17] = coef[3];
+    double y = oracle_mlp(params, x, bf);
+    return coef[0] * jprev + coef[1] * (e + s * y);
+}
+
+/* ---------------------------------------------------------------------------
  * 2D TEz: Ex at (i+1/2, j)   Ex[j*nx + i],      i < nx, j <= ny
  *         Ey at (i, j+1/2)   Ey[j*(nx+1) + i],  i <= nx, j < ny
  *         Hz at (i+1/2,j+1/2) Hz[j*nx + i],     i < nx, j < ny
@@ -303,8 +365,13 @@ int oracle_run2d(int nx, int ny, double dx, double courant,
                  long long step0, long long nsteps,
                  double *Ex, double *Ey, double *Hz, double *Jx, double *Jy,
                  double *psi, double *df,
-                 int nprobe, const int *probe_idx, double *probe_out)
+                 int nprobe, const int *probe_idx, double *probe_out,
+                 const int *cell_mode, const double *clo_coef, const double *mlp_params,
+                 int emulate_bf16, double *clo_hist, double *clo_J)
 {
+    /* cell_mode (per plasma cell, may be NULL): 0 kinetic F1, 1 learned closure with
+     * clo_coef[c][4] = (alpha, beta, q1, q2) of that cell, clo_hist[c][2][16] its field
+     * history and clo_J[c][2] its normalised current dt/eps0 * J (state, in/out). */
     if (nx < 2 || ny < 2 || nv < 2 || dx <= 0.0) return -1;
     if (courant <= 0.0 || courant > 1.0 / sqrt(2.0)) return -1;
     if (2 * ncpml >= nx || 2 * ncpml >= ny) return -1;
@@ -368,6 +435,16 @@ int oracle_run2d(int nx, int ny, double dx, double courant,
             int k = cell_idx[c], i = k % nx, j = k / nx;
             double exc = 0.5 * (Ex[(size_t)j * nx + i] + Ex[(size_t)(j + 1) * nx + i]);
             double eyc = 0.5 * (Ey[(size_t)j * (nx + 1) + i] + Ey[(size_t)j * (nx + 1) + i + 1]);
+            if (cell_mode && cell_mode[c] == 1) {
+                const double *cf = clo_coef + 4 * (size_t)c;
+                clo_J[2 * c] = closure_step(clo_hist + 32 * (size_t)c, exc, clo_J[2 * c], cf,
+                                            mlp_params, emulate_bf16);
+                clo_J[2 * c + 1] = closure_step(clo_hist + 32 * (size_t)c + 16, eyc,
+                                                clo_J[2 * c + 1], cf, mlp_params, emulate_bf16);
+                jbx[k] = clo_J[2 * c] * K_EPS0 / dt;
+                jby[k] = clo_J[2 * c + 1] * K_EPS0 / dt;
+                continue;
+            }
             double *f = df + (size_t)c * nv2;
             double accx = 0.0, accy = 0.0;
             for (int a = 0; a < nv; ++a)

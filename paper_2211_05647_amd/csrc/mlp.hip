@@ -29,14 +29,19 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
 }
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-__device__ __forceinline__ float gelu_f(float x) {
-  const float k = 0.7978845608028654f;   // sqrt(2/pi)
-  return 0.5f * x * (1.0f + tanhf(k * (x + 0.044715f * x * x * x)));
+// GELU in its tanh form, evaluated through 0.5 (1 + tanh u) = 1 / (1 + exp(-2u)) with the
+// hardware exp2 and reciprocal (relative error ~1e-7, far below the bf16 operand rounding).
+__device__ __forceinline__ float gelu_sig(float x) {
+  const float k2 = 2.0f * 0.7978845608028654f * 1.4426950408889634f;   // 2 sqrt(2/pi) log2(e)
+  const float u = x * fmaf(0.044715f * x, x, 1.0f);
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-k2 * u));   // 0.5 (1 + tanh)
 }
+__device__ __forceinline__ float gelu_f(float x) { return x * gelu_sig(x); }
 __device__ __forceinline__ float gelu_grad_f(float x) {
   const float k = 0.7978845608028654f;
-  const float t = tanhf(k * (x + 0.044715f * x * x * x));
-  return 0.5f * (1.0f + t) + 0.5f * x * (1.0f - t * t) * k * (1.0f + 3.0f * 0.044715f * x * x);
+  const float sg = gelu_sig(x);                         // (1 + t) / 2
+  const float t = 2.0f * sg - 1.0f;
+  return sg + 0.5f * x * (1.0f - t * t) * k * fmaf(3.0f * 0.044715f * x, x, 1.0f);
 }
 
 __device__ __forceinline__ f4 mfma(s4 a, s4 b, f4 c) {

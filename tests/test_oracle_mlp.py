@@ -170,3 +170,42 @@ def test_replay2v_const_nu_is_drude():
     jy = M.closure_run(Ey, al, be) * A.EPS0 / dt
     assert np.max(np.abs(Jx - jx)) < 1e-12 * np.max(np.abs(jx))
     assert np.max(np.abs(Jy - jy)) < 1e-12 * np.max(np.abs(jy))
+
+
+def test_c_and_numpy_networks_agree():
+    """The oracle's two independent network codes (plain C loops and numpy matmuls) agree,
+    with and without bf16 operand emulation."""
+    from oracle.core import mlp as cmlp
+    p = M.init_params(11) + 0.02 * np.random.default_rng(12).standard_normal(M.NPARAM)
+    X, _ = _batch(20, 13)
+    for bf in (False, True):
+        ref = M.forward(p, X, emulate_bf16=bf)[0]
+        got = np.array([cmlp(p, x, bf) for x in X])
+        assert np.max(np.abs(got - ref)) < 1e-12 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_2d_closure_without_network_is_kinetic_at_constant_nu():
+    """2D oracle: cells switched to the closure with a zero network and the const-nu single
+    pole evolve exactly as kinetic cells (section 5.2 model with nu independent of v)."""
+    from oracle.core import Oracle2D
+    nx, ny, nv = 48, 40, 8
+    ne = np.zeros((ny, nx))
+    nu = np.zeros((ny, nx))
+    jj, ii = np.mgrid[0:ny, 0:nx]
+    blob = (ii - 27.5) ** 2 + (jj - 19.5) ** 2 < 81
+    ne[blob] = W.density_from_ratio(1.2, W.F_REF)
+    nu[blob] = 0.1 * 2 * math.pi * W.F_REF
+    kw = dict(nv=nv, te_ev=5.0, ncpml=0, nu_model="const", src_kind=2, src_i=10, src_j=20,
+              **W.pulse(W.F_REF))
+    kin = Oracle2D(nx, ny, W.DX_REF, 0.5, ne, nu, **kw)
+    clo = Oracle2D(nx, ny, W.DX_REF, 0.5, ne, nu, **kw)
+    w, s = A.velocity_weights(nv, 6.0, 5.0, "const", dims=2)
+    coef = []
+    for c in clo.cells:
+        a, b = M.effective_pole(w, s, clo.nubar[c], A.plasma_omega2(clo.ne[c]), clo.dt)
+        coef.append((a, b, 0.0, 0.0))
+    clo.set_closure(np.ones(len(clo.cells)), np.array(coef), np.zeros(M.NPARAM), emulate_bf16=False)
+    kin.run(400)
+    clo.run(400)
+    assert np.max(np.abs(clo.Ey - kin.Ey)) < 1e-12 * np.max(np.abs(kin.Ey))
+    assert np.max(np.abs(clo.Jx - kin.Jx)) < 1e-11 * np.max(np.abs(kin.Jx))
