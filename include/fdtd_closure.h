@@ -36,6 +36,21 @@ typedef struct fdtd_closure fdtd_closure;
 
 #define FDTD_CLOSURE_NPARAM 19073
 #define FDTD_CLOSURE_NIN 18
+#define FDTD_MLP_MAGIC 0x4d4c5043u
+
+/* A trained closure as fdtd_profile.mlp expects it (2D runs with closure = FDTD_CLOSURE_MLP).
+ * The run uses the network only if dims, nv, nu_model, te_ev, vmax_over_vth and dt match
+ * the kinetic model it was trained on (dt to 1e-9 relative); a plasma cell uses it only if
+ * its (omega_p dt, log10(nu_mean dt)) lies inside box, every other cell keeps the kinetic
+ * F1 step (the fallback).  box = (p1 lo, p1 hi, p2 lo, p2 hi). */
+typedef struct {
+  uint32_t magic;        /* FDTD_MLP_MAGIC */
+  uint32_t version;      /* 1 */
+  int32_t dims, nv, nu_model, reserved;
+  double te_ev, vmax_over_vth, dt;
+  double box[4];
+  float params[FDTD_CLOSURE_NPARAM];
+} fdtd_mlp_blob;
 
 /* Workspace for a trainer/evaluator handling up to max_rows feature rows per call and
  * max_series replay series. */
@@ -80,6 +95,9 @@ int fdtd_closure_make_pairs(fdtd_closure *c, const float *E_dev, int64_t e_strid
                             int32_t nseries, const float *series4, const int64_t *idx,
                             int32_t npairs, float *X_dev, float *T_dev);
 void fdtd_closure_destroy(fdtd_closure *c);
+
+/* Plasma cells of a 2D run served by the closure and by the kinetic fallback. */
+int fdtd_plasma_closure_counts(fdtd_plasma *h, int64_t *closure_cells, int64_t *kinetic_cells);
 
 /* Device pointer and geometry of a batch run's tap buffer ([ntap][cap][2] FP32:
  * E^n in V/m, normalised (dt/eps0) J^{n+1/2}), for feeding fdtd_closure_replay2v and

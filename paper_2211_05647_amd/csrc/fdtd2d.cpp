@@ -9,10 +9,15 @@
 #include <new>
 #include <vector>
 
+#include "../../include/fdtd_closure.h"
 #include "common.h"
 #include "host_internal.h"
+#include "mlp_common.h"
 
 namespace fdtdp {
+
+hipError_t mlp_launch_cells2d(const void* run, const MlpWeights& W, const MlpCells2D& C,
+                              int64_t step, hipStream_t st);
 
 struct Host2D {
   fdtd_grid g;
@@ -31,6 +36,15 @@ struct Host2D {
   size_t state_end = 0, probe_off = 0, total = 0;
   char* ws = nullptr;
   int nbk = 0, nbh = 0, nbe = 0;
+  // learned closure (closure cells are not in cell_idx: those hold the kinetic cells)
+  bool closure = false;
+  std::vector<float> mlp_params;
+  std::vector<int32_t> mlp_idx;
+  std::vector<float> mlp_coef;     // [n][4] alpha, beta, q1, q2
+  size_t off_ring = 0, off_midx = 0, off_mcoef = 0, off_W1 = 0, off_W2 = 0, off_W2T = 0,
+         off_mb = 0;
+  MlpWeights W{};
+  MlpCells2D C{};
 };
 
 namespace {
@@ -48,6 +62,8 @@ size_t layout(Host2D* h, int max_probes, int probe_cap) {
   h->off_Jcx = cv.take((size_t)ny * nx * es);
   h->off_Jcy = cv.take((size_t)ny * nx * es);
   h->off_df = cv.take((size_t)std::max(h->ncell, 1) * h->half * es);
+  const size_t nm = std::max<size_t>(h->mlp_idx.size(), 1);
+  h->off_ring = cv.take(nm * 2 * kHist * 4);
   h->state_end = cv.size();
   h->probe_off = cv.take((size_t)std::max(max_probes, 1) * std::max(probe_cap, 1) * es);
   const size_t nc = std::max(h->ncell, 1);
@@ -61,6 +77,12 @@ size_t layout(Host2D* h, int max_probes, int probe_cap) {
   h->off_wy = cv.take((size_t)h->half * 8);
   h->off_prof = cv.take((size_t)(6 * (nx + 1) + 6 * (ny + 1)) * es);
   h->off_run = cv.take(std::max(sizeof(Run2D<double>), sizeof(Run2D<float>)));
+  h->off_midx = cv.take(nm * 4);
+  h->off_mcoef = cv.take(nm * 16);
+  h->off_W1 = cv.take(kNH * kK1P * 2);
+  h->off_W2 = cv.take(kNH * kK2P * 2);
+  h->off_W2T = cv.take(kNH * kK2P * 2);
+  h->off_mb = cv.take((3 * kNH + 1) * 4);
   h->total = cv.size() + 256;
   return h->total;
 }
@@ -198,6 +220,48 @@ int upload(Host2D* h, char* ws, hipStream_t st, const std::vector<ProbeInfo>& pr
   }
   e = put(h->off_run, &R, sizeof R);
   if (e) return hip_fail(e, "upload 2D run descriptor");
+  if (h->closure && !h->mlp_idx.empty()) {
+    // bf16 (ties to even) copies of the network weights, padded rows, as the kernels read them
+    auto bf = [](float f) {
+      uint32_t u;
+      std::memcpy(&u, &f, 4);
+      u += 0x7FFFu + ((u >> 16) & 1u);
+      return (uint16_t)(u >> 16);
+    };
+    const float* P = h->mlp_params.data();
+    std::vector<uint16_t> w1(kNH * kK1P, 0), w2(kNH * kK2P, 0), w2t(kNH * kK2P, 0);
+    for (int n = 0; n < kNH; ++n) {
+      for (int k = 0; k < kNIn; ++k) w1[n * kK1P + k] = bf(P[kOffW1 + n * kNIn + k]);
+      for (int k = 0; k < kNH; ++k) {
+        w2[n * kK2P + k] = bf(P[kOffW2 + n * kNH + k]);
+        w2t[n * kK2P + k] = bf(P[kOffW2 + k * kNH + n]);
+      }
+    }
+    std::vector<float> mb(3 * kNH + 1);
+    for (int n = 0; n < kNH; ++n) {
+      mb[n] = P[kOffB1 + n];
+      mb[kNH + n] = P[kOffB2 + n];
+      const uint32_t u = (uint32_t)bf(P[kOffW3 + n]) << 16;
+      std::memcpy(&mb[2 * kNH + n], &u, 4);
+    }
+    mb[3 * kNH] = P[kOffB3];
+    if ((e = put(h->off_midx, h->mlp_idx.data(), h->mlp_idx.size() * 4)) ||
+        (e = put(h->off_mcoef, h->mlp_coef.data(), h->mlp_coef.size() * 4)) ||
+        (e = put(h->off_W1, w1.data(), w1.size() * 2)) || (e = put(h->off_W2, w2.data(), w2.size() * 2)) ||
+        (e = put(h->off_W2T, w2t.data(), w2t.size() * 2)) || (e = put(h->off_mb, mb.data(), mb.size() * 4)))
+      return hip_fail(e, "upload closure");
+    h->W.W1 = reinterpret_cast<uint16_t*>(ws + h->off_W1);
+    h->W.W2 = reinterpret_cast<uint16_t*>(ws + h->off_W2);
+    h->W.W2T = reinterpret_cast<uint16_t*>(ws + h->off_W2T);
+    h->W.b1 = reinterpret_cast<float*>(ws + h->off_mb);
+    h->W.b2 = h->W.b1 + kNH;
+    h->W.w3q = h->W.b1 + 2 * kNH;
+    h->W.b3 = h->W.b1 + 3 * kNH;
+    h->C.idx = reinterpret_cast<const int32_t*>(ws + h->off_midx);
+    h->C.coef = reinterpret_cast<const float*>(ws + h->off_mcoef);
+    h->C.ring = reinterpret_cast<float*>(ws + h->off_ring);
+    h->C.n = (int)h->mlp_idx.size();
+  }
   return FDTD_OK;
 }
 
@@ -212,6 +276,8 @@ void set_grid(Host2D* h) {
 template <class T>
 hipError_t launch_step2d_t(const void* run, int nbk, int nbh, int nbe, int64_t step,
                            hipStream_t stream);
+hipError_t launch_step2d_closure(const void* run, int nbk, int nbh, int nbe, int64_t step,
+                                 hipStream_t stream, const MlpWeights& W, const MlpCells2D& C);
 
 int validate_2d(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s) {
   if (!g || !p) return fail(FDTD_EINVAL, "null grid or profile");
@@ -240,8 +306,18 @@ int validate_2d(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s)
     return fail(FDTD_EINVAL, "te_ev and vmax_over_vth must be > 0");
   if (p->nu_model != FDTD_NU_HARD_SPHERE && p->nu_model != FDTD_NU_CONST)
     return fail(FDTD_EINVAL, "unknown nu_model %d", p->nu_model);
-  if (p->closure != FDTD_CLOSURE_KINETIC)
-    return fail(FDTD_EINVAL, "this build runs the kinetic closure in 2D");
+  if (p->closure == FDTD_CLOSURE_MLP) {
+    if (g->precision != FDTD_FP32) return fail(FDTD_EINVAL, "the learned closure runs in FP32");
+    const fdtd_mlp_blob* b = reinterpret_cast<const fdtd_mlp_blob*>(p->mlp);
+    if (!b || b->magic != FDTD_MLP_MAGIC || b->version != 1)
+      return fail(FDTD_EINVAL, "profile.mlp is not a closure blob");
+    for (int i = 0; i < FDTD_CLOSURE_NPARAM; ++i)
+      if (!std::isfinite(b->params[i])) return fail(FDTD_EINVAL, "closure parameter %d not finite", i);
+    if (!(b->box[1] > b->box[0]) || !(b->box[3] > b->box[2]))
+      return fail(FDTD_EINVAL, "closure box is empty");
+  } else if (p->closure != FDTD_CLOSURE_KINETIC) {
+    return fail(FDTD_EINVAL, "unknown closure %d", p->closure);
+  }
   if (!p->ne || !p->nu_mean) return fail(FDTD_EINVAL, "null ne or nu_mean");
   const size_t n = (size_t)g->nx * g->ny;
   for (size_t k = 0; k < n; ++k) {
@@ -282,8 +358,46 @@ static Host2D* new_host(const fdtd_grid* g, const fdtd_profile* p, const fdtd_so
   h->nu.assign(p->nu_mean, p->nu_mean + n);
   h->p.ne = h->ne.data();
   h->p.nu_mean = h->nu.data();
-  for (size_t k = 0; k < n; ++k)
-    if (h->ne[k] > 0) h->cell_idx.push_back((int32_t)k);
+  const fdtd_mlp_blob* b = p->closure == FDTD_CLOSURE_MLP
+                               ? reinterpret_cast<const fdtd_mlp_blob*>(p->mlp) : nullptr;
+  // the network is used only for the kinetic model it was trained on
+  h->closure = b && b->dims == 2 && b->nv == p->nv && b->nu_model == p->nu_model &&
+               std::fabs(b->te_ev / p->te_ev - 1.0) < 1e-9 &&
+               std::fabs(b->vmax_over_vth / p->vmax_over_vth - 1.0) < 1e-9 &&
+               std::fabs(b->dt / h->dt - 1.0) < 1e-9;
+  double sw = 0.0, swn = 0.0;
+  if (h->closure) {
+    h->mlp_params.assign(b->params, b->params + FDTD_CLOSURE_NPARAM);
+    // single-pole weights: w = vx^2 F0 dv^2 / vth^2 and the nu shape, summed over the grid
+    VTable vt = build_vtable(2, p->nv, p->vmax_over_vth, p->te_ev, p->nu_model, h->dt);
+    const double vth2 = vt.vth * vt.vth;
+    for (int a = 0; a < p->nv; ++a)
+      for (int c = 0; c < p->nv; ++c) {
+        const double w = vt.v[a] * vt.v[a] * vt.f[a] * vt.f[c] * vt.dv * vt.dv / vth2;
+        const double sp = std::sqrt(vt.v[a] * vt.v[a] + vt.v[c] * vt.v[c]);
+        sw += w;
+        swn += w * (p->nu_model == FDTD_NU_HARD_SPHERE ? sp / vt.mean_speed : 1.0);
+      }
+  }
+  for (size_t k = 0; k < n; ++k) {
+    if (!(h->ne[k] > 0)) continue;
+    if (h->closure && h->nu[k] > 0) {
+      const double wp = std::sqrt(h->ne[k] * kQe * kQe / (kEps0 * kMe));
+      const double q1 = 2.0 * (wp * h->dt - b->box[0]) / (b->box[1] - b->box[0]) - 1.0;
+      const double q2 = 2.0 * (std::log10(h->nu[k] * h->dt) - b->box[2]) / (b->box[3] - b->box[2]) - 1.0;
+      if (q1 >= -1.0 && q1 <= 1.0 && q2 >= -1.0 && q2 <= 1.0) {
+        const double nu_eff = h->nu[k] * swn / sw;
+        const double wt2 = wp * wp * sw;
+        h->mlp_idx.push_back((int32_t)k);
+        h->mlp_coef.push_back((float)((2.0 - h->dt * nu_eff) / (2.0 + h->dt * nu_eff)));
+        h->mlp_coef.push_back((float)(2.0 * h->dt * h->dt * wt2 / (2.0 + h->dt * nu_eff)));
+        h->mlp_coef.push_back((float)q1);
+        h->mlp_coef.push_back((float)q2);
+        continue;
+      }
+    }
+    h->cell_idx.push_back((int32_t)k);     // kinetic F1 (also the fallback of the closure)
+  }
   h->ncell = (int)h->cell_idx.size();
   // about 64 KB of F1 per kinetic work-group
   h->cells_per_block = std::max(4, std::min(256, 65536 / (h->half * h->es)));
@@ -317,8 +431,15 @@ int upload_2d(Host2D* h, char* ws, hipStream_t stream, const std::vector<ProbeIn
 
 hipError_t launch_step2d(Host2D* h, int64_t step, hipStream_t stream) {
   const void* run = h->ws + h->off_run;
-  return h->es == 8 ? launch_step2d_t<double>(run, h->nbk, h->nbh, h->nbe, step, stream)
-                    : launch_step2d_t<float>(run, h->nbk, h->nbh, h->nbe, step, stream);
+  if (h->es == 8) return launch_step2d_t<double>(run, h->nbk, h->nbh, h->nbe, step, stream);
+  if (h->C.n > 0) return launch_step2d_closure(run, h->nbk, h->nbh, h->nbe, step, stream, h->W, h->C);
+  return launch_step2d_t<float>(run, h->nbk, h->nbh, h->nbe, step, stream);
+}
+
+int closure_counts_2d(const Host2D* h, int64_t* nm, int64_t* nk) {
+  *nm = (int64_t)h->mlp_idx.size();
+  *nk = h->ncell;
+  return FDTD_OK;
 }
 
 int field_size_2d(const Host2D* h, int field, size_t* n) {

@@ -905,6 +905,18 @@ int fdtd_plasma_tap_buffer(fdtd_plasma* h, int32_t run, const float** dev, int64
   return FDTD_OK;
 }
 
+int fdtd_plasma_closure_counts(fdtd_plasma* h, int64_t* closure_cells, int64_t* kinetic_cells) {
+  if (!h || !closure_cells || !kinetic_cells) return fail(FDTD_EINVAL, "null argument");
+  if (h->dims != 2) {
+    *closure_cells = 0;
+    int64_t k = 0;
+    for (auto& x : h->h1) k += x.ncell;
+    *kinetic_cells = k;
+    return FDTD_OK;
+  }
+  return closure_counts_2d(h->h2, closure_cells, kinetic_cells);
+}
+
 int fdtd_plasma_run_status(fdtd_plasma* h, int32_t run, int32_t* status) {
   if (!h || !status) return fail(FDTD_EINVAL, "null argument");
   if (h->dims != 1) { *status = 0; return FDTD_OK; }

@@ -84,5 +84,6 @@ int check_probe_2d(const Host2D* h, int field, int i, int j);
 double probe_scale_2d(const Host2D* h, int field);
 int set_tiling_2d(Host2D* h, char* ws, hipStream_t stream, int tile, int cells_per_group);
 void destroy_2d(Host2D* h);
+int closure_counts_2d(const Host2D* h, int64_t* nm, int64_t* nk);
 
 }  // namespace fdtdp

@@ -12,6 +12,7 @@
 // F1 layout: [cell][vx bin a][vy bin b >= nv/2]: the half plane vy > 0 (F1 is odd under
 // v -> -v), one contiguous row of nv*nv/2 values per cell.
 #include "common.h"
+#include "mlp_common.h"
 
 namespace fdtdp {
 
@@ -225,6 +226,21 @@ hipError_t launch_step2d_t(const void* run, int nbk, int nbh, int nbe, int64_t s
   hipError_t e = hipGetLastError();
   if (e) return e;
   hipLaunchKernelGGL(k_e2d<T>, dim3(nbe), dim3(kBlock), 0, stream, r, step);
+  return hipGetLastError();
+}
+
+hipError_t mlp_launch_cells2d(const void* run, const MlpWeights& W, const MlpCells2D& C,
+                              int64_t step, hipStream_t st);
+
+hipError_t launch_step2d_closure(const void* run, int nbk, int nbh, int nbe, int64_t step,
+                                 hipStream_t stream, const MlpWeights& W, const MlpCells2D& C) {
+  const Run2D<float>* r = static_cast<const Run2D<float>*>(run);
+  hipLaunchKernelGGL(k_h2d_kin<float>, dim3(nbk + nbh), dim3(kBlock), 0, stream, r, step);
+  hipError_t e = hipGetLastError();
+  if (e) return e;
+  e = mlp_launch_cells2d(run, W, C, step, stream);
+  if (e) return e;
+  hipLaunchKernelGGL(k_e2d<float>, dim3(nbe), dim3(kBlock), 0, stream, r, step);
   return hipGetLastError();
 }
 

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "common.h"
 #include "mlp_common.h"
 
 namespace fdtdp {
@@ -427,6 +428,83 @@ __global__ void k_make_pairs(const float* __restrict__ E, int64_t e_stride, int6
   x[kHist + 1] = S.q2;
   const float jn = Js[n], jp = n > 0 ? Js[n - 1] : 0.f;
   Tt[p] = ((jn - S.alpha * jp) / S.beta - h[0]) / sc;
+}
+
+// --- the closure inside a 2D run ----------------------------------------------------
+// Per step, for every closure cell and both current components: push the cell-centre
+// E^n (mean of the two bounding edges) into the cell's 16-sample ring, run the network on
+// [E^n..E^{n-15}]/s, p1, p2 and advance Jc = alpha Jc + beta (E^n + s y) in place.
+// 64 rows (32 cells x 2 components) per work-group pass, 16 rows per wavefront.
+__global__ __launch_bounds__(256) void k_mlp2d(const Run2D<float>* __restrict__ rp, MlpWeights W,
+                                               MlpCells2D C, int64_t step) {
+  __shared__ MlpLds L;
+  __shared__ uint16_t Xs[4][16 * kK1P];
+  __shared__ uint16_t A1s[4][16 * kK2P];
+  __shared__ float rowE[64], rowS[64];
+  load_weights(L, W, false);
+  const Run2D<float>& R = *rp;
+  const int nx = R.nx;
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int slot = (int)(step & (kHist - 1));
+  for (int base = blockIdx.x * 32; base < C.n; base += gridDim.x * 32) {
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const int r = threadIdx.x, cell = base + (r >> 1), comp = r & 1;
+      uint16_t* x = Xs[r >> 4] + (r & 15) * kK1P;
+      float e = 0.f, sc = 1.f;
+      if (cell < C.n) {
+        const int k = C.idx[cell];
+        const int j = k / nx, i = k - j * nx;
+        e = comp == 0 ? 0.5f * (R.Ex[(size_t)j * nx + i] + R.Ex[(size_t)(j + 1) * nx + i])
+                      : 0.5f * (R.Ey[(size_t)j * (nx + 1) + i] + R.Ey[(size_t)j * (nx + 1) + i + 1]);
+        float* ring = C.ring + ((size_t)cell * 2 + comp) * kHist;
+        ring[slot] = e;
+        float h[kHist];
+        float m = 0.f;
+#pragma unroll
+        for (int q = 0; q < kHist; ++q) {
+          h[q] = q == 0 ? e : ring[(slot - q) & (kHist - 1)];
+          m = fmaxf(m, fabsf(h[q]));
+        }
+        sc = fmaxf(m, 1e-30f);
+#pragma unroll
+        for (int q = 0; q < kHist; ++q) x[q] = to_bf16(h[q] / sc);
+        x[kHist] = to_bf16(C.coef[4 * cell + 2]);
+        x[kHist + 1] = to_bf16(C.coef[4 * cell + 3]);
+      } else {
+        for (int q = 0; q < kNIn; ++q) x[q] = 0;
+      }
+      for (int q = kNIn; q < kK1; ++q) x[q] = 0;
+      rowE[r] = e;
+      rowS[r] = sc;
+    }
+    __syncthreads();
+    f4 z1[8], z2[8];
+    float y[4];
+    wave_forward(L, Xs[wave], A1s[wave], z1, z2, y);
+    if ((l & 15) == 0) {
+      const int kq = l >> 4;
+#pragma unroll
+      for (int e4 = 0; e4 < 4; ++e4) {
+        const int row = wave * 16 + kq * 4 + e4;
+        const int cell = base + (row >> 1);
+        if (cell < C.n) {
+          const int k = C.idx[cell];
+          float* Jc = (row & 1) ? R.Jcy : R.Jcx;
+          Jc[k] = fmaf(C.coef[4 * cell], Jc[k], C.coef[4 * cell + 1] * fmaf(rowS[row], y[e4], rowE[row]));
+        }
+      }
+    }
+  }
+}
+
+hipError_t mlp_launch_cells2d(const void* run, const MlpWeights& W, const MlpCells2D& C,
+                              int64_t step, hipStream_t st) {
+  if (C.n <= 0) return hipSuccess;
+  const int blocks = (C.n + 31) / 32 < 2048 ? (C.n + 31) / 32 : 2048;
+  hipLaunchKernelGGL(k_mlp2d, dim3(blocks), dim3(256), 0, st,
+                     static_cast<const Run2D<float>*>(run), W, C, step);
+  return hipGetLastError();
 }
 
 // --- host wrappers ---------------------------------------------------------------

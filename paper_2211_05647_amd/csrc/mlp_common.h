@@ -37,6 +37,14 @@ struct ReplayCell {
   float dens;      // electron density
 };
 
+// Closure cells of a 2D run.
+struct MlpCells2D {
+  const int32_t* idx;   // [n] grid index j * nx + i of each closure cell
+  const float* coef;    // [n][4] alpha, beta, q1, q2
+  float* ring;          // [n][2][kHist] cell-centre E history of (x, y), slot = step % kHist
+  int n;
+};
+
 struct PairSeries {
   float alpha, beta;   // single-pole recurrence of the cell's current
   float q1, q2;        // scaled omega_p dt and log10(nu_mean dt)
