@@ -146,7 +146,53 @@ def extra_workloads(B, W, torch, autotune):
                               "2 Nx steps each, one persistent launch",
                      updates_per_s=work / wall, seconds=wall, hbm_gbs=by / wall / 1e9,
                      hbm_frac=by / wall / 1e9 / HBM_PEAK_GBS)
+    out.update(closure_speedup(B, W, torch))
     return out
+
+
+def closure_speedup(B, W, torch, steps=50):
+    """4096^2 blob workload: time per step with every plasma cell on the kinetic F1 step,
+    and with the trained closure (cells outside the training box stay kinetic).  The
+    closure is trained first on the batch workload's taps (timed separately)."""
+    from paper_2211_05647_amd import closure as CL
+    t0 = time.perf_counter()
+    data, c = CL.gather_data(log=log)
+    t1 = time.perf_counter()
+    params, hist = CL.fit(data, c, log=lambda m: None)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    net, zero = CL.evaluate(data, c, data.held)
+    blob = CL.make_blob(params, data.box, data.dt)
+    c.close()
+    run = W.c4()
+    log(f"c4: {run.nx}x{run.ny}, plasma cells {run.plasma_cells}")
+    res = {}
+    for name, kw in (("kinetic", dict()), ("closure", dict(closure=B.CLOSURE_MLP, mlp_blob=blob))):
+        sim = B.Sim(run, precision=B.FP32, **kw)
+        sim.run(5)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sim.run(steps)
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t) / steps
+        res[name + "_event"] = sim.last_run_ms() * 1e-3
+        if name == "closure":
+            import ctypes as C
+            a, b = C.c_int64(), C.c_int64()
+            B.check(B.lib().fdtd_plasma_closure_counts(sim.h, C.byref(a), C.byref(b)), "counts")
+            res["closure_cells"], res["fallback_cells"] = a.value, b.value
+        sim.close()
+        torch.cuda.empty_cache()
+    rows = 2 * res["closure_cells"]
+    flops = rows * 2 * (18 * 128 + 128 * 128 + 128)
+    return {"c4_closure": dict(
+        workload="2D TEz 4096x4096, 48 plasma blobs, 32x32 bins; learned closure vs kinetic",
+        kinetic_ms_per_step=res["kinetic"] * 1e3, closure_ms_per_step=res["closure"] * 1e3,
+        speedup=res["kinetic"] / res["closure"], closure_cells=res["closure_cells"],
+        fallback_cells=res["fallback_cells"],
+        network_tflops_lower_bound=flops / res["closure"] / 1e12,
+        network_frac_of_bf16_peak_lower_bound=flops / res["closure"] / 2.5e15,
+        training=dict(gather_s=t1 - t0, fit_s=t2 - t1, held_out_mse=net, held_out_mse_without_net=zero))}
 
 
 def calibrate_copy(torch):

@@ -65,10 +65,13 @@ enum fdtd_source_kind { FDTD_SRC_NONE = 0, FDTD_SRC_LINE_SOFT = 1, FDTD_SRC_POIN
  * 2D TEz grids (Ex at (i+1/2, j), Ey at (i, j+1/2), Hz at (i+1/2, j+1/2)):
  *   FDTD_F_EX [ny+1][nx], FDTD_F_EY [ny][nx+1], FDTD_F_HZ [ny][nx] (A/m),
  *   FDTD_F_JX [ny+1][nx], FDTD_F_JY [ny][nx+1] (edge currents, A/m^2),
- *   FDTD_F_DF [ncell][nv][nv] (vx index, vy index), plasma cells in row-major order. */
+ *   FDTD_F_JCX, FDTD_F_JCY [ny][nx] cell-centre currents (A/m^2, 0 off plasma),
+ *   FDTD_F_DF [ncell][nv][nv] (vx index, vy index), the cells that run the kinetic step,
+ *             in row-major order (with the learned closure: its fallback cells only). */
 enum fdtd_field {
   FDTD_F_E = 0, FDTD_F_H = 1, FDTD_F_J = 2, FDTD_F_DF = 3,
-  FDTD_F_EX = 4, FDTD_F_EY = 5, FDTD_F_HZ = 6, FDTD_F_JX = 7, FDTD_F_JY = 8
+  FDTD_F_EX = 4, FDTD_F_EY = 5, FDTD_F_HZ = 6, FDTD_F_JX = 7, FDTD_F_JY = 8,
+  FDTD_F_JCX = 9, FDTD_F_JCY = 10
 };
 
 /* Grid (section 2): dims 1 = (Ez, Hy) line, 2 = TEz plane.  nx (and ny) in cells,

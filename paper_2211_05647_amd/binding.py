@@ -19,7 +19,7 @@ BC_PEC, BC_MUR1, BC_CPML = 0, 1, 2
 NU_HARD_SPHERE, NU_CONST = 0, 1
 CLOSURE_KINETIC, CLOSURE_MLP = 0, 1
 SRC_NONE, SRC_LINE, SRC_POINT = 0, 1, 2
-F_E, F_H, F_J, F_DF, F_EX, F_EY, F_HZ, F_JX, F_JY = range(9)
+F_E, F_H, F_J, F_DF, F_EX, F_EY, F_HZ, F_JX, F_JY, F_JCX, F_JCY = range(11)
 
 OK, EINVAL, ENOMEM, EDEVICE, ERANGE, ENUMERIC, ESTATE = 0, -1, -2, -3, -4, -5, -6
 

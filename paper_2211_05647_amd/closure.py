@@ -98,7 +98,7 @@ def gather_data(runs=None, ntap=8, te_ev=5.0, seed=2211, held_runs=24, closure=N
     p1 = plasma_dt(ne) * dt
     p2 = np.log10(nu * dt)
     box = (float(p1.min()), float(p1.max()), float(p2.min()), float(p2.max()))
-    c = closure or B.Closure(max_rows=4096, max_series=max(ns, 16))
+    c = closure or B.Closure(max_rows=8192, max_series=max(ns, 16))
     J = torch.zeros_like(E)
     c.replay2v(E.data_ptr(), 1, T, ns, T, ne, nu, te_ev, dt, J, T)
     torch.cuda.synchronize()
@@ -140,9 +140,9 @@ def init_params(seed):
     return np.concatenate([W1.ravel(), np.zeros(nh), W2.ravel(), np.zeros(nh), w3, [0.0]]).astype(np.float32)
 
 
-def fit(data, closure, iters=4000, batch=4096, lr=1e-3, lr_end=1e-4, seed=7, log=print):
+def fit(data, closure, iters=6000, batch=8192, lr=2e-3, lr_end=2e-5, seed=7, log=print):
     """Adam on fresh random minibatches of training pairs (cosine-decayed learning rate).
-    Returns the trained parameters and the loss history (every 200 iterations)."""
+    Returns the trained parameters and the loss history (every 500 iterations)."""
     g = np.random.default_rng(seed)
     closure.set_params(init_params(seed))
     hist = []
@@ -151,7 +151,7 @@ def fit(data, closure, iters=4000, batch=4096, lr=1e-3, lr_end=1e-4, seed=7, log
         idx = sample(data, data.train, batch, g)
         X, Tt = closure.make_pairs(data.E.data_ptr(), 1, T, data.J, T, data.series4, idx)
         rate = lr_end + 0.5 * (lr - lr_end) * (1 + math.cos(math.pi * it / max(iters - 1, 1)))
-        want = (it % 200 == 0) or it == iters - 1
+        want = (it % 500 == 0) or it == iters - 1
         loss = closure.train_step(X, Tt, rate, want_loss=want)
         if want:
             hist.append((it, loss))

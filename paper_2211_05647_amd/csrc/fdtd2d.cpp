@@ -447,7 +447,7 @@ int field_size_2d(const Host2D* h, int field, size_t* n) {
   switch (field) {
     case FDTD_F_EX: case FDTD_F_JX: *n = (ny + 1) * nx; return FDTD_OK;
     case FDTD_F_EY: case FDTD_F_JY: *n = ny * (nx + 1); return FDTD_OK;
-    case FDTD_F_HZ: *n = ny * nx; return FDTD_OK;
+    case FDTD_F_HZ: case FDTD_F_JCX: case FDTD_F_JCY: *n = ny * nx; return FDTD_OK;
     case FDTD_F_DF: *n = (size_t)h->ncell * h->nv * h->nv; return FDTD_OK;
     default: return fail(FDTD_EINVAL, "field %d not defined on a 2D grid", field);
   }
@@ -481,6 +481,11 @@ int read_2d(Host2D* h, char* ws, int field, int64_t, double* dst) {
     case FDTD_F_HZ:
       rc = grab(h->off_Hz, (size_t)ny * nx, v);
       if (!rc) for (size_t k = 0; k < v.size(); ++k) dst[k] = v[k] / kEta0;
+      break;
+    case FDTD_F_JCX:
+    case FDTD_F_JCY:
+      rc = grab(field == FDTD_F_JCX ? h->off_Jcx : h->off_Jcy, (size_t)ny * nx, v);
+      if (!rc) for (size_t k = 0; k < v.size(); ++k) dst[k] = v[k] * jscale;
       break;
     case FDTD_F_JX:
       rc = grab(h->off_Jcx, (size_t)ny * nx, v);

@@ -122,33 +122,109 @@ __device__ __forceinline__ void wave_forward(const MlpLds& L, const uint16_t* Xs
   }
 }
 
-// --- inference on rows in global memory ----------------------------------------------
-__global__ __launch_bounds__(256) void k_mlp_rows(MlpWeights W, const float* __restrict__ X,
-                                                  int n, float* __restrict__ Y) {
-  __shared__ MlpLds L;
-  __shared__ uint16_t Xs[4][16 * kK1P];
-  __shared__ uint16_t A1s[4][16 * kK2P];
-  load_weights(L, W, false);
-  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-  for (int base = blockIdx.x * 64; base < n; base += gridDim.x * 64) {
-    __syncthreads();
-    // stage this wave's 16 feature rows as bf16 (zero padding beyond 18 and n)
-    for (int q = l; q < 16 * kK1; q += 64) {
-      const int r = q / kK1, k = q - r * kK1;
-      const int row = base + wave * 16 + r;
-      const float v = (row < n && k < kNIn) ? X[(size_t)row * kNIn + k] : 0.f;
-      Xs[wave][r * kK1P + k] = to_bf16(v);
+// Register-chained forward pass of G groups of 16 rows held by one wavefront, with every
+// layer computed transposed (Z^T = W X^T): the MFMA result of a layer lands in exactly the
+// lane layout the next layer takes as its B operand, so activations never leave
+// registers and only the weights are read from LDS (each weight fragment serves G groups).
+//   xb[g][kk]: B operand of layer 1, lane (r0, kq) holds X[row r0][16 kk + 4 kq + e]
+//   returns y[g] of row r0 of group g (on all four kq lanes of that row)
+template <int G>
+__device__ __forceinline__ void wave_forward_t(const MlpLds& L, const s4 (&xb)[G][2],
+                                               float (&y)[G]) {
+  const int l = threadIdx.x & 63, r0 = l & 15, kq = l >> 4;
+  s4 a1[G][8];
+#pragma unroll
+  for (int nt = 0; nt < 8; ++nt) {
+    const s4 w0 = *reinterpret_cast<const s4*>(L.W1 + (nt * 16 + r0) * kK1P + kq * 4);
+    const s4 w1 = *reinterpret_cast<const s4*>(L.W1 + (nt * 16 + r0) * kK1P + 16 + kq * 4);
+    float bias[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) bias[e] = L.b1[nt * 16 + kq * 4 + e];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      f4 c = {0.f, 0.f, 0.f, 0.f};
+      c = mfma(w0, xb[g][0], c);
+      c = mfma(w1, xb[g][1], c);
+      s4 o;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) o[e] = (short)to_bf16(gelu_f(c[e] + bias[e]));
+      a1[g][nt] = o;
     }
-    __syncthreads();
-    f4 z1[8], z2[8];
-    float y[4];
-    wave_forward(L, Xs[wave], A1s[wave], z1, z2, y);
-    const int r0 = l & 15, kq = l >> 4;
-    if (r0 == 0) {
+  }
+  float yp[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) yp[g] = 0.f;
+#pragma unroll 1
+  for (int nt = 0; nt < 8; ++nt) {
+    f4 c[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) c[g] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      const s4 w = *reinterpret_cast<const s4*>(L.W2 + (nt * 16 + r0) * kK2P + kk * 16 + kq * 4);
+#pragma unroll
+      for (int g = 0; g < G; ++g) c[g] = mfma(w, a1[g][kk], c[g]);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float bias = L.b2[nt * 16 + kq * 4 + e], w3 = L.w3[nt * 16 + kq * 4 + e];
+#pragma unroll
+      for (int g = 0; g < G; ++g) yp[g] = fmaf(gelu_f(c[g][e] + bias), w3, yp[g]);
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    float v = yp[g];
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    y[g] = v + L.b3;
+  }
+}
+
+// Pack 4 floats / s into bf16 (ties to even).
+__device__ __forceinline__ s4 pack4(float a, float b, float c, float d) {
+  s4 o;
+  o[0] = (short)to_bf16(a);
+  o[1] = (short)to_bf16(b);
+  o[2] = (short)to_bf16(c);
+  o[3] = (short)to_bf16(d);
+  return o;
+}
+
+// --- inference on rows in global memory ----------------------------------------------
+constexpr int kInferWaves = 8;   // wavefronts per inference work-group (weights shared in LDS)
+constexpr int kInferG = 4;       // 16-row groups per wavefront
+
+__global__ __launch_bounds__(kInferWaves * 64) void k_mlp_rows(MlpWeights W,
+                                                              const float* __restrict__ X, int n,
+                                                              float* __restrict__ Y) {
+  __shared__ MlpLds L;
+  load_weights(L, W, false);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, r0 = l & 15, kq = l >> 4;
+  const int nwaves = gridDim.x * kInferWaves;
+  for (int t = blockIdx.x * kInferWaves + wave; t * 64 < n; t += nwaves) {
+    s4 xb[kInferG][2];
+#pragma unroll
+    for (int g = 0; g < kInferG; ++g) {
+      const int row = t * 64 + g * 16 + r0;
+      float v[8];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int row = base + wave * 16 + kq * 4 + e;
-        if (row < n) Y[row] = y[e];
+        v[e] = row < n ? X[(size_t)row * kNIn + kq * 4 + e] : 0.f;
+        const int k2 = 16 + kq * 4 + e;
+        v[4 + e] = (row < n && k2 < kNIn) ? X[(size_t)row * kNIn + k2] : 0.f;
+      }
+      xb[g][0] = pack4(v[0], v[1], v[2], v[3]);
+      xb[g][1] = pack4(v[4], v[5], v[6], v[7]);
+    }
+    float y[kInferG];
+    wave_forward_t<kInferG>(L, xb, y);
+    if (kq == 0) {
+#pragma unroll
+      for (int g = 0; g < kInferG; ++g) {
+        const int row = t * 64 + g * 16 + r0;
+        if (row < n) Y[row] = y[g];
       }
     }
   }
@@ -434,64 +510,68 @@ __global__ void k_make_pairs(const float* __restrict__ E, int64_t e_stride, int6
 // Per step, for every closure cell and both current components: push the cell-centre
 // E^n (mean of the two bounding edges) into the cell's 16-sample ring, run the network on
 // [E^n..E^{n-15}]/s, p1, p2 and advance Jc = alpha Jc + beta (E^n + s y) in place.
-// 64 rows (32 cells x 2 components) per work-group pass, 16 rows per wavefront.
-__global__ __launch_bounds__(256) void k_mlp2d(const Run2D<float>* __restrict__ rp, MlpWeights W,
-                                               MlpCells2D C, int64_t step) {
+// Each wavefront takes tiles of 64 rows (32 cells x 2 components); the four lanes
+// (kq = 0..3) of row r0 stage history samples 4 kq .. 4 kq + 3 of that row, which is the
+// B-operand layout of the transposed first layer, so features go straight to registers.
+__global__ __launch_bounds__(kInferWaves * 64) void k_mlp2d(const Run2D<float>* __restrict__ rp,
+                                                           MlpWeights W, MlpCells2D C,
+                                                           int64_t step) {
   __shared__ MlpLds L;
-  __shared__ uint16_t Xs[4][16 * kK1P];
-  __shared__ uint16_t A1s[4][16 * kK2P];
-  __shared__ float rowE[64], rowS[64];
   load_weights(L, W, false);
+  __syncthreads();
   const Run2D<float>& R = *rp;
   const int nx = R.nx;
-  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, r0 = l & 15, kq = l >> 4;
   const int slot = (int)(step & (kHist - 1));
-  for (int base = blockIdx.x * 32; base < C.n; base += gridDim.x * 32) {
-    __syncthreads();
-    if (threadIdx.x < 64) {
-      const int r = threadIdx.x, cell = base + (r >> 1), comp = r & 1;
-      uint16_t* x = Xs[r >> 4] + (r & 15) * kK1P;
-      float e = 0.f, sc = 1.f;
+  const int nwaves = gridDim.x * kInferWaves;
+  const int nrows = 2 * C.n;
+  for (int t = blockIdx.x * kInferWaves + wave; t * 64 < nrows; t += nwaves) {
+    s4 xb[kInferG][2];
+    float ev[kInferG], sv[kInferG];
+    int kidx[kInferG];
+#pragma unroll
+    for (int g = 0; g < kInferG; ++g) {
+      const int row = t * 64 + g * 16 + r0;
+      const int cell = row >> 1, comp = row & 1;
+      float h[4] = {0.f, 0.f, 0.f, 0.f};
+      float e = 0.f, m = 0.f, q1 = 0.f, q2 = 0.f;
+      kidx[g] = -1;
       if (cell < C.n) {
         const int k = C.idx[cell];
+        kidx[g] = k;
         const int j = k / nx, i = k - j * nx;
         e = comp == 0 ? 0.5f * (R.Ex[(size_t)j * nx + i] + R.Ex[(size_t)(j + 1) * nx + i])
                       : 0.5f * (R.Ey[(size_t)j * (nx + 1) + i] + R.Ey[(size_t)j * (nx + 1) + i + 1]);
         float* ring = C.ring + ((size_t)cell * 2 + comp) * kHist;
-        ring[slot] = e;
-        float h[kHist];
-        float m = 0.f;
 #pragma unroll
-        for (int q = 0; q < kHist; ++q) {
-          h[q] = q == 0 ? e : ring[(slot - q) & (kHist - 1)];
+        for (int q = 0; q < 4; ++q) {
+          const int kh = kq * 4 + q;                 // history index: E^{n - kh}
+          h[q] = kh == 0 ? e : ring[(slot - kh) & (kHist - 1)];
           m = fmaxf(m, fabsf(h[q]));
         }
-        sc = fmaxf(m, 1e-30f);
-#pragma unroll
-        for (int q = 0; q < kHist; ++q) x[q] = to_bf16(h[q] / sc);
-        x[kHist] = to_bf16(C.coef[4 * cell + 2]);
-        x[kHist + 1] = to_bf16(C.coef[4 * cell + 3]);
-      } else {
-        for (int q = 0; q < kNIn; ++q) x[q] = 0;
+        if (kq == 0) ring[slot] = e;
+        q1 = C.coef[4 * cell + 2];
+        q2 = C.coef[4 * cell + 3];
       }
-      for (int q = kNIn; q < kK1; ++q) x[q] = 0;
-      rowE[r] = e;
-      rowS[r] = sc;
+      m = fmaxf(m, __shfl_xor(m, 16));
+      m = fmaxf(m, __shfl_xor(m, 32));
+      const float sc = fmaxf(m, 1e-30f);
+      xb[g][0] = pack4(h[0] / sc, h[1] / sc, h[2] / sc, h[3] / sc);
+      xb[g][1] = kq == 0 ? pack4(q1, q2, 0.f, 0.f) : pack4(0.f, 0.f, 0.f, 0.f);
+      ev[g] = e;
+      sv[g] = sc;
     }
-    __syncthreads();
-    f4 z1[8], z2[8];
-    float y[4];
-    wave_forward(L, Xs[wave], A1s[wave], z1, z2, y);
-    if ((l & 15) == 0) {
-      const int kq = l >> 4;
+    float y[kInferG];
+    wave_forward_t<kInferG>(L, xb, y);
+    if (kq == 0) {
 #pragma unroll
-      for (int e4 = 0; e4 < 4; ++e4) {
-        const int row = wave * 16 + kq * 4 + e4;
-        const int cell = base + (row >> 1);
-        if (cell < C.n) {
-          const int k = C.idx[cell];
+      for (int g = 0; g < kInferG; ++g) {
+        if (kidx[g] >= 0) {
+          const int row = t * 64 + g * 16 + r0;
+          const int cell = row >> 1;
           float* Jc = (row & 1) ? R.Jcy : R.Jcx;
-          Jc[k] = fmaf(C.coef[4 * cell], Jc[k], C.coef[4 * cell + 1] * fmaf(rowS[row], y[e4], rowE[row]));
+          const float alpha = C.coef[4 * cell], beta = C.coef[4 * cell + 1];
+          Jc[kidx[g]] = fmaf(alpha, Jc[kidx[g]], beta * fmaf(sv[g], y[g], ev[g]));
         }
       }
     }
@@ -501,8 +581,9 @@ __global__ __launch_bounds__(256) void k_mlp2d(const Run2D<float>* __restrict__ 
 hipError_t mlp_launch_cells2d(const void* run, const MlpWeights& W, const MlpCells2D& C,
                               int64_t step, hipStream_t st) {
   if (C.n <= 0) return hipSuccess;
-  const int blocks = (C.n + 31) / 32 < 2048 ? (C.n + 31) / 32 : 2048;
-  hipLaunchKernelGGL(k_mlp2d, dim3(blocks), dim3(256), 0, st,
+  const int tiles = (2 * C.n + 63) / 64;
+  const int blocks = (tiles + kInferWaves - 1) / kInferWaves < 1024 ? (tiles + kInferWaves - 1) / kInferWaves : 1024;
+  hipLaunchKernelGGL(k_mlp2d, dim3(blocks), dim3(kInferWaves * 64), 0, st,
                      static_cast<const Run2D<float>*>(run), W, C, step);
   return hipGetLastError();
 }
@@ -510,8 +591,9 @@ hipError_t mlp_launch_cells2d(const void* run, const MlpWeights& W, const MlpCel
 // --- host wrappers ---------------------------------------------------------------
 hipError_t mlp_launch_rows(const MlpWeights& W, const float* X, int n, float* Y, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  const int blocks = (n + 63) / 64 < 2048 ? (n + 63) / 64 : 2048;
-  hipLaunchKernelGGL(k_mlp_rows, dim3(blocks), dim3(256), 0, st, W, X, n, Y);
+  const int tiles = (n + 63) / 64;
+  const int blocks = (tiles + kInferWaves - 1) / kInferWaves < 1024 ? (tiles + kInferWaves - 1) / kInferWaves : 1024;
+  hipLaunchKernelGGL(k_mlp_rows, dim3(blocks), dim3(kInferWaves * 64), 0, st, W, X, n, Y);
   return hipGetLastError();
 }
 

@@ -155,7 +155,7 @@ def trained():
     import torch
     _banner("gathering training data from the 256-run batch")
     data, c = CL.gather_data(log=lambda m: _banner(m))
-    params, hist = CL.fit(data, c, iters=3000, log=lambda m: _banner(m))
+    params, hist = CL.fit(data, c, log=lambda m: _banner(m))
     net, zero = CL.evaluate(data, c, data.held)
     _banner(f"held-out MSE: network {net:.4e}, without network {zero:.4e}")
     return data, c, params, (net, zero)
