@@ -177,10 +177,7 @@ def closure_speedup(B, W, torch, steps=50):
         res[name] = (time.perf_counter() - t) / steps
         res[name + "_event"] = sim.last_run_ms() * 1e-3
         if name == "closure":
-            import ctypes as C
-            a, b = C.c_int64(), C.c_int64()
-            B.check(B.lib().fdtd_plasma_closure_counts(sim.h, C.byref(a), C.byref(b)), "counts")
-            res["closure_cells"], res["fallback_cells"] = a.value, b.value
+            res["closure_cells"], res["fallback_cells"] = sim.closure_counts()
         sim.close()
         torch.cuda.empty_cache()
     rows = 2 * res["closure_cells"]
@@ -216,6 +213,8 @@ def main():
     ap.add_argument("--quick", action="store_true", help="only the headline workload")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--only", choices=["closure"], default=None,
+                    help="run only one of the extra measurements (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the kinetic-FDTD path here runs on a single "
@@ -230,6 +229,9 @@ def main():
     from paper_2211_05647_amd import autotune
     from paper_2211_05647_amd import binding as B
     from paper_2211_05647_amd import workloads as W
+    if args.only == "closure":
+        print(json.dumps(closure_speedup(B, W, torch)), flush=True)
+        return
 
     run = W.c1()
     log(f"workload c1: Nx={run.nx} Nv={run.nv} plasma cells={run.plasma_cells}")

@@ -62,6 +62,7 @@ _SIGS = {
     "fdtd_plasma_set_batch_mode": ([C.c_void_p, C.c_int32, C.c_int32], C.c_int),
     "fdtd_plasma_read_taps": ([C.c_void_p, C.c_int32, _dp, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
     "fdtd_plasma_run_status": ([C.c_void_p, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
+    "fdtd_plasma_closure_counts": ([C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
     "fdtd_plasma_step": ([C.c_void_p], C.c_int),
     "fdtd_plasma_run": ([C.c_void_p, C.c_int64], C.c_int),
     "fdtd_plasma_steps": ([C.c_void_p, C.POINTER(C.c_int64)], C.c_int),
@@ -279,6 +280,12 @@ class Sim:
         st = C.c_int32()
         check(lib().fdtd_plasma_run_status(self.h, run, C.byref(st)), "run_status")
         return st.value
+
+    def closure_counts(self):
+        """(closure cells, kinetic cells) of a 2D run with the learned closure."""
+        a, b = C.c_int64(), C.c_int64()
+        check(lib().fdtd_plasma_closure_counts(self.h, C.byref(a), C.byref(b)), "closure_counts")
+        return a.value, b.value
 
     def tap_buffer(self, run):
         """(device pointer, capacity, ntap) of a batch run's tap buffer [ntap][cap][2] FP32."""

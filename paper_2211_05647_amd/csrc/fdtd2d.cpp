@@ -13,6 +13,7 @@
 #include "common.h"
 #include "host_internal.h"
 #include "mlp_common.h"
+#include "yee2d.h"
 
 namespace fdtdp {
 
@@ -267,8 +268,8 @@ int upload(Host2D* h, char* ws, hipStream_t st, const std::vector<ProbeInfo>& pr
 
 void set_grid(Host2D* h) {
   h->nbk = h->ncell > 0 ? (h->ncell + h->cells_per_block - 1) / h->cells_per_block : 0;
-  h->nbh = (h->nx * h->ny + kBlock - 1) / kBlock;
-  h->nbe = ((h->nx + 1) * (h->ny + 1) + kBlock - 1) / kBlock;
+  h->nbh = row_segments(h->nx, h->ny, kBlock);
+  h->nbe = row_segments(h->nx + 1, h->ny + 1, kBlock);
 }
 
 }  // namespace
@@ -276,7 +277,7 @@ void set_grid(Host2D* h) {
 template <class T>
 hipError_t launch_step2d_t(const void* run, int nbk, int nbh, int nbe, int64_t step,
                            hipStream_t stream);
-hipError_t launch_step2d_closure(const void* run, int nbk, int nbh, int nbe, int64_t step,
+hipError_t launch_step2d_closure(const void* run, int nbk, int nx, int ny, int nbe, int64_t step,
                                  hipStream_t stream, const MlpWeights& W, const MlpCells2D& C);
 
 int validate_2d(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s) {
@@ -432,7 +433,8 @@ int upload_2d(Host2D* h, char* ws, hipStream_t stream, const std::vector<ProbeIn
 hipError_t launch_step2d(Host2D* h, int64_t step, hipStream_t stream) {
   const void* run = h->ws + h->off_run;
   if (h->es == 8) return launch_step2d_t<double>(run, h->nbk, h->nbh, h->nbe, step, stream);
-  if (h->C.n > 0) return launch_step2d_closure(run, h->nbk, h->nbh, h->nbe, step, stream, h->W, h->C);
+  if (h->C.n > 0)
+    return launch_step2d_closure(run, h->nbk, h->nx, h->ny, h->nbe, step, stream, h->W, h->C);
   return launch_step2d_t<float>(run, h->nbk, h->nbh, h->nbe, step, stream);
 }
 

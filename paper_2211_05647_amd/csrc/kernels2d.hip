@@ -6,13 +6,16 @@
 //   k_h2d_kin  blocks [0, nbk): F1 update of a range of plasma cells, driven by E^n
 //              averaged from the cell's two bounding edges to its centre, and the
 //              FP64 moments (Jx, Jy) of the cell;  blocks [nbk, ...): Hz^{n+1/2} with
-//              the CPML psi of the H side.  Both halves only read E^n.
+//              the CPML psi of the H side, one row segment per block.  Both halves only
+//              read E^n.
 //   k_e2d      E^{n+1} with the CPML psi of the E side, the edge current (mean of the
 //              two adjacent cell-centre currents), PEC walls and the soft source.
+// With the learned closure, the network and Hz share a launch instead (mlp.hip).
 // F1 layout: [cell][vx bin a][vy bin b >= nv/2]: the half plane vy > 0 (F1 is odd under
 // v -> -v), one contiguous row of nv*nv/2 values per cell.
 #include "common.h"
 #include "mlp_common.h"
+#include "yee2d.h"
 
 namespace fdtdp {
 
@@ -124,14 +127,6 @@ __device__ __forceinline__ void kinetic2d_block(const Run2D<T>& R, int c0, int c
 }
 
 template <class T>
-__device__ __forceinline__ void record_probe(const Run2D<T>& R, int field, int i, int j, T val,
-                                             int64_t step) {
-  for (int p = 0; p < R.nprobe; ++p)
-    if (R.probe_field[p] == field && R.probe_i[p] == i && R.probe_j[p] == j)
-      R.probe_buf[(size_t)p * R.probe_cap + (size_t)(step % R.probe_cap)] = val;
-}
-
-template <class T>
 __global__ __launch_bounds__(kBlock) void k_h2d_kin(const Run2D<T>* __restrict__ rp, int64_t step) {
   const Run2D<T>& R = *rp;
   if ((int)blockIdx.x < R.nbk) {
@@ -144,78 +139,22 @@ __global__ __launch_bounds__(kBlock) void k_h2d_kin(const Run2D<T>* __restrict__
     else kinetic2d_block<T, 1>(R, c0, c1);
     return;
   }
-  const int nx = R.nx, ny = R.ny, m = R.m;
-  const int q = ((int)blockIdx.x - R.nbk) * kBlock + threadIdx.x;
-  if (q >= nx * ny) return;
-  const int j = q / nx, i = q - j * nx;
-  const T dEx = R.Ex[(size_t)(j + 1) * nx + i] - R.Ex[(size_t)j * nx + i];
-  const T dEy = R.Ey[(size_t)j * (nx + 1) + i + 1] - R.Ey[(size_t)j * (nx + 1) + i];
-  T acc = dEx * R.rkhy[j] - dEy * R.rkhx[i];
-  if (m > 0) {
-    if (i < m || i >= nx - m) {
-      const int sx = i < m ? i : i - (nx - 2 * m);
-      T* p = R.psi_hzx + (size_t)j * (2 * m) + sx;
-      const T v = fma(R.bhx[i], *p, R.ahx[i] * dEy);
-      *p = v;
-      acc -= v;
-    }
-    if (j < m || j >= ny - m) {
-      const int sy = j < m ? j : j - (ny - 2 * m);
-      T* p = R.psi_hzy + (size_t)sy * nx + i;
-      const T v = fma(R.bhy[j], *p, R.ahy[j] * dEx);
-      *p = v;
-      acc += v;
-    }
-  }
-  const T hz = fma(R.S, acc, R.Hz[q]);
-  R.Hz[q] = hz;
-  if (R.nprobe) record_probe(R, 6 /* FDTD_F_HZ */, i, j, hz, step);
+  // Hz: one row segment of kBlock points per block
+  const int seg = (int)blockIdx.x - R.nbk;
+  const int spr = (R.nx + kBlock - 1) / kBlock;
+  const int j = seg / spr;
+  const int i = (seg - j * spr) * kBlock + (int)threadIdx.x;
+  if (j < R.ny && i < R.nx) h2d_point(R, i, j, step);
 }
 
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_e2d(const Run2D<T>* __restrict__ rp, int64_t step) {
   const Run2D<T>& R = *rp;
-  const int nx = R.nx, ny = R.ny, m = R.m;
-  const int q = blockIdx.x * kBlock + threadIdx.x;
-  if (q >= (nx + 1) * (ny + 1)) return;
-  const int j = q / (nx + 1), i = q - j * (nx + 1);
-  // Ex at (i+1/2, j), tangential walls j = 0 and j = ny stay zero
-  if (i < nx && j >= 1 && j <= ny - 1) {
-    const size_t k = (size_t)j * nx + i;
-    const T dHz = R.Hz[k] - R.Hz[k - nx];
-    T acc = dHz * R.rkey[j];
-    if (m > 0 && (j < m || j > ny - m)) {
-      const int sy = j < m ? j : j - ny + 2 * m - 1;
-      T* p = R.psi_exy + (size_t)sy * nx + i;
-      const T v = fma(R.bey[j], *p, R.aey[j] * dHz);
-      *p = v;
-      acc += v;
-    }
-    const T jx = T(0.5) * (R.Jcx[k - nx] + R.Jcx[k]);
-    const T ex = fma(R.S, acc, R.Ex[k]) - jx;
-    R.Ex[k] = ex;
-    if (R.nprobe) record_probe(R, 4 /* FDTD_F_EX */, i, j, ex, step);
-  }
-  // Ey at (i, j+1/2), tangential walls i = 0 and i = nx stay zero
-  if (j < ny && i >= 1 && i <= nx - 1) {
-    const size_t k = (size_t)j * (nx + 1) + i;
-    const size_t kc = (size_t)j * nx + i;
-    const T dHz = R.Hz[kc] - R.Hz[kc - 1];
-    T acc = dHz * R.rkex[i];
-    if (m > 0 && (i < m || i > nx - m)) {
-      const int sx = i < m ? i : i - nx + 2 * m - 1;
-      T* p = R.psi_eyx + (size_t)j * (2 * m) + sx;
-      const T v = fma(R.bex[i], *p, R.aex[i] * dHz);
-      *p = v;
-      acc += v;
-    }
-    const T jy = T(0.5) * (R.Jcy[kc - 1] + R.Jcy[kc]);
-    T ey = fma(-R.S, acc, R.Ey[k]) - jy;
-    if (R.src_kind != 0 && i == R.src_i && (R.src_kind == 1 || j == R.src_j))
-      ey += (T)source_wave((double)(step + 1) * R.dt, R.src_amp, R.src_w, R.src_tau, R.src_t0);
-    R.Ey[k] = ey;
-    if (R.nprobe) record_probe(R, 5 /* FDTD_F_EY */, i, j, ey, step);
-  }
+  // one row segment of kBlock points of the (nx+1) x (ny+1) lattice per block
+  const int spr = (R.nx + kBlock) / kBlock;
+  const int j = (int)blockIdx.x / spr;
+  const int i = ((int)blockIdx.x - j * spr) * kBlock + (int)threadIdx.x;
+  if (j <= R.ny && i <= R.nx) e2d_point(R, i, j, step);
 }
 
 template <class T>
@@ -230,15 +169,21 @@ hipError_t launch_step2d_t(const void* run, int nbk, int nbh, int nbe, int64_t s
 }
 
 hipError_t mlp_launch_cells2d(const void* run, const MlpWeights& W, const MlpCells2D& C,
-                              int64_t step, hipStream_t st);
+                              int nx, int ny, int64_t step, hipStream_t st);
 
-hipError_t launch_step2d_closure(const void* run, int nbk, int nbh, int nbe, int64_t step,
+// Closure step: kinetic blocks for the fallback cells (if any), then one launch that runs
+// the network of every closure cell and the Hz update side by side (both only read E^n,
+// and the network's arithmetic hides the field update's memory traffic), then E.
+hipError_t launch_step2d_closure(const void* run, int nbk, int nx, int ny, int nbe, int64_t step,
                                  hipStream_t stream, const MlpWeights& W, const MlpCells2D& C) {
   const Run2D<float>* r = static_cast<const Run2D<float>*>(run);
-  hipLaunchKernelGGL(k_h2d_kin<float>, dim3(nbk + nbh), dim3(kBlock), 0, stream, r, step);
-  hipError_t e = hipGetLastError();
-  if (e) return e;
-  e = mlp_launch_cells2d(run, W, C, step, stream);
+  hipError_t e;
+  if (nbk > 0) {
+    hipLaunchKernelGGL(k_h2d_kin<float>, dim3(nbk), dim3(kBlock), 0, stream, r, step);
+    e = hipGetLastError();
+    if (e) return e;
+  }
+  e = mlp_launch_cells2d(run, W, C, nx, ny, step, stream);
   if (e) return e;
   hipLaunchKernelGGL(k_e2d<float>, dim3(nbe), dim3(kBlock), 0, stream, r, step);
   return hipGetLastError();

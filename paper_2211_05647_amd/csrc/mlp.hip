@@ -17,6 +17,7 @@
 
 #include "common.h"
 #include "mlp_common.h"
+#include "yee2d.h"
 
 namespace fdtdp {
 
@@ -24,18 +25,17 @@ typedef short s4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);      // round to nearest, ties to even
-  return (uint16_t)(u >> 16);
+  return __builtin_bit_cast(uint16_t, (__bf16)f);   // v_cvt_pk_bf16_f32: round to nearest even
 }
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // GELU in its tanh form, evaluated through 0.5 (1 + tanh u) = 1 / (1 + exp(-2u)) with the
 // hardware exp2 and reciprocal (relative error ~1e-7, far below the bf16 operand rounding).
 __device__ __forceinline__ float gelu_sig(float x) {
-  const float k2 = 2.0f * 0.7978845608028654f * 1.4426950408889634f;   // 2 sqrt(2/pi) log2(e)
-  const float u = x * fmaf(0.044715f * x, x, 1.0f);
-  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-k2 * u));   // 0.5 (1 + tanh)
+  // -2 sqrt(2/pi) log2(e) (x + 0.044715 x^3) = x (c0 + c1 x^2)
+  constexpr float c0 = -2.0f * 0.7978845608028654f * 1.4426950408889634f;
+  constexpr float c1 = c0 * 0.044715f;
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(x * fmaf(c1, x * x, c0)));
 }
 __device__ __forceinline__ float gelu_f(float x) { return x * gelu_sig(x); }
 __device__ __forceinline__ float gelu_grad_f(float x) {
@@ -193,7 +193,8 @@ __device__ __forceinline__ s4 pack4(float a, float b, float c, float d) {
 
 // --- inference on rows in global memory ----------------------------------------------
 constexpr int kInferWaves = 8;   // wavefronts per inference work-group (weights shared in LDS)
-constexpr int kInferG = 4;       // 16-row groups per wavefront
+constexpr int kInferG = 1;       // 16-row groups per wavefront
+constexpr int kWaveRows = 16 * kInferG;   // rows of one wavefront tile
 
 __global__ __launch_bounds__(kInferWaves * 64) void k_mlp_rows(MlpWeights W,
                                                               const float* __restrict__ X, int n,
@@ -203,11 +204,11 @@ __global__ __launch_bounds__(kInferWaves * 64) void k_mlp_rows(MlpWeights W,
   __syncthreads();
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, r0 = l & 15, kq = l >> 4;
   const int nwaves = gridDim.x * kInferWaves;
-  for (int t = blockIdx.x * kInferWaves + wave; t * 64 < n; t += nwaves) {
+  for (int t = blockIdx.x * kInferWaves + wave; t * kWaveRows < n; t += nwaves) {
     s4 xb[kInferG][2];
 #pragma unroll
     for (int g = 0; g < kInferG; ++g) {
-      const int row = t * 64 + g * 16 + r0;
+      const int row = t * kWaveRows + g * 16 + r0;
       float v[8];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(kInferWaves * 64) void k_mlp_rows(MlpWeights W,
     if (kq == 0) {
 #pragma unroll
       for (int g = 0; g < kInferG; ++g) {
-        const int row = t * 64 + g * 16 + r0;
+        const int row = t * kWaveRows + g * 16 + r0;
         if (row < n) Y[row] = y[g];
       }
     }
@@ -507,10 +508,14 @@ __global__ void k_make_pairs(const float* __restrict__ E, int64_t e_stride, int6
 }
 
 // --- the closure inside a 2D run ----------------------------------------------------
-// Per step, for every closure cell and both current components: push the cell-centre
+// One launch per step does two independent things that both only read E^n: the Hz
+// half-step (row segments of 64 points, one point per lane) and the closure.  Each
+// wavefront takes tile t of both, so the field update's memory traffic is overlapped by
+// the network's matrix and GELU arithmetic on the same compute units.
+// Closure: for every closure cell and both current components, push the cell-centre
 // E^n (mean of the two bounding edges) into the cell's 16-sample ring, run the network on
 // [E^n..E^{n-15}]/s, p1, p2 and advance Jc = alpha Jc + beta (E^n + s y) in place.
-// Each wavefront takes tiles of 64 rows (32 cells x 2 components); the four lanes
+// Each wavefront takes tiles of 16 kInferG rows (8 kInferG cells x 2 components); the four lanes
 // (kq = 0..3) of row r0 stage history samples 4 kq .. 4 kq + 3 of that row, which is the
 // B-operand layout of the transposed first layer, so features go straight to registers.
 __global__ __launch_bounds__(kInferWaves * 64) void k_mlp2d(const Run2D<float>* __restrict__ rp,
@@ -525,13 +530,24 @@ __global__ __launch_bounds__(kInferWaves * 64) void k_mlp2d(const Run2D<float>* 
   const int slot = (int)(step & (kHist - 1));
   const int nwaves = gridDim.x * kInferWaves;
   const int nrows = 2 * C.n;
-  for (int t = blockIdx.x * kInferWaves + wave; t * 64 < nrows; t += nwaves) {
+  const int tiles_m = (nrows + kWaveRows - 1) / kWaveRows;
+  const int spr = (nx + 63) / 64;                   // Hz row segments of 64 points
+  const int tiles_h = spr * R.ny;
+  const int tiles = tiles_m > tiles_h ? tiles_m : tiles_h;
+  const int w0 = __builtin_amdgcn_readfirstlane(blockIdx.x * kInferWaves + wave);
+  for (int t = w0; t < tiles; t += nwaves) {
+    if (t < tiles_h) {
+      const int j = t / spr;
+      const int i = (t - j * spr) * 64 + l;
+      if (i < nx) h2d_point(R, i, j, step);
+    }
+    if (t >= tiles_m) continue;
     s4 xb[kInferG][2];
     float ev[kInferG], sv[kInferG];
     int kidx[kInferG];
 #pragma unroll
     for (int g = 0; g < kInferG; ++g) {
-      const int row = t * 64 + g * 16 + r0;
+      const int row = t * kWaveRows + g * 16 + r0;
       const int cell = row >> 1, comp = row & 1;
       float h[4] = {0.f, 0.f, 0.f, 0.f};
       float e = 0.f, m = 0.f, q1 = 0.f, q2 = 0.f;
@@ -567,7 +583,7 @@ __global__ __launch_bounds__(kInferWaves * 64) void k_mlp2d(const Run2D<float>* 
 #pragma unroll
       for (int g = 0; g < kInferG; ++g) {
         if (kidx[g] >= 0) {
-          const int row = t * 64 + g * 16 + r0;
+          const int row = t * kWaveRows + g * 16 + r0;
           const int cell = row >> 1;
           float* Jc = (row & 1) ? R.Jcy : R.Jcx;
           const float alpha = C.coef[4 * cell], beta = C.coef[4 * cell + 1];
@@ -579,9 +595,10 @@ __global__ __launch_bounds__(kInferWaves * 64) void k_mlp2d(const Run2D<float>* 
 }
 
 hipError_t mlp_launch_cells2d(const void* run, const MlpWeights& W, const MlpCells2D& C,
-                              int64_t step, hipStream_t st) {
-  if (C.n <= 0) return hipSuccess;
-  const int tiles = (2 * C.n + 63) / 64;
+                              int nx, int ny, int64_t step, hipStream_t st) {
+  const int tiles_m = (2 * C.n + kWaveRows - 1) / kWaveRows;
+  const int tiles_h = row_segments(nx, ny, 64);
+  const int tiles = tiles_m > tiles_h ? tiles_m : tiles_h;
   const int blocks = (tiles + kInferWaves - 1) / kInferWaves < 1024 ? (tiles + kInferWaves - 1) / kInferWaves : 1024;
   hipLaunchKernelGGL(k_mlp2d, dim3(blocks), dim3(kInferWaves * 64), 0, st,
                      static_cast<const Run2D<float>*>(run), W, C, step);
@@ -591,7 +608,7 @@ hipError_t mlp_launch_cells2d(const void* run, const MlpWeights& W, const MlpCel
 // --- host wrappers ---------------------------------------------------------------
 hipError_t mlp_launch_rows(const MlpWeights& W, const float* X, int n, float* Y, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  const int tiles = (n + 63) / 64;
+  const int tiles = (n + kWaveRows - 1) / kWaveRows;
   const int blocks = (tiles + kInferWaves - 1) / kInferWaves < 1024 ? (tiles + kInferWaves - 1) / kInferWaves : 1024;
   hipLaunchKernelGGL(k_mlp_rows, dim3(blocks), dim3(kInferWaves * 64), 0, st, W, X, n, Y);
   return hipGetLastError();

@@ -75,10 +75,7 @@ def run_pair(sim, orc, steps, every=50):
 
 
 def counts(sim):
-    import ctypes as C
-    a, b = C.c_int64(), C.c_int64()
-    B.check(B.lib().fdtd_plasma_closure_counts(sim.h, C.byref(a), C.byref(b)), "closure_counts")
-    return a.value, b.value
+    return sim.closure_counts()
 
 
 @pytest.mark.parametrize("hot", [False, True])
