@@ -105,31 +105,37 @@ def time_single(run, B, torch, steps, warmup, tile=0):
     return wall, ms
 
 
-def extra_workloads(B, W, torch, autotune):
-    out = {}
-    # 1D line with Nx = 2^20: F1 (1.07 GB) far above every cache
+def extra_c1l(B, W, torch, autotune):
+    """1D line with Nx = 2^20: F1 (1.07 GB) far above every cache."""
     run = W.c1_large()
     log(f"c1l: Nx={run.nx} plasma cells={run.plasma_cells}")
     tile = autotune.lookup(run, B.FP32) or autotune.lookup(W.c1(nx=4096, steps=1), B.FP32)
     wall, ms = time_single(run, B, torch, run.steps, 50, tile)
     by = bytes_1d(run)
-    out["c1_nx2e20"] = dict(workload="1D Yee + 1V kinetic, Nx=1048576, Nv=512, FP32, 2000 steps",
-                            updates_per_s=run.plasma_cells * run.nv * run.steps / wall,
-                            ms_per_step=wall / run.steps * 1e3, kernel_ms=ms,
-                            hbm_gbs=by / (ms * 1e-3) / 1e9,
-                            hbm_frac=by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
-    # 2D column
+    return {"c1_nx2e20": dict(workload="1D Yee + 1V kinetic, Nx=1048576, Nv=512, FP32, 2000 steps",
+                              updates_per_s=run.plasma_cells * run.nv * run.steps / wall,
+                              ms_per_step=wall / run.steps * 1e3, kernel_ms=ms,
+                              hbm_gbs=by / (ms * 1e-3) / 1e9,
+                              hbm_frac=by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)}
+
+
+def extra_c2(B, W, torch, autotune, steps=None):
+    """2D column, 512^2, 32x32 velocity bins."""
     run = W.c2()
+    steps = steps or run.steps
     log(f"c2: {run.nx}x{run.ny} plasma cells={run.plasma_cells}")
     tile = autotune.lookup(run, B.FP32)
-    wall, ms = time_single(run, B, torch, run.steps, 100, tile)
+    wall, ms = time_single(run, B, torch, steps, 100, tile)
     by = bytes_2d(run)
-    out["c2"] = dict(workload="2D TEz 512x512 + 2V kinetic 32x32, FP32, 4000 steps",
-                     updates_per_s=run.plasma_cells * run.nv ** 2 * run.steps / wall,
-                     ms_per_step=wall / run.steps * 1e3, step_ms=ms,
-                     hbm_gbs=by / (ms * 1e-3) / 1e9,
-                     hbm_frac=by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
-    # batch of 256 uneven runs, one persistent launch
+    return {"c2": dict(workload=f"2D TEz 512x512 + 2V kinetic 32x32, FP32, {steps} steps",
+                       updates_per_s=run.plasma_cells * run.nv ** 2 * steps / wall,
+                       ms_per_step=wall / steps * 1e3, step_ms=ms,
+                       hbm_gbs=by / (ms * 1e-3) / 1e9,
+                       hbm_frac=by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)}
+
+
+def extra_c3(B, W, torch):
+    """Batch of 256 uneven 1D runs."""
     runs = W.c3()
     work = sum(r.plasma_cells * r.nv * r.steps for r in runs)
     by = sum(bytes_1d(r) * r.steps for r in runs)
@@ -142,10 +148,39 @@ def extra_workloads(B, W, torch, autotune):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     sim.close()
-    out["c3"] = dict(workload="256 independent 1D runs, Nx in [500, 20000], Nv in {64,128,256}, "
-                              "2 Nx steps each, one persistent launch",
-                     updates_per_s=work / wall, seconds=wall, hbm_gbs=by / wall / 1e9,
-                     hbm_frac=by / wall / 1e9 / HBM_PEAK_GBS)
+    return {"c3": dict(workload="256 independent 1D runs, Nx in [500, 20000], Nv in {64,128,256}, "
+                                "2 Nx steps each",
+                       updates_per_s=work / wall, seconds=wall, hbm_gbs=by / wall / 1e9,
+                       hbm_frac=by / wall / 1e9 / HBM_PEAK_GBS)}
+
+
+def c4_steps(B, W, torch, steps):
+    """The 4096^2 blob workload for a few steps, kinetic and with a closure network of
+    freshly initialised weights (the same instruction stream as a trained one; for
+    profiling without the training kernels)."""
+    from paper_2211_05647_amd import closure as CL
+    run = W.c4()
+    dt = run.courant * run.dx / 299792458.0
+    blob = CL.make_blob(CL.init_params(3), (0.0, 1.0, -6.0, 1.0), dt)
+    res = {}
+    for name, kw in (("kinetic", dict()), ("closure", dict(closure=B.CLOSURE_MLP, mlp_blob=blob))):
+        sim = B.Sim(run, precision=B.FP32, **kw)
+        sim.run(steps)
+        torch.cuda.synchronize()
+        res[name + "_ms_per_step"] = sim.last_run_ms()
+        by = bytes_2d(run)
+        if name == "kinetic":
+            res["kinetic_hbm_frac"] = by / (res["kinetic_ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS
+        sim.close()
+        torch.cuda.empty_cache()
+    return {"c4_steps": res}
+
+
+def extra_workloads(B, W, torch, autotune):
+    out = {}
+    out.update(extra_c1l(B, W, torch, autotune))
+    out.update(extra_c2(B, W, torch, autotune))
+    out.update(extra_c3(B, W, torch))
     out.update(closure_speedup(B, W, torch))
     return out
 
@@ -213,8 +248,9 @@ def main():
     ap.add_argument("--quick", action="store_true", help="only the headline workload")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true")
-    ap.add_argument("--only", choices=["closure"], default=None,
-                    help="run only one of the extra measurements (for profiling)")
+    ap.add_argument("--only", choices=["c1l", "c2", "c3", "closure", "c4"], default=None,
+                    help="run only one of the extra measurements (for profiling); c2 and c4 "
+                         "take --steps steps")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the kinetic-FDTD path here runs on a single "
@@ -229,8 +265,13 @@ def main():
     from paper_2211_05647_amd import autotune
     from paper_2211_05647_amd import binding as B
     from paper_2211_05647_amd import workloads as W
-    if args.only == "closure":
-        print(json.dumps(closure_speedup(B, W, torch)), flush=True)
+    if args.only:
+        only = {"c1l": lambda: extra_c1l(B, W, torch, autotune),
+                "c2": lambda: extra_c2(B, W, torch, autotune, args.steps),
+                "c3": lambda: extra_c3(B, W, torch),
+                "closure": lambda: closure_speedup(B, W, torch),
+                "c4": lambda: c4_steps(B, W, torch, args.steps)}[args.only]
+        print(json.dumps(only()), flush=True)
         return
 
     run = W.c1()

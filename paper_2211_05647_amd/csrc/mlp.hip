@@ -572,7 +572,8 @@ __global__ __launch_bounds__(kInferWaves * 64) void k_mlp2d(const Run2D<float>* 
       m = fmaxf(m, __shfl_xor(m, 16));
       m = fmaxf(m, __shfl_xor(m, 32));
       const float sc = fmaxf(m, 1e-30f);
-      xb[g][0] = pack4(h[0] / sc, h[1] / sc, h[2] / sc, h[3] / sc);
+      const float rs = 1.0f / sc;   // features h / s as h * (1 / s): within 1 ulp, then bf16
+      xb[g][0] = pack4(h[0] * rs, h[1] * rs, h[2] * rs, h[3] * rs);
       xb[g][1] = kq == 0 ? pack4(q1, q2, 0.f, 0.f) : pack4(0.f, 0.f, 0.f, 0.f);
       ev[g] = e;
       sv[g] = sc;
