@@ -228,15 +228,24 @@ def closure_speedup(B, W, torch, steps=50):
 
 
 def calibrate_copy(torch):
-    """Plain device copies of known size: 5 x 1 GiB read + 1 GiB written."""
+    """Plain device copies of known size: 10 x (1 GiB read + 1 GiB written); the last five
+    are timed (the read + write rate a streaming kernel can reach on this device)."""
     n = 1 << 28
     a = torch.ones(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     for _ in range(5):
         b.copy_(a)
     torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(5):
+        b.copy_(a)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / 5
     print(json.dumps({"copy_bytes_read_per_launch": n * 4, "copy_bytes_written_per_launch": n * 4,
-                      "launches": 5}), flush=True)
+                      "launches": 10, "copy_ms": ms,
+                      "copy_read_plus_write_gbs": 2 * n * 4 / (ms * 1e-3) / 1e9}), flush=True)
 
 
 def main():

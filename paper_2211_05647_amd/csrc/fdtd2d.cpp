@@ -275,10 +275,11 @@ void set_grid(Host2D* h) {
 }  // namespace
 
 template <class T>
-hipError_t launch_step2d_t(const void* run, int nbk, int nbh, int nbe, int64_t step,
+hipError_t launch_step2d_t(const void* run, int half, int nbk, int nbh, int nbe, int64_t step,
                            hipStream_t stream);
-hipError_t launch_step2d_closure(const void* run, int nbk, int nx, int ny, int nbe, int64_t step,
-                                 hipStream_t stream, const MlpWeights& W, const MlpCells2D& C);
+hipError_t launch_step2d_closure(const void* run, int half, int nbk, int nx, int ny, int nbe,
+                                 int64_t step, hipStream_t stream, const MlpWeights& W,
+                                 const MlpCells2D& C);
 
 int validate_2d(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s) {
   if (!g || !p) return fail(FDTD_EINVAL, "null grid or profile");
@@ -432,10 +433,11 @@ int upload_2d(Host2D* h, char* ws, hipStream_t stream, const std::vector<ProbeIn
 
 hipError_t launch_step2d(Host2D* h, int64_t step, hipStream_t stream) {
   const void* run = h->ws + h->off_run;
-  if (h->es == 8) return launch_step2d_t<double>(run, h->nbk, h->nbh, h->nbe, step, stream);
+  if (h->es == 8) return launch_step2d_t<double>(run, h->half, h->nbk, h->nbh, h->nbe, step, stream);
   if (h->C.n > 0)
-    return launch_step2d_closure(run, h->nbk, h->nx, h->ny, h->nbe, step, stream, h->W, h->C);
-  return launch_step2d_t<float>(run, h->nbk, h->nbh, h->nbe, step, stream);
+    return launch_step2d_closure(run, h->half, h->nbk, h->nx, h->ny, h->nbe, step, stream, h->W,
+                                 h->C);
+  return launch_step2d_t<float>(run, h->half, h->nbk, h->nbh, h->nbe, step, stream);
 }
 
 int closure_counts_2d(const Host2D* h, int64_t* nm, int64_t* nk) {

@@ -126,17 +126,139 @@ __device__ __forceinline__ void kinetic2d_block(const Run2D<T>& R, int c0, int c
   }
 }
 
-template <class T>
+// FP32 2V kinetic step specialised for NV bins per axis (NV = 8, 16 or 32): every size is
+// a compile-time constant, so the update of a lane's chunks is straight-line code.
+//   A cell's row of NV*NV/2 stored values is CH float4 chunks; L lanes share a cell, lane
+//   li owning the C chunks li + L m (m < C), so one load instruction of the wavefront
+//   reads L consecutive chunks of each of its G cells.  Chunk li + L m lies in vx row
+//   a(li) + m NV/C at the same four vy bins for every m, so the FP64 moment weights are
+//   C values of vx and 4 values of vy per lane.
+//   FP64 moments: each lane accumulates (Jx, Jy) over its 4 C values; a reduce-scatter
+//   over the L lanes leaves Jx on lane 0 and Jy on lane L/2 of the group.
+//   The next cell's row and scalars are loaded before the current cell is updated, so
+//   every wavefront keeps two rows in flight.
+constexpr int kKin2vChunks = 4;       // C: float4 chunks per lane
+constexpr bool kKin2vPrefetch = true;
+
+struct Kin2vCell {
+  int k;          // grid index of the cell
+  float nex, ney, tau;
+};
+
+template <int NV, int C>
+__device__ __forceinline__ void kin2v_load(const Run2D<float>& R, int c, bool ok, int li,
+                                           float4 (&f)[C], Kin2vCell& q) {
+  constexpr int CH = NV * NV / 8, L = CH / C;
+  if (ok) {
+    const int nx = R.nx;
+    const int k = R.cell_idx[c];
+    const int j = k / nx, i = k - j * nx;
+    const float ne = R.dens[c];
+    q.k = k;
+    q.nex = ne * (0.5f * (R.Ex[(size_t)j * nx + i] + R.Ex[(size_t)(j + 1) * nx + i]));
+    q.ney = ne * (0.5f * (R.Ey[(size_t)j * (nx + 1) + i] + R.Ey[(size_t)j * (nx + 1) + i + 1]));
+    q.tau = R.tau[c];
+    const float4* row = reinterpret_cast<const float4*>(R.df) + (size_t)c * CH;
+#pragma unroll
+    for (int m = 0; m < C; ++m) f[m] = row[li + L * m];
+  } else {
+    q.k = 0;
+    q.nex = q.ney = q.tau = 0.f;
+#pragma unroll
+    for (int m = 0; m < C; ++m) f[m] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+
+template <int NV, int C, bool PF>
+__device__ __forceinline__ void kinetic2v_f32(const Run2D<float>& R, int c0, int c1) {
+  constexpr int CH = NV * NV / 8;
+  constexpr int L = CH / C;
+  constexpr int G = 64 / L;
+  constexpr int kWaves = kBlock / 64;
+  static_assert(L >= 2 && L <= 64 && CH % C == 0, "kinetic2v_f32 layout");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane / L, li = lane - g * L;
+  float4 s[C], bx[C], by[C];
+  double wx[C], wy[4];
+#pragma unroll
+  for (int m = 0; m < C; ++m) {
+    const int k = li + L * m;
+    s[m] = reinterpret_cast<const float4*>(R.s_bin)[k];
+    bx[m] = reinterpret_cast<const float4*>(R.bx_bin)[k];
+    by[m] = reinterpret_cast<const float4*>(R.by_bin)[k];
+    wx[m] = R.wx_bin[4 * k];
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) wy[e] = R.wy_bin[4 * li + e];
+  float4* __restrict__ dfv = reinterpret_cast<float4*>(R.df);
+  int base = c0 + wave * G;
+  float4 f[C];
+  Kin2vCell q;
+  if (PF) kin2v_load<NV, C>(R, base + g, base + g < c1, li, f, q);
+  for (; base < c1; base += kWaves * G) {
+    const int c = base + g;
+    const bool ok = c < c1;
+    float4 fn_[C];
+    Kin2vCell qn;
+    if (PF) {
+      const int cn = c + kWaves * G;
+      kin2v_load<NV, C>(R, cn, cn < c1, li, fn_, qn);
+    } else {
+      kin2v_load<NV, C>(R, c, ok, li, f, q);
+    }
+    double ax = 0.0, ay = 0.0;
+#pragma unroll
+    for (int m = 0; m < C; ++m) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float x = q.tau * lane_at(s[m], e);
+        const float r = cn_recip(2.f + x);
+        const float fv = lane_at(f[m], e);
+        const float drive = fmaf(lane_at(bx[m], e), q.nex, lane_at(by[m], e) * q.ney);
+        const float fn = fmaf(fmaf(-(x + x), fv, drive), r, fv);
+        lane_at(f[m], e) = fn;
+        ax = fma(wx[m], (double)fn, ax);
+        ay = fma(wy[e], (double)fn, ay);
+      }
+    }
+    if (ok) {
+      float4* row = dfv + (size_t)c * CH;
+#pragma unroll
+      for (int m = 0; m < C; ++m) row[li + L * m] = f[m];
+    }
+    // reduce-scatter of (ax, ay) over the L lanes of the group
+    const bool hi = (li & (L / 2)) != 0;
+    double keep = hi ? ay : ax;
+    keep += __shfl_xor(hi ? ax : ay, L / 2);
+#pragma unroll
+    for (int o = L / 4; o > 0; o >>= 1) keep += __shfl_xor(keep, o);
+    if (ok && li == 0) R.Jcx[q.k] = (float)keep;
+    if (ok && li == L / 2) R.Jcy[q.k] = (float)keep;
+    if (PF) {
+#pragma unroll
+      for (int m = 0; m < C; ++m) f[m] = fn_[m];
+      q = qn;
+    }
+  }
+}
+
+// NV > 0: FP32 with NV bins per velocity axis (the specialised kinetic path); NV = 0: any
+// bin count and precision.
+template <class T, int NV>
 __global__ __launch_bounds__(kBlock) void k_h2d_kin(const Run2D<T>* __restrict__ rp, int64_t step) {
   const Run2D<T>& R = *rp;
   if ((int)blockIdx.x < R.nbk) {
     const int c0 = blockIdx.x * R.cells_per_block;
     const int c1 = min(R.ncell, c0 + R.cells_per_block);
-    const int ch = R.half / Vec<T>::n;
-    const int cpl = ch < 64 ? 1 : ch / 64;
-    if (cpl == 1) kinetic2d_block<T, 4>(R, c0, c1);
-    else if (cpl == 2) kinetic2d_block<T, 2>(R, c0, c1);
-    else kinetic2d_block<T, 1>(R, c0, c1);
+    if constexpr (NV > 0) {
+      kinetic2v_f32<NV, kKin2vChunks, kKin2vPrefetch>(R, c0, c1);
+    } else {
+      const int ch = R.half / Vec<T>::n;
+      const int cpl = ch < 64 ? 1 : ch / 64;
+      if (cpl == 1) kinetic2d_block<T, 4>(R, c0, c1);
+      else if (cpl == 2) kinetic2d_block<T, 2>(R, c0, c1);
+      else kinetic2d_block<T, 1>(R, c0, c1);
+    }
     return;
   }
   // Hz: one row segment of kBlock points per block
@@ -157,12 +279,33 @@ __global__ __launch_bounds__(kBlock) void k_e2d(const Run2D<T>* __restrict__ rp,
   if (j <= R.ny && i <= R.nx) e2d_point(R, i, j, step);
 }
 
+// H + kinetic launch, picking the kinetic path by the stored bins per cell
 template <class T>
-hipError_t launch_step2d_t(const void* run, int nbk, int nbh, int nbe, int64_t step,
+hipError_t launch_h2d_kin(const Run2D<T>* r, int half, int grid, int64_t step, hipStream_t stream) {
+  if (grid <= 0) return hipSuccess;
+  if constexpr (sizeof(T) == 4) {
+    if (half == 32) {
+      hipLaunchKernelGGL((k_h2d_kin<T, 8>), dim3(grid), dim3(kBlock), 0, stream, r, step);
+      return hipGetLastError();
+    }
+    if (half == 128) {
+      hipLaunchKernelGGL((k_h2d_kin<T, 16>), dim3(grid), dim3(kBlock), 0, stream, r, step);
+      return hipGetLastError();
+    }
+    if (half == 512) {
+      hipLaunchKernelGGL((k_h2d_kin<T, 32>), dim3(grid), dim3(kBlock), 0, stream, r, step);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_h2d_kin<T, 0>), dim3(grid), dim3(kBlock), 0, stream, r, step);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_step2d_t(const void* run, int half, int nbk, int nbh, int nbe, int64_t step,
                            hipStream_t stream) {
   const Run2D<T>* r = static_cast<const Run2D<T>*>(run);
-  hipLaunchKernelGGL(k_h2d_kin<T>, dim3(nbk + nbh), dim3(kBlock), 0, stream, r, step);
-  hipError_t e = hipGetLastError();
+  hipError_t e = launch_h2d_kin(r, half, nbk + nbh, step, stream);
   if (e) return e;
   hipLaunchKernelGGL(k_e2d<T>, dim3(nbe), dim3(kBlock), 0, stream, r, step);
   return hipGetLastError();
@@ -174,22 +317,19 @@ hipError_t mlp_launch_cells2d(const void* run, const MlpWeights& W, const MlpCel
 // Closure step: kinetic blocks for the fallback cells (if any), then one launch that runs
 // the network of every closure cell and the Hz update side by side (both only read E^n,
 // and the network's arithmetic hides the field update's memory traffic), then E.
-hipError_t launch_step2d_closure(const void* run, int nbk, int nx, int ny, int nbe, int64_t step,
-                                 hipStream_t stream, const MlpWeights& W, const MlpCells2D& C) {
+hipError_t launch_step2d_closure(const void* run, int half, int nbk, int nx, int ny, int nbe,
+                                 int64_t step, hipStream_t stream, const MlpWeights& W,
+                                 const MlpCells2D& C) {
   const Run2D<float>* r = static_cast<const Run2D<float>*>(run);
-  hipError_t e;
-  if (nbk > 0) {
-    hipLaunchKernelGGL(k_h2d_kin<float>, dim3(nbk), dim3(kBlock), 0, stream, r, step);
-    e = hipGetLastError();
-    if (e) return e;
-  }
+  hipError_t e = launch_h2d_kin(r, half, nbk, step, stream);
+  if (e) return e;
   e = mlp_launch_cells2d(run, W, C, nx, ny, step, stream);
   if (e) return e;
   hipLaunchKernelGGL(k_e2d<float>, dim3(nbe), dim3(kBlock), 0, stream, r, step);
   return hipGetLastError();
 }
 
-template hipError_t launch_step2d_t<float>(const void*, int, int, int, int64_t, hipStream_t);
-template hipError_t launch_step2d_t<double>(const void*, int, int, int, int64_t, hipStream_t);
+template hipError_t launch_step2d_t<float>(const void*, int, int, int, int, int64_t, hipStream_t);
+template hipError_t launch_step2d_t<double>(const void*, int, int, int, int, int64_t, hipStream_t);
 
 }  // namespace fdtdp
