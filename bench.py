@@ -28,15 +28,16 @@ HBM_PEAK_GBS = 8000.0
 
 def kernel_hash():
     h = hashlib.sha256()
-    for f in ("common.h", "kernels1d.hip"):
+    for f in ("common.h", "kernels1d.hip", "kernels1d_tb.hip"):
         h.update(open(os.path.join(ROOT, "paper_2211_05647_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def pmc_traffic():
+def pmc_traffic(kb=1):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
     on the kernel as it is now (else None)."""
-    p = os.path.join(ROOT, "profiles", "k_step1d_c1_pmc.json")
+    name = "k_step1d_tb_c1_pmc.json" if kb > 1 else "k_step1d_c1_pmc.json"
+    p = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
@@ -88,7 +89,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def time_single(run, B, torch, steps, warmup, tile=0):
+def time_single(run, B, torch, steps, warmup, tile=0, info=None):
     sim = B.Sim(run, precision=B.FP32, tile=tile)
     sim.run(warmup)
     torch.cuda.synchronize()
@@ -101,8 +102,18 @@ def time_single(run, B, torch, steps, warmup, tile=0):
         sim.read(B.F_EY)
     else:
         sim.read(B.F_E)
+        if info is not None:
+            info["time_block"], info["rows_per_launch"] = sim.time_block(rows=True)
     sim.close()
     return wall, ms
+
+
+def bytes_1d_blocked(run, rows):
+    """Algorithmic bytes of one launch of the temporally blocked kernel (K steps): the F1
+    rows it reads (owned + halo) with their per-cell scalars, the owned rows written
+    back, the fields read and written once per launch."""
+    half, nx = run.nv // 2, run.nx
+    return rows * (half * 4 + 12) + run.plasma_cells * half * 4 + (nx + 1) * 4 * 5
 
 
 def extra_c1l(B, W, torch, autotune):
@@ -110,13 +121,17 @@ def extra_c1l(B, W, torch, autotune):
     run = W.c1_large()
     log(f"c1l: Nx={run.nx} plasma cells={run.plasma_cells}")
     tile = autotune.lookup(run, B.FP32) or autotune.lookup(W.c1(nx=4096, steps=1), B.FP32)
-    wall, ms = time_single(run, B, torch, run.steps, 50, tile)
-    by = bytes_1d(run)
+    info = {}
+    wall, ms = time_single(run, B, torch, run.steps, 50, tile, info)
+    kb = info.get("time_block", 1)
+    by = bytes_1d_blocked(run, info["rows_per_launch"]) / kb if kb > 1 else bytes_1d(run)
     return {"c1_nx2e20": dict(workload="1D Yee + 1V kinetic, Nx=1048576, Nv=512, FP32, 2000 steps",
                               updates_per_s=run.plasma_cells * run.nv * run.steps / wall,
-                              ms_per_step=wall / run.steps * 1e3, kernel_ms=ms,
+                              ms_per_step=wall / run.steps * 1e3, kernel_ms_per_step=ms,
+                              steps_per_launch=kb,
                               hbm_gbs=by / (ms * 1e-3) / 1e9,
-                              hbm_frac=by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)}
+                              hbm_frac=by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                              one_step_stream_equivalent_gbs=bytes_1d(run) / (ms * 1e-3) / 1e9)}
 
 
 def extra_c2(B, W, torch, autotune, steps=None):
@@ -287,12 +302,22 @@ def main():
     log(f"workload c1: Nx={run.nx} Nv={run.nv} plasma cells={run.plasma_cells}")
     tile = args.tile or autotune.lookup(run, B.FP32)
     log(f"tile={tile or 'default'}")
-    wall, ms_dev = time_single(run, B, torch, args.steps, args.warmup, tile)
+    info = {}
+    wall, ms_dev = time_single(run, B, torch, args.steps, args.warmup, tile, info)
 
     ncell, nv, half, nx = run.plasma_cells, run.nv, run.nv // 2, run.nx
     value = ncell * nv * args.steps / wall
-    bytes_alg = bytes_1d(run)
-    achieved = bytes_alg / (ms_dev * 1e-3) / 1e9
+    kb = info.get("time_block", 1)
+    if kb > 1:
+        # one launch = kb steps of the temporally blocked kernel
+        kernel = f"k_step1d_tb<{kb}, {half // 4}>"
+        bytes_alg = bytes_1d_blocked(run, info["rows_per_launch"])
+        launch_ms = ms_dev * kb
+    else:
+        kernel = "k_step1d<float>"
+        bytes_alg = bytes_1d(run)
+        launch_ms = ms_dev
+    achieved = bytes_alg / (launch_ms * 1e-3) / 1e9
     out = {
         "metric": "kinetic-FDTD phase-space updates/s",
         "value": value,
@@ -308,12 +333,13 @@ def main():
         "data": "synthetic, seeded",
         "config": {"workload": "1D Yee + 1V kinetic, Nx=65536, Nv=512, FP32",
                    "nx": nx, "nv": nv, "plasma_cells": ncell, "steps": args.steps,
-                   "tile": tile},
+                   "tile": tile, "steps_per_launch": kb},
         "stored_bin_updates_per_s": ncell * half * args.steps / wall,
-        "roofline": {"bound": "hbm", "kernel": "k_step1d<float>", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": kernel, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": pmc_traffic(), "bytes_per_launch": bytes_alg,
-                     "launch_ms": ms_dev},
+                     "traffic": pmc_traffic(kb), "bytes_per_launch": bytes_alg,
+                     "launch_ms": launch_ms,
+                     "one_step_stream_equivalent_gbs": bytes_1d(run) / (ms_dev * 1e-3) / 1e9},
         "context": "paper: MATLAB plasma code ~20x GPU (GTX 1050) over serial CPU (i7-7700HQ)",
     }
     if not args.quick:

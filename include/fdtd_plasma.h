@@ -204,6 +204,20 @@ int fdtd_plasma_load_state(fdtd_plasma *h, const void *src, size_t len);
  * first step. */
 int fdtd_plasma_set_tiling(fdtd_plasma *h, int32_t tile, int32_t cells_per_group);
 
+/* Temporal blocking of a single 1D run in FP32 storage with Nv in {64, 128, 256, 512}:
+ * fdtd_plasma_run advances `steps` time steps per kernel launch (each work-group
+ * recomputes a halo of `steps` nodes per side, so F1 crosses HBM once per `steps` steps)
+ * and the remainder one step per launch.  steps = 1 turns it off; 3, 5, 7 and 9 are accepted.
+ * Results are bitwise those of one-step launches (the kinetic step is local in space, see
+ * section 5.2).  Default 7.  Other runs (FP64, batches, 2D, other Nv, lines too short to
+ * cut into blocks) always step one step per launch; the call then only records the value.
+ * May be called between runs.  fdtd_plasma_time_block reports the steps per launch in
+ * effect (1 when the run is not blocked) and, if rows_per_launch is not NULL, the number of
+ * F1 rows one blocked launch reads (owned rows plus the halo rows it recomputes; 0 when
+ * not blocked). */
+int fdtd_plasma_set_time_block(fdtd_plasma *h, int32_t steps);
+int fdtd_plasma_time_block(const fdtd_plasma *h, int32_t *steps, int64_t *rows_per_launch);
+
 /* Average device time per step of the last fdtd_plasma_run, measured with HIP events
  * on the handle's stream (synchronises). */
 int fdtd_plasma_last_run_ms(fdtd_plasma *h, double *ms_per_step);

@@ -63,6 +63,8 @@ _SIGS = {
     "fdtd_plasma_read_taps": ([C.c_void_p, C.c_int32, _dp, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
     "fdtd_plasma_run_status": ([C.c_void_p, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
     "fdtd_plasma_closure_counts": ([C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
+    "fdtd_plasma_set_time_block": ([C.c_void_p, C.c_int32], C.c_int),
+    "fdtd_plasma_time_block": ([C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int64)], C.c_int),
     "fdtd_plasma_step": ([C.c_void_p], C.c_int),
     "fdtd_plasma_run": ([C.c_void_p, C.c_int64], C.c_int),
     "fdtd_plasma_steps": ([C.c_void_p, C.POINTER(C.c_int64)], C.c_int),
@@ -144,7 +146,7 @@ class Sim:
 
     def __init__(self, workload, precision=FP32, device=0, max_probes=0, probe_capacity=0,
                  closure=CLOSURE_KINETIC, mlp_blob=None, tile=0, cells_per_group=0,
-                 taps=None, batch_mode=None, groups=0):
+                 taps=None, batch_mode=None, groups=0, time_block=None):
         import torch
         self.torch = torch
         L = lib()
@@ -214,6 +216,8 @@ class Sim:
             check(L.fdtd_plasma_set_batch_mode(self.h, mode, groups), "set_batch_mode")
         if tile or cells_per_group:
             check(L.fdtd_plasma_set_tiling(self.h, tile, cells_per_group), "set_tiling")
+        if time_block is not None:
+            self.set_time_block(time_block)
 
     def close(self):
         if getattr(self, "h", None):
@@ -280,6 +284,16 @@ class Sim:
         st = C.c_int32()
         check(lib().fdtd_plasma_run_status(self.h, run, C.byref(st)), "run_status")
         return st.value
+
+    def set_time_block(self, steps):
+        """Steps per launch of a single FP32 1D run (1 = one step per launch)."""
+        check(lib().fdtd_plasma_set_time_block(self.h, int(steps)), "set_time_block")
+
+    def time_block(self, rows=False):
+        """Steps per launch in effect; with rows=True also the F1 rows one launch reads."""
+        v, r = C.c_int32(), C.c_int64()
+        check(lib().fdtd_plasma_time_block(self.h, C.byref(v), C.byref(r)), "time_block")
+        return (v.value, r.value) if rows else v.value
 
     def closure_counts(self):
         """(closure cells, kinetic cells) of a 2D run with the learned closure."""

@@ -176,6 +176,11 @@ struct fdtd_plasma {
   std::vector<int64_t> tile_limit;   // step limit of each tile, non-increasing
   size_t order_off = 0, queue_off = 0, status_off = 0;
   int batch_mode = 1, batch_groups = 0, ntap = 0;   // batch default: per-step launches
+  // temporal blocking of a single FP32 1D run: time_block steps per launch (1 = off)
+  int time_block = kDefaultTimeBlock;
+  size_t tbtiles_off = 0;
+  int ntbtiles = 0;
+  int64_t tb_rows = 0;     // F1 rows one blocked launch reads (owned plus halo)
   // probes
   int max_probes = 0, probe_cap = 0;
   size_t probe_off = 0;
@@ -231,6 +236,8 @@ size_t layout_1d(fdtd_plasma* h, const std::vector<RunSpec1D>& specs, int precis
   size_t max_tiles = 0;
   for (auto& x : hs) max_tiles += (size_t)(x.nx + 1 + 31) / 32;
   const size_t tiles_off = cv.take(max_tiles * sizeof(Tile1D));
+  // tiles of the temporally blocked kernel (single runs; never narrower than 32 nodes)
+  const size_t tbtiles_off = cv.take((specs.size() == 1 ? max_tiles : 1) * sizeof(Tile1D));
   const size_t order_off = cv.take(sz<int32_t>(specs.size()));
   const size_t queue_off = cv.take(sz<int32_t>(1));
   const size_t status_off = cv.take(sz<int32_t>(specs.size()));
@@ -243,6 +250,7 @@ size_t layout_1d(fdtd_plasma* h, const std::vector<RunSpec1D>& specs, int precis
     h->probe_off = probe_off;
     h->runs_off = runs_off;
     h->tiles_off = tiles_off;
+    h->tbtiles_off = tbtiles_off;
   }
   if (out) *out = hs;
   return cv.size() + 256;
@@ -361,6 +369,50 @@ int upload_1d(fdtd_plasma* h) {
   return FDTD_OK;
 }
 
+// Tiles of the temporally blocked kernel: owned ranges of W nodes whose extended range
+// (W + 2K nodes, clipped to the line) fits one work-group; W is chosen so that the tiles
+// fill the device in as few rounds of resident work-groups as possible.
+int build_tb_tiles(fdtd_plasma* h) {
+  h->ntbtiles = 0;
+  const int k = h->time_block;
+  if (k < 3 || h->nruns != 1 || h->precision != FDTD_FP32) return FDTD_OK;
+  const Host1D& x = h->h1[0];
+  if (!tb_supported(x.half)) return FDTD_OK;
+  const int cap = std::min(tb_block(), tb_max_rows(x.half));
+  const int wmax = cap - 2 * k;
+  const int nodes = x.nx + 1;
+  if (wmax < 32 || nodes < 4 * wmax) return FDTD_OK;
+  int cus = 256;
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
+  const int conc = std::max(1, cus * tb_blocks_per_cu(k, x.half));
+  const int rounds = (nodes + conc * wmax - 1) / (conc * wmax);
+  const int w = std::max(32, std::min(wmax, (nodes + rounds * conc - 1) / (rounds * conc)));
+  std::vector<Tile1D> tiles;
+  int c0 = 0, c1 = 0;
+  for (int n0 = 0; n0 < nodes; n0 += w) {
+    Tile1D t;
+    t.run = 0;
+    t.node0 = n0;
+    t.node1 = std::min(nodes, n0 + w);
+    const int lo = std::max(0, n0 - k), hi = std::min(nodes, t.node1 + k);
+    while (c0 < x.ncell && x.cell_node[c0] < lo) ++c0;
+    c1 = std::max(c1, c0);
+    while (c1 < x.ncell && x.cell_node[c1] < hi) ++c1;
+    t.cell0 = c0;
+    t.cell1 = c1;
+    if (c1 - c0 > cap) return FDTD_OK;   // cannot happen (one cell per node), stay unblocked
+    tiles.push_back(t);
+  }
+  int64_t rows = 0;
+  for (const Tile1D& t : tiles) rows += t.cell1 - t.cell0;
+  hipError_t e = hipMemcpyAsync(h->ws + h->tbtiles_off, tiles.data(), tiles.size() * sizeof(Tile1D),
+                                hipMemcpyHostToDevice, h->stream);
+  if (e) return hip_fail(e, "upload blocked tiles");
+  h->ntbtiles = (int)tiles.size();
+  h->tb_rows = rows;
+  return FDTD_OK;
+}
+
 int build_tiles_1d(fdtd_plasma* h) {
   std::vector<std::pair<int64_t, Tile1D>> all;
   for (int r = 0; r < h->nruns; ++r) {
@@ -405,7 +457,7 @@ int build_tiles_1d(fdtd_plasma* h) {
   e = hipMemcpyAsync(h->ws + h->order_off, order.data(), order.size() * 4, hipMemcpyHostToDevice,
                      h->stream);
   if (e) return hip_fail(e, "upload run order");
-  return FDTD_OK;
+  return build_tb_tiles(h);
 }
 
 int batch_groups(const fdtd_plasma* h) {
@@ -644,7 +696,17 @@ int fdtd_plasma_run(fdtd_plasma* h, int64_t nsteps) {
     if (e) return hip_fail(e, "launch persistent batch kernel");
     nsteps_loop = 0;
   }
-  for (int64_t k = 0; k < nsteps_loop; ++k) {
+  int64_t k0 = 0;
+  if (h->dims == 1 && h->ntbtiles > 0) {
+    // K steps per launch while at least K remain; the rest one step per launch
+    const int kb = h->time_block;
+    for (; k0 + kb <= nsteps_loop; k0 += kb) {
+      e = launch_step1d_tb(h->ws + h->runs_off, h->ws + h->tbtiles_off, h->ntbtiles, h->step + k0,
+                           kb, h->h1[0].half, h->stream);
+      if (e) return hip_fail(e, "launch blocked step kernel");
+    }
+  }
+  for (int64_t k = k0; k < nsteps_loop; ++k) {
     const int64_t s = h->step + k;
     if (h->dims == 1) {
       // active tiles: those whose run still has steps left (limits are non-increasing)
@@ -945,6 +1007,25 @@ int fdtd_plasma_set_tiling(fdtd_plasma* h, int32_t tile, int32_t cells_per_group
     return e ? hip_fail(e, "synchronise") : FDTD_OK;
   }
   return set_tiling_2d(h->h2, h->ws, h->stream, tile, cells_per_group);
+}
+
+int fdtd_plasma_set_time_block(fdtd_plasma* h, int32_t steps) {
+  if (!h) return fail(FDTD_EINVAL, "null handle");
+  if (steps != 1 && steps != 3 && steps != 5 && steps != 7 && steps != 9)
+    return fail(FDTD_EINVAL, "steps per pass must be 1, 3, 5, 7 or 9 (got %d)", steps);
+  if (h->dims != 1) return FDTD_OK;
+  h->time_block = steps;
+  int rc = build_tb_tiles(h);
+  if (rc) return rc;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  return e ? hip_fail(e, "synchronise") : FDTD_OK;
+}
+
+int fdtd_plasma_time_block(const fdtd_plasma* h, int32_t* steps, int64_t* rows_per_launch) {
+  if (!h || !steps) return fail(FDTD_EINVAL, "null argument");
+  *steps = h->ntbtiles > 0 ? h->time_block : 1;
+  if (rows_per_launch) *rows_per_launch = h->ntbtiles > 0 ? h->tb_rows : 0;
+  return FDTD_OK;
 }
 
 void fdtd_plasma_destroy(fdtd_plasma* h) {

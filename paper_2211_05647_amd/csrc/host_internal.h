@@ -69,6 +69,15 @@ hipError_t launch_batch1d_persistent(const void* runs, const int32_t* order, int
                                      int32_t* queue, int64_t s0, int64_t s1, int groups,
                                      hipStream_t stream);
 
+// Temporally blocked 1D launch (kernels1d_tb.hip): k steps of every tile of one FP32 run.
+constexpr int kDefaultTimeBlock = 7;
+bool tb_supported(int half);             // stored bins per node the blocked kernel handles
+int tb_block();                          // threads per work-group = largest extended range
+int tb_max_rows(int half);               // plasma rows one work-group holds
+int tb_blocks_per_cu(int k, int half);   // resident work-groups per compute unit
+hipError_t launch_step1d_tb(const void* runs, const void* tiles, int ntiles, int64_t step, int k,
+                            int half, hipStream_t stream);
+
 // 2D TEz (fdtd2d.cpp / kernels2d.hip)
 struct Host2D;
 int validate_2d(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s);

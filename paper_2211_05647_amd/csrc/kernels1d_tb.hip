@@ -1,0 +1,292 @@
+// kernels1d_tb.hip -- K leap-frog steps of the 1D (Ez, Hy) Yee line with the 1V kinetic
+// F1 of every plasma node per launch (arXiv 2211.05647, section 2 and section 5.2):
+// temporal blocking with halo recomputation.
+//
+// The kinetic step has no spatial coupling (the model carries no streaming term), so a
+// node's state after K steps depends only on the fields and F1 within K nodes of it.  A
+// work-group owns nodes [node0, node1) and loads the fields of the extended range
+// [node0 - K, node1 + K) (clipped to the line) and the F1 rows of every plasma node in it;
+// it then takes all of them through K steps on chip -- fields in LDS, F1 rows in
+// registers -- while the range of valid nodes shrinks by one per step and side (not at
+// the line's ends, where the Mur update needs only nodes inside the line).  Only the owned
+// nodes and their F1 rows are written back.  F1 therefore crosses HBM once per K steps
+// (plus the halo rows), instead of once per step.
+//
+// Every value is produced by the same arithmetic as the one-step kernel (the same
+// update functions, operand order, lane-to-bin mapping and butterfly pairing of the
+// FP64 moment), so a blocked run is bitwise the run of K one-step launches.
+//
+// Requirements (checked on the host): FP32 storage, Nv/2 in {32, 64, 128, 256} stored bins
+// per node (one 16-byte chunk per lane, at least 8 lanes per row), K odd (the launch reads
+// field buffer step & 1 and writes the other), extended ranges of at most kTbBlock nodes
+// and tb_max_rows(Nv/2) plasma nodes.
+#include "common.h"
+#include "host_internal.h"
+
+namespace fdtdp {
+
+constexpr int kTbBlock = 512;               // threads per work-group (8 wavefronts)
+constexpr int kTbWaves = kTbBlock / 64;
+constexpr int kTbU = 4;                     // rows per lane group per row slot group
+constexpr int kTbIters = 3;                 // row slot groups per lane group (126 VGPRs:
+                                            // two work-groups per compute unit)
+constexpr int kTbRowsPerGroup = kTbIters * kTbU;
+
+template <int K, int LPC>
+__global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __restrict__ runs,
+                                                        const Tile1D* __restrict__ tiles,
+                                                        int64_t step) {
+  __shared__ float Es[2][kTbBlock];
+  __shared__ float Hs[2][kTbBlock];
+  __shared__ float Js[kTbBlock];
+  __shared__ float tauS[kTbBlock];
+  __shared__ float neS[kTbBlock];
+  __shared__ int locS[kTbBlock];
+  __shared__ float srcS[K];
+
+  const Tile1D tile = tiles[blockIdx.x];
+  const Run1D<float>& R = runs[tile.run];
+  // source samples of the K sub-steps, evaluated before the F1 rows occupy registers
+  if ((int)threadIdx.x < K)
+    srcS[threadIdx.x] = (float)source_wave((double)(step + threadIdx.x + 1) * R.dt, R.src_amp,
+                                           R.src_w, R.src_tau, R.src_t0);
+  const int nx = R.nx;
+  const int x0 = tile.node0 - K > 0 ? tile.node0 - K : 0;
+  const int x1 = tile.node1 + K < nx + 1 ? tile.node1 + K : nx + 1;
+  const int k = threadIdx.x;
+  const int i = x0 + k;
+  const int par = (int)(step & 1);
+  const int ncell = tile.cell1 - tile.cell0;   // plasma nodes of the extended range
+
+  // fields of the extended range, per-cell scalars
+  if (i < x1) {
+    Es[0][k] = R.E[par][i];
+    Hs[0][k] = i < nx ? R.H[par][i] : 0.f;
+    Js[k] = 0.f;
+  }
+  if (k < ncell) {
+    const int c = tile.cell0 + k;
+    tauS[k] = R.tau[c];
+    neS[k] = R.dens[c];
+    locS[k] = R.cell_node[c] - x0;
+  }
+
+  // F1 rows in registers: lane group `sub` of wave `wave`, slot (it, u) holds cell
+  // it * stride + wave * cpw * U + u * cpw + sub of the range
+  const int lane = k & 63, wave = k >> 6;
+  constexpr int lpc = LPC;                     // lanes per row (one float4 each)
+  constexpr int cpw = 64 / lpc;
+  constexpr int stride = kTbWaves * cpw * kTbU;
+  const int sub = lane / lpc, li = lane - sub * lpc;
+  float4 sb = reinterpret_cast<const float4*>(R.s_bin)[li];
+  float4 bb = reinterpret_cast<const float4*>(R.b_bin)[li];
+  double w[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) w[v] = R.w_bin[li * 4 + v];
+  float4 f[kTbIters][kTbU];
+  const float4* __restrict__ dfr = reinterpret_cast<const float4*>(R.df);
+#pragma unroll
+  for (int it = 0; it < kTbIters; ++it)
+#pragma unroll
+    for (int u = 0; u < kTbU; ++u) {
+      const int cl = it * stride + wave * cpw * kTbU + u * cpw + sub;
+      f[it][u] = cl < ncell ? dfr[(size_t)(tile.cell0 + cl) * lpc + li]
+                            : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+
+  int lo = x0, hi = x1;    // nodes whose E is valid at the start of the sub-step
+  const float S = R.S;
+#pragma unroll 1
+  for (int s = 0; s < K; ++s) {
+    const int p = s & 1;
+    const int64_t gs = step + s;
+    __syncthreads();
+    // keep the per-row scalars in LDS: re-read each sub-step instead of being hoisted
+    // into registers for all rows at once
+    asm volatile("" ::: "memory");
+    // kinetic update of the rows whose node holds a valid E, FP64 moment -> Js
+#pragma unroll
+    for (int it = 0; it < kTbIters; ++it) {
+      double acc[kTbU];
+      int loc[kTbU];
+#pragma unroll
+      for (int u = 0; u < kTbU; ++u) {
+        const int cl = it * stride + wave * cpw * kTbU + u * cpw + sub;
+        acc[u] = 0.0;
+        loc[u] = -1;
+        if (cl < ncell) {
+          const int lc = locS[cl];
+          if (x0 + lc >= lo && x0 + lc < hi) {
+            loc[u] = lc;
+            const float tau = tauS[cl];
+            const float nE = neS[cl] * Es[p][lc];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const float x = tau * lane_at(sb, v);
+              const float r = cn_recip(2.f + x);
+              const float fv = lane_at(f[it][u], v);
+              const float t = fmaf(-(x + x), fv, lane_at(bb, v) * nE);
+              const float fn = fmaf(t, r, fv);
+              lane_at(f[it][u], v) = fn;
+              acc[u] = fma(w[v], (double)fn, acc[u]);
+            }
+          }
+        }
+      }
+      int which = 0;
+      const double tot = group_reduce<kTbU>(acc, lpc, li, which);
+#pragma unroll
+      for (int u = 0; u < kTbU; ++u)
+        if (which == u && li == reporter<kTbU>(u, lpc) && loc[u] >= 0) Js[loc[u]] = (float)tot;
+    }
+    __syncthreads();
+
+    // H^{n+1/2} on [lo, hi - 1), E^{n+1} on the next valid range
+    const int nlo = lo == 0 ? 0 : lo + 1;
+    const int nhi = hi == nx + 1 ? nx + 1 : hi - 1;
+    if (i >= lo && i < hi) {
+      const float e0 = Es[p][k];
+      const float jv = Js[k];
+      float en = 0.f, hn = 0.f;
+      bool has_e = i >= nlo && i < nhi;
+      if (i == 0) {
+        const float ep = Es[p][k + 1], h0 = Hs[p][k];
+        hn = h_update(h0, S, ep, e0);
+        if (R.bc == 1) {
+          const float h1 = h_update(Hs[p][k + 1], S, Es[p][k + 2], ep);
+          const float e1 = e_update(ep, S, h1, hn, 0.f);
+          en = fmaf(R.q, e1 - e0, ep);
+        }
+        Hs[p ^ 1][k] = hn;
+      } else if (i == nx) {
+        if (R.bc == 1) {
+          const float em = Es[p][k - 1], hm = Hs[p][k - 1];
+          const float ha = h_update(hm, S, e0, em);
+          const float hb = h_update(Hs[p][k - 2], S, em, Es[p][k - 2]);
+          const float e = e_update(em, S, ha, hb, 0.f);
+          en = fmaf(R.q, e - e0, em);
+        }
+      } else {
+        if (i < hi - 1) {
+          hn = h_update(Hs[p][k], S, Es[p][k + 1], e0);
+          Hs[p ^ 1][k] = hn;
+        }
+        if (has_e) {
+          const float hl = h_update(Hs[p][k - 1], S, e0, Es[p][k - 1]);
+          en = e_update(e0, S, hn, hl, jv);
+          if (i == R.src_node) en += srcS[s];
+        }
+      }
+      if (has_e) Es[p ^ 1][k] = en;
+      if (has_e && i >= tile.node0 && i < tile.node1) {
+        if (!isfinite(en)) atomicOr(R.status, 1);
+        for (int q = 0; q < R.nprobe; ++q) {
+          if (R.probe_node[q] == i) {
+            const int fld = R.probe_field[q];
+            const float val = (fld == 0) ? en : (fld == 1 ? hn : jv);
+            R.probe_buf[(size_t)q * R.probe_cap + (size_t)(gs % R.probe_cap)] = val;
+          }
+        }
+        for (int t = 0; t < R.ntap; ++t) {
+          if (R.tap_node[t] == i && gs < R.tap_cap) {
+            float* dst = R.tap_buf + ((size_t)t * R.tap_cap + (size_t)gs) * 2;
+            dst[0] = e0;
+            dst[1] = jv;
+          }
+        }
+      }
+    }
+    lo = nlo;
+    hi = nhi;
+  }
+  __syncthreads();
+
+  // owned nodes and their F1 rows back to HBM (the other field buffer)
+  constexpr int pf = K & 1;
+  if (i >= tile.node0 && i < tile.node1) {
+    R.E[par ^ 1][i] = Es[pf][k];
+    if (i < nx) R.H[par ^ 1][i] = Hs[pf][k];
+    R.J[i] = Js[k];
+  }
+  // the row addresses are formed again here rather than kept live across the K steps
+  asm volatile("" ::: "memory");
+  float4* __restrict__ dfw = reinterpret_cast<float4*>(R.df);
+#pragma unroll
+  for (int it = 0; it < kTbIters; ++it)
+#pragma unroll
+    for (int u = 0; u < kTbU; ++u) {
+      const int cl = it * stride + wave * cpw * kTbU + u * cpw + sub;
+      if (cl < ncell) {
+        const int node = x0 + locS[cl];
+        if (node >= tile.node0 && node < tile.node1)
+          dfw[(size_t)(tile.cell0 + cl) * lpc + li] = f[it][u];
+      }
+    }
+}
+
+bool tb_supported(int half) { return half == 32 || half == 64 || half == 128 || half == 256; }
+
+int tb_block() { return kTbBlock; }
+
+// Plasma rows one work-group holds for rows of `half` stored bins.
+int tb_max_rows(int half) {
+  const int lpc = half / 4;
+  return kTbWaves * (64 / lpc) * kTbRowsPerGroup;
+}
+
+template <int K, int LPC>
+int tb_occupancy() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step1d_tb<K, LPC>, kTbBlock, 0) != hipSuccess)
+    return 1;
+  return n > 0 ? n : 1;
+}
+
+template <int K>
+int tb_occupancy_k(int half) {
+  switch (half) {
+    case 32: return tb_occupancy<K, 8>();
+    case 64: return tb_occupancy<K, 16>();
+    case 128: return tb_occupancy<K, 32>();
+    default: return tb_occupancy<K, 64>();
+  }
+}
+
+int tb_blocks_per_cu(int k, int half) {
+  switch (k) {
+    case 3: return tb_occupancy_k<3>(half);
+    case 5: return tb_occupancy_k<5>(half);
+    case 7: return tb_occupancy_k<7>(half);
+    default: return tb_occupancy_k<9>(half);
+  }
+}
+
+template <int K>
+hipError_t launch_tb_k(const Run1D<float>* r, const Tile1D* t, int ntiles, int64_t step, int half,
+                       hipStream_t stream) {
+  switch (half) {
+    case 32: hipLaunchKernelGGL((k_step1d_tb<K, 8>), dim3(ntiles), dim3(kTbBlock), 0, stream, r, t, step); break;
+    case 64: hipLaunchKernelGGL((k_step1d_tb<K, 16>), dim3(ntiles), dim3(kTbBlock), 0, stream, r, t, step); break;
+    case 128: hipLaunchKernelGGL((k_step1d_tb<K, 32>), dim3(ntiles), dim3(kTbBlock), 0, stream, r, t, step); break;
+    case 256: hipLaunchKernelGGL((k_step1d_tb<K, 64>), dim3(ntiles), dim3(kTbBlock), 0, stream, r, t, step); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// K steps [step, step + K) of the tiles (every tile of one run, half = Nv/2 of that run).
+hipError_t launch_step1d_tb(const void* runs, const void* tiles, int ntiles, int64_t step, int k,
+                            int half, hipStream_t stream) {
+  if (ntiles <= 0) return hipSuccess;
+  const Run1D<float>* r = static_cast<const Run1D<float>*>(runs);
+  const Tile1D* t = static_cast<const Tile1D*>(tiles);
+  switch (k) {
+    case 3: return launch_tb_k<3>(r, t, ntiles, step, half, stream);
+    case 5: return launch_tb_k<5>(r, t, ntiles, step, half, stream);
+    case 7: return launch_tb_k<7>(r, t, ntiles, step, half, stream);
+    case 9: return launch_tb_k<9>(r, t, ntiles, step, half, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace fdtdp

@@ -125,3 +125,42 @@ def test_short_buffer_and_bad_field(gpu_lib):
     assert rc == B.ERANGE and np.all(buf == 0)
     rc = gpu_lib.fdtd_plasma_read_fields(sim.h, 0, B.F_EX, buf.ctypes.data_as(C.POINTER(C.c_double)), 5, None)
     assert rc == B.EINVAL
+
+
+@pytest.mark.parametrize("nv,k", [(512, 3), (512, 5), (512, 7), (512, 9), (64, 5), (128, 3), (256, 7)])
+def test_time_blocked_run_is_bitwise_the_stepped_run(gpu_lib, nv, k):
+    """K steps per launch with halo recomputation against one step per launch: fields,
+    current, F1, probe series and a non-multiple step count (remainder steps) must agree
+    bit for bit."""
+    run = W.c1(nx=6000 if nv == 512 else 12000, steps=1)
+    run.nv = nv
+    steps = 1201 + k          # the pulse reaches the plasma (node 400) after ~600 steps
+    _banner(f"time block nv={nv} k={k}, {steps} steps")
+    probes = [run.src_node, 450, 1000, 3000]
+    sims = []
+    for tb in (1, k):
+        sim = B.Sim(run, precision=B.FP32, max_probes=len(probes) + 1, probe_capacity=steps,
+                    time_block=tb)
+        ids = [sim.add_probe(B.F_E, p) for p in probes] + [sim.add_probe(B.F_H, 2000)]
+        sims.append((sim, ids))
+    assert sims[0][0].time_block() == 1
+    assert sims[1][0].time_block() == k, "the line should be long enough to be blocked"
+    for sim, _ in sims:
+        sim.run(steps // 2)
+        sim.run(steps - steps // 2)
+    (a, ia), (b, ib) = sims
+    for f in (B.F_E, B.F_H, B.F_J, B.F_DF):
+        assert np.array_equal(a.read(f), b.read(f)), f
+    for p, q in zip(ia, ib):
+        assert np.array_equal(a.read_probe(p, steps), b.read_probe(q, steps))
+    assert np.max(np.abs(a.read(B.F_E))) > 1e-3
+    assert np.max(np.abs(a.read(B.F_DF))) > 0.0
+
+
+def test_time_block_rejects_even_and_reports_off_for_fp64(gpu_lib):
+    run = W.c1(nx=6000, steps=1)
+    sim = B.Sim(run, precision=B.FP64)
+    with pytest.raises(B.FdtdError):
+        sim.set_time_block(4)
+    sim.set_time_block(5)
+    assert sim.time_block() == 1
