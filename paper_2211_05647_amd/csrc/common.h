@@ -93,6 +93,49 @@ __device__ __forceinline__ int reporter(int u, int lpc) {
   return li;
 }
 
+// FP64 sums of four rows held by a full wavefront (64 lanes, one partial per row per
+// lane), without LDS traffic: two half-wave swaps (v_permlane32_swap, v_permlane16_swap)
+// scatter the rows so that 16-lane row r holds row r's partials, then four DPP rounds
+// (xor 1, xor 2, mirror within 8, mirror within 16) sum each 16-lane row.  Every lane of
+// 16-lane row r returns the total of row r; `which` = lane / 16.  The pairing tree is the
+// same on every call, so results are reproducible bit for bit.
+__device__ __forceinline__ double f64_join(uint32_t lo, uint32_t hi) {
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ uint32_t f64_lo(double v) { return (uint32_t)__double_as_longlong(v); }
+__device__ __forceinline__ uint32_t f64_hi(double v) {
+  return (uint32_t)((unsigned long long)__double_as_longlong(v) >> 32);
+}
+// lanes 0-31 get a[l] + a[l+32], lanes 32-63 get b[l-32] + b[l]
+__device__ __forceinline__ double swap32_sum(double a, double b) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(f64_lo(a), f64_lo(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(f64_hi(a), f64_hi(b), false, false);
+  return f64_join(lo[0], hi[0]) + f64_join(lo[1], hi[1]);
+}
+// even 16-lane rows get a[l] + a[l+16], odd rows get b[l-16] + b[l]
+__device__ __forceinline__ double swap16_sum(double a, double b) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(f64_lo(a), f64_lo(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(f64_hi(a), f64_hi(b), false, false);
+  return f64_join(lo[0], hi[0]) + f64_join(lo[1], hi[1]);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint32_t lo = __builtin_amdgcn_update_dpp(0u, f64_lo(v), CTRL, 0xF, 0xF, false);
+  const uint32_t hi = __builtin_amdgcn_update_dpp(0u, f64_hi(v), CTRL, 0xF, 0xF, false);
+  return f64_join(lo, hi);
+}
+__device__ __forceinline__ double wave_reduce4(const double (&a)[4], int& which) {
+  const double s0 = swap32_sum(a[0], a[2]);   // rows 0-1 of the wave: a0, rows 2-3: a2
+  const double s1 = swap32_sum(a[1], a[3]);   // rows 0-1: a1, rows 2-3: a3
+  double t = swap16_sum(s0, s1);              // row r: a_r
+  t += dpp_f64<0xB1>(t);                      // quad_perm [1,0,3,2]
+  t += dpp_f64<0x4E>(t);                      // quad_perm [2,3,0,1]
+  t += dpp_f64<0x141>(t);                     // row_half_mirror
+  t += dpp_f64<0x140>(t);                     // row_mirror
+  which = (int)(threadIdx.x & 63) >> 4;
+  return t;
+}
+
 struct Tile1D {
   int32_t run, node0, node1, cell0, cell1;
 };

@@ -153,6 +153,17 @@ int default_tile_1d(int half, int elem, int nx, int ncell) {
 
 }  // namespace
 
+// Owned nodes per blocked tile in a batch (capped by what the extended range allows):
+// the wider the tile, the less halo work per owned node.
+constexpr int kTbBatchWidth = 512;
+
+// Blocked tiles of one Nv: [off, off + limit.size()) of the blocked tile list, with the
+// step limit of each tile's run (non-increasing).
+struct TbSeg {
+  int half = 0, off = 0;
+  std::vector<int64_t> limit;
+};
+
 struct fdtd_plasma {
   int dims = 1;
   int precision = FDTD_FP32;
@@ -180,7 +191,8 @@ struct fdtd_plasma {
   int time_block = kDefaultTimeBlock;
   size_t tbtiles_off = 0;
   int ntbtiles = 0;
-  int64_t tb_rows = 0;     // F1 rows one blocked launch reads (owned plus halo)
+  int64_t tb_rows = 0;     // F1 rows one blocked pass reads (owned plus halo)
+  std::vector<TbSeg> tb_seg;
   // probes
   int max_probes = 0, probe_cap = 0;
   size_t probe_off = 0;
@@ -237,7 +249,7 @@ size_t layout_1d(fdtd_plasma* h, const std::vector<RunSpec1D>& specs, int precis
   for (auto& x : hs) max_tiles += (size_t)(x.nx + 1 + 31) / 32;
   const size_t tiles_off = cv.take(max_tiles * sizeof(Tile1D));
   // tiles of the temporally blocked kernel (single runs; never narrower than 32 nodes)
-  const size_t tbtiles_off = cv.take((specs.size() == 1 ? max_tiles : 1) * sizeof(Tile1D));
+  const size_t tbtiles_off = cv.take(max_tiles * sizeof(Tile1D));
   const size_t order_off = cv.take(sz<int32_t>(specs.size()));
   const size_t queue_off = cv.take(sz<int32_t>(1));
   const size_t status_off = cv.take(sz<int32_t>(specs.size()));
@@ -370,46 +382,74 @@ int upload_1d(fdtd_plasma* h) {
 }
 
 // Tiles of the temporally blocked kernel: owned ranges of W nodes whose extended range
-// (W + 2K nodes, clipped to the line) fits one work-group; W is chosen so that the tiles
-// fill the device in as few rounds of resident work-groups as possible.
+// (W + 2K nodes, clipped to the line) fits one work-group.  A single run takes W so that
+// its tiles fill the device in as few rounds of resident work-groups as possible; in a
+// batch every run takes W = kTbBatchWidth (or less if the extended range requires).  Tiles are grouped by Nv (one kernel instance per
+// group) and, inside a group, ordered by the run's step limit, longest first, so that
+// the tiles of the runs with K steps left are a prefix.  Blocking applies to FP32 runs
+// whose Nv the kernel handles; if any run of a batch is not such a run, none is blocked.
 int build_tb_tiles(fdtd_plasma* h) {
   h->ntbtiles = 0;
+  h->tb_rows = 0;
+  h->tb_seg.clear();
   const int k = h->time_block;
-  if (k < 3 || h->nruns != 1 || h->precision != FDTD_FP32) return FDTD_OK;
-  const Host1D& x = h->h1[0];
-  if (!tb_supported(x.half)) return FDTD_OK;
-  const int cap = std::min(tb_block(), tb_max_rows(x.half));
-  const int wmax = cap - 2 * k;
-  const int nodes = x.nx + 1;
-  if (wmax < 32 || nodes < 4 * wmax) return FDTD_OK;
+  if (k < 3 || h->precision != FDTD_FP32) return FDTD_OK;
+  for (int r = 0; r < h->nruns; ++r) {
+    const Host1D& x = h->h1[r];
+    if (!tb_supported(x.half)) return FDTD_OK;
+    if (std::min(tb_block(), tb_max_rows(x.half)) - 2 * k < 32) return FDTD_OK;
+  }
   int cus = 256;
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
-  const int conc = std::max(1, cus * tb_blocks_per_cu(k, x.half));
-  const int rounds = (nodes + conc * wmax - 1) / (conc * wmax);
-  const int w = std::max(32, std::min(wmax, (nodes + rounds * conc - 1) / (rounds * conc)));
-  std::vector<Tile1D> tiles;
-  int c0 = 0, c1 = 0;
-  for (int n0 = 0; n0 < nodes; n0 += w) {
-    Tile1D t;
-    t.run = 0;
-    t.node0 = n0;
-    t.node1 = std::min(nodes, n0 + w);
-    const int lo = std::max(0, n0 - k), hi = std::min(nodes, t.node1 + k);
-    while (c0 < x.ncell && x.cell_node[c0] < lo) ++c0;
-    c1 = std::max(c1, c0);
-    while (c1 < x.ncell && x.cell_node[c1] < hi) ++c1;
-    t.cell0 = c0;
-    t.cell1 = c1;
-    if (c1 - c0 > cap) return FDTD_OK;   // cannot happen (one cell per node), stay unblocked
-    tiles.push_back(t);
+  struct Item { int half; int64_t limit; Tile1D t; };
+  std::vector<Item> items;
+  for (int r = 0; r < h->nruns; ++r) {
+    const Host1D& x = h->h1[r];
+    const int cap = std::min(tb_block(), tb_max_rows(x.half));
+    const int wmax = cap - 2 * k;
+    const int nodes = x.nx + 1;
+    int w = std::min(wmax, kTbBatchWidth);
+    if (h->nruns == 1) {
+      if (nodes < 4 * wmax) return FDTD_OK;   // too short to be worth blocking
+      const int conc = std::max(1, cus * tb_blocks_per_cu(k, x.half));
+      const int rounds = (nodes + conc * wmax - 1) / (conc * wmax);
+      w = std::max(32, std::min(wmax, (nodes + rounds * conc - 1) / (rounds * conc)));
+    }
+    int c0 = 0, c1 = 0;
+    for (int n0 = 0; n0 < nodes; n0 += w) {
+      Tile1D t;
+      t.run = r;
+      t.node0 = n0;
+      t.node1 = std::min(nodes, n0 + w);
+      const int lo = std::max(0, n0 - k), hi = std::min(nodes, t.node1 + k);
+      while (c0 < x.ncell && x.cell_node[c0] < lo) ++c0;
+      c1 = std::max(c1, c0);
+      while (c1 < x.ncell && x.cell_node[c1] < hi) ++c1;
+      t.cell0 = c0;
+      t.cell1 = c1;
+      if (c1 - c0 > cap) return FDTD_OK;   // cannot happen (one cell per node)
+      items.push_back({x.half, h->specs[r].steps, t});
+    }
   }
-  int64_t rows = 0;
-  for (const Tile1D& t : tiles) rows += t.cell1 - t.cell0;
+  std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
+    return a.half != b.half ? a.half < b.half : a.limit > b.limit;
+  });
+  std::vector<Tile1D> tiles;
+  for (size_t i = 0; i < items.size(); ++i) {
+    if (i == 0 || items[i].half != items[i - 1].half) {
+      TbSeg sg;
+      sg.half = items[i].half;
+      sg.off = (int)i;
+      h->tb_seg.push_back(sg);
+    }
+    h->tb_seg.back().limit.push_back(items[i].limit);
+    tiles.push_back(items[i].t);
+    h->tb_rows += items[i].t.cell1 - items[i].t.cell0;
+  }
   hipError_t e = hipMemcpyAsync(h->ws + h->tbtiles_off, tiles.data(), tiles.size() * sizeof(Tile1D),
                                 hipMemcpyHostToDevice, h->stream);
   if (e) return hip_fail(e, "upload blocked tiles");
   h->ntbtiles = (int)tiles.size();
-  h->tb_rows = rows;
   return FDTD_OK;
 }
 
@@ -698,12 +738,39 @@ int fdtd_plasma_run(fdtd_plasma* h, int64_t nsteps) {
   }
   int64_t k0 = 0;
   if (h->dims == 1 && h->ntbtiles > 0) {
-    // K steps per launch while at least K remain; the rest one step per launch
+    // K steps per launch for the runs with at least K steps left; a run that ends inside
+    // the pass takes its last steps one launch per step.  Once a batch is down to fewer
+    // blocked work-groups than compute units (only its longest runs left), and for the
+    // last steps of the call, one step per launch.
     const int kb = h->time_block;
+    auto count_ge = [](const std::vector<int64_t>& lim, int64_t v) {   // limits >= v
+      return (int)(std::upper_bound(lim.begin(), lim.end(), v,
+                                    [](int64_t x, int64_t l) { return x > l; }) -
+                   lim.begin());
+    };
+    const Tile1D* tb = reinterpret_cast<const Tile1D*>(h->ws + h->tbtiles_off);
+    const Tile1D* rt = reinterpret_cast<const Tile1D*>(h->ws + h->tiles_off);
+    int min_tiles = 256;   // fewer blocked work-groups than compute units: step instead
+    hipDeviceGetAttribute(&min_tiles, hipDeviceAttributeMultiprocessorCount, h->device);
+    if (h->nruns == 1) min_tiles = 1;
     for (; k0 + kb <= nsteps_loop; k0 += kb) {
-      e = launch_step1d_tb(h->ws + h->runs_off, h->ws + h->tbtiles_off, h->ntbtiles, h->step + k0,
-                           kb, h->h1[0].half, h->stream);
-      if (e) return hip_fail(e, "launch blocked step kernel");
+      const int64_t s = h->step + k0;
+      int nblocked = 0;
+      for (const TbSeg& sg : h->tb_seg) nblocked += count_ge(sg.limit, s + kb);
+      if (nblocked < min_tiles) break;   // the tail of a batch: one step per launch
+      for (const TbSeg& sg : h->tb_seg) {
+        const int n = count_ge(sg.limit, s + kb);
+        e = launch_step1d_tb(h->ws + h->runs_off, tb + sg.off, n, s, kb, sg.half, h->stream);
+        if (e) return hip_fail(e, "launch blocked step kernel");
+      }
+      if (h->nruns > 1) {
+        const int p1 = count_ge(h->tile_limit, s + kb), p2 = count_ge(h->tile_limit, s + 1);
+        for (int64_t ss = s; p2 > p1 && ss < s + kb; ++ss) {
+          const int n = count_ge(h->tile_limit, ss + 1) - p1;
+          e = launch_step1d<float>(h->ws + h->runs_off, rt + p1, n, ss, h->stream);
+          if (e) return hip_fail(e, "launch step kernel");
+        }
+      }
     }
   }
   for (int64_t k = k0; k < nsteps_loop; ++k) {

@@ -120,10 +120,23 @@ __device__ __forceinline__ void kinetic_tile(const Run1D<T>& R, const T* eloc,
       }
     } else {
       int which = 0;
-      const double tot = group_reduce<U>(acc, lpc, li, which);
+      bool done = false;
+      if constexpr (U == 4) {
+        if (lpc == 64) {
+          // a row per wavefront: cross-lane swaps and DPP, no LDS round trips
+          const double tot = wave_reduce4(acc, which);
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (which == u && li == reporter<U>(u, lpc) && loc[u] >= 0) jloc[loc[u]] = (T)tot;
+          for (int u = 0; u < U; ++u)
+            if (li == 16 * u && loc[u] >= 0) jloc[loc[u]] = (T)tot;
+          done = true;
+        }
+      }
+      if (!done) {
+        const double tot = group_reduce<U>(acc, lpc, li, which);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (which == u && li == reporter<U>(u, lpc) && loc[u] >= 0) jloc[loc[u]] = (T)tot;
+      }
     }
   }
 }

@@ -13,8 +13,8 @@
 // (plus the halo rows), instead of once per step.
 //
 // Every value is produced by the same arithmetic as the one-step kernel (the same
-// update functions, operand order, lane-to-bin mapping and butterfly pairing of the
-// FP64 moment), so a blocked run is bitwise the run of K one-step launches.
+// update functions, operand order, lane-to-bin mapping and pairing tree of the FP64
+// moment), so a blocked run is bitwise the run of K one-step launches.
 //
 // Requirements (checked on the host): FP32 storage, Nv/2 in {32, 64, 128, 256} stored bins
 // per node (one 16-byte chunk per lane, at least 8 lanes per row), K odd (the launch reads
@@ -38,7 +38,7 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
                                                         int64_t step) {
   __shared__ float Es[2][kTbBlock];
   __shared__ float Hs[2][kTbBlock];
-  __shared__ float Js[kTbBlock];
+  __shared__ float Js[kTbBlock + 1];        // + a spare slot for rows without a valid E
   __shared__ float tauS[kTbBlock];
   __shared__ float neS[kTbBlock];
   __shared__ int locS[kTbBlock];
@@ -62,8 +62,10 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
   if (i < x1) {
     Es[0][k] = R.E[par][i];
     Hs[0][k] = i < nx ? R.H[par][i] : 0.f;
-    Js[k] = 0.f;
   }
+  Es[1][k] = 0.f;
+  Hs[1][k] = 0.f;
+  Js[k] = 0.f;
   if (k < ncell) {
     const int c = tile.cell0 + k;
     tauS[k] = R.tau[c];
@@ -74,6 +76,7 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
   // F1 rows in registers: lane group `sub` of wave `wave`, slot (it, u) holds cell
   // it * stride + wave * cpw * U + u * cpw + sub of the range
   const int lane = k & 63, wave = k >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
   constexpr int lpc = LPC;                     // lanes per row (one float4 each)
   constexpr int cpw = 64 / lpc;
   constexpr int stride = kTbWaves * cpw * kTbU;
@@ -111,33 +114,53 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
       int loc[kTbU];
 #pragma unroll
       for (int u = 0; u < kTbU; ++u) {
-        const int cl = it * stride + wave * cpw * kTbU + u * cpw + sub;
+        const int cl = it * stride + wv * cpw * kTbU + u * cpw + sub;
         acc[u] = 0.0;
-        loc[u] = -1;
-        if (cl < ncell) {
-          const int lc = locS[cl];
-          if (x0 + lc >= lo && x0 + lc < hi) {
-            loc[u] = lc;
-            const float tau = tauS[cl];
-            const float nE = neS[cl] * Es[p][lc];
+        loc[u] = kTbBlock;            // rows without a valid E report to the spare slot
+        bool live = cl < ncell;
+        int lc = 0;
+        if constexpr (LPC == 64) {
+          // one row per wavefront: the row's scalars and its validity are uniform
+          if (live) {
+            lc = __builtin_amdgcn_readfirstlane(locS[cl]);
+            live = x0 + lc >= lo && x0 + lc < hi;
+          }
+        } else if (live) {
+          lc = locS[cl];
+          live = x0 + lc >= lo && x0 + lc < hi;
+        }
+        if (live) {
+          loc[u] = lc;
+          float tau = tauS[cl], nE = neS[cl] * Es[p][lc];
+          if constexpr (LPC == 64) {
+            tau = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(tau)));
+            nE = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(nE)));
+          }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const float x = tau * lane_at(sb, v);
-              const float r = cn_recip(2.f + x);
-              const float fv = lane_at(f[it][u], v);
-              const float t = fmaf(-(x + x), fv, lane_at(bb, v) * nE);
-              const float fn = fmaf(t, r, fv);
-              lane_at(f[it][u], v) = fn;
-              acc[u] = fma(w[v], (double)fn, acc[u]);
-            }
+          for (int v = 0; v < 4; ++v) {
+            const float x = tau * lane_at(sb, v);
+            const float r = cn_recip(2.f + x);
+            const float fv = lane_at(f[it][u], v);
+            const float t = fmaf(-(x + x), fv, lane_at(bb, v) * nE);
+            const float fn = fmaf(t, r, fv);
+            lane_at(f[it][u], v) = fn;
+            acc[u] = fma(w[v], (double)fn, acc[u]);
           }
         }
       }
       int which = 0;
-      const double tot = group_reduce<kTbU>(acc, lpc, li, which);
+      if constexpr (LPC == 64) {
+        static_assert(kTbU == 4, "wave_reduce4 sums four rows");
+        const double tot = wave_reduce4(acc, which);
 #pragma unroll
-      for (int u = 0; u < kTbU; ++u)
-        if (which == u && li == reporter<kTbU>(u, lpc) && loc[u] >= 0) Js[loc[u]] = (float)tot;
+        for (int u = 0; u < kTbU; ++u)
+          if (li == 16 * u) Js[loc[u]] = (float)tot;
+      } else {
+        const double tot = group_reduce<kTbU>(acc, lpc, li, which);
+#pragma unroll
+        for (int u = 0; u < kTbU; ++u)
+          if (li == reporter<kTbU>(u, lpc)) Js[loc[u]] = (float)tot;
+      }
     }
     __syncthreads();
 

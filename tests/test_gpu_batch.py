@@ -135,3 +135,27 @@ def test_nonfinite_run_is_flagged_alone(gpu_lib):
         solo = B.Sim(runs[r])
         solo.run(runs[r].steps)
         assert np.array_equal(bat.read(B.F_E, run=r), solo.read(B.F_E))
+
+
+def test_time_blocked_batch_is_bitwise_the_stepped_batch(gpu_lib):
+    """The batch with K steps per launch (runs ending inside a pass finish one step per
+    launch) against one step per launch: fields, F1 and taps bit for bit, for several K
+    and a step count that is not a multiple of K."""
+    runs = small_batch(8, seed=51, nx_hi=3000)
+    taps = tap_nodes(runs, 3)
+    total = max(r.steps for r in runs)
+    _banner(f"time-blocked batch, {total} steps")
+    ref = B.Sim(runs, taps=taps, time_block=1)
+    assert ref.time_block() == 1
+    ref.run(total // 3)
+    ref.run(total - total // 3)
+    for k in (3, 7):
+        bat = B.Sim(runs, taps=taps, time_block=k)
+        assert bat.time_block() == k
+        bat.run(total // 3)
+        bat.run(total - total // 3)
+        for r in range(len(runs)):
+            for f in FIELDS:
+                assert np.array_equal(bat.read(f, run=r), ref.read(f, run=r)), (k, r, f)
+            assert np.array_equal(bat.read_taps(r), ref.read_taps(r)), (k, r)
+        bat.close()
