@@ -120,8 +120,9 @@ __device__ __forceinline__ double swap16_sum(double a, double b) {
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
-  const uint32_t lo = __builtin_amdgcn_update_dpp(0u, f64_lo(v), CTRL, 0xF, 0xF, false);
-  const uint32_t hi = __builtin_amdgcn_update_dpp(0u, f64_hi(v), CTRL, 0xF, 0xF, false);
+  // every lane reads a lane of its own row, so no lane keeps its old value
+  const uint32_t lo = __builtin_amdgcn_mov_dpp(f64_lo(v), CTRL, 0xF, 0xF, true);
+  const uint32_t hi = __builtin_amdgcn_mov_dpp(f64_hi(v), CTRL, 0xF, 0xF, true);
   return f64_join(lo, hi);
 }
 __device__ __forceinline__ double wave_reduce4(const double (&a)[4], int& which) {

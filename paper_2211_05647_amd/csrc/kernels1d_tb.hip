@@ -88,6 +88,21 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
   for (int v = 0; v < 4; ++v) w[v] = R.w_bin[li * 4 + v];
   float4 f[kTbIters][kTbU];
   const float4* __restrict__ dfr = reinterpret_cast<const float4*>(R.df);
+  // one row per wavefront (LPC = 64): lane q of these registers holds the scalars of the
+  // wavefront's row slot q, read into scalar registers with v_readlane when needed
+  int tab_loc = kTbBlock;
+  float tab_tau = 0.f, tab_ne = 0.f;
+  if constexpr (LPC == 64) {
+    if (lane < kTbIters * kTbU) {
+      const int cl = (lane / kTbU) * stride + wv * cpw * kTbU + (lane % kTbU) * cpw;
+      if (cl < ncell) {
+        const int c = tile.cell0 + cl;
+        tab_loc = R.cell_node[c] - x0;
+        tab_tau = R.tau[c];
+        tab_ne = R.dens[c];
+      }
+    }
+  }
 #pragma unroll
   for (int it = 0; it < kTbIters; ++it)
 #pragma unroll
@@ -119,23 +134,23 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
         loc[u] = kTbBlock;            // rows without a valid E report to the spare slot
         bool live = cl < ncell;
         int lc = 0;
+        float tau = 0.f, ne = 0.f;
         if constexpr (LPC == 64) {
           // one row per wavefront: the row's scalars and its validity are uniform
-          if (live) {
-            lc = __builtin_amdgcn_readfirstlane(locS[cl]);
-            live = x0 + lc >= lo && x0 + lc < hi;
-          }
+          const int q = it * kTbU + u;
+          lc = __builtin_amdgcn_readlane(tab_loc, q);
+          tau = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tab_tau), q));
+          ne = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tab_ne), q));
+          live = live && x0 + lc >= lo && x0 + lc < hi;
         } else if (live) {
           lc = locS[cl];
+          tau = tauS[cl];
+          ne = neS[cl];
           live = x0 + lc >= lo && x0 + lc < hi;
         }
         if (live) {
           loc[u] = lc;
-          float tau = tauS[cl], nE = neS[cl] * Es[p][lc];
-          if constexpr (LPC == 64) {
-            tau = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(tau)));
-            nE = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(nE)));
-          }
+          const float nE = ne * Es[p][lc];
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const float x = tau * lane_at(sb, v);
