@@ -1,10 +1,12 @@
 """Launch-shape autotuner for the step kernels.
 
 For a workload it times every candidate tile (E nodes per work-group in 1D, cells per
-work-group in 2D) with HIP events around ``fdtd_plasma_run`` and keeps the fastest in a
+work-group in 2D) and, for single 1D runs, every steps-per-launch value of the temporally
+blocked kernel, with HIP events around ``fdtd_plasma_run``, and keeps the fastest in a
 JSON cache keyed by (dims, nv, precision, size class).  Timing runs are short and start
-from the zero state; the chosen tile only changes the launch shape, never the result
-(every tile gives bitwise-identical fields).
+from the zero state; the choices only change the launch shape, never the result (every
+tile and every steps-per-launch value gives bitwise-identical fields).
+``python -m paper_2211_05647_amd.autotune`` tunes the benchmark workloads.
 """
 from __future__ import annotations
 
@@ -42,7 +44,8 @@ def tune(run, precision=B.FP32, steps=200, candidates=None, save=True, log=print
     cands = candidates or (CANDIDATES_2D if dims == 2 else CANDIDATES_1D)
     res = {}
     for t in cands:
-        sim = B.Sim(run, precision=precision, tile=t)
+        # 1D tiles shape the one-step kernel: time it without temporal blocking
+        sim = B.Sim(run, precision=precision, tile=t, time_block=1 if dims == 1 else None)
         sim.run(20)
         sim.run(steps)
         ms = sim.last_run_ms()
@@ -56,3 +59,48 @@ def tune(run, precision=B.FP32, steps=200, candidates=None, save=True, log=print
         with open(CACHE, "w") as f:
             json.dump(d, f, indent=1, sort_keys=True)
     return best, res
+
+
+CANDIDATES_TB = (1, 3, 5, 7, 9)
+
+
+def lookup_time_block(run, precision):
+    """Steps per launch chosen for this workload class (0 = not tuned: library default)."""
+    return load().get(key(run, precision), {}).get("time_block", 0)
+
+
+def tune_time_block(run, precision=B.FP32, steps=630, save=True, log=print):
+    """Time every steps-per-launch candidate of the temporally blocked 1D kernel (the
+    result is bitwise the same for all of them) and keep the fastest."""
+    tile = lookup(run, precision)
+    res = {}
+    for k in CANDIDATES_TB:
+        sim = B.Sim(run, precision=precision, tile=tile, time_block=k)
+        if sim.time_block() != k:
+            sim.close()
+            continue
+        sim.run(63)
+        sim.run(steps)
+        res[k] = sim.last_run_ms()
+        sim.close()
+        log(f"[autotune] {key(run, precision)} time_block={k}: {res[k] * 1e3:.2f} us/step")
+    if not res:
+        return 0, res
+    best = min(res, key=res.get)
+    if save:
+        d = load()
+        e = d.setdefault(key(run, precision), {})
+        e["time_block"] = best
+        e["us_per_step_by_time_block"] = {str(k): v * 1e3 for k, v in res.items()}
+        with open(CACHE, "w") as f:
+            json.dump(d, f, indent=1, sort_keys=True)
+    return best, res
+
+
+if __name__ == "__main__":
+    # tune the launch shapes of the benchmark workloads on the current device
+    from . import workloads as W
+    for run in (W.c1(), W.c1_large()):
+        tune(run)
+        tune_time_block(run)
+    tune(W.c2(), candidates=(8, 16, 32, 64))
