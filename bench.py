@@ -22,6 +22,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
 # Vector ALU roofline of the temporally blocked kernel: 256 CUs x 4 SIMDs x 16 lanes x
@@ -199,6 +201,55 @@ def c4_steps(B, W, torch, steps):
     return {"c4_steps": res}
 
 
+def nmcps_sweep(B, W, torch, cpu_budget_s=2.0):
+    """Execution speed against mesh size, in the paper's measure (eq. (5): NMCPS = steps x
+    cells / seconds x 1e-6): a 2D TEz vacuum grid with 8-cell CPML and a soft line source,
+    n x n cells from 32^2 to 4096^2, on the GPU (FP32) and on the host with the FP64 oracle
+    (sizes up to 512^2, time-bounded).  Beside it, the coupled 1D kinetic line (Nv = 512,
+    plasma over all but the ends) against its length, in phase-space updates/s."""
+    sys.path.insert(0, ROOT)
+    from oracle.core import Oracle2D, threads
+    out = {"vacuum_2d": [], "kinetic_1d": []}
+    for n in (32, 64, 128, 256, 512, 1024, 2048, 4096):
+        run = W.Run2D(name=f"vac{n}", nx=n, ny=n, nv=8, ne=np.zeros((n, n)),
+                      nubar=np.zeros((n, n)), src_kind=1, src_i=n // 8, src_j=0,
+                      steps=0, **W.pulse(W.F_REF))
+        steps = max(200, min(4000, int(4e9 / (n * n))))
+        sim = B.Sim(run, precision=B.FP32)
+        sim.run(20)
+        sim.run(steps)
+        ms = sim.last_run_ms()
+        sim.close()
+        row = {"n": n, "cells": n * n, "gpu_nmcps": n * n / (ms * 1e-3) * 1e-6, "gpu_us_per_step": ms * 1e3}
+        if n <= 512:
+            o = Oracle2D(n, n, run.dx, run.courant, run.ne, run.nubar, nv=8, ncpml=run.ncpml,
+                         src_kind=1, src_i=run.src_i, src_amp=run.src_amp, src_f=run.src_f,
+                         src_tau=run.src_tau, src_t0=run.src_t0)
+            t0 = time.perf_counter()
+            o.run(5)
+            per = (time.perf_counter() - t0) / 5
+            k = max(5, int(cpu_budget_s / max(per, 1e-7)))
+            t0 = time.perf_counter()
+            o.run(k)
+            row["cpu_oracle_nmcps"] = n * n * k / (time.perf_counter() - t0) * 1e-6
+            row["cpu_threads"] = threads()
+        out["vacuum_2d"].append(row)
+        log(f"sweep 2D vacuum {n}^2: {row}")
+    for nx in (1024, 4096, 16384, 65536, 262144, 1048576):
+        run = W.c1(nx=nx, steps=1)
+        steps = max(180, min(4500, int(2e10 / (run.plasma_cells * run.nv)))) // 9 * 9
+        sim = B.Sim(run, precision=B.FP32)
+        sim.run(18)
+        sim.run(steps)
+        ms = sim.last_run_ms()
+        row = {"nx": nx, "plasma_cells": run.plasma_cells, "time_block": sim.time_block(),
+               "updates_per_s": run.plasma_cells * run.nv / (ms * 1e-3), "us_per_step": ms * 1e3}
+        sim.close()
+        out["kinetic_1d"].append(row)
+        log(f"sweep 1D kinetic Nx={nx}: {row}")
+    return {"nmcps_sweep": out}
+
+
 def extra_workloads(B, W, torch, autotune):
     out = {}
     out.update(extra_c1l(B, W, torch, autotune))
@@ -283,7 +334,7 @@ def main():
                     help="steps per launch of the large 1D workload (default: tuned; 1 = one "
                          "step per launch)")
     ap.add_argument("--calibrate-copy", action="store_true")
-    ap.add_argument("--only", choices=["c1l", "c2", "c3", "closure", "c4"], default=None,
+    ap.add_argument("--only", choices=["c1l", "c2", "c3", "closure", "c4", "sweep"], default=None,
                     help="run only one of the extra measurements (for profiling); c2 and c4 "
                          "take --steps steps")
     args = ap.parse_args()
@@ -305,7 +356,8 @@ def main():
                 "c2": lambda: extra_c2(B, W, torch, autotune, args.steps),
                 "c3": lambda: extra_c3(B, W, torch),
                 "closure": lambda: closure_speedup(B, W, torch),
-                "c4": lambda: c4_steps(B, W, torch, args.steps)}[args.only]
+                "c4": lambda: c4_steps(B, W, torch, args.steps),
+                "sweep": lambda: nmcps_sweep(B, W, torch)}[args.only]
         print(json.dumps(only()), flush=True)
         return
 

@@ -73,14 +73,17 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
     locS[k] = R.cell_node[c] - x0;
   }
 
-  // F1 rows in registers: lane group `sub` of wave `wave`, slot (it, u) holds cell
-  // it * stride + wave * cpw * U + u * cpw + sub of the range
+  // F1 rows in registers: lane group `sub` of wavefront `wv`, slot (it, u) holds the row
+  // row_slot(it * U + u, wv, sub) of the range
   const int lane = k & 63, wave = k >> 6;
   const int wv = __builtin_amdgcn_readfirstlane(wave);
   constexpr int lpc = LPC;                     // lanes per row (one float4 each)
   constexpr int cpw = 64 / lpc;
-  constexpr int stride = kTbWaves * cpw * kTbU;
   const int sub = lane / lpc, li = lane - sub * lpc;
+  // row slot q of lane group `sub` of wavefront w holds plasma row (q * waves + w) * cpw +
+  // sub of the range: consecutive rows go to different wavefronts, so every wavefront gets
+  // the same number of rows (to one) whatever the range holds
+  auto row_slot = [&](int q, int w, int sb) { return (q * kTbWaves + w) * cpw + sb; };
   float4 sb = reinterpret_cast<const float4*>(R.s_bin)[li];
   float4 bb = reinterpret_cast<const float4*>(R.b_bin)[li];
   double w[4];
@@ -94,7 +97,7 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
   float tab_tau = 0.f, tab_ne = 0.f;
   if constexpr (LPC == 64) {
     if (lane < kTbIters * kTbU) {
-      const int cl = (lane / kTbU) * stride + wv * cpw * kTbU + (lane % kTbU) * cpw;
+      const int cl = row_slot(lane, wv, 0);
       if (cl < ncell) {
         const int c = tile.cell0 + cl;
         tab_loc = R.cell_node[c] - x0;
@@ -107,7 +110,7 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
   for (int it = 0; it < kTbIters; ++it)
 #pragma unroll
     for (int u = 0; u < kTbU; ++u) {
-      const int cl = it * stride + wave * cpw * kTbU + u * cpw + sub;
+      const int cl = row_slot(it * kTbU + u, wv, sub);
       f[it][u] = cl < ncell ? dfr[(size_t)(tile.cell0 + cl) * lpc + li]
                             : make_float4(0.f, 0.f, 0.f, 0.f);
     }
@@ -129,7 +132,7 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
       int loc[kTbU];
 #pragma unroll
       for (int u = 0; u < kTbU; ++u) {
-        const int cl = it * stride + wv * cpw * kTbU + u * cpw + sub;
+        const int cl = row_slot(it * kTbU + u, wv, sub);
         acc[u] = 0.0;
         loc[u] = kTbBlock;            // rows without a valid E report to the spare slot
         bool live = cl < ncell;
@@ -253,7 +256,7 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
   for (int it = 0; it < kTbIters; ++it)
 #pragma unroll
     for (int u = 0; u < kTbU; ++u) {
-      const int cl = it * stride + wave * cpw * kTbU + u * cpw + sub;
+      const int cl = row_slot(it * kTbU + u, wv, sub);
       if (cl < ncell) {
         const int node = x0 + locS[cl];
         if (node >= tile.node0 && node < tile.node1)
