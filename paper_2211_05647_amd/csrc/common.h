@@ -199,6 +199,7 @@ template <class T> struct Run2D {
   const T *bex, *aex, *rkex, *bhx, *ahx, *rkhx;
   const T *bey, *aey, *rkey, *bhy, *ahy, *rkhy;
   int32_t nx, ny, m, ncell, half, cells_per_block, nbk;
+  int32_t hrows, erows;   // rows per thread of the Hz and E updates (1 or 4)
   T S;
   int32_t src_kind, src_i, src_j;
   double src_amp, src_w, src_tau, src_t0, dt;

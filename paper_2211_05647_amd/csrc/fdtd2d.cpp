@@ -36,7 +36,7 @@ struct Host2D {
          off_wx = 0, off_wy = 0, off_prof = 0, off_run = 0;
   size_t state_end = 0, probe_off = 0, total = 0;
   char* ws = nullptr;
-  int nbk = 0, nbh = 0, nbe = 0;
+  int nbk = 0, nbh = 0, nbe = 0, hrows = 1, erows = 1;
   // learned closure (closure cells are not in cell_idx: those hold the kinetic cells)
   bool closure = false;
   std::vector<float> mlp_params;
@@ -206,6 +206,8 @@ int upload(Host2D* h, char* ws, hipStream_t st, const std::vector<ProbeInfo>& pr
   R.nx = nx; R.ny = ny; R.m = m; R.ncell = h->ncell; R.half = half;
   R.cells_per_block = h->cells_per_block;
   R.nbk = h->nbk;
+  R.hrows = h->hrows;
+  R.erows = h->erows;
   R.S = (T)h->g.courant;
   R.src_kind = (h->s.kind != FDTD_SRC_NONE && h->s.amplitude != 0.0) ? h->s.kind : 0;
   R.src_i = h->s.i; R.src_j = h->s.j;
@@ -268,8 +270,10 @@ int upload(Host2D* h, char* ws, hipStream_t st, const std::vector<ProbeInfo>& pr
 
 void set_grid(Host2D* h) {
   h->nbk = h->ncell > 0 ? (h->ncell + h->cells_per_block - 1) / h->cells_per_block : 0;
-  h->nbh = row_segments(h->nx, h->ny, kBlock);
-  h->nbe = row_segments(h->nx + 1, h->ny + 1, kBlock);
+  h->hrows = field_rows(h->nx, h->ny);
+  h->erows = field_rows(h->nx + 1, h->ny + 1);
+  h->nbh = ((h->nx + kBlock - 1) / kBlock) * ((h->ny + h->hrows - 1) / h->hrows);
+  h->nbe = ((h->nx + kBlock) / kBlock) * ((h->ny + 1 + h->erows - 1) / h->erows);
 }
 
 }  // namespace

@@ -261,22 +261,26 @@ __global__ __launch_bounds__(kBlock) void k_h2d_kin(const Run2D<T>* __restrict__
     }
     return;
   }
-  // Hz: one row segment of kBlock points per block
+  // Hz: kBlock columns by R.hrows (1 or 4) rows per block
   const int seg = (int)blockIdx.x - R.nbk;
   const int spr = (R.nx + kBlock - 1) / kBlock;
-  const int j = seg / spr;
-  const int i = (seg - j * spr) * kBlock + (int)threadIdx.x;
-  if (j < R.ny && i < R.nx) h2d_point(R, i, j, step);
+  const int strip = seg / spr;
+  const int i = (seg - strip * spr) * kBlock + (int)threadIdx.x;
+  if (i >= R.nx) return;
+  if (R.hrows == 4) h2d_rows<4>(R, i, strip * 4, step);
+  else h2d_rows<1>(R, i, strip, step);
 }
 
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_e2d(const Run2D<T>* __restrict__ rp, int64_t step) {
   const Run2D<T>& R = *rp;
-  // one row segment of kBlock points of the (nx+1) x (ny+1) lattice per block
+  // kBlock columns by R.erows (1 or 4) rows of the (nx+1) x (ny+1) lattice per block
   const int spr = (R.nx + kBlock) / kBlock;
-  const int j = (int)blockIdx.x / spr;
-  const int i = ((int)blockIdx.x - j * spr) * kBlock + (int)threadIdx.x;
-  if (j <= R.ny && i <= R.nx) e2d_point(R, i, j, step);
+  const int strip = (int)blockIdx.x / spr;
+  const int i = ((int)blockIdx.x - strip * spr) * kBlock + (int)threadIdx.x;
+  if (i > R.nx) return;
+  if (R.erows == 4) e2d_rows<4>(R, i, strip * 4, step);
+  else e2d_rows<1>(R, i, strip, step);
 }
 
 // H + kinetic launch, picking the kinetic path by the stored bins per cell
