@@ -509,7 +509,7 @@ __global__ void k_make_pairs(const float* __restrict__ E, int64_t e_stride, int6
 
 // --- the closure inside a 2D run ----------------------------------------------------
 // One launch per step does two independent things that both only read E^n: the Hz
-// half-step (row segments of 64 points, one point per lane) and the closure.  Each
+// half-step (64 columns by 4 rows, one column per lane) and the closure.  Each
 // wavefront takes tile t of both, so the field update's memory traffic is overlapped by
 // the network's matrix and GELU arithmetic on the same compute units.
 // Closure: for every closure cell and both current components, push the cell-centre
@@ -531,15 +531,15 @@ __global__ __launch_bounds__(kInferWaves * 64) void k_mlp2d(const Run2D<float>* 
   const int nwaves = gridDim.x * kInferWaves;
   const int nrows = 2 * C.n;
   const int tiles_m = (nrows + kWaveRows - 1) / kWaveRows;
-  const int spr = (nx + 63) / 64;                   // Hz row segments of 64 points
-  const int tiles_h = spr * R.ny;
+  const int spr = (nx + 63) / 64;                   // Hz: 64 columns by 4 rows
+  const int tiles_h = spr * ((R.ny + 3) / 4);
   const int tiles = tiles_m > tiles_h ? tiles_m : tiles_h;
   const int w0 = __builtin_amdgcn_readfirstlane(blockIdx.x * kInferWaves + wave);
   for (int t = w0; t < tiles; t += nwaves) {
     if (t < tiles_h) {
-      const int j = t / spr;
-      const int i = (t - j * spr) * 64 + l;
-      if (i < nx) h2d_point(R, i, j, step);
+      const int strip = t / spr;
+      const int i = (t - strip * spr) * 64 + l;
+      if (i < nx) h2d_rows<4>(R, i, strip * 4, step);
     }
     if (t >= tiles_m) continue;
     s4 xb[kInferG][2];
@@ -598,7 +598,7 @@ __global__ __launch_bounds__(kInferWaves * 64) void k_mlp2d(const Run2D<float>* 
 hipError_t mlp_launch_cells2d(const void* run, const MlpWeights& W, const MlpCells2D& C,
                               int nx, int ny, int64_t step, hipStream_t st) {
   const int tiles_m = (2 * C.n + kWaveRows - 1) / kWaveRows;
-  const int tiles_h = row_segments(nx, ny, 64);
+  const int tiles_h = ((nx + 63) / 64) * ((ny + 3) / 4);
   const int tiles = tiles_m > tiles_h ? tiles_m : tiles_h;
   const int blocks = (tiles + kInferWaves - 1) / kInferWaves < 1024 ? (tiles + kInferWaves - 1) / kInferWaves : 1024;
   hipLaunchKernelGGL(k_mlp2d, dim3(blocks), dim3(kInferWaves * 64), 0, st,

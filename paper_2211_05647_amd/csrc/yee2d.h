@@ -1,9 +1,10 @@
-// yee2d.h -- per-point TEz Yee updates with the CPML (arXiv 2211.05647, section 2, eq.
+// yee2d.h -- TEz Yee updates with the CPML (arXiv 2211.05647, section 2, eq.
 // (2)-(5) and the CPML auxiliary fields of eq. (4)), shared by the 2D step kernels and the
 // closure kernel, which runs the H half-step beside the network.
 //
-// Work is mapped in row segments: a segment is `width` consecutive x points of one row,
-// so the row and column of a point come from one wave-uniform division per segment.
+// Work is mapped in strips: a work-group (wavefront in the closure kernel) takes a run of
+// consecutive columns, one per lane, and 1 or 4 rows, so the strip's row and column come
+// from one wave-uniform division and a row shared by two points is read once.
 #pragma once
 #include "common.h"
 
@@ -17,39 +18,10 @@ __device__ __forceinline__ void record_probe(const Run2D<T>& R, int field, int i
       R.probe_buf[(size_t)p * R.probe_cap + (size_t)(step % R.probe_cap)] = val;
 }
 
-// Hz^{n+1/2} at (i+1/2, j+1/2), 0 <= i < nx, 0 <= j < ny, with the H-side psi strips.
-template <class T>
-__device__ __forceinline__ void h2d_point(const Run2D<T>& R, int i, int j, int64_t step) {
-  const int nx = R.nx, ny = R.ny, m = R.m;
-  const size_t q = (size_t)j * nx + i;
-  const T dEx = R.Ex[q + nx] - R.Ex[q];
-  const T dEy = R.Ey[(size_t)j * (nx + 1) + i + 1] - R.Ey[(size_t)j * (nx + 1) + i];
-  T acc = dEx * R.rkhy[j] - dEy * R.rkhx[i];
-  if (m > 0) {
-    if (i < m || i >= nx - m) {
-      const int sx = i < m ? i : i - (nx - 2 * m);
-      T* p = R.psi_hzx + (size_t)j * (2 * m) + sx;
-      const T v = fma(R.bhx[i], *p, R.ahx[i] * dEy);
-      *p = v;
-      acc -= v;
-    }
-    if (j < m || j >= ny - m) {
-      const int sy = j < m ? j : j - (ny - 2 * m);
-      T* p = R.psi_hzy + (size_t)sy * nx + i;
-      const T v = fma(R.bhy[j], *p, R.ahy[j] * dEx);
-      *p = v;
-      acc += v;
-    }
-  }
-  const T hz = fma(R.S, acc, R.Hz[q]);
-  R.Hz[q] = hz;
-  if (R.nprobe) record_probe(R, 6 /* FDTD_F_HZ */, i, j, hz, step);
-}
-
-// Hz^{n+1/2} on rows j0 .. j0 + RR - 1 (those below ny) of column i < nx: every input of
-// the RR points is loaded before any arithmetic (RR + 1 Ex, 2 RR Ey and RR Hz values in
-// flight per lane, Ex of a shared row read once), then the RR updates, each with the
-// arithmetic of h2d_point.
+// Hz^{n+1/2} at (i+1/2, j+1/2) for rows j0 .. j0 + RR - 1 (those below ny) of column
+// i < nx, with the H-side psi strips: every input of the RR points is loaded before any
+// arithmetic (RR + 1 Ex, 2 RR Ey and RR Hz values in flight per lane, Ex of a shared row
+// read once).
 template <int RR, class T>
 __device__ __forceinline__ void h2d_rows(const Run2D<T>& R, int i, int j0, int64_t step) {
   const int nx = R.nx, ny = R.ny, m = R.m;
@@ -174,11 +146,6 @@ __device__ __forceinline__ void e2d_rows(const Run2D<T>& R, int i, int j0, int64
 __host__ __device__ inline int field_rows(int cols, int rows) {
   const int segs = (cols + 255) / 256;
   return segs * ((rows + 3) / 4) >= 2048 ? 4 : 1;
-}
-
-// Number of row segments of `width` points covering `rows` rows of `cols` points.
-__host__ __device__ inline int row_segments(int cols, int rows, int width) {
-  return ((cols + width - 1) / width) * rows;
 }
 
 }  // namespace fdtdp
