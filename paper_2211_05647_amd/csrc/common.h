@@ -137,6 +137,51 @@ __device__ __forceinline__ double wave_reduce4(const double (&a)[4], int& which)
   return t;
 }
 
+// FP64 sums of four rows held by lane groups of LPC = 8, 16 or 32 lanes (aligned to LPC),
+// one partial per row per lane, without LDS traffic: reduce-scatter rounds that halve the
+// rows a lane holds (v_permlane16_swap between the 16-lane halves of a 32-lane group,
+// then DPP mirrors across 8-lane halves, quads or lane pairs), then DPP rounds inside the
+// part of the group that holds one row.  Every lane returns the total of row `which`;
+// lane u * LPC / 4 of the group holds row u.
+template <int CTRL>
+__device__ __forceinline__ double xchg_sum(bool keep_first, double a, double b) {
+  // keep a and send b (keep_first), or keep b and send a; add the partner's sent value
+  const double keep = keep_first ? a : b, send = keep_first ? b : a;
+  return keep + dpp_f64<CTRL>(send);
+}
+
+template <int LPC>
+__device__ __forceinline__ double group_reduce4_dpp(const double (&a)[4], int& which) {
+  const int li = (int)(threadIdx.x & 63) & (LPC - 1);
+  double t;
+  if constexpr (LPC == 32) {
+    const double s0 = swap16_sum(a[0], a[2]);       // 16-lane half 0: a0, half 1: a2
+    const double s1 = swap16_sum(a[1], a[3]);       // half 0: a1, half 1: a3
+    t = xchg_sum<0x140>((li & 8) == 0, s0, s1);     // row_mirror across 8-lane halves
+    t += dpp_f64<0xB1>(t);                          // xor 1
+    t += dpp_f64<0x4E>(t);                          // xor 2
+    t += dpp_f64<0x141>(t);                         // row_half_mirror across quads
+    which = ((li & 16) ? 2 : 0) + ((li & 8) ? 1 : 0);
+  } else if constexpr (LPC == 16) {
+    const bool lo = (li & 8) == 0;                  // 8-lane half 0 keeps a0, a1
+    const double s0 = xchg_sum<0x140>(lo, a[0], a[2]);
+    const double s1 = xchg_sum<0x140>(lo, a[1], a[3]);
+    t = xchg_sum<0x141>((li & 4) == 0, s0, s1);     // row_half_mirror across quads
+    t += dpp_f64<0xB1>(t);
+    t += dpp_f64<0x4E>(t);
+    which = ((li & 8) ? 2 : 0) + ((li & 4) ? 1 : 0);
+  } else {
+    static_assert(LPC == 8, "lane groups of 8, 16 or 32");
+    const bool lo = (li & 4) == 0;                  // quad 0 keeps a0, a1
+    const double s0 = xchg_sum<0x141>(lo, a[0], a[2]);
+    const double s1 = xchg_sum<0x141>(lo, a[1], a[3]);
+    t = xchg_sum<0x4E>((li & 2) == 0, s0, s1);      // quad_perm [2,3,0,1] across pairs
+    t += dpp_f64<0xB1>(t);
+    which = ((li & 4) ? 2 : 0) + ((li & 2) ? 1 : 0);
+  }
+  return t;
+}
+
 struct Tile1D {
   int32_t run, node0, node1, cell0, cell1;
 };

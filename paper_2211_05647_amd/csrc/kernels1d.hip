@@ -122,13 +122,17 @@ __device__ __forceinline__ void kinetic_tile(const Run1D<T>& R, const T* eloc,
       int which = 0;
       bool done = false;
       if constexpr (U == 4) {
-        if (lpc == 64) {
-          // a row per wavefront: cross-lane swaps and DPP, no LDS round trips
-          const double tot = wave_reduce4(acc, which);
+        // cross-lane swaps and DPP, no LDS round trips
+        double tot = 0.0;
+        if (lpc == 64) tot = wave_reduce4(acc, which), done = true;
+        else if (lpc == 32) tot = group_reduce4_dpp<32>(acc, which), done = true;
+        else if (lpc == 16) tot = group_reduce4_dpp<16>(acc, which), done = true;
+        else if (lpc == 8) tot = group_reduce4_dpp<8>(acc, which), done = true;
+        if (done) {
+          const int step_u = lpc / 4;
 #pragma unroll
           for (int u = 0; u < U; ++u)
-            if (li == 16 * u && loc[u] >= 0) jloc[loc[u]] = (T)tot;
-          done = true;
+            if (li == step_u * u && loc[u] >= 0) jloc[loc[u]] = (T)tot;
         }
       }
       if (!done) {

@@ -174,10 +174,10 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
         for (int u = 0; u < kTbU; ++u)
           if (li == 16 * u) Js[loc[u]] = (float)tot;
       } else {
-        const double tot = group_reduce<kTbU>(acc, lpc, li, which);
+        const double tot = group_reduce4_dpp<LPC>(acc, which);
 #pragma unroll
         for (int u = 0; u < kTbU; ++u)
-          if (li == reporter<kTbU>(u, lpc)) Js[loc[u]] = (float)tot;
+          if (li == u * (LPC / 4)) Js[loc[u]] = (float)tot;
       }
     }
     __syncthreads();
