@@ -82,16 +82,18 @@ __device__ __forceinline__ void kinetic_tile(const Run1D<T>& R, const T* eloc,
       acc[u] = 0.0;
       if (loc[u] >= 0) {
         const T nE = ne[u] * eloc[loc[u]];
+        const T tau2 = tau[u] + tau[u];
 #pragma unroll
         for (int m = 0; m < CPL; ++m) {
           if (m < cpl) {
 #pragma unroll
             for (int v = 0; v < VPL; ++v) {
-              const T x = tau[u] * lane_at(s[m], v);       // dt * nu_j
-              const T r = cn_recip(T(2) + x);
+              // x = dt nu_j; F1' = ((2 - x) F1 + 2 dt (e/m) n dF0/dv E) / (2 + x), as an
+              // increment; 2 x = (2 dt nu_mean) s_j exactly
+              const T r = cn_recip(fma(tau[u], lane_at(s[m], v), T(2)));
+              const T x2 = tau2 * lane_at(s[m], v);
               const T fv = lane_at(f[u][m], v);
-              // F1' = ((2 - x) F1 + 2 dt (e/m) n dF0/dv E) / (2 + x), as an increment
-              const T t = fma(-(x + x), fv, lane_at(b[m], v) * nE);
+              const T t = fma(-x2, fv, lane_at(b[m], v) * nE);
               const T fn = fma(t, r, fv);
               lane_at(f[u][m], v) = fn;
               acc[u] = fma(w[m][v], (double)fn, acc[u]);

@@ -133,7 +133,6 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
 #pragma unroll
       for (int u = 0; u < kTbU; ++u) {
         const int cl = row_slot(it * kTbU + u, wv, sub);
-        acc[u] = 0.0;
         loc[u] = kTbBlock;            // rows without a valid E report to the spare slot
         bool live = cl < ncell;
         int lc = 0;
@@ -154,16 +153,22 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
         if (live) {
           loc[u] = lc;
           const float nE = ne * Es[p][lc];
+          const float tau2 = tau + tau;
+          double a = 0.0;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const float x = tau * lane_at(sb, v);
-            const float r = cn_recip(2.f + x);
+            // x = dt nu_j; (2 x) = (2 dt nu_mean) s_j exactly
+            const float r = cn_recip(fmaf(tau, lane_at(sb, v), 2.f));
+            const float x2 = tau2 * lane_at(sb, v);
             const float fv = lane_at(f[it][u], v);
-            const float t = fmaf(-(x + x), fv, lane_at(bb, v) * nE);
+            const float t = fmaf(-x2, fv, lane_at(bb, v) * nE);
             const float fn = fmaf(t, r, fv);
             lane_at(f[it][u], v) = fn;
-            acc[u] = fma(w[v], (double)fn, acc[u]);
+            a = fma(w[v], (double)fn, a);
           }
+          acc[u] = a;
+        } else {
+          acc[u] = 0.0;   // zero only on the (uniform, for 64-lane rows) path of idle rows
         }
       }
       int which = 0;
