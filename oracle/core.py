@@ -39,7 +39,7 @@ def lib():
              C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
              C.c_longlong, C.c_longlong,
              _dp, _dp, _dp, _dp,
-             C.c_int, _ip, _dp, C.c_int, _dp])
+             C.c_int, _ip, _dp, C.c_int, _dp, C.c_int])
         L.oracle_run2d.argtypes = (
             [C.c_int, C.c_int, C.c_double, C.c_double,
              C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
@@ -55,6 +55,8 @@ def lib():
         L.oracle_mlp.restype = C.c_double
         L.oracle_replay1v.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, C.c_double,
                                       C.c_double, C.c_double, C.c_longlong, _dp, _dp]
+        L.oracle_full1v.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, C.c_double,
+                                    C.c_double, C.c_double, C.c_longlong, _dp, _dp, _dp]
         L.oracle_replay2v.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, C.c_double,
                                       C.c_double, C.c_double, C.c_longlong, _dp, _dp, _dp, _dp]
         _lib = L
@@ -135,6 +137,25 @@ def replay1v(E, ne, nubar, dt, nv=64, vmax_over_vth=6.0, te_ev=2.0, nu_model="ha
     return J
 
 
+def full1v(E, ne, nubar, dt, delta=None, nv=64, vmax_over_vth=6.0, te_ev=2.0,
+           nu_model="hard_sphere"):
+    """One isolated node of the full-distribution model driven by E[n] = E^n.
+
+    ``delta`` (nv values, f = ne fhat + delta) is advanced in place when given (zeros
+    otherwise); returns (J^{n+1/2} series in A/m^2, delta)."""
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    J = np.zeros_like(E)
+    d = np.zeros(nv) if delta is None else delta
+    assert d.dtype == np.float64 and d.shape == (nv,) and d.flags["C_CONTIGUOUS"]
+    rc = lib().oracle_full1v(nv, vmax_over_vth, te_ev, {"hard_sphere": 0, "const": 1}[nu_model],
+                             ne, nubar, dt, len(E), _p(E), _p(d), _p(J))
+    if rc == -2:
+        raise ValueError("field too strong for the velocity grid: |a dt / dv| > 1")
+    if rc:
+        raise ValueError("bad arguments")
+    return J, d
+
+
 def replay2v(Ex, Ey, ne, nubar, dt, nv=32, vmax_over_vth=6.0, te_ev=5.0, nu_model="hard_sphere"):
     """One isolated 2V cell driven by (Ex, Ey)[n]; returns (Jx, Jy)^{n+1/2} (A/m^2)."""
     Ex = np.ascontiguousarray(Ex, dtype=np.float64)
@@ -151,11 +172,14 @@ class Oracle1D:
     """1D (Ez, Hy) Yee grid coupled to a 1V kinetic F1 in every plasma node.
 
     ``ne``/``nubar`` are per E node (nx+1 values).  ``bc`` is ``"mur"`` or ``"pec"``.
+    ``kinetic`` is ``"linear"`` (F1 against the frozen F0) or ``"full"`` (the whole f
+    evolves; ``df`` then holds f - ne fhat per node).
     """
 
     def __init__(self, nx, dx, courant, ne, nubar, nv=64, vmax_over_vth=6.0, te_ev=2.0,
                  nu_model="hard_sphere", bc="mur", src_node=0, src_amp=0.0, src_f=0.0,
-                 src_tau=1.0, src_t0=0.0):
+                 src_tau=1.0, src_t0=0.0, kinetic="linear"):
+        self.model = {"linear": 0, "full": 1}[kinetic]
         self.nx, self.dx, self.courant = int(nx), float(dx), float(courant)
         self.ne = np.ascontiguousarray(ne, dtype=np.float64)
         self.nubar = np.ascontiguousarray(nubar, dtype=np.float64)
@@ -185,7 +209,9 @@ class Oracle1D:
             self.step, int(nsteps),
             _p(self.E), _p(self.H), _p(self.J), _p(self.df),
             len(probes), _p(probes) if len(probes) else None, _p(pout),
-            int(snap_every), _p(sout))
+            int(snap_every), _p(sout), self.model)
+        if rc == -2:
+            raise ValueError("field too strong for the velocity grid: |a dt / dv| > 1")
         if rc:
             raise ValueError("oracle_run1d rejected its arguments")
         self.step += int(nsteps)

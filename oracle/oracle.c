@@ -36,6 +36,19 @@
  *   - 2D TEz: F1 lives at plasma cell centres; E is averaged from the two
  *     bounding edges to the centre and J is averaged back to each edge with
  *     the transposed weights, so field-to-plasma work is exchanged exactly.
+ *   - full-distribution model (model = 1, 1V): instead of freezing F0 and
+ *     evolving F1 alone, the whole f of each plasma node evolves under
+ *     df/dt - (e/m) E df/dv = C(f) (the kinetic equation of section 5.1 with
+ *     the streaming and magnetic terms dropped as in section 5.2); in 1V its
+ *     even part plays F0 (the l = 0 equation: it heats) and its odd part F1.
+ *     Stored: delta = f - n F0hat (zero at start), on the full signed grid.
+ *     Velocity derivative in conservative flux form with the Lax-Wendroff
+ *     flux (second order, stable for |a dt/dv| <= 1) and zero flux through
+ *     +-vmax, so the electron number is conserved exactly; the collision term
+ *     acts on the odd part with the same Crank-Nicolson factor as the linear
+ *     model, and the drive is taken at E^n.  For small fields the odd part
+ *     obeys the linear model's update with dF0/dv replaced by a central
+ *     difference.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -153,6 +166,87 @@ static double source_wave(double t, double amp, double f, double tau, double t0)
  * Snapshots: E after every snap_every-th step, snap_E[k * (nx+1) + i].
  * Returns 0, or -1 on bad arguments.
  * ------------------------------------------------------------------------- */
+/* ---------------------------------------------------------------------------
+ * One step of the full-distribution model for one plasma node: delta (nv
+ * values, f = nf0 + delta) from level n-1/2 to n+1/2 with the acceleration
+ * a = -(e/m) E^n, c = a dt / dv; nf0 = n * fhat, nu_j = nubar * sh_j.
+ * f splits into its even part fe = nf0 + e and odd part o (o_j = -o_{nv-1-j}).
+ * Both parts are advanced in conservative flux form with zero flux through
+ * the outer faces of the grid (work: nv + 1 faces in gbuf, nv values in obuf):
+ *   odd:  p_{j+1/2} = (c/2)(fe_j + fe_{j+1}) - (c^2/2)(o_{j+1} - o_j),
+ *         o'_j = ((2 - dt nu_j) o_j - 2 (p_{j+1/2} - p_{j-1/2})) / (2 + dt nu_j)
+ *         (the linear model's Crank-Nicolson collision step with its drive;
+ *         the c^2 term is the Lax-Wendroff correction of the advection);
+ *   even: q_{j+1/2} = (c/4)(o_j + o'_j + o_{j+1} + o'_{j+1}),
+ *         e'_j = e_j - (q_{j+1/2} - q_{j-1/2})
+ *         (the odd part time-centred, so that the energy it hands to the even
+ *         part is second order in dt also with collisions).
+ * ------------------------------------------------------------------------- */
+static void full_cell_step(int nv, const double *nf0, const double *sh, double nubar,
+                           double dt, double c, double *delta, double *gbuf, double *obuf)
+{
+    gbuf[0] = 0.0;
+    gbuf[nv] = 0.0;
+    /* odd part: p on the inner faces */
+    for (int j = 0; j + 1 < nv; ++j) {
+        int m = nv - 1 - j, mr = nv - 2 - j;           /* mirrors of j and j + 1 */
+        double fel = nf0[j] + 0.5 * (delta[j] + delta[m]);
+        double fer = nf0[j + 1] + 0.5 * (delta[j + 1] + delta[mr]);
+        double ol = 0.5 * (delta[j] - delta[m]), orr = 0.5 * (delta[j + 1] - delta[mr]);
+        gbuf[j + 1] = 0.5 * c * (fel + fer) - 0.5 * c * c * (orr - ol);
+    }
+    for (int j = 0; j < nv; ++j) {
+        int m = nv - 1 - j;
+        double o = 0.5 * (delta[j] - delta[m]);
+        double x = dt * nubar * sh[j];
+        obuf[j] = ((2.0 - x) * o - 2.0 * (gbuf[j + 1] - gbuf[j])) / (2.0 + x);
+    }
+    /* even part: q on the inner faces from the time-centred odd part */
+    for (int j = 0; j + 1 < nv; ++j) {
+        int m = nv - 1 - j, mr = nv - 2 - j;
+        double ol = 0.5 * (delta[j] - delta[m]), orr = 0.5 * (delta[j + 1] - delta[mr]);
+        gbuf[j + 1] = 0.25 * c * (ol + obuf[j] + orr + obuf[j + 1]);
+    }
+    double en[nv];
+    for (int j = 0; j < nv; ++j) {
+        int m = nv - 1 - j;
+        en[j] = 0.5 * (delta[j] + delta[m]) - (gbuf[j + 1] - gbuf[j]);
+    }
+    for (int j = 0; j < nv; ++j) delta[j] = en[j] + obuf[j];
+}
+
+/* Isolated node of the full-distribution model driven by E[n] = E^n: delta
+ * (nv values, in/out, f = n fhat + delta) and J[n] = J^{n+1/2} (A/m^2).
+ * Returns -1 on bad arguments, -2 if |a dt/dv| > 1 at some step. */
+int oracle_full1v(int nv, double vmax_over_vth, double te_ev, int nu_model,
+                  double ne, double nubar, double dt, long long nsteps,
+                  const double *E, double *delta, double *J)
+{
+    if (nv < 2 || (nv & 1)) return -1;
+    double *v = malloc(sizeof(double) * nv), *fh = malloc(sizeof(double) * nv);
+    double *gh = malloc(sizeof(double) * nv), *sh = malloc(sizeof(double) * nv);
+    double *nf0 = malloc(sizeof(double) * nv), *g = malloc(sizeof(double) * (nv + 1));
+    double *ob = malloc(sizeof(double) * nv);
+    double dv, vth;
+    int rc = 0;
+    if (oracle_vgrid(nv, vmax_over_vth, te_ev, v, fh, gh, &dv, &vth) != 0) {
+        rc = -1;
+    } else {
+        oracle_nu_shape(1, nv, v, fh, dv, nu_model, sh);
+        for (int j = 0; j < nv; ++j) nf0[j] = ne * fh[j];
+        for (long long n = 0; n < nsteps && rc == 0; ++n) {
+            double c = -(K_QE / K_ME) * E[n] * dt / dv;
+            if (fabs(c) > 1.0) { rc = -2; break; }
+            full_cell_step(nv, nf0, sh, nubar, dt, c, delta, g, ob);
+            double acc = 0.0;
+            for (int j = 0; j < nv; ++j) acc += v[j] * delta[j];
+            J[n] = -K_QE * dv * acc;
+        }
+    }
+    free(v); free(fh); free(gh); free(sh); free(nf0); free(g); free(ob);
+    return rc;
+}
+
 int oracle_run1d(int nx, double dx, double courant, int bc,
                  int nv, double vmax_over_vth, double te_ev, int nu_model,
                  const double *ne, const double *nubar,
@@ -160,9 +254,10 @@ int oracle_run1d(int nx, double dx, double courant, int bc,
                  long long step0, long long nsteps,
                  double *E, double *H, double *J, double *df,
                  int nprobe, const int *probe_node, double *probe_E,
-                 int snap_every, double *snap_E)
+                 int snap_every, double *snap_E, int model)
 {
     if (nx < 2 || nv < 2 || dx <= 0.0 || courant <= 0.0 || courant > 1.0) return -1;
+    if (model != 0 && model != 1) return -1;
     if (ne[0] > 0.0 || ne[nx] > 0.0) return -1;
     double dt = courant * dx / K_C0;
 
@@ -189,21 +284,32 @@ int oracle_run1d(int nx, double dx, double courant, int bc,
         /* 1. Faraday: H^{n+1/2} = H^{n-1/2} + dt/(mu0 dx) (E_{i+1} - E_i) */
         for (int i = 0; i < nx; ++i) H[i] += ch * (E[i + 1] - E[i]);
 
-        /* 2-3. F1 update driven by E^n (section 5.2 update of f_1x), then the
-         *      current moment J^{n+1/2} = -e dv sum_j v_j F1_j. */
-        #pragma omp parallel for schedule(static)
+        /* 2-3. F1 update driven by E^n (section 5.2 update of f_1x), or the
+         *      full-distribution step, then the current moment
+         *      J^{n+1/2} = -e dv sum_j v_j F1_j (F1: the odd part of delta). */
+        int bad = 0;
+        #pragma omp parallel for schedule(static) reduction(|:bad)
         for (int c = 0; c < ncell; ++c) {
             int i = cell_node[c];
             double *f = df + (size_t)c * nv;
             double acc = 0.0;
-            for (int j = 0; j < nv; ++j) {
-                double nu = nubar[i] * sh[j];
-                f[j] = ((2.0 - dt * nu) * f[j]
-                        + 2.0 * dt * (K_QE / K_ME) * ne[i] * gh[j] * E[i]) / (2.0 + dt * nu);
-                acc += v[j] * f[j];
+            if (model == 0) {
+                for (int j = 0; j < nv; ++j) {
+                    double nu = nubar[i] * sh[j];
+                    f[j] = ((2.0 - dt * nu) * f[j]
+                            + 2.0 * dt * (K_QE / K_ME) * ne[i] * gh[j] * E[i]) / (2.0 + dt * nu);
+                }
+            } else {
+                double nf0[nv], g[nv + 1], ob[nv];
+                for (int j = 0; j < nv; ++j) nf0[j] = ne[i] * fh[j];
+                double cfl = -(K_QE / K_ME) * E[i] * dt / dv;
+                if (fabs(cfl) > 1.0) bad = 1;
+                full_cell_step(nv, nf0, sh, nubar[i], dt, cfl, f, g, ob);
             }
+            for (int j = 0; j < nv; ++j) acc += v[j] * f[j];
             J[i] = -K_QE * dv * acc;
         }
+        if (bad) { free(v); free(fh); free(gh); free(sh); free(cell_node); return -2; }
 
         /* 4. Ampere: E^{n+1} = E^n + dt/(eps0 dx)(H_{i+1/2} - H_{i-1/2}) - dt/eps0 J^{n+1/2} */
         double e0 = E[0], e1 = E[1], en1 = E[nx - 1], en = E[nx];
