@@ -56,12 +56,14 @@ enum fdtd_boundary { FDTD_BC_PEC = 0, FDTD_BC_MUR1 = 1, FDTD_BC_CPML = 2 };
 enum fdtd_nu_model { FDTD_NU_HARD_SPHERE = 0, FDTD_NU_CONST = 1 };
 enum fdtd_closure_kind { FDTD_CLOSURE_KINETIC = 0, FDTD_CLOSURE_MLP = 1 };
 enum fdtd_source_kind { FDTD_SRC_NONE = 0, FDTD_SRC_LINE_SOFT = 1, FDTD_SRC_POINT_SOFT = 2 };
+enum fdtd_kinetic_model { FDTD_KINETIC_LINEAR = 0, FDTD_KINETIC_FULL = 1 };
 
 /* Field selectors for read_fields / add_probe.
  * 1D grids (Ez at nodes i = 0..nx, Hy at i + 1/2):
  *   FDTD_F_E  Ez [nx+1] V/m,  FDTD_F_H Hy [nx] A/m,  FDTD_F_J Jz [nx+1] A/m^2,
  *   FDTD_F_DF F1 on the full signed velocity grid, [ncell][nv] (s/m^4), plasma nodes
- *             in increasing order (mirror bins reconstructed from the stored half).
+ *             in increasing order (mirror bins reconstructed from the stored half);
+ *             with the full kinetic model, f - ne fhat on that grid.
  * 2D TEz grids (Ex at (i+1/2, j), Ey at (i, j+1/2), Hz at (i+1/2, j+1/2)):
  *   FDTD_F_EX [ny+1][nx], FDTD_F_EY [ny][nx+1], FDTD_F_HZ [ny][nx] (A/m),
  *   FDTD_F_JX [ny+1][nx], FDTD_F_JY [ny][nx+1] (edge currents, A/m^2),
@@ -95,7 +97,15 @@ typedef struct {
  * at zero.  nv bins per velocity axis (a power of two, >= 8), cell-centred on
  * +-vmax_over_vth * v_th.  nu_model HARD_SPHERE: nu(v) = N s |v| scaled so its
  * Maxwellian mean is nu_mean; CONST: nu = nu_mean.  closure: KINETIC, or MLP with the
- * network blob `mlp` (fdtd_mlp_blob) and the kinetic step as fallback. */
+ * network blob `mlp` (fdtd_mlp_blob) and the kinetic step as fallback.
+ * kinetic: LINEAR is the model of section 5.2 (F0 frozen, F1 driven by E dF0/dv).
+ * FULL (1D single runs only) evolves the whole f of each plasma node under
+ * df/dt - (e/m) E df/dv = C(f) (the kinetic equation of section 5.1 without the
+ * streaming and magnetic terms): its even part is the l = 0 equation's F0, which heats,
+ * its odd part F1.  The velocity derivative is in conservative flux form with zero flux
+ * through +-vmax (electron number is kept exactly) and is explicit: each step needs
+ * |(e/m) E dt / dv| <= 1, and a step that breaks it sets the run status (see
+ * fdtd_plasma_run_status).  FULL runs are never temporally blocked. */
 typedef struct {
   const double *ne;
   const double *nu_mean;
@@ -105,6 +115,7 @@ typedef struct {
   int32_t nu_model;
   int32_t closure;
   const void *mlp;
+  int32_t kinetic;
 } fdtd_profile;
 
 /* Soft source (section 5.2 table): adds amplitude * sin(2 pi f (t - t0))

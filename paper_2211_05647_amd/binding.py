@@ -18,6 +18,7 @@ FP64, FP32 = 0, 1
 BC_PEC, BC_MUR1, BC_CPML = 0, 1, 2
 NU_HARD_SPHERE, NU_CONST = 0, 1
 CLOSURE_KINETIC, CLOSURE_MLP = 0, 1
+KINETIC_LINEAR, KINETIC_FULL = 0, 1
 SRC_NONE, SRC_LINE, SRC_POINT = 0, 1, 2
 F_E, F_H, F_J, F_DF, F_EX, F_EY, F_HZ, F_JX, F_JY, F_JCX, F_JCY = range(11)
 
@@ -38,7 +39,7 @@ class Grid(C.Structure):
 class Profile(C.Structure):
     _fields_ = [("ne", _dp), ("nu_mean", _dp), ("te_ev", C.c_double), ("nv", C.c_int32),
                 ("vmax_over_vth", C.c_double), ("nu_model", C.c_int32),
-                ("closure", C.c_int32), ("mlp", C.c_void_p)]
+                ("closure", C.c_int32), ("mlp", C.c_void_p), ("kinetic", C.c_int32)]
 
 
 class Source(C.Structure):
@@ -177,7 +178,8 @@ class Sim:
                 mlp_ptr = mlp_blob.ctypes.data_as(C.c_void_p)
             p = Profile(pne, pnu, w.te_ev, w.nv, w.vmax_over_vth,
                         NU_HARD_SPHERE if w.nu_model == "hard_sphere" else NU_CONST,
-                        closure, mlp_ptr)
+                        closure, mlp_ptr,
+                        KINETIC_FULL if getattr(w, "kinetic", "linear") == "full" else KINETIC_LINEAR)
             grids.append(g)
             profs.append(p)
             srcs.append(src)

@@ -215,6 +215,11 @@ template <class T> struct Run1D {
   int64_t tap_cap;
   int32_t* status; // bit 0: a non-finite E value was produced
   const int32_t* chunk_cell;  // [nchunk + 1] first plasma cell of each kBatchBlock-node chunk
+  // kinetic model: 0 linear F1 (df: [ncell][half]); 1 full distribution (df:
+  // [ncell][2 half], odd then even half of f - n fhat; b_bin then holds the equilibrium
+  // flux differences -(dt/dv)(-e/m)(fhat_{k+1} - fhat_{k-1}) per unit density and field)
+  int32_t model;
+  T kc;            // -(e/m) dt / dv: the velocity CFL number per unit E
 };
 
 // One 2D TEz run.  Ex [ny+1][nx] at (i+1/2, j), Ey [ny][nx+1] at (i, j+1/2),

@@ -312,6 +312,8 @@ int validate_2d(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s)
     return fail(FDTD_EINVAL, "te_ev and vmax_over_vth must be > 0");
   if (p->nu_model != FDTD_NU_HARD_SPHERE && p->nu_model != FDTD_NU_CONST)
     return fail(FDTD_EINVAL, "unknown nu_model %d", p->nu_model);
+  if (p->kinetic != FDTD_KINETIC_LINEAR)
+    return fail(FDTD_EINVAL, "2D runs take the linear kinetic model");
   if (p->closure == FDTD_CLOSURE_MLP) {
     if (g->precision != FDTD_FP32) return fail(FDTD_EINVAL, "the learned closure runs in FP32");
     const fdtd_mlp_blob* b = reinterpret_cast<const fdtd_mlp_blob*>(p->mlp);

@@ -116,6 +116,10 @@ int validate_1d(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s,
     return fail(FDTD_EINVAL, "unknown nu_model %d", p->nu_model);
   if (p->closure != FDTD_CLOSURE_KINETIC)
     return fail(FDTD_EINVAL, "1D runs take the kinetic closure");
+  if (p->kinetic != FDTD_KINETIC_LINEAR && p->kinetic != FDTD_KINETIC_FULL)
+    return fail(FDTD_EINVAL, "unknown kinetic model %d", p->kinetic);
+  if (batch && p->kinetic != FDTD_KINETIC_LINEAR)
+    return fail(FDTD_EINVAL, "batched runs take the linear kinetic model");
   if (!p->ne || !p->nu_mean) return fail(FDTD_EINVAL, "null ne or nu_mean");
   const int nx = g->nx;
   for (int i = 0; i <= nx; ++i) {
@@ -220,12 +224,14 @@ size_t layout_1d(fdtd_plasma* h, const std::vector<RunSpec1D>& specs, int precis
     x.nx = sp.g.nx;
     x.nv = sp.p.nv;
     x.half = sp.p.nv / 2;
+    x.model = sp.p.kinetic;
+    x.row = x.model == FDTD_KINETIC_FULL ? sp.p.nv : x.half;
     x.ncell = 0;
     for (int i = 0; i <= x.nx; ++i) if (sp.p.ne[i] > 0) ++x.ncell;
     for (int b = 0; b < 2; ++b) x.off_E[b] = cv.take((size_t)(x.nx + 1) * es);
     for (int b = 0; b < 2; ++b) x.off_H[b] = cv.take((size_t)(x.nx + 1) * es);
     x.off_J = cv.take((size_t)(x.nx + 1) * es);
-    x.off_df = cv.take((size_t)std::max(x.ncell, 1) * x.half * es);
+    x.off_df = cv.take((size_t)std::max(x.ncell, 1) * x.row * es);
   }
   const size_t state_end = cv.size();
   const size_t probe_off = cv.take((size_t)std::max(max_probes, 1) * std::max(probe_cap, 1) * es);
@@ -287,6 +293,17 @@ int upload_1d(fdtd_plasma* h) {
       s[k] = (T)(sp.p.nu_model == FDTD_NU_HARD_SPHERE ? std::fabs(vt.v[j]) / vt.mean_speed : 1.0);
       b[k] = (T)(2.0 * dt * (kQe / kMe) * g);
       w[k] = (dt / kEps0) * (-2.0 * kQe * vt.dv) * vt.v[j];
+    }
+    // full model: velocity CFL number per unit field, and the equilibrium part's face-flux
+    // difference per unit density and field, -kc (fhat_{j+1} - fhat_{j-1}) (no flux
+    // through +vmax: -kc (-(fhat_{j-1} + fhat_j)) on the last bin)
+    const double kc = -(kQe / kMe) * dt / vt.dv;
+    if (x.model == FDTD_KINETIC_FULL) {
+      for (int k = 0; k < half; ++k) {
+        const int j = half + k;
+        const double d0 = k + 1 < half ? vt.f[j + 1] - vt.f[j - 1] : -(vt.f[j - 1] + vt.f[j]);
+        b[k] = (T)(-kc * d0);
+      }
     }
     std::vector<int32_t> cn;
     std::vector<T> tau, dens;
@@ -359,6 +376,8 @@ int upload_1d(fdtd_plasma* h) {
     R.tap_cap = x.tap_cap;
     R.status = reinterpret_cast<int32_t*>(base + h->status_off) + r;
     R.chunk_cell = reinterpret_cast<const int32_t*>(base + x.off_chunk);
+    R.model = x.model;
+    R.kc = (T)kc;
   }
   // probes
   for (size_t p = 0; p < h->probes.size(); ++p) {
@@ -396,7 +415,7 @@ int build_tb_tiles(fdtd_plasma* h) {
   if (k < 3 || h->precision != FDTD_FP32) return FDTD_OK;
   for (int r = 0; r < h->nruns; ++r) {
     const Host1D& x = h->h1[r];
-    if (!tb_supported(x.half)) return FDTD_OK;
+    if (x.model != FDTD_KINETIC_LINEAR || !tb_supported(x.half)) return FDTD_OK;
     if (std::min(tb_block(), tb_max_rows(x.half)) - 2 * k < 32) return FDTD_OK;
   }
   int cus = 256;
@@ -458,7 +477,7 @@ int build_tiles_1d(fdtd_plasma* h) {
   for (int r = 0; r < h->nruns; ++r) {
     const Host1D& x = h->h1[r];
     const int es = elem_size(h->precision);
-    int tile = h->tile > 0 ? h->tile : default_tile_1d(x.half, es, x.nx, x.ncell);
+    int tile = h->tile > 0 ? h->tile : default_tile_1d(x.row, es, x.nx, x.ncell);
     tile = std::max(32, std::min(kMaxTile1D, tile));
     int c = 0;
     for (int n0 = 0; n0 <= x.nx; n0 += tile) {
@@ -491,7 +510,7 @@ int build_tiles_1d(fdtd_plasma* h) {
   auto work = [&](int r) {
     const Host1D& x = h->h1[r];
     const double st = h->specs[r].steps == INT64_MAX ? 1.0 : (double)h->specs[r].steps;
-    return st * ((double)x.ncell * x.half + 5.0 * (x.nx + 1));
+    return st * ((double)x.ncell * x.row + 5.0 * (x.nx + 1));
   };
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
   e = hipMemcpyAsync(h->ws + h->order_off, order.data(), order.size() * 4, hipMemcpyHostToDevice,
@@ -767,7 +786,7 @@ int fdtd_plasma_run(fdtd_plasma* h, int64_t nsteps) {
         const int p1 = count_ge(h->tile_limit, s + kb), p2 = count_ge(h->tile_limit, s + 1);
         for (int64_t ss = s; p2 > p1 && ss < s + kb; ++ss) {
           const int n = count_ge(h->tile_limit, ss + 1) - p1;
-          e = launch_step1d<float>(h->ws + h->runs_off, rt + p1, n, ss, h->stream);
+          e = launch_step1d<float>(h->ws + h->runs_off, rt + p1, n, ss, h->stream, false);
           if (e) return hip_fail(e, "launch step kernel");
         }
       }
@@ -783,9 +802,11 @@ int fdtd_plasma_run(fdtd_plasma* h, int64_t nsteps) {
                                    [](int64_t v, int64_t lim) { return v >= lim; }) -
                   h->tile_limit.begin());
       }
+      // full-model runs are single runs (never batched), so run 0 decides the kernel
+      const bool full = h->h1[0].model == FDTD_KINETIC_FULL;
       e = h->precision == FDTD_FP64
-              ? launch_step1d<double>(h->ws + h->runs_off, h->ws + h->tiles_off, n, s, h->stream)
-              : launch_step1d<float>(h->ws + h->runs_off, h->ws + h->tiles_off, n, s, h->stream);
+              ? launch_step1d<double>(h->ws + h->runs_off, h->ws + h->tiles_off, n, s, h->stream, full)
+              : launch_step1d<float>(h->ws + h->runs_off, h->ws + h->tiles_off, n, s, h->stream, full);
     } else {
       e = launch_step2d(h->h2, s, h->stream);
     }
@@ -851,7 +872,7 @@ int fdtd_plasma_read_fields(fdtd_plasma* h, int32_t run, int32_t field, double* 
       case FDTD_F_E: off = x.off_E[par]; cnt = x.nx + 1; break;
       case FDTD_F_H: off = x.off_H[par]; cnt = x.nx; scale = 1.0 / kEta0; break;
       case FDTD_F_J: off = x.off_J; cnt = x.nx + 1; scale = kEps0 / x.dt; break;
-      case FDTD_F_DF: off = x.off_df; cnt = (size_t)x.ncell * x.half; break;
+      case FDTD_F_DF: off = x.off_df; cnt = (size_t)x.ncell * x.row; break;
     }
     std::vector<char> buf(std::max<size_t>(cnt, 1) * es);
     if (cnt) {
@@ -861,7 +882,15 @@ int fdtd_plasma_read_fields(fdtd_plasma* h, int32_t run, int32_t field, double* 
     auto val = [&](size_t k) -> double {
       return es == 8 ? reinterpret_cast<double*>(buf.data())[k] : reinterpret_cast<float*>(buf.data())[k];
     };
-    if (field == FDTD_F_DF) {
+    if (field == FDTD_F_DF && x.model == FDTD_KINETIC_FULL) {
+      // row: odd half then even half on the v > 0 bins
+      for (int c = 0; c < x.ncell; ++c)
+        for (int k = 0; k < x.half; ++k) {
+          const double o = val((size_t)c * x.nv + k), ev = val((size_t)c * x.nv + x.half + k);
+          dst[(size_t)c * x.nv + x.half + k] = ev + o;
+          dst[(size_t)c * x.nv + x.half - 1 - k] = ev - o;
+        }
+    } else if (field == FDTD_F_DF) {
       for (int c = 0; c < x.ncell; ++c)
         for (int k = 0; k < x.half; ++k) {
           const double f = val((size_t)c * x.half + k);
@@ -1056,6 +1085,8 @@ int fdtd_plasma_run_status(fdtd_plasma* h, int32_t run, int32_t* status) {
   e = hipMemcpy(&v, h->ws + h->status_off + 4 * (size_t)run, 4, hipMemcpyDeviceToHost);
   if (e) return hip_fail(e, "copy status");
   *status = v ? FDTD_ENUMERIC : FDTD_OK;
+  if (v & 2) fail(FDTD_ENUMERIC, "run %d: a field broke the velocity CFL limit", run);
+  else if (v & 1) fail(FDTD_ENUMERIC, "run %d: non-finite field", run);
   return FDTD_OK;
 }
 

@@ -50,6 +50,8 @@ struct ProbeInfo {
 
 struct Host1D {
   int nx = 0, nv = 0, half = 0, ncell = 0;
+  int model = 0;      // FDTD_KINETIC_LINEAR / FULL
+  int row = 0;        // stored values per plasma node: half (linear) or nv (full)
   double dt = 0;
   VTable vt;
   std::vector<int32_t> cell_node;
@@ -63,7 +65,7 @@ struct Host1D {
 // 1D launch (kernels1d.hip)
 template <class T>
 hipError_t launch_step1d(const void* runs, const void* tiles, int ntiles, int64_t step,
-                         hipStream_t stream);
+                         hipStream_t stream, bool full);
 
 hipError_t launch_batch1d_persistent(const void* runs, const int32_t* order, int nruns,
                                      int32_t* queue, int64_t s0, int64_t s1, int groups,

@@ -147,9 +147,187 @@ __device__ __forceinline__ void kinetic_tile(const Run1D<T>& R, const T* eloc,
   }
 }
 
+// Full-distribution model: the whole f of each plasma node evolves under
+// df/dt - (e/m) E df/dv = C(f) (section 5.1 without streaming and magnetic terms; elastic
+// collisions damp the odd part as in section 5.2).  Row of a plasma node: [odd | even]
+// halves of delta = f - n fhat on the v > 0 bins, o_k and e_k (the v < 0 bins are their
+// mirrors).  With c = a dt / dv (a = -(e/m) E^n) and zero flux through +-vmax:
+//   odd:  p_{k+1/2} = (c/2)(e_k + e_{k+1}) - (c^2/2)(o_{k+1} - o_k)   (perturbation faces;
+//         the face at v = 0 carries c e_0 - c^2 o_0), plus the equilibrium part n fhat
+//         whose face differences come precomputed in b_bin (times n E);
+//         o'_k = o_k + (-2x o_k + b_k n E - 2 (p_{k+1/2} - p_{k-1/2})) / (2 + x);
+//   even: q_{k+1/2} = (c/4)(s_k + s_{k+1}), s = o + o' (zero at v = 0 and at vmax);
+//         e'_k = e_k - (q_{k+1/2} - q_{k-1/2});
+//   J = -e dv sum over both halves of v f = the linear model's moment of o'.
+// A lane group of lpc lanes holds a row in 16-byte chunks (chunk li + m lpc of each half);
+// the neighbour bins across chunk edges come from the next / previous lane by shuffles.
+template <class T, int CPL, int NT>
+__device__ __forceinline__ void kinetic_tile_full(const Run1D<T>& R, const T* eloc,
+                                                  const Tile1D& tile, T* jloc) {
+  using V = typename Vec<T>::type;
+  constexpr int VPL = Vec<T>::n;
+  constexpr int kWaves = NT / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ch = R.half / VPL;            // chunks per half row
+  const int lpc = ch < 64 ? ch : 64;      // lanes per row; ch == CPL * lpc by dispatch
+  const int cpw = 64 / lpc;
+  const int sub = lane / lpc, li = lane - sub * lpc;
+  const int nxt = sub * lpc + ((li + 1) & (lpc - 1));
+  const int prv = sub * lpc + ((li - 1) & (lpc - 1));
+  const bool last_lane = li == lpc - 1, first_lane = li == 0;
+
+  V s[CPL], b[CPL];
+  double w[CPL][VPL];
+#pragma unroll
+  for (int m = 0; m < CPL; ++m) {
+    const int k = li + m * lpc;
+    s[m] = reinterpret_cast<const V*>(R.s_bin)[k];
+    b[m] = reinterpret_cast<const V*>(R.b_bin)[k];
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) w[m][v] = R.w_bin[k * VPL + v];
+  }
+  V* __restrict__ dfv = reinterpret_cast<V*>(R.df);
+  for (int c0 = tile.cell0 + wave * cpw; c0 < tile.cell1; c0 += kWaves * cpw) {
+    const int c = c0 + sub;
+    const bool live = c < tile.cell1;   // groups past the end still take part in shuffles
+    V o[CPL], e[CPL];
+    T ne = T(0), tau = T(0), Ev = T(0);
+    int loc = -1;
+    if (live) {
+      loc = R.cell_node[c] - tile.node0;
+      tau = R.tau[c];
+      ne = R.dens[c];
+      Ev = eloc[loc];
+      const V* row = dfv + (size_t)c * (2 * ch);
+#pragma unroll
+      for (int m = 0; m < CPL; ++m) {
+        o[m] = row[li + m * lpc];
+        e[m] = row[ch + li + m * lpc];
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < CPL; ++m)
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) lane_at(o[m], v) = lane_at(e[m], v) = T(0);
+    }
+    const T cf = R.kc * Ev;
+    if (live && first_lane && !(fabs(cf) <= T(1))) atomicOr(R.status, 2);
+    const T ch2 = T(0.5) * cf, cc2 = T(0.5) * cf * cf, cq = T(0.25) * cf;
+    const T nE = ne * Ev;
+    // odd pass: perturbation face fluxes right of every bin
+    T pr[CPL][VPL];
+    {
+      T no[CPL], nev[CPL];
+#pragma unroll
+      for (int m = 0; m < CPL; ++m) {
+        no[m] = __shfl(lane_at(o[m], 0), nxt);
+        nev[m] = __shfl(lane_at(e[m], 0), nxt);
+      }
+#pragma unroll
+      for (int m = 0; m < CPL; ++m) {
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) {
+          T orr, er;
+          bool outer = false;
+          if (v + 1 < VPL) {
+            orr = lane_at(o[m], v + 1);
+            er = lane_at(e[m], v + 1);
+          } else if (!last_lane) {
+            orr = no[m];
+            er = nev[m];
+          } else if (m + 1 < CPL) {
+            orr = no[m + 1 < CPL ? m + 1 : m];
+            er = nev[m + 1 < CPL ? m + 1 : m];
+          } else {
+            orr = er = T(0);
+            outer = true;
+          }
+          const T ol = lane_at(o[m], v), el = lane_at(e[m], v);
+          pr[m][v] = outer ? T(0) : fma(ch2, el + er, -cc2 * (orr - ol));
+        }
+      }
+    }
+    T pl0[CPL];   // face left of element 0 of chunk m
+    {
+      T got[CPL];
+#pragma unroll
+      for (int m = 0; m < CPL; ++m) got[m] = __shfl(pr[m][VPL - 1], prv);
+      const T pc = fma(cf, lane_at(e[0], 0), -cf * cf * lane_at(o[0], 0));  // face at v = 0
+#pragma unroll
+      for (int m = 0; m < CPL; ++m)
+        pl0[m] = !first_lane ? got[m] : (m > 0 ? got[m > 0 ? m - 1 : 0] : pc);
+    }
+    V on[CPL];
+    T sm[CPL][VPL];
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < CPL; ++m) {
+#pragma unroll
+      for (int v = 0; v < VPL; ++v) {
+        const T pl = v == 0 ? pl0[m] : pr[m][v - 1];
+        const T sv = lane_at(s[m], v);
+        const T r = cn_recip(fma(tau, sv, T(2)));
+        const T x2 = (tau + tau) * sv;
+        const T ov = lane_at(o[m], v);
+        const T t = fma(-x2, ov, fma(lane_at(b[m], v), nE, T(-2) * (pr[m][v] - pl)));
+        const T onv = fma(t, r, ov);
+        lane_at(on[m], v) = onv;
+        sm[m][v] = ov + onv;
+        acc = fma(w[m][v], (double)onv, acc);
+      }
+    }
+    // even pass: faces of the time-centred odd part
+    T qr[CPL][VPL];
+    {
+      T ns[CPL];
+#pragma unroll
+      for (int m = 0; m < CPL; ++m) ns[m] = __shfl(sm[m][0], nxt);
+#pragma unroll
+      for (int m = 0; m < CPL; ++m) {
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) {
+          T sr;
+          bool outer = false;
+          if (v + 1 < VPL) sr = sm[m][v + 1];
+          else if (!last_lane) sr = ns[m];
+          else if (m + 1 < CPL) sr = ns[m + 1 < CPL ? m + 1 : m];
+          else { sr = T(0); outer = true; }
+          qr[m][v] = outer ? T(0) : cq * (sm[m][v] + sr);
+        }
+      }
+    }
+    {
+      T got[CPL];
+#pragma unroll
+      for (int m = 0; m < CPL; ++m) got[m] = __shfl(qr[m][VPL - 1], prv);
+#pragma unroll
+      for (int m = 0; m < CPL; ++m) {
+        const T ql0 = !first_lane ? got[m] : (m > 0 ? got[m > 0 ? m - 1 : 0] : T(0));
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) {
+          const T ql = v == 0 ? ql0 : qr[m][v - 1];
+          lane_at(e[m], v) = lane_at(e[m], v) - (qr[m][v] - ql);
+        }
+      }
+    }
+    if (live) {
+      V* row = dfv + (size_t)c * (2 * ch);
+#pragma unroll
+      for (int m = 0; m < CPL; ++m) {
+        row[li + m * lpc] = on[m];
+        row[ch + li + m * lpc] = e[m];
+      }
+    }
+    double a1[1] = {acc};
+    int which = 0;
+    const double tot = group_reduce<1>(a1, lpc, li, which);
+    if (live && first_lane) jloc[loc] = (T)tot;
+  }
+}
+
 // One step of one tile by a work-group of NT threads (tile.node1 - tile.node0 <= NT).
 // jloc / eloc: LDS arrays of NT values.  The caller synchronises before reusing them.
-template <class T, int NT>
+template <class T, int NT, bool FULL = false>
 __device__ __forceinline__ void step_tile(const Run1D<T>& R, const Tile1D& tile, int64_t step,
                                           T* jloc, T* eloc) {
   const int par = (int)(step & 1);
@@ -180,7 +358,11 @@ __device__ __forceinline__ void step_tile(const Run1D<T>& R, const Tile1D& tile,
   if (tile.cell1 > tile.cell0) {
     const int ch = R.half / Vec<T>::n;
     const int cpl = ch < 64 ? 1 : ch / 64;
-    if (cpl == 1) kinetic_tile<T, 4, NT>(R, eloc, tile, jloc);
+    if constexpr (FULL) {
+      if (cpl == 1) kinetic_tile_full<T, 1, NT>(R, eloc, tile, jloc);
+      else if (cpl == 2) kinetic_tile_full<T, 2, NT>(R, eloc, tile, jloc);
+      else kinetic_tile_full<T, 4, NT>(R, eloc, tile, jloc);
+    } else if (cpl == 1) kinetic_tile<T, 4, NT>(R, eloc, tile, jloc);
     else if (cpl == 2) kinetic_tile<T, 2, NT>(R, eloc, tile, jloc);
     else kinetic_tile<T, 1, NT>(R, eloc, tile, jloc);
   }
@@ -251,6 +433,20 @@ __global__ __launch_bounds__(kBlock) void k_step1d(const Run1D<T>* __restrict__ 
   step_tile<T, kBlock>(R, tile, step, jloc, eloc);
 }
 
+// The same step for runs of the full-distribution model (a kernel of its own, so the
+// linear model's kernels keep their register budget).
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_step1d_full(const Run1D<T>* __restrict__ runs,
+                                                        const Tile1D* __restrict__ tiles,
+                                                        int64_t step) {
+  __shared__ T jloc[kMaxTile1D];
+  __shared__ T eloc[kMaxTile1D];
+  const Tile1D tile = tiles[blockIdx.x];
+  const Run1D<T>& R = runs[tile.run];
+  if (step >= R.step_limit) return;
+  step_tile<T, kBlock, true>(R, tile, step, jloc, eloc);
+}
+
 // Persistent batch: steps [s0, s1) of every run, runs taken longest first from `order`
 // through the counter `*queue` (zero at launch).  Every work-group leaves the loop once
 // the counter passes nruns.
@@ -289,11 +485,16 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch1d_persistent(
 
 template <class T>
 hipError_t launch_step1d(const void* runs, const void* tiles, int ntiles, int64_t step,
-                         hipStream_t stream) {
+                         hipStream_t stream, bool full) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_step1d<T>, dim3(ntiles), dim3(kBlock), 0, stream,
-                     static_cast<const Run1D<T>*>(runs), static_cast<const Tile1D*>(tiles),
-                     step);
+  if (full)
+    hipLaunchKernelGGL(k_step1d_full<T>, dim3(ntiles), dim3(kBlock), 0, stream,
+                       static_cast<const Run1D<T>*>(runs), static_cast<const Tile1D*>(tiles),
+                       step);
+  else
+    hipLaunchKernelGGL(k_step1d<T>, dim3(ntiles), dim3(kBlock), 0, stream,
+                       static_cast<const Run1D<T>*>(runs), static_cast<const Tile1D*>(tiles),
+                       step);
   return hipGetLastError();
 }
 
@@ -308,7 +509,9 @@ hipError_t launch_batch1d_persistent(const void* runs, const int32_t* order, int
   return hipGetLastError();
 }
 
-template hipError_t launch_step1d<float>(const void*, const void*, int, int64_t, hipStream_t);
-template hipError_t launch_step1d<double>(const void*, const void*, int, int64_t, hipStream_t);
+template hipError_t launch_step1d<float>(const void*, const void*, int, int64_t, hipStream_t,
+                                         bool);
+template hipError_t launch_step1d<double>(const void*, const void*, int, int64_t, hipStream_t,
+                                          bool);
 
 }  // namespace fdtdp

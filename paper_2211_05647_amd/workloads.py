@@ -76,6 +76,7 @@ class Run1D:
     nu_model: str = "hard_sphere"
     bc: str = "mur"
     meta: dict = field(default_factory=dict)
+    kinetic: str = "linear"     # "linear" (F0 frozen) or "full" (the whole f evolves)
 
     @property
     def plasma_cells(self) -> int:

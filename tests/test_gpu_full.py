@@ -1,0 +1,97 @@
+"""GPU parity of the full-distribution kinetic model (the whole f of each plasma node
+evolves: its even part heats, its odd part carries the current) against the FP64 oracle,
+through the C ABI.  Tolerances as for the linear model: FP64 storage <= 1e-12 relative
+L2, FP32 storage <= 1e-5 relative L2 over space and time."""
+import numpy as np
+import pytest
+
+from paper_2211_05647_amd import binding as B
+from paper_2211_05647_amd import workloads as W
+from parity import oracle_1d, rel_l2, space_time_1d
+
+pytestmark = pytest.mark.gpu
+
+
+def _banner(msg):
+    print(f"[gpu-full] {msg}", flush=True)
+
+
+def _strong(nv, steps=700, amp64=3e5):
+    """Slab over several tiles with a vacuum gap, driven hard enough that the electrons
+    heat to a few times their thermal energy (velocity CFL about 0.1-0.2 at every Nv)."""
+    run = W.slab_1d(777, nv, 130, 555, 1.1, 0.2, W.F_REF, 40, steps)
+    run.ne[300:320] = 0.0
+    run.src_amp = amp64 * 64 / nv
+    run.kinetic = "full"
+    return run
+
+
+@pytest.mark.parametrize("nv,tile", [(8, 32), (16, 64), (64, 96), (128, 256), (512, 64),
+                                     (1024, 32)])
+def test_full_model_parity(gpu_lib, nv, tile):
+    """Every lane layout of the full-model kernel (lanes per row 1..64, chunks per lane
+    1..4), ragged tiles, both storage precisions, both collision models; E over space
+    and time, J, and f - n fhat on the signed grid."""
+    run = _strong(nv)
+    for prec, tol in ((B.FP64, 1e-12), (B.FP32, 1e-5)):
+        for model in ("hard_sphere", "const"):
+            _banner(f"nv={nv} tile={tile} prec={prec} nu={model}")
+            run.nu_model = model
+            sim = B.Sim(run, precision=prec, tile=tile)
+            assert sim.time_block() == 1
+            orc = oracle_1d(run)
+            snaps = []
+            g, o, _, _ = space_time_1d(sim, orc, run.steps, 100, [], df_snaps=snaps)
+            err = rel_l2(g, o)
+            _banner(f"  E space-time rel L2 = {err:.3e}")
+            assert err <= tol, (prec, model)
+            assert rel_l2(sim.read(B.F_J), orc.J) <= tol
+            gd = np.concatenate([a.ravel() for a, _ in snaps])
+            od = np.concatenate([b.ravel() for _, b in snaps])
+            assert rel_l2(gd, od) <= tol
+            sim.close()
+
+
+def test_full_model_differs_from_linear_and_keeps_number(gpu_lib):
+    """At this drive the full model departs from the linear one by over 10 % (heating
+    is exercised), and every node keeps its electron number: the signed-grid rows of
+    f - n fhat sum to zero to rounding (FP64)."""
+    run = _strong(64)
+    sim = B.Sim(run, precision=B.FP64)
+    sim.run(run.steps)
+    E_full = sim.read(B.F_E)
+    rows = sim.read(B.F_DF).reshape(-1, run.nv)
+    sim.close()
+    assert np.abs(rows).max() > 0
+    assert np.max(np.abs(rows.sum(axis=1))) <= 1e-12 * np.abs(rows).max() * run.nv
+    run.kinetic = "linear"
+    lin = B.Sim(run, precision=B.FP64)
+    lin.run(run.steps)
+    assert rel_l2(E_full, lin.read(B.F_E)) > 0.1
+    lin.close()
+
+
+def test_full_model_velocity_cfl_flagged(gpu_lib):
+    """A field that breaks |(e/m) E dt / dv| <= 1 sets the run status; a run within the
+    limit reports none."""
+    run = _strong(64, steps=700)
+    sim = B.Sim(run, precision=B.FP64)
+    sim.run(run.steps)
+    assert sim.run_status(0) == 0
+    sim.close()
+    run.src_amp *= 20.0
+    sim = B.Sim(run, precision=B.FP64)
+    sim.run(run.steps)
+    assert sim.run_status(0) != 0
+    sim.close()
+
+
+def test_full_model_configurations_rejected(gpu_lib):
+    """The full model runs 1D single runs: batches and 2D runs refuse it."""
+    run = _strong(64)
+    with pytest.raises(B.FdtdError):
+        B.Sim([run, run], precision=B.FP32)
+    r2 = W.c2(n=64, radius=10.0, steps=10)
+    r2.kinetic = "full"
+    with pytest.raises(B.FdtdError):
+        B.Sim(r2, precision=B.FP32)
