@@ -144,6 +144,34 @@ def extra_c1l(B, W, torch, autotune):
                               one_step_stream_equivalent_gbs=bytes_1d(run) / (ms * 1e-3) / 1e9)}
 
 
+def bytes_1d_full(run):
+    """Algorithmic bytes of one launch of the full-model step kernel: the node's whole
+    row (odd and even halves of f - n fhat, Nv values, FP32) read + written, per-cell
+    scalars, fields over the line."""
+    ncell, nv, nx = run.plasma_cells, run.nv, run.nx
+    return ncell * nv * 4 * 2 + ncell * 12 + (nx + 1) * 4 * 5
+
+
+def extra_full(B, W, torch):
+    """The full-distribution model (F0 evolves, electrons heat) on the C1 line and on the
+    Nx = 2^20 line, FP32, one step per launch."""
+    out = {}
+    for key, run, steps in (("full_c1", W.c1(steps=2000), 2000),
+                            ("full_c1_nx2e20", W.c1_large(), 300)):
+        run.kinetic = "full"
+        log(f"{key}: Nx={run.nx} Nv={run.nv} plasma cells={run.plasma_cells}")
+        wall, ms = time_single(run, B, torch, steps, 50)
+        by = bytes_1d_full(run)
+        out[key] = dict(workload=f"1D Yee + full-distribution 1V kinetic, Nx={run.nx}, "
+                                 f"Nv={run.nv}, FP32, {steps} steps",
+                        kernel="k_step1d_full<float>",
+                        updates_per_s=run.plasma_cells * run.nv * steps / wall,
+                        ms_per_step=wall / steps * 1e3, kernel_ms_per_step=ms,
+                        hbm_gbs=by / (ms * 1e-3) / 1e9,
+                        hbm_frac=by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+    return out
+
+
 def extra_c2(B, W, torch, autotune, steps=None):
     """2D column, 512^2, 32x32 velocity bins."""
     run = W.c2()
@@ -256,6 +284,7 @@ def extra_workloads(B, W, torch, autotune):
     out.update(extra_c2(B, W, torch, autotune))
     out.update(extra_c3(B, W, torch))
     out.update(closure_speedup(B, W, torch))
+    out.update(extra_full(B, W, torch))
     return out
 
 
@@ -334,7 +363,7 @@ def main():
                     help="steps per launch of the large 1D workload (default: tuned; 1 = one "
                          "step per launch)")
     ap.add_argument("--calibrate-copy", action="store_true")
-    ap.add_argument("--only", choices=["c1l", "c2", "c3", "closure", "c4", "sweep"], default=None,
+    ap.add_argument("--only", choices=["c1l", "c2", "c3", "closure", "c4", "sweep", "full"], default=None,
                     help="run only one of the extra measurements (for profiling); c2 and c4 "
                          "take --steps steps")
     args = ap.parse_args()
@@ -357,7 +386,8 @@ def main():
                 "c3": lambda: extra_c3(B, W, torch),
                 "closure": lambda: closure_speedup(B, W, torch),
                 "c4": lambda: c4_steps(B, W, torch, args.steps),
-                "sweep": lambda: nmcps_sweep(B, W, torch)}[args.only]
+                "sweep": lambda: nmcps_sweep(B, W, torch),
+                "full": lambda: extra_full(B, W, torch)}[args.only]
         print(json.dumps(only()), flush=True)
         return
 
