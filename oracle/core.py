@@ -57,6 +57,19 @@ def lib():
                                       C.c_double, C.c_double, C.c_longlong, _dp, _dp]
         L.oracle_full1v.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, C.c_double,
                                     C.c_double, C.c_double, C.c_longlong, _dp, _dp, _dp]
+        L.oracle_sgrid.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, _dp, _dp, _dp, _dp, _dp]
+        L.oracle_snu_shape.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_int, _dp]
+        L.oracle_plasma3d_count.argtypes = [C.c_int, C.c_int, C.c_int, _dp]
+        L.oracle_run3d.argtypes = (
+            [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
+             C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
+             C.c_int, C.c_double, C.c_double, C.c_int, C.c_int,
+             _dp, _dp,
+             C.c_int, C.c_int, C.c_int, C.c_int,
+             C.c_double, C.c_double, C.c_double, C.c_double,
+             C.c_longlong, C.c_longlong,
+             _dp, _dp, _dp, _dp, _dp,
+             C.c_int, _ip, _dp])
         L.oracle_replay2v.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, C.c_double,
                                       C.c_double, C.c_double, C.c_longlong, _dp, _dp, _dp, _dp]
         _lib = L
@@ -93,6 +106,25 @@ def vgrid(nv, vmax_over_vth, te_ev):
     if rc:
         raise ValueError("bad velocity grid")
     return v, fh, gh, dv.value, vth.value
+
+
+def sgrid(vdim, vmax_over_vth, te_ev, f0_model=0):
+    """Speed grid and isotropic F0 tables of the 3D model (see ``oracle_sgrid``):
+    (v, F0, dF0/dv, gam, v_th); f0_model 0 Maxwellian, 1 Druyvesteyn."""
+    v, F0, dF0 = np.zeros(vdim), np.zeros(vdim), np.zeros(vdim)
+    gam, vth = C.c_double(), C.c_double()
+    rc = lib().oracle_sgrid(vdim, vmax_over_vth, te_ev, f0_model, _p(v), _p(F0), _p(dF0),
+                            C.byref(gam), C.byref(vth))
+    if rc:
+        raise ValueError("bad speed grid")
+    return v, F0, dF0, gam.value, vth.value
+
+
+def snu_shape(vdim, vmax_over_vth, te_ev, f0_model, model):
+    v, F0, dF0, gam, vth = sgrid(vdim, vmax_over_vth, te_ev, f0_model)
+    s = np.zeros(vdim)
+    lib().oracle_snu_shape(vdim, _p(v), _p(F0), gam, model, _p(s))
+    return s
 
 
 def nu_shape(dims, nv, vmax_over_vth, te_ev, model):
@@ -286,3 +318,78 @@ class Oracle2D:
 
     def df_cells(self):
         return self.df.reshape(len(self.cells), self.nv, self.nv)
+
+
+class Oracle3D:
+    """3D Yee cube with CPML on all faces and, at every plasma E point, the F1 component
+    of that E on a speed grid of ``vdim`` speeds (the paper's production model).
+
+    ``ne``/``nubar`` are per cell, shape (nz, ny, nx).  Fields are kept as flat arrays in
+    the library's layout; ``Ex``/``Ey``/``Ez`` (and H, J) give shaped views.
+    ``src_kind``: 0 none, 1 Ex sheet on plane ``src_k``, 2 Ex point (src_i, src_j, src_k).
+    """
+
+    def __init__(self, nx, ny, nz, dx, courant, ne, nubar, vdim=31, vmax_over_vth=4.0,
+                 te_ev=1.0, nu_model="hard_sphere", f0_model="maxwell", ncpml=8,
+                 cpml_order=3.0, sigma_factor=1.0, kappa_max=5.0, alpha_min=0.0,
+                 alpha_max=0.05, src_kind=0, src_i=0, src_j=0, src_k=0, src_amp=0.0,
+                 src_f=0.0, src_tau=1.0, src_t0=0.0):
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.dx, self.courant = float(dx), float(courant)
+        self.ne = np.ascontiguousarray(ne, dtype=np.float64).reshape(-1)
+        self.nubar = np.ascontiguousarray(nubar, dtype=np.float64).reshape(-1)
+        assert self.ne.shape == (nx * ny * nz,) and self.nubar.shape == self.ne.shape
+        self.vdim, self.vmax, self.te = int(vdim), float(vmax_over_vth), float(te_ev)
+        self.nu_model = {"hard_sphere": 0, "const": 1}[nu_model]
+        self.f0_model = {"maxwell": 0, "druyvesteyn": 1}[f0_model]
+        self.cpml = (int(ncpml), float(cpml_order), float(sigma_factor), float(kappa_max),
+                     float(alpha_min), float(alpha_max))
+        self.src = (int(src_kind), int(src_i), int(src_j), int(src_k), float(src_amp),
+                    float(src_f), float(src_tau), float(src_t0))
+        X, Y, Z = self.nx, self.ny, self.nz
+        self.shapes_e = [(Z + 1, Y + 1, X), (Z + 1, Y, X + 1), (Z, Y + 1, X + 1)]
+        self.shapes_h = [(Z, Y, X + 1), (Z, Y + 1, X), (Z + 1, Y, X)]
+        ne_ = int(sum(np.prod(s) for s in self.shapes_e))
+        nh_ = int(sum(np.prod(s) for s in self.shapes_h))
+        self.E = np.zeros(ne_)
+        self.H = np.zeros(nh_)
+        self.J = np.zeros(ne_)
+        self.psi = np.zeros(2 * ne_ + 2 * nh_)
+        self.npoints = int(lib().oracle_plasma3d_count(X, Y, Z, _p(self.ne)))
+        self.df = np.zeros(self.npoints * self.vdim)
+        self.step = 0
+        self.dt = self.courant * self.dx / constants()["c"]
+
+    def _views(self, flat, shapes):
+        out, o = [], 0
+        for s in shapes:
+            n = int(np.prod(s))
+            out.append(flat[o:o + n].reshape(s))
+            o += n
+        return out
+
+    def fields(self):
+        """dict of shaped views: Ex, Ey, Ez, Hx, Hy, Hz, Jx, Jy, Jz."""
+        ex, ey, ez = self._views(self.E, self.shapes_e)
+        hx, hy, hz = self._views(self.H, self.shapes_h)
+        jx, jy, jz = self._views(self.J, self.shapes_e)
+        return dict(Ex=ex, Ey=ey, Ez=ez, Hx=hx, Hy=hy, Hz=hz, Jx=jx, Jy=jy, Jz=jz)
+
+    def run(self, nsteps, probes=()):
+        """``probes``: flat indices into E; returns E there after every step."""
+        idx = np.ascontiguousarray(probes, dtype=np.int32)
+        pout = np.zeros(max(1, nsteps * len(idx)))
+        rc = lib().oracle_run3d(
+            self.nx, self.ny, self.nz, self.dx, self.courant, *self.cpml,
+            self.vdim, self.vmax, self.te, self.nu_model, self.f0_model,
+            _p(self.ne), _p(self.nubar), *self.src,
+            self.step, int(nsteps),
+            _p(self.E), _p(self.H), _p(self.J), _p(self.psi), _p(self.df),
+            len(idx), _p(idx) if len(idx) else None, _p(pout))
+        if rc:
+            raise ValueError("oracle_run3d rejected its arguments")
+        self.step += int(nsteps)
+        return pout[: nsteps * len(idx)].reshape(nsteps, len(idx))
+
+    def df_rows(self):
+        return self.df.reshape(self.npoints, self.vdim)

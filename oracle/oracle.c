@@ -36,6 +36,14 @@
  *   - 2D TEz: F1 lives at plasma cell centres; E is averaged from the two
  *     bounding edges to the centre and J is averaged back to each edge with
  *     the transposed weights, so field-to-plasma work is exchanged exactly.
+ *   - 3D (the paper's production model): F1 is a vector on a speed grid
+ *     v_k = (k + 1/2) gam, one component at each E component's point, with
+ *     J = -e (4 pi / 3) gam sum v^3 F1 as section 5.3 prints it; F0 Maxwellian
+ *     or Druyvesteyn (the paper names the latter without its formula: taken as
+ *     exp(-(v/vD)^4) with the Maxwellian's mean energy (3/2) e T_e), normalised
+ *     by 4 pi gam sum v^2 F0 = 1; an E point's density and mean collision
+ *     frequency are the means over the four cells around its edge; tangential
+ *     E on the outer faces stays zero behind the CPML.
  *   - full-distribution model (model = 1, 1V): instead of freezing F0 and
  *     evolving F1 alone, the whole f of each plasma node evolves under
  *     df/dt - (e/m) E df/dv = C(f) (the kinetic equation of section 5.1 with
@@ -679,5 +687,309 @@ int oracle_replay2v(int nv, double vmax_over_vth, double te_ev, int nu_model,
         Jy[n] = -K_QE * dv * dv * ay;
     }
     free(v); free(fh); free(gh); free(sh); free(f);
+    return 0;
+}
+
+/* ===========================================================================
+ * 3D: the paper's production model.  Yee cube (section 2, eq. (1)-(5) in
+ * their 3D form) with the CPML of eq. (4) on all six faces; in every plasma
+ * point the anisotropic part F1 of the distribution is a vector on a speed
+ * grid (section 5.1 expansion F = F0 + (v/|v|).F1, section 5.3 arrays with
+ * v_dim speeds), one component at each E component's point, updated by the
+ * section 5.3 Crank-Nicolson form with J = -e (4 pi / 3) gam sum v^3 F1.
+ * ======================================================================== */
+
+/* Speed grid v_k = (k + 1/2) gam, k = 0..vdim-1, gam = vmax / vdim, vmax =
+ * vmax_over_vth * v_th (v_th = sqrt(e Te / m)).  F0 isotropic, normalised by
+ * 4 pi gam sum v_k^2 F0_k = 1:
+ *   model 0 Maxwellian  F0 ~ exp(-v^2 / (2 v_th^2)),  dF0/dv = -v F0 / v_th^2;
+ *   model 1 Druyvesteyn F0 ~ exp(-(v / vD)^4) with the Maxwellian's mean energy
+ *           (3/2) e Te: vD^2 = 3 v_th^2 Gamma(3/4) / Gamma(5/4); dF0/dv = -4 v^3 F0 / vD^4. */
+int oracle_sgrid(int vdim, double vmax_over_vth, double te_ev, int f0_model,
+                 double *v, double *F0, double *dF0, double *gam_out, double *vth_out)
+{
+    if (vdim < 1 || te_ev <= 0.0 || vmax_over_vth <= 0.0 || (f0_model != 0 && f0_model != 1))
+        return -1;
+    double vth = sqrt(K_QE * te_ev / K_ME);
+    double gam = vmax_over_vth * vth / (double)vdim;
+    double vd4 = 0.0;
+    if (f0_model == 1) {
+        double vd2 = 3.0 * vth * vth * tgamma(0.75) / tgamma(1.25);
+        vd4 = vd2 * vd2;
+    }
+    double norm = 0.0;
+    for (int k = 0; k < vdim; ++k) {
+        v[k] = ((double)k + 0.5) * gam;
+        double u = v[k];
+        F0[k] = (f0_model == 0) ? exp(-u * u / (2.0 * vth * vth)) : exp(-u * u * u * u / vd4);
+        norm += 4.0 * K_PI * gam * u * u * F0[k];
+    }
+    for (int k = 0; k < vdim; ++k) {
+        F0[k] /= norm;
+        double u = v[k];
+        dF0[k] = (f0_model == 0) ? -u * F0[k] / (vth * vth) : -4.0 * u * u * u * F0[k] / vd4;
+    }
+    *gam_out = gam;
+    *vth_out = vth;
+    return 0;
+}
+
+/* nu_k = nubar * s_k: hard sphere (nu = N s v) s_k = v_k / <v> with the mean
+ * speed <v> = 4 pi gam sum v^3 F0; const: s_k = 1. */
+int oracle_snu_shape(int vdim, const double *v, const double *F0, double gam, int model,
+                     double *s)
+{
+    double mean = 0.0;
+    for (int k = 0; k < vdim; ++k) mean += 4.0 * K_PI * gam * v[k] * v[k] * v[k] * F0[k];
+    for (int k = 0; k < vdim; ++k) s[k] = (model == 0) ? v[k] / mean : 1.0;
+    return 0;
+}
+
+/* Storage (i fastest, then j, then k):
+ *   Ex [nz+1][ny+1][nx]  at (i+1/2, j, k)      Hx [nz][ny][nx+1]    at (i, j+1/2, k+1/2)
+ *   Ey [nz+1][ny][nx+1]  at (i, j+1/2, k)      Hy [nz][ny+1][nx]    at (i+1/2, j, k+1/2)
+ *   Ez [nz][ny+1][nx+1]  at (i, j, k+1/2)      Hz [nz+1][ny][nx]    at (i+1/2, j+1/2, k)
+ * E = Ex|Ey|Ez and H = Hx|Hy|Hz concatenated; J like E (SI).  psi: 12 arrays,
+ * each the size of its field, in the order ex_y ex_z ey_z ey_x ez_x ez_y
+ * hx_z hx_y hy_x hy_z hz_y hz_x.  Tangential E on the outer faces stays zero
+ * (PEC backing of the CPML).  ne / nubar per cell [nz][ny][nx]; an E point is
+ * a plasma point if it is updated (not on a face its component is tangential
+ * to) and the mean density of the four cells that share its edge is > 0; its
+ * n and nubar are those means.  df rows (vdim values): the plasma points of
+ * Ex, then of Ey, then of Ez, each in storage order.
+ * Source kinds: 1 sheet, Ex += g at every updated Ex point of plane k = src_k;
+ * 2 point, Ex += g at (src_i + 1/2, src_j, src_k). */
+static int o3_plasma(int nx, int ny, int nz, const double *ne, const double *nubar,
+                     int *pidx, double *pn, double *pnu)
+{
+    int np = 0;
+#define CELL(a, b, c) ((size_t)(c) * ny * nx + (size_t)(b) * nx + (a))
+    for (int k = 1; k < nz; ++k)
+        for (int j = 1; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                double n = 0.25 * (ne[CELL(i, j - 1, k - 1)] + ne[CELL(i, j, k - 1)] +
+                                   ne[CELL(i, j - 1, k)] + ne[CELL(i, j, k)]);
+                if (n > 0.0) {
+                    if (pidx) {
+                        pidx[np] = (int)(((size_t)k * (ny + 1) + j) * nx + i);
+                        pn[np] = n;
+                        pnu[np] = 0.25 * (nubar[CELL(i, j - 1, k - 1)] + nubar[CELL(i, j, k - 1)] +
+                                          nubar[CELL(i, j - 1, k)] + nubar[CELL(i, j, k)]);
+                    }
+                    ++np;
+                }
+            }
+    size_t offy = (size_t)nx * (ny + 1) * (nz + 1);
+    for (int k = 1; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 1; i < nx; ++i) {
+                double n = 0.25 * (ne[CELL(i - 1, j, k - 1)] + ne[CELL(i, j, k - 1)] +
+                                   ne[CELL(i - 1, j, k)] + ne[CELL(i, j, k)]);
+                if (n > 0.0) {
+                    if (pidx) {
+                        pidx[np] = (int)(offy + ((size_t)k * ny + j) * (nx + 1) + i);
+                        pn[np] = n;
+                        pnu[np] = 0.25 * (nubar[CELL(i - 1, j, k - 1)] + nubar[CELL(i, j, k - 1)] +
+                                          nubar[CELL(i - 1, j, k)] + nubar[CELL(i, j, k)]);
+                    }
+                    ++np;
+                }
+            }
+    size_t offz = offy + (size_t)(nx + 1) * ny * (nz + 1);
+    for (int k = 0; k < nz; ++k)
+        for (int j = 1; j < ny; ++j)
+            for (int i = 1; i < nx; ++i) {
+                double n = 0.25 * (ne[CELL(i - 1, j - 1, k)] + ne[CELL(i, j - 1, k)] +
+                                   ne[CELL(i - 1, j, k)] + ne[CELL(i, j, k)]);
+                if (n > 0.0) {
+                    if (pidx) {
+                        pidx[np] = (int)(offz + ((size_t)k * (ny + 1) + j) * (nx + 1) + i);
+                        pn[np] = n;
+                        pnu[np] = 0.25 * (nubar[CELL(i - 1, j - 1, k)] + nubar[CELL(i, j - 1, k)] +
+                                          nubar[CELL(i - 1, j, k)] + nubar[CELL(i, j, k)]);
+                    }
+                    ++np;
+                }
+            }
+#undef CELL
+    return np;
+}
+
+int oracle_plasma3d_count(int nx, int ny, int nz, const double *ne)
+{
+    return o3_plasma(nx, ny, nz, ne, ne, NULL, NULL, NULL);
+}
+
+int oracle_run3d(int nx, int ny, int nz, double dx, double courant,
+                 int ncpml, double cpml_order, double sigma_factor, double kappa_max,
+                 double alpha_min, double alpha_max,
+                 int vdim, double vmax_over_vth, double te_ev, int nu_model, int f0_model,
+                 const double *ne, const double *nubar,
+                 int src_kind, int src_i, int src_j, int src_k,
+                 double src_amp, double src_f, double src_tau, double src_t0,
+                 long long step0, long long nsteps,
+                 double *E, double *H, double *J, double *psi, double *df,
+                 int nprobe, const int *probe_idx, double *probe_out)
+{
+    if (nx < 2 || ny < 2 || nz < 2 || vdim < 1 || dx <= 0.0) return -1;
+    if (courant <= 0.0 || courant > 1.0 / sqrt(3.0)) return -1;
+    if (2 * ncpml >= nx || 2 * ncpml >= ny || 2 * ncpml >= nz) return -1;
+    const double dt = courant * dx / K_C0;
+    const size_t NX = nx, NY = ny, NZ = nz;
+    const size_t nEx = NX * (NY + 1) * (NZ + 1), nEy = (NX + 1) * NY * (NZ + 1),
+                 nEz = (NX + 1) * (NY + 1) * NZ;
+    const size_t nHx = (NX + 1) * NY * NZ, nHy = NX * (NY + 1) * NZ, nHz = NX * NY * (NZ + 1);
+    double *Ex = E, *Ey = E + nEx, *Ez = E + nEx + nEy;
+    double *Hx = H, *Hy = H + nHx, *Hz = H + nHx + nHy;
+    double *Jx = J, *Jy = J + nEx, *Jz = J + nEx + nEy;
+    double *p_exy = psi, *p_exz = p_exy + nEx, *p_eyz = p_exz + nEx, *p_eyx = p_eyz + nEy;
+    double *p_ezx = p_eyx + nEy, *p_ezy = p_ezx + nEz;
+    double *p_hxz = p_ezy + nEz, *p_hxy = p_hxz + nHx, *p_hyx = p_hxy + nHx, *p_hyz = p_hyx + nHy;
+    double *p_hzy = p_hyz + nHy, *p_hzx = p_hzy + nHz;
+
+    double *v = malloc(sizeof(double) * vdim), *F0 = malloc(sizeof(double) * vdim);
+    double *dF0 = malloc(sizeof(double) * vdim), *sh = malloc(sizeof(double) * vdim);
+    double gam, vth;
+    if (oracle_sgrid(vdim, vmax_over_vth, te_ev, f0_model, v, F0, dF0, &gam, &vth) != 0) {
+        free(v); free(F0); free(dF0); free(sh); return -1;
+    }
+    oracle_snu_shape(vdim, v, F0, gam, nu_model, sh);
+
+    double *pr[3][6];   /* be ae ke bh ah kh per axis */
+    int nn[3] = {nx, ny, nz};
+    for (int a = 0; a < 3; ++a) {
+        for (int q = 0; q < 6; ++q) pr[a][q] = malloc(sizeof(double) * (nn[a] + 1));
+        oracle_cpml_profile(nn[a], ncpml, dx, dt, cpml_order, sigma_factor, kappa_max,
+                            alpha_min, alpha_max, pr[a][0], pr[a][1], pr[a][2],
+                            pr[a][3], pr[a][4], pr[a][5]);
+    }
+    const double *bex = pr[0][0], *aex = pr[0][1], *kex = pr[0][2];
+    const double *bhx = pr[0][3], *ahx = pr[0][4], *khx = pr[0][5];
+    const double *bey = pr[1][0], *aey = pr[1][1], *key = pr[1][2];
+    const double *bhy = pr[1][3], *ahy = pr[1][4], *khy = pr[1][5];
+    const double *bez = pr[2][0], *aez = pr[2][1], *kez = pr[2][2];
+    const double *bhz = pr[2][3], *ahz = pr[2][4], *khz = pr[2][5];
+
+    int np = o3_plasma(nx, ny, nz, ne, nubar, NULL, NULL, NULL);
+    int *pidx = malloc(sizeof(int) * (np > 0 ? np : 1));
+    double *pn = malloc(sizeof(double) * (np > 0 ? np : 1));
+    double *pnu = malloc(sizeof(double) * (np > 0 ? np : 1));
+    o3_plasma(nx, ny, nz, ne, nubar, pidx, pn, pnu);
+
+    const double ch = dt / k_mu0(), ce = dt / K_EPS0;
+#define IEX(i, j, k) (((size_t)(k) * (NY + 1) + (j)) * NX + (i))
+#define IEY(i, j, k) (((size_t)(k) * NY + (j)) * (NX + 1) + (i))
+#define IEZ(i, j, k) (((size_t)(k) * (NY + 1) + (j)) * (NX + 1) + (i))
+#define IHX(i, j, k) (((size_t)(k) * NY + (j)) * (NX + 1) + (i))
+#define IHY(i, j, k) (((size_t)(k) * (NY + 1) + (j)) * NX + (i))
+#define IHZ(i, j, k) (((size_t)(k) * NY + (j)) * NX + (i))
+    for (long long s = 0; s < nsteps; ++s) {
+        long long n = step0 + s;
+        /* 1. H^{n+1/2}: mu dH/dt = -curl E with the CPML-stretched derivatives */
+        #pragma omp parallel for schedule(static)
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i <= nx; ++i) {
+                    size_t q = IHX(i, j, k);
+                    double dEy_z = Ey[IEY(i, j, k + 1)] - Ey[IEY(i, j, k)];
+                    double dEz_y = Ez[IEZ(i, j + 1, k)] - Ez[IEZ(i, j, k)];
+                    p_hxz[q] = bhz[k] * p_hxz[q] + ahz[k] * dEy_z;
+                    p_hxy[q] = bhy[j] * p_hxy[q] + ahy[j] * dEz_y;
+                    Hx[q] += ch * (dEy_z / (khz[k] * dx) + p_hxz[q] - dEz_y / (khy[j] * dx) - p_hxy[q]);
+                }
+        #pragma omp parallel for schedule(static)
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j <= ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    size_t q = IHY(i, j, k);
+                    double dEz_x = Ez[IEZ(i + 1, j, k)] - Ez[IEZ(i, j, k)];
+                    double dEx_z = Ex[IEX(i, j, k + 1)] - Ex[IEX(i, j, k)];
+                    p_hyx[q] = bhx[i] * p_hyx[q] + ahx[i] * dEz_x;
+                    p_hyz[q] = bhz[k] * p_hyz[q] + ahz[k] * dEx_z;
+                    Hy[q] += ch * (dEz_x / (khx[i] * dx) + p_hyx[q] - dEx_z / (khz[k] * dx) - p_hyz[q]);
+                }
+        #pragma omp parallel for schedule(static)
+        for (int k = 0; k <= nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    size_t q = IHZ(i, j, k);
+                    double dEx_y = Ex[IEX(i, j + 1, k)] - Ex[IEX(i, j, k)];
+                    double dEy_x = Ey[IEY(i + 1, j, k)] - Ey[IEY(i, j, k)];
+                    p_hzy[q] = bhy[j] * p_hzy[q] + ahy[j] * dEx_y;
+                    p_hzx[q] = bhx[i] * p_hzx[q] + ahx[i] * dEy_x;
+                    Hz[q] += ch * (dEx_y / (khy[j] * dx) + p_hzy[q] - dEy_x / (khx[i] * dx) - p_hzx[q]);
+                }
+
+        /* 2-3. F1 of every plasma point driven by its E component at t^n, and
+         *      the current J^{n+1/2} = -e (4 pi / 3) gam sum v^3 F1 (section 5.3) */
+        #pragma omp parallel for schedule(static)
+        for (int p = 0; p < np; ++p) {
+            double *f = df + (size_t)p * vdim;
+            double e = E[pidx[p]], acc = 0.0;
+            for (int k = 0; k < vdim; ++k) {
+                double nu = pnu[p] * sh[k];
+                f[k] = ((2.0 - dt * nu) * f[k] + 2.0 * dt * (K_QE / K_ME) * pn[p] * dF0[k] * e)
+                       / (2.0 + dt * nu);
+                acc += v[k] * v[k] * v[k] * f[k];
+            }
+            J[pidx[p]] = -K_QE * (4.0 * K_PI / 3.0) * gam * acc;
+        }
+
+        /* 4. E^{n+1}: eps dE/dt = curl H - J, interior (tangential) points only */
+        #pragma omp parallel for schedule(static)
+        for (int k = 1; k < nz; ++k)
+            for (int j = 1; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    size_t q = IEX(i, j, k);
+                    double dHz_y = Hz[IHZ(i, j, k)] - Hz[IHZ(i, j - 1, k)];
+                    double dHy_z = Hy[IHY(i, j, k)] - Hy[IHY(i, j, k - 1)];
+                    p_exy[q] = bey[j] * p_exy[q] + aey[j] * dHz_y;
+                    p_exz[q] = bez[k] * p_exz[q] + aez[k] * dHy_z;
+                    Ex[q] += ce * (dHz_y / (key[j] * dx) + p_exy[q] - dHy_z / (kez[k] * dx) - p_exz[q] - Jx[q]);
+                }
+        #pragma omp parallel for schedule(static)
+        for (int k = 1; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 1; i < nx; ++i) {
+                    size_t q = IEY(i, j, k);
+                    double dHx_z = Hx[IHX(i, j, k)] - Hx[IHX(i, j, k - 1)];
+                    double dHz_x = Hz[IHZ(i, j, k)] - Hz[IHZ(i - 1, j, k)];
+                    p_eyz[q] = bez[k] * p_eyz[q] + aez[k] * dHx_z;
+                    p_eyx[q] = bex[i] * p_eyx[q] + aex[i] * dHz_x;
+                    Ey[q] += ce * (dHx_z / (kez[k] * dx) + p_eyz[q] - dHz_x / (kex[i] * dx) - p_eyx[q] - Jy[q]);
+                }
+        #pragma omp parallel for schedule(static)
+        for (int k = 0; k < nz; ++k)
+            for (int j = 1; j < ny; ++j)
+                for (int i = 1; i < nx; ++i) {
+                    size_t q = IEZ(i, j, k);
+                    double dHy_x = Hy[IHY(i, j, k)] - Hy[IHY(i - 1, j, k)];
+                    double dHx_y = Hx[IHX(i, j, k)] - Hx[IHX(i, j - 1, k)];
+                    p_ezx[q] = bex[i] * p_ezx[q] + aex[i] * dHy_x;
+                    p_ezy[q] = bey[j] * p_ezy[q] + aey[j] * dHx_y;
+                    Ez[q] += ce * (dHy_x / (kex[i] * dx) + p_ezx[q] - dHx_y / (key[j] * dx) - p_ezy[q] - Jz[q]);
+                }
+
+        /* 5. soft source at t^{n+1} */
+        if (src_amp != 0.0 && src_kind != 0 && src_k > 0 && src_k < nz) {
+            double g = source_wave((double)(n + 1) * dt, src_amp, src_f, src_tau, src_t0);
+            if (src_kind == 1)
+                for (int j = 1; j < ny; ++j)
+                    for (int i = 0; i < nx; ++i) Ex[IEX(i, j, src_k)] += g;
+            if (src_kind == 2 && src_i >= 0 && src_i < nx && src_j > 0 && src_j < ny)
+                Ex[IEX(src_i, src_j, src_k)] += g;
+        }
+        for (int p = 0; p < nprobe; ++p) probe_out[s * nprobe + p] = E[probe_idx[p]];
+    }
+#undef IEX
+#undef IEY
+#undef IEZ
+#undef IHX
+#undef IHY
+#undef IHZ
+    free(v); free(F0); free(dF0); free(sh);
+    for (int a = 0; a < 3; ++a)
+        for (int q = 0; q < 6; ++q) free(pr[a][q]);
+    free(pidx); free(pn); free(pnu);
     return 0;
 }
