@@ -57,6 +57,7 @@ enum fdtd_nu_model { FDTD_NU_HARD_SPHERE = 0, FDTD_NU_CONST = 1 };
 enum fdtd_closure_kind { FDTD_CLOSURE_KINETIC = 0, FDTD_CLOSURE_MLP = 1 };
 enum fdtd_source_kind { FDTD_SRC_NONE = 0, FDTD_SRC_LINE_SOFT = 1, FDTD_SRC_POINT_SOFT = 2 };
 enum fdtd_kinetic_model { FDTD_KINETIC_LINEAR = 0, FDTD_KINETIC_FULL = 1 };
+enum fdtd_f0_model { FDTD_F0_MAXWELL = 0, FDTD_F0_DRUYVESTEYN = 1 };
 
 /* Field selectors for read_fields / add_probe.
  * 1D grids (Ez at nodes i = 0..nx, Hy at i + 1/2):
@@ -69,18 +70,27 @@ enum fdtd_kinetic_model { FDTD_KINETIC_LINEAR = 0, FDTD_KINETIC_FULL = 1 };
  *   FDTD_F_JX [ny+1][nx], FDTD_F_JY [ny][nx+1] (edge currents, A/m^2),
  *   FDTD_F_JCX, FDTD_F_JCY [ny][nx] cell-centre currents (A/m^2, 0 off plasma),
  *   FDTD_F_DF [ncell][nv][nv] (vx index, vy index), the cells that run the kinetic step,
- *             in row-major order (with the learned closure: its fallback cells only). */
+ *             in row-major order (with the learned closure: its fallback cells only).
+ * 3D grids (storage [k][j][i], i fastest; H in A/m, J in A/m^2):
+ *   FDTD_F_EX [nz+1][ny+1][nx] at (i+1/2, j, k), FDTD_F_EY [nz+1][ny][nx+1] at (i, j+1/2, k),
+ *   FDTD_F_EZ [nz][ny+1][nx+1] at (i, j, k+1/2), FDTD_F_HX [nz][ny][nx+1] at (i, j+1/2, k+1/2),
+ *   FDTD_F_HY [nz][ny+1][nx] at (i+1/2, j, k+1/2), FDTD_F_HZ [nz+1][ny][nx] at (i+1/2, j+1/2, k),
+ *   FDTD_F_JX / JY / JZ shaped like EX / EY / EZ,
+ *   FDTD_F_DF [npoint][nv]: F1 on the speed grid (s^3/m^6) of every plasma point, the
+ *             Ex points first, then Ey, then Ez, each in storage order. */
 enum fdtd_field {
   FDTD_F_E = 0, FDTD_F_H = 1, FDTD_F_J = 2, FDTD_F_DF = 3,
   FDTD_F_EX = 4, FDTD_F_EY = 5, FDTD_F_HZ = 6, FDTD_F_JX = 7, FDTD_F_JY = 8,
-  FDTD_F_JCX = 9, FDTD_F_JCY = 10
+  FDTD_F_JCX = 9, FDTD_F_JCY = 10,
+  FDTD_F_EZ = 11, FDTD_F_HX = 12, FDTD_F_HY = 13, FDTD_F_JZ = 14
 };
 
-/* Grid (section 2): dims 1 = (Ez, Hy) line, 2 = TEz plane.  nx (and ny) in cells,
- * dx in metres (dy = dx), courant = c dt / dx (rejected above 1 in 1D, 1/sqrt(2) in 2D).
- * boundary: 1D takes PEC or MUR1, 2D takes PEC or CPML.  The CPML parameters follow
- * the paper's ranges (thickness 8 cells, order 2-4, sigma factor 0.7-1.5, kappa_max
- * 5-11, alpha_max 0-0.05 S/m). */
+/* Grid (section 2): dims 1 = (Ez, Hy) line, 2 = TEz plane, 3 = Yee cube.  nx, ny, nz in
+ * cells (nz read for dims 3 only), dx in metres (dy = dz = dx), courant = c dt / dx
+ * (rejected above 1 in 1D, 1/sqrt(2) in 2D, 1/sqrt(3) in 3D).  boundary: 1D takes PEC or
+ * MUR1, 2D and 3D take PEC or CPML (3D: the layer on all six faces).  The CPML parameters
+ * follow the paper's ranges (thickness 8 cells, order 2-4, sigma factor 0.7-1.5,
+ * kappa_max 5-11, alpha_max 0-0.05 S/m). */
 typedef struct {
   int32_t dims;
   int32_t nx, ny;
@@ -90,6 +100,7 @@ typedef struct {
   int32_t boundary;
   int32_t cpml_cells;
   double cpml_order, cpml_sigma_factor, cpml_kappa_max, cpml_alpha_min, cpml_alpha_max;
+  int32_t nz;
 } fdtd_grid;
 
 /* Plasma profile (section 5.2).  ne / nu_mean: host arrays, 1D: [nx+1] per E node,
@@ -105,7 +116,15 @@ typedef struct {
  * its odd part F1.  The velocity derivative is in conservative flux form with zero flux
  * through +-vmax (electron number is kept exactly) and is explicit: each step needs
  * |(e/m) E dt / dv| <= 1, and a step that breaks it sets the run status (see
- * fdtd_plasma_run_status).  FULL runs are never temporally blocked. */
+ * fdtd_plasma_run_status).  FULL runs are never temporally blocked.
+ * 3D grids (the paper's production model, section 5.3): ne / nu_mean are per cell
+ * [nz][ny][nx]; F1 is a vector on a speed grid of nv speeds (1..64; the paper uses 31)
+ * v_k = (k + 1/2) vmax / nv, one component at every E point whose edge touches plasma (the
+ * point takes the mean ne and nu_mean of the four cells around its edge), updated as
+ * in 2D with J = -e (4 pi / 3) (vmax / nv) sum v^3 F1.  f0_model (3D only): MAXWELL, or
+ * DRUYVESTEYN, exp(-(v / vD)^4) with the Maxwellian's mean energy (3/2) e te_ev; either
+ * normalised by 4 pi (vmax / nv) sum v^2 F0 = 1.  3D runs take the kinetic closure and
+ * the linear model. */
 typedef struct {
   const double *ne;
   const double *nu_mean;
@@ -116,15 +135,19 @@ typedef struct {
   int32_t closure;
   const void *mlp;
   int32_t kinetic;
+  int32_t f0_model;
 } fdtd_profile;
 
 /* Soft source (section 5.2 table): adds amplitude * sin(2 pi f (t - t0))
  * exp(-((t - t0)/tau)^2) to E at t^{n+1} after each E update.  1D: node i (POINT).
- * 2D: LINE adds to every Ey(i, j + 1/2) of column i; POINT adds to Ey(i, j + 1/2). */
+ * 2D: LINE adds to every Ey(i, j + 1/2) of column i; POINT adds to Ey(i, j + 1/2).
+ * 3D: LINE adds to every updated Ex(i + 1/2, j, k) of the plane k (a sheet: a plane wave
+ * along z), POINT to Ex(i + 1/2, j, k); 0 < k < nz. */
 typedef struct {
   int32_t kind;
   int32_t i, j;
   double amplitude, f_hz, tau_s, t0_s;
+  int32_t k;
 } fdtd_source;
 
 /* Device binding.  hip_stream: a hipStream_t (NULL = null stream).  workspace: device
@@ -196,7 +219,8 @@ int fdtd_plasma_read_fields(fdtd_plasma *h, int32_t run, int32_t field, double *
                             size_t dst_len, int64_t *step_out);
 
 /* Record `field` at grid index (i, j) after every step (1D: j ignored).  Only before
- * the first step; at most fdtd_device.max_probes.  *id receives the probe id. */
+ * the first step; at most fdtd_device.max_probes.  *id receives the probe id.  3D handles
+ * take no probes (FDTD_EINVAL): read whole fields instead. */
 int fdtd_plasma_add_probe(fdtd_plasma *h, int32_t run, int32_t field, int32_t i, int32_t j,
                           int32_t *id);
 /* Copy the last min(steps, probe_capacity) samples of probe `id` (oldest first). */

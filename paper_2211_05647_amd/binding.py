@@ -19,8 +19,9 @@ BC_PEC, BC_MUR1, BC_CPML = 0, 1, 2
 NU_HARD_SPHERE, NU_CONST = 0, 1
 CLOSURE_KINETIC, CLOSURE_MLP = 0, 1
 KINETIC_LINEAR, KINETIC_FULL = 0, 1
+F0_MAXWELL, F0_DRUYVESTEYN = 0, 1
 SRC_NONE, SRC_LINE, SRC_POINT = 0, 1, 2
-F_E, F_H, F_J, F_DF, F_EX, F_EY, F_HZ, F_JX, F_JY, F_JCX, F_JCY = range(11)
+F_E, F_H, F_J, F_DF, F_EX, F_EY, F_HZ, F_JX, F_JY, F_JCX, F_JCY, F_EZ, F_HX, F_HY, F_JZ = range(15)
 
 OK, EINVAL, ENOMEM, EDEVICE, ERANGE, ENUMERIC, ESTATE = 0, -1, -2, -3, -4, -5, -6
 
@@ -33,19 +34,21 @@ class Grid(C.Structure):
                 ("precision", C.c_int32), ("boundary", C.c_int32),
                 ("cpml_cells", C.c_int32), ("cpml_order", C.c_double),
                 ("cpml_sigma_factor", C.c_double), ("cpml_kappa_max", C.c_double),
-                ("cpml_alpha_min", C.c_double), ("cpml_alpha_max", C.c_double)]
+                ("cpml_alpha_min", C.c_double), ("cpml_alpha_max", C.c_double),
+                ("nz", C.c_int32)]
 
 
 class Profile(C.Structure):
     _fields_ = [("ne", _dp), ("nu_mean", _dp), ("te_ev", C.c_double), ("nv", C.c_int32),
                 ("vmax_over_vth", C.c_double), ("nu_model", C.c_int32),
-                ("closure", C.c_int32), ("mlp", C.c_void_p), ("kinetic", C.c_int32)]
+                ("closure", C.c_int32), ("mlp", C.c_void_p), ("kinetic", C.c_int32),
+                ("f0_model", C.c_int32)]
 
 
 class Source(C.Structure):
     _fields_ = [("kind", C.c_int32), ("i", C.c_int32), ("j", C.c_int32),
                 ("amplitude", C.c_double), ("f_hz", C.c_double), ("tau_s", C.c_double),
-                ("t0_s", C.c_double)]
+                ("t0_s", C.c_double), ("k", C.c_int32)]
 
 
 class Device(C.Structure):
@@ -132,9 +135,9 @@ def _arr(a):
 
 
 def make_grid(dims, nx, ny, dx, courant, precision, boundary, cpml_cells=8, cpml_order=3.0,
-              sigma_factor=1.0, kappa_max=5.0, alpha_min=0.0, alpha_max=0.05):
+              sigma_factor=1.0, kappa_max=5.0, alpha_min=0.0, alpha_max=0.05, nz=1):
     return Grid(dims, nx, ny, dx, courant, precision, boundary, cpml_cells, cpml_order,
-                sigma_factor, kappa_max, alpha_min, alpha_max)
+                sigma_factor, kappa_max, alpha_min, alpha_max, nz)
 
 
 class Sim:
@@ -159,7 +162,12 @@ class Sim:
         self._keep = []
         grids, profs, srcs = [], [], []
         for w in runs:
-            if hasattr(w, "ny"):
+            if hasattr(w, "nz"):
+                g = make_grid(3, w.nx, w.ny, w.dx, w.courant, precision,
+                              BC_CPML if w.ncpml > 0 else BC_PEC, max(w.ncpml, 0), nz=w.nz)
+                src = Source(w.src_kind if w.src_amp != 0 else SRC_NONE, w.src_i, w.src_j,
+                             w.src_amp, w.src_f, w.src_tau, w.src_t0, w.src_k)
+            elif hasattr(w, "ny"):
                 g = make_grid(2, w.nx, w.ny, w.dx, w.courant, precision, BC_CPML, w.ncpml)
                 if w.ncpml == 0:
                     g.boundary = BC_PEC
@@ -179,7 +187,9 @@ class Sim:
             p = Profile(pne, pnu, w.te_ev, w.nv, w.vmax_over_vth,
                         NU_HARD_SPHERE if w.nu_model == "hard_sphere" else NU_CONST,
                         closure, mlp_ptr,
-                        KINETIC_FULL if getattr(w, "kinetic", "linear") == "full" else KINETIC_LINEAR)
+                        KINETIC_FULL if getattr(w, "kinetic", "linear") == "full" else KINETIC_LINEAR,
+                        F0_DRUYVESTEYN if getattr(w, "f0_model", "maxwell") == "druyvesteyn"
+                        else F0_MAXWELL)
             grids.append(g)
             profs.append(p)
             srcs.append(src)

@@ -260,4 +260,31 @@ template <class T> struct Run2D {
   T* probe_buf;
 };
 
+// One 3D run (the Yee cube with the CPML on all faces, section 2, and the speed-grid F1
+// of section 5.3).  Storage [k][j][i], i fastest: Ex [nz+1][ny+1][nx], Ey [nz+1][ny][nx+1],
+// Ez [nz][ny+1][nx+1], Hx [nz][ny][nx+1], Hy [nz][ny+1][nx], Hz [nz+1][ny][nx]; E (and J)
+// components contiguous, so a plasma point is one index into Ex..Ez.  Normalised: H by
+// eta0, J by dt/eps0, psi by dx.  Each psi array lives only in the layer of its derivative
+// axis: that axis's extent is replaced by 2m (first m: the low layer, then the high one).
+template <class T> struct Run3D {
+  T *Ex, *Ey, *Ez, *Hx, *Hy, *Hz, *Jx, *Jy, *Jz;
+  T *p_exy, *p_exz, *p_eyz, *p_eyx, *p_ezx, *p_ezy;
+  T *p_hxz, *p_hxy, *p_hyx, *p_hyz, *p_hzy, *p_hzx;
+  T* df;                  // [np][row] F1 on the speed grid, row >= vdim (padding stays 0)
+  const int32_t* pidx;    // [np] index of the plasma point into the E (and J) arrays
+  const T* tau;           // [np] dt * nu_mean
+  const T* dens;          // [np] electron density
+  const T* s_bin;         // [row] collision-frequency shape (0 in the padding)
+  const T* b_bin;         // [row] 2 dt (e/m) dF0/dv per unit density (0 in the padding)
+  const double* w_bin;    // [row] (dt/eps0)(-e)(4 pi / 3) gam v^3 (0 in the padding)
+  // CPML profiles per axis: e side at integer positions, h side at half positions
+  const T *bex, *aex, *rkex, *bhx, *ahx, *rkhx;
+  const T *bey, *aey, *rkey, *bhy, *ahy, *rkhy;
+  const T *bez, *aez, *rkez, *bhz, *ahz, *rkhz;
+  int32_t nx, ny, nz, m, np, row;
+  T S;
+  int32_t src_kind, src_i, src_j, src_k;
+  double src_amp, src_w, src_tau, src_t0, dt;
+};
+
 }  // namespace fdtdp

@@ -90,42 +90,6 @@ size_t layout(Host2D* h, int max_probes, int probe_cap) {
 
 // CPML coefficients at depth rho into a layer of thickness `thick` (section 2 formulas):
 // b = exp(-(sigma/kappa + alpha) dt / eps0), a = sigma (b - 1) / (sigma kappa + alpha kappa^2)
-void cpml_point(const fdtd_grid& g, double rho, double thick, double dt, double* b, double* a,
-                double* rk) {
-  if (rho <= 0.0) { *b = 0.0; *a = 0.0; *rk = 1.0; return; }
-  const double smax = g.cpml_sigma_factor * (g.cpml_order + 1.0) / (150.0 * M_PI * g.dx);
-  const double r = rho / thick;
-  const double sig = smax * std::pow(r, g.cpml_order);
-  const double kap = 1.0 + (g.cpml_kappa_max - 1.0) * std::pow(r, g.cpml_order);
-  const double alp = g.cpml_alpha_min + (g.cpml_alpha_max - g.cpml_alpha_min) * (1.0 - r);
-  *b = std::exp(-(sig / kap + alp) * dt / kEps0);
-  *a = sig * (*b - 1.0) / (sig * kap + alp * kap * kap);
-  *rk = 1.0 / kap;
-}
-
-template <class T>
-void axis_profile(const fdtd_grid& g, int n, int m, double dt, T* be, T* ae, T* rke, T* bh,
-                  T* ah, T* rkh) {
-  const double thick = m * g.dx;
-  for (int i = 0; i <= n; ++i) {
-    double rho = 0.0;
-    if (m > 0 && i < m) rho = (m - i) * g.dx;
-    if (m > 0 && i > n - m) rho = (i - (n - m)) * g.dx;
-    double b, a, rk;
-    cpml_point(g, rho, thick, dt, &b, &a, &rk);
-    be[i] = (T)b; ae[i] = (T)a; rke[i] = (T)rk;
-  }
-  for (int i = 0; i < n; ++i) {
-    const double x = i + 0.5;
-    double rho = 0.0;
-    if (m > 0 && x < m) rho = (m - x) * g.dx;
-    if (m > 0 && x > n - m) rho = (x - (n - m)) * g.dx;
-    double b, a, rk;
-    cpml_point(g, rho, thick, dt, &b, &a, &rk);
-    bh[i] = (T)b; ah[i] = (T)a; rkh[i] = (T)rk;
-  }
-}
-
 template <class T>
 int upload(Host2D* h, char* ws, hipStream_t st, const std::vector<ProbeInfo>& probes,
            size_t probe_off, int probe_cap) {

@@ -203,6 +203,8 @@ struct fdtd_plasma {
   std::vector<ProbeInfo> probes;
   // 2D
   Host2D* h2 = nullptr;
+  // 3D
+  Host3D* h3 = nullptr;
   // timing
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int64_t last_n = 0;
@@ -535,6 +537,9 @@ int finish_upload(fdtd_plasma* h) {
     if (rc) return rc;
     rc = build_tiles_1d(h);
     if (rc) return rc;
+  } else if (h->dims == 3) {
+    rc = upload_3d(h->h3, h->ws, h->stream);
+    if (rc) return rc;
   } else {
     rc = upload_2d(h->h2, h->ws, h->stream, h->probes, h->probe_off, h->probe_cap);
     if (rc) return rc;
@@ -640,6 +645,12 @@ int fdtd_plasma_workspace_size(const fdtd_grid* grid, const fdtd_profile* profil
     *bytes = workspace_2d(grid, profile, mp, pc);
     return FDTD_OK;
   }
+  if (grid->dims == 3) {
+    int rc = validate_3d(grid, profile, nullptr);
+    if (rc) return rc;
+    *bytes = workspace_3d(grid, profile);
+    return FDTD_OK;
+  }
   int rc = validate_1d(grid, profile, nullptr, false);
   if (rc) return rc;
   std::vector<RunSpec1D> specs(1);
@@ -698,6 +709,43 @@ int fdtd_plasma_create(const fdtd_grid* grid, const fdtd_profile* profile,
     h->state_bytes = state_bytes;
     h->probe_off = probe_off;
     int rc2 = attach_workspace(h, dev, workspace_2d(grid, profile, dev->max_probes, dev->probe_capacity));
+    if (!rc2) rc2 = finish_upload(h);
+    if (!rc2) {
+      hipError_t e = hipEventCreate(&h->ev0);
+      if (!e) e = hipEventCreate(&h->ev1);
+      if (e) rc2 = hip_fail(e, "hipEventCreate");
+    }
+    if (rc2) {
+      fdtd_plasma_destroy(h);
+      return rc2;
+    }
+    *out = h;
+    return FDTD_OK;
+  }
+  if (grid->dims == 3) {
+    int rc = validate_3d(grid, profile, source);
+    if (rc) return rc;
+    rc = check_device(dev);
+    if (rc) return rc;
+    fdtd_plasma* h = new (std::nothrow) fdtd_plasma();
+    if (!h) return fail(FDTD_ENOMEM, "host allocation");
+    h->dims = 3;
+    h->nruns = 1;
+    h->precision = grid->precision;
+    h->device = dev->device;
+    h->stream = reinterpret_cast<hipStream_t>(dev->hip_stream);
+    h->max_probes = 0;      // 3D handles take no probes
+    h->probe_cap = 0;
+    size_t state_bytes = 0;
+    h->h3 = make_3d(grid, profile, source, &state_bytes);
+    if (!h->h3) {
+      delete h;
+      return fail(FDTD_ENOMEM, "host allocation (3D)");
+    }
+    h->state_off = 0;
+    h->state_bytes = state_bytes;
+    h->probe_off = 0;
+    int rc2 = attach_workspace(h, dev, workspace_3d(grid, profile));
     if (!rc2) rc2 = finish_upload(h);
     if (!rc2) {
       hipError_t e = hipEventCreate(&h->ev0);
@@ -807,6 +855,8 @@ int fdtd_plasma_run(fdtd_plasma* h, int64_t nsteps) {
       e = h->precision == FDTD_FP64
               ? launch_step1d<double>(h->ws + h->runs_off, h->ws + h->tiles_off, n, s, h->stream, full)
               : launch_step1d<float>(h->ws + h->runs_off, h->ws + h->tiles_off, n, s, h->stream, full);
+    } else if (h->dims == 3) {
+      e = launch_step3d(h->h3, s, h->stream);
     } else {
       e = launch_step2d(h->h2, s, h->stream);
     }
@@ -840,6 +890,7 @@ int fdtd_plasma_field_size(const fdtd_plasma* h, int32_t run, int32_t field, siz
   if (!h || !n) return fail(FDTD_EINVAL, "null argument");
   if (run < 0 || run >= h->nruns) return fail(FDTD_ERANGE, "run %d out of range", run);
   if (h->dims == 2) return field_size_2d(h->h2, field, n);
+  if (h->dims == 3) return field_size_3d(h->h3, field, n);
   const Host1D& x = h->h1[run];
   switch (field) {
     case FDTD_F_E: case FDTD_F_J: *n = x.nx + 1; return FDTD_OK;
@@ -860,6 +911,9 @@ int fdtd_plasma_read_fields(fdtd_plasma* h, int32_t run, int32_t field, double* 
   if (e) return hip_fail(e, "synchronise");
   if (h->dims == 2) {
     rc = read_2d(h->h2, h->ws, field, h->step, dst);
+    if (rc) return rc;
+  } else if (h->dims == 3) {
+    rc = read_3d(h->h3, h->ws, field, dst);
     if (rc) return rc;
   } else {
     const Host1D& x = h->h1[run];
@@ -902,7 +956,7 @@ int fdtd_plasma_read_fields(fdtd_plasma* h, int32_t run, int32_t field, double* 
     }
     if (step_out) *step_out = srun;
   }
-  if (step_out && h->dims == 2) *step_out = h->step;
+  if (step_out && h->dims != 1) *step_out = h->step;
   for (size_t k = 0; k < n; ++k)
     if (!std::isfinite(dst[k])) return fail(FDTD_ENUMERIC, "non-finite value at index %zu", k);
   return FDTD_OK;
@@ -911,6 +965,7 @@ int fdtd_plasma_read_fields(fdtd_plasma* h, int32_t run, int32_t field, double* 
 int fdtd_plasma_add_probe(fdtd_plasma* h, int32_t run, int32_t field, int32_t i, int32_t j,
                           int32_t* id) {
   if (!h || !id) return fail(FDTD_EINVAL, "null argument");
+  if (h->dims == 3) return fail(FDTD_EINVAL, "3D handles take no probes");
   if (h->started) return fail(FDTD_ESTATE, "probes must be added before the first step");
   if ((int)h->probes.size() >= h->max_probes) return fail(FDTD_ERANGE, "no probe slot left");
   if (h->probe_cap <= 0) return fail(FDTD_ERANGE, "probe_capacity is 0");
@@ -1065,6 +1120,11 @@ int fdtd_plasma_tap_buffer(fdtd_plasma* h, int32_t run, const float** dev, int64
 
 int fdtd_plasma_closure_counts(fdtd_plasma* h, int64_t* closure_cells, int64_t* kinetic_cells) {
   if (!h || !closure_cells || !kinetic_cells) return fail(FDTD_EINVAL, "null argument");
+  if (h->dims == 3) {
+    *closure_cells = 0;
+    *kinetic_cells = points_3d(h->h3);
+    return FDTD_OK;
+  }
   if (h->dims != 2) {
     *closure_cells = 0;
     int64_t k = 0;
@@ -1104,6 +1164,7 @@ int fdtd_plasma_set_tiling(fdtd_plasma* h, int32_t tile, int32_t cells_per_group
     hipError_t e = hipStreamSynchronize(h->stream);
     return e ? hip_fail(e, "synchronise") : FDTD_OK;
   }
+  if (h->dims == 3) return FDTD_OK;   // one fixed launch shape
   return set_tiling_2d(h->h2, h->ws, h->stream, tile, cells_per_group);
 }
 
@@ -1134,6 +1195,7 @@ void fdtd_plasma_destroy(fdtd_plasma* h) {
   if (h->ev1) hipEventDestroy(h->ev1);
   if (h->owns_ws && h->ws) hipFree(h->ws);
   if (h->h2) destroy_2d(h->h2);
+  if (h->h3) destroy_3d(h->h3);
   delete h;
 }
 

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdarg>
 #include <cstddef>
 #include <cstdint>
@@ -96,5 +97,60 @@ double probe_scale_2d(const Host2D* h, int field);
 int set_tiling_2d(Host2D* h, char* ws, hipStream_t stream, int tile, int cells_per_group);
 void destroy_2d(Host2D* h);
 int closure_counts_2d(const Host2D* h, int64_t* nm, int64_t* nk);
+
+// 3D path (fdtd3d.cpp)
+struct Host3D;
+int validate_3d(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s);
+size_t workspace_3d(const fdtd_grid* g, const fdtd_profile* p);
+Host3D* make_3d(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s,
+                size_t* state_bytes);
+int upload_3d(Host3D* h, char* ws, hipStream_t stream);
+hipError_t launch_step3d(Host3D* h, int64_t step, hipStream_t stream);
+int points_3d(const Host3D* h);
+int field_size_3d(const Host3D* h, int field, size_t* n);
+int read_3d(Host3D* h, char* ws, int field, double* dst);
+void destroy_3d(Host3D* h);
+
+
+// CPML coefficients of section 2 (eq. (4) and the grading formulas after it) at depth rho
+// into a layer of thickness m dx: b, a (dimensionless: the derivative's dx folded in) and
+// 1/kappa.  axis_profile samples them along an axis of n cells with the layer at both
+// ends: e side at integer positions 0..n, h side at i + 1/2.
+inline void cpml_point(const fdtd_grid& g, double rho, double thick, double dt, double* b, double* a,
+                double* rk) {
+  if (rho <= 0.0) { *b = 0.0; *a = 0.0; *rk = 1.0; return; }
+  const double smax = g.cpml_sigma_factor * (g.cpml_order + 1.0) / (150.0 * M_PI * g.dx);
+  const double r = rho / thick;
+  const double sig = smax * std::pow(r, g.cpml_order);
+  const double kap = 1.0 + (g.cpml_kappa_max - 1.0) * std::pow(r, g.cpml_order);
+  const double alp = g.cpml_alpha_min + (g.cpml_alpha_max - g.cpml_alpha_min) * (1.0 - r);
+  *b = std::exp(-(sig / kap + alp) * dt / kEps0);
+  *a = sig * (*b - 1.0) / (sig * kap + alp * kap * kap);
+  *rk = 1.0 / kap;
+}
+
+template <class T>
+void axis_profile(const fdtd_grid& g, int n, int m, double dt, T* be, T* ae, T* rke, T* bh,
+                  T* ah, T* rkh) {
+  const double thick = m * g.dx;
+  for (int i = 0; i <= n; ++i) {
+    double rho = 0.0;
+    if (m > 0 && i < m) rho = (m - i) * g.dx;
+    if (m > 0 && i > n - m) rho = (i - (n - m)) * g.dx;
+    double b, a, rk;
+    cpml_point(g, rho, thick, dt, &b, &a, &rk);
+    be[i] = (T)b; ae[i] = (T)a; rke[i] = (T)rk;
+  }
+  for (int i = 0; i < n; ++i) {
+    const double x = i + 0.5;
+    double rho = 0.0;
+    if (m > 0 && x < m) rho = (m - x) * g.dx;
+    if (m > 0 && x > n - m) rho = (x - (n - m)) * g.dx;
+    double b, a, rk;
+    cpml_point(g, rho, thick, dt, &b, &a, &rk);
+    bh[i] = (T)b; ah[i] = (T)a; rkh[i] = (T)rk;
+  }
+}
+
 
 }  // namespace fdtdp

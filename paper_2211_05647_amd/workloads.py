@@ -225,3 +225,80 @@ def c4(n: int = 4096, nblobs: int = 48, extra_hot: int = 0, steps: int = 2000) -
     nub = nur * 2.0 * math.pi * F_REF
     return Run2D(name="c4", nx=n, ny=n, nv=32, ne=ne, nubar=nub, src_kind=1, src_i=20,
                  src_j=0, steps=steps, meta=dict(blobs=specs), **pulse(F_REF))
+
+
+COURANT_3D = 0.5
+
+# The paper's 3D Argon experiment (section 5.3 table): n = 1e19 m^-3, neutral density
+# N = 1e23 m^-3, Te = 1 eV, a 4 mm plasma slab along z between air, a 20 GHz Gaussian-
+# modulated plane wave (tau 48 ps, t0 217 ps).  Its elastic cross section s is not given:
+# a constant s = 1e-19 m^2 stands in (nu = N s v).
+ARGON_NE = 1e19
+ARGON_N = 1e23
+ARGON_S = 1e-19
+ARGON_TE = 1.0
+
+
+@dataclass
+class Run3D:
+    """One 3D run (Yee cube, CPML on all faces) with the speed-grid F1 in every plasma
+    point: per-cell inputs of shape (nz, ny, nx)."""
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    nv: int            # speeds of the grid (the paper's v_dim)
+    ne: np.ndarray
+    nubar: np.ndarray
+    src_kind: int      # 1 sheet of Ex on plane src_k (plane wave along z), 2 point
+    src_i: int
+    src_j: int
+    src_k: int
+    src_amp: float
+    src_f: float
+    src_tau: float
+    src_t0: float
+    steps: int
+    dx: float = DX_REF
+    courant: float = COURANT_3D
+    te_ev: float = ARGON_TE
+    vmax_over_vth: float = 5.0
+    nu_model: str = "hard_sphere"
+    f0_model: str = "druyvesteyn"
+    ncpml: int = 8
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def plasma_cells(self) -> int:
+        return int(np.count_nonzero(self.ne > 0))
+
+
+def argon_nubar(te_ev=ARGON_TE, f0="druyvesteyn"):
+    """Mean collision frequency N s <v> of the argon stand-in, with <v> the mean speed of
+    the F0 (continuous): Maxwellian sqrt(8 e Te / (pi m)); Druyvesteyn with the same mean
+    energy, vD Gamma(1) / Gamma(3/4), vD^2 = 3 (e Te / m) Gamma(3/4) / Gamma(5/4)."""
+    vth2 = _QE * te_ev / _ME
+    if f0 == "maxwell":
+        vbar = math.sqrt(8.0 * vth2 / math.pi)
+    else:
+        vd = math.sqrt(3.0 * vth2 * math.gamma(0.75) / math.gamma(1.25))
+        vbar = vd * math.gamma(1.0) / math.gamma(0.75)
+    return ARGON_N * ARGON_S * vbar
+
+
+def argon_slab_3d(nx=64, ny=64, nz=256, nv=31, steps=1200, slab_mm=4.0, ncpml=8,
+                  f0="druyvesteyn", name="argon3d") -> Run3D:
+    """The paper's 3D slab: air, a slab_mm plasma slab along z starting at the middle of
+    the box, air; a sheet source of Ex (a plane wave along z) 12 cells inside the low z
+    layer; CPML on all faces; density 1e19 m^-3 with +-5 % seeded cell-to-cell texture."""
+    g = rng("misc")
+    ne = np.zeros((nz, ny, nx))
+    nu = np.zeros((nz, ny, nx))
+    k0 = nz // 2
+    k1 = k0 + max(1, int(round(slab_mm * 1e-3 / DX_REF)))
+    ne[k0:k1] = ARGON_NE * (1.0 + 0.05 * (2.0 * g.random((k1 - k0, ny, nx)) - 1.0))
+    nu[k0:k1] = argon_nubar(f0=f0)
+    p = dict(src_amp=1.0, src_f=20e9, src_tau=48e-12, src_t0=217e-12)
+    return Run3D(name=name, nx=nx, ny=ny, nz=nz, nv=nv, ne=ne, nubar=nu, src_kind=1, src_i=0,
+                 src_j=0, src_k=ncpml + 4, steps=steps, ncpml=ncpml, f0_model=f0,
+                 meta=dict(slab=(k0, k1)), **p)

@@ -52,3 +52,34 @@ def space_time_1d(sim, orc, nsteps, every, probes, df_snaps=None):
         g_pr = np.stack([sim.read_probe(p, nsteps) for p in pids], axis=1)
         o_pr = np.concatenate(o_pr, axis=0)
     return np.array(g_snap), np.array(o_snap), g_pr, o_pr
+
+
+def oracle_3d(run):
+    """Oracle for a Run3D (same per-cell inputs, same source and layer)."""
+    from oracle.core import Oracle3D
+    return Oracle3D(run.nx, run.ny, run.nz, run.dx, run.courant, run.ne, run.nubar,
+                    vdim=run.nv, vmax_over_vth=run.vmax_over_vth, te_ev=run.te_ev,
+                    nu_model=run.nu_model, f0_model=run.f0_model, ncpml=run.ncpml,
+                    src_kind=run.src_kind, src_i=run.src_i, src_j=run.src_j, src_k=run.src_k,
+                    src_amp=run.src_amp, src_f=run.src_f, src_tau=run.src_tau,
+                    src_t0=run.src_t0)
+
+
+def space_time_3d(sim, orc, nsteps, every):
+    """Snapshots after every ``every`` steps from both sides: E, H and J (all three
+    components each) and the F1 rows.  Returns {name: (gpu, oracle)} of stacked arrays."""
+    from paper_2211_05647_amd import binding as B
+    out = {k: ([], []) for k in ("E", "H", "J", "DF")}
+    done = 0
+    while done < nsteps:
+        k = min(every, nsteps - done)
+        sim.run(k)
+        orc.run(k)
+        done += k
+        for name, fs, ref in (("E", (B.F_EX, B.F_EY, B.F_EZ), orc.E),
+                              ("H", (B.F_HX, B.F_HY, B.F_HZ), orc.H),
+                              ("J", (B.F_JX, B.F_JY, B.F_JZ), orc.J),
+                              ("DF", (B.F_DF,), orc.df)):
+            out[name][0].append(np.concatenate([sim.read(f) for f in fs]))
+            out[name][1].append(ref.copy())
+    return {k: (np.array(a), np.array(b)) for k, (a, b) in out.items()}
