@@ -172,6 +172,83 @@ def extra_full(B, W, torch):
     return out
 
 
+def bytes_3d(run, npoints, row):
+    """Algorithmic bytes of one 3D step (three launches): H read + written and E read once
+    by the H update; E read + written and H read by the E update; CPML memory read +
+    written inside the strips; F1 rows read + written with their scalars, E read and
+    written (J taken off in place) and J written by the kinetic update (FP32)."""
+    X, Y, Z, m = run.nx, run.ny, run.nz, run.ncpml
+    cells = X * Y * Z
+    strips = 4 * 2 * m * (X * Y + Y * Z + Z * X) if m > 0 else 0.0
+    return (cells * 3 * 4 * 3 + cells * 3 * 4 * 3 + strips * 8
+            + npoints * (row * 8 + 12 + 12))
+
+
+def extra_3d(B, W, torch, steps=300):
+    """The paper's production model in 3D: the argon-style slab (Druyvesteyn F0, v_dim = 31
+    speeds, a 4 mm slab along z, sheet source, CPML on all faces) at 128 x 128 x 512."""
+    run = W.argon_slab_3d(nx=128, ny=128, nz=512, steps=steps)
+    sim = B.Sim(run, precision=B.FP32)
+    npoints = sim.closure_counts()[1]
+    log(f"argon3d: {run.nx}x{run.ny}x{run.nz}, plasma points {npoints}")
+    sim.run(20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.run(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = sim.last_run_ms()
+    sim.read(B.F_EX)
+    sim.close()
+    row = 32
+    by = bytes_3d(run, npoints, row)
+    cells = run.nx * run.ny * run.nz
+    return {"argon3d": dict(workload=f"3D Yee + CPML + speed-grid F1 (v_dim {run.nv}, Druyvesteyn), "
+                                     f"{run.nx}x{run.ny}x{run.nz}, FP32, {steps} steps",
+                            plasma_points=npoints, cells=cells,
+                            updates_per_s=npoints * run.nv * steps / wall,
+                            nmcps=cells * steps / wall * 1e-6,
+                            ms_per_step=wall / steps * 1e3, kernel_ms_per_step=ms,
+                            hbm_gbs=by / (ms * 1e-3) / 1e9,
+                            hbm_frac=by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)}
+
+
+def sweep_3d(B, W, torch, cpu_budget_s=2.0):
+    """NMCPS (eq. (5)) of the 3D vacuum cube (CPML on all faces, sheet source) from 16^3
+    to 384^3 on the GPU (FP32), and on the host with the FP64 oracle up to 96^3."""
+    sys.path.insert(0, ROOT)
+    from oracle.core import Oracle3D, threads
+    out = []
+    for n in (16, 32, 64, 128, 192, 256, 384):
+        z = np.zeros((n, n, n))
+        run = W.Run3D(name=f"vac3d{n}", nx=n, ny=n, nz=n, nv=1, ne=z, nubar=z, src_kind=1,
+                      src_i=0, src_j=0, src_k=n // 4, steps=0, ncpml=min(8, n // 4),
+                      **W.pulse(W.F_REF))
+        steps = max(60, min(2000, int(2e9 / n ** 3)))
+        sim = B.Sim(run, precision=B.FP32)
+        sim.run(10)
+        sim.run(steps)
+        ms = sim.last_run_ms()
+        sim.close()
+        row = {"n": n, "cells": n ** 3, "gpu_nmcps": n ** 3 / (ms * 1e-3) * 1e-6,
+               "gpu_us_per_step": ms * 1e3}
+        if n <= 96:
+            o = Oracle3D(n, n, n, run.dx, run.courant, z, z, vdim=1, ncpml=run.ncpml,
+                         src_kind=1, src_k=run.src_k, src_amp=run.src_amp, src_f=run.src_f,
+                         src_tau=run.src_tau, src_t0=run.src_t0)
+            t0 = time.perf_counter()
+            o.run(3)
+            per = (time.perf_counter() - t0) / 3
+            k = max(3, int(cpu_budget_s / max(per, 1e-7)))
+            t0 = time.perf_counter()
+            o.run(k)
+            row["cpu_oracle_nmcps"] = n ** 3 * k / (time.perf_counter() - t0) * 1e-6
+            row["cpu_threads"] = threads()
+        out.append(row)
+        log(f"sweep 3D vacuum {n}^3: {row}")
+    return {"vacuum_3d": out}
+
+
 def extra_c2(B, W, torch, autotune, steps=None):
     """2D column, 512^2, 32x32 velocity bins."""
     run = W.c2()
@@ -285,6 +362,7 @@ def extra_workloads(B, W, torch, autotune):
     out.update(extra_c3(B, W, torch))
     out.update(closure_speedup(B, W, torch))
     out.update(extra_full(B, W, torch))
+    out.update(extra_3d(B, W, torch))
     return out
 
 
@@ -363,7 +441,7 @@ def main():
                     help="steps per launch of the large 1D workload (default: tuned; 1 = one "
                          "step per launch)")
     ap.add_argument("--calibrate-copy", action="store_true")
-    ap.add_argument("--only", choices=["c1l", "c2", "c3", "closure", "c4", "sweep", "full"], default=None,
+    ap.add_argument("--only", choices=["c1l", "c2", "c3", "closure", "c4", "sweep", "full", "3d", "sweep3d"], default=None,
                     help="run only one of the extra measurements (for profiling); c2 and c4 "
                          "take --steps steps")
     args = ap.parse_args()
@@ -387,7 +465,9 @@ def main():
                 "closure": lambda: closure_speedup(B, W, torch),
                 "c4": lambda: c4_steps(B, W, torch, args.steps),
                 "sweep": lambda: nmcps_sweep(B, W, torch),
-                "full": lambda: extra_full(B, W, torch)}[args.only]
+                "full": lambda: extra_full(B, W, torch),
+                "3d": lambda: extra_3d(B, W, torch, args.steps),
+                "sweep3d": lambda: sweep_3d(B, W, torch)}[args.only]
         print(json.dumps(only()), flush=True)
         return
 

@@ -7,7 +7,8 @@
 //   k_kin3d  F1 of every plasma point driven by its E component at t^n (Crank-Nicolson in
 //            the collision term) and the FP64 moment J = -e (4 pi / 3) gam sum v^3 F1,
 //            one lane group per point row;
-//   k_e3d    E^{n+1} = E^n + S curl H - J with the CPML memory, the soft source at t^{n+1}.
+//   k_e3d    E^{n+1} = E^n + S curl H - J with the CPML memory, the soft source at t^{n+1}
+//            (the kinetic launch subtracts J at the plasma points, in place).
 // Tangential E on the outer faces is never written (PEC backing of the layer).
 #include "common.h"
 
@@ -27,12 +28,42 @@ __device__ __forceinline__ int layer_h(int u, int n, int m) {
 
 }  // namespace
 
+// The H and E launches map one thread to one lattice point (i, j) of a k plane: the
+// plane's (nx+1)(ny+1) points are numbered i fastest and cut into tiles of 256, so every
+// lane has work whatever nx is.  Work-groups are dealt to the 8 XCDs round robin
+// (work-group b runs on XCD b mod 8); the tiles are renumbered so that each XCD takes a
+// contiguous slab of planes, in order: the neighbouring plane a point's curl reads
+// (k + 1 for H, k - 1 for E) was then just loaded into that XCD's L2.  (A thread marching
+// through a run of planes with that neighbour in a register measured slower: fewer
+// threads, a serial chain of loads.)
+constexpr int kXcds = 8;
+
+struct PlaneTile {
+  int i, j, k;
+  bool ok;
+};
+
+__device__ __forceinline__ PlaneTile plane_tile(int nx, int ny, int nz) {
+  const int tiles = ((nx + 1) * (ny + 1) + 255) / 256;
+  const int per_xcd = gridDim.x / kXcds;          // gridDim.x is a multiple of kXcds
+  const int b = blockIdx.x;
+  const int logical = (b % kXcds) * per_xcd + b / kXcds;
+  const int k = logical / tiles, tile = logical - k * tiles;
+  const int t = tile * 256 + threadIdx.x;
+  PlaneTile p;
+  p.ok = k <= nz && t < (nx + 1) * (ny + 1);
+  p.j = t / (nx + 1);
+  p.i = t - p.j * (nx + 1);
+  p.k = k;
+  return p;
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void k_h3d(const Run3D<T> R) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y, k = blockIdx.z;
   const int nx = R.nx, ny = R.ny, nz = R.nz, m = R.m;
-  if (i > nx) return;
+  const PlaneTile pt = plane_tile(nx, ny, nz);
+  if (!pt.ok) return;
+  const int i = pt.i, j = pt.j, k = pt.k;
   const size_t sEx_j = nx, sEx_k = (size_t)(ny + 1) * nx;
   const size_t sEy_j = nx + 1, sEy_k = (size_t)ny * (nx + 1);
   const size_t sEz_j = nx + 1, sEz_k = (size_t)(ny + 1) * (nx + 1);
@@ -126,7 +157,8 @@ __global__ __launch_bounds__(256) void k_kin3d(const Run3D<T> R) {
 #pragma unroll
   for (int v = 0; v < VPL; ++v) w[v] = R.w_bin[li * VPL + v];
   V* __restrict__ dfv = reinterpret_cast<V*>(R.df);
-  const T* __restrict__ E = R.Ex;   // Ex, Ey, Ez are contiguous
+  const T* E = R.Ex;   // Ex, Ey, Ez are contiguous
+  T* Ee = R.Ex;
   T* __restrict__ J = R.Jx;
   for (int base = wave * cpw; base < R.np; base += nwave * cpw) {
     const int p = base + sub;
@@ -155,16 +187,23 @@ __global__ __launch_bounds__(256) void k_kin3d(const Run3D<T> R) {
     double a1[1] = {acc};
     int which = 0;
     const double tot = group_reduce<1>(a1, lpc, li, which);
-    if (live && li == 0) J[at] = (T)tot;
+    if (live && li == 0) {
+      // Ampere's law takes -J: applied here, so the E launch reads no current array
+      const T jv = (T)tot;
+      J[at] = jv;
+      Ee[at] = E[at] - jv;
+    }
   }
 }
 
+// E^{n+1} = E^n + S curl H (the kinetic launch has already taken J^{n+1/2} off E^n at
+// the plasma points).
 template <class T>
 __global__ __launch_bounds__(256) void k_e3d(const Run3D<T> R, int64_t step) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y, k = blockIdx.z;
   const int nx = R.nx, ny = R.ny, nz = R.nz, m = R.m;
-  if (i > nx) return;
+  const PlaneTile pt = plane_tile(nx, ny, nz);
+  if (!pt.ok) return;
+  const int i = pt.i, j = pt.j, k = pt.k;
   const size_t sHx_j = nx + 1, sHx_k = (size_t)ny * (nx + 1);
   const size_t sHy_j = nx, sHy_k = (size_t)(ny + 1) * nx;
   const size_t sHz_j = nx, sHz_k = (size_t)ny * nx;
@@ -190,7 +229,7 @@ __global__ __launch_bounds__(256) void k_e3d(const Run3D<T> R, int64_t step) {
         acc -= v;
       }
     }
-    T e = fma(S, acc, R.Ex[q]) - R.Jx[q];
+    T e = fma(S, acc, R.Ex[q]);
     if (R.src_kind != 0 && k == R.src_k && (R.src_kind == 1 || (i == R.src_i && j == R.src_j)))
       e += (T)source_wave((double)(step + 1) * R.dt, R.src_amp, R.src_w, R.src_tau, R.src_t0);
     R.Ex[q] = e;
@@ -216,7 +255,7 @@ __global__ __launch_bounds__(256) void k_e3d(const Run3D<T> R, int64_t step) {
         acc -= v;
       }
     }
-    R.Ey[q] = fma(S, acc, R.Ey[q]) - R.Jy[q];
+    R.Ey[q] = fma(S, acc, R.Ey[q]);
   }
   // Ez at (i, j, k+1/2), tangential to the x and y faces
   if (i >= 1 && i < nx && j >= 1 && j < ny && k < nz) {
@@ -239,7 +278,7 @@ __global__ __launch_bounds__(256) void k_e3d(const Run3D<T> R, int64_t step) {
         acc -= v;
       }
     }
-    R.Ez[q] = fma(S, acc, R.Ez[q]) - R.Jz[q];
+    R.Ez[q] = fma(S, acc, R.Ez[q]);
   }
 }
 
@@ -247,7 +286,9 @@ template <class T>
 hipError_t launch_step3d_t(const void* run, int nx, int ny, int nz, int np, int kin_groups,
                            int64_t step, hipStream_t stream) {
   const Run3D<T>& R = *static_cast<const Run3D<T>*>(run);
-  const dim3 grid((nx + 1 + 255) / 256, ny + 1, nz + 1);
+  const int tiles = ((nx + 1) * (ny + 1) + 255) / 256;
+  const int blocks = (tiles * (nz + 1) + kXcds - 1) / kXcds * kXcds;
+  const dim3 grid(blocks);
   hipLaunchKernelGGL(k_h3d<T>, grid, dim3(256), 0, stream, R);
   if (np > 0) hipLaunchKernelGGL(k_kin3d<T>, dim3(kin_groups), dim3(256), 0, stream, R);
   hipLaunchKernelGGL(k_e3d<T>, grid, dim3(256), 0, stream, R, step);
