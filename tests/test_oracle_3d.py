@@ -289,3 +289,39 @@ def test_cpml_absorbs():
     peak = np.abs(ref).max()
     assert np.max(np.abs(series(box(40, 8)) - ref)) < 1e-3 * peak
     assert np.max(np.abs(series(box(40, 0)) - ref)) > 0.1 * peak
+
+
+def test_second_order_convergence_3d():
+    """Order of accuracy 2 (the vacuum validation of section 4, in 3D): the Ez cavity mode
+    sin(k_x x) sin(k_y y) cos(w t) with the continuous w, started from the exact fields,
+    is off the continuous solution after a fixed time by an error that falls 4x when dx
+    and dt halve."""
+    errs = []
+    L, S = 0.016, 0.5
+    for n in (8, 16, 32):
+        dx = L / n
+        ne = np.zeros((n, n, n))
+        o = Oracle3D(n, n, n, dx, S, ne, ne, vdim=4, ncpml=0)
+        F = o.fields()
+        kx = ky = math.pi / L
+        w = K["c"] * math.sqrt(kx ** 2 + ky ** 2)
+        zz, yy, xx = np.meshgrid(np.arange(n) + 0.5, np.arange(n + 1), np.arange(n + 1),
+                                 indexing="ij")
+        F["Ez"][...] = np.sin(kx * xx * dx) * np.sin(ky * yy * dx)
+        # H at t = -dt/2 from the continuous Faraday law
+        t0 = -0.5 * o.dt
+        zz, yy, xx = np.meshgrid(np.arange(n) + 0.5, np.arange(n) + 0.5, np.arange(n + 1),
+                                 indexing="ij")
+        F["Hx"][...] = -(ky / (A.MU0 * w)) * np.sin(kx * xx * dx) * np.cos(ky * yy * dx) * math.sin(w * t0)
+        zz, yy, xx = np.meshgrid(np.arange(n) + 0.5, np.arange(n + 1), np.arange(n) + 0.5,
+                                 indexing="ij")
+        F["Hy"][...] = (kx / (A.MU0 * w)) * np.cos(kx * xx * dx) * np.sin(ky * yy * dx) * math.sin(w * t0)
+        steps = 8 * n            # the same physical time at every resolution
+        o.run(steps)
+        zz, yy, xx = np.meshgrid(np.arange(n) + 0.5, np.arange(n + 1), np.arange(n + 1),
+                                 indexing="ij")
+        exact = np.sin(kx * xx * dx) * np.sin(ky * yy * dx) * math.cos(w * steps * o.dt)
+        errs.append(np.max(np.abs(o.fields()["Ez"] - exact)))
+    assert errs[0] < 0.1
+    for e0, e1 in zip(errs, errs[1:]):
+        assert 3.5 < e0 / e1 < 4.5, errs
