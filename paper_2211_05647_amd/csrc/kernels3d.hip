@@ -58,6 +58,8 @@ __device__ __forceinline__ PlaneTile plane_tile(int nx, int ny, int nz) {
   return p;
 }
 
+// Every operand of the point's three components is loaded before any arithmetic (the
+// stores of one component would otherwise order the loads of the next behind them).
 template <class T>
 __global__ __launch_bounds__(256) void k_h3d(const Run3D<T> R) {
   const int nx = R.nx, ny = R.ny, nz = R.nz, m = R.m;
@@ -67,75 +69,61 @@ __global__ __launch_bounds__(256) void k_h3d(const Run3D<T> R) {
   const size_t sEx_j = nx, sEx_k = (size_t)(ny + 1) * nx;
   const size_t sEy_j = nx + 1, sEy_k = (size_t)ny * (nx + 1);
   const size_t sEz_j = nx + 1, sEz_k = (size_t)(ny + 1) * (nx + 1);
+  const T* __restrict__ Ex = R.Ex;
+  const T* __restrict__ Ey = R.Ey;
+  const T* __restrict__ Ez = R.Ez;
+  // Hx at (i, j+1/2, k+1/2), Hy at (i+1/2, j, k+1/2), Hz at (i+1/2, j+1/2, k)
+  const bool vx = j < ny && k < nz, vy = i < nx && k < nz, vz = i < nx && j < ny;
+  const size_t qx = ((size_t)k * ny + j) * (nx + 1) + i;
+  const size_t qy = ((size_t)k * (ny + 1) + j) * nx + i;
+  const size_t qz = ((size_t)k * ny + j) * nx + i;
+  const size_t ey = k * sEy_k + j * sEy_j + i, ez = k * sEz_k + j * sEz_j + i,
+               ex = k * sEx_k + j * sEx_j + i;
+  const T ey0 = (vx || vz) ? Ey[ey] : T(0);
+  const T eyk = vx ? Ey[ey + sEy_k] : T(0);
+  const T eyi = vz ? Ey[ey + 1] : T(0);
+  const T ez0 = (vx || vy) ? Ez[ez] : T(0);
+  const T ezj = vx ? Ez[ez + sEz_j] : T(0);
+  const T ezi = vy ? Ez[ez + 1] : T(0);
+  const T ex0 = (vy || vz) ? Ex[ex] : T(0);
+  const T exk = vy ? Ex[ex + sEx_k] : T(0);
+  const T exj = vz ? Ex[ex + sEx_j] : T(0);
+  const T hx = vx ? R.Hx[qx] : T(0);
+  const T hy = vy ? R.Hy[qy] : T(0);
+  const T hz = vz ? R.Hz[qz] : T(0);
+  const int sx = (m > 0 && i < nx) ? layer_h(i, nx, m) : -1;
+  const int sy = (m > 0 && j < ny) ? layer_h(j, ny, m) : -1;
+  const int sz = (m > 0 && k < nz) ? layer_h(k, nz, m) : -1;
+  T* const p_hxz = (vx && sz >= 0) ? R.p_hxz + ((size_t)sz * ny + j) * (nx + 1) + i : nullptr;
+  T* const p_hxy = (vx && sy >= 0) ? R.p_hxy + ((size_t)k * 2 * m + sy) * (nx + 1) + i : nullptr;
+  T* const p_hyx = (vy && sx >= 0) ? R.p_hyx + ((size_t)k * (ny + 1) + j) * 2 * m + sx : nullptr;
+  T* const p_hyz = (vy && sz >= 0) ? R.p_hyz + ((size_t)sz * (ny + 1) + j) * nx + i : nullptr;
+  T* const p_hzy = (vz && sy >= 0) ? R.p_hzy + ((size_t)k * 2 * m + sy) * nx + i : nullptr;
+  T* const p_hzx = (vz && sx >= 0) ? R.p_hzx + ((size_t)k * ny + j) * 2 * m + sx : nullptr;
+  const T phxz = p_hxz ? *p_hxz : T(0), phxy = p_hxy ? *p_hxy : T(0);
+  const T phyx = p_hyx ? *p_hyx : T(0), phyz = p_hyz ? *p_hyz : T(0);
+  const T phzy = p_hzy ? *p_hzy : T(0), phzx = p_hzx ? *p_hzx : T(0);
   const T S = R.S;
-  // Hx at (i, j+1/2, k+1/2)
-  if (j < ny && k < nz) {
-    const size_t q = ((size_t)k * ny + j) * (nx + 1) + i;
-    const T dEy_z = R.Ey[(k + 1) * sEy_k + j * sEy_j + i] - R.Ey[k * sEy_k + j * sEy_j + i];
-    const T dEz_y = R.Ez[k * sEz_k + (j + 1) * sEz_j + i] - R.Ez[k * sEz_k + j * sEz_j + i];
+  if (vx) {
+    const T dEy_z = eyk - ey0, dEz_y = ezj - ez0;
     T acc = dEy_z * R.rkhz[k] - dEz_y * R.rkhy[j];
-    if (m > 0) {
-      const int sz = layer_h(k, nz, m), sy = layer_h(j, ny, m);
-      if (sz >= 0) {
-        T* p = R.p_hxz + ((size_t)sz * ny + j) * (nx + 1) + i;
-        const T v = fma(R.bhz[k], *p, R.ahz[k] * dEy_z);
-        *p = v;
-        acc += v;
-      }
-      if (sy >= 0) {
-        T* p = R.p_hxy + ((size_t)k * 2 * m + sy) * (nx + 1) + i;
-        const T v = fma(R.bhy[j], *p, R.ahy[j] * dEz_y);
-        *p = v;
-        acc -= v;
-      }
-    }
-    R.Hx[q] = fma(S, acc, R.Hx[q]);
+    if (p_hxz) { const T v = fma(R.bhz[k], phxz, R.ahz[k] * dEy_z); *p_hxz = v; acc += v; }
+    if (p_hxy) { const T v = fma(R.bhy[j], phxy, R.ahy[j] * dEz_y); *p_hxy = v; acc -= v; }
+    R.Hx[qx] = fma(S, acc, hx);
   }
-  // Hy at (i+1/2, j, k+1/2)
-  if (i < nx && k < nz) {
-    const size_t q = ((size_t)k * (ny + 1) + j) * nx + i;
-    const T dEz_x = R.Ez[k * sEz_k + j * sEz_j + i + 1] - R.Ez[k * sEz_k + j * sEz_j + i];
-    const T dEx_z = R.Ex[(k + 1) * sEx_k + j * sEx_j + i] - R.Ex[k * sEx_k + j * sEx_j + i];
+  if (vy) {
+    const T dEz_x = ezi - ez0, dEx_z = exk - ex0;
     T acc = dEz_x * R.rkhx[i] - dEx_z * R.rkhz[k];
-    if (m > 0) {
-      const int sx = layer_h(i, nx, m), sz = layer_h(k, nz, m);
-      if (sx >= 0) {
-        T* p = R.p_hyx + ((size_t)k * (ny + 1) + j) * 2 * m + sx;
-        const T v = fma(R.bhx[i], *p, R.ahx[i] * dEz_x);
-        *p = v;
-        acc += v;
-      }
-      if (sz >= 0) {
-        T* p = R.p_hyz + ((size_t)sz * (ny + 1) + j) * nx + i;
-        const T v = fma(R.bhz[k], *p, R.ahz[k] * dEx_z);
-        *p = v;
-        acc -= v;
-      }
-    }
-    R.Hy[q] = fma(S, acc, R.Hy[q]);
+    if (p_hyx) { const T v = fma(R.bhx[i], phyx, R.ahx[i] * dEz_x); *p_hyx = v; acc += v; }
+    if (p_hyz) { const T v = fma(R.bhz[k], phyz, R.ahz[k] * dEx_z); *p_hyz = v; acc -= v; }
+    R.Hy[qy] = fma(S, acc, hy);
   }
-  // Hz at (i+1/2, j+1/2, k)
-  if (i < nx && j < ny) {
-    const size_t q = ((size_t)k * ny + j) * nx + i;
-    const T dEx_y = R.Ex[k * sEx_k + (j + 1) * sEx_j + i] - R.Ex[k * sEx_k + j * sEx_j + i];
-    const T dEy_x = R.Ey[k * sEy_k + j * sEy_j + i + 1] - R.Ey[k * sEy_k + j * sEy_j + i];
+  if (vz) {
+    const T dEx_y = exj - ex0, dEy_x = eyi - ey0;
     T acc = dEx_y * R.rkhy[j] - dEy_x * R.rkhx[i];
-    if (m > 0) {
-      const int sy = layer_h(j, ny, m), sx = layer_h(i, nx, m);
-      if (sy >= 0) {
-        T* p = R.p_hzy + ((size_t)k * 2 * m + sy) * nx + i;
-        const T v = fma(R.bhy[j], *p, R.ahy[j] * dEx_y);
-        *p = v;
-        acc += v;
-      }
-      if (sx >= 0) {
-        T* p = R.p_hzx + ((size_t)k * ny + j) * 2 * m + sx;
-        const T v = fma(R.bhx[i], *p, R.ahx[i] * dEy_x);
-        *p = v;
-        acc -= v;
-      }
-    }
-    R.Hz[q] = fma(S, acc, R.Hz[q]);
+    if (p_hzy) { const T v = fma(R.bhy[j], phzy, R.ahy[j] * dEx_y); *p_hzy = v; acc += v; }
+    if (p_hzx) { const T v = fma(R.bhx[i], phzx, R.ahx[i] * dEy_x); *p_hzx = v; acc -= v; }
+    R.Hz[qz] = fma(S, acc, hz);
   }
 }
 
@@ -197,7 +185,7 @@ __global__ __launch_bounds__(256) void k_kin3d(const Run3D<T> R) {
 }
 
 // E^{n+1} = E^n + S curl H (the kinetic launch has already taken J^{n+1/2} off E^n at
-// the plasma points).
+// the plasma points); every operand loaded before any arithmetic, as in k_h3d.
 template <class T>
 __global__ __launch_bounds__(256) void k_e3d(const Run3D<T> R, int64_t step) {
   const int nx = R.nx, ny = R.ny, nz = R.nz, m = R.m;
@@ -207,78 +195,68 @@ __global__ __launch_bounds__(256) void k_e3d(const Run3D<T> R, int64_t step) {
   const size_t sHx_j = nx + 1, sHx_k = (size_t)ny * (nx + 1);
   const size_t sHy_j = nx, sHy_k = (size_t)(ny + 1) * nx;
   const size_t sHz_j = nx, sHz_k = (size_t)ny * nx;
+  const T* __restrict__ Hx = R.Hx;
+  const T* __restrict__ Hy = R.Hy;
+  const T* __restrict__ Hz = R.Hz;
+  // Ex at (i+1/2, j, k), Ey at (i, j+1/2, k), Ez at (i, j, k+1/2); tangential E on the
+  // outer faces is never written
+  const bool ik = k >= 1 && k < nz;
+  const bool vx = i < nx && j >= 1 && j < ny && ik;
+  const bool vy = i >= 1 && i < nx && j < ny && ik;
+  const bool vz = i >= 1 && i < nx && j >= 1 && j < ny && k < nz;
+  const size_t qx = ((size_t)k * (ny + 1) + j) * nx + i;
+  const size_t qy = ((size_t)k * ny + j) * (nx + 1) + i;
+  const size_t qz = ((size_t)k * (ny + 1) + j) * (nx + 1) + i;
+  const size_t hxo = k * sHx_k + j * sHx_j + i, hyo = k * sHy_k + j * sHy_j + i,
+               hzo = k * sHz_k + j * sHz_j + i;
+  const T hz0 = (vx || vy) ? Hz[hzo] : T(0);
+  const T hzj = vx ? Hz[hzo - sHz_j] : T(0);
+  const T hzi = vy ? Hz[hzo - 1] : T(0);
+  const T hy0 = (vx || vz) ? Hy[hyo] : T(0);
+  const T hyk = vx ? Hy[hyo - sHy_k] : T(0);
+  const T hyi = vz ? Hy[hyo - 1] : T(0);
+  const T hx0 = (vy || vz) ? Hx[hxo] : T(0);
+  const T hxk = vy ? Hx[hxo - sHx_k] : T(0);
+  const T hxj = vz ? Hx[hxo - sHx_j] : T(0);
+  const T ex = vx ? R.Ex[qx] : T(0);
+  const T ey = vy ? R.Ey[qy] : T(0);
+  const T ez = vz ? R.Ez[qz] : T(0);
+  const int sx = m > 0 ? layer_e(i, nx, m) : -1;
+  const int sy = m > 0 ? layer_e(j, ny, m) : -1;
+  const int sz = m > 0 ? layer_e(k, nz, m) : -1;
+  T* const p_exy = (vx && sy >= 0) ? R.p_exy + ((size_t)k * 2 * m + sy) * nx + i : nullptr;
+  T* const p_exz = (vx && sz >= 0) ? R.p_exz + ((size_t)sz * (ny + 1) + j) * nx + i : nullptr;
+  T* const p_eyz = (vy && sz >= 0) ? R.p_eyz + ((size_t)sz * ny + j) * (nx + 1) + i : nullptr;
+  T* const p_eyx = (vy && sx >= 0) ? R.p_eyx + ((size_t)k * ny + j) * 2 * m + sx : nullptr;
+  T* const p_ezx = (vz && sx >= 0) ? R.p_ezx + ((size_t)k * (ny + 1) + j) * 2 * m + sx : nullptr;
+  T* const p_ezy = (vz && sy >= 0) ? R.p_ezy + ((size_t)k * 2 * m + sy) * (nx + 1) + i : nullptr;
+  const T pexy = p_exy ? *p_exy : T(0), pexz = p_exz ? *p_exz : T(0);
+  const T peyz = p_eyz ? *p_eyz : T(0), peyx = p_eyx ? *p_eyx : T(0);
+  const T pezx = p_ezx ? *p_ezx : T(0), pezy = p_ezy ? *p_ezy : T(0);
   const T S = R.S;
-  // Ex at (i+1/2, j, k), tangential to the y and z faces
-  if (i < nx && j >= 1 && j < ny && k >= 1 && k < nz) {
-    const size_t q = ((size_t)k * (ny + 1) + j) * nx + i;
-    const T dHz_y = R.Hz[k * sHz_k + j * sHz_j + i] - R.Hz[k * sHz_k + (j - 1) * sHz_j + i];
-    const T dHy_z = R.Hy[k * sHy_k + j * sHy_j + i] - R.Hy[(k - 1) * sHy_k + j * sHy_j + i];
+  if (vx) {
+    const T dHz_y = hz0 - hzj, dHy_z = hy0 - hyk;
     T acc = dHz_y * R.rkey[j] - dHy_z * R.rkez[k];
-    if (m > 0) {
-      const int sy = layer_e(j, ny, m), sz = layer_e(k, nz, m);
-      if (sy >= 0) {
-        T* p = R.p_exy + ((size_t)k * 2 * m + sy) * nx + i;
-        const T v = fma(R.bey[j], *p, R.aey[j] * dHz_y);
-        *p = v;
-        acc += v;
-      }
-      if (sz >= 0) {
-        T* p = R.p_exz + ((size_t)sz * (ny + 1) + j) * nx + i;
-        const T v = fma(R.bez[k], *p, R.aez[k] * dHy_z);
-        *p = v;
-        acc -= v;
-      }
-    }
-    T e = fma(S, acc, R.Ex[q]);
+    if (p_exy) { const T v = fma(R.bey[j], pexy, R.aey[j] * dHz_y); *p_exy = v; acc += v; }
+    if (p_exz) { const T v = fma(R.bez[k], pexz, R.aez[k] * dHy_z); *p_exz = v; acc -= v; }
+    T e = fma(S, acc, ex);
     if (R.src_kind != 0 && k == R.src_k && (R.src_kind == 1 || (i == R.src_i && j == R.src_j)))
       e += (T)source_wave((double)(step + 1) * R.dt, R.src_amp, R.src_w, R.src_tau, R.src_t0);
-    R.Ex[q] = e;
+    R.Ex[qx] = e;
   }
-  // Ey at (i, j+1/2, k), tangential to the x and z faces
-  if (i >= 1 && i < nx && j < ny && k >= 1 && k < nz) {
-    const size_t q = ((size_t)k * ny + j) * (nx + 1) + i;
-    const T dHx_z = R.Hx[k * sHx_k + j * sHx_j + i] - R.Hx[(k - 1) * sHx_k + j * sHx_j + i];
-    const T dHz_x = R.Hz[k * sHz_k + j * sHz_j + i] - R.Hz[k * sHz_k + j * sHz_j + i - 1];
+  if (vy) {
+    const T dHx_z = hx0 - hxk, dHz_x = hz0 - hzi;
     T acc = dHx_z * R.rkez[k] - dHz_x * R.rkex[i];
-    if (m > 0) {
-      const int sz = layer_e(k, nz, m), sx = layer_e(i, nx, m);
-      if (sz >= 0) {
-        T* p = R.p_eyz + ((size_t)sz * ny + j) * (nx + 1) + i;
-        const T v = fma(R.bez[k], *p, R.aez[k] * dHx_z);
-        *p = v;
-        acc += v;
-      }
-      if (sx >= 0) {
-        T* p = R.p_eyx + ((size_t)k * ny + j) * 2 * m + sx;
-        const T v = fma(R.bex[i], *p, R.aex[i] * dHz_x);
-        *p = v;
-        acc -= v;
-      }
-    }
-    R.Ey[q] = fma(S, acc, R.Ey[q]);
+    if (p_eyz) { const T v = fma(R.bez[k], peyz, R.aez[k] * dHx_z); *p_eyz = v; acc += v; }
+    if (p_eyx) { const T v = fma(R.bex[i], peyx, R.aex[i] * dHz_x); *p_eyx = v; acc -= v; }
+    R.Ey[qy] = fma(S, acc, ey);
   }
-  // Ez at (i, j, k+1/2), tangential to the x and y faces
-  if (i >= 1 && i < nx && j >= 1 && j < ny && k < nz) {
-    const size_t q = ((size_t)k * (ny + 1) + j) * (nx + 1) + i;
-    const T dHy_x = R.Hy[k * sHy_k + j * sHy_j + i] - R.Hy[k * sHy_k + j * sHy_j + i - 1];
-    const T dHx_y = R.Hx[k * sHx_k + j * sHx_j + i] - R.Hx[k * sHx_k + (j - 1) * sHx_j + i];
+  if (vz) {
+    const T dHy_x = hy0 - hyi, dHx_y = hx0 - hxj;
     T acc = dHy_x * R.rkex[i] - dHx_y * R.rkey[j];
-    if (m > 0) {
-      const int sx = layer_e(i, nx, m), sy = layer_e(j, ny, m);
-      if (sx >= 0) {
-        T* p = R.p_ezx + ((size_t)k * (ny + 1) + j) * 2 * m + sx;
-        const T v = fma(R.bex[i], *p, R.aex[i] * dHy_x);
-        *p = v;
-        acc += v;
-      }
-      if (sy >= 0) {
-        T* p = R.p_ezy + ((size_t)k * 2 * m + sy) * (nx + 1) + i;
-        const T v = fma(R.bey[j], *p, R.aey[j] * dHx_y);
-        *p = v;
-        acc -= v;
-      }
-    }
-    R.Ez[q] = fma(S, acc, R.Ez[q]);
+    if (p_ezx) { const T v = fma(R.bex[i], pezx, R.aex[i] * dHy_x); *p_ezx = v; acc += v; }
+    if (p_ezy) { const T v = fma(R.bey[j], pezy, R.aey[j] * dHx_y); *p_ezy = v; acc -= v; }
+    R.Ez[qz] = fma(S, acc, ez);
   }
 }
 
