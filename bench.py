@@ -152,12 +152,12 @@ def bytes_1d_full(run):
     return ncell * nv * 4 * 2 + ncell * 12 + (nx + 1) * 4 * 5
 
 
-def extra_full(B, W, torch):
+def extra_full(B, W, torch, steps=None):
     """The full-distribution model (F0 evolves, electrons heat) on the C1 line and on the
-    Nx = 2^20 line, FP32, one step per launch."""
+    Nx = 2^20 line, FP32, one step per launch (2000 and 300 steps, or ``steps``)."""
     out = {}
-    for key, run, steps in (("full_c1", W.c1(steps=2000), 2000),
-                            ("full_c1_nx2e20", W.c1_large(), 300)):
+    for key, run, steps in (("full_c1", W.c1(steps=2000), steps or 2000),
+                            ("full_c1_nx2e20", W.c1_large(), steps or 300)):
         run.kinetic = "full"
         log(f"{key}: Nx={run.nx} Nv={run.nv} plasma cells={run.plasma_cells}")
         wall, ms = time_single(run, B, torch, steps, 50)
@@ -169,6 +169,23 @@ def extra_full(B, W, torch):
                         ms_per_step=wall / steps * 1e3, kernel_ms_per_step=ms,
                         hbm_gbs=by / (ms * 1e-3) / 1e9,
                         hbm_frac=by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+    # the FP64 oracle's full-distribution model on the host, same Nx = 65536 line
+    sys.path.insert(0, ROOT)
+    from oracle.core import Oracle1D, threads
+    run = W.c1(steps=1)
+    o = Oracle1D(run.nx, run.dx, run.courant, run.ne, run.nubar, nv=run.nv, te_ev=run.te_ev,
+                 src_node=run.src_node, src_amp=run.src_amp, src_f=run.src_f,
+                 src_tau=run.src_tau, src_t0=run.src_t0, kinetic="full")
+    t0 = time.perf_counter()
+    o.run(20)
+    per = (time.perf_counter() - t0) / 20
+    k = max(20, int(5.0 / per))
+    t0 = time.perf_counter()
+    o.run(k)
+    dt = time.perf_counter() - t0
+    out["full_c1"]["cpu_oracle"] = dict(kind="oracle", cores=threads(),
+                                        updates_per_s=run.plasma_cells * run.nv * k / dt,
+                                        sample=f"Nx=65536 line, {k} steps after 20, FP64 full grid")
     return out
 
 
@@ -203,7 +220,21 @@ def extra_3d(B, W, torch, steps=300):
     row = 32
     by = bytes_3d(run, npoints, row)
     cells = run.nx * run.ny * run.nz
-    return {"argon3d": dict(workload=f"3D Yee + CPML + speed-grid F1 (v_dim {run.nv}, Druyvesteyn), "
+    # the FP64 oracle on the host, same workload, a few steps
+    sys.path.insert(0, ROOT)
+    from oracle.core import Oracle3D, threads
+    o = Oracle3D(run.nx, run.ny, run.nz, run.dx, run.courant, run.ne, run.nubar, vdim=run.nv,
+                 vmax_over_vth=run.vmax_over_vth, te_ev=run.te_ev, nu_model=run.nu_model,
+                 f0_model=run.f0_model, ncpml=run.ncpml, src_kind=run.src_kind,
+                 src_k=run.src_k, src_amp=run.src_amp, src_f=run.src_f, src_tau=run.src_tau,
+                 src_t0=run.src_t0)
+    o.run(1)
+    t0 = time.perf_counter()
+    o.run(4)
+    cdt = (time.perf_counter() - t0) / 4
+    cpu = dict(kind="oracle", cores=threads(), nmcps=cells / cdt * 1e-6,
+               updates_per_s=npoints * run.nv / cdt, sample="4 steps after 1, FP64")
+    return {"argon3d": dict(cpu_oracle=cpu, workload=f"3D Yee + CPML + speed-grid F1 (v_dim {run.nv}, Druyvesteyn), "
                                      f"{run.nx}x{run.ny}x{run.nz}, FP32, {steps} steps",
                             plasma_points=npoints, cells=cells,
                             updates_per_s=npoints * run.nv * steps / wall,
@@ -465,7 +496,7 @@ def main():
                 "closure": lambda: closure_speedup(B, W, torch),
                 "c4": lambda: c4_steps(B, W, torch, args.steps),
                 "sweep": lambda: nmcps_sweep(B, W, torch),
-                "full": lambda: extra_full(B, W, torch),
+                "full": lambda: extra_full(B, W, torch, min(args.steps, 2000)),
                 "3d": lambda: extra_3d(B, W, torch, args.steps),
                 "sweep3d": lambda: sweep_3d(B, W, torch)}[args.only]
         print(json.dumps(only()), flush=True)
