@@ -32,7 +32,11 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # Arithmetic of one stored-bin update of F1 and its moment: FP32 dt*nu (mul), 2 + x (add),
 # reciprocal, 2x (add), drive (mul), two FMAs (4 flops); FP64 moment FMA (2 flops).
-FLOPS_PER_BIN = 11
+# arithmetic of one stored-bin update in the blocked kernel: per step 2 dt nu (1), the drive
+# b n E (1), two FP32 FMAs (4) and the FP64 moment FMA (2); once per launch the
+# Crank-Nicolson factor 1/(2 + dt nu) (an FMA and a reciprocal, 3)
+FLOPS_PER_BIN_STEP = 8
+FLOPS_PER_BIN_LAUNCH = 3
 
 
 def kernel_hash():
@@ -519,7 +523,7 @@ def main():
         kernel = f"k_step1d_tb<{kb}, {half // 4}>"
         bytes_alg = bytes_1d_blocked(run, info["rows_per_launch"])
         launch_ms = ms_dev * kb
-        flops = FLOPS_PER_BIN * ncell * half * kb
+        flops = (FLOPS_PER_BIN_STEP * kb + FLOPS_PER_BIN_LAUNCH) * ncell * half
         roof = {"bound": "alu", "kernel": kernel,
                 "achieved": flops / (launch_ms * 1e-3) / 1e12, "peak": VALU_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": flops / (launch_ms * 1e-3) / 1e12 / VALU_PEAK_TFLOPS,

@@ -28,8 +28,11 @@ namespace fdtdp {
 constexpr int kTbBlock = 512;               // threads per work-group (8 wavefronts)
 constexpr int kTbWaves = kTbBlock / 64;
 constexpr int kTbU = 4;                     // rows per lane group per row slot group
-constexpr int kTbIters = 3;                 // row slot groups per lane group (126 VGPRs:
-                                            // two work-groups per compute unit)
+constexpr int kTbIters = 2;                 // row slot groups per lane group: 8 row
+                                            // slots with their Crank-Nicolson factors
+                                            // (108 VGPRs: two work-groups per compute
+                                            // unit; 12 slots that recompute the factor
+                                            // every step measured 10% slower)
 constexpr int kTbRowsPerGroup = kTbIters * kTbU;
 
 template <int K, int LPC>
@@ -114,6 +117,21 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
       f[it][u] = cl < ncell ? dfr[(size_t)(tile.cell0 + cl) * lpc + li]
                             : make_float4(0.f, 0.f, 0.f, 0.f);
     }
+  // Crank-Nicolson factors 1/(2 + dt nu_j) of every row slot, the same for all K steps
+  float4 rr[kTbIters][kTbU];
+#pragma unroll
+  for (int it = 0; it < kTbIters; ++it)
+#pragma unroll
+    for (int u = 0; u < kTbU; ++u) {
+      const int cl = row_slot(it * kTbU + u, wv, sub);
+      float tau = 0.f;
+      if constexpr (LPC == 64)
+        tau = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tab_tau), it * kTbU + u));
+      else
+        tau = cl < ncell ? R.tau[tile.cell0 + cl] : 0.f;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) lane_at(rr[it][u], v) = cn_recip(fmaf(tau, lane_at(sb, v), 2.f));
+    }
 
   int lo = x0, hi = x1;    // nodes whose E is valid at the start of the sub-step
   const float S = R.S;
@@ -158,7 +176,7 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             // x = dt nu_j; (2 x) = (2 dt nu_mean) s_j exactly
-            const float r = cn_recip(fmaf(tau, lane_at(sb, v), 2.f));
+            const float r = lane_at(rr[it][u], v);
             const float x2 = tau2 * lane_at(sb, v);
             const float fv = lane_at(f[it][u], v);
             const float t = fmaf(-x2, fv, lane_at(bb, v) * nE);
