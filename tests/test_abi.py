@@ -114,3 +114,33 @@ def test_seeded_workloads_are_reproducible():
     runs = W.c3()
     assert len(runs) == 256 and {x.nv for x in runs} == {64, 128, 256}
     assert all(500 <= x.nx <= 20000 and x.steps == 2 * x.nx for x in runs)
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of the ABI structs have the size and field offsets the C
+    compiler gives the header's structs (a field added on one side only would shift every
+    later field silently)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"fdtd_grid": B.Grid, "fdtd_profile": B.Profile, "fdtd_source": B.Source,
+               "fdtd_device": B.Device}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fdtd_plasma.h"',
+             'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
