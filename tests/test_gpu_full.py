@@ -95,3 +95,30 @@ def test_full_model_configurations_rejected(gpu_lib):
     r2.kinetic = "full"
     with pytest.raises(B.FdtdError):
         B.Sim(r2, precision=B.FP32)
+
+
+def test_full_model_at_benchmark_size_prefix_parity(gpu_lib):
+    """The full-distribution model at the benchmark's size (Nx = 65536, Nv = 512, FP32, one
+    step per launch as timed): after 1500 steps the field has travelled at most 1500 nodes,
+    so the oracle on the prefix [0, src + 1510] is exact there; beyond it everything stays
+    at its initial value (zero field, f = n fhat)."""
+    run = W.c1()
+    run.kinetic = "full"
+    steps = 1500
+    cut = run.src_node + steps + 10
+    _banner("full model, Nx=65536 prefix")
+    sim = B.Sim(run, precision=B.FP32)
+    assert sim.time_block() == 1
+    orc = oracle_1d(run, nx=cut)
+    snaps = []
+    g, o, _, _ = space_time_1d(sim, orc, steps, 250, [], df_snaps=snaps)
+    err = rel_l2(g, o)
+    _banner(f"  E space-time rel L2 = {err:.3e}")
+    assert err <= 1e-5
+    err_df = rel_l2(np.concatenate([a for a, _ in snaps]), np.concatenate([b for _, b in snaps]))
+    _banner(f"  f - n fhat space-time rel L2 = {err_df:.3e}")
+    assert err_df <= 1e-5
+    assert np.all(sim.read(B.F_E)[cut + 1:] == 0.0)
+    df = sim.read(B.F_DF).reshape(run.plasma_cells, run.nv)
+    assert np.all(df[len(orc.cells):] == 0.0)
+    sim.close()
