@@ -107,3 +107,34 @@ def test_3d_rejections(gpu_lib):
     bad.courant = 0.6
     with pytest.raises(B.FdtdError):
         B.Sim(bad, precision=B.FP32)
+
+
+def test_benchmark_size_light_cone_parity(gpu_lib):
+    """The benchmark's 3D workload at its full size (128 x 128 x 512, FP32, the launch shape
+    timed): in 150 steps the sheet source's field reaches at most 151 planes past it, so the
+    oracle on the same transverse box cut at 180 planes (its own high-z layer unreached) is
+    exact there, and every plane beyond stays zero."""
+    run = W.argon_slab_3d(nx=128, ny=128, nz=512, steps=150)
+    steps, cutz = 150, 180
+    _banner("argon slab, full size, light cone")
+    sim = B.Sim(run, precision=B.FP32)
+    sim.run(steps)
+    small = W.argon_slab_3d(nx=128, ny=128, nz=cutz, steps=steps)
+    small.ne[:] = 0.0
+    small.src_k = run.src_k
+    orc = oracle_3d(small)
+    orc.run(steps)
+    F = orc.fields()
+    ex = sim.read(B.F_EX).reshape(run.nz + 1, run.ny + 1, run.nx)
+    ey = sim.read(B.F_EY).reshape(run.nz + 1, run.ny, run.nx + 1)
+    ez = sim.read(B.F_EZ).reshape(run.nz, run.ny + 1, run.nx + 1)
+    lim = run.src_k + steps + 2
+    assert lim < cutz - run.ncpml
+    g = np.concatenate([ex[:lim].ravel(), ey[:lim].ravel(), ez[:lim].ravel()])
+    o = np.concatenate([F["Ex"][:lim].ravel(), F["Ey"][:lim].ravel(), F["Ez"][:lim].ravel()])
+    err = rel_l2(g, o)
+    _banner(f"  E rel L2 on the light cone = {err:.3e}")
+    assert err <= 1e-5
+    assert np.abs(o).max() > 0
+    assert np.all(ex[lim:] == 0.0) and np.all(ey[lim:] == 0.0) and np.all(ez[lim:] == 0.0)
+    sim.close()
