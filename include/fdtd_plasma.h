@@ -56,7 +56,8 @@ enum fdtd_boundary { FDTD_BC_PEC = 0, FDTD_BC_MUR1 = 1, FDTD_BC_CPML = 2 };
 enum fdtd_nu_model { FDTD_NU_HARD_SPHERE = 0, FDTD_NU_CONST = 1 };
 enum fdtd_closure_kind { FDTD_CLOSURE_KINETIC = 0, FDTD_CLOSURE_MLP = 1 };
 enum fdtd_source_kind { FDTD_SRC_NONE = 0, FDTD_SRC_LINE_SOFT = 1, FDTD_SRC_POINT_SOFT = 2 };
-enum fdtd_kinetic_model { FDTD_KINETIC_LINEAR = 0, FDTD_KINETIC_FULL = 1 };
+enum fdtd_kinetic_model { FDTD_KINETIC_LINEAR = 0, FDTD_KINETIC_FULL = 1,
+                          FDTD_KINETIC_TWO_TERM = 2 };
 enum fdtd_f0_model { FDTD_F0_MAXWELL = 0, FDTD_F0_DRUYVESTEYN = 1 };
 
 /* Field selectors for read_fields / add_probe.
@@ -117,11 +118,20 @@ typedef struct {
  * through +-vmax (electron number is kept exactly) and is explicit: each step needs
  * |(e/m) E dt / dv| <= 1, and a step that breaks it sets the run status (see
  * fdtd_plasma_run_status).  FULL runs are never temporally blocked.
+ * TWO_TERM (1D single runs only): the paper's own representation, section 5.1's
+ * expansion F = F0 + (v/|v|).F1 with its l = 0 and l = 1 equations on a speed grid of nv
+ * speeds (2..256; the paper uses 31) v_k = (k + 1/2) vmax / nv, F0 (f0_model) evolving
+ * under the l = 0 equation without streaming (elastic collisions only: their l = 0 term,
+ * of order the electron-to-neutral mass ratio, is dropped), F1 = the z component driven
+ * by dF0/dv of the current F0, J = -e (4 pi / 3) gam sum w_k F1_k with w_k the mean of
+ * v^3 over the bin's flux-carrying faces, which makes the field energy J removes exactly
+ * the electrons' kinetic energy gain.  FDTD_F_DF then gives [ncell][2 nv]: F1, then
+ * F0 - ne F0hat.  Never temporally blocked.
  * 3D grids (the paper's production model, section 5.3): ne / nu_mean are per cell
  * [nz][ny][nx]; F1 is a vector on a speed grid of nv speeds (1..64; the paper uses 31)
  * v_k = (k + 1/2) vmax / nv, one component at every E point whose edge touches plasma (the
  * point takes the mean ne and nu_mean of the four cells around its edge), updated as
- * in 2D with J = -e (4 pi / 3) (vmax / nv) sum v^3 F1.  f0_model (3D only): MAXWELL, or
+ * in 2D with J = -e (4 pi / 3) (vmax / nv) sum v^3 F1.  f0_model (3D and the 1D TWO_TERM model): MAXWELL, or
  * DRUYVESTEYN, exp(-(v / vD)^4) with the Maxwellian's mean energy (3/2) e te_ev; either
  * normalised by 4 pi (vmax / nv) sum v^2 F0 = 1.  3D runs take the kinetic closure and
  * the linear model. */

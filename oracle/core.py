@@ -70,6 +70,14 @@ def lib():
              C.c_longlong, C.c_longlong,
              _dp, _dp, _dp, _dp, _dp,
              C.c_int, _ip, _dp])
+        L.oracle_run1d_twoterm.argtypes = (
+            [C.c_int, C.c_double, C.c_double, C.c_int,
+             C.c_int, C.c_double, C.c_double, C.c_int, C.c_int,
+             _dp, _dp,
+             C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
+             C.c_longlong, C.c_longlong,
+             _dp, _dp, _dp, _dp,
+             C.c_int, _ip, _dp, C.c_int])
         L.oracle_replay2v.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, C.c_double,
                                       C.c_double, C.c_double, C.c_longlong, _dp, _dp, _dp, _dp]
         _lib = L
@@ -205,13 +213,17 @@ class Oracle1D:
 
     ``ne``/``nubar`` are per E node (nx+1 values).  ``bc`` is ``"mur"`` or ``"pec"``.
     ``kinetic`` is ``"linear"`` (F1 against the frozen F0) or ``"full"`` (the whole f
-    evolves; ``df`` then holds f - ne fhat per node).
+    evolves; ``df`` then holds f - ne fhat per node) on the signed grid of ``nv`` bins, or
+    ``"two_term"`` (F1 and an evolving F0 on a speed grid of ``nv`` speeds; ``df`` rows
+    hold [F1 | F0 - ne F0hat]) / ``"two_term_frozen"`` (the same with F0 held), with
+    ``f0_model`` ``"maxwell"`` or ``"druyvesteyn"``.
     """
 
     def __init__(self, nx, dx, courant, ne, nubar, nv=64, vmax_over_vth=6.0, te_ev=2.0,
                  nu_model="hard_sphere", bc="mur", src_node=0, src_amp=0.0, src_f=0.0,
-                 src_tau=1.0, src_t0=0.0, kinetic="linear"):
-        self.model = {"linear": 0, "full": 1}[kinetic]
+                 src_tau=1.0, src_t0=0.0, kinetic="linear", f0_model="maxwell"):
+        self.model = {"linear": 0, "full": 1, "two_term": 2, "two_term_frozen": 3}[kinetic]
+        self.f0_model = {"maxwell": 0, "druyvesteyn": 1}[f0_model]
         self.nx, self.dx, self.courant = int(nx), float(dx), float(courant)
         self.ne = np.ascontiguousarray(ne, dtype=np.float64)
         self.nubar = np.ascontiguousarray(nubar, dtype=np.float64)
@@ -224,12 +236,27 @@ class Oracle1D:
         self.E = np.zeros(nx + 1)
         self.H = np.zeros(nx)
         self.J = np.zeros(nx + 1)
-        self.df = np.zeros(len(self.cells) * self.nv)
+        self.row = self.nv * (2 if self.model >= 2 else 1)
+        self.df = np.zeros(len(self.cells) * self.row)
         self.step = 0
         self.dt = self.courant * self.dx / constants()["c"]
 
     def run(self, nsteps, probes=(), snap_every=0):
         probes = np.ascontiguousarray(probes, dtype=np.int32)
+        if self.model >= 2:
+            pout = np.zeros(max(1, nsteps * len(probes)))
+            rc = lib().oracle_run1d_twoterm(
+                self.nx, self.dx, self.courant, self.bc,
+                self.nv, self.vmax, self.te, self.nu_model, self.f0_model,
+                _p(self.ne), _p(self.nubar), *self.src,
+                self.step, int(nsteps),
+                _p(self.E), _p(self.H), _p(self.J), _p(self.df),
+                len(probes), _p(probes) if len(probes) else None, _p(pout),
+                int(self.model == 2))
+            if rc:
+                raise ValueError("oracle_run1d_twoterm rejected its arguments")
+            self.step += int(nsteps)
+            return pout[: nsteps * len(probes)].reshape(nsteps, len(probes)), np.zeros((0, self.nx + 1))
         pout = np.zeros(max(1, nsteps * len(probes)))
         nsnap = nsteps // snap_every if snap_every > 0 else 0
         sout = np.zeros(max(1, nsnap * (self.nx + 1)))
@@ -251,7 +278,7 @@ class Oracle1D:
                 sout[: nsnap * (self.nx + 1)].reshape(nsnap, self.nx + 1))
 
     def df_rows(self):
-        return self.df.reshape(len(self.cells), self.nv)
+        return self.df.reshape(len(self.cells), self.row)
 
 
 class Oracle2D:

@@ -993,3 +993,112 @@ int oracle_run3d(int nx, int ny, int nz, double dx, double courant,
     free(pidx); free(pn); free(pnu);
     return 0;
 }
+
+/* ===========================================================================
+ * 1D two-term model on the speed grid: the paper's own representation
+ * (section 5.1 expansion F = F0 + (v/|v|).F1, the l = 0 and l = 1 equations,
+ * section 5.3 speed grid) in the geometry of its argon experiment, a field
+ * E = Ez along the line.  Per plasma node: F1 (the z component) and F0 on the
+ * speed grid v_k = (k + 1/2) gam of oracle_sgrid, row = [F1 | F0 - n F0hat].
+ * Per step (after H^{n+1/2}):
+ *   F1^{n+1/2} = ((2 - dt nu_k) F1 + 2 dt (e/m) E^n D_k) / (2 + dt nu_k),
+ *     D_k = n dF0hat/dv (analytic) + centred difference of (F0 - n F0hat),
+ *     even across v = 0, zero beyond vmax;
+ *   J^{n+1/2} = -e (4 pi / 3) gam sum_k w_k F1_k,
+ *     w_k = (v_{k-1/2}^3 + v_{k+1/2}^3) / 2 over the faces of bin k that carry
+ *     flux (v_{-1/2} = 0; the face at vmax carries none);
+ *   E^{n+1} (Ampere with -J), boundaries, source;
+ *   F0^{n+1} = F0^n + dt (e / 3m) Ebar (phi_{k+1/2} - phi_{k-1/2}) / (v_k^2 gam),
+ *     phi = v^2 (F1_k + F1_{k+1}) / 2 on the inner faces, 0 at v = 0 and vmax,
+ *     Ebar = (E^n + E^{n+1}) / 2   (l = 0 equation without streaming; only
+ *     elastic collisions, whose l = 0 term carries the electron-to-neutral
+ *     mass ratio and is dropped).
+ * The weights w_k make the F0 update exactly the adjoint of the current: the
+ * field energy that J^{n+1/2} removes, dt Ebar J, is exactly the kinetic energy
+ * (m/2) 4 pi gam sum v_k^4 F0_k gained, and the electron number
+ * 4 pi gam sum v_k^2 F0_k is kept.  evolve_f0 = 0 freezes F0 (the linear
+ * speed-grid model with these weights).
+ * ======================================================================== */
+int oracle_run1d_twoterm(int nx, double dx, double courant, int bc,
+                         int vdim, double vmax_over_vth, double te_ev, int nu_model, int f0_model,
+                         const double *ne, const double *nubar,
+                         int src_node, double src_amp, double src_f, double src_tau, double src_t0,
+                         long long step0, long long nsteps,
+                         double *E, double *H, double *J, double *df,
+                         int nprobe, const int *probe_node, double *probe_E, int evolve_f0)
+{
+    if (nx < 2 || vdim < 2 || dx <= 0.0 || courant <= 0.0 || courant > 1.0) return -1;
+    if (ne[0] > 0.0 || ne[nx] > 0.0) return -1;
+    const double dt = courant * dx / K_C0;
+    double *v = malloc(sizeof(double) * vdim), *F0 = malloc(sizeof(double) * vdim);
+    double *dF0 = malloc(sizeof(double) * vdim), *sh = malloc(sizeof(double) * vdim);
+    double *w = malloc(sizeof(double) * vdim);
+    double gam, vth;
+    if (oracle_sgrid(vdim, vmax_over_vth, te_ev, f0_model, v, F0, dF0, &gam, &vth) != 0) {
+        free(v); free(F0); free(dF0); free(sh); free(w); return -1;
+    }
+    oracle_snu_shape(vdim, v, F0, gam, nu_model, sh);
+    for (int k = 0; k < vdim; ++k) {
+        double lo = (double)k * gam, hi = (double)(k + 1) * gam;      /* faces of bin k */
+        w[k] = 0.5 * (lo * lo * lo + (k + 1 < vdim ? hi * hi * hi : 0.0));
+    }
+    int ncell = 0;
+    for (int i = 0; i <= nx; ++i) if (ne[i] > 0.0) ++ncell;
+    int *cell_node = malloc(sizeof(int) * (ncell > 0 ? ncell : 1));
+    for (int i = 0, c = 0; i <= nx; ++i) if (ne[i] > 0.0) cell_node[c++] = i;
+    double *Eold = malloc(sizeof(double) * (nx + 1));
+
+    const double ch = dt / (k_mu0() * dx), ce = dt / (K_EPS0 * dx), cj = dt / K_EPS0;
+    const double q = (K_C0 * dt - dx) / (K_C0 * dt + dx);
+    const double a0 = K_QE / (3.0 * K_ME);
+    for (long long s = 0; s < nsteps; ++s) {
+        long long n = step0 + s;
+        for (int i = 0; i < nx; ++i) H[i] += ch * (E[i + 1] - E[i]);
+        /* F1 driven by E^n and the current F0, then J */
+        #pragma omp parallel for schedule(static)
+        for (int c = 0; c < ncell; ++c) {
+            int i = cell_node[c];
+            double *f1 = df + (size_t)c * 2 * vdim, *d0 = f1 + vdim;
+            double acc = 0.0;
+            for (int k = 0; k < vdim; ++k) {
+                double below = k > 0 ? d0[k - 1] : d0[0];
+                double above = k + 1 < vdim ? d0[k + 1] : 0.0;
+                double D = ne[i] * dF0[k] + (above - below) / (2.0 * gam);
+                double x = dt * nubar[i] * sh[k];
+                f1[k] = ((2.0 - x) * f1[k] + 2.0 * dt * (K_QE / K_ME) * E[i] * D) / (2.0 + x);
+                acc += w[k] * f1[k];
+            }
+            J[i] = -K_QE * (4.0 * K_PI / 3.0) * gam * acc;
+        }
+        memcpy(Eold, E, sizeof(double) * (nx + 1));
+        double e0 = E[0], e1 = E[1], en1 = E[nx - 1], en = E[nx];
+        for (int i = 1; i < nx; ++i) E[i] += ce * (H[i] - H[i - 1]) - cj * J[i];
+        if (bc == 1) {
+            E[0] = e1 + q * (E[1] - e0);
+            E[nx] = en1 + q * (E[nx - 1] - en);
+        } else {
+            E[0] = 0.0; E[nx] = 0.0;
+        }
+        if (src_amp != 0.0 && src_node > 0 && src_node < nx)
+            E[src_node] += source_wave((double)(n + 1) * dt, src_amp, src_f, src_tau, src_t0);
+        /* F0^{n+1} from the l = 0 equation with Ebar = (E^n + E^{n+1}) / 2 */
+        if (evolve_f0) {
+            #pragma omp parallel for schedule(static)
+            for (int c = 0; c < ncell; ++c) {
+                int i = cell_node[c];
+                double *f1 = df + (size_t)c * 2 * vdim, *d0 = f1 + vdim;
+                double eb = 0.5 * (Eold[i] + E[i]);
+                double phi_lo = 0.0;
+                for (int k = 0; k < vdim; ++k) {
+                    double vf = (double)(k + 1) * gam;
+                    double phi_hi = (k + 1 < vdim) ? vf * vf * 0.5 * (f1[k] + f1[k + 1]) : 0.0;
+                    d0[k] += dt * a0 * eb * (phi_hi - phi_lo) / (v[k] * v[k] * gam);
+                    phi_lo = phi_hi;
+                }
+            }
+        }
+        for (int p = 0; p < nprobe; ++p) probe_E[s * nprobe + p] = E[probe_node[p]];
+    }
+    free(v); free(F0); free(dF0); free(sh); free(w); free(cell_node); free(Eold);
+    return 0;
+}

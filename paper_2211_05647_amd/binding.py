@@ -18,7 +18,7 @@ FP64, FP32 = 0, 1
 BC_PEC, BC_MUR1, BC_CPML = 0, 1, 2
 NU_HARD_SPHERE, NU_CONST = 0, 1
 CLOSURE_KINETIC, CLOSURE_MLP = 0, 1
-KINETIC_LINEAR, KINETIC_FULL = 0, 1
+KINETIC_LINEAR, KINETIC_FULL, KINETIC_TWO_TERM = 0, 1, 2
 F0_MAXWELL, F0_DRUYVESTEYN = 0, 1
 SRC_NONE, SRC_LINE, SRC_POINT = 0, 1, 2
 F_E, F_H, F_J, F_DF, F_EX, F_EY, F_HZ, F_JX, F_JY, F_JCX, F_JCY, F_EZ, F_HX, F_HY, F_JZ = range(15)
@@ -187,7 +187,8 @@ class Sim:
             p = Profile(pne, pnu, w.te_ev, w.nv, w.vmax_over_vth,
                         NU_HARD_SPHERE if w.nu_model == "hard_sphere" else NU_CONST,
                         closure, mlp_ptr,
-                        KINETIC_FULL if getattr(w, "kinetic", "linear") == "full" else KINETIC_LINEAR,
+                        {"linear": KINETIC_LINEAR, "full": KINETIC_FULL,
+                         "two_term": KINETIC_TWO_TERM}[getattr(w, "kinetic", "linear")],
                         F0_DRUYVESTEYN if getattr(w, "f0_model", "maxwell") == "druyvesteyn"
                         else F0_MAXWELL)
             grids.append(g)

@@ -219,7 +219,12 @@ template <class T> struct Run1D {
   // [ncell][2 half], odd then even half of f - n fhat; b_bin then holds the equilibrium
   // flux differences -(dt/dv)(-e/m)(fhat_{k+1} - fhat_{k-1}) per unit density and field)
   int32_t model;
-  T kc;            // -(e/m) dt / dv: the velocity CFL number per unit E
+  T kc;            // full model: -(e/m) dt / dv, the velocity CFL number per unit E;
+                   // two-term model: dt (e/m) / gam
+  // two-term model (model 2): l = 0 update factor dt e / (3 m v_k^2 gam) and the face
+  // weight v_{k+1/2}^2 / 2 of each speed bin (both 0 in the padding, the latter also at vmax)
+  const T* c_bin;
+  const T* v2h_bin;
 };
 
 // One 2D TEz run.  Ex [ny+1][nx] at (i+1/2, j), Ey [ny][nx+1] at (i, j+1/2),

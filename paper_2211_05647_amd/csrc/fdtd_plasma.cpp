@@ -108,15 +108,22 @@ int validate_1d(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s,
     return fail(FDTD_EINVAL, "batched runs are FP32");
   if (g->boundary != FDTD_BC_PEC && g->boundary != FDTD_BC_MUR1)
     return fail(FDTD_EINVAL, "1D boundary must be PEC or MUR1");
-  if (!is_pow2(p->nv) || p->nv < 8 || p->nv > 1024)
+  if (p->kinetic == FDTD_KINETIC_TWO_TERM) {
+    if (p->nv < 2 || p->nv > 256)
+      return fail(FDTD_EINVAL, "two-term speed count nv must lie in [2, 256], got %d", p->nv);
+    if (p->f0_model != FDTD_F0_MAXWELL && p->f0_model != FDTD_F0_DRUYVESTEYN)
+      return fail(FDTD_EINVAL, "unknown f0_model %d", p->f0_model);
+  } else if (!is_pow2(p->nv) || p->nv < 8 || p->nv > 1024) {
     return fail(FDTD_EINVAL, "nv must be a power of two in [8, 1024], got %d", p->nv);
+  }
   if (!(p->te_ev > 0.0) || !(p->vmax_over_vth > 0.0))
     return fail(FDTD_EINVAL, "te_ev and vmax_over_vth must be > 0");
   if (p->nu_model != FDTD_NU_HARD_SPHERE && p->nu_model != FDTD_NU_CONST)
     return fail(FDTD_EINVAL, "unknown nu_model %d", p->nu_model);
   if (p->closure != FDTD_CLOSURE_KINETIC)
     return fail(FDTD_EINVAL, "1D runs take the kinetic closure");
-  if (p->kinetic != FDTD_KINETIC_LINEAR && p->kinetic != FDTD_KINETIC_FULL)
+  if (p->kinetic != FDTD_KINETIC_LINEAR && p->kinetic != FDTD_KINETIC_FULL &&
+      p->kinetic != FDTD_KINETIC_TWO_TERM)
     return fail(FDTD_EINVAL, "unknown kinetic model %d", p->kinetic);
   if (batch && p->kinetic != FDTD_KINETIC_LINEAR)
     return fail(FDTD_EINVAL, "batched runs take the linear kinetic model");
@@ -227,7 +234,13 @@ size_t layout_1d(fdtd_plasma* h, const std::vector<RunSpec1D>& specs, int precis
     x.nv = sp.p.nv;
     x.half = sp.p.nv / 2;
     x.model = sp.p.kinetic;
-    x.row = x.model == FDTD_KINETIC_FULL ? sp.p.nv : x.half;
+    if (x.model == FDTD_KINETIC_TWO_TERM) {
+      // speed bins padded to a power of two of at least one 16-byte vector
+      int hp = 16 / es;
+      while (hp < sp.p.nv) hp *= 2;
+      x.half = hp;
+    }
+    x.row = x.model == FDTD_KINETIC_LINEAR ? x.half : 2 * x.half;
     x.ncell = 0;
     for (int i = 0; i <= x.nx; ++i) if (sp.p.ne[i] > 0) ++x.ncell;
     for (int b = 0; b < 2; ++b) x.off_E[b] = cv.take((size_t)(x.nx + 1) * es);
@@ -248,6 +261,8 @@ size_t layout_1d(fdtd_plasma* h, const std::vector<RunSpec1D>& specs, int precis
     x.off_dens = cv.take((size_t)std::max(x.ncell, 1) * es);
     x.off_s = cv.take((size_t)x.half * es);
     x.off_b = cv.take((size_t)x.half * es);
+    x.off_c = cv.take((size_t)x.half * es);
+    x.off_v2h = cv.take((size_t)x.half * es);
     x.off_w = cv.take(sz<double>(x.half));
   }
   const size_t runs_off = cv.take(specs.size() * (precision == FDTD_FP64 ? sizeof(Run1D<double>)
@@ -284,12 +299,53 @@ int upload_1d(fdtd_plasma* h) {
     Host1D& x = h->h1[r];
     const double dt = sp.g.courant * sp.g.dx / kC0;
     x.dt = dt;
-    VTable vt = build_vtable(1, sp.p.nv, sp.p.vmax_over_vth, sp.p.te_ev, sp.p.nu_model, dt);
-    x.vt = vt;
     const int half = x.half;
-    std::vector<T> s(half), b(half);
-    std::vector<double> w(half);
-    for (int k = 0; k < half; ++k) {
+    std::vector<T> s(half, T(0)), b(half, T(0)), cb(half, T(0)), v2h(half, T(0));
+    std::vector<double> w(half, 0.0);
+    double kc = 0.0;
+    if (x.model == FDTD_KINETIC_TWO_TERM) {
+      // speed grid v_k = (k + 1/2) gam on [0, vmax], F0 normalised by 4 pi gam sum v^2 F0
+      const int vd = sp.p.nv;
+      const double vth = std::sqrt(kQe * sp.p.te_ev / kMe);
+      const double gam = sp.p.vmax_over_vth * vth / vd;
+      double vd4 = 0.0;
+      if (sp.p.f0_model == FDTD_F0_DRUYVESTEYN) {
+        const double vd2 = 3.0 * vth * vth * std::tgamma(0.75) / std::tgamma(1.25);
+        vd4 = vd2 * vd2;
+      }
+      std::vector<double> v(vd), F0(vd);
+      double norm = 0.0, mean = 0.0;
+      for (int k = 0; k < vd; ++k) {
+        v[k] = (k + 0.5) * gam;
+        F0[k] = sp.p.f0_model == FDTD_F0_DRUYVESTEYN ? std::exp(-std::pow(v[k], 4) / vd4)
+                                                     : std::exp(-v[k] * v[k] / (2.0 * vth * vth));
+        norm += 4.0 * M_PI * gam * v[k] * v[k] * F0[k];
+      }
+      for (int k = 0; k < vd; ++k) {
+        F0[k] /= norm;
+        mean += 4.0 * M_PI * gam * v[k] * v[k] * v[k] * F0[k];
+      }
+      for (int k = 0; k < vd; ++k) {
+        const double dF0 = sp.p.f0_model == FDTD_F0_DRUYVESTEYN
+                               ? -4.0 * v[k] * v[k] * v[k] * F0[k] / vd4
+                               : -v[k] * F0[k] / (vth * vth);
+        const double lo = k * gam, hi = (k + 1) * gam;   // faces of the bin
+        const double wk = 0.5 * (lo * lo * lo + (k + 1 < vd ? hi * hi * hi : 0.0));
+        s[k] = (T)(sp.p.nu_model == FDTD_NU_HARD_SPHERE ? v[k] / mean : 1.0);
+        b[k] = (T)(2.0 * dt * (kQe / kMe) * dF0);
+        w[k] = (dt / kEps0) * (-kQe) * (4.0 * M_PI / 3.0) * gam * wk;
+        cb[k] = (T)(dt * kQe / (3.0 * kMe) / (v[k] * v[k] * gam));
+        v2h[k] = (T)(k + 1 < vd ? 0.5 * hi * hi : 0.0);
+      }
+      kc = dt * (kQe / kMe) / gam;
+    }
+    VTable vt;
+    if (x.model != FDTD_KINETIC_TWO_TERM) {
+      vt = build_vtable(1, sp.p.nv, sp.p.vmax_over_vth, sp.p.te_ev, sp.p.nu_model, dt);
+      kc = -(kQe / kMe) * dt / vt.dv;
+    }
+    x.vt = vt;
+    for (int k = 0; k < half && x.model != FDTD_KINETIC_TWO_TERM; ++k) {
       const int j = half + k;  // v_j > 0
       const double g = -vt.v[j] * vt.f[j] / (vt.vth * vt.vth);       // dF0/dv per unit density
       s[k] = (T)(sp.p.nu_model == FDTD_NU_HARD_SPHERE ? std::fabs(vt.v[j]) / vt.mean_speed : 1.0);
@@ -299,7 +355,6 @@ int upload_1d(fdtd_plasma* h) {
     // full model: velocity CFL number per unit field, and the equilibrium part's face-flux
     // difference per unit density and field, -kc (fhat_{j+1} - fhat_{j-1}) (no flux
     // through +vmax: -kc (-(fhat_{j-1} + fhat_j)) on the last bin)
-    const double kc = -(kQe / kMe) * dt / vt.dv;
     if (x.model == FDTD_KINETIC_FULL) {
       for (int k = 0; k < half; ++k) {
         const int j = half + k;
@@ -339,7 +394,9 @@ int upload_1d(fdtd_plasma* h) {
     }
     if ((e = hipMemcpyAsync(base + x.off_s, s.data(), half * sizeof(T), hipMemcpyHostToDevice, h->stream)) ||
         (e = hipMemcpyAsync(base + x.off_b, b.data(), half * sizeof(T), hipMemcpyHostToDevice, h->stream)) ||
-        (e = hipMemcpyAsync(base + x.off_w, w.data(), half * sizeof(double), hipMemcpyHostToDevice, h->stream)))
+        (e = hipMemcpyAsync(base + x.off_w, w.data(), half * sizeof(double), hipMemcpyHostToDevice, h->stream)) ||
+        (e = hipMemcpyAsync(base + x.off_c, cb.data(), half * sizeof(T), hipMemcpyHostToDevice, h->stream)) ||
+        (e = hipMemcpyAsync(base + x.off_v2h, v2h.data(), half * sizeof(T), hipMemcpyHostToDevice, h->stream)))
       return hip_fail(e, "upload velocity tables");
 
     Run1D<T>& R = rd[r];
@@ -380,6 +437,8 @@ int upload_1d(fdtd_plasma* h) {
     R.chunk_cell = reinterpret_cast<const int32_t*>(base + x.off_chunk);
     R.model = x.model;
     R.kc = (T)kc;
+    R.c_bin = reinterpret_cast<const T*>(base + x.off_c);
+    R.v2h_bin = reinterpret_cast<const T*>(base + x.off_v2h);
   }
   // probes
   for (size_t p = 0; p < h->probes.size(); ++p) {
@@ -850,17 +909,34 @@ int fdtd_plasma_run(fdtd_plasma* h, int64_t nsteps) {
                                    [](int64_t v, int64_t lim) { return v >= lim; }) -
                   h->tile_limit.begin());
       }
-      // full-model runs are single runs (never batched), so run 0 decides the kernel
-      const bool full = h->h1[0].model == FDTD_KINETIC_FULL;
-      e = h->precision == FDTD_FP64
-              ? launch_step1d<double>(h->ws + h->runs_off, h->ws + h->tiles_off, n, s, h->stream, full)
-              : launch_step1d<float>(h->ws + h->runs_off, h->ws + h->tiles_off, n, s, h->stream, full);
+      // full-model and two-term runs are single runs (never batched): run 0 decides
+      const int model = h->h1[0].model;
+      if (model == FDTD_KINETIC_TWO_TERM) {
+        // the l = 0 update of step s - 1 rides on step s (none pending at a call's start)
+        const bool pending = k > k0;
+        e = h->precision == FDTD_FP64
+                ? launch_step1d_tt<double>(h->ws + h->runs_off, h->ws + h->tiles_off, n, s, pending, false, h->stream)
+                : launch_step1d_tt<float>(h->ws + h->runs_off, h->ws + h->tiles_off, n, s, pending, false, h->stream);
+      } else {
+        const bool full = model == FDTD_KINETIC_FULL;
+        e = h->precision == FDTD_FP64
+                ? launch_step1d<double>(h->ws + h->runs_off, h->ws + h->tiles_off, n, s, h->stream, full)
+                : launch_step1d<float>(h->ws + h->runs_off, h->ws + h->tiles_off, n, s, h->stream, full);
+      }
     } else if (h->dims == 3) {
       e = launch_step3d(h->h3, s, h->stream);
     } else {
       e = launch_step2d(h->h2, s, h->stream);
     }
     if (e) return hip_fail(e, "launch step kernel");
+  }
+  if (h->dims == 1 && h->h1[0].model == FDTD_KINETIC_TWO_TERM && nsteps_loop > k0) {
+    // the last step's l = 0 update, so that the state after the call is complete
+    const int64_t s = h->step + nsteps_loop;
+    e = h->precision == FDTD_FP64
+            ? launch_step1d_tt<double>(h->ws + h->runs_off, h->ws + h->tiles_off, h->ntiles, s, true, true, h->stream)
+            : launch_step1d_tt<float>(h->ws + h->runs_off, h->ws + h->tiles_off, h->ntiles, s, true, true, h->stream);
+    if (e) return hip_fail(e, "launch l = 0 flush");
   }
   if ((e = hipEventRecord(h->ev1, h->stream))) return hip_fail(e, "hipEventRecord");
   h->step += nsteps;
@@ -895,7 +971,9 @@ int fdtd_plasma_field_size(const fdtd_plasma* h, int32_t run, int32_t field, siz
   switch (field) {
     case FDTD_F_E: case FDTD_F_J: *n = x.nx + 1; return FDTD_OK;
     case FDTD_F_H: *n = x.nx; return FDTD_OK;
-    case FDTD_F_DF: *n = (size_t)x.ncell * x.nv; return FDTD_OK;
+    case FDTD_F_DF:
+      *n = (size_t)x.ncell * x.nv * (x.model == FDTD_KINETIC_TWO_TERM ? 2 : 1);
+      return FDTD_OK;
     default: return fail(FDTD_EINVAL, "field %d not defined on a 1D grid", field);
   }
 }
@@ -936,7 +1014,14 @@ int fdtd_plasma_read_fields(fdtd_plasma* h, int32_t run, int32_t field, double* 
     auto val = [&](size_t k) -> double {
       return es == 8 ? reinterpret_cast<double*>(buf.data())[k] : reinterpret_cast<float*>(buf.data())[k];
     };
-    if (field == FDTD_F_DF && x.model == FDTD_KINETIC_FULL) {
+    if (field == FDTD_F_DF && x.model == FDTD_KINETIC_TWO_TERM) {
+      // row: F1 then F0 - n F0hat over the padded speed bins
+      for (int c = 0; c < x.ncell; ++c)
+        for (int k = 0; k < x.nv; ++k) {
+          dst[(size_t)c * 2 * x.nv + k] = val((size_t)c * x.row + k);
+          dst[(size_t)c * 2 * x.nv + x.nv + k] = val((size_t)c * x.row + x.half + k);
+        }
+    } else if (field == FDTD_F_DF && x.model == FDTD_KINETIC_FULL) {
       // row: odd half then even half on the v > 0 bins
       for (int c = 0; c < x.ncell; ++c)
         for (int k = 0; k < x.half; ++k) {

@@ -51,13 +51,15 @@ struct ProbeInfo {
 
 struct Host1D {
   int nx = 0, nv = 0, half = 0, ncell = 0;
-  int model = 0;      // FDTD_KINETIC_LINEAR / FULL
-  int row = 0;        // stored values per plasma node: half (linear) or nv (full)
+  int model = 0;      // FDTD_KINETIC_LINEAR / FULL / TWO_TERM
+  int row = 0;        // stored values per plasma node: half (linear), nv (full) or
+                      // 2 x the padded speed count (two-term)
   double dt = 0;
   VTable vt;
   std::vector<int32_t> cell_node;
   size_t off_E[2] = {0, 0}, off_H[2] = {0, 0}, off_J = 0, off_df = 0;
   size_t off_cell_node = 0, off_tau = 0, off_dens = 0, off_s = 0, off_b = 0, off_w = 0;
+  size_t off_c = 0, off_v2h = 0;   // two-term model tables
   int ntap = 0;
   int64_t tap_cap = 0;
   size_t off_tap = 0, off_chunk = 0;
@@ -67,6 +69,10 @@ struct Host1D {
 template <class T>
 hipError_t launch_step1d(const void* runs, const void* tiles, int ntiles, int64_t step,
                          hipStream_t stream, bool full);
+
+template <class T>
+hipError_t launch_step1d_tt(const void* runs, const void* tiles, int ntiles, int64_t step,
+                            bool pending, bool flush, hipStream_t stream);
 
 hipError_t launch_batch1d_persistent(const void* runs, const int32_t* order, int nruns,
                                      int32_t* queue, int64_t s0, int64_t s1, int groups,

@@ -325,11 +325,155 @@ __device__ __forceinline__ void kinetic_tile_full(const Run1D<T>& R, const T* el
   }
 }
 
+// Two-term model on the speed grid (section 5.1 expansion, l = 0 and l = 1 equations,
+// section 5.3 speed grid) with the field along the line.  Row of a plasma node:
+// [F1 | F0 - n F0hat] over `half` speed bins (the speed count padded to a power of two; the
+// padding stays zero).  With `pending`, the l = 0 update of the previous step is applied
+// first: F0 += c_k Ebar (phi_{k+1/2} - phi_{k-1/2}), phi = (v^2/2)(F1_k + F1_{k+1}) on the
+// inner faces (v2h_bin), zero at v = 0 and vmax, Ebar = (E^{n-1} + E^n)/2 with F1^{n-1/2}
+// as stored.  Then (unless `flush`) F1' = F1 + (-2x F1 + E (n b_k + kd (d_{k+1} - d_{k-1})))
+// / (2 + x), d = F0 - n F0hat (even across v = 0, zero beyond vmax), and the FP64 moment
+// with the face-averaged weights w_k.  Deferring the l = 0 update to the next step lets it
+// reuse that step's read of the row; a run ends with a flush launch.
+template <class T, int CPL, int NT>
+__device__ __forceinline__ void kinetic_tile_tt(const Run1D<T>& R, const T* eloc, const T* eprev,
+                                                const Tile1D& tile, T* jloc, bool pending,
+                                                bool flush) {
+  using V = typename Vec<T>::type;
+  constexpr int VPL = Vec<T>::n;
+  constexpr int kWaves = NT / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ch = R.half / VPL;
+  const int lpc = ch < 64 ? ch : 64;
+  const int cpw = 64 / lpc;
+  const int sub = lane / lpc, li = lane - sub * lpc;
+  const int nxt = sub * lpc + ((li + 1) & (lpc - 1));
+  const int prv = sub * lpc + ((li - 1) & (lpc - 1));
+  const bool last_lane = li == lpc - 1, first_lane = li == 0;
+
+  V s[CPL], b[CPL], cf[CPL], vh[CPL];
+  double w[CPL][VPL];
+#pragma unroll
+  for (int m = 0; m < CPL; ++m) {
+    const int k = li + m * lpc;
+    s[m] = reinterpret_cast<const V*>(R.s_bin)[k];
+    b[m] = reinterpret_cast<const V*>(R.b_bin)[k];
+    cf[m] = reinterpret_cast<const V*>(R.c_bin)[k];
+    vh[m] = reinterpret_cast<const V*>(R.v2h_bin)[k];
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) w[m][v] = R.w_bin[k * VPL + v];
+  }
+  const T kd = R.kc;   // dt (e/m) / gam
+  V* __restrict__ dfv = reinterpret_cast<V*>(R.df);
+  for (int c0 = tile.cell0 + wave * cpw; c0 < tile.cell1; c0 += kWaves * cpw) {
+    const int c = c0 + sub;
+    const bool live = c < tile.cell1;
+    V f[CPL], d[CPL];
+    T ne = T(0), tau = T(0), Ev = T(0), Eb = T(0);
+    int loc = -1;
+    if (live) {
+      loc = R.cell_node[c] - tile.node0;
+      tau = R.tau[c];
+      ne = R.dens[c];
+      Ev = eloc[loc];
+      if (pending) Eb = T(0.5) * (eprev[loc] + Ev);
+      const V* row = dfv + (size_t)c * (2 * ch);
+#pragma unroll
+      for (int m = 0; m < CPL; ++m) {
+        f[m] = row[li + m * lpc];
+        d[m] = row[ch + li + m * lpc];
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < CPL; ++m)
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) lane_at(f[m], v) = lane_at(d[m], v) = T(0);
+    }
+    // the deferred l = 0 update
+    if (pending) {
+      T nf[CPL];
+#pragma unroll
+      for (int m = 0; m < CPL; ++m) nf[m] = __shfl(lane_at(f[m], 0), nxt);
+      T ph[CPL][VPL];
+#pragma unroll
+      for (int m = 0; m < CPL; ++m) {
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) {
+          T fr;
+          if (v + 1 < VPL) fr = lane_at(f[m], v + 1);
+          else if (!last_lane) fr = nf[m];
+          else fr = (m + 1 < CPL) ? nf[m + 1 < CPL ? m + 1 : m] : T(0);
+          ph[m][v] = lane_at(vh[m], v) * (lane_at(f[m], v) + fr);   // 0 on the top face
+        }
+      }
+      T got[CPL];
+#pragma unroll
+      for (int m = 0; m < CPL; ++m) got[m] = __shfl(ph[m][VPL - 1], prv);
+#pragma unroll
+      for (int m = 0; m < CPL; ++m) {
+        const T pl0 = !first_lane ? got[m] : (m > 0 ? got[m > 0 ? m - 1 : 0] : T(0));
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) {
+          const T pl = v == 0 ? pl0 : ph[m][v - 1];
+          lane_at(d[m], v) = fma(lane_at(cf[m], v) * Eb, ph[m][v] - pl, lane_at(d[m], v));
+        }
+      }
+    }
+    double acc = 0.0;
+    if (!flush) {
+      // neighbours of d: d_{k+1} from the next lane, d_{k-1} from the previous one
+      T nd[CPL], pd[CPL];
+#pragma unroll
+      for (int m = 0; m < CPL; ++m) {
+        nd[m] = __shfl(lane_at(d[m], 0), nxt);
+        pd[m] = __shfl(lane_at(d[m], VPL - 1), prv);
+      }
+      const T nE = ne * Ev, kE = kd * Ev, tau2 = tau + tau;
+#pragma unroll
+      for (int m = 0; m < CPL; ++m) {
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) {
+          T dr, dl;
+          if (v + 1 < VPL) dr = lane_at(d[m], v + 1);
+          else if (!last_lane) dr = nd[m];
+          else dr = (m + 1 < CPL) ? nd[m + 1 < CPL ? m + 1 : m] : T(0);
+          if (v > 0) dl = lane_at(d[m], v - 1);
+          else if (!first_lane) dl = pd[m];
+          else dl = (m > 0) ? pd[m > 0 ? m - 1 : 0] : lane_at(d[m], 0);   // even at v = 0
+          const T sv = lane_at(s[m], v);
+          const T r = cn_recip(fma(tau, sv, T(2)));
+          const T fv = lane_at(f[m], v);
+          const T drive = fma(kE, dr - dl, lane_at(b[m], v) * nE);
+          const T t = fma(-(tau2 * sv), fv, drive);
+          const T fn = fma(t, r, fv);
+          lane_at(f[m], v) = fn;
+          acc = fma(w[m][v], (double)fn, acc);
+        }
+      }
+    }
+    if (live) {
+      V* row = dfv + (size_t)c * (2 * ch);
+#pragma unroll
+      for (int m = 0; m < CPL; ++m) {
+        if (!flush) row[li + m * lpc] = f[m];
+        if (pending) row[ch + li + m * lpc] = d[m];
+      }
+    }
+    if (!flush) {
+      double a1[1] = {acc};
+      int which = 0;
+      const double tot = group_reduce<1>(a1, lpc, li, which);
+      if (live && first_lane) jloc[loc] = (T)tot;
+    }
+  }
+}
+
 // One step of one tile by a work-group of NT threads (tile.node1 - tile.node0 <= NT).
 // jloc / eloc: LDS arrays of NT values.  The caller synchronises before reusing them.
-template <class T, int NT, bool FULL = false>
+template <class T, int NT, int KIND = 0>
 __device__ __forceinline__ void step_tile(const Run1D<T>& R, const Tile1D& tile, int64_t step,
-                                          T* jloc, T* eloc) {
+                                          T* jloc, T* eloc, bool pending = false,
+                                          bool flush = false) {
   const int par = (int)(step & 1);
   const T* __restrict__ Ec = R.E[par];
   T* __restrict__ En = R.E[par ^ 1];
@@ -358,15 +502,22 @@ __device__ __forceinline__ void step_tile(const Run1D<T>& R, const Tile1D& tile,
   if (tile.cell1 > tile.cell0) {
     const int ch = R.half / Vec<T>::n;
     const int cpl = ch < 64 ? 1 : ch / 64;
-    if constexpr (FULL) {
+    if constexpr (KIND == 1) {
       if (cpl == 1) kinetic_tile_full<T, 1, NT>(R, eloc, tile, jloc);
       else if (cpl == 2) kinetic_tile_full<T, 2, NT>(R, eloc, tile, jloc);
       else kinetic_tile_full<T, 4, NT>(R, eloc, tile, jloc);
+    } else if constexpr (KIND == 2) {
+      // E^{n-1} at the tile's nodes, from the buffer this step's E update overwrites
+      // after the barrier below (every tile writes only its own nodes)
+      const T* eprev = En + tile.node0;
+      if (cpl == 1) kinetic_tile_tt<T, 1, NT>(R, eloc, eprev, tile, jloc, pending, flush);
+      else kinetic_tile_tt<T, 2, NT>(R, eloc, eprev, tile, jloc, pending, flush);
     } else if (cpl == 1) kinetic_tile<T, 4, NT>(R, eloc, tile, jloc);
     else if (cpl == 2) kinetic_tile<T, 2, NT>(R, eloc, tile, jloc);
     else kinetic_tile<T, 1, NT>(R, eloc, tile, jloc);
   }
   __syncthreads();
+  if (flush) return;   // the l = 0 update alone, after a run's last step
 
   // 3. H^{n+1/2} and E^{n+1}
   if (own) {
@@ -444,7 +595,21 @@ __global__ __launch_bounds__(kBlock) void k_step1d_full(const Run1D<T>* __restri
   const Tile1D tile = tiles[blockIdx.x];
   const Run1D<T>& R = runs[tile.run];
   if (step >= R.step_limit) return;
-  step_tile<T, kBlock, true>(R, tile, step, jloc, eloc);
+  step_tile<T, kBlock, 1>(R, tile, step, jloc, eloc);
+}
+
+// The same step for runs of the two-term model; `pending` applies the previous step's
+// l = 0 update first, `flush` applies only that (step = the number of steps done).
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_step1d_tt(const Run1D<T>* __restrict__ runs,
+                                                      const Tile1D* __restrict__ tiles,
+                                                      int64_t step, int pending, int flush) {
+  __shared__ T jloc[kMaxTile1D];
+  __shared__ T eloc[kMaxTile1D];
+  const Tile1D tile = tiles[blockIdx.x];
+  const Run1D<T>& R = runs[tile.run];
+  if (!flush && step >= R.step_limit) return;
+  step_tile<T, kBlock, 2>(R, tile, step, jloc, eloc, pending != 0, flush != 0);
 }
 
 // Persistent batch: steps [s0, s1) of every run, runs taken longest first from `order`
@@ -484,6 +649,16 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch1d_persistent(
 }
 
 template <class T>
+hipError_t launch_step1d_tt(const void* runs, const void* tiles, int ntiles, int64_t step,
+                            bool pending, bool flush, hipStream_t stream) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_step1d_tt<T>, dim3(ntiles), dim3(kBlock), 0, stream,
+                     static_cast<const Run1D<T>*>(runs), static_cast<const Tile1D*>(tiles),
+                     step, (int)pending, (int)flush);
+  return hipGetLastError();
+}
+
+template <class T>
 hipError_t launch_step1d(const void* runs, const void* tiles, int ntiles, int64_t step,
                          hipStream_t stream, bool full) {
   if (ntiles <= 0) return hipSuccess;
@@ -513,5 +688,9 @@ template hipError_t launch_step1d<float>(const void*, const void*, int, int64_t,
                                          bool);
 template hipError_t launch_step1d<double>(const void*, const void*, int, int64_t, hipStream_t,
                                           bool);
+template hipError_t launch_step1d_tt<float>(const void*, const void*, int, int64_t, bool, bool,
+                                            hipStream_t);
+template hipError_t launch_step1d_tt<double>(const void*, const void*, int, int64_t, bool, bool,
+                                             hipStream_t);
 
 }  // namespace fdtdp

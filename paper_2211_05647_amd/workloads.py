@@ -76,7 +76,9 @@ class Run1D:
     nu_model: str = "hard_sphere"
     bc: str = "mur"
     meta: dict = field(default_factory=dict)
-    kinetic: str = "linear"     # "linear" (F0 frozen) or "full" (the whole f evolves)
+    kinetic: str = "linear"     # "linear" (F0 frozen), "full" (the whole f evolves) or
+                                # "two_term" (speed grid: F1 and an evolving F0)
+    f0_model: str = "maxwell"   # two-term model: "maxwell" or "druyvesteyn"
 
     @property
     def plasma_cells(self) -> int:

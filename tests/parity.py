@@ -23,7 +23,8 @@ def oracle_1d(run, nx=None):
                     nv=run.nv, vmax_over_vth=run.vmax_over_vth, te_ev=run.te_ev,
                     nu_model=run.nu_model, bc=run.bc, src_node=run.src_node,
                     src_amp=run.src_amp, src_f=run.src_f, src_tau=run.src_tau,
-                    src_t0=run.src_t0, kinetic=getattr(run, "kinetic", "linear"))
+                    src_t0=run.src_t0, kinetic=getattr(run, "kinetic", "linear"),
+                    f0_model=getattr(run, "f0_model", "maxwell"))
 
 
 def space_time_1d(sim, orc, nsteps, every, probes, df_snaps=None):
