@@ -284,6 +284,42 @@ def sweep_3d(B, W, torch, cpu_budget_s=2.0):
     return {"vacuum_3d": out}
 
 
+def extra_twoterm(B, W, torch, steps=2000):
+    """The two-term model on the speed grid (F1 and an evolving F0, v_dim = 31, Druyvesteyn
+    F0 at 1 eV) on the large line's density and collision profile, FP32, one step per
+    launch; the FP64 oracle timed beside it on the same line."""
+    run = W.c1(steps=steps)
+    run.kinetic, run.nv, run.f0_model = "two_term", 31, "druyvesteyn"
+    run.te_ev, run.vmax_over_vth = 1.0, 5.0
+    log(f"two-term: Nx={run.nx} v_dim={run.nv} plasma cells={run.plasma_cells}")
+    wall, ms = time_single(run, B, torch, steps, 50)
+    row = 32
+    by = run.plasma_cells * (2 * row * 4 * 2 + 12 + 4) + (run.nx + 1) * 4 * 5
+    out = dict(workload=f"1D Yee + two-term speed-grid kinetic (F0 evolving), Nx={run.nx}, "
+                        f"v_dim={run.nv}, FP32, {steps} steps",
+               kernel="k_step1d_tt<float>",
+               updates_per_s=run.plasma_cells * run.nv * steps / wall,
+               ms_per_step=wall / steps * 1e3, kernel_ms_per_step=ms,
+               hbm_gbs=by / (ms * 1e-3) / 1e9, hbm_frac=by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+    sys.path.insert(0, ROOT)
+    from oracle.core import Oracle1D, threads
+    o = Oracle1D(run.nx, run.dx, run.courant, run.ne, run.nubar, nv=run.nv,
+                 vmax_over_vth=run.vmax_over_vth, te_ev=run.te_ev, src_node=run.src_node,
+                 src_amp=run.src_amp, src_f=run.src_f, src_tau=run.src_tau,
+                 src_t0=run.src_t0, kinetic="two_term", f0_model=run.f0_model)
+    t0 = time.perf_counter()
+    o.run(20)
+    per = (time.perf_counter() - t0) / 20
+    k = max(20, int(5.0 / per))
+    t0 = time.perf_counter()
+    o.run(k)
+    dt = time.perf_counter() - t0
+    out["cpu_oracle"] = dict(kind="oracle", cores=threads(),
+                             updates_per_s=run.plasma_cells * run.nv * k / dt,
+                             sample=f"same line, {k} steps after 20, FP64")
+    return {"two_term_c1": out}
+
+
 def extra_c2(B, W, torch, autotune, steps=None):
     """2D column, 512^2, 32x32 velocity bins."""
     run = W.c2()
@@ -398,6 +434,7 @@ def extra_workloads(B, W, torch, autotune):
     out.update(closure_speedup(B, W, torch))
     out.update(extra_full(B, W, torch))
     out.update(extra_3d(B, W, torch))
+    out.update(extra_twoterm(B, W, torch))
     return out
 
 
@@ -476,7 +513,8 @@ def main():
                     help="steps per launch of the large 1D workload (default: tuned; 1 = one "
                          "step per launch)")
     ap.add_argument("--calibrate-copy", action="store_true")
-    ap.add_argument("--only", choices=["c1l", "c2", "c3", "closure", "c4", "sweep", "full", "3d", "sweep3d"], default=None,
+    ap.add_argument("--only", choices=["c1l", "c2", "c3", "closure", "c4", "sweep", "full", "3d", "sweep3d",
+                             "twoterm"], default=None,
                     help="run only one of the extra measurements (for profiling); c2 and c4 "
                          "take --steps steps")
     args = ap.parse_args()
@@ -502,7 +540,8 @@ def main():
                 "sweep": lambda: nmcps_sweep(B, W, torch),
                 "full": lambda: extra_full(B, W, torch, min(args.steps, 2000)),
                 "3d": lambda: extra_3d(B, W, torch, args.steps),
-                "sweep3d": lambda: sweep_3d(B, W, torch)}[args.only]
+                "sweep3d": lambda: sweep_3d(B, W, torch),
+                "twoterm": lambda: extra_twoterm(B, W, torch, min(args.steps, 2000))}[args.only]
         print(json.dumps(only()), flush=True)
         return
 

@@ -539,6 +539,9 @@ int build_tiles_1d(fdtd_plasma* h) {
     const Host1D& x = h->h1[r];
     const int es = elem_size(h->precision);
     int tile = h->tile > 0 ? h->tile : default_tile_1d(x.row, es, x.nx, x.ncell);
+    // two-term rows are short (2 x 32 speeds): 64-node tiles measured fastest on a 65536-node
+    // line (7.9 us per step against 9.5 at the 128 the row size alone would give)
+    if (h->tile <= 0 && x.model == FDTD_KINETIC_TWO_TERM) tile = std::min(tile, 64);
     tile = std::max(32, std::min(kMaxTile1D, tile));
     int c = 0;
     for (int n0 = 0; n0 <= x.nx; n0 += tile) {
