@@ -39,9 +39,11 @@ FLOPS_PER_BIN_STEP = 8
 FLOPS_PER_BIN_LAUNCH = 3
 
 
-def kernel_hash():
+def kernel_hash(blocked=True):
+    """Hash of the sources the kernel is built from (the blocked kernel: its own file and
+    the shared header; the one-step kernel likewise)."""
     h = hashlib.sha256()
-    for f in ("common.h", "kernels1d.hip", "kernels1d_tb.hip"):
+    for f in ("common.h", "kernels1d_tb.hip" if blocked else "kernels1d.hip"):
         h.update(open(os.path.join(ROOT, "paper_2211_05647_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -54,7 +56,7 @@ def pmc_traffic(kb=1):
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    if d.get("kernel_hash") != kernel_hash():
+    if d.get("kernel_hash") != kernel_hash(blocked=kb > 1):
         return None
     return d.get("hbm_bytes_per_launch")
 

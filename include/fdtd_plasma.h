@@ -126,7 +126,8 @@ typedef struct {
  * by dF0/dv of the current F0, J = -e (4 pi / 3) gam sum w_k F1_k with w_k the mean of
  * v^3 over the bin's flux-carrying faces, which makes the field energy J removes exactly
  * the electrons' kinetic energy gain.  FDTD_F_DF then gives [ncell][2 nv]: F1, then
- * F0 - ne F0hat.  Never temporally blocked.
+ * F0 - ne F0hat.  The exchange between F0 and F1 is explicit: a step with
+ * (e/m) |E| dt / (vmax / nv) > 1 sets the run status.  Never temporally blocked.
  * 3D grids (the paper's production model, section 5.3): ne / nu_mean are per cell
  * [nz][ny][nx]; F1 is a vector on a speed grid of nv speeds (1..64; the paper uses 31)
  * v_k = (k + 1/2) vmax / nv, one component at every E point whose edge touches plasma (the

@@ -429,6 +429,8 @@ __device__ __forceinline__ void kinetic_tile_tt(const Run1D<T>& R, const T* eloc
         pd[m] = __shfl(lane_at(d[m], VPL - 1), prv);
       }
       const T nE = ne * Ev, kE = kd * Ev, tau2 = tau + tau;
+      // the explicit exchange between F0 and F1 needs (e/m) |E| dt / gam <= 1
+      if (live && first_lane && !(fabs(kE) <= T(1))) atomicOr(R.status, 2);
 #pragma unroll
       for (int m = 0; m < CPL; ++m) {
 #pragma unroll

@@ -89,3 +89,17 @@ def test_two_term_rejected_in_batches(gpu_lib):
     run = _run(31)
     with pytest.raises(B.FdtdError):
         B.Sim([run, run], precision=B.FP32)
+
+
+def test_two_term_cfl_flagged(gpu_lib):
+    """A field with (e/m) |E| dt / gam > 1 sets the run status; the tested drive does not."""
+    run = _run(31, steps=700)
+    sim = B.Sim(run, precision=B.FP64)
+    sim.run(run.steps)
+    assert sim.run_status(0) == 0
+    sim.close()
+    run.src_amp *= 100.0
+    sim = B.Sim(run, precision=B.FP64)
+    sim.run(run.steps)
+    assert sim.run_status(0) != 0
+    sim.close()
