@@ -1,0 +1,35 @@
+"""Scattering parameters of a plasma slab (the paper's S11 and S21, section 5.3 results):
+E recorded on the device at two ports, before and after the slab, in the slab run and in
+the same run with the plasma removed; S11 = spectrum of the reflected part at port 1 over
+the incident spectrum there, S21 = transmitted spectrum at port 2 over the vacuum run's.
+The time stepping runs in the library; this module only reads the two probe series back
+and takes their discrete Fourier transforms."""
+import copy
+
+import numpy as np
+
+from . import binding as B
+
+
+def _series(run, ports, precision):
+    sim = B.Sim(run, precision=precision, max_probes=len(ports), probe_capacity=run.steps)
+    ids = [sim.add_probe(B.F_E, p) for p in ports]
+    sim.run(run.steps)
+    out = [sim.read_probe(i, run.steps) for i in ids]
+    sim.close()
+    return out
+
+
+def slab_sparams(run, freqs_hz, precision=B.FP32, ports=None):
+    """(S11, S21) at ``freqs_hz`` for a 1D Run1D (ports default to run.meta['ports'])."""
+    ports = tuple(ports or run.meta["ports"])
+    vac = copy.deepcopy(run)
+    vac.ne = np.zeros_like(run.ne)
+    vac.nubar = np.zeros_like(run.nubar)
+    s1, s2 = _series(run, ports, precision)
+    v1, v2 = _series(vac, ports, precision)
+    dt = run.courant * run.dx / 299792458.0
+    t = (np.arange(run.steps) + 1) * dt
+    ph = np.exp(-2j * np.pi * np.outer(np.asarray(freqs_hz, dtype=np.float64), t))
+    inc = ph @ v1
+    return (ph @ (s1 - v1)) / inc, (ph @ s2) / (ph @ v2)

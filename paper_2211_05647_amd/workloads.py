@@ -304,3 +304,26 @@ def argon_slab_3d(nx=64, ny=64, nz=256, nv=31, steps=1200, slab_mm=4.0, ncpml=8,
     return Run3D(name=name, nx=nx, ny=ny, nz=nz, nv=nv, ne=ne, nubar=nu, src_kind=1, src_i=0,
                  src_j=0, src_k=ncpml + 4, steps=steps, ncpml=ncpml, f0_model=f0,
                  meta=dict(slab=(k0, k1)), **p)
+
+
+def argon_line_1d(nv=31, kinetic="two_term", f0="druyvesteyn", slab_mm=4.0,
+                  cells_per_mm=5, steps=4000) -> Run1D:
+    """The paper's argon experiment along its propagation axis (the plane wave sees only z):
+    air, a slab_mm slab of 1e19 m^-3 argon plasma (Te = 1 eV, nu = N s <v> of the stand-in
+    cross section), air; Mur ends; the section 5.3 pulse (20 GHz, tau 48 ps, t0 217 ps)
+    from a soft source 100 cells before the slab.  The ports of the scattering parameters
+    sit at the two faces of the slab (the paper's z = 0 and z = 4 mm)."""
+    dx = 1e-3 / cells_per_mm
+    n_slab = int(round(slab_mm * cells_per_mm))
+    lo = 400
+    hi = lo + n_slab
+    nx = hi + 400
+    ne = np.zeros(nx + 1)
+    nub = np.zeros(nx + 1)
+    ne[lo:hi] = ARGON_NE
+    nub[lo:hi] = argon_nubar(f0=f0)
+    run = Run1D(name="argon1d", nx=nx, nv=nv, ne=ne, nubar=nub, src_node=lo - 100,
+                src_amp=1.0, src_f=20e9, src_tau=48e-12, src_t0=217e-12, steps=steps, dx=dx,
+                te_ev=ARGON_TE, vmax_over_vth=5.0, kinetic=kinetic, f0_model=f0,
+                meta=dict(ports=(lo - 1, hi)))
+    return run
