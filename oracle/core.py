@@ -60,6 +60,8 @@ def lib():
         L.oracle_sgrid.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, _dp, _dp, _dp, _dp, _dp]
         L.oracle_snu_shape.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_int, _dp]
         L.oracle_plasma3d_count.argtypes = [C.c_int, C.c_int, C.c_int, _dp]
+        L.oracle_plasma3d_count_strict.argtypes = [C.c_int, C.c_int, C.c_int, _dp, _ip]
+        L.oracle_plasma3d_map.argtypes = [C.c_int, C.c_int, C.c_int, _dp, C.c_int, _ip, _ip]
         L.oracle_run3d.argtypes = (
             [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
              C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
@@ -69,7 +71,7 @@ def lib():
              C.c_double, C.c_double, C.c_double, C.c_double,
              C.c_longlong, C.c_longlong,
              _dp, _dp, _dp, _dp, _dp,
-             C.c_int, _ip, _dp])
+             C.c_int, _ip, _dp, C.c_int])
         L.oracle_run1d_twoterm.argtypes = (
             [C.c_int, C.c_double, C.c_double, C.c_int,
              C.c_int, C.c_double, C.c_double, C.c_int, C.c_int,
@@ -351,6 +353,12 @@ class Oracle3D:
     """3D Yee cube with CPML on all faces and, at every plasma E point, the F1 component
     of that E on a speed grid of ``vdim`` speeds (the paper's production model).
 
+    ``kinetic``: "linear" (F0 held, F1 on every E point touching plasma), "two_term"
+    (F0 per plasma cell evolving under the l = 0 equation, F1 on the E points whose four
+    cells are all plasma) or "two_term_frozen" (that model with F0 held).  ``df`` holds
+    the F1 rows of the points, then for the two-term models the F0 - n F0hat rows of
+    the plasma cells (cells with ne > 0 in storage order).
+
     ``ne``/``nubar`` are per cell, shape (nz, ny, nx).  Fields are kept as flat arrays in
     the library's layout; ``Ex``/``Ey``/``Ez`` (and H, J) give shaped views.
     ``src_kind``: 0 none, 1 Ex sheet on plane ``src_k``, 2 Ex point (src_i, src_j, src_k).
@@ -360,7 +368,8 @@ class Oracle3D:
                  te_ev=1.0, nu_model="hard_sphere", f0_model="maxwell", ncpml=8,
                  cpml_order=3.0, sigma_factor=1.0, kappa_max=5.0, alpha_min=0.0,
                  alpha_max=0.05, src_kind=0, src_i=0, src_j=0, src_k=0, src_amp=0.0,
-                 src_f=0.0, src_tau=1.0, src_t0=0.0):
+                 src_f=0.0, src_tau=1.0, src_t0=0.0, kinetic="linear"):
+        self.model = {"linear": 0, "two_term": 1, "two_term_frozen": 2}[kinetic]
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.dx, self.courant = float(dx), float(courant)
         self.ne = np.ascontiguousarray(ne, dtype=np.float64).reshape(-1)
@@ -382,8 +391,16 @@ class Oracle3D:
         self.H = np.zeros(nh_)
         self.J = np.zeros(ne_)
         self.psi = np.zeros(2 * ne_ + 2 * nh_)
-        self.npoints = int(lib().oracle_plasma3d_count(X, Y, Z, _p(self.ne)))
-        self.df = np.zeros(self.npoints * self.vdim)
+        strict = int(self.model != 0)
+        np_ = int(lib().oracle_plasma3d_map(X, Y, Z, _p(self.ne), strict, None, None))
+        self.pidx = np.zeros(max(np_, 1), dtype=np.int32)
+        self.pcell = np.zeros(4 * max(np_, 1), dtype=np.int32)
+        lib().oracle_plasma3d_map(X, Y, Z, _p(self.ne), strict, _p(self.pidx), _p(self.pcell))
+        self.npoints = np_
+        self.pidx, self.pcell = self.pidx[:np_], self.pcell[:4 * np_].reshape(np_, 4)
+        self.cells = np.flatnonzero(self.ne > 0) if strict else np.zeros(0, dtype=np.int64)
+        self.ncells = len(self.cells)
+        self.df = np.zeros((self.npoints + self.ncells) * self.vdim)
         self.step = 0
         self.dt = self.courant * self.dx / constants()["c"]
 
@@ -412,11 +429,16 @@ class Oracle3D:
             _p(self.ne), _p(self.nubar), *self.src,
             self.step, int(nsteps),
             _p(self.E), _p(self.H), _p(self.J), _p(self.psi), _p(self.df),
-            len(idx), _p(idx) if len(idx) else None, _p(pout))
+            len(idx), _p(idx) if len(idx) else None, _p(pout), self.model)
         if rc:
             raise ValueError("oracle_run3d rejected its arguments")
         self.step += int(nsteps)
         return pout[: nsteps * len(idx)].reshape(nsteps, len(idx))
 
     def df_rows(self):
-        return self.df.reshape(self.npoints, self.vdim)
+        """F1 rows of the plasma points."""
+        return self.df[: self.npoints * self.vdim].reshape(self.npoints, self.vdim)
+
+    def f0_rows(self):
+        """F0 - n F0hat rows of the plasma cells (two-term models)."""
+        return self.df[self.npoints * self.vdim:].reshape(self.ncells, self.vdim)

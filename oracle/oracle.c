@@ -50,13 +50,22 @@
  *     the streaming and magnetic terms dropped as in section 5.2); in 1V its
  *     even part plays F0 (the l = 0 equation: it heats) and its odd part F1.
  *     Stored: delta = f - n F0hat (zero at start), on the full signed grid.
- *     Velocity derivative in conservative flux form with the Lax-Wendroff
- *     flux (second order, stable for |a dt/dv| <= 1) and zero flux through
- *     +-vmax, so the electron number is conserved exactly; the collision term
- *     acts on the odd part with the same Crank-Nicolson factor as the linear
- *     model, and the drive is taken at E^n.  For small fields the odd part
- *     obeys the linear model's update with dF0/dv replaced by a central
- *     difference.
+ *     Velocity derivative in conservative flux form, zero flux through
+ *     +-vmax (the electron number is conserved exactly), the odd part first
+ *     (central flux with a Lax-Wendroff correction, the collision term with
+ *     the linear model's Crank-Nicolson factor), then the even part from the
+ *     time-centred odd part; the drive is taken at E^n.  For small fields the
+ *     odd part obeys the linear model's update with dF0/dv replaced by a
+ *     central difference.
+ *   - two-term model on the speed grid (1D line and 3D cube): F0 - n F0hat
+ *     evolves under the l = 0 equation in flux form over the speed faces,
+ *     the flux through a face the face's v^2 times the mean of the two F1
+ *     values beside it times the time-centred E, none through v = 0 or vmax;
+ *     the F1 drive adds the central difference of F0 - n F0hat (reflected
+ *     evenly below v_0, zero above vmax); the l = 0 collision term (energy
+ *     loss to the gas) is left out.  In 3D an edge sees the mean F0 of its
+ *     four cells and each cell takes a quarter of every one of its plasma
+ *     edges' E.F1; plasma points are the edges with all four cells plasma.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -758,66 +767,98 @@ int oracle_snu_shape(int vdim, const double *v, const double *F0, double gam, in
  * n and nubar are those means.  df rows (vdim values): the plasma points of
  * Ex, then of Ey, then of Ez, each in storage order.
  * Source kinds: 1 sheet, Ex += g at every updated Ex point of plane k = src_k;
- * 2 point, Ex += g at (src_i + 1/2, src_j, src_k). */
-static int o3_plasma(int nx, int ny, int nz, const double *ne, const double *nubar,
-                     int *pidx, double *pn, double *pnu)
+ * 2 point, Ex += g at (src_i + 1/2, src_j, src_k).
+ * model 0 is the above with F0 held.  Models 1 and 2 are the two-term model of
+ * sections 5.1-5.3 (F0 evolving under the l = 0 equation, or held): a plasma
+ * point is then an updated E point whose four cells all have ne > 0, F0 - n F0hat
+ * lives in every cell with ne > 0 (df rows after the points' F1 rows, cells in
+ * storage order), an edge sees the mean of its four cells' F0 in its F1 drive,
+ * and each cell collects a quarter of E.F1 from each of its plasma edges for its
+ * l = 0 flux; J takes the weights (v^3 at the lower speed face + v^3 at the upper,
+ * zero at vmax) / 2, which makes the exchange of energy between the field and
+ * the cells' electrons exact. */
+/* One candidate E point at flat index `at` whose edge touches the cells c[0..3]:
+ * a plasma point if the mean density is > 0 (strict: if all four cells are
+ * plasma, the reading of the two-term model, whose F0 lives in the cells). */
+static int o3_point(size_t at, const size_t c[4], const double *ne, const double *nubar,
+                    int strict, int np, int *pidx, double *pn, double *pnu, int *pcell)
+{
+    double n = 0.25 * (ne[c[0]] + ne[c[1]] + ne[c[2]] + ne[c[3]]);
+    int ok = strict ? (ne[c[0]] > 0.0 && ne[c[1]] > 0.0 && ne[c[2]] > 0.0 && ne[c[3]] > 0.0)
+                    : n > 0.0;
+    if (!ok) return np;
+    if (pidx) {
+        pidx[np] = (int)at;
+        pn[np] = n;
+        pnu[np] = 0.25 * (nubar[c[0]] + nubar[c[1]] + nubar[c[2]] + nubar[c[3]]);
+        if (pcell)
+            for (int q = 0; q < 4; ++q) pcell[4 * np + q] = (int)c[q];
+    }
+    return np + 1;
+}
+
+static int o3_plasma_ex(int nx, int ny, int nz, const double *ne, const double *nubar,
+                        int strict, int *pidx, double *pn, double *pnu, int *pcell)
 {
     int np = 0;
-#define CELL(a, b, c) ((size_t)(c) * ny * nx + (size_t)(b) * nx + (a))
+#define CELL(a, b, cc) ((size_t)(cc) * ny * nx + (size_t)(b) * nx + (a))
     for (int k = 1; k < nz; ++k)
         for (int j = 1; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
-                double n = 0.25 * (ne[CELL(i, j - 1, k - 1)] + ne[CELL(i, j, k - 1)] +
-                                   ne[CELL(i, j - 1, k)] + ne[CELL(i, j, k)]);
-                if (n > 0.0) {
-                    if (pidx) {
-                        pidx[np] = (int)(((size_t)k * (ny + 1) + j) * nx + i);
-                        pn[np] = n;
-                        pnu[np] = 0.25 * (nubar[CELL(i, j - 1, k - 1)] + nubar[CELL(i, j, k - 1)] +
-                                          nubar[CELL(i, j - 1, k)] + nubar[CELL(i, j, k)]);
-                    }
-                    ++np;
-                }
+                size_t c[4] = {CELL(i, j - 1, k - 1), CELL(i, j, k - 1), CELL(i, j - 1, k), CELL(i, j, k)};
+                np = o3_point(((size_t)k * (ny + 1) + j) * nx + i, c, ne, nubar, strict, np,
+                              pidx, pn, pnu, pcell);
             }
     size_t offy = (size_t)nx * (ny + 1) * (nz + 1);
     for (int k = 1; k < nz; ++k)
         for (int j = 0; j < ny; ++j)
             for (int i = 1; i < nx; ++i) {
-                double n = 0.25 * (ne[CELL(i - 1, j, k - 1)] + ne[CELL(i, j, k - 1)] +
-                                   ne[CELL(i - 1, j, k)] + ne[CELL(i, j, k)]);
-                if (n > 0.0) {
-                    if (pidx) {
-                        pidx[np] = (int)(offy + ((size_t)k * ny + j) * (nx + 1) + i);
-                        pn[np] = n;
-                        pnu[np] = 0.25 * (nubar[CELL(i - 1, j, k - 1)] + nubar[CELL(i, j, k - 1)] +
-                                          nubar[CELL(i - 1, j, k)] + nubar[CELL(i, j, k)]);
-                    }
-                    ++np;
-                }
+                size_t c[4] = {CELL(i - 1, j, k - 1), CELL(i, j, k - 1), CELL(i - 1, j, k), CELL(i, j, k)};
+                np = o3_point(offy + ((size_t)k * ny + j) * (nx + 1) + i, c, ne, nubar, strict, np,
+                              pidx, pn, pnu, pcell);
             }
     size_t offz = offy + (size_t)(nx + 1) * ny * (nz + 1);
     for (int k = 0; k < nz; ++k)
         for (int j = 1; j < ny; ++j)
             for (int i = 1; i < nx; ++i) {
-                double n = 0.25 * (ne[CELL(i - 1, j - 1, k)] + ne[CELL(i, j - 1, k)] +
-                                   ne[CELL(i - 1, j, k)] + ne[CELL(i, j, k)]);
-                if (n > 0.0) {
-                    if (pidx) {
-                        pidx[np] = (int)(offz + ((size_t)k * (ny + 1) + j) * (nx + 1) + i);
-                        pn[np] = n;
-                        pnu[np] = 0.25 * (nubar[CELL(i - 1, j - 1, k)] + nubar[CELL(i, j - 1, k)] +
-                                          nubar[CELL(i - 1, j, k)] + nubar[CELL(i, j, k)]);
-                    }
-                    ++np;
-                }
+                size_t c[4] = {CELL(i - 1, j - 1, k), CELL(i, j - 1, k), CELL(i - 1, j, k), CELL(i, j, k)};
+                np = o3_point(offz + ((size_t)k * (ny + 1) + j) * (nx + 1) + i, c, ne, nubar, strict,
+                              np, pidx, pn, pnu, pcell);
             }
 #undef CELL
     return np;
 }
 
+static int o3_plasma(int nx, int ny, int nz, const double *ne, const double *nubar,
+                     int *pidx, double *pn, double *pnu)
+{
+    return o3_plasma_ex(nx, ny, nz, ne, nubar, 0, pidx, pn, pnu, NULL);
+}
+
 int oracle_plasma3d_count(int nx, int ny, int nz, const double *ne)
 {
     return o3_plasma(nx, ny, nz, ne, ne, NULL, NULL, NULL);
+}
+
+/* Plasma points of the two-term 3D model (all four cells around the edge are
+ * plasma) and plasma cells (ne > 0). */
+int oracle_plasma3d_count_strict(int nx, int ny, int nz, const double *ne, int *ncell)
+{
+    size_t n = (size_t)nx * ny * nz;
+    int nc = 0;
+    for (size_t q = 0; q < n; ++q) nc += ne[q] > 0.0;
+    *ncell = nc;
+    return o3_plasma_ex(nx, ny, nz, ne, ne, 1, NULL, NULL, NULL, NULL);
+}
+
+/* E index and four cells of every plasma point, in the order df stores them */
+int oracle_plasma3d_map(int nx, int ny, int nz, const double *ne, int strict, int *pidx, int *pcell)
+{
+    int np = o3_plasma_ex(nx, ny, nz, ne, ne, strict, NULL, NULL, NULL, NULL);
+    double *tmp = malloc(sizeof(double) * 2 * (np > 0 ? np : 1));
+    o3_plasma_ex(nx, ny, nz, ne, ne, strict, pidx, tmp, tmp + (np > 0 ? np : 1), pcell);
+    free(tmp);
+    return np;
 }
 
 int oracle_run3d(int nx, int ny, int nz, double dx, double courant,
@@ -829,9 +870,10 @@ int oracle_run3d(int nx, int ny, int nz, double dx, double courant,
                  double src_amp, double src_f, double src_tau, double src_t0,
                  long long step0, long long nsteps,
                  double *E, double *H, double *J, double *psi, double *df,
-                 int nprobe, const int *probe_idx, double *probe_out)
+                 int nprobe, const int *probe_idx, double *probe_out, int model)
 {
     if (nx < 2 || ny < 2 || nz < 2 || vdim < 1 || dx <= 0.0) return -1;
+    if (model < 0 || model > 2) return -1;
     if (courant <= 0.0 || courant > 1.0 / sqrt(3.0)) return -1;
     if (2 * ncpml >= nx || 2 * ncpml >= ny || 2 * ncpml >= nz) return -1;
     const double dt = courant * dx / K_C0;
@@ -870,11 +912,38 @@ int oracle_run3d(int nx, int ny, int nz, double dx, double courant,
     const double *bez = pr[2][0], *aez = pr[2][1], *kez = pr[2][2];
     const double *bhz = pr[2][3], *ahz = pr[2][4], *khz = pr[2][5];
 
-    int np = o3_plasma(nx, ny, nz, ne, nubar, NULL, NULL, NULL);
+    /* model 0: F1 on every E point with plasma around it, F0 frozen (J weights
+     * v^3, as printed); models 1 (F0 evolving) and 2 (held): the two-term model
+     * with F0 in the plasma cells, F1 on the points whose four cells are all
+     * plasma, face-averaged moment weights (the adjoint of the l = 0 flux form) */
+    const int tt = model != 0;
+    int np = o3_plasma_ex(nx, ny, nz, ne, nubar, tt, NULL, NULL, NULL, NULL);
     int *pidx = malloc(sizeof(int) * (np > 0 ? np : 1));
     double *pn = malloc(sizeof(double) * (np > 0 ? np : 1));
     double *pnu = malloc(sizeof(double) * (np > 0 ? np : 1));
-    o3_plasma(nx, ny, nz, ne, nubar, pidx, pn, pnu);
+    int *pcell = malloc(sizeof(int) * 4 * (np > 0 ? np : 1));
+    o3_plasma_ex(nx, ny, nz, ne, nubar, tt, pidx, pn, pnu, pcell);
+    double *w = malloc(sizeof(double) * vdim);
+    for (int k = 0; k < vdim; ++k) {
+        double lo = (double)k * gam, hi = (double)(k + 1) * gam;
+        w[k] = tt ? 0.5 * (lo * lo * lo + (k + 1 < vdim ? hi * hi * hi : 0.0))
+                  : v[k] * v[k] * v[k];
+    }
+    /* plasma cells (F0 rows after the np F1 rows of df), each cell's edges */
+    const size_t ncells = NX * NY * NZ;
+    int *crow = malloc(sizeof(int) * ncells);
+    int nc = 0;
+    for (size_t q = 0; q < ncells; ++q) crow[q] = (tt && ne[q] > 0.0) ? nc++ : -1;
+    int *cedge = malloc(sizeof(int) * 12 * (nc > 0 ? nc : 1));
+    int *cnt = calloc(nc > 0 ? nc : 1, sizeof(int));
+    for (int q = 0; q < 12 * nc; ++q) cedge[q] = -1;
+    for (int p = 0; tt && p < np; ++p)
+        for (int q = 0; q < 4; ++q) {
+            int r = crow[pcell[4 * p + q]];
+            cedge[12 * r + cnt[r]++] = p;
+        }
+    double *d0 = df + (size_t)np * vdim;
+    double *estash = malloc(sizeof(double) * (np > 0 ? np : 1));
 
     const double ch = dt / k_mu0(), ce = dt / K_EPS0;
 #define IEX(i, j, k) (((size_t)(k) * (NY + 1) + (j)) * NX + (i))
@@ -926,11 +995,23 @@ int oracle_run3d(int nx, int ny, int nz, double dx, double courant,
         for (int p = 0; p < np; ++p) {
             double *f = df + (size_t)p * vdim;
             double e = E[pidx[p]], acc = 0.0;
+            estash[p] = e;
+            /* two-term: F0 - n F0hat at the edge = mean over its four cells */
+            double dm[vdim > 0 ? vdim : 1];
+            for (int k = 0; k < vdim; ++k) {
+                dm[k] = 0.0;
+                if (tt)
+                    for (int q = 0; q < 4; ++q) dm[k] += 0.25 * d0[(size_t)crow[pcell[4 * p + q]] * vdim + k];
+            }
             for (int k = 0; k < vdim; ++k) {
                 double nu = pnu[p] * sh[k];
-                f[k] = ((2.0 - dt * nu) * f[k] + 2.0 * dt * (K_QE / K_ME) * pn[p] * dF0[k] * e)
-                       / (2.0 + dt * nu);
-                acc += v[k] * v[k] * v[k] * f[k];
+                double D = pn[p] * dF0[k];
+                if (tt) {
+                    double below = k > 0 ? dm[k - 1] : dm[0], above = k + 1 < vdim ? dm[k + 1] : 0.0;
+                    D += (above - below) / (2.0 * gam);
+                }
+                f[k] = ((2.0 - dt * nu) * f[k] + 2.0 * dt * (K_QE / K_ME) * e * D) / (2.0 + dt * nu);
+                acc += w[k] * f[k];
             }
             J[pidx[p]] = -K_QE * (4.0 * K_PI / 3.0) * gam * acc;
         }
@@ -979,6 +1060,30 @@ int oracle_run3d(int nx, int ny, int nz, double dx, double courant,
             if (src_kind == 2 && src_i >= 0 && src_i < nx && src_j > 0 && src_j < ny)
                 Ex[IEX(src_i, src_j, src_k)] += g;
         }
+        /* 6. two-term: F0^{n+1} of every plasma cell from the l = 0 equation, the
+         *    flux through each speed face summed over the cell's edges, each edge
+         *    handing a quarter of its Ebar F1 to each of its four cells */
+        if (model == 1) {
+            #pragma omp parallel for schedule(static)
+            for (int r = 0; r < nc; ++r) {
+                double G[vdim > 0 ? vdim : 1];
+                for (int k = 0; k < vdim; ++k) G[k] = 0.0;
+                for (int q = 0; q < 12; ++q) {
+                    int p = cedge[12 * r + q];
+                    if (p < 0) continue;
+                    double eb = 0.25 * 0.5 * (estash[p] + E[pidx[p]]);
+                    for (int k = 0; k < vdim; ++k) G[k] += eb * df[(size_t)p * vdim + k];
+                }
+                double phi_lo = 0.0;
+                for (int k = 0; k < vdim; ++k) {
+                    double vf = (double)(k + 1) * gam;
+                    double phi_hi = (k + 1 < vdim) ? vf * vf * 0.5 * (G[k] + G[k + 1]) : 0.0;
+                    d0[(size_t)r * vdim + k] += dt * (K_QE / (3.0 * K_ME)) * (phi_hi - phi_lo)
+                                                / (v[k] * v[k] * gam);
+                    phi_lo = phi_hi;
+                }
+            }
+        }
         for (int p = 0; p < nprobe; ++p) probe_out[s * nprobe + p] = E[probe_idx[p]];
     }
 #undef IEX
@@ -990,7 +1095,8 @@ int oracle_run3d(int nx, int ny, int nz, double dx, double courant,
     free(v); free(F0); free(dF0); free(sh);
     for (int a = 0; a < 3; ++a)
         for (int q = 0; q < 6; ++q) free(pr[a][q]);
-    free(pidx); free(pn); free(pnu);
+    free(pidx); free(pn); free(pnu); free(pcell); free(w); free(crow); free(cedge); free(cnt);
+    free(estash);
     return 0;
 }
 
