@@ -207,13 +207,24 @@ def bytes_3d(run, npoints, row):
             + npoints * (row * 8 + 12 + 12))
 
 
-def extra_3d(B, W, torch, steps=300):
+def bytes_3d_tt(run, npoints, ncells, row):
+    """bytes_3d plus the two-term traffic: the cells' F0 rows read by the kinetic update
+    and read + written by the l = 0 update, the points' F1 rows read by the latter with
+    their E^n, E^{n+1} and index (the stash of E^n written once) (FP32)."""
+    return bytes_3d(run, npoints, row) + ncells * row * 4 * 3 + npoints * (row * 4 + 16)
+
+
+def extra_3d(B, W, torch, steps=300, kinetic="linear"):
     """The paper's production model in 3D: the argon-style slab (Druyvesteyn F0, v_dim = 31
-    speeds, a 4 mm slab along z, sheet source, CPML on all faces) at 128 x 128 x 512."""
-    run = W.argon_slab_3d(nx=128, ny=128, nz=512, steps=steps)
+    speeds, a 4 mm slab along z, sheet source, CPML on all faces) at 128 x 128 x 512, with
+    F0 held (linear) or evolving in every plasma cell (two_term)."""
+    tt = kinetic == "two_term"
+    run = W.argon_slab_3d(nx=128, ny=128, nz=512, steps=steps, kinetic=kinetic)
     sim = B.Sim(run, precision=B.FP32)
     npoints = sim.closure_counts()[1]
-    log(f"argon3d: {run.nx}x{run.ny}x{run.nz}, plasma points {npoints}")
+    ncells = run.plasma_cells if tt else 0
+    key = "argon3d_two_term" if tt else "argon3d"
+    log(f"{key}: {run.nx}x{run.ny}x{run.nz}, plasma points {npoints}, cells {ncells}")
     sim.run(20)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -224,7 +235,7 @@ def extra_3d(B, W, torch, steps=300):
     sim.read(B.F_EX)
     sim.close()
     row = 32
-    by = bytes_3d(run, npoints, row)
+    by = bytes_3d_tt(run, npoints, ncells, row) if tt else bytes_3d(run, npoints, row)
     cells = run.nx * run.ny * run.nz
     # the FP64 oracle on the host, same workload, a few steps
     sys.path.insert(0, ROOT)
@@ -233,16 +244,17 @@ def extra_3d(B, W, torch, steps=300):
                  vmax_over_vth=run.vmax_over_vth, te_ev=run.te_ev, nu_model=run.nu_model,
                  f0_model=run.f0_model, ncpml=run.ncpml, src_kind=run.src_kind,
                  src_k=run.src_k, src_amp=run.src_amp, src_f=run.src_f, src_tau=run.src_tau,
-                 src_t0=run.src_t0)
+                 src_t0=run.src_t0, kinetic=kinetic)
     o.run(1)
     t0 = time.perf_counter()
     o.run(4)
     cdt = (time.perf_counter() - t0) / 4
     cpu = dict(kind="oracle", cores=threads(), nmcps=cells / cdt * 1e-6,
                updates_per_s=npoints * run.nv / cdt, sample="4 steps after 1, FP64")
-    return {"argon3d": dict(cpu_oracle=cpu, workload=f"3D Yee + CPML + speed-grid F1 (v_dim {run.nv}, Druyvesteyn), "
+    model = "two-term F1 + evolving F0" if tt else "speed-grid F1"
+    return {key: dict(cpu_oracle=cpu, workload=f"3D Yee + CPML + {model} (v_dim {run.nv}, Druyvesteyn), "
                                      f"{run.nx}x{run.ny}x{run.nz}, FP32, {steps} steps",
-                            plasma_points=npoints, cells=cells,
+                            plasma_points=npoints, plasma_cells=ncells, cells=cells,
                             updates_per_s=npoints * run.nv * steps / wall,
                             nmcps=cells * steps / wall * 1e-6,
                             ms_per_step=wall / steps * 1e3, kernel_ms_per_step=ms,
@@ -436,6 +448,7 @@ def extra_workloads(B, W, torch, autotune):
     out.update(closure_speedup(B, W, torch))
     out.update(extra_full(B, W, torch))
     out.update(extra_3d(B, W, torch))
+    out.update(extra_3d(B, W, torch, kinetic="two_term"))
     out.update(extra_twoterm(B, W, torch))
     return out
 
@@ -516,7 +529,7 @@ def main():
                          "step per launch)")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--only", choices=["c1l", "c2", "c3", "closure", "c4", "sweep", "full", "3d", "sweep3d",
-                             "twoterm"], default=None,
+                             "twoterm", "3dtt"], default=None,
                     help="run only one of the extra measurements (for profiling); c2 and c4 "
                          "take --steps steps")
     args = ap.parse_args()
@@ -542,6 +555,7 @@ def main():
                 "sweep": lambda: nmcps_sweep(B, W, torch),
                 "full": lambda: extra_full(B, W, torch, min(args.steps, 2000)),
                 "3d": lambda: extra_3d(B, W, torch, args.steps),
+                "3dtt": lambda: extra_3d(B, W, torch, args.steps, kinetic="two_term"),
                 "sweep3d": lambda: sweep_3d(B, W, torch),
                 "twoterm": lambda: extra_twoterm(B, W, torch, min(args.steps, 2000))}[args.only]
         print(json.dumps(only()), flush=True)

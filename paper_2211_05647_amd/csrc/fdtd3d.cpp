@@ -1,7 +1,7 @@
 // fdtd3d.cpp -- host side of the 3D path: validation, FP64 tables (speed grid, isotropic
 // F0 -- Maxwellian or Druyvesteyn -- and its derivative, collision shape, moment weights,
-// CPML profiles of section 2 per axis), plasma points, workspace layout, launches and
-// readback.
+// CPML profiles of section 2 per axis), plasma points (and, for the two-term model, plasma
+// cells with their edges), workspace layout, launches and readback.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -17,7 +17,8 @@ namespace fdtdp {
 
 template <class T>
 hipError_t launch_step3d_t(const void* run, int nx, int ny, int nz, int np, int kin_groups,
-                           int64_t step, hipStream_t stream);
+                           int nc, int f0_groups, bool two_term, int64_t step,
+                           hipStream_t stream);
 
 struct Host3D {
   fdtd_grid g;
@@ -25,37 +26,56 @@ struct Host3D {
   fdtd_source s;
   std::vector<double> ne, nu;
   int nx = 0, ny = 0, nz = 0, m = 0, vdim = 0, row = 0, np = 0, es = 4;
+  bool two_term = false;
+  int nc = 0;             // plasma cells (two-term model)
   double dt = 0;
   size_t nE[3] = {0, 0, 0}, nH[3] = {0, 0, 0};
   std::vector<int32_t> pidx;
   std::vector<double> pn, pnu;
+  std::vector<int32_t> pcell, cedge;   // [np][4] cell rows, [nc][12] edges (two-term)
   // workspace offsets
   size_t off_E = 0, off_H = 0, off_J = 0, off_psi[12] = {}, off_df = 0;
+  size_t off_f0 = 0, off_en = 0, off_status = 0;
   size_t off_pidx = 0, off_tau = 0, off_dens = 0, off_s = 0, off_b = 0, off_w = 0, off_prof = 0;
+  size_t off_pcell = 0, off_cedge = 0, off_c = 0, off_v2h = 0;
   size_t state_end = 0, total = 0;
-  int kin_groups = 1;
+  int kin_groups = 1, f0_groups = 1;
   alignas(16) unsigned char run[sizeof(Run3D<double>)];
 };
 
 namespace {
 
 // Plasma points: every E point that is updated (not on a face its component is
-// tangential to) and whose edge's four cells have a positive mean density.  Order: Ex
-// points, then Ey, then Ez, each in storage order.
+// tangential to) and whose edge's four cells have a positive mean density -- for the
+// two-term model, whose four cells all have a positive density, so that each point's F0
+// comes from plasma cells and hands its work back to them.  Order: Ex points, then Ey,
+// then Ez, each in storage order.  Plasma cells (two-term): ne > 0, in storage order.
 void find_points(Host3D* h) {
   const int nx = h->nx, ny = h->ny, nz = h->nz;
+  const size_t ncell = (size_t)nx * ny * nz;
+  std::vector<int32_t> crow;
+  h->nc = 0;
+  if (h->two_term) {
+    crow.assign(ncell, -1);
+    for (size_t q = 0; q < ncell; ++q)
+      if (h->ne[q] > 0.0) crow[q] = h->nc++;
+  }
   auto cell = [&](int i, int j, int k) { return ((size_t)k * ny + j) * nx + i; };
   auto add = [&](size_t at, size_t c0, size_t c1, size_t c2, size_t c3) {
     const double n = 0.25 * (h->ne[c0] + h->ne[c1] + h->ne[c2] + h->ne[c3]);
-    if (n > 0.0) {
+    const bool all = h->ne[c0] > 0.0 && h->ne[c1] > 0.0 && h->ne[c2] > 0.0 && h->ne[c3] > 0.0;
+    if (h->two_term ? all : n > 0.0) {
       h->pidx.push_back((int32_t)at);
       h->pn.push_back(n);
       h->pnu.push_back(0.25 * (h->nu[c0] + h->nu[c1] + h->nu[c2] + h->nu[c3]));
+      if (h->two_term)
+        for (size_t c : {c0, c1, c2, c3}) h->pcell.push_back(crow[c]);
     }
   };
   h->pidx.clear();
   h->pn.clear();
   h->pnu.clear();
+  h->pcell.clear();
   for (int k = 1; k < nz; ++k)
     for (int j = 1; j < ny; ++j)
       for (int i = 0; i < nx; ++i)
@@ -74,6 +94,15 @@ void find_points(Host3D* h) {
         add(oz + ((size_t)k * (ny + 1) + j) * (nx + 1) + i, cell(i - 1, j - 1, k),
             cell(i, j - 1, k), cell(i - 1, j, k), cell(i, j, k));
   h->np = (int)h->pidx.size();
+  h->cedge.assign((size_t)h->nc * 12, -1);
+  if (h->two_term) {
+    std::vector<int> fill(h->nc, 0);
+    for (int p = 0; p < h->np; ++p)
+      for (int q = 0; q < 4; ++q) {
+        const int r = h->pcell[(size_t)4 * p + q];
+        h->cedge[(size_t)12 * r + fill[r]++] = p;   // a cell has 12 edges
+      }
+  }
 }
 
 void layout(Host3D* h) {
@@ -89,6 +118,9 @@ void layout(Host3D* h) {
       Z * (Y + 1) * m2, m2 * (Y + 1) * X, (Z + 1) * m2 * X, (Z + 1) * Y * m2};
   for (int q = 0; q < 12; ++q) h->off_psi[q] = cv.take(sizes[q] * es);
   h->off_df = cv.take((size_t)std::max(h->np, 1) * h->row * es);
+  h->off_f0 = cv.take((size_t)std::max(h->nc, 1) * h->row * es);
+  h->off_en = cv.take((size_t)std::max(h->np, 1) * es);
+  h->off_status = cv.take(4);
   h->state_end = cv.size();
   h->off_pidx = cv.take((size_t)std::max(h->np, 1) * 4);
   h->off_tau = cv.take((size_t)std::max(h->np, 1) * es);
@@ -97,6 +129,10 @@ void layout(Host3D* h) {
   h->off_b = cv.take((size_t)h->row * es);
   h->off_w = cv.take((size_t)h->row * 8);
   h->off_prof = cv.take((size_t)6 * (X + Y + Z + 3) * es);
+  h->off_pcell = cv.take((size_t)std::max(h->np, 1) * 16);
+  h->off_cedge = cv.take((size_t)std::max(h->nc, 1) * 48);
+  h->off_c = cv.take((size_t)h->row * es);
+  h->off_v2h = cv.take((size_t)h->row * es);
   h->total = cv.size() + 256;
 }
 
@@ -111,6 +147,7 @@ Host3D* new_host(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s
   h->nz = g->nz;
   h->m = g->boundary == FDTD_BC_CPML ? g->cpml_cells : 0;
   h->vdim = p->nv;
+  h->two_term = p->kinetic == FDTD_KINETIC_TWO_TERM;
   h->es = g->precision == FDTD_FP64 ? 8 : 4;
   const int vpl = 16 / h->es;
   int row = vpl;
@@ -162,12 +199,22 @@ int upload(Host3D* h, char* ws, hipStream_t st) {
                                                   : -u * F0[k] / (vth * vth);
     mean += 4.0 * M_PI * gam * u * u * u * F0[k];
   }
-  std::vector<T> s(row, T(0)), b(row, T(0));
+  std::vector<T> s(row, T(0)), b(row, T(0)), cb(row, T(0)), v2h(row, T(0));
   std::vector<double> w(row, 0.0);
   for (int k = 0; k < vdim; ++k) {
     s[k] = (T)(h->p.nu_model == FDTD_NU_HARD_SPHERE ? v[k] / mean : 1.0);
     b[k] = (T)(2.0 * dt * (kQe / kMe) * dF0[k]);
-    w[k] = (dt / kEps0) * (-kQe) * (4.0 * M_PI / 3.0) * gam * v[k] * v[k] * v[k];
+    // linear model: v^3 as section 5.3 prints it; two-term: the mean of v^3 on the two
+    // speed faces (none at vmax), the adjoint of the l = 0 flux, so that the work the
+    // field does equals the heat the cells gain
+    const double lo = k * gam, hi = (k + 1) * gam;
+    const double cube = h->two_term ? 0.5 * (lo * lo * lo + (k + 1 < vdim ? hi * hi * hi : 0.0))
+                                    : v[k] * v[k] * v[k];
+    w[k] = (dt / kEps0) * (-kQe) * (4.0 * M_PI / 3.0) * gam * cube;
+    if (h->two_term) {
+      cb[k] = (T)(dt * kQe / (3.0 * kMe) / (v[k] * v[k] * gam));
+      v2h[k] = (T)(k + 1 < vdim ? 0.5 * hi * hi : 0.0);
+    }
   }
   std::vector<T> tau(h->np), dens(h->np);
   for (int q = 0; q < h->np; ++q) {
@@ -196,7 +243,11 @@ int upload(Host3D* h, char* ws, hipStream_t st) {
       (e = put(h->off_s, s.data(), row * sizeof(T))) ||
       (e = put(h->off_b, b.data(), row * sizeof(T))) ||
       (e = put(h->off_w, w.data(), row * 8)) ||
-      (e = put(h->off_prof, prof.data(), prof.size() * sizeof(T))))
+      (e = put(h->off_prof, prof.data(), prof.size() * sizeof(T))) ||
+      (e = put(h->off_pcell, h->pcell.data(), h->pcell.size() * 4)) ||
+      (e = put(h->off_cedge, h->cedge.data(), h->cedge.size() * 4)) ||
+      (e = put(h->off_c, cb.data(), row * sizeof(T))) ||
+      (e = put(h->off_v2h, v2h.data(), row * sizeof(T))))
     return hip_fail(e, "upload 3D tables");
 
   Run3D<T> R;
@@ -236,6 +287,16 @@ int upload(Host3D* h, char* ws, hipStream_t st) {
   R.src_tau = src.kind != FDTD_SRC_NONE ? src.tau_s : 1.0;
   R.src_t0 = src.t0_s;
   R.dt = dt;
+  R.f0 = reinterpret_cast<T*>(ws + h->off_f0);
+  R.en = reinterpret_cast<T*>(ws + h->off_en);
+  R.pcell = reinterpret_cast<const int32_t*>(ws + h->off_pcell);
+  R.cedge = reinterpret_cast<const int32_t*>(ws + h->off_cedge);
+  R.c_bin = reinterpret_cast<const T*>(ws + h->off_c);
+  R.v2h_bin = reinterpret_cast<const T*>(ws + h->off_v2h);
+  R.status = reinterpret_cast<int32_t*>(ws + h->off_status);
+  R.kc = (T)(dt * (kQe / kMe) / gam);
+  R.nc = h->nc;
+  R.model = h->two_term ? FDTD_KINETIC_TWO_TERM : FDTD_KINETIC_LINEAR;
   std::memcpy(h->run, &R, sizeof R);
   // lane groups of row / VPL lanes, 64 / that many rows per wavefront and pass
   int cus = 256, dev = 0;
@@ -243,6 +304,7 @@ int upload(Host3D* h, char* ws, hipStream_t st) {
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const int rows_per_block = 4 * (64 / (row / Vec<T>::n));
   h->kin_groups = std::max(1, std::min((h->np + rows_per_block - 1) / rows_per_block, 8 * cus));
+  h->f0_groups = std::max(1, std::min((h->nc + rows_per_block - 1) / rows_per_block, 8 * cus));
   return FDTD_OK;
 }
 
@@ -278,7 +340,10 @@ int validate_3d(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s)
   if (p->f0_model != FDTD_F0_MAXWELL && p->f0_model != FDTD_F0_DRUYVESTEYN)
     return fail(FDTD_EINVAL, "unknown f0_model %d", p->f0_model);
   if (p->closure != FDTD_CLOSURE_KINETIC) return fail(FDTD_EINVAL, "3D runs take the kinetic closure");
-  if (p->kinetic != FDTD_KINETIC_LINEAR) return fail(FDTD_EINVAL, "3D runs take the linear kinetic model");
+  if (p->kinetic != FDTD_KINETIC_LINEAR && p->kinetic != FDTD_KINETIC_TWO_TERM)
+    return fail(FDTD_EINVAL, "3D runs take the linear or the two-term kinetic model");
+  if (p->kinetic == FDTD_KINETIC_TWO_TERM && p->nv < 2)
+    return fail(FDTD_EINVAL, "the two-term model needs nv >= 2 speeds");
   if (!p->ne || !p->nu_mean) return fail(FDTD_EINVAL, "null ne or nu_mean");
   const size_t n = (size_t)g->nx * g->ny * g->nz;
   for (size_t k = 0; k < n; ++k) {
@@ -323,12 +388,18 @@ int upload_3d(Host3D* h, char* ws, hipStream_t stream) {
 
 hipError_t launch_step3d(Host3D* h, int64_t step, hipStream_t stream) {
   if (h->es == 8)
-    return launch_step3d_t<double>(h->run, h->nx, h->ny, h->nz, h->np, h->kin_groups, step,
-                                   stream);
-  return launch_step3d_t<float>(h->run, h->nx, h->ny, h->nz, h->np, h->kin_groups, step, stream);
+    return launch_step3d_t<double>(h->run, h->nx, h->ny, h->nz, h->np, h->kin_groups, h->nc,
+                                   h->f0_groups, h->two_term, step, stream);
+  return launch_step3d_t<float>(h->run, h->nx, h->ny, h->nz, h->np, h->kin_groups, h->nc,
+                                h->f0_groups, h->two_term, step, stream);
 }
 
 int points_3d(const Host3D* h) { return h->np; }
+
+int status_3d(Host3D* h, char* ws, int32_t* v) {
+  hipError_t e = hipMemcpy(v, ws + h->off_status, 4, hipMemcpyDeviceToHost);
+  return e ? hip_fail(e, "copy 3D status") : FDTD_OK;
+}
 
 int field_size_3d(const Host3D* h, int field, size_t* n) {
   switch (field) {
@@ -338,7 +409,7 @@ int field_size_3d(const Host3D* h, int field, size_t* n) {
     case FDTD_F_HX: *n = h->nH[0]; return FDTD_OK;
     case FDTD_F_HY: *n = h->nH[1]; return FDTD_OK;
     case FDTD_F_HZ: *n = h->nH[2]; return FDTD_OK;
-    case FDTD_F_DF: *n = (size_t)h->np * h->vdim; return FDTD_OK;
+    case FDTD_F_DF: *n = (size_t)(h->np + h->nc) * h->vdim; return FDTD_OK;
     default: return fail(FDTD_EINVAL, "field %d not defined on a 3D grid", field);
   }
 }
@@ -357,7 +428,7 @@ int read_3d(Host3D* h, char* ws, int field, double* dst) {
     case FDTD_F_JX: off = h->off_J; cnt = h->nE[0]; scale = kEps0 / h->dt; break;
     case FDTD_F_JY: off = h->off_J + h->nE[0] * es; cnt = h->nE[1]; scale = kEps0 / h->dt; break;
     case FDTD_F_JZ: off = h->off_J + (h->nE[0] + h->nE[1]) * es; cnt = h->nE[2]; scale = kEps0 / h->dt; break;
-    case FDTD_F_DF: off = h->off_df; cnt = (size_t)h->np * h->row; break;
+    case FDTD_F_DF: off = h->off_df; cnt = (size_t)h->np * h->row; break;   // then F0 rows
     default: return fail(FDTD_EINVAL, "field %d not defined on a 3D grid", field);
   }
   std::vector<char> buf(std::max<size_t>(cnt, 1) * es);
@@ -372,6 +443,19 @@ int read_3d(Host3D* h, char* ws, int field, double* dst) {
     for (int q = 0; q < h->np; ++q)
       for (int k = 0; k < h->vdim; ++k)
         dst[(size_t)q * h->vdim + k] = val((size_t)q * h->row + k);
+    if (h->nc > 0) {
+      const size_t n0 = (size_t)h->nc * h->row;
+      std::vector<char> b0(n0 * es);
+      hipError_t e = hipMemcpy(b0.data(), ws + h->off_f0, n0 * es, hipMemcpyDeviceToHost);
+      if (e) return hip_fail(e, "copy 3D F0");
+      double* d = dst + (size_t)h->np * h->vdim;
+      for (int c = 0; c < h->nc; ++c)
+        for (int k = 0; k < h->vdim; ++k) {
+          const size_t q = (size_t)c * h->row + k;
+          d[(size_t)c * h->vdim + k] =
+              es == 8 ? reinterpret_cast<double*>(b0.data())[q] : reinterpret_cast<float*>(b0.data())[q];
+        }
+    }
   } else {
     for (size_t k = 0; k < cnt; ++k) dst[k] = val(k) * scale;
   }

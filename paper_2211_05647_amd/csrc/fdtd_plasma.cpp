@@ -1225,13 +1225,18 @@ int fdtd_plasma_closure_counts(fdtd_plasma* h, int64_t* closure_cells, int64_t* 
 
 int fdtd_plasma_run_status(fdtd_plasma* h, int32_t run, int32_t* status) {
   if (!h || !status) return fail(FDTD_EINVAL, "null argument");
-  if (h->dims != 1) { *status = 0; return FDTD_OK; }
+  if (h->dims == 2) { *status = 0; return FDTD_OK; }
   if (run < 0 || run >= h->nruns) return fail(FDTD_ERANGE, "run out of range");
   hipError_t e = hipStreamSynchronize(h->stream);
   if (e) return hip_fail(e, "synchronise");
   int32_t v = 0;
-  e = hipMemcpy(&v, h->ws + h->status_off + 4 * (size_t)run, 4, hipMemcpyDeviceToHost);
-  if (e) return hip_fail(e, "copy status");
+  if (h->dims == 3) {
+    const int rc = status_3d(h->h3, h->ws, &v);
+    if (rc) return rc;
+  } else {
+    e = hipMemcpy(&v, h->ws + h->status_off + 4 * (size_t)run, 4, hipMemcpyDeviceToHost);
+    if (e) return hip_fail(e, "copy status");
+  }
   *status = v ? FDTD_ENUMERIC : FDTD_OK;
   if (v & 2) fail(FDTD_ENUMERIC, "run %d: a field broke the velocity CFL limit", run);
   else if (v & 1) fail(FDTD_ENUMERIC, "run %d: non-finite field", run);

@@ -113,6 +113,7 @@ Host3D* make_3d(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s,
 int upload_3d(Host3D* h, char* ws, hipStream_t stream);
 hipError_t launch_step3d(Host3D* h, int64_t step, hipStream_t stream);
 int points_3d(const Host3D* h);
+int status_3d(Host3D* h, char* ws, int32_t* v);
 int field_size_3d(const Host3D* h, int field, size_t* n);
 int read_3d(Host3D* h, char* ws, int field, double* dst);
 void destroy_3d(Host3D* h);

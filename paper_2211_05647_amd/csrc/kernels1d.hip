@@ -445,7 +445,8 @@ __device__ __forceinline__ void kinetic_tile_tt(const Run1D<T>& R, const T* eloc
           const T sv = lane_at(s[m], v);
           const T r = cn_recip(fma(tau, sv, T(2)));
           const T fv = lane_at(f[m], v);
-          const T drive = fma(kE, dr - dl, lane_at(b[m], v) * nE);
+          const T drive =
+              lane_at(cf[m], v) != T(0) ? fma(kE, dr - dl, lane_at(b[m], v) * nE) : T(0);
           const T t = fma(-(tau2 * sv), fv, drive);
           const T fn = fma(t, r, fv);
           lane_at(f[m], v) = fn;

@@ -1,14 +1,16 @@
 // kernels3d.hip -- one leap-frog step of the 3D Yee cube coupled to the speed-grid F1 of
 // every plasma point (arXiv 2211.05647, section 2 in its 3D form and section 5.3).
 //
-// Three launches per step, in the order of the method:
+// Three launches per step (four with F0 evolving), in the order of the method:
 //   k_h3d    H^{n+1/2} of the three components (one thread per lattice point), with the
 //            CPML memory of each derivative inside its layer;
 //   k_kin3d  F1 of every plasma point driven by its E component at t^n (Crank-Nicolson in
 //            the collision term) and the FP64 moment J = -e (4 pi / 3) gam sum v^3 F1,
 //            one lane group per point row;
 //   k_e3d    E^{n+1} = E^n + S curl H - J with the CPML memory, the soft source at t^{n+1}
-//            (the kinetic launch subtracts J at the plasma points, in place).
+//            (the kinetic launch subtracts J at the plasma points, in place);
+//   k_f0_3d  two-term model only: F0 of every plasma cell from the l = 0 equation (the
+//            kinetic launch is then k_kin3d_tt, whose F1 drive includes F0's change).
 // Tangential E on the outer faces is never written (PEC backing of the layer).
 #include "common.h"
 
@@ -184,6 +186,152 @@ __global__ __launch_bounds__(256) void k_kin3d(const Run3D<T> R) {
   }
 }
 
+// Two-term model (section 5.1 expansion with F0 evolving, section 5.3 speed grid): the F1
+// drive adds the speed derivative of F0 - n F0hat, taken as the central difference of the
+// mean of the four cells around the point's edge (even across v = 0, zero beyond vmax);
+// the moment takes the face-averaged weights of w_bin.  E^n is kept for the l = 0 update.
+template <class T>
+__global__ __launch_bounds__(256) void k_kin3d_tt(const Run3D<T> R) {
+  using V = typename Vec<T>::type;
+  constexpr int VPL = Vec<T>::n;
+  const int lane = threadIdx.x & 63;
+  const int lpc = R.row / VPL;             // power of two, <= 64
+  const int cpw = 64 / lpc;
+  const int sub = lane / lpc, li = lane - sub * lpc;
+  const int nxt = sub * lpc + ((li + 1) & (lpc - 1));
+  const int prv = sub * lpc + ((li - 1) & (lpc - 1));
+  const bool first_lane = li == 0, last_lane = li == lpc - 1;
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int nwave = (gridDim.x * blockDim.x) >> 6;
+  V s = reinterpret_cast<const V*>(R.s_bin)[li];
+  V b = reinterpret_cast<const V*>(R.b_bin)[li];
+  V cf = reinterpret_cast<const V*>(R.c_bin)[li];   // 0 marks the padding
+  double w[VPL];
+#pragma unroll
+  for (int v = 0; v < VPL; ++v) w[v] = R.w_bin[li * VPL + v];
+  const T kd = R.kc;
+  V* __restrict__ dfv = reinterpret_cast<V*>(R.df);
+  const V* __restrict__ d0v = reinterpret_cast<const V*>(R.f0);
+  const T* E = R.Ex;   // Ex, Ey, Ez are contiguous
+  T* Ee = R.Ex;
+  T* __restrict__ J = R.Jx;
+  for (int base = wave * cpw; base < R.np; base += nwave * cpw) {
+    const int p = base + sub;
+    const bool live = p < R.np;
+    int at = 0;
+    T tau = T(0), ne = T(0), Ev = T(0);
+    V f, dm;
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) lane_at(f, v) = lane_at(dm, v) = T(0);
+    if (live) {
+      at = R.pidx[p];
+      tau = R.tau[p];
+      ne = R.dens[p];
+      Ev = E[at];
+      f = dfv[(size_t)p * lpc + li];
+      const int4 c4 = reinterpret_cast<const int4*>(R.pcell)[p];
+      V d0 = d0v[(size_t)c4.x * lpc + li], d1 = d0v[(size_t)c4.y * lpc + li];
+      V d2 = d0v[(size_t)c4.z * lpc + li], d3 = d0v[(size_t)c4.w * lpc + li];
+#pragma unroll
+      for (int v = 0; v < VPL; ++v)
+        lane_at(dm, v) = T(0.25) * ((lane_at(d0, v) + lane_at(d1, v)) + (lane_at(d2, v) + lane_at(d3, v)));
+    }
+    const T nd = __shfl(lane_at(dm, 0), nxt);
+    const T pd = __shfl(lane_at(dm, VPL - 1), prv);
+    const T nE = ne * Ev, kE = kd * Ev, tau2 = tau + tau;
+    // the explicit exchange between F0 and F1 needs (e/m) |E| dt / gam <= 1
+    if (live && first_lane && !(fabs(kE) <= T(1))) atomicOr(R.status, 2);
+    double acc = 0.0;
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) {
+      const T dr = v + 1 < VPL ? lane_at(dm, v + 1 < VPL ? v + 1 : v) : (last_lane ? T(0) : nd);
+      const T dl = v > 0 ? lane_at(dm, v > 0 ? v - 1 : 0) : (first_lane ? lane_at(dm, 0) : pd);
+      const T sv = lane_at(s, v);
+      const T r = cn_recip(fma(tau, sv, T(2)));
+      const T fv = lane_at(f, v);
+      const T drive = lane_at(cf, v) != T(0) ? fma(kE, dr - dl, lane_at(b, v) * nE) : T(0);
+      const T t = fma(-(tau2 * sv), fv, drive);
+      const T fn = fma(t, r, fv);
+      lane_at(f, v) = fn;
+      acc = fma(w[v], (double)fn, acc);
+    }
+    if (live) dfv[(size_t)p * lpc + li] = f;
+    double a1[1] = {acc};
+    int which = 0;
+    const double tot = group_reduce<1>(a1, lpc, li, which);
+    if (live && li == 0) {
+      const T jv = (T)tot;
+      R.en[p] = Ev;
+      J[at] = jv;
+      Ee[at] = Ev - jv;
+    }
+  }
+}
+
+// l = 0 update of every plasma cell, after the E launch: G_k = sum over the cell's plasma
+// edges of Ebar F1_k / 4 (Ebar = (E^n + E^{n+1}) / 2, F1 at n+1/2), the flux through each
+// inner speed face v^2 (G_k + G_{k+1}) / 2 (none through v = 0 or vmax), and
+// F0 += dt (e / 3m) (flux above - flux below) / (v_k^2 gam).  Each cell gathers its own
+// edges, so the result does not depend on the order work-groups run in.
+template <class T>
+__global__ __launch_bounds__(256) void k_f0_3d(const Run3D<T> R) {
+  using V = typename Vec<T>::type;
+  constexpr int VPL = Vec<T>::n;
+  const int lane = threadIdx.x & 63;
+  const int lpc = R.row / VPL;
+  const int cpw = 64 / lpc;
+  const int sub = lane / lpc, li = lane - sub * lpc;
+  const int nxt = sub * lpc + ((li + 1) & (lpc - 1));
+  const int prv = sub * lpc + ((li - 1) & (lpc - 1));
+  const bool first_lane = li == 0, last_lane = li == lpc - 1;
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int nwave = (gridDim.x * blockDim.x) >> 6;
+  V cf = reinterpret_cast<const V*>(R.c_bin)[li];
+  V vh = reinterpret_cast<const V*>(R.v2h_bin)[li];
+  const V* __restrict__ dfv = reinterpret_cast<const V*>(R.df);
+  V* __restrict__ d0v = reinterpret_cast<V*>(R.f0);
+  const T* E = R.Ex;
+  for (int base = wave * cpw; base < R.nc; base += nwave * cpw) {
+    const int c = base + sub;
+    const bool live = c < R.nc;
+    V g;
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) lane_at(g, v) = T(0);
+    if (live) {
+      const int4* ce = reinterpret_cast<const int4*>(R.cedge) + (size_t)c * 3;
+      const int4 q0 = ce[0], q1 = ce[1], q2 = ce[2];
+      const int edge[12] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
+                            q2.x, q2.y, q2.z, q2.w};
+#pragma unroll
+      for (int q = 0; q < 12; ++q) {
+        const int p = edge[q];
+        if (p < 0) continue;
+        const T eb = T(0.125) * (R.en[p] + E[R.pidx[p]]);
+        V f = dfv[(size_t)p * lpc + li];
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) lane_at(g, v) = fma(eb, lane_at(f, v), lane_at(g, v));
+      }
+    }
+    const T ng = __shfl(lane_at(g, 0), nxt);
+    T ph[VPL];
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) {
+      const T gr = v + 1 < VPL ? lane_at(g, v + 1 < VPL ? v + 1 : v) : (last_lane ? T(0) : ng);
+      ph[v] = lane_at(vh, v) * (lane_at(g, v) + gr);   // 0 on the top face and beyond
+    }
+    const T pl0 = __shfl(ph[VPL - 1], prv);
+    if (live) {
+      V d = d0v[(size_t)c * lpc + li];
+#pragma unroll
+      for (int v = 0; v < VPL; ++v) {
+        const T pl = v > 0 ? ph[v > 0 ? v - 1 : 0] : (first_lane ? T(0) : pl0);
+        lane_at(d, v) = fma(lane_at(cf, v), ph[v] - pl, lane_at(d, v));
+      }
+      d0v[(size_t)c * lpc + li] = d;
+    }
+  }
+}
+
 // E^{n+1} = E^n + S curl H (the kinetic launch has already taken J^{n+1/2} off E^n at
 // the plasma points); every operand loaded before any arithmetic, as in k_h3d.
 template <class T>
@@ -262,20 +410,26 @@ __global__ __launch_bounds__(256) void k_e3d(const Run3D<T> R, int64_t step) {
 
 template <class T>
 hipError_t launch_step3d_t(const void* run, int nx, int ny, int nz, int np, int kin_groups,
-                           int64_t step, hipStream_t stream) {
+                           int nc, int f0_groups, bool two_term, int64_t step,
+                           hipStream_t stream) {
   const Run3D<T>& R = *static_cast<const Run3D<T>*>(run);
   const int tiles = ((nx + 1) * (ny + 1) + 255) / 256;
   const int blocks = (tiles * (nz + 1) + kXcds - 1) / kXcds * kXcds;
   const dim3 grid(blocks);
   hipLaunchKernelGGL(k_h3d<T>, grid, dim3(256), 0, stream, R);
-  if (np > 0) hipLaunchKernelGGL(k_kin3d<T>, dim3(kin_groups), dim3(256), 0, stream, R);
+  if (np > 0) {
+    if (two_term) hipLaunchKernelGGL(k_kin3d_tt<T>, dim3(kin_groups), dim3(256), 0, stream, R);
+    else hipLaunchKernelGGL(k_kin3d<T>, dim3(kin_groups), dim3(256), 0, stream, R);
+  }
   hipLaunchKernelGGL(k_e3d<T>, grid, dim3(256), 0, stream, R, step);
+  if (two_term && nc > 0 && np > 0)
+    hipLaunchKernelGGL(k_f0_3d<T>, dim3(f0_groups), dim3(256), 0, stream, R);
   return hipGetLastError();
 }
 
-template hipError_t launch_step3d_t<float>(const void*, int, int, int, int, int, int64_t,
-                                           hipStream_t);
-template hipError_t launch_step3d_t<double>(const void*, int, int, int, int, int, int64_t,
-                                            hipStream_t);
+template hipError_t launch_step3d_t<float>(const void*, int, int, int, int, int, int, int, bool,
+                                           int64_t, hipStream_t);
+template hipError_t launch_step3d_t<double>(const void*, int, int, int, int, int, int, int, bool,
+                                            int64_t, hipStream_t);
 
 }  // namespace fdtdp

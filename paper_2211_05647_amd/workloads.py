@@ -268,6 +268,7 @@ class Run3D:
     nu_model: str = "hard_sphere"
     f0_model: str = "druyvesteyn"
     ncpml: int = 8
+    kinetic: str = "linear"   # or "two_term" (F0 of every plasma cell evolving)
     meta: dict = field(default_factory=dict)
 
     @property
@@ -289,7 +290,7 @@ def argon_nubar(te_ev=ARGON_TE, f0="druyvesteyn"):
 
 
 def argon_slab_3d(nx=64, ny=64, nz=256, nv=31, steps=1200, slab_mm=4.0, ncpml=8,
-                  f0="druyvesteyn", name="argon3d") -> Run3D:
+                  f0="druyvesteyn", name="argon3d", kinetic="linear") -> Run3D:
     """The paper's 3D slab: air, a slab_mm plasma slab along z starting at the middle of
     the box, air; a sheet source of Ex (a plane wave along z) 12 cells inside the low z
     layer; CPML on all faces; density 1e19 m^-3 with +-5 % seeded cell-to-cell texture."""
@@ -303,7 +304,7 @@ def argon_slab_3d(nx=64, ny=64, nz=256, nv=31, steps=1200, slab_mm=4.0, ncpml=8,
     p = dict(src_amp=1.0, src_f=20e9, src_tau=48e-12, src_t0=217e-12)
     return Run3D(name=name, nx=nx, ny=ny, nz=nz, nv=nv, ne=ne, nubar=nu, src_kind=1, src_i=0,
                  src_j=0, src_k=ncpml + 4, steps=steps, ncpml=ncpml, f0_model=f0,
-                 meta=dict(slab=(k0, k1)), **p)
+                 kinetic=kinetic, meta=dict(slab=(k0, k1)), **p)
 
 
 def argon_line_1d(nv=31, kinetic="two_term", f0="druyvesteyn", slab_mm=4.0,

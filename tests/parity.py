@@ -63,12 +63,12 @@ def oracle_3d(run):
                     nu_model=run.nu_model, f0_model=run.f0_model, ncpml=run.ncpml,
                     src_kind=run.src_kind, src_i=run.src_i, src_j=run.src_j, src_k=run.src_k,
                     src_amp=run.src_amp, src_f=run.src_f, src_tau=run.src_tau,
-                    src_t0=run.src_t0)
+                    src_t0=run.src_t0, kinetic=run.kinetic)
 
 
 def space_time_3d(sim, orc, nsteps, every):
     """Snapshots after every ``every`` steps from both sides: E, H and J (all three
-    components each) and the F1 rows.  Returns {name: (gpu, oracle)} of stacked arrays."""
+    components each) and the F1 rows (then, for the two-term model, the cells' F0 rows).  Returns {name: (gpu, oracle)} of stacked arrays."""
     from paper_2211_05647_amd import binding as B
     out = {k: ([], []) for k in ("E", "H", "J", "DF")}
     done = 0

@@ -1,0 +1,124 @@
+"""GPU parity of the 3D two-term model (the paper's production representation with F0 of
+every plasma cell evolving under the l = 0 equation) against the FP64 oracle, through the
+C ABI.  Tolerances as for the other models: FP64 storage <= 1e-12 relative L2, FP32
+storage <= 1e-5 relative L2 over space and time."""
+import numpy as np
+import pytest
+
+from paper_2211_05647_amd import binding as B
+from paper_2211_05647_amd import workloads as W
+from parity import oracle_3d, rel_l2, space_time_3d
+
+pytestmark = pytest.mark.gpu
+
+
+def _banner(msg):
+    print(f"[gpu-twoterm3d] {msg}", flush=True)
+
+
+def _slab(nx=20, ny=18, nz=48, nv=31, f0="druyvesteyn", ncpml=6, steps=420, amp=3e4):
+    """The argon slab in a small box, driven hard enough that F0 visibly widens."""
+    run = W.argon_slab_3d(nx=nx, ny=ny, nz=nz, nv=nv, steps=steps, ncpml=ncpml, f0=f0,
+                          kinetic="two_term")
+    run.src_amp = amp
+    return run
+
+
+def _check(run, prec, tol, every=60):
+    sim = B.Sim(run, precision=prec)
+    orc = oracle_3d(run)
+    assert sim.closure_counts()[1] == orc.npoints > 0 and orc.ncells > 0
+    snaps = space_time_3d(sim, orc, run.steps, every)
+    eta0 = 376.730313668
+    ge, oe = snaps["E"]
+    gh, oh = snaps["H"]
+    snaps["EM"] = (np.concatenate([ge, eta0 * gh], axis=1), np.concatenate([oe, eta0 * oh], axis=1))
+    gd, od = snaps["DF"]
+    cut = orc.npoints * orc.vdim
+    snaps["F1"] = (gd[:, :cut], od[:, :cut])
+    snaps["F0"] = (gd[:, cut:], od[:, cut:])
+    for name in ("E", "EM", "J", "F1", "F0"):
+        g, o = snaps[name]
+        err = rel_l2(g, o)
+        _banner(f"  {name} space-time rel L2 = {err:.3e}")
+        assert err <= tol, name
+    assert np.abs(orc.f0_rows()).max() > 0          # F0 has moved
+    assert sim.run_status(0) == 0
+    sim.close()
+    return orc
+
+
+@pytest.mark.parametrize("prec,tol", [(B.FP64, 1e-12), (B.FP32, 1e-5)])
+def test_argon_slab_two_term_parity(gpu_lib, prec, tol):
+    """The paper's slab (Druyvesteyn F0, v_dim = 31, hard-sphere nu), CPML on every face:
+    E, H, J, F1 of the points and F0 of the cells over space and time."""
+    _banner(f"argon slab two-term prec={prec}")
+    _check(_slab(), prec, tol)
+
+
+@pytest.mark.parametrize("nv", [2, 8, 64])
+def test_two_term_speed_grids(gpu_lib, nv):
+    """Other speed counts (rows of 4 .. 64 bins: lanes per row 1 .. 16), the Maxwellian F0
+    with constant nu, a ragged box, a PEC box with a point source inside a plasma block
+    whose edges hold points on some faces only."""
+    run = _slab(nx=17, ny=13, nz=41, nv=nv, f0="maxwell", ncpml=5, steps=400)
+    run.nu_model = "const"
+    for prec, tol in ((B.FP64, 1e-12), (B.FP32, 1e-5)):
+        _banner(f"nv={nv} prec={prec}")
+        _check(run, prec, tol)
+    run = _slab(nx=16, ny=15, nz=22, nv=nv, ncpml=0, steps=300)
+    run.ne[:] = 0.0
+    run.ne[4:18, 3:12, 4:13] = W.ARGON_NE
+    run.src_kind, run.src_i, run.src_j, run.src_k = 2, 7, 7, 6
+    run.src_t0, run.src_tau = 60e-12, 20e-12
+    for prec, tol in ((B.FP64, 1e-12), (B.FP32, 1e-5)):
+        _banner(f"nv={nv} pec point prec={prec}")
+        _check(run, prec, tol, every=50)
+
+
+def test_two_term_differs_from_the_linear_model(gpu_lib):
+    """On the same drive the evolving F0 (and the strict point set) changes the field past
+    the slab by far more than the FP32 bar."""
+    a = _slab(steps=420)
+    b = _slab(steps=420)
+    b.kinetic = "linear"
+    sa, sb = B.Sim(a, precision=B.FP32), B.Sim(b, precision=B.FP32)
+    sa.run(a.steps)
+    sb.run(b.steps)
+    ea, eb = sa.read(B.F_EX), sb.read(B.F_EX)
+    assert rel_l2(ea, eb) > 1e-3
+    sa.close(); sb.close()
+
+
+def test_two_term_resume_is_bitwise(gpu_lib):
+    """Save after k steps, run on; load into a fresh handle and run the same steps: fields,
+    F1 and F0 agree to the bit (F0, E^n and the status word are part of the state)."""
+    run = _slab(steps=300)
+    a = B.Sim(run, precision=B.FP32)
+    a.run(150)
+    blob = a.save_state()
+    a.run(150)
+    b = B.Sim(run, precision=B.FP32)
+    b.load_state(blob)
+    for n in (1, 49, 100):
+        b.run(n)
+    for f in (B.F_EX, B.F_EY, B.F_EZ, B.F_HX, B.F_JX, B.F_DF):
+        assert np.array_equal(a.read(f), b.read(f))
+    a.close(); b.close()
+
+
+def test_two_term_3d_cfl_flagged_and_rejections(gpu_lib):
+    """A field with (e/m) |E| dt / gam > 1 sets the run status; the full-distribution model
+    and a one-speed grid are refused in 3D."""
+    run = _slab(steps=300, amp=3e7)
+    sim = B.Sim(run, precision=B.FP64)
+    sim.run(run.steps)
+    assert sim.run_status(0) != 0
+    sim.close()
+    bad = _slab(steps=10)
+    bad.kinetic = "full"
+    with pytest.raises(B.FdtdError):
+        B.Sim(bad, precision=B.FP32)
+    bad = _slab(steps=10, nv=1)
+    with pytest.raises(B.FdtdError):
+        B.Sim(bad, precision=B.FP32)
