@@ -78,7 +78,9 @@ enum fdtd_f0_model { FDTD_F0_MAXWELL = 0, FDTD_F0_DRUYVESTEYN = 1 };
  *   FDTD_F_HY [nz][ny+1][nx] at (i+1/2, j, k+1/2), FDTD_F_HZ [nz+1][ny][nx] at (i+1/2, j+1/2, k),
  *   FDTD_F_JX / JY / JZ shaped like EX / EY / EZ,
  *   FDTD_F_DF [npoint][nv]: F1 on the speed grid (s^3/m^6) of every plasma point, the
- *             Ex points first, then Ey, then Ez, each in storage order. */
+ *             Ex points first, then Ey, then Ez, each in storage order; with the TWO_TERM
+ *             model followed by [ncell][nv] F0 - ne F0hat of every cell with ne > 0, in
+ *             storage order. */
 enum fdtd_field {
   FDTD_F_E = 0, FDTD_F_H = 1, FDTD_F_J = 2, FDTD_F_DF = 3,
   FDTD_F_EX = 4, FDTD_F_EY = 5, FDTD_F_HZ = 6, FDTD_F_JX = 7, FDTD_F_JY = 8,
@@ -118,7 +120,7 @@ typedef struct {
  * through +-vmax (electron number is kept exactly) and is explicit: each step needs
  * |(e/m) E dt / dv| <= 1, and a step that breaks it sets the run status (see
  * fdtd_plasma_run_status).  FULL runs are never temporally blocked.
- * TWO_TERM (1D single runs only): the paper's own representation, section 5.1's
+ * TWO_TERM (1D single runs and 3D grids): the paper's own representation, section 5.1's
  * expansion F = F0 + (v/|v|).F1 with its l = 0 and l = 1 equations on a speed grid of nv
  * speeds (2..256; the paper uses 31) v_k = (k + 1/2) vmax / nv, F0 (f0_model) evolving
  * under the l = 0 equation without streaming (elastic collisions only: their l = 0 term,
@@ -135,7 +137,12 @@ typedef struct {
  * in 2D with J = -e (4 pi / 3) (vmax / nv) sum v^3 F1.  f0_model (3D and the 1D TWO_TERM model): MAXWELL, or
  * DRUYVESTEYN, exp(-(v / vD)^4) with the Maxwellian's mean energy (3/2) e te_ev; either
  * normalised by 4 pi (vmax / nv) sum v^2 F0 = 1.  3D runs take the kinetic closure and
- * the linear model. */
+ * the LINEAR or the TWO_TERM model.  3D TWO_TERM (nv >= 2): F0 lives in every cell with
+ * ne > 0 and F1 only at the E points whose four cells all have ne > 0; an edge's F1
+ * drive takes the mean F0 of its four cells, and each cell's l = 0 update takes a
+ * quarter of E.F1 from each of its plasma edges (E time-centred), so the field energy
+ * J removes is exactly the heat the cells gain; the explicit-exchange limit and the
+ * run status are as in 1D.  Four launches per step instead of three. */
 typedef struct {
   const double *ne;
   const double *nu_mean;
@@ -211,7 +218,9 @@ int fdtd_plasma_read_taps(fdtd_plasma *h, int32_t run, double *dst, size_t dst_l
                           size_t *n_out);
 
 /* Per-run status after the last run: 0, or FDTD_ENUMERIC if that run produced a
- * non-finite E value (other runs of the batch are unaffected). */
+ * non-finite E value (1D; other runs of the batch are unaffected) or, with the FULL or
+ * TWO_TERM model (1D and 3D), broke the explicit velocity-exchange limit.  2D handles
+ * report 0.  Later steps do not clear the flag. */
 int fdtd_plasma_run_status(fdtd_plasma *h, int32_t run, int32_t *status);
 
 /* One leap-frog step (H, F1 and J, E, boundary, source), enqueued. */
