@@ -294,7 +294,8 @@ template <class T> struct Run3D {
   T* f0;                  // [nc][row] F0 - n F0hat of the plasma cells
   T* en;                  // [np] E^n of every plasma point, kept for the l = 0 update
   const int32_t* pcell;   // [np][4] F0 rows of the four cells around the point's edge
-  const int32_t* cedge;   // [nc][12] plasma points on the cell's edges, -1 for none
+  const int32_t* cedge;   // [nc][12][2] (plasma point, its E index) of the cell's edges,
+                          // (-1, 0) for an edge without one
   const T* c_bin;         // [row] dt (e / 3m) / (v_k^2 gam) (0 in the padding)
   const T* v2h_bin;       // [row] v_{k+1/2}^2 / 2 on the inner speed faces, else 0
   int32_t* status;        // |= 2 when the field breaks the explicit exchange limit

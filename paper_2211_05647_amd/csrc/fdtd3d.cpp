@@ -32,7 +32,7 @@ struct Host3D {
   size_t nE[3] = {0, 0, 0}, nH[3] = {0, 0, 0};
   std::vector<int32_t> pidx;
   std::vector<double> pn, pnu;
-  std::vector<int32_t> pcell, cedge;   // [np][4] cell rows, [nc][12] edges (two-term)
+  std::vector<int32_t> pcell, cedge;   // [np][4] cell rows, [nc][12][2] edges (two-term)
   // workspace offsets
   size_t off_E = 0, off_H = 0, off_J = 0, off_psi[12] = {}, off_df = 0;
   size_t off_f0 = 0, off_en = 0, off_status = 0;
@@ -94,13 +94,16 @@ void find_points(Host3D* h) {
         add(oz + ((size_t)k * (ny + 1) + j) * (nx + 1) + i, cell(i - 1, j - 1, k),
             cell(i, j - 1, k), cell(i - 1, j, k), cell(i, j, k));
   h->np = (int)h->pidx.size();
-  h->cedge.assign((size_t)h->nc * 12, -1);
+  h->cedge.assign((size_t)h->nc * 24, 0);
+  for (size_t q = 0; q < h->cedge.size(); q += 2) h->cedge[q] = -1;
   if (h->two_term) {
     std::vector<int> fill(h->nc, 0);
     for (int p = 0; p < h->np; ++p)
       for (int q = 0; q < 4; ++q) {
         const int r = h->pcell[(size_t)4 * p + q];
-        h->cedge[(size_t)12 * r + fill[r]++] = p;   // a cell has 12 edges
+        const size_t at = (size_t)24 * r + 2 * fill[r]++;   // a cell has 12 edges
+        h->cedge[at] = p;
+        h->cedge[at + 1] = h->pidx[p];
       }
   }
 }
@@ -130,7 +133,7 @@ void layout(Host3D* h) {
   h->off_w = cv.take((size_t)h->row * 8);
   h->off_prof = cv.take((size_t)6 * (X + Y + Z + 3) * es);
   h->off_pcell = cv.take((size_t)std::max(h->np, 1) * 16);
-  h->off_cedge = cv.take((size_t)std::max(h->nc, 1) * 48);
+  h->off_cedge = cv.take((size_t)std::max(h->nc, 1) * 96);
   h->off_c = cv.take((size_t)h->row * es);
   h->off_v2h = cv.take((size_t)h->row * es);
   h->total = cv.size() + 256;
@@ -304,7 +307,12 @@ int upload(Host3D* h, char* ws, hipStream_t st) {
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const int rows_per_block = 4 * (64 / (row / Vec<T>::n));
   h->kin_groups = std::max(1, std::min((h->np + rows_per_block - 1) / rows_per_block, 8 * cus));
+  // the two-term launches renumber their work-groups per XCD: a multiple of 8
   h->f0_groups = std::max(1, std::min((h->nc + rows_per_block - 1) / rows_per_block, 8 * cus));
+  if (h->two_term) {
+    h->kin_groups = (h->kin_groups + 7) / 8 * 8;
+    h->f0_groups = (h->f0_groups + 7) / 8 * 8;
+  }
   return FDTD_OK;
 }
 

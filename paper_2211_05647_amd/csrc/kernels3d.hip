@@ -60,6 +60,18 @@ __device__ __forceinline__ PlaneTile plane_tile(int nx, int ny, int nz) {
   return p;
 }
 
+// Global wavefront index of a row-per-lane-group launch whose grid is a multiple of
+// kXcds, with the work-groups renumbered so that each XCD walks a contiguous range of
+// rows per pass: neighbouring rows share cells (and cells share edges).  (Measured on
+// the 128 x 128 x 512 slab: within a few per cent of the plain numbering; the gathers'
+// reuse spans more rows than one pass of one XCD holds.)
+__device__ __forceinline__ int xcd_wave() {
+  const int per_xcd = gridDim.x / kXcds;
+  const int b = blockIdx.x;
+  const int logical = (b % kXcds) * per_xcd + b / kXcds;
+  return (logical * blockDim.x + threadIdx.x) >> 6;
+}
+
 // Every operand of the point's three components is loaded before any arithmetic (the
 // stores of one component would otherwise order the loads of the next behind them).
 template <class T>
@@ -201,7 +213,7 @@ __global__ __launch_bounds__(256) void k_kin3d_tt(const Run3D<T> R) {
   const int nxt = sub * lpc + ((li + 1) & (lpc - 1));
   const int prv = sub * lpc + ((li - 1) & (lpc - 1));
   const bool first_lane = li == 0, last_lane = li == lpc - 1;
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int wave = xcd_wave();
   const int nwave = (gridDim.x * blockDim.x) >> 6;
   V s = reinterpret_cast<const V*>(R.s_bin)[li];
   V b = reinterpret_cast<const V*>(R.b_bin)[li];
@@ -284,7 +296,7 @@ __global__ __launch_bounds__(256) void k_f0_3d(const Run3D<T> R) {
   const int nxt = sub * lpc + ((li + 1) & (lpc - 1));
   const int prv = sub * lpc + ((li - 1) & (lpc - 1));
   const bool first_lane = li == 0, last_lane = li == lpc - 1;
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int wave = xcd_wave();
   const int nwave = (gridDim.x * blockDim.x) >> 6;
   V cf = reinterpret_cast<const V*>(R.c_bin)[li];
   V vh = reinterpret_cast<const V*>(R.v2h_bin)[li];
@@ -298,15 +310,17 @@ __global__ __launch_bounds__(256) void k_f0_3d(const Run3D<T> R) {
 #pragma unroll
     for (int v = 0; v < VPL; ++v) lane_at(g, v) = T(0);
     if (live) {
-      const int4* ce = reinterpret_cast<const int4*>(R.cedge) + (size_t)c * 3;
-      const int4 q0 = ce[0], q1 = ce[1], q2 = ce[2];
-      const int edge[12] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
-                            q2.x, q2.y, q2.z, q2.w};
+      // (point, E index) of each of the 12 edges, read together
+      const int4* ce = reinterpret_cast<const int4*>(R.cedge) + (size_t)c * 6;
+      int4 q[6];
 #pragma unroll
-      for (int q = 0; q < 12; ++q) {
-        const int p = edge[q];
+      for (int u = 0; u < 6; ++u) q[u] = ce[u];
+#pragma unroll
+      for (int u = 0; u < 12; ++u) {
+        const int p = (u & 1) ? q[u >> 1].z : q[u >> 1].x;
+        const int at = (u & 1) ? q[u >> 1].w : q[u >> 1].y;
         if (p < 0) continue;
-        const T eb = T(0.125) * (R.en[p] + E[R.pidx[p]]);
+        const T eb = T(0.125) * (R.en[p] + E[at]);
         V f = dfv[(size_t)p * lpc + li];
 #pragma unroll
         for (int v = 0; v < VPL; ++v) lane_at(g, v) = fma(eb, lane_at(f, v), lane_at(g, v));
