@@ -208,10 +208,12 @@ def bytes_3d(run, npoints, row):
 
 
 def bytes_3d_tt(run, npoints, ncells, row):
-    """bytes_3d plus the two-term traffic: the cells' F0 rows read by the kinetic update
-    and read + written by the l = 0 update, the points' F1 rows read by the latter with
-    their E^n, E^{n+1} and index (the stash of E^n written once) (FP32)."""
-    return bytes_3d(run, npoints, row) + ncells * row * 4 * 3 + npoints * (row * 4 + 16)
+    """bytes_3d plus the two-term traffic (FP32): per plasma cell its F0 row read by the
+    kinetic update and read + written by the l = 0 update, and its 12 (point, E index)
+    pairs; per plasma point its four cell rows' indices and its E^n (written by the
+    kinetic update), and its F1 row, E^n and E^{n+1} read by the l = 0 update."""
+    return (bytes_3d(run, npoints, row) + ncells * (row * 4 * 3 + 96)
+            + npoints * (16 + 4 + row * 4 + 8))
 
 
 def extra_3d(B, W, torch, steps=300, kinetic="linear"):
