@@ -33,6 +33,7 @@ struct Host3D {
   std::vector<int32_t> pidx;
   std::vector<double> pn, pnu;
   std::vector<int32_t> pcell, cedge;   // [np][4] cell rows, [nc][12][2] edges (two-term)
+  std::vector<int32_t> doc;            // readback row of every stored point row
   // workspace offsets
   size_t off_E = 0, off_H = 0, off_J = 0, off_psi[12] = {}, off_df = 0;
   size_t off_f0 = 0, off_en = 0, off_status = 0;
@@ -49,7 +50,10 @@ namespace {
 // tangential to) and whose edge's four cells have a positive mean density -- for the
 // two-term model, whose four cells all have a positive density, so that each point's F0
 // comes from plasma cells and hands its work back to them.  Order: Ex points, then Ey,
-// then Ez, each in storage order.  Plasma cells (two-term): ne > 0, in storage order.
+// then Ez, each in storage order (the readback order).  The two-term model then stores
+// them by lattice site (k, j, i, component), so that neighbouring rows share cells and a
+// cell's 12 edges lie in two planes of sites; `doc` maps a stored row to its readback
+// row.  Plasma cells (two-term): ne > 0, in storage order.
 void find_points(Host3D* h) {
   const int nx = h->nx, ny = h->ny, nz = h->nz;
   const size_t ncell = (size_t)nx * ny * nz;
@@ -94,6 +98,42 @@ void find_points(Host3D* h) {
         add(oz + ((size_t)k * (ny + 1) + j) * (nx + 1) + i, cell(i - 1, j - 1, k),
             cell(i, j - 1, k), cell(i - 1, j, k), cell(i, j, k));
   h->np = (int)h->pidx.size();
+  h->doc.resize(h->np);
+  for (int p = 0; p < h->np; ++p) h->doc[p] = p;
+  if (h->two_term) {
+    // lattice site of each point: E index -> (component, i, j, k)
+    std::vector<int64_t> key(h->np);
+    const size_t X = nx, Y = ny;
+    for (int p = 0; p < h->np; ++p) {
+      size_t at = (size_t)h->pidx[p];
+      int c = 0;
+      size_t i, j, k;
+      if (at < h->nE[0]) {
+        i = at % X; j = (at / X) % (Y + 1); k = at / (X * (Y + 1));
+      } else if (at < h->nE[0] + h->nE[1]) {
+        at -= h->nE[0]; c = 1;
+        i = at % (X + 1); j = (at / (X + 1)) % Y; k = at / ((X + 1) * Y);
+      } else {
+        at -= h->nE[0] + h->nE[1]; c = 2;
+        i = at % (X + 1); j = (at / (X + 1)) % (Y + 1); k = at / ((X + 1) * (Y + 1));
+      }
+      key[p] = ((int64_t)((k * (Y + 1) + j) * (X + 1) + i)) * 3 + c;
+    }
+    std::stable_sort(h->doc.begin(), h->doc.end(), [&](int a, int b) { return key[a] < key[b]; });
+    std::vector<int32_t> pidx(h->np), pcell((size_t)4 * h->np);
+    std::vector<double> pn(h->np), pnu(h->np);
+    for (int q = 0; q < h->np; ++q) {
+      const int p = h->doc[q];
+      pidx[q] = h->pidx[p];
+      pn[q] = h->pn[p];
+      pnu[q] = h->pnu[p];
+      for (int u = 0; u < 4; ++u) pcell[(size_t)4 * q + u] = h->pcell[(size_t)4 * p + u];
+    }
+    h->pidx.swap(pidx);
+    h->pn.swap(pn);
+    h->pnu.swap(pnu);
+    h->pcell.swap(pcell);
+  }
   h->cedge.assign((size_t)h->nc * 24, 0);
   for (size_t q = 0; q < h->cedge.size(); q += 2) h->cedge[q] = -1;
   if (h->two_term) {
@@ -450,7 +490,7 @@ int read_3d(Host3D* h, char* ws, int field, double* dst) {
   if (field == FDTD_F_DF) {
     for (int q = 0; q < h->np; ++q)
       for (int k = 0; k < h->vdim; ++k)
-        dst[(size_t)q * h->vdim + k] = val((size_t)q * h->row + k);
+        dst[(size_t)h->doc[q] * h->vdim + k] = val((size_t)q * h->row + k);
     if (h->nc > 0) {
       const size_t n0 = (size_t)h->nc * h->row;
       std::vector<char> b0(n0 * es);

@@ -60,16 +60,27 @@ __device__ __forceinline__ PlaneTile plane_tile(int nx, int ny, int nz) {
   return p;
 }
 
-// Global wavefront index of a row-per-lane-group launch whose grid is a multiple of
-// kXcds, with the work-groups renumbered so that each XCD walks a contiguous range of
-// rows per pass: neighbouring rows share cells (and cells share edges).  (Measured on
-// the 128 x 128 x 512 slab: within a few per cent of the plain numbering; the gathers'
-// reuse spans more rows than one pass of one XCD holds.)
-__device__ __forceinline__ int xcd_wave() {
+// Rows of a row-per-lane-group launch (grid a multiple of kXcds): work-group b runs on
+// XCD b mod 8, so XCD x takes the x-th eighth of the rows and its wavefronts walk that
+// range together, cpw rows per wavefront and pass.  Neighbouring rows share cells (and
+// cells share edges), so a row's gathers then find what the rows before it loaded in the
+// same XCD's L2.
+struct RowSpan {
+  int first, stride, end;
+};
+
+__device__ __forceinline__ RowSpan xcd_rows(int nrows, int cpw) {
   const int per_xcd = gridDim.x / kXcds;
-  const int b = blockIdx.x;
-  const int logical = (b % kXcds) * per_xcd + b / kXcds;
-  return (logical * blockDim.x + threadIdx.x) >> 6;
+  const int x = blockIdx.x % kXcds;
+  const int waves = blockDim.x >> 6;
+  const int wave = (blockIdx.x / kXcds) * waves + (threadIdx.x >> 6);
+  const int span = (nrows + kXcds - 1) / kXcds;
+  const int lo = x * span;
+  RowSpan r;
+  r.first = lo + wave * cpw;
+  r.stride = per_xcd * waves * cpw;
+  r.end = min(nrows, lo + span);
+  return r;
 }
 
 // Every operand of the point's three components is loaded before any arithmetic (the
@@ -213,8 +224,6 @@ __global__ __launch_bounds__(256) void k_kin3d_tt(const Run3D<T> R) {
   const int nxt = sub * lpc + ((li + 1) & (lpc - 1));
   const int prv = sub * lpc + ((li - 1) & (lpc - 1));
   const bool first_lane = li == 0, last_lane = li == lpc - 1;
-  const int wave = xcd_wave();
-  const int nwave = (gridDim.x * blockDim.x) >> 6;
   V s = reinterpret_cast<const V*>(R.s_bin)[li];
   V b = reinterpret_cast<const V*>(R.b_bin)[li];
   V cf = reinterpret_cast<const V*>(R.c_bin)[li];   // 0 marks the padding
@@ -227,9 +236,10 @@ __global__ __launch_bounds__(256) void k_kin3d_tt(const Run3D<T> R) {
   const T* E = R.Ex;   // Ex, Ey, Ez are contiguous
   T* Ee = R.Ex;
   T* __restrict__ J = R.Jx;
-  for (int base = wave * cpw; base < R.np; base += nwave * cpw) {
+  const RowSpan rs = xcd_rows(R.np, cpw);
+  for (int base = rs.first; base < rs.end; base += rs.stride) {
     const int p = base + sub;
-    const bool live = p < R.np;
+    const bool live = p < rs.end;
     int at = 0;
     T tau = T(0), ne = T(0), Ev = T(0);
     V f, dm;
@@ -296,16 +306,15 @@ __global__ __launch_bounds__(256) void k_f0_3d(const Run3D<T> R) {
   const int nxt = sub * lpc + ((li + 1) & (lpc - 1));
   const int prv = sub * lpc + ((li - 1) & (lpc - 1));
   const bool first_lane = li == 0, last_lane = li == lpc - 1;
-  const int wave = xcd_wave();
-  const int nwave = (gridDim.x * blockDim.x) >> 6;
   V cf = reinterpret_cast<const V*>(R.c_bin)[li];
   V vh = reinterpret_cast<const V*>(R.v2h_bin)[li];
   const V* __restrict__ dfv = reinterpret_cast<const V*>(R.df);
   V* __restrict__ d0v = reinterpret_cast<V*>(R.f0);
   const T* E = R.Ex;
-  for (int base = wave * cpw; base < R.nc; base += nwave * cpw) {
+  const RowSpan rs = xcd_rows(R.nc, cpw);
+  for (int base = rs.first; base < rs.end; base += rs.stride) {
     const int c = base + sub;
-    const bool live = c < R.nc;
+    const bool live = c < rs.end;
     V g;
 #pragma unroll
     for (int v = 0; v < VPL; ++v) lane_at(g, v) = T(0);
@@ -315,15 +324,24 @@ __global__ __launch_bounds__(256) void k_f0_3d(const Run3D<T> R) {
       int4 q[6];
 #pragma unroll
       for (int u = 0; u < 6; ++u) q[u] = ce[u];
+      // every edge's loads issued before any arithmetic (an edge without a plasma point
+      // reads point 0's row and the E index 0 and weighs them by zero)
+      T eb[12];
+      V f[12];
 #pragma unroll
       for (int u = 0; u < 12; ++u) {
         const int p = (u & 1) ? q[u >> 1].z : q[u >> 1].x;
         const int at = (u & 1) ? q[u >> 1].w : q[u >> 1].y;
-        if (p < 0) continue;
-        const T eb = T(0.125) * (R.en[p] + E[at]);
-        V f = dfv[(size_t)p * lpc + li];
+        const int ps = p < 0 ? 0 : p;
+        eb[u] = R.en[ps] + E[at];
+        if (p < 0) eb[u] = T(0);
+        f[u] = dfv[(size_t)ps * lpc + li];
+      }
 #pragma unroll
-        for (int v = 0; v < VPL; ++v) lane_at(g, v) = fma(eb, lane_at(f, v), lane_at(g, v));
+      for (int u = 0; u < 12; ++u) {
+        const T e8 = T(0.125) * eb[u];
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) lane_at(g, v) = fma(e8, lane_at(f[u], v), lane_at(g, v));
       }
     }
     const T ng = __shfl(lane_at(g, 0), nxt);
