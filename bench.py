@@ -32,11 +32,12 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # Arithmetic of one stored-bin update of F1 and its moment: FP32 dt*nu (mul), 2 + x (add),
 # reciprocal, 2x (add), drive (mul), two FMAs (4 flops); FP64 moment FMA (2 flops).
-# arithmetic of one stored-bin update in the blocked kernel: per step 2 dt nu (1), the drive
-# b n E (1), two FP32 FMAs (4) and the FP64 moment FMA (2); once per launch the
-# Crank-Nicolson factor 1/(2 + dt nu) (an FMA and a reciprocal, 3)
-FLOPS_PER_BIN_STEP = 8
-FLOPS_PER_BIN_LAUNCH = 3
+# arithmetic of one stored-bin update in the blocked kernel: per step two FP32 FMAs
+# (F1 + c n E, then + d F1: 4) and the FP64 moment FMA (2); once per launch the
+# Crank-Nicolson coefficients d = -2x / (2 + x) and c = b / (2 + x) (an FMA and a
+# reciprocal for 1 / (2 + x), two products for d, one for c: 6)
+FLOPS_PER_BIN_STEP = 6
+FLOPS_PER_BIN_LAUNCH = 6
 
 
 def kernel_hash(blocked=True):

@@ -82,19 +82,23 @@ __device__ __forceinline__ void kinetic_tile(const Run1D<T>& R, const T* eloc,
       acc[u] = 0.0;
       if (loc[u] >= 0) {
         const T nE = ne[u] * eloc[loc[u]];
-        const T tau2 = tau[u] + tau[u];
 #pragma unroll
         for (int m = 0; m < CPL; ++m) {
           if (m < cpl) {
 #pragma unroll
             for (int v = 0; v < VPL; ++v) {
-              // x = dt nu_j; F1' = ((2 - x) F1 + 2 dt (e/m) n dF0/dv E) / (2 + x), as an
-              // increment; 2 x = (2 dt nu_mean) s_j exactly
-              const T r = cn_recip(fma(tau[u], lane_at(s[m], v), T(2)));
-              const T x2 = tau2 * lane_at(s[m], v);
+              // x = dt nu_j; F1' = ((2 - x) F1 + 2 dt (e/m) n dF0/dv E) / (2 + x)
+              //              = F1 + d F1 + c n E, d = -2x / (2 + x), c = b / (2 + x):
+              // d keeps its full relative precision when x is small (1 - 2x / (2 + x)
+              // rounded once would bias the damping by half an ulp of 1 every step).
+              // 2 x = (2 dt nu_mean) s_j exactly; the blocked kernel forms d and c once
+              // per launch with these same operations, so the two agree to the bit.
+              const T sv = lane_at(s[m], v);
+              const T r = cn_recip(fma(tau[u], sv, T(2)));
+              const T d = -((tau[u] + tau[u]) * sv) * r;
+              const T c = lane_at(b[m], v) * r;
               const T fv = lane_at(f[u][m], v);
-              const T t = fma(-x2, fv, lane_at(b[m], v) * nE);
-              const T fn = fma(t, r, fv);
+              const T fn = fma(d, fv, fma(c, nE, fv));
               lane_at(f[u][m], v) = fn;
               acc[u] = fma(w[m][v], (double)fn, acc[u]);
             }

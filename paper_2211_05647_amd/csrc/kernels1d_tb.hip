@@ -29,10 +29,11 @@ constexpr int kTbBlock = 512;               // threads per work-group (8 wavefro
 constexpr int kTbWaves = kTbBlock / 64;
 constexpr int kTbU = 4;                     // rows per lane group per row slot group
 constexpr int kTbIters = 2;                 // row slot groups per lane group: 8 row
-                                            // slots with their Crank-Nicolson factors
-                                            // (108 VGPRs: two work-groups per compute
-                                            // unit; 12 slots that recompute the factor
-                                            // every step measured 10% slower)
+                                            // slots with their two Crank-Nicolson
+                                            // coefficients per bin (127 VGPRs: two
+                                            // work-groups per compute unit; 12 slots
+                                            // that recompute them every step measured
+                                            // 10% slower)
 constexpr int kTbRowsPerGroup = kTbIters * kTbU;
 
 template <int K, int LPC>
@@ -117,8 +118,9 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
       f[it][u] = cl < ncell ? dfr[(size_t)(tile.cell0 + cl) * lpc + li]
                             : make_float4(0.f, 0.f, 0.f, 0.f);
     }
-  // Crank-Nicolson factors 1/(2 + dt nu_j) of every row slot, the same for all K steps
-  float4 rr[kTbIters][kTbU];
+  // Crank-Nicolson coefficients of every row slot, the same for all K steps:
+  // F1' = F1 + d F1 + c n E, d = -2x / (2 + x), c = 2 dt (e/m) dF0/dv / (2 + x)
+  float4 dd[kTbIters][kTbU], cc[kTbIters][kTbU];
 #pragma unroll
   for (int it = 0; it < kTbIters; ++it)
 #pragma unroll
@@ -130,7 +132,11 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
       else
         tau = cl < ncell ? R.tau[tile.cell0 + cl] : 0.f;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) lane_at(rr[it][u], v) = cn_recip(fmaf(tau, lane_at(sb, v), 2.f));
+      for (int v = 0; v < 4; ++v) {
+        const float r = cn_recip(fmaf(tau, lane_at(sb, v), 2.f));
+        lane_at(dd[it][u], v) = -((tau + tau) * lane_at(sb, v)) * r;
+        lane_at(cc[it][u], v) = lane_at(bb, v) * r;
+      }
     }
 
   int lo = x0, hi = x1;    // nodes whose E is valid at the start of the sub-step
@@ -171,16 +177,11 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
         if (live) {
           loc[u] = lc;
           const float nE = ne * Es[p][lc];
-          const float tau2 = tau + tau;
           double a = 0.0;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            // x = dt nu_j; (2 x) = (2 dt nu_mean) s_j exactly
-            const float r = lane_at(rr[it][u], v);
-            const float x2 = tau2 * lane_at(sb, v);
             const float fv = lane_at(f[it][u], v);
-            const float t = fmaf(-x2, fv, lane_at(bb, v) * nE);
-            const float fn = fmaf(t, r, fv);
+            const float fn = fmaf(lane_at(dd[it][u], v), fv, fmaf(lane_at(cc[it][u], v), nE, fv));
             lane_at(f[it][u], v) = fn;
             a = fma(w[v], (double)fn, a);
           }
