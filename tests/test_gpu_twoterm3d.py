@@ -122,3 +122,29 @@ def test_two_term_3d_cfl_flagged_and_rejections(gpu_lib):
     bad = _slab(steps=10, nv=1)
     with pytest.raises(B.FdtdError):
         B.Sim(bad, precision=B.FP32)
+
+
+def test_benchmark_size_two_term_parity(gpu_lib):
+    """The benchmark's two-term workload at its full size (128 x 128 x 512, FP32, the timed
+    launch shape) for 800 steps, long enough for the pulse to cross into the slab, driven
+    at 3e4 V/m so F0 moves: E, J, F1 and F0 against the oracle on the same box."""
+    run = W.argon_slab_3d(nx=128, ny=128, nz=512, steps=800, kinetic="two_term")
+    run.src_amp = 3e4
+    _banner("argon slab two-term, full size, 800 steps")
+    sim = B.Sim(run, precision=B.FP32)
+    sim.run(run.steps)
+    orc = oracle_3d(run)
+    orc.run(run.steps)
+    assert sim.closure_counts()[1] == orc.npoints
+    ge = np.concatenate([sim.read(f) for f in (B.F_EX, B.F_EY, B.F_EZ)])
+    gj = np.concatenate([sim.read(f) for f in (B.F_JX, B.F_JY, B.F_JZ)])
+    gd = sim.read(B.F_DF)
+    cut = orc.npoints * orc.vdim
+    for name, g, o in (("E", ge, orc.E), ("J", gj, orc.J), ("F1", gd[:cut], orc.df[:cut]),
+                       ("F0", gd[cut:], orc.df[cut:])):
+        err = rel_l2(g, o)
+        _banner(f"  {name} rel L2 = {err:.3e}")
+        assert err <= 1e-5, name
+    assert np.abs(orc.f0_rows()).max() > 0 and np.abs(orc.J).max() > 0
+    assert sim.run_status(0) == 0
+    sim.close()
