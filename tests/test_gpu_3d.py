@@ -138,3 +138,24 @@ def test_benchmark_size_light_cone_parity(gpu_lib):
     assert np.abs(o).max() > 0
     assert np.all(ex[lim:] == 0.0) and np.all(ey[lim:] == 0.0) and np.all(ez[lim:] == 0.0)
     sim.close()
+
+
+def test_benchmark_size_parity_through_the_slab(gpu_lib):
+    """The benchmark's 3D workload at its full size (128 x 128 x 512, FP32, the launch shape
+    timed) for 800 steps, until the pulse is well into the slab: E, J and F1 against the
+    oracle on the same box."""
+    run = W.argon_slab_3d(nx=128, ny=128, nz=512, steps=800)
+    _banner("argon slab, full size, 800 steps")
+    sim = B.Sim(run, precision=B.FP32)
+    sim.run(run.steps)
+    orc = oracle_3d(run)
+    orc.run(run.steps)
+    assert sim.closure_counts()[1] == orc.npoints
+    ge = np.concatenate([sim.read(f) for f in (B.F_EX, B.F_EY, B.F_EZ)])
+    gj = np.concatenate([sim.read(f) for f in (B.F_JX, B.F_JY, B.F_JZ)])
+    for name, g, o in (("E", ge, orc.E), ("J", gj, orc.J), ("F1", sim.read(B.F_DF), orc.df)):
+        err = rel_l2(g, o)
+        _banner(f"  {name} rel L2 = {err:.3e}")
+        assert err <= 1e-5, name
+    assert np.abs(orc.J).max() > 0
+    sim.close()
