@@ -87,18 +87,26 @@ __device__ __forceinline__ void kinetic_tile(const Run1D<T>& R, const T* eloc,
           if (m < cpl) {
 #pragma unroll
             for (int v = 0; v < VPL; ++v) {
-              // x = dt nu_j; F1' = ((2 - x) F1 + 2 dt (e/m) n dF0/dv E) / (2 + x)
-              //              = F1 + d F1 + c n E, d = -2x / (2 + x), c = b / (2 + x):
-              // d keeps its full relative precision when x is small (1 - 2x / (2 + x)
-              // rounded once would bias the damping by half an ulp of 1 every step).
-              // 2 x = (2 dt nu_mean) s_j exactly; the blocked kernel forms d and c once
-              // per launch with these same operations, so the two agree to the bit.
+              // x = dt nu_j; F1' = ((2 - x) F1 + 2 dt (e/m) n dF0/dv E) / (2 + x), with
+              // 2 x = (2 dt nu_mean) s_j exactly.  Rows of 64 lanes (the blocked kernel
+              // keeps d and c per row there): F1 + d F1 + c n E, d = -2x / (2 + x),
+              // c = b / (2 + x); shorter rows: the increment form
+              // F1 + (b n E - 2x F1) / (2 + x).  Each form is the blocked kernel's for
+              // that row length, operation for operation, so the two agree to the bit;
+              // both keep the damping's relative precision when x is small.
               const T sv = lane_at(s[m], v);
               const T r = cn_recip(fma(tau[u], sv, T(2)));
-              const T d = -((tau[u] + tau[u]) * sv) * r;
-              const T c = lane_at(b[m], v) * r;
               const T fv = lane_at(f[u][m], v);
-              const T fn = fma(d, fv, fma(c, nE, fv));
+              T fn;
+              if (lpc == 64) {
+                const T d = -((tau[u] + tau[u]) * sv) * r;
+                const T c = lane_at(b[m], v) * r;
+                fn = fma(d, fv, fma(c, nE, fv));
+              } else {
+                const T x2 = (tau[u] + tau[u]) * sv;
+                const T t = fma(-x2, fv, lane_at(b[m], v) * nE);
+                fn = fma(t, r, fv);
+              }
               lane_at(f[u][m], v) = fn;
               acc[u] = fma(w[m][v], (double)fn, acc[u]);
             }

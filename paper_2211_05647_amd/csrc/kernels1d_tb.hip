@@ -118,9 +118,15 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
       f[it][u] = cl < ncell ? dfr[(size_t)(tile.cell0 + cl) * lpc + li]
                             : make_float4(0.f, 0.f, 0.f, 0.f);
     }
-  // Crank-Nicolson coefficients of every row slot, the same for all K steps:
-  // F1' = F1 + d F1 + c n E, d = -2x / (2 + x), c = 2 dt (e/m) dF0/dv / (2 + x)
-  float4 dd[kTbIters][kTbU], cc[kTbIters][kTbU];
+  // Crank-Nicolson coefficients of every row slot, the same for all K steps.  With one
+  // row per wavefront: F1' = F1 + d F1 + c n E, d = -2x / (2 + x), c = b / (2 + x), both
+  // kept (127 VGPRs).  With shorter rows the per-lane row scalars leave room for one
+  // coefficient only (the two would need 141 VGPRs: one work-group per compute unit), and
+  // the update keeps the increment form F1 + (b n E - 2x F1) / (2 + x) with 1 / (2 + x)
+  // kept.  The one-step kernel takes the same form for the same row length, so the two
+  // give the same bits.
+  constexpr bool kKeepDC = LPC == 64;
+  float4 dd[kTbIters][kTbU], cc[kKeepDC ? kTbIters : 1][kKeepDC ? kTbU : 1];
 #pragma unroll
   for (int it = 0; it < kTbIters; ++it)
 #pragma unroll
@@ -134,8 +140,12 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const float r = cn_recip(fmaf(tau, lane_at(sb, v), 2.f));
-        lane_at(dd[it][u], v) = -((tau + tau) * lane_at(sb, v)) * r;
-        lane_at(cc[it][u], v) = lane_at(bb, v) * r;
+        if constexpr (kKeepDC) {
+          lane_at(dd[it][u], v) = -((tau + tau) * lane_at(sb, v)) * r;
+          lane_at(cc[it][u], v) = lane_at(bb, v) * r;
+        } else {
+          lane_at(dd[it][u], v) = r;
+        }
       }
     }
 
@@ -181,7 +191,15 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const float fv = lane_at(f[it][u], v);
-            const float fn = fmaf(lane_at(dd[it][u], v), fv, fmaf(lane_at(cc[it][u], v), nE, fv));
+            float fn;
+            if constexpr (kKeepDC) {
+              fn = fmaf(lane_at(dd[it][u], v), fv, fmaf(lane_at(cc[it][u], v), nE, fv));
+            } else {
+              // x = dt nu_j; (2 x) = (2 dt nu_mean) s_j exactly
+              const float x2 = (tau + tau) * lane_at(sb, v);
+              const float t = fmaf(-x2, fv, lane_at(bb, v) * nE);
+              fn = fmaf(t, lane_at(dd[it][u], v), fv);
+            }
             lane_at(f[it][u], v) = fn;
             a = fma(w[v], (double)fn, a);
           }
