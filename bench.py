@@ -303,21 +303,36 @@ def sweep_3d(B, W, torch, cpu_budget_s=2.0):
 
 def extra_twoterm(B, W, torch, steps=2000):
     """The two-term model on the speed grid (F1 and an evolving F0, v_dim = 31, Druyvesteyn
-    F0 at 1 eV) on the large line's density and collision profile, FP32, one step per
-    launch; the FP64 oracle timed beside it on the same line."""
+    F0 at 1 eV) on the large line's density and collision profile, FP32: K steps per launch
+    (the default), and one step per launch beside it; the FP64 oracle timed beside them on
+    the same line."""
     run = W.c1(steps=steps)
     run.kinetic, run.nv, run.f0_model = "two_term", 31, "druyvesteyn"
     run.te_ev, run.vmax_over_vth = 1.0, 5.0
     log(f"two-term: Nx={run.nx} v_dim={run.nv} plasma cells={run.plasma_cells}")
-    wall, ms = time_single(run, B, torch, steps, 50)
+    info = {}
+    wall, ms = time_single(run, B, torch, steps, 50, 0, info)
+    kb, rows = info["time_block"], info["rows_per_launch"]
+    wall1, ms1 = time_single(run, B, torch, steps, 50, 0, None, 1)
     row = 32
-    by = run.plasma_cells * (2 * row * 4 * 2 + 12 + 4) + (run.nx + 1) * 4 * 5
+    # one step per launch: rows [F1 | F0] read and written, per-cell scalars, fields
+    by1 = run.plasma_cells * (2 * row * 4 * 2 + 12 + 4) + (run.nx + 1) * 4 * 5
+    # K steps per launch: rows read (owned + halo) with their scalars, owned rows written,
+    # fields once
+    byk = rows * (2 * row * 4 + 12) + run.plasma_cells * 2 * row * 4 + (run.nx + 1) * 4 * 5
+    by = byk / kb if kb > 1 else by1
     out = dict(workload=f"1D Yee + two-term speed-grid kinetic (F0 evolving), Nx={run.nx}, "
                         f"v_dim={run.nv}, FP32, {steps} steps",
-               kernel="k_step1d_tt<float>",
+               kernel=f"k_step1d_tb_tt<{kb}, 8>" if kb > 1 else "k_step1d_tt<float>",
+               steps_per_launch=kb,
                updates_per_s=run.plasma_cells * run.nv * steps / wall,
                ms_per_step=wall / steps * 1e3, kernel_ms_per_step=ms,
-               hbm_gbs=by / (ms * 1e-3) / 1e9, hbm_frac=by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+               hbm_gbs=by / (ms * 1e-3) / 1e9, hbm_frac=by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+               one_step_stream_equivalent_gbs=by1 / (ms * 1e-3) / 1e9,
+               one_step_per_launch=dict(kernel="k_step1d_tt<float>",
+                                        ms_per_step=wall1 / steps * 1e3, kernel_ms_per_step=ms1,
+                                        hbm_gbs=by1 / (ms1 * 1e-3) / 1e9,
+                                        hbm_frac=by1 / (ms1 * 1e-3) / 1e9 / HBM_PEAK_GBS))
     sys.path.insert(0, ROOT)
     from oracle.core import Oracle1D, threads
     o = Oracle1D(run.nx, run.dx, run.courant, run.ne, run.nubar, nv=run.nv,

@@ -474,10 +474,17 @@ int build_tb_tiles(fdtd_plasma* h) {
   h->tb_seg.clear();
   const int k = h->time_block;
   if (k < 3 || h->precision != FDTD_FP32) return FDTD_OK;
+  // plasma rows one work-group holds (the two-term kernel keeps two chunks per row)
+  auto rows_cap = [](const Host1D& x) {
+    return std::min(tb_block(), x.model == FDTD_KINETIC_TWO_TERM ? tb_tt_max_rows(x.half)
+                                                                  : tb_max_rows(x.half));
+  };
   for (int r = 0; r < h->nruns; ++r) {
     const Host1D& x = h->h1[r];
-    if (x.model != FDTD_KINETIC_LINEAR || !tb_supported(x.half)) return FDTD_OK;
-    if (std::min(tb_block(), tb_max_rows(x.half)) - 2 * k < 32) return FDTD_OK;
+    const bool ok = x.model == FDTD_KINETIC_LINEAR ? tb_supported(x.half)
+                    : x.model == FDTD_KINETIC_TWO_TERM ? tb_tt_supported(x.half) : false;
+    if (!ok) return FDTD_OK;
+    if (rows_cap(x) - 2 * k < 32) return FDTD_OK;
   }
   int cus = 256;
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
@@ -485,13 +492,15 @@ int build_tb_tiles(fdtd_plasma* h) {
   std::vector<Item> items;
   for (int r = 0; r < h->nruns; ++r) {
     const Host1D& x = h->h1[r];
-    const int cap = std::min(tb_block(), tb_max_rows(x.half));
+    const int cap = rows_cap(x);
     const int wmax = cap - 2 * k;
     const int nodes = x.nx + 1;
     int w = std::min(wmax, kTbBatchWidth);
     if (h->nruns == 1) {
       if (nodes < 4 * wmax) return FDTD_OK;   // too short to be worth blocking
-      const int conc = std::max(1, cus * tb_blocks_per_cu(k, x.half));
+      const int per_cu = x.model == FDTD_KINETIC_TWO_TERM ? tb_tt_blocks_per_cu(k, x.half)
+                                                          : tb_blocks_per_cu(k, x.half);
+      const int conc = std::max(1, cus * per_cu);
       const int rounds = (nodes + conc * wmax - 1) / (conc * wmax);
       w = std::max(32, std::min(wmax, (nodes + rounds * conc - 1) / (rounds * conc)));
     }
@@ -887,9 +896,13 @@ int fdtd_plasma_run(fdtd_plasma* h, int64_t nsteps) {
       int nblocked = 0;
       for (const TbSeg& sg : h->tb_seg) nblocked += count_ge(sg.limit, s + kb);
       if (nblocked < min_tiles) break;   // the tail of a batch: one step per launch
+      // two-term runs are single runs: run 0 decides (their blocked kernel leaves F0
+      // complete, so the one-step launches after it start with no l = 0 update pending)
+      const bool tt = h->h1[0].model == FDTD_KINETIC_TWO_TERM;
       for (const TbSeg& sg : h->tb_seg) {
         const int n = count_ge(sg.limit, s + kb);
-        e = launch_step1d_tb(h->ws + h->runs_off, tb + sg.off, n, s, kb, sg.half, h->stream);
+        e = tt ? launch_step1d_tb_tt(h->ws + h->runs_off, tb + sg.off, n, s, kb, sg.half, h->stream)
+               : launch_step1d_tb(h->ws + h->runs_off, tb + sg.off, n, s, kb, sg.half, h->stream);
         if (e) return hip_fail(e, "launch blocked step kernel");
       }
       if (h->nruns > 1) {

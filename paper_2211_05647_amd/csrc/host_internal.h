@@ -84,6 +84,12 @@ bool tb_supported(int half);             // stored bins per node the blocked ker
 int tb_block();                          // threads per work-group = largest extended range
 int tb_max_rows(int half);               // plasma rows one work-group holds
 int tb_blocks_per_cu(int k, int half);   // resident work-groups per compute unit
+// the same for the two-term model (half = speeds padded to a power of two)
+bool tb_tt_supported(int half);
+int tb_tt_max_rows(int half);
+int tb_tt_blocks_per_cu(int k, int half);
+hipError_t launch_step1d_tb_tt(const void* runs, const void* tiles, int ntiles, int64_t step,
+                               int k, int half, hipStream_t stream);
 hipError_t launch_step1d_tb(const void* runs, const void* tiles, int ntiles, int64_t step, int k,
                             int half, hipStream_t stream);
 

@@ -403,6 +403,9 @@ __device__ __forceinline__ void kinetic_tile_tt(const Run1D<T>& R, const T* eloc
     }
     // the deferred l = 0 update
     if (pending) {
+      // no contraction of v^2 (F1_k + F1_{k+1}) into the flux difference, so that the
+      // blocked kernel (which forms the same update) gives the same bits
+#pragma clang fp contract(off)
       T nf[CPL];
 #pragma unroll
       for (int m = 0; m < CPL; ++m) nf[m] = __shfl(lane_at(f[m], 0), nxt);

@@ -40,7 +40,7 @@ def test_two_term_parity(gpu_lib, nv, tile):
             run = _run(nv, f0=f0)
             run.nu_model = model
             _banner(f"nv={nv} tile={tile} prec={prec} f0={f0} nu={model}")
-            sim = B.Sim(run, precision=prec, tile=tile)
+            sim = B.Sim(run, precision=prec, tile=tile, time_block=1)   # one-step kernel
             assert sim.time_block() == 1
             orc = oracle_1d(run)
             snaps = []
@@ -102,4 +102,63 @@ def test_two_term_cfl_flagged(gpu_lib):
     sim = B.Sim(run, precision=B.FP64)
     sim.run(run.steps)
     assert sim.run_status(0) != 0
+    sim.close()
+
+
+def _long(nv, amp=3e4, steps=600):
+    """A line long enough for K steps per launch (5001 nodes; plasma over many tiles with
+    a vacuum gap), the source 90 nodes before the slab, so that the pulse is well inside
+    it within the run and F0 widens."""
+    run = W.slab_1d(5000, 8, 130, 4200, 1.1, 0.2, W.F_REF, 40, steps, te_ev=1.0)
+    run.ne[300:320] = 0.0
+    run.nv = nv
+    run.vmax_over_vth = 5.0
+    run.src_amp = amp
+    run.kinetic = "two_term"
+    run.f0_model = "druyvesteyn"
+    return run
+
+
+@pytest.mark.parametrize("nv", [31, 64])
+def test_blocked_two_term_is_bitwise_the_one_step_run(gpu_lib, nv):
+    """K steps per launch (rows of 32 or 64 speeds) against one step per launch: E, H, J,
+    F1 and F0 agree to the bit, also over calls that end inside a block (their last steps
+    run one per launch and end with the deferred l = 0 update)."""
+    run = _long(nv)
+    a = B.Sim(run, precision=B.FP32)
+    kb = a.time_block()
+    _banner(f"nv={nv}: {kb} steps per launch")
+    assert kb > 1
+    b = B.Sim(run, precision=B.FP32)
+    b.set_time_block(1)
+    assert b.time_block() == 1
+    for n in (kb * 20, 1, 2 * kb + 3, 250):
+        a.run(n)
+        b.run(n)
+        for f in (B.F_E, B.F_H, B.F_J, B.F_DF):
+            assert np.array_equal(a.read(f), b.read(f)), (n, f)
+    assert a.run_status(0) == 0
+    a.close(); b.close()
+
+
+@pytest.mark.parametrize("nv", [31, 64])
+def test_blocked_two_term_parity(gpu_lib, nv):
+    """The blocked run against the FP64 oracle: E over space and time, F1 and F0."""
+    run = _long(nv, steps=540)
+    sim = B.Sim(run, precision=B.FP32)
+    assert sim.time_block() > 1
+    orc = oracle_1d(run)
+    snaps = []
+    g, o, _, _ = space_time_1d(sim, orc, run.steps, 90, [], df_snaps=snaps)
+    err = rel_l2(g, o)
+    _banner(f"nv={nv} blocked: E space-time rel L2 = {err:.3e}")
+    assert err <= 1e-5
+    gd = np.concatenate([a.ravel() for a, _ in snaps])
+    od = np.concatenate([b.ravel() for _, b in snaps])
+    assert rel_l2(gd, od) <= 1e-5
+    rows = sim.read(B.F_DF).reshape(-1, 2 * nv)
+    assert np.abs(orc.df_rows()[:, nv:]).max() > 0
+    err0 = rel_l2(rows[:, nv:], orc.df_rows()[:, nv:])
+    _banner(f"  F0 - n F0hat rel L2 = {err0:.3e}")
+    assert err0 <= 1e-5
     sim.close()
