@@ -6,11 +6,12 @@
 //
 // A work-group owns nodes [node0, node1), holds the fields of the range extended by K
 // nodes per side in LDS and the [F1 | F0 - n F0hat] rows of its plasma nodes in registers,
-// and takes them through K steps.  Each sub-step: the F1 update (drive with the central
-// difference of F0 - n F0hat) and the FP64 moment; H and E; then the l = 0 update of F0
-// with E time-centred -- the update the one-step kernel defers to the start of the next
-// step, applied here at the end of this one with the same operands, so that F0 is complete
-// when the launch ends and a blocked run is bitwise the run of K one-step launches.
+// and takes them through K steps.  Each sub-step: the previous sub-step's l = 0 update of
+// F0 (E time-centred: E^{n-1} is still in the other LDS buffer), the F1 update (drive with
+// the central difference of F0 - n F0hat) and the FP64 moment; then H and E.  After the
+// last sub-step its l = 0 update is applied too, so that F0 is complete when the launch
+// ends; every update takes the operands of the one-step kernel's (which defers the l = 0
+// update the same way, across launches), so a blocked run is bitwise the one-step run.
 //
 // Requirements (checked on the host): FP32 storage, `half` (speeds padded to a power of
 // two) 32 or 64 (one 16-byte chunk of F1 and one of F0 per lane, 8 or 16 lanes per row), K
@@ -91,6 +92,30 @@ __global__ __launch_bounds__(kTtBlock) void k_step1d_tb_tt(const Run1D<float>* _
     d[u] = cl < ncell ? dfr[row + LPC + li] : make_float4(0.f, 0.f, 0.f, 0.f);
   }
 
+  // l = 0 update of slot u (F1 at n+1/2 in registers): F0 += c_k Ebar (phi_{k+1/2} -
+  // phi_{k-1/2}), phi = (v^2/2)(F1_k + F1_{k+1}) on the inner faces, Ebar = (E^n + E^{n+1})
+  // / 2 (eb); every lane takes part in the shuffles, `live` rows change
+  auto l0_update = [&](int u, bool live, float Eb) {
+    // no contraction of v^2 (F1_k + F1_{k+1}) into the flux difference, as in the
+    // one-step kernel
+#pragma clang fp contract(off)
+    const float nf = __shfl(f[u].x, nxt);
+    float ph[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float fr = v < 3 ? lane_at(f[u], v < 3 ? v + 1 : v) : (last_lane ? 0.f : nf);
+      ph[v] = lane_at(vh, v) * (lane_at(f[u], v) + fr);   // 0 on the top face
+    }
+    const float got = __shfl(ph[3], prv);
+    if (live) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const float pl = v > 0 ? ph[v > 0 ? v - 1 : 0] : (first_lane ? 0.f : got);
+        lane_at(d[u], v) = fmaf(lane_at(cf, v) * Eb, ph[v] - pl, lane_at(d[u], v));
+      }
+    }
+  };
+
   int lo = x0, hi = x1;
   const float S = R.S;
 #pragma unroll 1
@@ -99,6 +124,7 @@ __global__ __launch_bounds__(kTtBlock) void k_step1d_tb_tt(const Run1D<float>* _
     const int64_t gs = step + s;
     __syncthreads();
     asm volatile("" ::: "memory");
+    // the previous sub-step's l = 0 update (E^{n-1} is still in the other buffer), then
     // F1^{n+1/2} of the rows whose node holds a valid E^n, FP64 moment -> Js
 #pragma unroll
     for (int u = 0; u < kTtU; ++u) {
@@ -115,6 +141,7 @@ __global__ __launch_bounds__(kTtBlock) void k_step1d_tb_tt(const Run1D<float>* _
         ne = neS[cl];
         Ev = Es[p][lc];
       }
+      if (s > 0) l0_update(u, live, live ? 0.5f * (Es[p ^ 1][lc] + Ev) : 0.f);
       // d_{k+1} from the next lane, d_{k-1} from the previous one (every lane takes part)
       const float nd = __shfl(d[u].x, nxt);
       const float pd = __shfl(d[u].w, prv);
@@ -200,47 +227,26 @@ __global__ __launch_bounds__(kTtBlock) void k_step1d_tb_tt(const Run1D<float>* _
         }
       }
     }
-    __syncthreads();
-
-    // l = 0 update of the rows whose node holds a valid E^{n+1}:
-    // F0 += c_k Ebar (phi_{k+1/2} - phi_{k-1/2}), phi = (v^2/2)(F1_k + F1_{k+1}) on the
-    // inner faces, Ebar = (E^n + E^{n+1}) / 2, F1 at n+1/2
-#pragma unroll
-    for (int u = 0; u < kTtU; ++u) {
-      // no contraction of v^2 (F1_k + F1_{k+1}) into the flux difference, as in the
-      // one-step kernel
-#pragma clang fp contract(off)
-      const int cl = row_slot(u, wv, sub);
-      bool live = cl < ncell;
-      int lc = 0;
-      if (live) {
-        lc = locS[cl];
-        live = x0 + lc >= nlo && x0 + lc < nhi;
-      }
-      const float Eb = live ? 0.5f * (Es[p][lc] + Es[p ^ 1][lc]) : 0.f;
-      const float nf = __shfl(f[u].x, nxt);
-      float ph[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const float fr = v < 3 ? lane_at(f[u], v < 3 ? v + 1 : v) : (last_lane ? 0.f : nf);
-        ph[v] = lane_at(vh, v) * (lane_at(f[u], v) + fr);   // 0 on the top face
-      }
-      const float got = __shfl(ph[3], prv);
-      if (live) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const float pl = v > 0 ? ph[v > 0 ? v - 1 : 0] : (first_lane ? 0.f : got);
-          lane_at(d[u], v) = fmaf(lane_at(cf, v) * Eb, ph[v] - pl, lane_at(d[u], v));
-        }
-      }
-    }
     lo = nlo;
     hi = nhi;
   }
   __syncthreads();
 
-  // owned nodes and their rows back to HBM (the other field buffer)
+  // the last sub-step's l = 0 update: E^{n+K} in buffer pf, E^{n+K-1} in the other
   constexpr int pf = K & 1;
+#pragma unroll
+  for (int u = 0; u < kTtU; ++u) {
+    const int cl = row_slot(u, wv, sub);
+    bool live = cl < ncell;
+    int lc = 0;
+    if (live) {
+      lc = locS[cl];
+      live = x0 + lc >= lo && x0 + lc < hi;
+    }
+    l0_update(u, live, live ? 0.5f * (Es[pf ^ 1][lc] + Es[pf][lc]) : 0.f);
+  }
+
+  // owned nodes and their rows back to HBM (the other field buffer)
   if (i >= tile.node0 && i < tile.node1) {
     R.E[par ^ 1][i] = Es[pf][k];
     if (i < nx) R.H[par ^ 1][i] = Hs[pf][k];
