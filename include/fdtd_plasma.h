@@ -129,7 +129,8 @@ typedef struct {
  * v^3 over the bin's flux-carrying faces, which makes the field energy J removes exactly
  * the electrons' kinetic energy gain.  FDTD_F_DF then gives [ncell][2 nv]: F1, then
  * F0 - ne F0hat.  The exchange between F0 and F1 is explicit: a step with
- * (e/m) |E| dt / (vmax / nv) > 1 sets the run status.  Never temporally blocked.
+ * (e/m) |E| dt / (vmax / nv) > 1 sets the run status.  Temporally blocked as the LINEAR
+ * model is (fdtd_plasma_set_time_block) for 17..64 speeds.
  * 3D grids (the paper's production model, section 5.3): ne / nu_mean are per cell
  * [nz][ny][nx]; F1 is a vector on a speed grid of nv speeds (1..64; the paper uses 31)
  * v_k = (k + 1/2) vmax / nv, one component at every E point whose edge touches plasma (the
@@ -259,13 +260,15 @@ int fdtd_plasma_load_state(fdtd_plasma *h, const void *src, size_t len);
  * first step. */
 int fdtd_plasma_set_tiling(fdtd_plasma *h, int32_t tile, int32_t cells_per_group);
 
-/* Temporal blocking of a single 1D run in FP32 storage with Nv in {64, 128, 256, 512}:
+/* Temporal blocking of a single 1D run in FP32 storage with the LINEAR model and Nv in
+ * {64, 128, 256, 512}, or the TWO_TERM model with 17..64 speeds (rows padded to 32 or 64):
  * fdtd_plasma_run advances `steps` time steps per kernel launch (each work-group
- * recomputes a halo of `steps` nodes per side, so F1 crosses HBM once per `steps` steps)
- * and the remainder one step per launch.  steps = 1 turns it off; 3, 5, 7 and 9 are accepted.
- * Results are bitwise those of one-step launches (the kinetic step is local in space, see
- * section 5.2).  Default 7.  Other runs (FP64, batches, 2D, other Nv, lines too short to
- * cut into blocks) always step one step per launch; the call then only records the value.
+ * recomputes a halo of `steps` nodes per side, so F1 -- and F0 -- cross HBM once per
+ * `steps` steps) and the remainder one step per launch.  steps = 1 turns it off; 3, 5, 7
+ * and 9 are accepted.  Results are bitwise those of one-step launches (the kinetic step is
+ * local in space, see section 5.2).  Default 7.  Other runs (FP64, batches of the
+ * persistent mode, 2D, 3D, FULL, other speed counts, lines too short to cut into blocks)
+ * step one step per launch; the call then only records the value.
  * May be called between runs.  fdtd_plasma_time_block reports the steps per launch in
  * effect (1 when the run is not blocked) and, if rows_per_launch is not NULL, the number of
  * F1 rows one blocked launch reads (owned rows plus the halo rows it recomputes; 0 when
