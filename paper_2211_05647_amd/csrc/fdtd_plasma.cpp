@@ -204,6 +204,13 @@ struct fdtd_plasma {
   int ntbtiles = 0;
   int64_t tb_rows = 0;     // F1 rows one blocked pass reads (owned plus halo)
   std::vector<TbSeg> tb_seg;
+  // A blocked launch reads a run's rows from one copy and writes them to the other, so
+  // that no work-group reads halo rows a neighbour of the same launch has already
+  // advanced: each run's second copy sits df_delta bytes after its rows (the state
+  // region mirrored), df_cur[r] says which copy holds run r's current rows.  One-step
+  // launches, readback and saved states use the first copy (moved back when needed).
+  size_t df_delta = 0;
+  std::vector<uint8_t> df_cur;
   // probes
   int max_probes = 0, probe_cap = 0;
   size_t probe_off = 0;
@@ -249,6 +256,7 @@ size_t layout_1d(fdtd_plasma* h, const std::vector<RunSpec1D>& specs, int precis
     x.off_df = cv.take((size_t)std::max(x.ncell, 1) * x.row * es);
   }
   const size_t state_end = cv.size();
+  const size_t mirror_off = cv.take(state_end);   // second copy of the rows (blocked launches)
   const size_t probe_off = cv.take((size_t)std::max(max_probes, 1) * std::max(probe_cap, 1) * es);
   for (size_t r = 0; r < specs.size(); ++r) {
     Host1D& x = hs[r];
@@ -282,6 +290,8 @@ size_t layout_1d(fdtd_plasma* h, const std::vector<RunSpec1D>& specs, int precis
     h->status_off = status_off;
     h->state_off = 0;
     h->state_bytes = state_end;
+    h->df_delta = mirror_off;
+    h->df_cur.assign(specs.size(), 0);
     h->probe_off = probe_off;
     h->runs_off = runs_off;
     h->tiles_off = tiles_off;
@@ -856,6 +866,25 @@ int fdtd_plasma_create_batch(int32_t nruns, const fdtd_grid* grids, const fdtd_p
   return create_1d(nruns, grids, profiles, sources, steps, ntap, tap_nodes, dev, out, true);
 }
 
+// Move the rows of the runs whose current rows sit in the second copy back to the first
+// (every such run, or with below >= 0 those whose step limit is below `below`), on the
+// handle's stream.
+static int rows_home(fdtd_plasma* h, int64_t below) {
+  const size_t es = h->precision == FDTD_FP64 ? 8 : 4;
+  for (int r = 0; r < h->nruns; ++r) {
+    if (!h->df_cur[r] || (below >= 0 && h->specs[r].steps >= below)) continue;
+    const Host1D& x = h->h1[r];
+    const size_t bytes = (size_t)x.ncell * x.row * es;
+    if (bytes) {
+      hipError_t e = hipMemcpyAsync(h->ws + x.off_df, h->ws + x.off_df + h->df_delta, bytes,
+                                    hipMemcpyDeviceToDevice, h->stream);
+      if (e) return hip_fail(e, "move rows back");
+    }
+    h->df_cur[r] = 0;
+  }
+  return FDTD_OK;
+}
+
 int fdtd_plasma_step(fdtd_plasma* h) { return fdtd_plasma_run(h, 1); }
 
 int fdtd_plasma_run(fdtd_plasma* h, int64_t nsteps) {
@@ -867,6 +896,8 @@ int fdtd_plasma_run(fdtd_plasma* h, int64_t nsteps) {
   int64_t nsteps_loop = nsteps;
   if ((e = hipEventRecord(h->ev0, h->stream))) return hip_fail(e, "hipEventRecord");
   if (h->dims == 1 && h->nruns > 1 && h->batch_mode == 0) {
+    const int rc = rows_home(h, -1);
+    if (rc) return rc;
     e = launch_batch1d_persistent(h->ws + h->runs_off,
                                   reinterpret_cast<const int32_t*>(h->ws + h->order_off), h->nruns,
                                   reinterpret_cast<int32_t*>(h->ws + h->queue_off), h->step,
@@ -891,21 +922,38 @@ int fdtd_plasma_run(fdtd_plasma* h, int64_t nsteps) {
     int min_tiles = 256;   // fewer blocked work-groups than compute units: step instead
     hipDeviceGetAttribute(&min_tiles, hipDeviceAttributeMultiprocessorCount, h->device);
     if (h->nruns == 1) min_tiles = 1;
+    const int64_t delta = (int64_t)(h->df_delta / 4);   // FP32 elements
     for (; k0 + kb <= nsteps_loop; k0 += kb) {
       const int64_t s = h->step + k0;
       int nblocked = 0;
       for (const TbSeg& sg : h->tb_seg) nblocked += count_ge(sg.limit, s + kb);
       if (nblocked < min_tiles) break;   // the tail of a batch: one step per launch
+      // the runs of this pass (step limit >= s + K) have taken every earlier blocked pass,
+      // so their rows sit in the same copy
+      int cur = -1;
+      for (int r = 0; r < h->nruns; ++r) {
+        if (h->specs[r].steps < s + kb) continue;
+        if (cur >= 0 && cur != h->df_cur[r]) return fail(FDTD_ESTATE, "row copies out of step");
+        cur = h->df_cur[r];
+      }
+      const int64_t in_off = cur == 1 ? delta : 0, out_off = cur == 1 ? 0 : delta;
       // two-term runs are single runs: run 0 decides (their blocked kernel leaves F0
       // complete, so the one-step launches after it start with no l = 0 update pending)
       const bool tt = h->h1[0].model == FDTD_KINETIC_TWO_TERM;
       for (const TbSeg& sg : h->tb_seg) {
         const int n = count_ge(sg.limit, s + kb);
-        e = tt ? launch_step1d_tb_tt(h->ws + h->runs_off, tb + sg.off, n, s, kb, sg.half, h->stream)
-               : launch_step1d_tb(h->ws + h->runs_off, tb + sg.off, n, s, kb, sg.half, h->stream);
+        e = tt ? launch_step1d_tb_tt(h->ws + h->runs_off, tb + sg.off, n, s, kb, sg.half,
+                                     in_off, out_off, h->stream)
+               : launch_step1d_tb(h->ws + h->runs_off, tb + sg.off, n, s, kb, sg.half, in_off,
+                                  out_off, h->stream);
         if (e) return hip_fail(e, "launch blocked step kernel");
       }
+      for (int r = 0; r < h->nruns; ++r)
+        if (h->specs[r].steps >= s + kb) h->df_cur[r] ^= 1;
       if (h->nruns > 1) {
+        // runs ending inside the pass take their last steps one per launch, in place
+        const int rc = rows_home(h, s + kb);
+        if (rc) return rc;
         const int p1 = count_ge(h->tile_limit, s + kb), p2 = count_ge(h->tile_limit, s + 1);
         for (int64_t ss = s; p2 > p1 && ss < s + kb; ++ss) {
           const int n = count_ge(h->tile_limit, ss + 1) - p1;
@@ -914,6 +962,10 @@ int fdtd_plasma_run(fdtd_plasma* h, int64_t nsteps) {
         }
       }
     }
+  }
+  if (h->dims == 1 && k0 < nsteps_loop) {
+    const int rc = rows_home(h, -1);   // one-step launches work in place on the first copy
+    if (rc) return rc;
   }
   for (int64_t k = k0; k < nsteps_loop; ++k) {
     const int64_t s = h->step + k;
@@ -1020,7 +1072,10 @@ int fdtd_plasma_read_fields(fdtd_plasma* h, int32_t run, int32_t field, double* 
       case FDTD_F_E: off = x.off_E[par]; cnt = x.nx + 1; break;
       case FDTD_F_H: off = x.off_H[par]; cnt = x.nx; scale = 1.0 / kEta0; break;
       case FDTD_F_J: off = x.off_J; cnt = x.nx + 1; scale = kEps0 / x.dt; break;
-      case FDTD_F_DF: off = x.off_df; cnt = (size_t)x.ncell * x.row; break;
+      case FDTD_F_DF:
+        off = x.off_df + (h->df_cur[run] ? h->df_delta : 0);
+        cnt = (size_t)x.ncell * x.row;
+        break;
     }
     std::vector<char> buf(std::max<size_t>(cnt, 1) * es);
     if (cnt) {
@@ -1133,6 +1188,10 @@ int fdtd_plasma_save_state(fdtd_plasma* h, void* dst, size_t len) {
   int rc = fdtd_plasma_state_size(h, &need);
   if (rc) return rc;
   if (!dst || len < need) return fail(FDTD_ERANGE, "state buffer holds %zu bytes, need %zu", len, need);
+  if (h->dims == 1) {
+    rc = rows_home(h, -1);
+    if (rc) return rc;
+  }
   hipError_t e = hipStreamSynchronize(h->stream);
   if (e) return hip_fail(e, "synchronise");
   char* d = reinterpret_cast<char*>(dst);
@@ -1166,6 +1225,7 @@ int fdtd_plasma_load_state(fdtd_plasma* h, const void* src, size_t len) {
   if (e) return hip_fail(e, "copy state");
   h->step = step;
   h->started = true;
+  if (h->dims == 1) h->df_cur.assign(h->nruns, 0);
   return FDTD_OK;
 }
 

@@ -89,9 +89,12 @@ bool tb_tt_supported(int half);
 int tb_tt_max_rows(int half);
 int tb_tt_blocks_per_cu(int k, int half);
 hipError_t launch_step1d_tb_tt(const void* runs, const void* tiles, int ntiles, int64_t step,
-                               int k, int half, hipStream_t stream);
+                               int k, int half, int64_t in_off, int64_t out_off,
+                               hipStream_t stream);
+// K steps of the tiles; every run's rows are read at df + in_off and written at
+// df + out_off (elements), two distinct copies
 hipError_t launch_step1d_tb(const void* runs, const void* tiles, int ntiles, int64_t step, int k,
-                            int half, hipStream_t stream);
+                            int half, int64_t in_off, int64_t out_off, hipStream_t stream);
 
 // 2D TEz (fdtd2d.cpp / kernels2d.hip)
 struct Host2D;

@@ -10,7 +10,9 @@
 // registers -- while the range of valid nodes shrinks by one per step and side (not at
 // the line's ends, where the Mur update needs only nodes inside the line).  Only the owned
 // nodes and their F1 rows are written back.  F1 therefore crosses HBM once per K steps
-// (plus the halo rows), instead of once per step.
+// (plus the halo rows), instead of once per step.  The rows are read from one copy and
+// written to the other (in_off, out_off): a work-group that starts after its neighbour
+// has finished still reads that neighbour's rows as they were when the launch began.
 //
 // Every value is produced by the same arithmetic as the one-step kernel (the same
 // update functions, operand order, lane-to-bin mapping and pairing tree of the FP64
@@ -39,7 +41,8 @@ constexpr int kTbRowsPerGroup = kTbIters * kTbU;
 template <int K, int LPC>
 __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __restrict__ runs,
                                                         const Tile1D* __restrict__ tiles,
-                                                        int64_t step) {
+                                                        int64_t step, int64_t in_off,
+    int64_t out_off) {
   __shared__ float Es[2][kTbBlock];
   __shared__ float Hs[2][kTbBlock];
   __shared__ float Js[kTbBlock + 1];        // + a spare slot for rows without a valid E
@@ -94,7 +97,7 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
 #pragma unroll
   for (int v = 0; v < 4; ++v) w[v] = R.w_bin[li * 4 + v];
   float4 f[kTbIters][kTbU];
-  const float4* __restrict__ dfr = reinterpret_cast<const float4*>(R.df);
+  const float4* __restrict__ dfr = reinterpret_cast<const float4*>(R.df + in_off);
   // one row per wavefront (LPC = 64): lane q of these registers holds the scalars of the
   // wavefront's row slot q, read into scalar registers with v_readlane when needed
   int tab_loc = kTbBlock;
@@ -293,7 +296,7 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
   }
   // the row addresses are formed again here rather than kept live across the K steps
   asm volatile("" ::: "memory");
-  float4* __restrict__ dfw = reinterpret_cast<float4*>(R.df);
+  float4* __restrict__ dfw = reinterpret_cast<float4*>(R.df + out_off);
 #pragma unroll
   for (int it = 0; it < kTbIters; ++it)
 #pragma unroll
@@ -345,13 +348,13 @@ int tb_blocks_per_cu(int k, int half) {
 }
 
 template <int K>
-hipError_t launch_tb_k(const Run1D<float>* r, const Tile1D* t, int ntiles, int64_t step, int half,
+hipError_t launch_tb_k(const Run1D<float>* r, const Tile1D* t, int ntiles, int64_t step, int half, int64_t in_off, int64_t out_off,
                        hipStream_t stream) {
   switch (half) {
-    case 32: hipLaunchKernelGGL((k_step1d_tb<K, 8>), dim3(ntiles), dim3(kTbBlock), 0, stream, r, t, step); break;
-    case 64: hipLaunchKernelGGL((k_step1d_tb<K, 16>), dim3(ntiles), dim3(kTbBlock), 0, stream, r, t, step); break;
-    case 128: hipLaunchKernelGGL((k_step1d_tb<K, 32>), dim3(ntiles), dim3(kTbBlock), 0, stream, r, t, step); break;
-    case 256: hipLaunchKernelGGL((k_step1d_tb<K, 64>), dim3(ntiles), dim3(kTbBlock), 0, stream, r, t, step); break;
+    case 32: hipLaunchKernelGGL((k_step1d_tb<K, 8>), dim3(ntiles), dim3(kTbBlock), 0, stream, r, t, step, in_off, out_off); break;
+    case 64: hipLaunchKernelGGL((k_step1d_tb<K, 16>), dim3(ntiles), dim3(kTbBlock), 0, stream, r, t, step, in_off, out_off); break;
+    case 128: hipLaunchKernelGGL((k_step1d_tb<K, 32>), dim3(ntiles), dim3(kTbBlock), 0, stream, r, t, step, in_off, out_off); break;
+    case 256: hipLaunchKernelGGL((k_step1d_tb<K, 64>), dim3(ntiles), dim3(kTbBlock), 0, stream, r, t, step, in_off, out_off); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -359,15 +362,15 @@ hipError_t launch_tb_k(const Run1D<float>* r, const Tile1D* t, int ntiles, int64
 
 // K steps [step, step + K) of the tiles (every tile of one run, half = Nv/2 of that run).
 hipError_t launch_step1d_tb(const void* runs, const void* tiles, int ntiles, int64_t step, int k,
-                            int half, hipStream_t stream) {
+                            int half, int64_t in_off, int64_t out_off, hipStream_t stream) {
   if (ntiles <= 0) return hipSuccess;
   const Run1D<float>* r = static_cast<const Run1D<float>*>(runs);
   const Tile1D* t = static_cast<const Tile1D*>(tiles);
   switch (k) {
-    case 3: return launch_tb_k<3>(r, t, ntiles, step, half, stream);
-    case 5: return launch_tb_k<5>(r, t, ntiles, step, half, stream);
-    case 7: return launch_tb_k<7>(r, t, ntiles, step, half, stream);
-    case 9: return launch_tb_k<9>(r, t, ntiles, step, half, stream);
+    case 3: return launch_tb_k<3>(r, t, ntiles, step, half, in_off, out_off, stream);
+    case 5: return launch_tb_k<5>(r, t, ntiles, step, half, in_off, out_off, stream);
+    case 7: return launch_tb_k<7>(r, t, ntiles, step, half, in_off, out_off, stream);
+    case 9: return launch_tb_k<9>(r, t, ntiles, step, half, in_off, out_off, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -13,6 +13,9 @@
 // ends; every update takes the operands of the one-step kernel's (which defers the l = 0
 // update the same way, across launches), so a blocked run is bitwise the one-step run.
 //
+// As in the linear blocked kernel, rows are read from one copy and written to the other
+// (in_off, out_off), so that no work-group reads halo rows a neighbour already advanced.
+//
 // Requirements (checked on the host): FP32 storage, `half` (speeds padded to a power of
 // two) 32 or 64 (one 16-byte chunk of F1 and one of F0 per lane, 8 or 16 lanes per row), K
 // odd, extended ranges of at most kTtBlock nodes and tb_tt_max_rows(half) plasma nodes, no
@@ -29,7 +32,8 @@ constexpr int kTtU = 4;                     // row slots per lane group
 template <int K, int LPC>
 __global__ __launch_bounds__(kTtBlock) void k_step1d_tb_tt(const Run1D<float>* __restrict__ runs,
                                                            const Tile1D* __restrict__ tiles,
-                                                           int64_t step) {
+                                                           int64_t step, int64_t in_off,
+    int64_t out_off) {
   __shared__ float Es[2][kTtBlock];
   __shared__ float Hs[2][kTtBlock];
   __shared__ float Js[kTtBlock];
@@ -83,7 +87,7 @@ __global__ __launch_bounds__(kTtBlock) void k_step1d_tb_tt(const Run1D<float>* _
   for (int v = 0; v < 4; ++v) w[v] = R.w_bin[li * 4 + v];
   const float kd = R.kc;
   float4 f[kTtU], d[kTtU];
-  const float4* __restrict__ dfr = reinterpret_cast<const float4*>(R.df);
+  const float4* __restrict__ dfr = reinterpret_cast<const float4*>(R.df + in_off);
 #pragma unroll
   for (int u = 0; u < kTtU; ++u) {
     const int cl = row_slot(u, wv, sub);
@@ -252,7 +256,7 @@ __global__ __launch_bounds__(kTtBlock) void k_step1d_tb_tt(const Run1D<float>* _
     if (i < nx) R.H[par ^ 1][i] = Hs[pf][k];
     R.J[i] = Js[k];
   }
-  float4* __restrict__ dfw = reinterpret_cast<float4*>(R.df);
+  float4* __restrict__ dfw = reinterpret_cast<float4*>(R.df + out_off);
 #pragma unroll
   for (int u = 0; u < kTtU; ++u) {
     const int cl = row_slot(u, wv, sub);
@@ -292,10 +296,10 @@ int tb_tt_blocks_per_cu(int k, int half) {
 
 template <int K>
 hipError_t launch_tb_tt_k(const Run1D<float>* r, const Tile1D* t, int ntiles, int64_t step,
-                          int half, hipStream_t stream) {
+                          int half, int64_t in_off, int64_t out_off, hipStream_t stream) {
   switch (half) {
-    case 32: hipLaunchKernelGGL((k_step1d_tb_tt<K, 8>), dim3(ntiles), dim3(kTtBlock), 0, stream, r, t, step); break;
-    case 64: hipLaunchKernelGGL((k_step1d_tb_tt<K, 16>), dim3(ntiles), dim3(kTtBlock), 0, stream, r, t, step); break;
+    case 32: hipLaunchKernelGGL((k_step1d_tb_tt<K, 8>), dim3(ntiles), dim3(kTtBlock), 0, stream, r, t, step, in_off, out_off); break;
+    case 64: hipLaunchKernelGGL((k_step1d_tb_tt<K, 16>), dim3(ntiles), dim3(kTtBlock), 0, stream, r, t, step, in_off, out_off); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -303,15 +307,15 @@ hipError_t launch_tb_tt_k(const Run1D<float>* r, const Tile1D* t, int ntiles, in
 
 // K steps [step, step + K) of the tiles of a two-term run, F0 complete before and after.
 hipError_t launch_step1d_tb_tt(const void* runs, const void* tiles, int ntiles, int64_t step,
-                               int k, int half, hipStream_t stream) {
+                               int k, int half, int64_t in_off, int64_t out_off, hipStream_t stream) {
   if (ntiles <= 0) return hipSuccess;
   const Run1D<float>* r = static_cast<const Run1D<float>*>(runs);
   const Tile1D* t = static_cast<const Tile1D*>(tiles);
   switch (k) {
-    case 3: return launch_tb_tt_k<3>(r, t, ntiles, step, half, stream);
-    case 5: return launch_tb_tt_k<5>(r, t, ntiles, step, half, stream);
-    case 7: return launch_tb_tt_k<7>(r, t, ntiles, step, half, stream);
-    case 9: return launch_tb_tt_k<9>(r, t, ntiles, step, half, stream);
+    case 3: return launch_tb_tt_k<3>(r, t, ntiles, step, half, in_off, out_off, stream);
+    case 5: return launch_tb_tt_k<5>(r, t, ntiles, step, half, in_off, out_off, stream);
+    case 7: return launch_tb_tt_k<7>(r, t, ntiles, step, half, in_off, out_off, stream);
+    case 9: return launch_tb_tt_k<9>(r, t, ntiles, step, half, in_off, out_off, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -164,3 +164,27 @@ def test_time_block_rejects_even_and_reports_off_for_fp64(gpu_lib):
         sim.set_time_block(4)
     sim.set_time_block(5)
     assert sim.time_block() == 1
+
+
+def test_blocked_launch_over_several_rounds_is_bitwise(gpu_lib):
+    """The large line (Nx=65536: about three work-groups per resident slot) with the
+    source moved next to the tiles where a launch's second and third rounds of
+    work-groups begin: 9 steps per launch against one step per launch, bit for bit.  A
+    work-group that starts after its neighbour finished must still see that neighbour's
+    rows as they were at the launch's start (the rows are read from one copy and written
+    to the other)."""
+    for src in (21950, 43990):
+        run = W.c1(steps=2000)
+        run.src_node = src
+        a = B.Sim(run, precision=B.FP32, time_block=9)
+        b = B.Sim(run, precision=B.FP32, time_block=1)
+        assert a.time_block() == 9
+        _banner(f"rounds: source at {src}")
+        for n in (450, 451):
+            a.run(n)
+            b.run(n)
+            for f in (B.F_E, B.F_H, B.F_J, B.F_DF):
+                assert np.array_equal(a.read(f), b.read(f)), (src, n, f)
+        assert np.max(np.abs(b.read(B.F_DF))) > 0
+        a.close()
+        b.close()
