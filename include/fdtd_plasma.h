@@ -241,9 +241,16 @@ int fdtd_plasma_read_fields(fdtd_plasma *h, int32_t run, int32_t field, double *
 
 /* Record `field` at grid index (i, j) after every step (1D: j ignored).  Only before
  * the first step; at most fdtd_device.max_probes.  *id receives the probe id.  3D handles
- * take no probes (FDTD_EINVAL): read whole fields instead. */
+ * take fdtd_plasma_add_probe3d instead (FDTD_EINVAL here). */
 int fdtd_plasma_add_probe(fdtd_plasma *h, int32_t run, int32_t field, int32_t i, int32_t j,
                           int32_t *id);
+/* 3D handles: record E component `field` (FDTD_F_EX, _EY or _EZ) at its storage index
+ * (i, j, k) (the component's own shape, see enum fdtd_field) after every step, the ports of
+ * the paper's reflection and transmission measurement (section 5.3 results).  Rules as
+ * for fdtd_plasma_add_probe; FDTD_ERANGE for an index outside the component's array,
+ * FDTD_EINVAL for another field or a 1D / 2D handle.  Read with fdtd_plasma_read_probe. */
+int fdtd_plasma_add_probe3d(fdtd_plasma *h, int32_t field, int32_t i, int32_t j, int32_t k,
+                            int32_t *id);
 /* Copy the last min(steps, probe_capacity) samples of probe `id` (oldest first). */
 int fdtd_plasma_read_probe(fdtd_plasma *h, int32_t id, double *dst, size_t dst_len,
                            size_t *n_out);

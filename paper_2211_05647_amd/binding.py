@@ -75,6 +75,7 @@ _SIGS = {
     "fdtd_plasma_field_size": ([C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)], C.c_int),
     "fdtd_plasma_read_fields": ([C.c_void_p, C.c_int32, C.c_int32, _dp, C.c_size_t, C.POINTER(C.c_int64)], C.c_int),
     "fdtd_plasma_add_probe": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
+    "fdtd_plasma_add_probe3d": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
     "fdtd_plasma_read_probe": ([C.c_void_p, C.c_int32, _dp, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
     "fdtd_plasma_state_size": ([C.c_void_p, C.POINTER(C.c_size_t)], C.c_int),
     "fdtd_plasma_save_state": ([C.c_void_p, C.c_void_p, C.c_size_t], C.c_int),
@@ -267,6 +268,12 @@ class Sim:
     def add_probe(self, field, i, j=0, run=0):
         pid = C.c_int32()
         check(lib().fdtd_plasma_add_probe(self.h, run, field, i, j, C.byref(pid)), "add_probe")
+        return pid.value
+
+    def add_probe3d(self, field, i, j, k):
+        """3D handles: E component ``field`` (F_EX, F_EY, F_EZ) at storage index (i, j, k)."""
+        pid = C.c_int32()
+        check(lib().fdtd_plasma_add_probe3d(self.h, field, i, j, k, C.byref(pid)), "add_probe3d")
         return pid.value
 
     def read_probe(self, pid, n):

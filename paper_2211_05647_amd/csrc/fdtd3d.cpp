@@ -18,6 +18,7 @@ namespace fdtdp {
 template <class T>
 hipError_t launch_step3d_t(const void* run, int nx, int ny, int nz, int np, int kin_groups,
                            int nc, int f0_groups, bool two_term, int64_t step,
+                           const int32_t* pix, int nprobe, void* ring, int cap,
                            hipStream_t stream);
 
 struct Host3D {
@@ -39,6 +40,10 @@ struct Host3D {
   size_t off_f0 = 0, off_en = 0, off_status = 0;
   size_t off_pidx = 0, off_tau = 0, off_dens = 0, off_s = 0, off_b = 0, off_w = 0, off_prof = 0;
   size_t off_pcell = 0, off_cedge = 0, off_c = 0, off_v2h = 0;
+  // probes: E index of each probe point, ring of probe_cap samples per probe
+  int max_probes = 0, probe_cap = 0, nprobe = 0;
+  size_t off_probe = 0, off_pix = 0;
+  char* ws = nullptr;
   size_t state_end = 0, total = 0;
   int kin_groups = 1, f0_groups = 1;
   alignas(16) unsigned char run[sizeof(Run3D<double>)];
@@ -176,12 +181,17 @@ void layout(Host3D* h) {
   h->off_cedge = cv.take((size_t)std::max(h->nc, 1) * 96);
   h->off_c = cv.take((size_t)h->row * es);
   h->off_v2h = cv.take((size_t)h->row * es);
+  h->off_probe = cv.take((size_t)std::max(h->max_probes, 1) * std::max(h->probe_cap, 1) * es);
+  h->off_pix = cv.take((size_t)std::max(h->max_probes, 1) * 4);
   h->total = cv.size() + 256;
 }
 
-Host3D* new_host(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s) {
+Host3D* new_host(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s,
+                 int max_probes, int probe_cap) {
   Host3D* h = new (std::nothrow) Host3D();
   if (!h) return nullptr;
+  h->max_probes = max_probes;
+  h->probe_cap = probe_cap;
   h->g = *g;
   h->p = *p;
   if (s) h->s = *s; else std::memset(&h->s, 0, sizeof h->s);
@@ -215,7 +225,7 @@ Host3D* new_host(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s
 }
 
 template <class T>
-int upload(Host3D* h, char* ws, hipStream_t st) {
+int upload(Host3D* h, char* ws, hipStream_t st, const std::vector<ProbeInfo>& probes) {
   const int nx = h->nx, ny = h->ny, nz = h->nz, m = h->m, vdim = h->vdim, row = h->row;
   const double dt = h->dt;
   // speed grid and F0 (FP64), rounded once
@@ -292,6 +302,12 @@ int upload(Host3D* h, char* ws, hipStream_t st) {
       (e = put(h->off_c, cb.data(), row * sizeof(T))) ||
       (e = put(h->off_v2h, v2h.data(), row * sizeof(T))))
     return hip_fail(e, "upload 3D tables");
+  // probe points: the E index is kept in ProbeInfo::i
+  std::vector<int32_t> pix;
+  for (const ProbeInfo& pi : probes) pix.push_back(pi.i);
+  h->nprobe = (int)pix.size();
+  h->ws = ws;
+  if ((e = put(h->off_pix, pix.data(), pix.size() * 4))) return hip_fail(e, "upload 3D probes");
 
   Run3D<T> R;
   std::memset(&R, 0, sizeof R);
@@ -414,8 +430,8 @@ int validate_3d(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s)
   return FDTD_OK;
 }
 
-size_t workspace_3d(const fdtd_grid* g, const fdtd_profile* p) {
-  Host3D* h = new_host(g, p, nullptr);
+size_t workspace_3d(const fdtd_grid* g, const fdtd_profile* p, int max_probes, int probe_cap) {
+  Host3D* h = new_host(g, p, nullptr, max_probes, probe_cap);
   if (!h) return 0;
   const size_t n = h->total;
   delete h;
@@ -423,23 +439,45 @@ size_t workspace_3d(const fdtd_grid* g, const fdtd_profile* p) {
 }
 
 Host3D* make_3d(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s,
-                size_t* state_bytes) {
-  Host3D* h = new_host(g, p, s);
+                int max_probes, int probe_cap, size_t* state_bytes, size_t* probe_off) {
+  Host3D* h = new_host(g, p, s, max_probes, probe_cap);
   if (!h) return nullptr;
   *state_bytes = h->state_end;
+  *probe_off = h->off_probe;
   return h;
 }
 
-int upload_3d(Host3D* h, char* ws, hipStream_t stream) {
-  return h->es == 8 ? upload<double>(h, ws, stream) : upload<float>(h, ws, stream);
+int upload_3d(Host3D* h, char* ws, hipStream_t stream, const std::vector<ProbeInfo>& probes) {
+  return h->es == 8 ? upload<double>(h, ws, stream, probes) : upload<float>(h, ws, stream, probes);
+}
+
+// Flat E index of the E point (i, j, k) of component `field` (EX, EY, EZ), each in its
+// own storage shape.
+int probe_index_3d(const Host3D* h, int field, int i, int j, int k, int32_t* at) {
+  const size_t X = h->nx, Y = h->ny, Z = h->nz;
+  size_t nxc, nyc, nzc, base;
+  switch (field) {
+    case FDTD_F_EX: nxc = X; nyc = Y + 1; nzc = Z + 1; base = 0; break;
+    case FDTD_F_EY: nxc = X + 1; nyc = Y; nzc = Z + 1; base = h->nE[0]; break;
+    case FDTD_F_EZ: nxc = X + 1; nyc = Y + 1; nzc = Z; base = h->nE[0] + h->nE[1]; break;
+    default: return fail(FDTD_EINVAL, "3D probes record EX, EY or EZ");
+  }
+  if (i < 0 || j < 0 || k < 0 || (size_t)i >= nxc || (size_t)j >= nyc || (size_t)k >= nzc)
+    return fail(FDTD_ERANGE, "probe index (%d, %d, %d) out of range", i, j, k);
+  *at = (int32_t)(base + ((size_t)k * nyc + j) * nxc + i);
+  return FDTD_OK;
 }
 
 hipError_t launch_step3d(Host3D* h, int64_t step, hipStream_t stream) {
+  const int32_t* pix = reinterpret_cast<const int32_t*>(h->ws + h->off_pix);
+  void* ring = h->ws + h->off_probe;
   if (h->es == 8)
     return launch_step3d_t<double>(h->run, h->nx, h->ny, h->nz, h->np, h->kin_groups, h->nc,
-                                   h->f0_groups, h->two_term, step, stream);
+                                   h->f0_groups, h->two_term, step, pix, h->nprobe, ring,
+                                   std::max(h->probe_cap, 1), stream);
   return launch_step3d_t<float>(h->run, h->nx, h->ny, h->nz, h->np, h->kin_groups, h->nc,
-                                h->f0_groups, h->two_term, step, stream);
+                                h->f0_groups, h->two_term, step, pix, h->nprobe, ring,
+                                std::max(h->probe_cap, 1), stream);
 }
 
 int points_3d(const Host3D* h) { return h->np; }

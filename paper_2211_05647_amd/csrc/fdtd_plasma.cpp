@@ -619,7 +619,7 @@ int finish_upload(fdtd_plasma* h) {
     rc = build_tiles_1d(h);
     if (rc) return rc;
   } else if (h->dims == 3) {
-    rc = upload_3d(h->h3, h->ws, h->stream);
+    rc = upload_3d(h->h3, h->ws, h->stream, h->probes);
     if (rc) return rc;
   } else {
     rc = upload_2d(h->h2, h->ws, h->stream, h->probes, h->probe_off, h->probe_cap);
@@ -729,7 +729,7 @@ int fdtd_plasma_workspace_size(const fdtd_grid* grid, const fdtd_profile* profil
   if (grid->dims == 3) {
     int rc = validate_3d(grid, profile, nullptr);
     if (rc) return rc;
-    *bytes = workspace_3d(grid, profile);
+    *bytes = workspace_3d(grid, profile, mp, pc);
     return FDTD_OK;
   }
   int rc = validate_1d(grid, profile, nullptr, false);
@@ -815,18 +815,18 @@ int fdtd_plasma_create(const fdtd_grid* grid, const fdtd_profile* profile,
     h->precision = grid->precision;
     h->device = dev->device;
     h->stream = reinterpret_cast<hipStream_t>(dev->hip_stream);
-    h->max_probes = 0;      // 3D handles take no probes
-    h->probe_cap = 0;
-    size_t state_bytes = 0;
-    h->h3 = make_3d(grid, profile, source, &state_bytes);
+    h->max_probes = dev->max_probes;
+    h->probe_cap = dev->probe_capacity;
+    size_t state_bytes = 0, probe_off = 0;
+    h->h3 = make_3d(grid, profile, source, h->max_probes, h->probe_cap, &state_bytes, &probe_off);
     if (!h->h3) {
       delete h;
       return fail(FDTD_ENOMEM, "host allocation (3D)");
     }
     h->state_off = 0;
     h->state_bytes = state_bytes;
-    h->probe_off = 0;
-    int rc2 = attach_workspace(h, dev, workspace_3d(grid, profile));
+    h->probe_off = probe_off;
+    int rc2 = attach_workspace(h, dev, workspace_3d(grid, profile, h->max_probes, h->probe_cap));
     if (!rc2) rc2 = finish_upload(h);
     if (!rc2) {
       hipError_t e = hipEventCreate(&h->ev0);
@@ -1121,7 +1121,7 @@ int fdtd_plasma_read_fields(fdtd_plasma* h, int32_t run, int32_t field, double* 
 int fdtd_plasma_add_probe(fdtd_plasma* h, int32_t run, int32_t field, int32_t i, int32_t j,
                           int32_t* id) {
   if (!h || !id) return fail(FDTD_EINVAL, "null argument");
-  if (h->dims == 3) return fail(FDTD_EINVAL, "3D handles take no probes");
+  if (h->dims == 3) return fail(FDTD_EINVAL, "3D handles take probes through fdtd_plasma_add_probe3d");
   if (h->started) return fail(FDTD_ESTATE, "probes must be added before the first step");
   if ((int)h->probes.size() >= h->max_probes) return fail(FDTD_ERANGE, "no probe slot left");
   if (h->probe_cap <= 0) return fail(FDTD_ERANGE, "probe_capacity is 0");
@@ -1146,6 +1146,22 @@ int fdtd_plasma_add_probe(fdtd_plasma* h, int32_t run, int32_t field, int32_t i,
   return finish_upload(h) ? FDTD_EDEVICE : FDTD_OK;
 }
 
+int fdtd_plasma_add_probe3d(fdtd_plasma* h, int32_t field, int32_t i, int32_t j, int32_t k,
+                            int32_t* id) {
+  if (!h || !id) return fail(FDTD_EINVAL, "null argument");
+  if (h->dims != 3) return fail(FDTD_EINVAL, "fdtd_plasma_add_probe3d takes 3D handles");
+  if (h->started) return fail(FDTD_ESTATE, "probes must be added before the first step");
+  if ((int)h->probes.size() >= h->max_probes) return fail(FDTD_ERANGE, "no probe slot left");
+  if (h->probe_cap <= 0) return fail(FDTD_ERANGE, "probe_capacity is 0");
+  int32_t at = 0;
+  const int rc = probe_index_3d(h->h3, field, i, j, k, &at);
+  if (rc) return rc;
+  ProbeInfo p{0, field, at, -1};   // the flat E index
+  h->probes.push_back(p);
+  *id = (int)h->probes.size() - 1;
+  return finish_upload(h) ? FDTD_EDEVICE : FDTD_OK;
+}
+
 int fdtd_plasma_read_probe(fdtd_plasma* h, int32_t id, double* dst, size_t dst_len, size_t* n_out) {
   if (!h || !dst) return fail(FDTD_EINVAL, "null argument");
   if (id < 0 || id >= (int)h->probes.size()) return fail(FDTD_ERANGE, "probe id out of range");
@@ -1161,12 +1177,12 @@ int fdtd_plasma_read_probe(fdtd_plasma* h, int32_t id, double* dst, size_t dst_l
   e = hipMemcpy(buf.data(), h->ws + h->probe_off + (size_t)id * h->probe_cap * es,
                 buf.size(), hipMemcpyDeviceToHost);
   if (e) return hip_fail(e, "copy probe");
-  double scale = 1.0;
+  double scale = 1.0;   // 3D probes record E (V/m)
   if (h->dims == 1) {
     const Host1D& x = h->h1[p.run];
     if (p.field == FDTD_F_H) scale = 1.0 / kEta0;
     if (p.field == FDTD_F_J) scale = kEps0 / x.dt;
-  } else {
+  } else if (h->dims == 2) {
     scale = probe_scale_2d(h->h2, p.field);
   }
   for (size_t k = 0; k < n; ++k) {

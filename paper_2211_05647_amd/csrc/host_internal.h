@@ -116,10 +116,11 @@ int closure_counts_2d(const Host2D* h, int64_t* nm, int64_t* nk);
 // 3D path (fdtd3d.cpp)
 struct Host3D;
 int validate_3d(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s);
-size_t workspace_3d(const fdtd_grid* g, const fdtd_profile* p);
+size_t workspace_3d(const fdtd_grid* g, const fdtd_profile* p, int max_probes, int probe_cap);
 Host3D* make_3d(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s,
-                size_t* state_bytes);
-int upload_3d(Host3D* h, char* ws, hipStream_t stream);
+                int max_probes, int probe_cap, size_t* state_bytes, size_t* probe_off);
+int upload_3d(Host3D* h, char* ws, hipStream_t stream, const std::vector<ProbeInfo>& probes);
+int probe_index_3d(const Host3D* h, int field, int i, int j, int k, int32_t* at);
 hipError_t launch_step3d(Host3D* h, int64_t step, hipStream_t stream);
 int points_3d(const Host3D* h);
 int status_3d(Host3D* h, char* ws, int32_t* v);

@@ -440,9 +440,20 @@ __global__ __launch_bounds__(256) void k_e3d(const Run3D<T> R, int64_t step) {
   }
 }
 
+// E at the probe points after the step (E^{n+1}), into slot `step` mod cap of each
+// probe's ring.
+template <class T>
+__global__ __launch_bounds__(64) void k_probe3d(const T* __restrict__ E,
+                                                const int32_t* __restrict__ pix, int nprobe,
+                                                T* __restrict__ ring, int cap, int64_t step) {
+  const int q = threadIdx.x;
+  if (q < nprobe) ring[(size_t)q * cap + (size_t)(step % cap)] = E[pix[q]];
+}
+
 template <class T>
 hipError_t launch_step3d_t(const void* run, int nx, int ny, int nz, int np, int kin_groups,
                            int nc, int f0_groups, bool two_term, int64_t step,
+                           const int32_t* pix, int nprobe, void* ring, int cap,
                            hipStream_t stream) {
   const Run3D<T>& R = *static_cast<const Run3D<T>*>(run);
   const int tiles = ((nx + 1) * (ny + 1) + 255) / 256;
@@ -456,12 +467,15 @@ hipError_t launch_step3d_t(const void* run, int nx, int ny, int nz, int np, int 
   hipLaunchKernelGGL(k_e3d<T>, grid, dim3(256), 0, stream, R, step);
   if (two_term && nc > 0 && np > 0)
     hipLaunchKernelGGL(k_f0_3d<T>, dim3(f0_groups), dim3(256), 0, stream, R);
+  if (nprobe > 0)
+    hipLaunchKernelGGL(k_probe3d<T>, dim3(1), dim3(64), 0, stream, R.Ex, pix, nprobe,
+                       static_cast<T*>(ring), cap, step);
   return hipGetLastError();
 }
 
 template hipError_t launch_step3d_t<float>(const void*, int, int, int, int, int, int, int, bool,
-                                           int64_t, hipStream_t);
+                                           int64_t, const int32_t*, int, void*, int, hipStream_t);
 template hipError_t launch_step3d_t<double>(const void*, int, int, int, int, int, int, int, bool,
-                                            int64_t, hipStream_t);
+                                            int64_t, const int32_t*, int, void*, int, hipStream_t);
 
 }  // namespace fdtdp

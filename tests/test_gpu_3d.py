@@ -159,3 +159,63 @@ def test_benchmark_size_parity_through_the_slab(gpu_lib):
         assert err <= 1e-5, name
     assert np.abs(orc.J).max() > 0
     sim.close()
+
+
+def _e_index(run, comp, i, j, k):
+    """Flat index into [Ex | Ey | Ez] of the oracle's E of component comp at (i, j, k)."""
+    X, Y, Z = run.nx, run.ny, run.nz
+    shapes = [(X, Y + 1, Z + 1), (X + 1, Y, Z + 1), (X + 1, Y + 1, Z)]
+    base = sum(a * b * c for a, b, c in shapes[:comp])
+    nxc, nyc, _ = shapes[comp]
+    return base + (k * nyc + j) * nxc + i
+
+
+@pytest.mark.parametrize("prec,tol", [(B.FP64, 1e-12), (B.FP32, 1e-5)])
+def test_probes_3d_match_the_oracle(gpu_lib, prec, tol):
+    """Probes on the three E components (before, inside and after the slab, off the axis)
+    record after every step what the oracle's E holds there."""
+    run = _small(steps=400)
+    k0, k1 = run.meta["slab"]
+    pts = [(0, 10, 9, k0 - 1), (0, 3, 5, k0 + 2), (1, 7, 4, k1 + 1), (2, 8, 8, k0 + 4)]
+    fields = [B.F_EX, B.F_EY, B.F_EZ]
+    sim = B.Sim(run, precision=prec, max_probes=len(pts), probe_capacity=run.steps)
+    ids = [sim.add_probe3d(fields[c], i, j, k) for c, i, j, k in pts]
+    sim.run(run.steps)
+    g = np.stack([sim.read_probe(q, run.steps) for q in ids], axis=1)
+    orc = oracle_3d(run)
+    o = orc.run(run.steps, probes=[_e_index(run, c, i, j, k) for c, i, j, k in pts])
+    err = rel_l2(g, o)
+    _banner(f"probes prec={prec}: rel L2 = {err:.3e}")
+    assert err <= tol
+    assert np.abs(o).max() > 0
+    sim.close()
+
+
+def test_probe3d_rejections(gpu_lib):
+    """add_probe on a 3D handle, another field, an index outside the component's array,
+    more probes than slots, a probe after the first step, add_probe3d on a 1D handle."""
+    run = _small(steps=10)
+    sim = B.Sim(run, precision=B.FP32, max_probes=2, probe_capacity=10)
+    with pytest.raises(B.FdtdError):
+        sim.add_probe(B.F_EX, 3, 3)
+    with pytest.raises(B.FdtdError):
+        sim.add_probe3d(B.F_HX, 3, 3, 3)
+    with pytest.raises(B.FdtdError):
+        sim.add_probe3d(B.F_EX, run.nx, 3, 3)      # Ex has nx points along x
+    with pytest.raises(B.FdtdError):
+        sim.add_probe3d(B.F_EZ, 3, 3, run.nz)      # Ez has nz points along z
+    sim.add_probe3d(B.F_EY, run.nx, 3, 3)          # Ey has nx + 1
+    sim.add_probe3d(B.F_EZ, 3, 3, run.nz - 1)
+    with pytest.raises(B.FdtdError):
+        sim.add_probe3d(B.F_EX, 1, 1, 1)           # no slot left
+    sim.close()
+    sim = B.Sim(run, precision=B.FP32, max_probes=2, probe_capacity=10)
+    sim.run(1)
+    with pytest.raises(B.FdtdError):
+        sim.add_probe3d(B.F_EX, 1, 1, 1)
+    sim.close()
+    line = W.slab_1d(100, 8, 40, 60, 0.5, 0.1, W.F_REF, 20, 10)
+    s1 = B.Sim(line, precision=B.FP32, max_probes=1, probe_capacity=10)
+    with pytest.raises(B.FdtdError):
+        s1.add_probe3d(B.F_EX, 1, 1, 1)
+    s1.close()

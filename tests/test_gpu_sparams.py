@@ -51,3 +51,44 @@ def test_argon_slab_sparams(gpu_lib, prec, tol):
     assert np.all(a11[FREQS < 20e9] > 0.85)
     assert np.all(np.diff(a21) > 0)
     assert np.all(a11 ** 2 + a21 ** 2 <= 1.0 + 10 * tol)
+
+
+def _oracle_sparams_3d(run, ports):
+    from parity import oracle_3d
+    from test_gpu_3d import _e_index
+
+    def series(r):
+        o = oracle_3d(r)
+        pr = o.run(r.steps, probes=[_e_index(r, 0, *p) for p in ports])
+        return pr[:, 0], pr[:, 1]
+    s1, s2 = series(run)
+    vac = copy.deepcopy(run)
+    vac.ne[:] = 0.0
+    vac.nubar[:] = 0.0
+    v1, v2 = series(vac)
+    dt = run.courant * run.dx / 299792458.0
+    t = (np.arange(run.steps) + 1) * dt
+    ph = np.exp(-2j * np.pi * np.outer(FREQS, t))
+    return (ph @ (s1 - v1)) / (ph @ v1), (ph @ s2) / (ph @ v2)
+
+
+@pytest.mark.parametrize("prec,tol", [(B.FP64, 1e-10), (B.FP32, 1e-4)])
+def test_argon_slab_sparams_3d(gpu_lib, prec, tol):
+    """The 3D argon slab (a sheet source, so a plane wave along z; CPML on all faces) with
+    Ex probes at the middle of the cross-section on the planes at the slab's two faces:
+    S11 and S21 against the oracle's, and the same physics checks as in 1D."""
+    run = W.argon_slab_3d(nx=24, ny=24, nz=256, steps=1500, ncpml=6)
+    ports = sparams.slab_ports_3d(run)
+    print(f"[gpu-sparams] 3D prec={prec}", flush=True)
+    s11, s21 = sparams.slab_sparams_3d(run, FREQS, precision=prec)
+    o11, o21 = _oracle_sparams_3d(run, ports)
+    # only inside the pulse's band: at 40 GHz the incident spectrum is small enough that the
+    # ratios are set by the layers' residual reflections (|S11| > 1 there, in the oracle too)
+    band = FREQS <= 36e9
+    assert np.max(np.abs(s11 - o11)[band]) <= tol
+    assert np.max(np.abs(s21 - o21)[band]) <= tol
+    a11, a21 = np.abs(s11)[band], np.abs(s21)[band]
+    print(f"[gpu-sparams] 3D |S11| {np.round(a11, 3)} |S21| {np.round(a21, 3)}", flush=True)
+    assert np.all(a11[FREQS[band] < 20e9] > 0.8)
+    assert np.all(np.diff(a21) > 0)
+    assert np.all(a11 ** 2 + a21 ** 2 <= 1.0 + 10 * tol)
