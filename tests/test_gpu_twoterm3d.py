@@ -148,3 +148,24 @@ def test_benchmark_size_two_term_parity(gpu_lib):
     assert np.abs(orc.f0_rows()).max() > 0 and np.abs(orc.J).max() > 0
     assert sim.run_status(0) == 0
     sim.close()
+
+
+def test_two_term_without_plasma_points(gpu_lib):
+    """Plasma in a column one cell wide: no E point has four plasma cells, so the two-term
+    model has cells (F0 rows) but no points -- no current, F0 unchanged, the field that of
+    vacuum."""
+    run = _slab(nx=16, ny=15, nz=40, nv=8, ncpml=5, steps=200)
+    run.ne[:] = 0.0
+    run.ne[10:30, 7, 8] = W.ARGON_NE
+    vac = _slab(nx=16, ny=15, nz=40, nv=8, ncpml=5, steps=200)
+    vac.ne[:] = 0.0
+    a, b = B.Sim(run, precision=B.FP64), B.Sim(vac, precision=B.FP64)
+    assert a.closure_counts()[1] == 0
+    a.run(run.steps)
+    b.run(run.steps)
+    for f in (B.F_EX, B.F_EY, B.F_EZ, B.F_HX):
+        assert np.array_equal(a.read(f), b.read(f))
+    assert np.all(a.read(B.F_JX) == 0.0)
+    df = a.read(B.F_DF)
+    assert df.size == 20 * run.nv and np.all(df == 0.0)
+    a.close(); b.close()
