@@ -624,7 +624,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (f64 moments)",
+        "dtype": "f32",
+        "moment_dtype": "f64",
         "data": "synthetic, seeded",
         "config": {"workload": "1D Yee + 1V kinetic, Nx=65536, Nv=512, FP32",
                    "nx": nx, "nv": nv, "plasma_cells": ncell, "steps": args.steps,
