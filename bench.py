@@ -311,7 +311,7 @@ def extra_twoterm(B, W, torch, steps=2000):
     run.te_ev, run.vmax_over_vth = 1.0, 5.0
     log(f"two-term: Nx={run.nx} v_dim={run.nv} plasma cells={run.plasma_cells}")
     info = {}
-    # 9 steps per launch (measured: 3.52 us per step at 9, 3.74 at 7, 4.09 at 5, 8.03 at 1)
+    # 9 steps per launch (measured: 3.24 us per step at 9, 3.45 at 7, 3.82 at 5, 7.73 at 1)
     wall, ms = time_single(run, B, torch, steps, 54, 0, info, 9)
     kb, rows = info["time_block"], info["rows_per_launch"]
     wall1, ms1 = time_single(run, B, torch, steps, 50, 0, None, 1)

@@ -182,6 +182,30 @@ __device__ __forceinline__ double group_reduce4_dpp(const double (&a)[4], int& w
   return t;
 }
 
+// FP64 sum over an aligned lane group of LPC = 8 or 16 lanes, every lane returning the
+// total, by DPP rounds without LDS: xor 1, xor 2, then row_half_mirror (after two rounds a
+// quad holds one value, so the mirror fetches the other quad's sum) and, for 16 lanes,
+// row_mirror across the 8-lane halves.  Additions are commutative, so every lane of the
+// group ends with the same bits.
+template <int LPC>
+__device__ __forceinline__ double group_allreduce_dpp(double s) {
+  static_assert(LPC == 8 || LPC == 16, "lane groups of 8 or 16");
+  s += dpp_f64<0xB1>(s);                     // quad_perm [1,0,3,2]
+  s += dpp_f64<0x4E>(s);                     // quad_perm [2,3,0,1]
+  s += dpp_f64<0x141>(s);                    // row_half_mirror
+  if constexpr (LPC == 16) s += dpp_f64<0x140>(s);   // row_mirror
+  return s;
+}
+
+// A neighbouring lane's value inside a 16-lane row (row_shl:1 -- lane l reads lane l + 1 --
+// and row_shr:1 -- lane l reads lane l - 1; 0 past the row's ends), an exact copy.
+__device__ __forceinline__ float from_next_lane(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x101, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float from_prev_lane(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x111, 0xF, 0xF, true));
+}
+
 struct Tile1D {
   int32_t run, node0, node1, cell0, cell1;
 };

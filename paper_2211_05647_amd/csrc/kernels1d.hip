@@ -478,9 +478,17 @@ __device__ __forceinline__ void kinetic_tile_tt(const Run1D<T>& R, const T* eloc
       }
     }
     if (!flush) {
-      double a1[1] = {acc};
-      int which = 0;
-      const double tot = group_reduce<1>(a1, lpc, li, which);
+      // rows of 8 or 16 lanes: the DPP tree the blocked kernel uses too
+      double tot;
+      if (lpc == 8) {
+        tot = group_allreduce_dpp<8>(acc);
+      } else if (lpc == 16) {
+        tot = group_allreduce_dpp<16>(acc);
+      } else {
+        double a1[1] = {acc};
+        int which = 0;
+        tot = group_reduce<1>(a1, lpc, li, which);
+      }
       if (live && first_lane) jloc[loc] = (T)tot;
     }
   }

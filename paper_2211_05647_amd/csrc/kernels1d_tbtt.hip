@@ -73,8 +73,6 @@ __global__ __launch_bounds__(kTtBlock) void k_step1d_tb_tt(const Run1D<float>* _
   const int wv = __builtin_amdgcn_readfirstlane(wave);
   constexpr int cpw = 64 / LPC;
   const int sub = lane / LPC, li = lane - sub * LPC;
-  const int nxt = sub * LPC + ((li + 1) & (LPC - 1));
-  const int prv = sub * LPC + ((li - 1) & (LPC - 1));
   const bool first_lane = li == 0, last_lane = li == LPC - 1;
   // slot q of lane group `sub` of wavefront w holds plasma row (q * waves + w) * cpw + sub
   auto row_slot = [&](int q, int w, int sb) { return (q * kTtWaves + w) * cpw + sb; };
@@ -103,14 +101,14 @@ __global__ __launch_bounds__(kTtBlock) void k_step1d_tb_tt(const Run1D<float>* _
     // no contraction of v^2 (F1_k + F1_{k+1}) into the flux difference, as in the
     // one-step kernel
 #pragma clang fp contract(off)
-    const float nf = __shfl(f[u].x, nxt);
+    const float nf = from_next_lane(f[u].x);
     float ph[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const float fr = v < 3 ? lane_at(f[u], v < 3 ? v + 1 : v) : (last_lane ? 0.f : nf);
       ph[v] = lane_at(vh, v) * (lane_at(f[u], v) + fr);   // 0 on the top face
     }
-    const float got = __shfl(ph[3], prv);
+    const float got = from_prev_lane(ph[3]);
     if (live) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -146,9 +144,10 @@ __global__ __launch_bounds__(kTtBlock) void k_step1d_tb_tt(const Run1D<float>* _
         Ev = Es[p][lc];
       }
       if (s > 0) l0_update(u, live, live ? 0.5f * (Es[p ^ 1][lc] + Ev) : 0.f);
-      // d_{k+1} from the next lane, d_{k-1} from the previous one (every lane takes part)
-      const float nd = __shfl(d[u].x, nxt);
-      const float pd = __shfl(d[u].w, prv);
+      // d_{k+1} from the next lane, d_{k-1} from the previous one (every lane takes part;
+      // DPP row shifts: the values the one-step kernel's lane shuffles fetch)
+      const float nd = from_next_lane(d[u].x);
+      const float pd = from_prev_lane(d[u].w);
       const float nE = ne * Ev, kE = kd * Ev, tau2 = tau + tau;
       if (live && first_lane && !(fabsf(kE) <= 1.f)) atomicOr(R.status, 2);
       double acc = 0.0;
@@ -169,9 +168,7 @@ __global__ __launch_bounds__(kTtBlock) void k_step1d_tb_tt(const Run1D<float>* _
           acc = fma(w[v], (double)fn, acc);
         }
       }
-      double a1[1] = {acc};
-      int which = 0;
-      const double tot = group_reduce<1>(a1, LPC, li, which);
+      const double tot = group_allreduce_dpp<LPC>(acc);
       if (live && first_lane) Js[lc] = (float)tot;
     }
     __syncthreads();
