@@ -13,7 +13,8 @@ LIB = os.path.join(HERE, "libfdtdplasma.so")
 OBJ = os.path.join(HERE, "_build")
 
 SOURCES = ["fdtd_plasma.cpp", "fdtd2d.cpp", "fdtd3d.cpp", "closure.cpp", "kernels1d.hip",
-           "kernels1d_tb.hip", "kernels1d_tbtt.hip", "kernels2d.hip", "kernels3d.hip", "mlp.hip"]
+           "kernels1d_tb.hip", "kernels1d_tbtt.hip",
+           "kernels1d_tbfull.hip", "kernels2d.hip", "kernels3d.hip", "mlp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",

@@ -487,12 +487,14 @@ int build_tb_tiles(fdtd_plasma* h) {
   // plasma rows one work-group holds (the two-term kernel keeps two chunks per row)
   auto rows_cap = [](const Host1D& x) {
     return std::min(tb_block(), x.model == FDTD_KINETIC_TWO_TERM ? tb_tt_max_rows(x.half)
-                                                                  : tb_max_rows(x.half));
+                                : x.model == FDTD_KINETIC_FULL   ? tb_full_max_rows(x.half)
+                                                                 : tb_max_rows(x.half));
   };
   for (int r = 0; r < h->nruns; ++r) {
     const Host1D& x = h->h1[r];
     const bool ok = x.model == FDTD_KINETIC_LINEAR ? tb_supported(x.half)
-                    : x.model == FDTD_KINETIC_TWO_TERM ? tb_tt_supported(x.half) : false;
+                    : x.model == FDTD_KINETIC_TWO_TERM ? tb_tt_supported(x.half)
+                    : x.model == FDTD_KINETIC_FULL ? tb_full_supported(x.half) : false;
     if (!ok) return FDTD_OK;
     if (rows_cap(x) - 2 * k < 32) return FDTD_OK;
   }
@@ -509,6 +511,7 @@ int build_tb_tiles(fdtd_plasma* h) {
     if (h->nruns == 1) {
       if (nodes < 4 * wmax) return FDTD_OK;   // too short to be worth blocking
       const int per_cu = x.model == FDTD_KINETIC_TWO_TERM ? tb_tt_blocks_per_cu(k, x.half)
+                         : x.model == FDTD_KINETIC_FULL   ? tb_full_blocks_per_cu(k, x.half)
                                                           : tb_blocks_per_cu(k, x.half);
       const int conc = std::max(1, cus * per_cu);
       const int rounds = (nodes + conc * wmax - 1) / (conc * wmax);
@@ -939,13 +942,19 @@ int fdtd_plasma_run(fdtd_plasma* h, int64_t nsteps) {
       const int64_t in_off = cur == 1 ? delta : 0, out_off = cur == 1 ? 0 : delta;
       // two-term runs are single runs: run 0 decides (their blocked kernel leaves F0
       // complete, so the one-step launches after it start with no l = 0 update pending)
-      const bool tt = h->h1[0].model == FDTD_KINETIC_TWO_TERM;
+      // (full-model runs are single runs too)
+      const int model = h->h1[0].model;
       for (const TbSeg& sg : h->tb_seg) {
         const int n = count_ge(sg.limit, s + kb);
-        e = tt ? launch_step1d_tb_tt(h->ws + h->runs_off, tb + sg.off, n, s, kb, sg.half,
-                                     in_off, out_off, h->stream)
-               : launch_step1d_tb(h->ws + h->runs_off, tb + sg.off, n, s, kb, sg.half, in_off,
+        if (model == FDTD_KINETIC_TWO_TERM)
+          e = launch_step1d_tb_tt(h->ws + h->runs_off, tb + sg.off, n, s, kb, sg.half, in_off,
                                   out_off, h->stream);
+        else if (model == FDTD_KINETIC_FULL)
+          e = launch_step1d_tb_full(h->ws + h->runs_off, tb + sg.off, n, s, kb, sg.half, in_off,
+                                    out_off, h->stream);
+        else
+          e = launch_step1d_tb(h->ws + h->runs_off, tb + sg.off, n, s, kb, sg.half, in_off,
+                               out_off, h->stream);
         if (e) return hip_fail(e, "launch blocked step kernel");
       }
       for (int r = 0; r < h->nruns; ++r)

@@ -91,6 +91,13 @@ int tb_tt_blocks_per_cu(int k, int half);
 hipError_t launch_step1d_tb_tt(const void* runs, const void* tiles, int ntiles, int64_t step,
                                int k, int half, int64_t in_off, int64_t out_off,
                                hipStream_t stream);
+// the same for the full-distribution model (half = Nv / 2)
+bool tb_full_supported(int half);
+int tb_full_max_rows(int half);
+int tb_full_blocks_per_cu(int k, int half);
+hipError_t launch_step1d_tb_full(const void* runs, const void* tiles, int ntiles, int64_t step,
+                                 int k, int half, int64_t in_off, int64_t out_off,
+                                 hipStream_t stream);
 // K steps of the tiles; every run's rows are read at df + in_off and written at
 // df + out_off (elements), two distinct copies
 hipError_t launch_step1d_tb(const void* runs, const void* tiles, int ntiles, int64_t step, int k,

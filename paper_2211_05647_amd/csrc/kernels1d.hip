@@ -288,7 +288,10 @@ __device__ __forceinline__ void kinetic_tile_full(const Run1D<T>& R, const T* el
         acc = fma(w[m][v], (double)onv, acc);
       }
     }
-    // even pass: faces of the time-centred odd part
+    // even pass: faces of the time-centred odd part (no contraction of cq (s_k + s_{k+1})
+    // into the face difference, so that the blocked kernel gives the same bits)
+    {
+#pragma clang fp contract(off)
     T qr[CPL][VPL];
     {
       T ns[CPL];
@@ -321,6 +324,7 @@ __device__ __forceinline__ void kinetic_tile_full(const Run1D<T>& R, const T* el
           lane_at(e[m], v) = lane_at(e[m], v) - (qr[m][v] - ql);
         }
       }
+    }
     }
     if (live) {
       V* row = dfv + (size_t)c * (2 * ch);

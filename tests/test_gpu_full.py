@@ -37,7 +37,7 @@ def test_full_model_parity(gpu_lib, nv, tile):
         for model in ("hard_sphere", "const"):
             _banner(f"nv={nv} tile={tile} prec={prec} nu={model}")
             run.nu_model = model
-            sim = B.Sim(run, precision=prec, tile=tile)
+            sim = B.Sim(run, precision=prec, tile=tile, time_block=1)   # one-step kernel
             assert sim.time_block() == 1
             orc = oracle_1d(run)
             snaps = []
@@ -98,17 +98,17 @@ def test_full_model_configurations_rejected(gpu_lib):
 
 
 def test_full_model_at_benchmark_size_prefix_parity(gpu_lib):
-    """The full-distribution model at the benchmark's size (Nx = 65536, Nv = 512, FP32, one
-    step per launch as timed): after 1500 steps the field has travelled at most 1500 nodes,
-    so the oracle on the prefix [0, src + 1510] is exact there; beyond it everything stays
-    at its initial value (zero field, f = n fhat)."""
+    """The full-distribution model at the benchmark's size (Nx = 65536, Nv = 512, FP32, 9
+    steps per launch as timed): after 1500 steps the field has travelled at most 1500
+    nodes, so the oracle on the prefix [0, src + 1510] is exact there; beyond it everything
+    stays at its initial value (zero field, f = n fhat)."""
     run = W.c1()
     run.kinetic = "full"
     steps = 1500
     cut = run.src_node + steps + 10
     _banner("full model, Nx=65536 prefix")
-    sim = B.Sim(run, precision=B.FP32)
-    assert sim.time_block() == 1
+    sim = B.Sim(run, precision=B.FP32, time_block=9)
+    assert sim.time_block() == 9
     orc = oracle_1d(run, nx=cut)
     snaps = []
     g, o, _, _ = space_time_1d(sim, orc, steps, 250, [], df_snaps=snaps)
@@ -121,4 +121,54 @@ def test_full_model_at_benchmark_size_prefix_parity(gpu_lib):
     assert np.all(sim.read(B.F_E)[cut + 1:] == 0.0)
     df = sim.read(B.F_DF).reshape(run.plasma_cells, run.nv)
     assert np.all(df[len(orc.cells):] == 0.0)
+    sim.close()
+
+
+def _long(nv, steps=600):
+    """A line long enough for K steps per launch (5001 nodes, plasma over many tiles with a
+    vacuum gap), the source 90 nodes before the slab, driven until the electrons heat."""
+    run = W.slab_1d(5000, nv, 130, 4200, 1.1, 0.2, W.F_REF, 40, steps)
+    run.ne[300:320] = 0.0
+    run.src_amp = 3e5 * 64 / nv
+    run.kinetic = "full"
+    return run
+
+
+@pytest.mark.parametrize("nv", [64, 512])
+def test_blocked_full_model_is_bitwise_the_one_step_run(gpu_lib, nv):
+    """K steps per launch (rows of 32 or 256 stored bins per half) against one step per
+    launch: E, H, J and the rows agree to the bit, also over calls that end inside a
+    block."""
+    run = _long(nv)
+    a = B.Sim(run, precision=B.FP32)
+    kb = a.time_block()
+    _banner(f"nv={nv}: {kb} steps per launch")
+    assert kb > 1
+    b = B.Sim(run, precision=B.FP32, time_block=1)
+    for n in (kb * 20, 1, 2 * kb + 3, 250):
+        a.run(n)
+        b.run(n)
+        for f in (B.F_E, B.F_H, B.F_J, B.F_DF):
+            assert np.array_equal(a.read(f), b.read(f)), (n, f)
+    assert a.run_status(0) == 0
+    a.close(); b.close()
+
+
+@pytest.mark.parametrize("nv", [64, 512])
+def test_blocked_full_model_parity(gpu_lib, nv):
+    """The blocked run against the FP64 oracle: E over space and time, f - n fhat."""
+    run = _long(nv, steps=540)
+    sim = B.Sim(run, precision=B.FP32)
+    assert sim.time_block() > 1
+    orc = oracle_1d(run)
+    snaps = []
+    g, o, _, _ = space_time_1d(sim, orc, run.steps, 90, [], df_snaps=snaps)
+    err = rel_l2(g, o)
+    _banner(f"nv={nv} blocked: E space-time rel L2 = {err:.3e}")
+    assert err <= 1e-5
+    gd = np.concatenate([a.ravel() for a, _ in snaps])
+    od = np.concatenate([b.ravel() for _, b in snaps])
+    err_f = rel_l2(gd, od)
+    _banner(f"  f - n fhat space-time rel L2 = {err_f:.3e}")
+    assert err_f <= 1e-5
     sim.close()
