@@ -161,21 +161,37 @@ def bytes_1d_full(run):
 
 def extra_full(B, W, torch, steps=None):
     """The full-distribution model (F0 evolves, electrons heat) on the C1 line and on the
-    Nx = 2^20 line, FP32, one step per launch (2000 and 300 steps, or ``steps``)."""
+    Nx = 2^20 line, FP32: K steps per launch (9 and 7, the measured best: 25.4 us against
+    26.1 at 7 and 41.1 at 1 on the C1 line, 347 us against 359 at 9 and 794 at 1 on 2^20),
+    and one step per launch beside it (2000 and 300 steps, or ``steps``)."""
     out = {}
-    for key, run, steps in (("full_c1", W.c1(steps=2000), steps or 2000),
-                            ("full_c1_nx2e20", W.c1_large(), steps or 300)):
+    for key, run, steps, kb in (("full_c1", W.c1(steps=2000), steps or 2000, 9),
+                                ("full_c1_nx2e20", W.c1_large(), steps or 300, 7)):
         run.kinetic = "full"
         log(f"{key}: Nx={run.nx} Nv={run.nv} plasma cells={run.plasma_cells}")
-        wall, ms = time_single(run, B, torch, steps, 50)
-        by = bytes_1d_full(run)
+        info = {}
+        wall, ms = time_single(run, B, torch, steps, 6 * kb, 0, info, kb)
+        kb, rows = info["time_block"], info["rows_per_launch"]
+        wall1, ms1 = time_single(run, B, torch, steps, 50, 0, None, 1)
+        by1 = bytes_1d_full(run)
+        # K steps per launch: rows read (owned + halo) with their scalars, owned rows
+        # written, fields once
+        byk = rows * (run.nv * 4 + 12) + run.plasma_cells * run.nv * 4 + (run.nx + 1) * 4 * 5
+        by = byk / kb if kb > 1 else by1
         out[key] = dict(workload=f"1D Yee + full-distribution 1V kinetic, Nx={run.nx}, "
                                  f"Nv={run.nv}, FP32, {steps} steps",
-                        kernel="k_step1d_full<float>",
+                        kernel=f"k_step1d_tb_full<{kb}, 64>" if kb > 1 else "k_step1d_full<float>",
+                        steps_per_launch=kb,
                         updates_per_s=run.plasma_cells * run.nv * steps / wall,
                         ms_per_step=wall / steps * 1e3, kernel_ms_per_step=ms,
                         hbm_gbs=by / (ms * 1e-3) / 1e9,
-                        hbm_frac=by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+                        hbm_frac=by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                        one_step_stream_equivalent_gbs=by1 / (ms * 1e-3) / 1e9,
+                        one_step_per_launch=dict(kernel="k_step1d_full<float>",
+                                                 ms_per_step=wall1 / steps * 1e3,
+                                                 kernel_ms_per_step=ms1,
+                                                 hbm_gbs=by1 / (ms1 * 1e-3) / 1e9,
+                                                 hbm_frac=by1 / (ms1 * 1e-3) / 1e9 / HBM_PEAK_GBS))
     # the FP64 oracle's full-distribution model on the host, same Nx = 65536 line
     sys.path.insert(0, ROOT)
     from oracle.core import Oracle1D, threads
