@@ -119,7 +119,8 @@ typedef struct {
  * its odd part F1.  The velocity derivative is in conservative flux form with zero flux
  * through +-vmax (electron number is kept exactly) and is explicit: each step needs
  * |(e/m) E dt / dv| <= 1, and a step that breaks it sets the run status (see
- * fdtd_plasma_run_status).  FULL runs are never temporally blocked.
+ * fdtd_plasma_run_status).  Temporally blocked as the LINEAR model is
+ * (fdtd_plasma_set_time_block).
  * TWO_TERM (1D single runs and 3D grids): the paper's own representation, section 5.1's
  * expansion F = F0 + (v/|v|).F1 with its l = 0 and l = 1 equations on a speed grid of nv
  * speeds (2..256; the paper uses 31) v_k = (k + 1/2) vmax / nv, F0 (f0_model) evolving
@@ -267,14 +268,14 @@ int fdtd_plasma_load_state(fdtd_plasma *h, const void *src, size_t len);
  * first step. */
 int fdtd_plasma_set_tiling(fdtd_plasma *h, int32_t tile, int32_t cells_per_group);
 
-/* Temporal blocking of a single 1D run in FP32 storage with the LINEAR model and Nv in
- * {64, 128, 256, 512}, or the TWO_TERM model with 17..64 speeds (rows padded to 32 or 64):
+/* Temporal blocking of a single 1D run in FP32 storage with the LINEAR or FULL model and Nv
+ * in {64, 128, 256, 512}, or the TWO_TERM model with 17..64 speeds (rows padded to 32 or 64):
  * fdtd_plasma_run advances `steps` time steps per kernel launch (each work-group
  * recomputes a halo of `steps` nodes per side, so F1 -- and F0 -- cross HBM once per
  * `steps` steps) and the remainder one step per launch.  steps = 1 turns it off; 3, 5, 7
  * and 9 are accepted.  Results are bitwise those of one-step launches (the kinetic step is
  * local in space, see section 5.2).  Default 7.  Other runs (FP64, batches of the
- * persistent mode, 2D, 3D, FULL, other speed counts, lines too short to cut into blocks)
+ * persistent mode, 2D, 3D, other speed counts, lines too short to cut into blocks)
  * step one step per launch; the call then only records the value.
  * May be called between runs.  fdtd_plasma_time_block reports the steps per launch in
  * effect (1 when the run is not blocked) and, if rows_per_launch is not NULL, the number of
