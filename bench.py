@@ -161,8 +161,8 @@ def bytes_1d_full(run):
 
 def extra_full(B, W, torch, steps=None):
     """The full-distribution model (F0 evolves, electrons heat) on the C1 line and on the
-    Nx = 2^20 line, FP32: K steps per launch (9 and 7, the measured best: 25.4 us against
-    26.1 at 7 and 41.1 at 1 on the C1 line, 347 us against 359 at 9 and 794 at 1 on 2^20),
+    Nx = 2^20 line, FP32: K steps per launch (9 and 7, the measured best: 23.7 us against
+    24.3 at 7 and 38.5 at 1 on the C1 line, 311 us against 327 at 9 and 777 at 1 on 2^20),
     and one step per launch beside it (2000 and 300 steps, or ``steps``)."""
     out = {}
     for key, run, steps, kb in (("full_c1", W.c1(steps=2000), steps or 2000, 9),
@@ -327,7 +327,7 @@ def extra_twoterm(B, W, torch, steps=2000):
     run.te_ev, run.vmax_over_vth = 1.0, 5.0
     log(f"two-term: Nx={run.nx} v_dim={run.nv} plasma cells={run.plasma_cells}")
     info = {}
-    # 9 steps per launch (measured: 3.24 us per step at 9, 3.45 at 7, 3.82 at 5, 7.73 at 1)
+    # 9 steps per launch (measured: 3.25 us per step at 9, 3.49 at 7, 3.82 at 5, 7.62 at 1)
     wall, ms = time_single(run, B, torch, steps, 54, 0, info, 9)
     kb, rows = info["time_block"], info["rows_per_launch"]
     wall1, ms1 = time_single(run, B, torch, steps, 50, 0, None, 1)

@@ -197,6 +197,25 @@ __device__ __forceinline__ double group_allreduce_dpp(double s) {
   return s;
 }
 
+// FP64 sum over an aligned lane group of lpc = 8, 16, 32 or 64 lanes, every lane returning
+// the total: group_allreduce_dpp inside each 16-lane row, then v_permlane16_swap joins row
+// pairs (32 lanes) and v_permlane32_swap the wave halves (64); each join adds the lower
+// lanes' value first on both sides, so every lane of the group ends with the same bits.
+// Other group sizes fall back to lane shuffles.
+__device__ __forceinline__ double row_sum_dpp(double s, int lpc, int li) {
+  if (lpc == 8) return group_allreduce_dpp<8>(s);
+  if (lpc == 16) return group_allreduce_dpp<16>(s);
+  if (lpc == 32 || lpc == 64) {
+    double t = group_allreduce_dpp<16>(s);
+    t = swap16_sum(t, t);
+    if (lpc == 64) t = swap32_sum(t, t);
+    return t;
+  }
+  double a1[1] = {s};
+  int which = 0;
+  return group_reduce<1>(a1, lpc, li, which);
+}
+
 // A neighbouring lane's value inside a 16-lane row (row_shl:1 -- lane l reads lane l + 1 --
 // and row_shr:1 -- lane l reads lane l - 1; 0 past the row's ends), an exact copy.
 __device__ __forceinline__ float from_next_lane(float v) {
@@ -204,6 +223,32 @@ __device__ __forceinline__ float from_next_lane(float v) {
 }
 __device__ __forceinline__ float from_prev_lane(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x111, 0xF, 0xF, true));
+}
+
+// The next / previous lane's value for rows of lpc lanes: DPP row shifts for rows of up to
+// 16 lanes (inside one 16-lane DPP row), wave rotations (wave_rol:1, wave_ror:1) for 32 and
+// 64, so that in a 64-lane row holding several chunks per lane the last lane reads lane 0
+// (the next chunk's first bin) and lane 0 the last lane; only lanes whose neighbour is in
+// their own row, or in the row's next / previous chunk, use the result.
+template <class T>
+__device__ __forceinline__ T next_lane_of_row(T v, int lpc) {
+  if constexpr (sizeof(T) == 4) {
+    const int x = __float_as_int(v);
+    return __int_as_float(lpc <= 16 ? __builtin_amdgcn_mov_dpp(x, 0x101, 0xF, 0xF, true)
+                                    : __builtin_amdgcn_mov_dpp(x, 0x134, 0xF, 0xF, true));
+  } else {
+    return lpc <= 16 ? dpp_f64<0x101>(v) : dpp_f64<0x134>(v);
+  }
+}
+template <class T>
+__device__ __forceinline__ T prev_lane_of_row(T v, int lpc) {
+  if constexpr (sizeof(T) == 4) {
+    const int x = __float_as_int(v);
+    return __int_as_float(lpc <= 16 ? __builtin_amdgcn_mov_dpp(x, 0x111, 0xF, 0xF, true)
+                                    : __builtin_amdgcn_mov_dpp(x, 0x13C, 0xF, 0xF, true));
+  } else {
+    return lpc <= 16 ? dpp_f64<0x111>(v) : dpp_f64<0x13C>(v);
+  }
 }
 
 struct Tile1D {

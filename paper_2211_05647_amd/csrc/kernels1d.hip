@@ -184,8 +184,6 @@ __device__ __forceinline__ void kinetic_tile_full(const Run1D<T>& R, const T* el
   const int lpc = ch < 64 ? ch : 64;      // lanes per row; ch == CPL * lpc by dispatch
   const int cpw = 64 / lpc;
   const int sub = lane / lpc, li = lane - sub * lpc;
-  const int nxt = sub * lpc + ((li + 1) & (lpc - 1));
-  const int prv = sub * lpc + ((li - 1) & (lpc - 1));
   const bool last_lane = li == lpc - 1, first_lane = li == 0;
 
   V s[CPL], b[CPL];
@@ -232,8 +230,8 @@ __device__ __forceinline__ void kinetic_tile_full(const Run1D<T>& R, const T* el
       T no[CPL], nev[CPL];
 #pragma unroll
       for (int m = 0; m < CPL; ++m) {
-        no[m] = __shfl(lane_at(o[m], 0), nxt);
-        nev[m] = __shfl(lane_at(e[m], 0), nxt);
+        no[m] = next_lane_of_row(lane_at(o[m], 0), lpc);
+        nev[m] = next_lane_of_row(lane_at(e[m], 0), lpc);
       }
 #pragma unroll
       for (int m = 0; m < CPL; ++m) {
@@ -263,7 +261,7 @@ __device__ __forceinline__ void kinetic_tile_full(const Run1D<T>& R, const T* el
     {
       T got[CPL];
 #pragma unroll
-      for (int m = 0; m < CPL; ++m) got[m] = __shfl(pr[m][VPL - 1], prv);
+      for (int m = 0; m < CPL; ++m) got[m] = prev_lane_of_row(pr[m][VPL - 1], lpc);
       const T pc = fma(cf, lane_at(e[0], 0), -cf * cf * lane_at(o[0], 0));  // face at v = 0
 #pragma unroll
       for (int m = 0; m < CPL; ++m)
@@ -296,7 +294,7 @@ __device__ __forceinline__ void kinetic_tile_full(const Run1D<T>& R, const T* el
     {
       T ns[CPL];
 #pragma unroll
-      for (int m = 0; m < CPL; ++m) ns[m] = __shfl(sm[m][0], nxt);
+      for (int m = 0; m < CPL; ++m) ns[m] = next_lane_of_row(sm[m][0], lpc);
 #pragma unroll
       for (int m = 0; m < CPL; ++m) {
 #pragma unroll
@@ -314,7 +312,7 @@ __device__ __forceinline__ void kinetic_tile_full(const Run1D<T>& R, const T* el
     {
       T got[CPL];
 #pragma unroll
-      for (int m = 0; m < CPL; ++m) got[m] = __shfl(qr[m][VPL - 1], prv);
+      for (int m = 0; m < CPL; ++m) got[m] = prev_lane_of_row(qr[m][VPL - 1], lpc);
 #pragma unroll
       for (int m = 0; m < CPL; ++m) {
         const T ql0 = !first_lane ? got[m] : (m > 0 ? got[m > 0 ? m - 1 : 0] : T(0));
@@ -334,9 +332,7 @@ __device__ __forceinline__ void kinetic_tile_full(const Run1D<T>& R, const T* el
         row[ch + li + m * lpc] = e[m];
       }
     }
-    double a1[1] = {acc};
-    int which = 0;
-    const double tot = group_reduce<1>(a1, lpc, li, which);
+    const double tot = row_sum_dpp(acc, lpc, li);   // DPP rounds, as the blocked kernel
     if (live && first_lane) jloc[loc] = (T)tot;
   }
 }
@@ -363,8 +359,6 @@ __device__ __forceinline__ void kinetic_tile_tt(const Run1D<T>& R, const T* eloc
   const int lpc = ch < 64 ? ch : 64;
   const int cpw = 64 / lpc;
   const int sub = lane / lpc, li = lane - sub * lpc;
-  const int nxt = sub * lpc + ((li + 1) & (lpc - 1));
-  const int prv = sub * lpc + ((li - 1) & (lpc - 1));
   const bool last_lane = li == lpc - 1, first_lane = li == 0;
 
   V s[CPL], b[CPL], cf[CPL], vh[CPL];
@@ -412,7 +406,7 @@ __device__ __forceinline__ void kinetic_tile_tt(const Run1D<T>& R, const T* eloc
 #pragma clang fp contract(off)
       T nf[CPL];
 #pragma unroll
-      for (int m = 0; m < CPL; ++m) nf[m] = __shfl(lane_at(f[m], 0), nxt);
+      for (int m = 0; m < CPL; ++m) nf[m] = next_lane_of_row(lane_at(f[m], 0), lpc);
       T ph[CPL][VPL];
 #pragma unroll
       for (int m = 0; m < CPL; ++m) {
@@ -427,7 +421,7 @@ __device__ __forceinline__ void kinetic_tile_tt(const Run1D<T>& R, const T* eloc
       }
       T got[CPL];
 #pragma unroll
-      for (int m = 0; m < CPL; ++m) got[m] = __shfl(ph[m][VPL - 1], prv);
+      for (int m = 0; m < CPL; ++m) got[m] = prev_lane_of_row(ph[m][VPL - 1], lpc);
 #pragma unroll
       for (int m = 0; m < CPL; ++m) {
         const T pl0 = !first_lane ? got[m] : (m > 0 ? got[m > 0 ? m - 1 : 0] : T(0));
@@ -444,8 +438,8 @@ __device__ __forceinline__ void kinetic_tile_tt(const Run1D<T>& R, const T* eloc
       T nd[CPL], pd[CPL];
 #pragma unroll
       for (int m = 0; m < CPL; ++m) {
-        nd[m] = __shfl(lane_at(d[m], 0), nxt);
-        pd[m] = __shfl(lane_at(d[m], VPL - 1), prv);
+        nd[m] = next_lane_of_row(lane_at(d[m], 0), lpc);
+        pd[m] = prev_lane_of_row(lane_at(d[m], VPL - 1), lpc);
       }
       const T nE = ne * Ev, kE = kd * Ev, tau2 = tau + tau;
       // the explicit exchange between F0 and F1 needs (e/m) |E| dt / gam <= 1
@@ -482,17 +476,8 @@ __device__ __forceinline__ void kinetic_tile_tt(const Run1D<T>& R, const T* eloc
       }
     }
     if (!flush) {
-      // rows of 8 or 16 lanes: the DPP tree the blocked kernel uses too
-      double tot;
-      if (lpc == 8) {
-        tot = group_allreduce_dpp<8>(acc);
-      } else if (lpc == 16) {
-        tot = group_allreduce_dpp<16>(acc);
-      } else {
-        double a1[1] = {acc};
-        int which = 0;
-        tot = group_reduce<1>(a1, lpc, li, which);
-      }
+      // DPP rounds: the tree the blocked kernel uses too
+      const double tot = row_sum_dpp(acc, lpc, li);
       if (live && first_lane) jloc[loc] = (T)tot;
     }
   }

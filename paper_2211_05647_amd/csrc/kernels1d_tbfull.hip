@@ -10,7 +10,7 @@
 // slots per lane group), and takes them through K steps.  Each sub-step updates a row with
 // the same operations, in the same order, as the one-step kernel's tile (odd pass with the
 // Lax-Wendroff corrected faces, even pass from the time-centred odd part, FP64 moment with
-// the same reduction tree), then H and E, so that a blocked run is bitwise the one-step
+// the same DPP reduction tree), then H and E, so that a blocked run is bitwise the one-step
 // run.  Rows are read from one copy and written to the other (in_off, out_off), so that no
 // work-group reads halo rows a neighbour of the same launch already advanced.
 //
@@ -69,8 +69,6 @@ __global__ __launch_bounds__(kTfBlock) void k_step1d_tb_full(
   const int wv = __builtin_amdgcn_readfirstlane(wave);
   constexpr int cpw = 64 / LPC;
   const int sub = lane / LPC, li = lane - sub * LPC;
-  const int nxt = sub * LPC + ((li + 1) & (LPC - 1));
-  const int prv = sub * LPC + ((li - 1) & (LPC - 1));
   const bool first_lane = li == 0, last_lane = li == LPC - 1;
   // slot q of lane group `sub` of wavefront w holds plasma row (q * waves + w) * cpw + sub
   auto row_slot = [&](int q, int w, int sb) { return (q * kTfWaves + w) * cpw + sb; };
@@ -121,8 +119,8 @@ __global__ __launch_bounds__(kTfBlock) void k_step1d_tb_full(
       // odd pass: perturbation face fluxes right of every bin
       float pr[4];
       {
-        const float no = __shfl(o[u].x, nxt);
-        const float nev = __shfl(e[u].x, nxt);
+        const float no = next_lane_of_row(o[u].x, LPC);
+        const float nev = next_lane_of_row(e[u].x, LPC);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           float orr, er;
@@ -143,7 +141,7 @@ __global__ __launch_bounds__(kTfBlock) void k_step1d_tb_full(
       }
       float pl0;
       {
-        const float got = __shfl(pr[3], prv);
+        const float got = prev_lane_of_row(pr[3], LPC);
         const float pc = fmaf(cf, lane_at(e[u], 0), -cf * cf * lane_at(o[u], 0));  // v = 0
         pl0 = !first_lane ? got : pc;
       }
@@ -167,7 +165,7 @@ __global__ __launch_bounds__(kTfBlock) void k_step1d_tb_full(
       {
 #pragma clang fp contract(off)
         float qr[4];
-        const float ns = __shfl(sm[0], nxt);
+        const float ns = next_lane_of_row(sm[0], LPC);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           float sr;
@@ -177,7 +175,7 @@ __global__ __launch_bounds__(kTfBlock) void k_step1d_tb_full(
           else { sr = 0.f; outer = true; }
           qr[v] = outer ? 0.f : cq * (sm[v] + sr);
         }
-        const float got = __shfl(qr[3], prv);
+        const float got = prev_lane_of_row(qr[3], LPC);
         const float ql0 = !first_lane ? got : 0.f;
         if (live) {
 #pragma unroll
@@ -188,9 +186,7 @@ __global__ __launch_bounds__(kTfBlock) void k_step1d_tb_full(
           o[u] = on;
         }
       }
-      double a1[1] = {acc};
-      int which = 0;
-      const double tot = group_reduce<1>(a1, LPC, li, which);
+      const double tot = row_sum_dpp(acc, LPC, li);
       if (live && first_lane) Js[lc] = (float)tot;
     }
     __syncthreads();
