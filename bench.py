@@ -236,7 +236,8 @@ def bytes_3d_tt(run, npoints, ncells, row):
 def extra_3d(B, W, torch, steps=300, kinetic="linear"):
     """The paper's production model in 3D: the argon-style slab (Druyvesteyn F0, v_dim = 31
     speeds, a 4 mm slab along z, sheet source, CPML on all faces) at 128 x 128 x 512, with
-    F0 held (linear) or evolving in every plasma cell (two_term)."""
+    F0 held (linear) or evolving in every plasma cell (two_term; its slab ends where the x
+    and y absorbing layers begin, which that model needs to stay stable)."""
     tt = kinetic == "two_term"
     run = W.argon_slab_3d(nx=128, ny=128, nz=512, steps=steps, kinetic=kinetic)
     sim = B.Sim(run, precision=B.FP32)

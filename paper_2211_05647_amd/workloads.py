@@ -290,10 +290,18 @@ def argon_nubar(te_ev=ARGON_TE, f0="druyvesteyn"):
 
 
 def argon_slab_3d(nx=64, ny=64, nz=256, nv=31, steps=1200, slab_mm=4.0, ncpml=8,
-                  f0="druyvesteyn", name="argon3d", kinetic="linear") -> Run3D:
+                  f0="druyvesteyn", name="argon3d", kinetic="linear",
+                  plasma_in_cpml=None) -> Run3D:
     """The paper's 3D slab: air, a slab_mm plasma slab along z starting at the middle of
     the box, air; a sheet source of Ex (a plane wave along z) 12 cells inside the low z
-    layer; CPML on all faces; density 1e19 m^-3 with +-5 % seeded cell-to-cell texture."""
+    layer; CPML on all faces; density 1e19 m^-3 with +-5 % seeded cell-to-cell texture.
+
+    plasma_in_cpml: whether the slab runs on through the x and y absorbing layers (default:
+    yes for the linear model, no for the two-term one).  With its point set (E points whose
+    four cells all hold plasma) the two-term model has a mode that grows by about 6x per
+    500 steps once plasma lies inside those layers (the FP64 oracle grows alike, and so
+    does the linear model restricted to that point set); with the slab ending where the
+    layers begin it decays."""
     g = rng("misc")
     ne = np.zeros((nz, ny, nx))
     nu = np.zeros((nz, ny, nx))
@@ -301,6 +309,14 @@ def argon_slab_3d(nx=64, ny=64, nz=256, nv=31, steps=1200, slab_mm=4.0, ncpml=8,
     k1 = k0 + max(1, int(round(slab_mm * 1e-3 / DX_REF)))
     ne[k0:k1] = ARGON_NE * (1.0 + 0.05 * (2.0 * g.random((k1 - k0, ny, nx)) - 1.0))
     nu[k0:k1] = argon_nubar(f0=f0)
+    if plasma_in_cpml is None:
+        plasma_in_cpml = kinetic != "two_term"
+    if not plasma_in_cpml and ncpml > 0:
+        for a in (ne, nu):
+            a[:, :, :ncpml] = 0.0
+            a[:, :, nx - ncpml:] = 0.0
+            a[:, :ncpml, :] = 0.0
+            a[:, ny - ncpml:, :] = 0.0
     p = dict(src_amp=1.0, src_f=20e9, src_tau=48e-12, src_t0=217e-12)
     return Run3D(name=name, nx=nx, ny=ny, nz=nz, nv=nv, ne=ne, nubar=nu, src_kind=1, src_i=0,
                  src_j=0, src_k=ncpml + 4, steps=steps, ncpml=ncpml, f0_model=f0,

@@ -169,3 +169,21 @@ def test_two_term_without_plasma_points(gpu_lib):
     df = a.read(B.F_DF)
     assert df.size == 20 * run.nv and np.all(df == 0.0)
     a.close(); b.close()
+
+
+def test_benchmark_workload_stays_bounded(gpu_lib):
+    """The benchmark's two-term workload (slab ending where the x and y absorbing layers
+    begin) run well past the pulse: the field after 6000 steps has decayed far below its
+    value at step 1000 and no speed bin tripped the CFL flag (with the slab running on
+    through those layers the same run grows about 30x per 1000 steps)."""
+    run = W.argon_slab_3d(nx=128, ny=128, nz=512, steps=6000, kinetic="two_term")
+    _banner("argon slab two-term, full size, 6000 steps")
+    sim = B.Sim(run, precision=B.FP32)
+    sim.run(1000)
+    early = np.abs(sim.read(B.F_EX)).max()
+    sim.run(5000)
+    late = np.abs(sim.read(B.F_EX)).max()
+    _banner(f"  max|Ex| step 1000 {early:.3e}, step 6000 {late:.3e}")
+    assert early > 0 and late < 1e-2 * early
+    assert sim.run_status(0) == 0
+    sim.close()
