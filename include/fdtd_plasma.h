@@ -144,7 +144,11 @@ typedef struct {
  * drive takes the mean F0 of its four cells, and each cell's l = 0 update takes a
  * quarter of E.F1 from each of its plasma edges (E time-centred), so the field energy
  * J removes is exactly the heat the cells gain; the explicit-exchange limit and the
- * run status are as in 1D.  Four launches per step instead of three. */
+ * run status are as in 1D.  Four launches per step instead of three.  Keep 3D TWO_TERM
+ * plasma (ne > 0) out of the x and y absorbing layers.  With plasma inside them, this
+ * point set carries a mode that grows by tens per thousand steps until the fields
+ * overflow.  The library does not refuse such a profile: short runs are still correct.
+ * Readback then reports the non-finite values as an error. */
 typedef struct {
   const double *ne;
   const double *nu_mean;
