@@ -116,6 +116,24 @@ def test_seeded_workloads_are_reproducible():
     assert all(500 <= x.nx <= 20000 and x.steps == 2 * x.nx for x in runs)
 
 
+def test_two_term_slab_stays_out_of_the_side_layers():
+    """The 3D slab runs through the x and y absorbing layers for the linear model and stops
+    where they begin for the two-term model (whose point set grows a mode with plasma in
+    them); the slab's cells inside the box are the same in both."""
+    m = 6
+    lin = W.argon_slab_3d(nx=20, ny=18, nz=48, ncpml=m, steps=0)
+    tt = W.argon_slab_3d(nx=20, ny=18, nz=48, ncpml=m, steps=0, kinetic="two_term")
+    k0, k1 = lin.meta["slab"]
+    assert np.all(lin.ne[k0:k1] > 0)
+    side = np.ones(lin.ne.shape[1:], bool)
+    side[m:-m, m:-m] = False
+    assert np.all(tt.ne[:, side] == 0) and np.all(tt.nubar[:, side] == 0)
+    assert np.array_equal(tt.ne[:, ~side], lin.ne[:, ~side])
+    forced = W.argon_slab_3d(nx=20, ny=18, nz=48, ncpml=m, steps=0, kinetic="two_term",
+                             plasma_in_cpml=True)
+    assert np.array_equal(forced.ne, lin.ne)
+
+
 def test_struct_layouts_match_the_header(tmp_path):
     """The ctypes mirrors of the ABI structs have the size and field offsets the C
     compiler gives the header's structs (a field added on one side only would shift every
