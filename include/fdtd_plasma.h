@@ -144,11 +144,11 @@ typedef struct {
  * drive takes the mean F0 of its four cells, and each cell's l = 0 update takes a
  * quarter of E.F1 from each of its plasma edges (E time-centred), so the field energy
  * J removes is exactly the heat the cells gain; the explicit-exchange limit and the
- * run status are as in 1D.  Four launches per step instead of three.  Keep 3D TWO_TERM
- * plasma (ne > 0) out of the x and y absorbing layers.  With plasma inside them, this
- * point set carries a mode that grows by tens per thousand steps until the fields
- * overflow.  The library does not refuse such a profile: short runs are still correct.
- * Readback then reports the non-finite values as an error. */
+ * run status are as in 1D.  Four launches per step instead of three.  3D TWO_TERM
+ * plasma (ne > 0) must stay out of the x and y absorbing layers (the outer cpml_cells
+ * cells of x and y): with plasma inside them this point set carries a mode that grows
+ * by tens per thousand steps until the fields overflow, so fdtd_plasma_create refuses
+ * such a profile with FDTD_EINVAL. */
 typedef struct {
   const double *ne;
   const double *nu_mean;
@@ -200,9 +200,13 @@ int fdtd_plasma_create(const fdtd_grid *grid, const fdtd_profile *profile,
  * advanced together.  steps[r] is the step count of run r: fdtd_plasma_run advances
  * every run to min(its own count, the batch step).  ntap (0..8) training-pair taps per
  * run record (E^n, J^{n+1/2}) at the plasma nodes tap_nodes[r * ntap + k] after every
- * step of that run (NULL when ntap = 0).  Default launch: one launch per step over the
- * tiles of the runs still active (see fdtd_plasma_set_batch_mode for the persistent
- * form).  Workspace size via fdtd_plasma_workspace_size_batch. */
+ * step of that run (NULL when ntap = 0).  Default launch form (batch mode 1): the runs
+ * with at least K steps left advance K steps per launch (temporal blocking, K from
+ * fdtd_plasma_set_time_block, default 7), one launch per Nv group; runs that end inside
+ * such a pass, and the batch's tail once fewer blocked work-groups than compute units
+ * remain, take one step per launch over the tiles of the runs still active.  See
+ * fdtd_plasma_set_batch_mode for the persistent form.  Workspace size via
+ * fdtd_plasma_workspace_size_batch. */
 int fdtd_plasma_workspace_size_batch(int32_t nruns, const fdtd_grid *grids,
                                      const fdtd_profile *profiles, const int64_t *steps,
                                      int32_t ntap, const fdtd_device *dev, size_t *bytes);
@@ -214,8 +218,9 @@ int fdtd_plasma_create_batch(int32_t nruns, const fdtd_grid *grids,
 /* Batch launch form: mode 0 = one persistent launch per fdtd_plasma_run, `groups`
  * work-groups (0 = one per run, at most two per compute unit) each pulling whole runs
  * longest-first from a queue and taking them through every step alone; mode 1 (default)
- * = one launch per step over the tiles of the runs still active.  Both give bitwise
- * identical results.  Only before the first step. */
+ * = K-step blocked launches with one-step launches for the remainders, as described at
+ * fdtd_plasma_create_batch.  Both give bitwise identical results.  Only before the first
+ * step. */
 int fdtd_plasma_set_batch_mode(fdtd_plasma *h, int32_t mode, int32_t groups);
 
 /* Copy the taps of run `run`: [ntap][steps taken by that run][2] doubles, (E in V/m,
@@ -243,6 +248,17 @@ int fdtd_plasma_field_size(const fdtd_plasma *h, int32_t run, int32_t field, siz
  * step count of that run.  FDTD_ENUMERIC if the copied field holds a NaN or Inf. */
 int fdtd_plasma_read_fields(fdtd_plasma *h, int32_t run, int32_t field, double *dst,
                             size_t dst_len, int64_t *step_out);
+
+/* Overwrite a field of the current state with host values in SI units (E in V/m, H in
+ * A/m), in the read_fields layout: initial conditions such as the section 4 validation's
+ * travelling Gaussian pulse, or a cavity mode.  Writable: 1D FDTD_F_E and FDTD_F_H
+ * (E^n and H^{n-1/2} of run `run`), 2D FDTD_F_EX, _EY, _HZ, 3D FDTD_F_EX, _EY, _EZ,
+ * _HX, _HY, _HZ.  Values are rounded to the storage precision.  src_len must equal the
+ * field's size (FDTD_ERANGE otherwise); a non-finite value or another field gives
+ * FDTD_EINVAL and writes nothing.  Synchronises the handle's stream.  The learned
+ * closure's field history (2D) and the absorbing-layer memories are not rewritten. */
+int fdtd_plasma_write_fields(fdtd_plasma *h, int32_t run, int32_t field, const double *src,
+                             size_t src_len);
 
 /* Record `field` at grid index (i, j) after every step (1D: j ignored).  Only before
  * the first step; at most fdtd_device.max_probes.  *id receives the probe id.  3D handles
@@ -278,7 +294,9 @@ int fdtd_plasma_set_tiling(fdtd_plasma *h, int32_t tile, int32_t cells_per_group
  * recomputes a halo of `steps` nodes per side, so F1 -- and F0 -- cross HBM once per
  * `steps` steps) and the remainder one step per launch.  steps = 1 turns it off; 3, 5, 7
  * and 9 are accepted.  Results are bitwise those of one-step launches (the kinetic step is
- * local in space, see section 5.2).  Default 7.  Other runs (FP64, batches of the
+ * local in space, see section 5.2).  The library's default is 7; a caller with a tuning
+ * table sets its own (the Python package's autotuner stores 9 for the 65,536-node line
+ * at Nv = 512).  Other runs (FP64, batches of the
  * persistent mode, 2D, 3D, other speed counts, lines too short to cut into blocks)
  * step one step per launch; the call then only records the value.
  * May be called between runs.  fdtd_plasma_time_block reports the steps per launch in

@@ -31,6 +31,7 @@ def lib():
         L.oracle_collision1v.argtypes = [C.c_int, _dp, _dp, _dp]
         L.oracle_constants.argtypes = [_dp]
         L.oracle_threads.argtypes = []
+        L.oracle_set_threads.argtypes = [C.c_int]
         L.oracle_cpml_profile.argtypes = [C.c_int, C.c_int] + [C.c_double] * 7 + [_dp] * 6
         L.oracle_run1d.argtypes = (
             [C.c_int, C.c_double, C.c_double, C.c_int,
@@ -100,6 +101,11 @@ def _p(a):
 def threads():
     """OpenMP threads the oracle's parallel loops use."""
     return int(lib().oracle_threads())
+
+
+def set_threads(n):
+    """Use n threads in the oracle's parallel loops from now on; returns the count."""
+    return int(lib().oracle_set_threads(int(n)))
 
 
 def constants():

@@ -93,6 +93,17 @@ int oracle_threads(void)
 #endif
 }
 
+/* threads the following parallel loops use (n >= 1): lets a caller time the oracle on
+ * one core as well as on all of them */
+int oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#endif
+    (void)n;
+    return oracle_threads();
+}
+
 int oracle_constants(double *out4)
 {
     out4[0] = K_C0; out4[1] = K_EPS0; out4[2] = K_QE; out4[3] = K_ME;
@@ -426,7 +437,9 @@ static double o_gelu(double x)
     return 0.5 * x * (1.0 + tanh(sqrt(2.0 / K_PI) * (x + 0.044715 * x * x * x)));
 }
 
-double oracle_mlp(const double *p, const double *x, int bf)
+/* the network on weights already in their working precision (rounded to bfloat16 by
+ * mlp_round_weights when bf != 0); features and first-layer activations are rounded here */
+static double mlp_eval(const double *p, const double *x, int bf)
 {
     const double *W1 = p, *b1 = p + 2304, *W2 = p + 2432, *b2 = p + 18816, *w3 = p + 18944;
     const double b3 = p[19072];
@@ -434,21 +447,46 @@ double oracle_mlp(const double *p, const double *x, int bf)
     for (int k = 0; k < 18; ++k) xq[k] = bf ? o_bf16(x[k]) : x[k];
     for (int n = 0; n < 128; ++n) {
         double z = 0.0;
-        for (int k = 0; k < 18; ++k) z += (bf ? o_bf16(W1[n * 18 + k]) : W1[n * 18 + k]) * xq[k];
+        for (int k = 0; k < 18; ++k) z += W1[n * 18 + k] * xq[k];
         z += b1[n];
         a1[n] = bf ? o_bf16(o_gelu(z)) : o_gelu(z);
     }
     double y = 0.0;
     for (int n = 0; n < 128; ++n) {
         double z = 0.0;
-        for (int k = 0; k < 128; ++k) z += (bf ? o_bf16(W2[n * 128 + k]) : W2[n * 128 + k]) * a1[k];
+        for (int k = 0; k < 128; ++k) z += W2[n * 128 + k] * a1[k];
         z += b2[n];
-        y += o_gelu(z) * (bf ? o_bf16(w3[n]) : w3[n]);
+        y += o_gelu(z) * w3[n];
     }
     return y + b3;
 }
 
-/* one closure step of one current component; hist[0..15] newest first, shifted in place */
+/* copy of the 19073 parameters with W1, W2 and w3 rounded to bfloat16 when bf != 0
+ * (biases stay as they are); the caller frees it */
+static double *mlp_round_weights(const double *p, int bf)
+{
+    double *q = malloc(sizeof(double) * 19073);
+    if (!q) return NULL;
+    memcpy(q, p, sizeof(double) * 19073);
+    if (bf) {
+        for (int k = 0; k < 2304; ++k) q[k] = o_bf16(q[k]);
+        for (int k = 2432; k < 18816; ++k) q[k] = o_bf16(q[k]);
+        for (int k = 18944; k < 19072; ++k) q[k] = o_bf16(q[k]);
+    }
+    return q;
+}
+
+double oracle_mlp(const double *p, const double *x, int bf)
+{
+    double *q = mlp_round_weights(p, bf);
+    if (!q) return NAN;
+    const double y = mlp_eval(q, x, bf);
+    free(q);
+    return y;
+}
+
+/* one closure step of one current component; hist[0..15] newest first, shifted in place;
+ * params as given by mlp_round_weights */
 static double closure_step(double *hist, double e, double jprev, const double *coef,
                            const double *params, int bf)
 {
@@ -461,7 +499,7 @@ static double closure_step(double *hist, double e, double jprev, const double *c
     for (int k = 0; k < 16; ++k) x[k] = hist[k] / s;
     x[16] = coef[2];
     x[17] = coef[3];
-    double y = oracle_mlp(params, x, bf);
+    double y = mlp_eval(params, x, bf);
     return coef[0] * jprev + coef[1] * (e + s * y);
 }
 
@@ -498,6 +536,12 @@ int oracle_run2d(int nx, int ny, double dx, double courant,
     if (nx < 2 || ny < 2 || nv < 2 || dx <= 0.0) return -1;
     if (courant <= 0.0 || courant > 1.0 / sqrt(2.0)) return -1;
     if (2 * ncpml >= nx || 2 * ncpml >= ny) return -1;
+    /* the network's weights in their working precision, rounded once */
+    double *mlp_w = NULL;
+    if (cell_mode) {
+        mlp_w = mlp_round_weights(mlp_params, emulate_bf16);
+        if (!mlp_w) return -1;
+    }
     const double dt = courant * dx / K_C0;
     const size_t nEx = (size_t)nx * (ny + 1), nEy = (size_t)(nx + 1) * ny, nHz = (size_t)nx * ny;
     double *psi_exy = psi, *psi_eyx = psi + nEx, *psi_hzx = psi + nEx + nEy, *psi_hzy = psi_hzx + nHz;
@@ -507,7 +551,7 @@ int oracle_run2d(int nx, int ny, double dx, double courant,
     double *gh = malloc(sizeof(double) * nv), *sh = malloc(sizeof(double) * nv * nv);
     double dv, vth;
     if (oracle_vgrid(nv, vmax_over_vth, te_ev, v, fh, gh, &dv, &vth) != 0) {
-        free(v); free(fh); free(gh); free(sh); return -1;
+        free(v); free(fh); free(gh); free(sh); free(mlp_w); return -1;
     }
     oracle_nu_shape(2, nv, v, fh, dv, nu_model, sh);
     const int nv2 = nv * nv;
@@ -561,9 +605,9 @@ int oracle_run2d(int nx, int ny, double dx, double courant,
             if (cell_mode && cell_mode[c] == 1) {
                 const double *cf = clo_coef + 4 * (size_t)c;
                 clo_J[2 * c] = closure_step(clo_hist + 32 * (size_t)c, exc, clo_J[2 * c], cf,
-                                            mlp_params, emulate_bf16);
+                                            mlp_w, emulate_bf16);
                 clo_J[2 * c + 1] = closure_step(clo_hist + 32 * (size_t)c + 16, eyc,
-                                                clo_J[2 * c + 1], cf, mlp_params, emulate_bf16);
+                                                clo_J[2 * c + 1], cf, mlp_w, emulate_bf16);
                 jbx[k] = clo_J[2 * c] * K_EPS0 / dt;
                 jby[k] = clo_J[2 * c + 1] * K_EPS0 / dt;
                 continue;
@@ -631,7 +675,7 @@ int oracle_run2d(int nx, int ny, double dx, double courant,
     free(v); free(fh); free(gh); free(sh); free(gx); free(gy);
     free(bex); free(aex); free(kex); free(bhx); free(ahx); free(khx);
     free(bey); free(aey); free(key); free(bhy); free(ahy); free(khy);
-    free(cell_idx); free(jbx); free(jby);
+    free(cell_idx); free(jbx); free(jby); free(mlp_w);
     return 0;
 }
 

@@ -74,6 +74,7 @@ _SIGS = {
     "fdtd_plasma_steps": ([C.c_void_p, C.POINTER(C.c_int64)], C.c_int),
     "fdtd_plasma_field_size": ([C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)], C.c_int),
     "fdtd_plasma_read_fields": ([C.c_void_p, C.c_int32, C.c_int32, _dp, C.c_size_t, C.POINTER(C.c_int64)], C.c_int),
+    "fdtd_plasma_write_fields": ([C.c_void_p, C.c_int32, C.c_int32, _dp, C.c_size_t], C.c_int),
     "fdtd_plasma_add_probe": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
     "fdtd_plasma_add_probe3d": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
     "fdtd_plasma_read_probe": ([C.c_void_p, C.c_int32, _dp, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
@@ -264,6 +265,12 @@ class Sim:
         check(lib().fdtd_plasma_read_fields(self.h, run, field, out.ctypes.data_as(_dp), out.size, C.byref(st)),
               "read_fields")
         return out
+
+    def write(self, field, values, run=0):
+        """Overwrite a field (SI units, read_fields layout) of the current state."""
+        v = np.ascontiguousarray(values, dtype=np.float64).ravel()
+        check(lib().fdtd_plasma_write_fields(self.h, run, field, v.ctypes.data_as(_dp), v.size),
+              "write_fields")
 
     def add_probe(self, field, i, j=0, run=0):
         pid = C.c_int32()

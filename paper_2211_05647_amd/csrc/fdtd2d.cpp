@@ -427,6 +427,26 @@ int field_size_2d(const Host2D* h, int field, size_t* n) {
   }
 }
 
+int write_2d(Host2D* h, char* ws, int field, const double* src) {
+  const int nx = h->nx, ny = h->ny, es = h->es;
+  size_t off = 0, cnt = 0;
+  double scale = 1.0;
+  switch (field) {
+    case FDTD_F_EX: off = h->off_Ex; cnt = (size_t)(ny + 1) * nx; break;
+    case FDTD_F_EY: off = h->off_Ey; cnt = (size_t)ny * (nx + 1); break;
+    case FDTD_F_HZ: off = h->off_Hz; cnt = (size_t)ny * nx; scale = kEta0; break;
+    default: return fail(FDTD_EINVAL, "field %d cannot be written on a 2D grid", field);
+  }
+  std::vector<char> buf(std::max<size_t>(cnt, 1) * es);
+  for (size_t k = 0; k < cnt; ++k) {
+    if (es == 8) reinterpret_cast<double*>(buf.data())[k] = src[k] * scale;
+    else reinterpret_cast<float*>(buf.data())[k] = (float)(src[k] * scale);
+  }
+  hipError_t e = hipMemcpy(ws + off, buf.data(), cnt * es, hipMemcpyHostToDevice);
+  if (e) return hip_fail(e, "write 2D field");
+  return FDTD_OK;
+}
+
 int read_2d(Host2D* h, char* ws, int field, int64_t, double* dst) {
   const int nx = h->nx, ny = h->ny, es = h->es;
   auto grab = [&](size_t off, size_t cnt, std::vector<double>& out) -> int {

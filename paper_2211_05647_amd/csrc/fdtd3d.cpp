@@ -416,6 +416,21 @@ int validate_3d(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s)
     if (!(p->nu_mean[k] >= 0.0) || !std::isfinite(p->nu_mean[k]))
       return fail(FDTD_EINVAL, "nu_mean[%zu] must be finite and >= 0", k);
   }
+  // The two-term point set (E points whose four cells all hold plasma) with plasma inside
+  // the x or y absorbing layers carries a mode that grows until the fields overflow (the
+  // FP64 reference grows alike), so such a profile is refused rather than run.
+  if (p->kinetic == FDTD_KINETIC_TWO_TERM && g->boundary == FDTD_BC_CPML) {
+    const int m = g->cpml_cells;
+    for (int k = 0; k < g->nz; ++k)
+      for (int j = 0; j < g->ny; ++j)
+        for (int i = 0; i < g->nx; ++i) {
+          const bool side = i < m || i >= g->nx - m || j < m || j >= g->ny - m;
+          if (side && p->ne[((size_t)k * g->ny + j) * g->nx + i] > 0.0)
+            return fail(FDTD_EINVAL,
+                        "3D two-term plasma inside the x/y absorbing layers (cell i=%d j=%d "
+                        "k=%d): keep ne = 0 in the outer %d cells of x and y", i, j, k, m);
+        }
+  }
   if (s && s->kind != FDTD_SRC_NONE) {
     if (s->kind != FDTD_SRC_LINE_SOFT && s->kind != FDTD_SRC_POINT_SOFT)
       return fail(FDTD_EINVAL, "3D source must be a sheet (LINE) or a point");
@@ -498,6 +513,29 @@ int field_size_3d(const Host3D* h, int field, size_t* n) {
     case FDTD_F_DF: *n = (size_t)(h->np + h->nc) * h->vdim; return FDTD_OK;
     default: return fail(FDTD_EINVAL, "field %d not defined on a 3D grid", field);
   }
+}
+
+int write_3d(Host3D* h, char* ws, int field, const double* src) {
+  size_t off = 0, cnt = 0;
+  double scale = 1.0;
+  const size_t es = h->es;
+  switch (field) {
+    case FDTD_F_EX: off = h->off_E; cnt = h->nE[0]; break;
+    case FDTD_F_EY: off = h->off_E + h->nE[0] * es; cnt = h->nE[1]; break;
+    case FDTD_F_EZ: off = h->off_E + (h->nE[0] + h->nE[1]) * es; cnt = h->nE[2]; break;
+    case FDTD_F_HX: off = h->off_H; cnt = h->nH[0]; scale = kEta0; break;
+    case FDTD_F_HY: off = h->off_H + h->nH[0] * es; cnt = h->nH[1]; scale = kEta0; break;
+    case FDTD_F_HZ: off = h->off_H + (h->nH[0] + h->nH[1]) * es; cnt = h->nH[2]; scale = kEta0; break;
+    default: return fail(FDTD_EINVAL, "field %d cannot be written on a 3D grid", field);
+  }
+  std::vector<char> buf(std::max<size_t>(cnt, 1) * es);
+  for (size_t k = 0; k < cnt; ++k) {
+    if (es == 8) reinterpret_cast<double*>(buf.data())[k] = src[k] * scale;
+    else reinterpret_cast<float*>(buf.data())[k] = (float)(src[k] * scale);
+  }
+  hipError_t e = hipMemcpy(ws + off, buf.data(), cnt * es, hipMemcpyHostToDevice);
+  if (e) return hip_fail(e, "write 3D field");
+  return FDTD_OK;
 }
 
 int read_3d(Host3D* h, char* ws, int field, double* dst) {

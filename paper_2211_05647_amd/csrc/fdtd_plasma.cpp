@@ -1127,6 +1127,42 @@ int fdtd_plasma_read_fields(fdtd_plasma* h, int32_t run, int32_t field, double* 
   return FDTD_OK;
 }
 
+int fdtd_plasma_write_fields(fdtd_plasma* h, int32_t run, int32_t field, const double* src,
+                             size_t src_len) {
+  if (!h || !src) return fail(FDTD_EINVAL, "null argument");
+  const bool ok = h->dims == 1   ? (field == FDTD_F_E || field == FDTD_F_H)
+                  : h->dims == 2 ? (field == FDTD_F_EX || field == FDTD_F_EY || field == FDTD_F_HZ)
+                                 : (field == FDTD_F_EX || field == FDTD_F_EY || field == FDTD_F_EZ ||
+                                    field == FDTD_F_HX || field == FDTD_F_HY || field == FDTD_F_HZ);
+  if (!ok) return fail(FDTD_EINVAL, "field %d cannot be written on a %dD grid", field, h->dims);
+  size_t n = 0;
+  int rc = fdtd_plasma_field_size(h, run, field, &n);
+  if (rc) return rc;
+  if (src_len != n) return fail(FDTD_ERANGE, "source holds %zu values, the field %zu", src_len, n);
+  for (size_t k = 0; k < n; ++k)
+    if (!std::isfinite(src[k])) return fail(FDTD_EINVAL, "non-finite value at index %zu", k);
+  hipError_t e = hipSetDevice(h->device);
+  if (e) return hip_fail(e, "hipSetDevice");
+  e = hipStreamSynchronize(h->stream);
+  if (e) return hip_fail(e, "synchronise");
+  if (h->dims == 2) return write_2d(h->h2, h->ws, field, src);
+  if (h->dims == 3) return write_3d(h->h3, h->ws, field, src);
+  const Host1D& x = h->h1[run];
+  const int es = elem_size(h->precision);
+  const int64_t srun = std::min<int64_t>(h->step, h->specs[run].steps);
+  const int par = (int)(srun & 1);
+  const size_t off = field == FDTD_F_E ? x.off_E[par] : x.off_H[par];
+  const double scale = field == FDTD_F_E ? 1.0 : kEta0;
+  std::vector<char> buf(std::max<size_t>(n, 1) * es);
+  for (size_t k = 0; k < n; ++k) {
+    if (es == 8) reinterpret_cast<double*>(buf.data())[k] = src[k] * scale;
+    else reinterpret_cast<float*>(buf.data())[k] = (float)(src[k] * scale);
+  }
+  e = hipMemcpy(h->ws + off, buf.data(), n * es, hipMemcpyHostToDevice);
+  if (e) return hip_fail(e, "write field");
+  return FDTD_OK;
+}
+
 int fdtd_plasma_add_probe(fdtd_plasma* h, int32_t run, int32_t field, int32_t i, int32_t j,
                           int32_t* id) {
   if (!h || !id) return fail(FDTD_EINVAL, "null argument");

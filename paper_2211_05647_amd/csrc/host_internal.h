@@ -114,6 +114,7 @@ int upload_2d(Host2D* h, char* ws, hipStream_t stream, const std::vector<ProbeIn
 hipError_t launch_step2d(Host2D* h, int64_t step, hipStream_t stream);
 int field_size_2d(const Host2D* h, int field, size_t* n);
 int read_2d(Host2D* h, char* ws, int field, int64_t step, double* dst);
+int write_2d(Host2D* h, char* ws, int field, const double* src);
 int check_probe_2d(const Host2D* h, int field, int i, int j);
 double probe_scale_2d(const Host2D* h, int field);
 int set_tiling_2d(Host2D* h, char* ws, hipStream_t stream, int tile, int cells_per_group);
@@ -133,6 +134,7 @@ int points_3d(const Host3D* h);
 int status_3d(Host3D* h, char* ws, int32_t* v);
 int field_size_3d(const Host3D* h, int field, size_t* n);
 int read_3d(Host3D* h, char* ws, int field, double* dst);
+int write_3d(Host3D* h, char* ws, int field, const double* src);
 void destroy_3d(Host3D* h);
 
 

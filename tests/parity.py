@@ -84,3 +84,41 @@ def space_time_3d(sim, orc, nsteps, every):
             out[name][0].append(np.concatenate([sim.read(f) for f in fs]))
             out[name][1].append(ref.copy())
     return {k: (np.array(a), np.array(b)) for k, (a, b) in out.items()}
+
+
+def max_rel(a, b):
+    """Largest single-element error relative to the largest reference magnitude: bounds an
+    error confined to a few cells, which a whole-array relative L2 can average away."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = float(np.max(np.abs(b))) if b.size else 0.0
+    return float(np.max(np.abs(a - b)) / (den if den > 0 else 1.0)) if b.size else 0.0
+
+
+class ErrSum:
+    """Running relative L2 and max-abs figures over pairs of arrays compared one at a time
+    (so that large snapshots need not be kept)."""
+
+    def __init__(self):
+        self.d2 = 0.0
+        self.r2 = 0.0
+        self.dmax = 0.0
+        self.rmax = 0.0
+
+    def add(self, a, b):
+        a = np.asarray(a, dtype=np.float64)
+        b = np.asarray(b, dtype=np.float64)
+        d = a - b
+        self.d2 += float(np.dot(d, d))
+        self.r2 += float(np.dot(b, b))
+        if d.size:
+            self.dmax = max(self.dmax, float(np.max(np.abs(d))))
+            self.rmax = max(self.rmax, float(np.max(np.abs(b))))
+
+    @property
+    def rel_l2(self):
+        return float(np.sqrt(self.d2 / self.r2)) if self.r2 > 0 else float(np.sqrt(self.d2))
+
+    @property
+    def max_rel(self):
+        return self.dmax / self.rmax if self.rmax > 0 else self.dmax

@@ -134,6 +134,48 @@ def test_two_term_slab_stays_out_of_the_side_layers():
     assert np.array_equal(forced.ne, lin.ne)
 
 
+def _grid_profile_3d(run, precision=B.FP32):
+    g = B.make_grid(3, run.nx, run.ny, run.dx, run.courant, precision, B.BC_CPML, run.ncpml,
+                    nz=run.nz)
+    ne = np.ascontiguousarray(run.ne, dtype=np.float64)
+    nu = np.ascontiguousarray(run.nubar, dtype=np.float64)
+    p = B.Profile(ne.ctypes.data_as(C.POINTER(C.c_double)), nu.ctypes.data_as(C.POINTER(C.c_double)),
+                  run.te_ev, run.nv, run.vmax_over_vth, B.NU_HARD_SPHERE, B.CLOSURE_KINETIC, None,
+                  B.KINETIC_TWO_TERM, B.F0_DRUYVESTEYN)
+    return g, p, (ne, nu)
+
+
+@pytest.mark.parametrize("where", ["x_low", "x_high", "y_low", "y_high"])
+def test_two_term_3d_plasma_in_the_side_layers_is_refused(where):
+    """The 3D two-term model refuses plasma inside the x or y absorbing layers (its point
+    set grows a mode there until the fields overflow) before touching a device, both when
+    sizing the workspace and at create; a single plasma cell in a layer is enough, and the
+    same box with that cell emptied is accepted."""
+    L = B.lib()
+    m = 6
+    run = W.argon_slab_3d(nx=20, ny=18, nz=48, ncpml=m, steps=0, kinetic="two_term")
+    k0, _ = run.meta["slab"]
+    g, p, keep = _grid_profile_3d(run)
+    n = C.c_size_t()
+    assert L.fdtd_plasma_workspace_size(C.byref(g), C.byref(p), None, C.byref(n)) == B.OK
+    j, i = {"x_low": (9, m - 1), "x_high": (9, run.nx - m), "y_low": (m - 1, 10),
+            "y_high": (run.ny - m, 10)}[where]
+    assert run.ne[k0, j, i] == 0.0
+    run.ne[k0, j, i] = W.ARGON_NE
+    g, p, keep = _grid_profile_3d(run)
+    n = C.c_size_t(777)
+    assert L.fdtd_plasma_workspace_size(C.byref(g), C.byref(p), None, C.byref(n)) == B.EINVAL
+    assert n.value == 777
+    assert b"absorbing" in L.fdtd_plasma_last_error()
+    h = C.c_void_p()
+    src = B.Source(B.SRC_NONE, 0, 0, 0.0, 0.0, 0.0, 0.0, 0)
+    assert L.fdtd_plasma_create(C.byref(g), C.byref(p), C.byref(src), None, C.byref(h)) == B.EINVAL
+    assert not h.value
+    # the linear model takes the same profile (its point set does not grow there)
+    p.kinetic = B.KINETIC_LINEAR
+    assert L.fdtd_plasma_workspace_size(C.byref(g), C.byref(p), None, C.byref(n)) == B.OK
+
+
 def test_struct_layouts_match_the_header(tmp_path):
     """The ctypes mirrors of the ABI structs have the size and field offsets the C
     compiler gives the header's structs (a field added on one side only would shift every

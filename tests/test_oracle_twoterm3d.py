@@ -158,29 +158,40 @@ def test_hotter_f0_drives_f1_as_the_model_built_hotter(f0):
     assert a < {"maxwell": 0.5, "druyvesteyn": 10.0}[f0] * b
 
 
-def test_slab_through_the_absorbing_layers_grows_and_kept_out_decays():
-    """The two-term point set (E points with four plasma cells) and plasma inside the x and
-    y absorbing layers together carry a growing mode; the linear model's point set in the
-    same box does not, and neither does the two-term model once the slab ends where those
-    layers begin (the 3D slab workload's default for this model).  Small box, 1500 steps
-    of the slab's own pulse; the late field is compared with the field at step 500."""
+def _late_over_early(kinetic, in_cpml):
+    """max |E| after 1500 steps of the slab's own pulse over max |E| at step 500, in a
+    16 x 14 x 40 box with a 6-cell layer on every face."""
     from paper_2211_05647_amd import workloads as W
+    run = W.argon_slab_3d(nx=16, ny=14, nz=40, nv=31, steps=0, ncpml=6, kinetic=kinetic,
+                          plasma_in_cpml=in_cpml)
+    o = Oracle3D(run.nx, run.ny, run.nz, run.dx, run.courant, run.ne, run.nubar,
+                 vdim=run.nv, vmax_over_vth=run.vmax_over_vth, te_ev=run.te_ev,
+                 nu_model=run.nu_model, f0_model=run.f0_model, ncpml=run.ncpml,
+                 src_kind=run.src_kind, src_k=run.src_k, src_amp=run.src_amp,
+                 src_f=run.src_f, src_tau=run.src_tau, src_t0=run.src_t0,
+                 kinetic=kinetic)
+    o.run(500)
+    early = np.abs(o.E).max()
+    o.run(1000)
+    return np.abs(o.E).max() / early
 
-    def late_over_early(kinetic, in_cpml):
-        run = W.argon_slab_3d(nx=16, ny=14, nz=40, nv=31, steps=0, ncpml=6, kinetic=kinetic,
-                              plasma_in_cpml=in_cpml)
-        o = Oracle3D(run.nx, run.ny, run.nz, run.dx, run.courant, run.ne, run.nubar,
-                     vdim=run.nv, vmax_over_vth=run.vmax_over_vth, te_ev=run.te_ev,
-                     nu_model=run.nu_model, f0_model=run.f0_model, ncpml=run.ncpml,
-                     src_kind=run.src_kind, src_k=run.src_k, src_amp=run.src_amp,
-                     src_f=run.src_f, src_tau=run.src_tau, src_t0=run.src_t0,
-                     kinetic=kinetic)
-        o.run(500)
-        early = np.abs(o.E).max()
-        o.run(1000)
-        return np.abs(o.E).max() / early
 
-    assert late_over_early("two_term", True) > 5.0
-    assert late_over_early("linear", True) < 0.5
-    assert late_over_early("two_term", False) < 0.5
-    assert late_over_early("two_term_frozen", False) < 0.5
+def test_slab_kept_out_of_the_side_layers_decays():
+    """Once the slab ends where the x and y absorbing layers begin (the 3D slab workload's
+    default for the two-term model, and the only profile the library accepts for it), the
+    field decays after the pulse has passed, with F0 evolving and with F0 held; the linear
+    model's point set decays with the slab running on through those layers too."""
+    assert _late_over_early("two_term", False) < 0.5
+    assert _late_over_early("two_term_frozen", False) < 0.5
+    assert _late_over_early("linear", True) < 0.5
+
+
+@pytest.mark.xfail(strict=False, reason="open discretisation issue: the two-term point set "
+                   "(E points with four plasma cells) with plasma inside the x and y "
+                   "absorbing layers carries a growing mode (about 6x per 500 steps here); "
+                   "the library refuses such profiles")
+def test_slab_through_the_side_layers_stays_bounded():
+    """Characterisation of the open issue, not a requirement: with plasma inside the side
+    layers the two-term model should decay like the others.  It grows instead, so this is
+    expected to fail until the treatment of the layer-plasma interface is fixed."""
+    assert _late_over_early("two_term", True) < 0.5
