@@ -68,6 +68,23 @@ int fdtd_closure_forward(fdtd_closure *c, const float *x_dev, int32_t n, float *
  * fdtd_closure_adam); optional host copies (NULL to skip). */
 int fdtd_closure_grad(fdtd_closure *c, const float *x_dev, const float *t_dev, int32_t n,
                       float *grad_host, float *loss_host);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the gradient fdtd_closure_grad
+ * computes, with no handle and no allocation.  params_dev: the FDTD_CLOSURE_NPARAM FP32
+ * parameters in device memory (the layout of fdtd_closure_get_params); x_dev [n][18] and
+ * t_dev [n]: the rows and targets (device); grad_dev [FDTD_CLOSURE_NPARAM] and loss_dev [1]
+ * (device) receive the gradient of the mean squared error and the loss.  The kernels'
+ * scratch (bf16 weight copies, per-block partial gradients) is one fixed device array
+ * inside the library, about 9.9 MB on each GPU it runs on, held until the process ends;
+ * hence n is limited to FDTD_CLOSURE_STATIC_MAX_ROWS (FDTD_ERANGE above it).  Work goes on
+ * hip_stream (NULL = the null stream) and nothing synchronises; the results are bitwise
+ * those of fdtd_closure_grad with the same parameters.  Every call on one GPU uses that
+ * GPU's array, so calls that overlap on one GPU race.  Errors: FDTD_EINVAL for a null
+ * pointer or a bad device, FDTD_EDEVICE for a HIP error. */
+#define FDTD_CLOSURE_STATIC_MAX_ROWS 8192
+int fdtd_closure_grad_static(int32_t device, void *hip_stream, const float *params_dev,
+                             const float *x_dev, const float *t_dev, int32_t n,
+                             float *grad_dev, float *loss_dev);
 /* One Adam step (Kingma & Ba) on the master weights with the last gradient. */
 int fdtd_closure_adam(fdtd_closure *c, float lr, float beta1, float beta2, float eps);
 /* grad + Adam(lr, 0.9, 0.999, 1e-8); loss_host (optional, synchronises). */

@@ -96,6 +96,7 @@ _SIGS = {
     "fdtd_closure_single_pole": ([C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_double, C.c_double, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
     "fdtd_closure_replay2v": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int32, C.c_int64, _dp, _dp, C.c_double, C.c_double, C.c_int32, C.c_double, C.c_void_p, C.c_int64], C.c_int),
     "fdtd_closure_make_pairs": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_int64), C.c_int32, C.c_void_p, C.c_void_p], C.c_int),
+    "fdtd_closure_grad_static": ([C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p], C.c_int),
     "fdtd_closure_destroy": ([C.c_void_p], None),
     "fdtd_plasma_strerror": ([C.c_int], C.c_char_p),
     "fdtd_plasma_last_error": ([], C.c_char_p),

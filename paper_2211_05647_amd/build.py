@@ -12,7 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfdtdplasma.so")
 OBJ = os.path.join(HERE, "_build")
 
-SOURCES = ["fdtd_plasma.cpp", "fdtd2d.cpp", "fdtd3d.cpp", "closure.cpp", "kernels1d.hip",
+SOURCES = ["fdtd_plasma.cpp", "fdtd2d.cpp", "fdtd3d.cpp", "closure.cpp", "closure_static.hip",
+           "kernels1d.hip",
            "kernels1d_tb.hip", "kernels1d_tbtt.hip",
            "kernels1d_tbfull.hip", "kernels2d.hip", "kernels3d.hip", "mlp.hip"]
 
