@@ -81,7 +81,8 @@ __device__ __forceinline__ void kinetic_tile(const Run1D<T>& R, const T* eloc,
     for (int u = 0; u < U; ++u) {
       acc[u] = 0.0;
       if (loc[u] >= 0) {
-        const T nE = ne[u] * eloc[loc[u]];
+        const T Eu = eloc[loc[u]];
+        const T nE = ne[u] * Eu;
 #pragma unroll
         for (int m = 0; m < CPL; ++m) {
           if (m < cpl) {
@@ -89,8 +90,8 @@ __device__ __forceinline__ void kinetic_tile(const Run1D<T>& R, const T* eloc,
             for (int v = 0; v < VPL; ++v) {
               // x = dt nu_j; F1' = ((2 - x) F1 + 2 dt (e/m) n dF0/dv E) / (2 + x), with
               // 2 x = (2 dt nu_mean) s_j exactly.  Rows of 64 lanes (the blocked kernel
-              // keeps d and c per row there): F1 + d F1 + c n E, d = -2x / (2 + x),
-              // c = b / (2 + x); shorter rows: the increment form
+              // keeps d and c' per row there): (F1 + d F1) + c' E, d = -2x / (2 + x),
+              // c' = (b / (2 + x)) n; shorter rows: the increment form
               // F1 + (b n E - 2x F1) / (2 + x).  Each form is the blocked kernel's for
               // that row length, operation for operation, so the two agree to the bit;
               // both keep the damping's relative precision when x is small.
@@ -100,8 +101,8 @@ __device__ __forceinline__ void kinetic_tile(const Run1D<T>& R, const T* eloc,
               T fn;
               if (lpc == 64) {
                 const T d = -((tau[u] + tau[u]) * sv) * r;
-                const T c = lane_at(b[m], v) * r;
-                fn = fma(d, fv, fma(c, nE, fv));
+                const T c = (lane_at(b[m], v) * r) * ne[u];
+                fn = fma(c, Eu, fma(d, fv, fv));
               } else {
                 const T x2 = (tau[u] + tau[u]) * sv;
                 const T t = fma(-x2, fv, lane_at(b[m], v) * nE);

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
   Es[1][k] = 0.f;
   Hs[1][k] = 0.f;
   Js[k] = 0.f;
-  if (k < ncell) {
+  if (LPC != 64 && k < ncell) {
     const int c = tile.cell0 + k;
     tauS[k] = R.tau[c];
     neS[k] = R.dens[c];
@@ -100,7 +100,9 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
   const float4* __restrict__ dfr = reinterpret_cast<const float4*>(R.df + in_off);
   // one row per wavefront (LPC = 64): lane q of these registers holds the scalars of the
   // wavefront's row slot q, read into scalar registers with v_readlane when needed
-  int tab_loc = kTbBlock;
+  // (an empty slot keeps node 0 of the range, density 0 and no row: its coefficients and
+  // F1 stay 0, and it never reports a current)
+  int tab_loc = LPC == 64 ? 0 : kTbBlock, tab_row = 0;
   float tab_tau = 0.f, tab_ne = 0.f;
   if constexpr (LPC == 64) {
     if (lane < kTbIters * kTbU) {
@@ -110,6 +112,7 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
         tab_loc = R.cell_node[c] - x0;
         tab_tau = R.tau[c];
         tab_ne = R.dens[c];
+        tab_row = 1;
       }
     }
   }
@@ -122,12 +125,12 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
                             : make_float4(0.f, 0.f, 0.f, 0.f);
     }
   // Crank-Nicolson coefficients of every row slot, the same for all K steps.  With one
-  // row per wavefront: F1' = F1 + d F1 + c n E, d = -2x / (2 + x), c = b / (2 + x), both
-  // kept (127 VGPRs).  With shorter rows the per-lane row scalars leave room for one
-  // coefficient only (the two would need 141 VGPRs: one work-group per compute unit), and
-  // the update keeps the increment form F1 + (b n E - 2x F1) / (2 + x) with 1 / (2 + x)
-  // kept.  The one-step kernel takes the same form for the same row length, so the two
-  // give the same bits.
+  // row per wavefront: F1' = (F1 + d F1) + c' E, d = -2x / (2 + x), c' = (b / (2 + x)) n
+  // (the row's density folded in), both kept; both FMAs update F1 in place.  With shorter rows the per-lane row scalars
+  // leave room for one coefficient only (the two would need 141 VGPRs: one work-group
+  // per compute unit), and the update keeps the increment form
+  // F1 + (b n E - 2x F1) / (2 + x) with 1 / (2 + x) kept.  The one-step kernel takes the
+  // same form for the same row length, so the two give the same bits.
   constexpr bool kKeepDC = LPC == 64;
   float4 dd[kTbIters][kTbU], cc[kKeepDC ? kTbIters : 1][kKeepDC ? kTbU : 1];
 #pragma unroll
@@ -135,17 +138,19 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
 #pragma unroll
     for (int u = 0; u < kTbU; ++u) {
       const int cl = row_slot(it * kTbU + u, wv, sub);
-      float tau = 0.f;
-      if constexpr (LPC == 64)
+      float tau = 0.f, ne = 0.f;
+      if constexpr (LPC == 64) {
         tau = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tab_tau), it * kTbU + u));
-      else
+        ne = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tab_ne), it * kTbU + u));
+      } else {
         tau = cl < ncell ? R.tau[tile.cell0 + cl] : 0.f;
+      }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const float r = cn_recip(fmaf(tau, lane_at(sb, v), 2.f));
         if constexpr (kKeepDC) {
           lane_at(dd[it][u], v) = -((tau + tau) * lane_at(sb, v)) * r;
-          lane_at(cc[it][u], v) = lane_at(bb, v) * r;
+          lane_at(cc[it][u], v) = (lane_at(bb, v) * r) * ne;
         } else {
           lane_at(dd[it][u], v) = r;
         }
@@ -154,71 +159,91 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
 
   int lo = x0, hi = x1;    // nodes whose E is valid at the start of the sub-step
   const float S = R.S;
+  // the run's constants the field phase needs, read once (scalar registers) rather than
+  // from the run record in every sub-step
+  const int bc = R.bc, src_node = R.src_node, nprobe = R.nprobe, ntap = R.ntap;
+  const float mq = R.q;
 #pragma unroll 1
   for (int s = 0; s < K; ++s) {
     const int p = s & 1;
     const int64_t gs = step + s;
     __syncthreads();
-    // keep the per-row scalars in LDS: re-read each sub-step instead of being hoisted
-    // into registers for all rows at once
-    asm volatile("" ::: "memory");
-    // kinetic update of the rows whose node holds a valid E, FP64 moment -> Js
+    if constexpr (LPC == 64) {
+      // One row per wavefront slot.  Every slot is updated, also rows whose node has
+      // dropped out of the valid range: their F1 is never written back and their current
+      // never reported, and the update stays finite (|1 + d| < 1, E finite), so the
+      // uniform, branch-free form costs nothing in results.  The E of the eight slots
+      // comes from one LDS read (lane q reads slot q's node) and v_readlane.
+      const float ev = Es[p][tab_loc];
 #pragma unroll
-    for (int it = 0; it < kTbIters; ++it) {
-      double acc[kTbU];
-      int loc[kTbU];
+      for (int it = 0; it < kTbIters; ++it) {
+        double acc[kTbU];
 #pragma unroll
-      for (int u = 0; u < kTbU; ++u) {
-        const int cl = row_slot(it * kTbU + u, wv, sub);
-        loc[u] = kTbBlock;            // rows without a valid E report to the spare slot
-        bool live = cl < ncell;
-        int lc = 0;
-        float tau = 0.f, ne = 0.f;
-        if constexpr (LPC == 64) {
-          // one row per wavefront: the row's scalars and its validity are uniform
-          const int q = it * kTbU + u;
-          lc = __builtin_amdgcn_readlane(tab_loc, q);
-          tau = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tab_tau), q));
-          ne = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tab_ne), q));
-          live = live && x0 + lc >= lo && x0 + lc < hi;
-        } else if (live) {
-          lc = locS[cl];
-          tau = tauS[cl];
-          ne = neS[cl];
-          live = x0 + lc >= lo && x0 + lc < hi;
-        }
-        if (live) {
-          loc[u] = lc;
-          const float nE = ne * Es[p][lc];
+        for (int u = 0; u < kTbU; ++u) {
+          const float E = __int_as_float(
+              __builtin_amdgcn_readlane(__float_as_int(ev), it * kTbU + u));
           double a = 0.0;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const float fv = lane_at(f[it][u], v);
-            float fn;
-            if constexpr (kKeepDC) {
-              fn = fmaf(lane_at(dd[it][u], v), fv, fmaf(lane_at(cc[it][u], v), nE, fv));
-            } else {
-              // x = dt nu_j; (2 x) = (2 dt nu_mean) s_j exactly
-              const float x2 = (tau + tau) * lane_at(sb, v);
-              const float t = fmaf(-x2, fv, lane_at(bb, v) * nE);
-              fn = fmaf(t, lane_at(dd[it][u], v), fv);
-            }
+            const float fn = fmaf(lane_at(cc[it][u], v), E, fmaf(lane_at(dd[it][u], v), fv, fv));
             lane_at(f[it][u], v) = fn;
             a = fma(w[v], (double)fn, a);
           }
           acc[u] = a;
-        } else {
-          acc[u] = 0.0;   // zero only on the (uniform, for 64-lane rows) path of idle rows
         }
-      }
-      int which = 0;
-      if constexpr (LPC == 64) {
         static_assert(kTbU == 4, "wave_reduce4 sums four rows");
+        int which = 0;
         const double tot = wave_reduce4(acc, which);
+        // 16-lane row `which` holds the total of slot it * U + which; its first lane
+        // reports it if that slot holds a row whose node has a valid E this sub-step
+        const int q = it * kTbU + which;
+        const int lc = __shfl(tab_loc, q);
+        const int has = __shfl(tab_row, q);
+        if ((li & 15) == 0 && has && x0 + lc >= lo && x0 + lc < hi) Js[lc] = (float)tot;
+      }
+    } else {
+      // keep the per-row scalars in LDS: re-read each sub-step instead of being hoisted
+      // into registers for all rows at once
+      asm volatile("" ::: "memory");
+      // kinetic update of the rows whose node holds a valid E, FP64 moment -> Js
 #pragma unroll
-        for (int u = 0; u < kTbU; ++u)
-          if (li == 16 * u) Js[loc[u]] = (float)tot;
-      } else {
+      for (int it = 0; it < kTbIters; ++it) {
+        double acc[kTbU];
+        int loc[kTbU];
+#pragma unroll
+        for (int u = 0; u < kTbU; ++u) {
+          const int cl = row_slot(it * kTbU + u, wv, sub);
+          loc[u] = kTbBlock;            // rows without a valid E report to the spare slot
+          bool live = cl < ncell;
+          int lc = 0;
+          float tau = 0.f, ne = 0.f;
+          if (live) {
+            lc = locS[cl];
+            tau = tauS[cl];
+            ne = neS[cl];
+            live = x0 + lc >= lo && x0 + lc < hi;
+          }
+          if (live) {
+            loc[u] = lc;
+            const float nE = ne * Es[p][lc];
+            double a = 0.0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const float fv = lane_at(f[it][u], v);
+              // x = dt nu_j; (2 x) = (2 dt nu_mean) s_j exactly
+              const float x2 = (tau + tau) * lane_at(sb, v);
+              const float t = fmaf(-x2, fv, lane_at(bb, v) * nE);
+              const float fn = fmaf(t, lane_at(dd[it][u], v), fv);
+              lane_at(f[it][u], v) = fn;
+              a = fma(w[v], (double)fn, a);
+            }
+            acc[u] = a;
+          } else {
+            acc[u] = 0.0;
+          }
+        }
+        int which = 0;
         const double tot = group_reduce4_dpp<LPC>(acc, which);
 #pragma unroll
         for (int u = 0; u < kTbU; ++u)
@@ -238,19 +263,19 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
       if (i == 0) {
         const float ep = Es[p][k + 1], h0 = Hs[p][k];
         hn = h_update(h0, S, ep, e0);
-        if (R.bc == 1) {
+        if (bc == 1) {
           const float h1 = h_update(Hs[p][k + 1], S, Es[p][k + 2], ep);
           const float e1 = e_update(ep, S, h1, hn, 0.f);
-          en = fmaf(R.q, e1 - e0, ep);
+          en = fmaf(mq, e1 - e0, ep);
         }
         Hs[p ^ 1][k] = hn;
       } else if (i == nx) {
-        if (R.bc == 1) {
+        if (bc == 1) {
           const float em = Es[p][k - 1], hm = Hs[p][k - 1];
           const float ha = h_update(hm, S, e0, em);
           const float hb = h_update(Hs[p][k - 2], S, em, Es[p][k - 2]);
           const float e = e_update(em, S, ha, hb, 0.f);
-          en = fmaf(R.q, e - e0, em);
+          en = fmaf(mq, e - e0, em);
         }
       } else {
         if (i < hi - 1) {
@@ -260,20 +285,20 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
         if (has_e) {
           const float hl = h_update(Hs[p][k - 1], S, e0, Es[p][k - 1]);
           en = e_update(e0, S, hn, hl, jv);
-          if (i == R.src_node) en += srcS[s];
+          if (i == src_node) en += srcS[s];
         }
       }
       if (has_e) Es[p ^ 1][k] = en;
       if (has_e && i >= tile.node0 && i < tile.node1) {
         if (!isfinite(en)) atomicOr(R.status, 1);
-        for (int q = 0; q < R.nprobe; ++q) {
+        for (int q = 0; q < nprobe; ++q) {
           if (R.probe_node[q] == i) {
             const int fld = R.probe_field[q];
             const float val = (fld == 0) ? en : (fld == 1 ? hn : jv);
             R.probe_buf[(size_t)q * R.probe_cap + (size_t)(gs % R.probe_cap)] = val;
           }
         }
-        for (int t = 0; t < R.ntap; ++t) {
+        for (int t = 0; t < ntap; ++t) {
           if (R.tap_node[t] == i && gs < R.tap_cap) {
             float* dst = R.tap_buf + ((size_t)t * R.tap_cap + (size_t)gs) * 2;
             dst[0] = e0;
@@ -303,7 +328,8 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
     for (int u = 0; u < kTbU; ++u) {
       const int cl = row_slot(it * kTbU + u, wv, sub);
       if (cl < ncell) {
-        const int node = x0 + locS[cl];
+        const int node =
+            x0 + (LPC == 64 ? __builtin_amdgcn_readlane(tab_loc, it * kTbU + u) : locS[cl]);
         if (node >= tile.node0 && node < tile.node1)
           dfw[(size_t)(tile.cell0 + cl) * lpc + li] = f[it][u];
       }
