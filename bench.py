@@ -145,6 +145,11 @@ def hbm(by, ms):
 # ---------------------------------------------------------------------------------------
 # GPU timing
 # ---------------------------------------------------------------------------------------
+def blocked_kernel(k, half):
+    """Name of the kernel a single run's K-step launches use."""
+    return f"k_step1d_tb<{k}, {half // 4}>"
+
+
 def time_1d(run, B, torch, steps, warmup, tile=0, time_block=0, reps=1):
     """Time `reps` regions of exactly `steps` steps of a single 1D run.  A region is two
     library calls: the q K-step blocked launches (K = steps per launch in effect,
@@ -226,7 +231,7 @@ def extra_c1l(B, W, torch, autotune):
     log(f"c1l: Nx={run.nx} plasma cells={run.plasma_cells}")
     tile = autotune.lookup(run, B.FP32)
     t = time_1d(run, B, torch, run.steps, 49, tile, autotune.lookup_time_block(run, B.FP32), reps=3)
-    out = blocked_entry(run, t, run.steps, kernel=f"k_step1d_tb<{t['k']}, 64>")
+    out = blocked_entry(run, t, run.steps, kernel=blocked_kernel(t["k"], run.nv // 2))
     out["workload"] = "1D Yee + 1V kinetic, Nx=1048576, Nv=512, FP32, 2000 steps"
     out["hbm_bytes_per_launch_counters"] = pmc_bytes("k_step1d_tb_c1l_pmc.json")
     # one step per launch on the same line: the streaming kernel beyond the Infinity Cache
@@ -842,14 +847,15 @@ def main():
         # one launch = kb steps of the temporally blocked kernel, priced against HBM with
         # its own algorithmic bytes (rows read with their halo, owned rows written, fields
         # once): its arithmetic intensity lies below the FP32 ridge
-        kernel = f"k_step1d_tb<{kb}, {half // 4}>"
+        kernel = blocked_kernel(kb, half)
         by = bytes_1d_blocked(run, t["rows"])
         launch_ms = t["launch_ms"]
         achieved, frac = hbm(by, launch_ms)
         flops = (FLOPS_PER_BIN_STEP * kb + FLOPS_PER_BIN_LAUNCH) * ncell * half
         tflops = flops / (launch_ms * 1e-3) / 1e12
         roof = {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": frac, "traffic": pmc_bytes("k_step1d_tb_c1_pmc.json"),
+                "unit": "GB/s", "frac": frac,
+                "traffic": pmc_bytes("k_step1d_tb_c1_pmc.json"),
                 "bytes_per_launch": by, "launch_ms": launch_ms,
                 "launch_ms_reps": t["launch_ms_reps"], "launches_timed": t["launches_timed"],
                 "flops_per_launch": flops, "intensity_flop_per_byte": flops / by,

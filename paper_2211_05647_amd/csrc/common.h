@@ -19,9 +19,22 @@ template <> struct Vec<double> { using type = double2; static constexpr int n = 
 template <class V> __device__ __forceinline__ auto& lane_at(V& v, int k) {
   return reinterpret_cast<typename std::remove_reference<decltype(v.x)>::type*>(&v)[k];
 }
+template <class V> __device__ __forceinline__ auto lane_at(const V& v, int k) {
+  using E = typename std::remove_cv<typename std::remove_reference<decltype(v.x)>::type>::type;
+  return reinterpret_cast<const E*>(&v)[k];
+}
 
 // Reciprocal used by the Crank-Nicolson factor 1/(2 + dt nu): the hardware estimate in
 // FP32 (the increment it scales is small next to F1 itself), exact division in FP64.
+// A pointer into device global memory with its address space stated, so that accesses
+// through it compile to global_* rather than flat_* instructions.  A flat access might
+// reach LDS, and the compiler then makes the next LDS access wait for it as well (and
+// with it for every global load in flight).
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gptr(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 __device__ __forceinline__ float cn_recip(float d) { return __builtin_amdgcn_rcpf(d); }
 __device__ __forceinline__ double cn_recip(double d) { return 1.0 / d; }
 

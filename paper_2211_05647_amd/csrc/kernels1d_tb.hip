@@ -38,6 +38,155 @@ constexpr int kTbIters = 2;                 // row slot groups per lane group: 8
                                             // 10% slower)
 constexpr int kTbRowsPerGroup = kTbIters * kTbU;
 
+// One sub-step of the fields of a tile's extended range, by the thread of node
+// i = x0 + k: H^{n+1/2} on [lo, hi - 1) and E^{n+1} (minus the current Js, plus the soft
+// source sample `src`) on the next valid range [nlo, nhi), with the first-order Mur ends;
+// the owned nodes also check for non-finite E and feed the probe and tap buffers.  The
+// same operations as the one-step kernel's field update.
+template <int NW>
+__device__ __forceinline__ void tb_fields(const Run1D<float>& R, const Tile1D& tile,
+                                          float (*Es)[NW], float (*Hs)[NW],
+                                          const float* Js, float src, int k, int i, int p,
+                                          int lo, int hi, int nlo, int nhi, int nx, float S,
+                                          int bc, float mq, int src_node, int nprobe, int ntap,
+                                          int64_t gs) {
+  if (i >= lo && i < hi) {
+    // every LDS value of the interior update, read in one batch (one LDS round trip on the
+    // sub-step's critical path); the clamped neighbours are the ones read only where they
+    // exist (k - 1 where E is produced, k + 1 where H is)
+    const int km = k > 0 ? k - 1 : 0;
+    const int kp = k + 1 < NW ? k + 1 : k;
+    const float e0 = Es[p][k], jv = Js[k], ep = Es[p][kp], em = Es[p][km];
+    const float h0 = Hs[p][k], hm = Hs[p][km];
+    float en = 0.f, hn = 0.f;
+    bool has_e = i >= nlo && i < nhi;
+    if (i == 0) {
+      hn = h_update(h0, S, ep, e0);
+      if (bc == 1) {
+        const float h1 = h_update(Hs[p][k + 1], S, Es[p][k + 2], ep);
+        const float e1 = e_update(ep, S, h1, hn, 0.f);
+        en = fmaf(mq, e1 - e0, ep);
+      }
+      Hs[p ^ 1][k] = hn;
+    } else if (i == nx) {
+      if (bc == 1) {
+        const float ha = h_update(hm, S, e0, em);
+        const float hb = h_update(Hs[p][k - 2], S, em, Es[p][k - 2]);
+        const float e = e_update(em, S, ha, hb, 0.f);
+        en = fmaf(mq, e - e0, em);
+      }
+    } else {
+      if (i < hi - 1) {
+        hn = h_update(h0, S, ep, e0);
+        Hs[p ^ 1][k] = hn;
+      }
+      if (has_e) {
+        const float hl = h_update(hm, S, e0, em);
+        en = e_update(e0, S, hn, hl, jv);
+        if (i == src_node) en += src;
+      }
+    }
+    if (has_e) Es[p ^ 1][k] = en;
+    if (has_e && i >= tile.node0 && i < tile.node1) {
+      if (!isfinite(en))
+        __hip_atomic_fetch_or(gptr(R.status), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int q = 0; q < nprobe; ++q) {
+        if (gptr(R.probe_node)[q] == i) {
+          const int fld = gptr(R.probe_field)[q];
+          const float val = (fld == 0) ? en : (fld == 1 ? hn : jv);
+          gptr(R.probe_buf)[(size_t)q * R.probe_cap + (size_t)(gs % R.probe_cap)] = val;
+        }
+      }
+      for (int t = 0; t < ntap; ++t) {
+        if (gptr(R.tap_node)[t] == i && gs < R.tap_cap) {
+          auto dst = gptr(R.tap_buf) + ((size_t)t * R.tap_cap + (size_t)gs) * 2;
+          dst[0] = e0;
+          dst[1] = jv;
+        }
+      }
+    }
+  }
+}
+
+// The half of the kinetic update that does not depend on E, F1 + d F1, in place: done
+// before the sub-step's E is ready (while wavefront 0 updates the fields).
+__device__ __forceinline__ void tb_drive64(float4 (&f)[kTbIters][kTbU],
+                                           const float4 (&dd)[kTbIters][kTbU]) {
+#pragma unroll
+  for (int it = 0; it < kTbIters; ++it)
+#pragma unroll
+    for (int u = 0; u < kTbU; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const float fv = lane_at(f[it][u], v);
+        lane_at(f[it][u], v) = fmaf(lane_at(dd[it][u], v), fv, fv);
+      }
+}
+
+// The kinetic phase of one sub-step for rows of 64 lanes (one row per wavefront slot,
+// 4 bins per lane), given f = F1 + d F1 from tb_drive64: F1' = f + c' E -- the same
+// operations, in the same order, as F1' = (F1 + d F1) + c' E in one go -- and the FP64
+// moment of every slot, the totals
+// of the slots whose node holds a valid E (lo <= node < hi) written to Js.  Every slot is
+// updated, also rows whose node has dropped out of the valid range: their F1 is never
+// written back and their current never reported, and the update stays finite
+// (|1 + d| < 1, E finite), so the uniform, branch-free form costs nothing in results.
+// The E of the eight slots comes from one LDS read (lane q reads slot q's node,
+// tab_loc) and v_readlane; tab_row says whether slot q holds a row.
+__device__ __forceinline__ void tb_kinetic64(float4 (&f)[kTbIters][kTbU],
+                                             const float4 (&cc)[kTbIters][kTbU],
+                                             const double (&w)[4], const float* Esp, float* Js,
+                                             int tab_loc, int tab_row, int x0, int lo, int hi,
+                                             int li) {
+  const float ev = Esp[tab_loc];
+#pragma unroll
+  for (int it = 0; it < kTbIters; ++it) {
+    double acc[kTbU];
+#pragma unroll
+    for (int u = 0; u < kTbU; ++u) {
+      const float E = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ev), it * kTbU + u));
+      double a = 0.0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const float fn = fmaf(lane_at(cc[it][u], v), E, lane_at(f[it][u], v));
+        lane_at(f[it][u], v) = fn;
+        a = fma(w[v], (double)fn, a);
+      }
+      acc[u] = a;
+    }
+    static_assert(kTbU == 4, "wave_reduce4 sums four rows");
+    int which = 0;
+    const double tot = wave_reduce4(acc, which);
+    // 16-lane row `which` holds the total of slot it * U + which; its first lane reports
+    // it if that slot holds a row whose node has a valid E this sub-step
+    const int q = it * kTbU + which;
+    const int lc = __shfl(tab_loc, q);
+    const int has = __shfl(tab_row, q);
+    if ((li & 15) == 0 && has && x0 + lc >= lo && x0 + lc < hi) Js[lc] = (float)tot;
+  }
+}
+
+// Crank-Nicolson coefficients of the eight row slots of a wavefront for rows of 64 lanes:
+// d = -2x / (2 + x) and c' = (b / (2 + x)) n per bin, x = dt nu_j (lane q of tab_tau /
+// tab_ne holds slot q's dt nu_mean and density; an empty slot has both 0).
+__device__ __forceinline__ void tb_coef64(float4 (&dd)[kTbIters][kTbU], float4 (&cc)[kTbIters][kTbU],
+                                          const float4& sb, const float4& bb, float tab_tau,
+                                          float tab_ne) {
+#pragma unroll
+  for (int it = 0; it < kTbIters; ++it)
+#pragma unroll
+    for (int u = 0; u < kTbU; ++u) {
+      const float tau = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tab_tau), it * kTbU + u));
+      const float ne = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tab_ne), it * kTbU + u));
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const float r = cn_recip(fmaf(tau, lane_at(sb, v), 2.f));
+        lane_at(dd[it][u], v) = -((tau + tau) * lane_at(sb, v)) * r;
+        lane_at(cc[it][u], v) = (lane_at(bb, v) * r) * ne;
+      }
+    }
+}
+
 template <int K, int LPC>
 __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __restrict__ runs,
                                                         const Tile1D* __restrict__ tiles,
@@ -133,29 +282,20 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
   // same form for the same row length, so the two give the same bits.
   constexpr bool kKeepDC = LPC == 64;
   float4 dd[kTbIters][kTbU], cc[kKeepDC ? kTbIters : 1][kKeepDC ? kTbU : 1];
+  if constexpr (kKeepDC) {
+    tb_coef64(dd, cc, sb, bb, tab_tau, tab_ne);
+    tb_drive64(f, dd);   // the first sub-step's E-independent half
+  } else {
 #pragma unroll
-  for (int it = 0; it < kTbIters; ++it)
+    for (int it = 0; it < kTbIters; ++it)
 #pragma unroll
-    for (int u = 0; u < kTbU; ++u) {
-      const int cl = row_slot(it * kTbU + u, wv, sub);
-      float tau = 0.f, ne = 0.f;
-      if constexpr (LPC == 64) {
-        tau = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tab_tau), it * kTbU + u));
-        ne = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tab_ne), it * kTbU + u));
-      } else {
-        tau = cl < ncell ? R.tau[tile.cell0 + cl] : 0.f;
+      for (int u = 0; u < kTbU; ++u) {
+        const int cl = row_slot(it * kTbU + u, wv, sub);
+        const float tau = cl < ncell ? R.tau[tile.cell0 + cl] : 0.f;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) lane_at(dd[it][u], v) = cn_recip(fmaf(tau, lane_at(sb, v), 2.f));
       }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const float r = cn_recip(fmaf(tau, lane_at(sb, v), 2.f));
-        if constexpr (kKeepDC) {
-          lane_at(dd[it][u], v) = -((tau + tau) * lane_at(sb, v)) * r;
-          lane_at(cc[it][u], v) = (lane_at(bb, v) * r) * ne;
-        } else {
-          lane_at(dd[it][u], v) = r;
-        }
-      }
-    }
+  }
 
   int lo = x0, hi = x1;    // nodes whose E is valid at the start of the sub-step
   const float S = R.S;
@@ -169,39 +309,7 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
     const int64_t gs = step + s;
     __syncthreads();
     if constexpr (LPC == 64) {
-      // One row per wavefront slot.  Every slot is updated, also rows whose node has
-      // dropped out of the valid range: their F1 is never written back and their current
-      // never reported, and the update stays finite (|1 + d| < 1, E finite), so the
-      // uniform, branch-free form costs nothing in results.  The E of the eight slots
-      // comes from one LDS read (lane q reads slot q's node) and v_readlane.
-      const float ev = Es[p][tab_loc];
-#pragma unroll
-      for (int it = 0; it < kTbIters; ++it) {
-        double acc[kTbU];
-#pragma unroll
-        for (int u = 0; u < kTbU; ++u) {
-          const float E = __int_as_float(
-              __builtin_amdgcn_readlane(__float_as_int(ev), it * kTbU + u));
-          double a = 0.0;
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const float fv = lane_at(f[it][u], v);
-            const float fn = fmaf(lane_at(cc[it][u], v), E, fmaf(lane_at(dd[it][u], v), fv, fv));
-            lane_at(f[it][u], v) = fn;
-            a = fma(w[v], (double)fn, a);
-          }
-          acc[u] = a;
-        }
-        static_assert(kTbU == 4, "wave_reduce4 sums four rows");
-        int which = 0;
-        const double tot = wave_reduce4(acc, which);
-        // 16-lane row `which` holds the total of slot it * U + which; its first lane
-        // reports it if that slot holds a row whose node has a valid E this sub-step
-        const int q = it * kTbU + which;
-        const int lc = __shfl(tab_loc, q);
-        const int has = __shfl(tab_row, q);
-        if ((li & 15) == 0 && has && x0 + lc >= lo && x0 + lc < hi) Js[lc] = (float)tot;
-      }
+      tb_kinetic64(f, cc, w, Es[p], Js, tab_loc, tab_row, x0, lo, hi, li);
     } else {
       // keep the per-row scalars in LDS: re-read each sub-step instead of being hoisted
       // into registers for all rows at once
@@ -255,58 +363,11 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
     // H^{n+1/2} on [lo, hi - 1), E^{n+1} on the next valid range
     const int nlo = lo == 0 ? 0 : lo + 1;
     const int nhi = hi == nx + 1 ? nx + 1 : hi - 1;
-    if (i >= lo && i < hi) {
-      const float e0 = Es[p][k];
-      const float jv = Js[k];
-      float en = 0.f, hn = 0.f;
-      bool has_e = i >= nlo && i < nhi;
-      if (i == 0) {
-        const float ep = Es[p][k + 1], h0 = Hs[p][k];
-        hn = h_update(h0, S, ep, e0);
-        if (bc == 1) {
-          const float h1 = h_update(Hs[p][k + 1], S, Es[p][k + 2], ep);
-          const float e1 = e_update(ep, S, h1, hn, 0.f);
-          en = fmaf(mq, e1 - e0, ep);
-        }
-        Hs[p ^ 1][k] = hn;
-      } else if (i == nx) {
-        if (bc == 1) {
-          const float em = Es[p][k - 1], hm = Hs[p][k - 1];
-          const float ha = h_update(hm, S, e0, em);
-          const float hb = h_update(Hs[p][k - 2], S, em, Es[p][k - 2]);
-          const float e = e_update(em, S, ha, hb, 0.f);
-          en = fmaf(mq, e - e0, em);
-        }
-      } else {
-        if (i < hi - 1) {
-          hn = h_update(Hs[p][k], S, Es[p][k + 1], e0);
-          Hs[p ^ 1][k] = hn;
-        }
-        if (has_e) {
-          const float hl = h_update(Hs[p][k - 1], S, e0, Es[p][k - 1]);
-          en = e_update(e0, S, hn, hl, jv);
-          if (i == src_node) en += srcS[s];
-        }
-      }
-      if (has_e) Es[p ^ 1][k] = en;
-      if (has_e && i >= tile.node0 && i < tile.node1) {
-        if (!isfinite(en)) atomicOr(R.status, 1);
-        for (int q = 0; q < nprobe; ++q) {
-          if (R.probe_node[q] == i) {
-            const int fld = R.probe_field[q];
-            const float val = (fld == 0) ? en : (fld == 1 ? hn : jv);
-            R.probe_buf[(size_t)q * R.probe_cap + (size_t)(gs % R.probe_cap)] = val;
-          }
-        }
-        for (int t = 0; t < ntap; ++t) {
-          if (R.tap_node[t] == i && gs < R.tap_cap) {
-            float* dst = R.tap_buf + ((size_t)t * R.tap_cap + (size_t)gs) * 2;
-            dst[0] = e0;
-            dst[1] = jv;
-          }
-        }
-      }
-    }
+    tb_fields(R, tile, Es, Hs, Js, srcS[s], k, i, p, lo, hi, nlo, nhi, nx, S, bc, mq, src_node,
+              nprobe, ntap, gs);
+    // the next sub-step's E-independent half runs while wavefront 0 updates the fields
+    if constexpr (LPC == 64)
+      if (s + 1 < K) tb_drive64(f, dd);
     lo = nlo;
     hi = nhi;
   }
