@@ -53,7 +53,7 @@ struct fdtd_closure {
 namespace {
 
 struct ClosureLayout {
-  size_t master, m, v, G, P, lossp, loss, W1, W2, W2T, b1, b2, w3q, b3, cells, series, idx, s, bx, wx,
+  size_t master, m, v, G, P, lossp, loss, W1, W2, W2T, W2P, b1, b2, w3q, b3, cells, series, idx, s, bx, wx,
       total;
 };
 
@@ -71,6 +71,7 @@ ClosureLayout closure_layout(int max_rows, int max_series) {
   L.W1 = cv.take(kNH * kK1P * 2);
   L.W2 = cv.take(kNH * kK2P * 2);
   L.W2T = cv.take(kNH * kK2P * 2);
+  L.W2P = cv.take(kNH * kK2P * 2);
   L.b1 = cv.take(kNH * 4);
   L.b2 = cv.take(kNH * 4);
   L.w3q = cv.take(kNH * 4);
@@ -144,6 +145,7 @@ int fdtd_closure_create(const fdtd_device* dev, int32_t max_rows, int32_t max_se
   c->W.W1 = reinterpret_cast<uint16_t*>(b + L.W1);
   c->W.W2 = reinterpret_cast<uint16_t*>(b + L.W2);
   c->W.W2T = reinterpret_cast<uint16_t*>(b + L.W2T);
+  c->W.W2P = reinterpret_cast<uint16_t*>(b + L.W2P);
   c->W.b1 = reinterpret_cast<float*>(b + L.b1);
   c->W.b2 = reinterpret_cast<float*>(b + L.b2);
   c->W.w3q = reinterpret_cast<float*>(b + L.w3q);

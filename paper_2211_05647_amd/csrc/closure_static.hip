@@ -3,7 +3,8 @@
 // capture, tight serving loops).  Its kernels are those of fdtd_closure_grad (bf16 packing
 // of the FP32 parameters, forward + backward of 64-row blocks with per-block partial
 // gradients, the fixed-order reduction); their scratch buffers -- the bf16 weight copies
-// and the per-block partials -- live in one file-scope device array of fixed size.
+// (the packing writes all of them, the inference layout included) and the per-block
+// partials -- live in one file-scope device array of fixed size.
 #include <hip/hip_runtime.h>
 
 #include <mutex>
@@ -26,7 +27,8 @@ constexpr size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 constexpr size_t kScrW1 = 0;
 constexpr size_t kScrW2 = kScrW1 + align256((size_t)kNH * kK1P * 2);
 constexpr size_t kScrW2T = kScrW2 + align256((size_t)kNH * kK2P * 2);
-constexpr size_t kScrB1 = kScrW2T + align256((size_t)kNH * kK2P * 2);
+constexpr size_t kScrW2P = kScrW2T + align256((size_t)kNH * kK2P * 2);
+constexpr size_t kScrB1 = kScrW2P + align256((size_t)kNH * kK2P * 2);
 constexpr size_t kScrB2 = kScrB1 + align256(kNH * 4);
 constexpr size_t kScrW3 = kScrB2 + align256(kNH * 4);
 constexpr size_t kScrB3 = kScrW3 + align256(kNH * 4);
@@ -81,6 +83,7 @@ extern "C" int fdtd_closure_grad_static(int32_t device, void* hip_stream, const 
   W.W1 = reinterpret_cast<uint16_t*>(base + kScrW1);
   W.W2 = reinterpret_cast<uint16_t*>(base + kScrW2);
   W.W2T = reinterpret_cast<uint16_t*>(base + kScrW2T);
+  W.W2P = reinterpret_cast<uint16_t*>(base + kScrW2P);
   W.b1 = reinterpret_cast<float*>(base + kScrB1);
   W.b2 = reinterpret_cast<float*>(base + kScrB2);
   W.w3q = reinterpret_cast<float*>(base + kScrW3);

@@ -42,7 +42,7 @@ struct Host2D {
   std::vector<float> mlp_params;
   std::vector<int32_t> mlp_idx;
   std::vector<float> mlp_coef;     // [n][4] alpha, beta, q1, q2
-  size_t off_ring = 0, off_midx = 0, off_mcoef = 0, off_W1 = 0, off_W2 = 0, off_W2T = 0,
+  size_t off_ring = 0, off_midx = 0, off_mcoef = 0, off_W1 = 0, off_W2 = 0, off_W2T = 0, off_W2P = 0,
          off_mb = 0;
   MlpWeights W{};
   MlpCells2D C{};
@@ -83,6 +83,7 @@ size_t layout(Host2D* h, int max_probes, int probe_cap) {
   h->off_W1 = cv.take(kNH * kK1P * 2);
   h->off_W2 = cv.take(kNH * kK2P * 2);
   h->off_W2T = cv.take(kNH * kK2P * 2);
+  h->off_W2P = cv.take(kNH * kK2P * 2);
   h->off_mb = cv.take((3 * kNH + 1) * 4);
   h->total = cv.size() + 256;
   return h->total;
@@ -196,12 +197,14 @@ int upload(Host2D* h, char* ws, hipStream_t st, const std::vector<ProbeInfo>& pr
       return (uint16_t)(u >> 16);
     };
     const float* P = h->mlp_params.data();
-    std::vector<uint16_t> w1(kNH * kK1P, 0), w2(kNH * kK2P, 0), w2t(kNH * kK2P, 0);
+    std::vector<uint16_t> w1(kNH * kK1P, 0), w2(kNH * kK2P, 0), w2t(kNH * kK2P, 0),
+        w2p(kNH * kK2P, 0);
     for (int n = 0; n < kNH; ++n) {
       for (int k = 0; k < kNIn; ++k) w1[n * kK1P + k] = bf(P[kOffW1 + n * kNIn + k]);
       for (int k = 0; k < kNH; ++k) {
         w2[n * kK2P + k] = bf(P[kOffW2 + n * kNH + k]);
         w2t[n * kK2P + k] = bf(P[kOffW2 + k * kNH + n]);
+        w2p[n * kK2P + k] = bf(P[kOffW2 + n * kNH + mlp_w2p_col(k)]);
       }
     }
     std::vector<float> mb(3 * kNH + 1);
@@ -215,11 +218,13 @@ int upload(Host2D* h, char* ws, hipStream_t st, const std::vector<ProbeInfo>& pr
     if ((e = put(h->off_midx, h->mlp_idx.data(), h->mlp_idx.size() * 4)) ||
         (e = put(h->off_mcoef, h->mlp_coef.data(), h->mlp_coef.size() * 4)) ||
         (e = put(h->off_W1, w1.data(), w1.size() * 2)) || (e = put(h->off_W2, w2.data(), w2.size() * 2)) ||
-        (e = put(h->off_W2T, w2t.data(), w2t.size() * 2)) || (e = put(h->off_mb, mb.data(), mb.size() * 4)))
+        (e = put(h->off_W2T, w2t.data(), w2t.size() * 2)) ||
+        (e = put(h->off_W2P, w2p.data(), w2p.size() * 2)) || (e = put(h->off_mb, mb.data(), mb.size() * 4)))
       return hip_fail(e, "upload closure");
     h->W.W1 = reinterpret_cast<uint16_t*>(ws + h->off_W1);
     h->W.W2 = reinterpret_cast<uint16_t*>(ws + h->off_W2);
     h->W.W2T = reinterpret_cast<uint16_t*>(ws + h->off_W2T);
+    h->W.W2P = reinterpret_cast<uint16_t*>(ws + h->off_W2P);
     h->W.b1 = reinterpret_cast<float*>(ws + h->off_mb);
     h->W.b2 = h->W.b1 + kNH;
     h->W.w3q = h->W.b1 + 2 * kNH;

@@ -4,14 +4,15 @@
 // trained on currents of the kinetic model of section 5.2 (arXiv 2211.05647).
 //
 // GEMM operands are bfloat16 (round to nearest even), accumulation FP32, on the matrix
-// cores (v_mfma_f32_16x16x16_bf16).  One wavefront owns 16 rows; a work-group of 4
-// wavefronts owns 64 rows and keeps the bf16 weights in LDS (rows padded by 8 elements so
-// the 16 lanes of a fragment load hit distinct banks).
+// cores.  Inference (k_mlp_rows, k_mlp2d) uses gfx950's v_mfma_f32_16x16x32_bf16 with
+// every layer transposed and register-chained; training (k_mlp_grad) uses
+// v_mfma_f32_16x16x16_bf16 with activations staged in LDS.  The bf16 weights sit in LDS,
+// rows padded by 8 elements so the 16 lanes of a fragment load hit distinct banks.
 //
-// MFMA 16x16x16 fragment layout (lane l, r0 = l % 16, kq = l / 16):
-//   A (16 x 16, rows x k):  A[r0][4 kq + e], e = 0..3
-//   B (16 x 16, k x cols):  B[4 kq + e][r0]
-//   D (16 x 16):            D[4 kq + e][r0]
+// MFMA fragment layouts (lane l, r0 = l % 16, kq = l / 16):
+//   16x16x16: A[r0][4 kq + e], B[4 kq + e][r0], e = 0..3
+//   16x16x32: A[r0][8 kq + e], B[8 kq + e][r0], e = 0..7
+//   D (16 x 16, both):  D[4 kq + e][r0], e = 0..3
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -22,6 +23,8 @@
 namespace fdtdp {
 
 typedef short s4 __attribute__((ext_vector_type(4)));
+typedef short s8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t to_bf16(float f) {
@@ -48,18 +51,27 @@ __device__ __forceinline__ float gelu_grad_f(float x) {
 __device__ __forceinline__ f4 mfma(s4 a, s4 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ f4 mfma32(s8 a, s8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a),
+                                                 __builtin_bit_cast(bf8, b), c, 0, 0, 0);
+}
 
 // --- weights in LDS -----------------------------------------------------------------
-struct MlpLds {
+// 16-byte aligned (W1 and W2 rows are whole multiples of 16 bytes), so that a lane's 8-bf16
+// weight fragment is one ds_read_b128; with the 80- and 272-byte row pitches the 8 lanes of
+// each pass of such a read fall on distinct 16-byte bank groups.
+struct alignas(16) MlpLds {
   uint16_t W1[kNH * kK1P];     // W1[n][k], k < 18 real, rest zero
   uint16_t W2[kNH * kK2P];     // W2[n][k]
   float b1[kNH], b2[kNH], w3[kNH];
   float b3;
 };
 
-__device__ void load_weights(MlpLds& L, const MlpWeights& W, bool transposed_w2) {
+enum class W2Form { kPlain, kPermuted };   // W.W2 (training) or W.W2P (inference)
+
+__device__ void load_weights(MlpLds& L, const MlpWeights& W, W2Form form) {
   const int t = threadIdx.x, nt = blockDim.x;
-  const uint16_t* src2 = transposed_w2 ? W.W2T : W.W2;
+  const uint16_t* src2 = form == W2Form::kPermuted ? W.W2P : W.W2;
   for (int i = t; i < kNH * kK1P / 4; i += nt)
     reinterpret_cast<uint2*>(L.W1)[i] = reinterpret_cast<const uint2*>(W.W1)[i];
   for (int i = t; i < kNH * kK2P / 4; i += nt)
@@ -123,31 +135,29 @@ __device__ __forceinline__ void wave_forward(const MlpLds& L, const uint16_t* Xs
 }
 
 // Register-chained forward pass of G groups of 16 rows held by one wavefront, with every
-// layer computed transposed (Z^T = W X^T): the MFMA result of a layer lands in exactly the
-// lane layout the next layer takes as its B operand, so activations never leave
-// registers and only the weights are read from LDS (each weight fragment serves G groups).
-//   xb[g][kk]: B operand of layer 1, lane (r0, kq) holds X[row r0][16 kk + 4 kq + e]
+// layer computed transposed (Z^T = W X^T) on 16x16x32 MFMAs: the D registers of two
+// layer-1 tiles form one B operand of layer 2 (the k order W2P is packed in), so
+// activations never leave registers and only the weights are read from LDS (each weight
+// fragment serves G groups).  The biases start the accumulators.
+//   xb[g]: B operand of layer 1, lane (r0, kq) holds X[row r0][8 kq + e], e = 0..7
 //   returns y[g] of row r0 of group g (on all four kq lanes of that row)
 template <int G>
-__device__ __forceinline__ void wave_forward_t(const MlpLds& L, const s4 (&xb)[G][2],
+__device__ __forceinline__ void wave_forward_t(const MlpLds& L, const s8 (&xb)[G],
                                                float (&y)[G]) {
   const int l = threadIdx.x & 63, r0 = l & 15, kq = l >> 4;
-  s4 a1[G][8];
+  s4 a1[G][8];   // tile nt: hidden units 16 nt + 4 kq + e of row r0
 #pragma unroll
   for (int nt = 0; nt < 8; ++nt) {
-    const s4 w0 = *reinterpret_cast<const s4*>(L.W1 + (nt * 16 + r0) * kK1P + kq * 4);
-    const s4 w1 = *reinterpret_cast<const s4*>(L.W1 + (nt * 16 + r0) * kK1P + 16 + kq * 4);
-    float bias[4];
+    const s8 w = *reinterpret_cast<const s8*>(L.W1 + (nt * 16 + r0) * kK1P + kq * 8);
+    f4 bias;
 #pragma unroll
     for (int e = 0; e < 4; ++e) bias[e] = L.b1[nt * 16 + kq * 4 + e];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      f4 c = {0.f, 0.f, 0.f, 0.f};
-      c = mfma(w0, xb[g][0], c);
-      c = mfma(w1, xb[g][1], c);
+      const f4 c = mfma32(w, xb[g], bias);
       s4 o;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) o[e] = (short)to_bf16(gelu_f(c[e] + bias[e]));
+      for (int e = 0; e < 4; ++e) o[e] = (short)to_bf16(gelu_f(c[e]));
       a1[g][nt] = o;
     }
   }
@@ -157,19 +167,26 @@ __device__ __forceinline__ void wave_forward_t(const MlpLds& L, const s4 (&xb)[G
 #pragma unroll 1
   for (int nt = 0; nt < 8; ++nt) {
     f4 c[G];
+    f4 bias;
 #pragma unroll
-    for (int g = 0; g < G; ++g) c[g] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int e = 0; e < 4; ++e) bias[e] = L.b2[nt * 16 + kq * 4 + e];
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) {
-      const s4 w = *reinterpret_cast<const s4*>(L.W2 + (nt * 16 + r0) * kK2P + kk * 16 + kq * 4);
+    for (int g = 0; g < G; ++g) c[g] = bias;
 #pragma unroll
-      for (int g = 0; g < G; ++g) c[g] = mfma(w, a1[g][kk], c[g]);
+    for (int kk = 0; kk < 4; ++kk) {
+      const s8 w = *reinterpret_cast<const s8*>(L.W2 + (nt * 16 + r0) * kK2P + kk * 32 + kq * 8);
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const s8 b = __builtin_shufflevector(a1[g][2 * kk], a1[g][2 * kk + 1], 0, 1, 2, 3, 4, 5,
+                                             6, 7);
+        c[g] = mfma32(w, b, c[g]);
+      }
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const float bias = L.b2[nt * 16 + kq * 4 + e], w3 = L.w3[nt * 16 + kq * 4 + e];
+      const float w3 = L.w3[nt * 16 + kq * 4 + e];
 #pragma unroll
-      for (int g = 0; g < G; ++g) yp[g] = fmaf(gelu_f(c[g][e] + bias), w3, yp[g]);
+      for (int g = 0; g < G; ++g) yp[g] = fmaf(gelu_f(c[g][e]), w3, yp[g]);
     }
   }
 #pragma unroll
@@ -181,13 +198,16 @@ __device__ __forceinline__ void wave_forward_t(const MlpLds& L, const s4 (&xb)[G
   }
 }
 
-// Pack 4 floats / s into bf16 (ties to even).
-__device__ __forceinline__ s4 pack4(float a, float b, float c, float d) {
-  s4 o;
-  o[0] = (short)to_bf16(a);
-  o[1] = (short)to_bf16(b);
-  o[2] = (short)to_bf16(c);
-  o[3] = (short)to_bf16(d);
+// Two floats as two bf16 (ties to even) in one dword, the first in the low half.
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+  return (uint32_t)to_bf16(a) | ((uint32_t)to_bf16(b) << 16);
+}
+
+// Pack 8 floats into bf16 (ties to even).
+__device__ __forceinline__ s8 pack8(const float (&v)[8]) {
+  s8 o;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) o[e] = (short)to_bf16(v[e]);
   return o;
 }
 
@@ -200,24 +220,22 @@ __global__ __launch_bounds__(kInferWaves * 64) void k_mlp_rows(MlpWeights W,
                                                               const float* __restrict__ X, int n,
                                                               float* __restrict__ Y) {
   __shared__ MlpLds L;
-  load_weights(L, W, false);
+  load_weights(L, W, W2Form::kPermuted);
   __syncthreads();
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, r0 = l & 15, kq = l >> 4;
   const int nwaves = gridDim.x * kInferWaves;
   for (int t = blockIdx.x * kInferWaves + wave; t * kWaveRows < n; t += nwaves) {
-    s4 xb[kInferG][2];
+    s8 xb[kInferG];
 #pragma unroll
     for (int g = 0; g < kInferG; ++g) {
       const int row = t * kWaveRows + g * 16 + r0;
       float v[8];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        v[e] = row < n ? X[(size_t)row * kNIn + kq * 4 + e] : 0.f;
-        const int k2 = 16 + kq * 4 + e;
-        v[4 + e] = (row < n && k2 < kNIn) ? X[(size_t)row * kNIn + k2] : 0.f;
+      for (int e = 0; e < 8; ++e) {
+        const int k = kq * 8 + e;
+        v[e] = (row < n && k < kNIn) ? X[(size_t)row * kNIn + k] : 0.f;
       }
-      xb[g][0] = pack4(v[0], v[1], v[2], v[3]);
-      xb[g][1] = pack4(v[4], v[5], v[6], v[7]);
+      xb[g] = pack8(v);
     }
     float y[kInferG];
     wave_forward_t<kInferG>(L, xb, y);
@@ -244,7 +262,7 @@ __global__ __launch_bounds__(256) void k_mlp_grad(MlpWeights W, const float* __r
   __shared__ uint16_t dZ2s[64 * kK2P];
   __shared__ uint16_t dZ1s[64 * kK2P];
   __shared__ float red[4][3 * kNH + 2];     // per-wave column sums: db1, db2, dw3, db3, loss
-  load_weights(L, W, false);
+  load_weights(L, W, W2Form::kPlain);
   for (int i = threadIdx.x; i < kNH * kK2P / 4; i += blockDim.x)
     reinterpret_cast<uint2*>(W2T)[i] = reinterpret_cast<const uint2*>(W.W2T)[i];
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, r0 = l & 15, kq = l >> 4;
@@ -422,6 +440,7 @@ __global__ void k_mlp_pack(const float* __restrict__ master, MlpWeights W) {
     const int nrow = t / kK2P, k = t - nrow * kK2P;
     W.W2[t] = k < kNH ? to_bf16(master[kOffW2 + nrow * kNH + k]) : (uint16_t)0;
     W.W2T[t] = k < kNH ? to_bf16(master[kOffW2 + k * kNH + nrow]) : (uint16_t)0;
+    W.W2P[t] = k < kNH ? to_bf16(master[kOffW2 + nrow * kNH + mlp_w2p_col(k)]) : (uint16_t)0;
   }
   if (t < kNH) {
     W.b1[t] = master[kOffB1 + t];
@@ -522,7 +541,7 @@ __global__ __launch_bounds__(kInferWaves * 64) void k_mlp2d(const Run2D<float>* 
                                                            MlpWeights W, MlpCells2D C,
                                                            int64_t step) {
   __shared__ MlpLds L;
-  load_weights(L, W, false);
+  load_weights(L, W, W2Form::kPermuted);
   __syncthreads();
   const Run2D<float>& R = *rp;
   const int nx = R.nx;
@@ -542,13 +561,17 @@ __global__ __launch_bounds__(kInferWaves * 64) void k_mlp2d(const Run2D<float>* 
       if (i < nx) h2d_rows<4>(R, i, strip * 4, step);
     }
     if (t >= tiles_m) continue;
-    s4 xb[kInferG][2];
+    s8 xb[kInferG];
     float ev[kInferG], sv[kInferG];
     int kidx[kInferG];
 #pragma unroll
     for (int g = 0; g < kInferG; ++g) {
       const int row = t * kWaveRows + g * 16 + r0;
       const int cell = row >> 1, comp = row & 1;
+      // each lane gathers 4 history samples E^{n - kh}, kh = 4 kq + q (the four lanes of
+      // a row share the loads); the B operand wants features 8 kq .. 8 kq + 7 in lane
+      // (r0, kq): the history on kq = 0, 1 (joined from lanes 2 kq and 2 kq + 1 of the
+      // row by two lane permutations), omega_p dt and log10(nu dt) on kq = 2
       float h[4] = {0.f, 0.f, 0.f, 0.f};
       float e = 0.f, m = 0.f, q1 = 0.f, q2 = 0.f;
       kidx[g] = -1;
@@ -561,7 +584,7 @@ __global__ __launch_bounds__(kInferWaves * 64) void k_mlp2d(const Run2D<float>* 
         float* ring = C.ring + ((size_t)cell * 2 + comp) * kHist;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int kh = kq * 4 + q;                 // history index: E^{n - kh}
+          const int kh = kq * 4 + q;
           h[q] = kh == 0 ? e : ring[(slot - kh) & (kHist - 1)];
           m = fmaxf(m, fabsf(h[q]));
         }
@@ -573,8 +596,19 @@ __global__ __launch_bounds__(kInferWaves * 64) void k_mlp2d(const Run2D<float>* 
       m = fmaxf(m, __shfl_xor(m, 32));
       const float sc = fmaxf(m, 1e-30f);
       const float rs = 1.0f / sc;   // features h / s as h * (1 / s): within 1 ulp, then bf16
-      xb[g][0] = pack4(h[0] * rs, h[1] * rs, h[2] * rs, h[3] * rs);
-      xb[g][1] = kq == 0 ? pack4(q1, q2, 0.f, 0.f) : pack4(0.f, 0.f, 0.f, 0.f);
+      const uint32_t p0 = pack_bf16x2(h[0] * rs, h[1] * rs);
+      const uint32_t p1 = pack_bf16x2(h[2] * rs, h[3] * rs);
+      // lane (r0, kq), kq < 2, takes the packed samples of lanes (r0, 2 kq) and (r0, 2 kq + 1)
+      const int src_lo = r0 + 32 * (kq & 1), src_hi = src_lo + 16;
+      const uint32_t lo0 = __shfl(p0, src_lo), lo1 = __shfl(p1, src_lo);
+      const uint32_t hi0 = __shfl(p0, src_hi), hi1 = __shfl(p1, src_hi);
+      const uint32_t pq = pack_bf16x2(q1, q2);
+      uint32_t d[4];
+      d[0] = kq < 2 ? lo0 : (kq == 2 ? pq : 0u);
+      d[1] = kq < 2 ? lo1 : 0u;
+      d[2] = kq < 2 ? hi0 : 0u;
+      d[3] = kq < 2 ? hi1 : 0u;
+      xb[g] = __builtin_bit_cast(s8, d);
       ev[g] = e;
       sv[g] = sc;
     }

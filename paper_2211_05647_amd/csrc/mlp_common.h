@@ -26,11 +26,24 @@ struct MlpWeights {
   uint16_t* W1;    // [128][kK1P]
   uint16_t* W2;    // [128][kK2P]
   uint16_t* W2T;   // [128][kK2P], W2 transposed
+  uint16_t* W2P;   // [128][kK2P], W2 with its columns in the inference kernels' k order
+                   // (mlp_w2p_col: the 16x16x32 B-operand order of the layer-1 output)
   float* b1;
   float* b2;
   float* w3q;      // w3 rounded to bf16, held as float
   float* b3;
 };
+
+// Column of W2 held at column k of W2P.  The inference kernels compute each layer
+// transposed (Z^T = W X^T) with 16x16x32 MFMAs, so the layer-1 output of hidden tile t
+// lands in lane (r, q) as units 16 t + 4 q + e, e < 4 (the D layout); the B operand of a
+// 32-deep k block of layer 2 takes 8 consecutive k per lane, k = 32 kk + 8 q + e.  Joining
+// the D registers of tiles 2 kk and 2 kk + 1 gives exactly that operand if k stands for
+// hidden unit 32 kk + 16 (e / 4) + 4 q + (e % 4) -- a fixed permutation of the sum's terms.
+constexpr int mlp_w2p_col(int k) {
+  const int kk = k >> 5, q = (k >> 3) & 3, e = k & 7;
+  return 32 * kk + 16 * (e >> 2) + 4 * q + (e & 3);
+}
 
 struct ReplayCell {
   float tau;       // dt * nu_mean
