@@ -357,17 +357,20 @@ def extra_c2(B, W, torch, autotune, steps=None):
                        bytes_per_step=bytes_2d(run), hbm_gbs=gbs, hbm_frac=frac)}
 
 
-def extra_c3(B, W, torch, reps=3):
+def extra_c3(B, W, torch, reps=3, autotune=None):
     """Batch of 256 uneven 1D runs, advanced to the last run's end in its default launch
-    form."""
+    form (blocked launches per Nv group), with the steps per launch the autotuner stored
+    for this batch (the library default if none)."""
     runs = W.c3()
+    kb = autotune.lookup_batch_time_block(runs) if autotune else 0
     work = sum(r.plasma_cells * r.nv * r.steps for r in runs)
     stream_by = sum(bytes_1d(r) * r.steps for r in runs)
     tot = max(r.steps for r in runs)
     log(f"c3: {len(runs)} runs, {tot} steps max")
     walls = []
     for _ in range(reps):
-        sim = B.Sim(runs)
+        sim = B.Sim(runs, time_block=kb or None)
+        k_used = sim.time_block()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         sim.run(tot)
@@ -378,6 +381,7 @@ def extra_c3(B, W, torch, reps=3):
     out = dict(workload="256 independent 1D runs, Nx in [500, 20000], Nv in {64,128,256}, "
                         "2 Nx steps each",
                updates_per_s=work / wall, seconds=wall, seconds_reps=walls,
+               steps_per_launch=k_used,
                one_step_stream_equivalent_gbs=stream_by / wall / 1e9,
                one_step_stream_equivalent_frac=stream_by / wall / 1e9 / HBM_PEAK_GBS)
     cb = pmc_bytes("k_step1d_c3_batch_pmc.json")
@@ -849,7 +853,7 @@ def main():
     if args.only:
         only = {"c1l": lambda: extra_c1l(B, W, torch, autotune),
                 "c2": lambda: extra_c2(B, W, torch, autotune, args.steps),
-                "c3": lambda: extra_c3(B, W, torch, reps=1),
+                "c3": lambda: extra_c3(B, W, torch, reps=1, autotune=autotune),
                 "fp64": lambda: extra_fp64(B, W, torch, min(args.steps, 2000)),
                 "closure": lambda: closure_speedup(B, W, torch),
                 "c4": lambda: c4_steps(B, W, torch, args.steps),
@@ -926,7 +930,7 @@ def main():
         for f in (lambda: extra_c1l(B, W, torch, autotune),
                   lambda: extra_fp64(B, W, torch),
                   lambda: extra_c2(B, W, torch, autotune),
-                  lambda: extra_c3(B, W, torch),
+                  lambda: extra_c3(B, W, torch, autotune=autotune),
                   lambda: closure_speedup(B, W, torch),
                   lambda: extra_full(B, W, torch),
                   lambda: extra_3d(B, W, torch),

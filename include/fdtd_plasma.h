@@ -202,7 +202,7 @@ int fdtd_plasma_create(const fdtd_grid *grid, const fdtd_profile *profile,
  * run record (E^n, J^{n+1/2}) at the plasma nodes tap_nodes[r * ntap + k] after every
  * step of that run (NULL when ntap = 0).  Default launch form (batch mode 1): the runs
  * with at least K steps left advance K steps per launch (temporal blocking, K from
- * fdtd_plasma_set_time_block, default 7), one launch per Nv group; runs that end inside
+ * fdtd_plasma_set_time_block, default 9), one launch per Nv group; runs that end inside
  * such a pass, and the batch's tail once fewer blocked work-groups than compute units
  * remain, take one step per launch over the tiles of the runs still active.  See
  * fdtd_plasma_set_batch_mode for the persistent form.  Workspace size via
@@ -294,9 +294,9 @@ int fdtd_plasma_set_tiling(fdtd_plasma *h, int32_t tile, int32_t cells_per_group
  * recomputes a halo of `steps` nodes per side, so F1 -- and F0 -- cross HBM once per
  * `steps` steps) and the remainder one step per launch.  steps = 1 turns it off; 3, 5, 7
  * and 9 are accepted.  Results are bitwise those of one-step launches (the kinetic step is
- * local in space, see section 5.2).  The library's default is 7; a caller with a tuning
- * table sets its own (the Python package's autotuner stores 9 for the 65,536-node line
- * at Nv = 512).  Other runs (FP64, batches of the
+ * local in space, see section 5.2).  The library's default is 9 (the fastest measured on
+ * MI355X for the 65,536-node line at Nv = 512 and for a 256-run batch); a caller with a
+ * tuning table sets its own.  Other runs (FP64, batches of the
  * persistent mode, 2D, 3D, other speed counts, lines too short to cut into blocks)
  * step one step per launch; the call then only records the value.
  * May be called between runs.  fdtd_plasma_time_block reports the steps per launch in

@@ -79,7 +79,7 @@ hipError_t launch_batch1d_persistent(const void* runs, const int32_t* order, int
                                      hipStream_t stream);
 
 // Temporally blocked 1D launch (kernels1d_tb.hip): k steps of every tile of one FP32 run.
-constexpr int kDefaultTimeBlock = 7;
+constexpr int kDefaultTimeBlock = 9;
 bool tb_supported(int half);             // stored bins per node the blocked kernel handles
 int tb_block();                          // threads per work-group = largest extended range
 int tb_max_rows(int half);               // plasma rows one work-group holds
