@@ -70,16 +70,23 @@ PMC_FILES = {
 }
 
 
-def pmc_bytes(name):
-    """HBM bytes per launch (or per run, for the batch) from a committed rocprofv3 counter
-    summary, if it was taken on the kernel sources as they are now (else None)."""
-    p = os.path.join(ROOT, "profiles", name)
-    if not os.path.exists(p):
+def pmc_file(name):
+    """A counter summary from profiles/ if it was taken on the kernel sources as they are."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
         return None
-    d = json.load(open(p))
+    with open(path) as f:
+        d = json.load(f)
     if d.get("kernel_hash") != kernel_hash(PMC_FILES[name]):
         return None
-    return d.get("hbm_bytes_per_launch", d.get("hbm_bytes_total"))
+    return d
+
+
+def pmc_bytes(name):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it was taken on
+    the kernel sources as they are now (else None)."""
+    d = pmc_file(name)
+    return d.get("hbm_bytes_per_launch") if d else None
 
 
 def bytes_1d(run, fb=4):
@@ -357,12 +364,25 @@ def extra_c2(B, W, torch, autotune, steps=None):
                        bytes_per_step=bytes_2d(run), hbm_gbs=gbs, hbm_frac=frac)}
 
 
-def extra_c3(B, W, torch, reps=3, autotune=None):
+def extra_c3(B, W, torch, reps=3, autotune=None, limit=None):
     """Batch of 256 uneven 1D runs, advanced to the last run's end in its default launch
     form (blocked launches per Nv group), with the steps per launch the autotuner stored
-    for this batch (the library default if none)."""
+    for this batch (the library default if none).  `limit` stops after that many steps
+    instead, with a progress line every 1000 steps (for counter collection, which
+    serialises every dispatch)."""
     runs = W.c3()
     kb = autotune.lookup_batch_time_block(runs) if autotune else 0
+    if limit:
+        sim = B.Sim(runs, time_block=kb or None)
+        done = 0
+        while done < limit:
+            n = min(1000, limit - done)
+            sim.run(n)
+            torch.cuda.synchronize()
+            done += n
+            log(f"c3: {done} of {limit} steps")
+        sim.close()
+        return {"c3_prefix": dict(steps=limit, steps_per_launch=kb or None)}
     work = sum(r.plasma_cells * r.nv * r.steps for r in runs)
     stream_by = sum(bytes_1d(r) * r.steps for r in runs)
     tot = max(r.steps for r in runs)
@@ -384,11 +404,12 @@ def extra_c3(B, W, torch, reps=3, autotune=None):
                steps_per_launch=k_used,
                one_step_stream_equivalent_gbs=stream_by / wall / 1e9,
                one_step_stream_equivalent_frac=stream_by / wall / 1e9 / HBM_PEAK_GBS)
-    cb = pmc_bytes("k_step1d_c3_batch_pmc.json")
-    if cb:
-        out["hbm_bytes_counters"] = cb
-        out["hbm_gbs_counters"] = cb / wall / 1e9
-        out["hbm_frac_counters"] = cb / wall / 1e9 / HBM_PEAK_GBS
+    pf = pmc_file("k_step1d_c3_batch_pmc.json")
+    if pf:
+        # counter traffic of the blocked launches over the batch's first 4500 steps (every
+        # run still going), against the same dispatches' trace time
+        out["blocked_hbm_gbs_counters_prefix"] = pf["blocked_prefix_hbm_gbs"]
+        out["blocked_hbm_frac_counters_prefix"] = pf["blocked_prefix_hbm_gbs"] / HBM_PEAK_GBS
     return {"c3": out}
 
 
@@ -835,7 +856,8 @@ def main():
     ap.add_argument("--only", choices=["c1l", "fp64", "c2", "c3", "closure", "c4", "sweep", "full", "3d", "sweep3d",
                              "twoterm", "3dtt"], default=None,
                     help="run only one of the extra measurements (for profiling); c2 and c4 "
-                         "take --steps steps")
+                         "take --steps steps; c3 with an explicit --steps runs only that many "
+                         "steps of the batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the kinetic-FDTD path here runs on a single "
@@ -853,7 +875,8 @@ def main():
     if args.only:
         only = {"c1l": lambda: extra_c1l(B, W, torch, autotune),
                 "c2": lambda: extra_c2(B, W, torch, autotune, args.steps),
-                "c3": lambda: extra_c3(B, W, torch, reps=1, autotune=autotune),
+                "c3": lambda: extra_c3(B, W, torch, reps=1, autotune=autotune,
+                                       limit=args.steps if args.steps != ap.get_default("steps") else None),
                 "fp64": lambda: extra_fp64(B, W, torch, min(args.steps, 2000)),
                 "closure": lambda: closure_speedup(B, W, torch),
                 "c4": lambda: c4_steps(B, W, torch, args.steps),
