@@ -215,12 +215,14 @@ int fdtd_plasma_create_batch(int32_t nruns, const fdtd_grid *grids,
                              const int64_t *steps, int32_t ntap, const int32_t *tap_nodes,
                              const fdtd_device *dev, fdtd_plasma **out);
 
-/* Batch launch form: mode 0 = one persistent launch per fdtd_plasma_run, `groups`
- * work-groups (0 = one per run, at most two per compute unit) each pulling whole runs
- * longest-first from a queue and taking them through every step alone; mode 1 (default)
- * = K-step blocked launches with one-step launches for the remainders, as described at
- * fdtd_plasma_create_batch.  Both give bitwise identical results.  Only before the first
- * step. */
+/* Batch launch form: mode 1 (default) = K-step blocked launches with one-step launches
+ * for the remainders, as described at fdtd_plasma_create_batch; mode 0 = one persistent
+ * launch per fdtd_plasma_run: `groups` work-groups (0 = as many as fit on the device) take
+ * (tile, K-step block) items of every run in order from a work counter, a block of a tile
+ * starting once the tile and its two neighbours have finished the block before; each
+ * run's last steps go as one odd block or two.  Mode 0 needs what the blocked path needs
+ * (K >= 3, runs of supported Nv); otherwise the batch steps one step per launch.  Both
+ * modes give bitwise identical results.  Only before the first step. */
 int fdtd_plasma_set_batch_mode(fdtd_plasma *h, int32_t mode, int32_t groups);
 
 /* Copy the taps of run `run`: [ntap][steps taken by that run][2] doubles, (E in V/m,
@@ -230,7 +232,9 @@ int fdtd_plasma_read_taps(fdtd_plasma *h, int32_t run, double *dst, size_t dst_l
 
 /* Per-run status after the last run: 0, or FDTD_ENUMERIC if that run produced a
  * non-finite E value (1D; other runs of the batch are unaffected) or, with the FULL or
- * TWO_TERM model (1D and 3D), broke the explicit velocity-exchange limit.  2D handles
+ * TWO_TERM model (1D and 3D), broke the explicit velocity-exchange limit, or FDTD_ESTATE if
+ * a persistent batch launch (batch mode 0) gave up waiting for a neighbouring tile (the
+ * batch's results are then void; it does not happen in a correct launch).  2D handles
  * report 0.  Later steps do not clear the flag. */
 int fdtd_plasma_run_status(fdtd_plasma *h, int32_t run, int32_t *status);
 
@@ -296,9 +300,9 @@ int fdtd_plasma_set_tiling(fdtd_plasma *h, int32_t tile, int32_t cells_per_group
  * and 9 are accepted.  Results are bitwise those of one-step launches (the kinetic step is
  * local in space, see section 5.2).  The library's default is 9 (the fastest measured on
  * MI355X for the 65,536-node line at Nv = 512 and for a 256-run batch); a caller with a
- * tuning table sets its own.  Other runs (FP64, batches of the
- * persistent mode, 2D, 3D, other speed counts, lines too short to cut into blocks)
- * step one step per launch; the call then only records the value.
+ * tuning table sets its own.  Batches use K for both launch forms (the persistent one
+ * takes K-step blocks too).  Other runs (FP64, 2D, 3D, other speed counts, lines too short
+ * to cut into blocks) step one step per launch; the call then only records the value.
  * May be called between runs.  fdtd_plasma_time_block reports the steps per launch in
  * effect (1 when the run is not blocked) and, if rows_per_launch is not NULL, the number of
  * F1 rows one blocked launch reads (owned rows plus the halo rows it recomputes; 0 when

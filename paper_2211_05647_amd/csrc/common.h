@@ -8,7 +8,6 @@ namespace fdtdp {
 constexpr int kMaxProbes = 16;
 constexpr int kBlock = 256;        // threads per work-group of the step kernels
 constexpr int kMaxTile1D = 256;    // nodes per 1D tile: one node per thread
-constexpr int kBatchBlock = 1024;  // threads (and nodes per chunk) of the persistent batch kernel
 constexpr int kMaxTaps = 8;        // training-pair taps per 1D run
 
 // 16-byte vector of the storage type: 4 floats or 2 doubles per lane per chunk.
@@ -268,6 +267,15 @@ struct Tile1D {
   int32_t run, node0, node1, cell0, cell1;
 };
 
+// A tile of the persistent batch launch with what its items need besides: the run's full
+// K-step blocks in the launch and the steps left after them, and flags (bit 0: the tile
+// has a right neighbour in its run; a left one exists when node0 > 0).  32 bytes, read in
+// one go.
+struct alignas(16) TbQueueTile {
+  Tile1D tile;
+  int32_t full, rest, flags;
+};
+
 // One 1D run as the step kernel sees it.  Ping-pong field buffers: at step n the
 // current E/H live in buffer (n & 1) and the kernel writes buffer (n & 1) ^ 1.
 template <class T> struct Run1D {
@@ -296,7 +304,6 @@ template <class T> struct Run1D {
   T* tap_buf;      // [ntap][tap_cap][2]
   int64_t tap_cap;
   int32_t* status; // bit 0: a non-finite E value was produced
-  const int32_t* chunk_cell;  // [nchunk + 1] first plasma cell of each kBatchBlock-node chunk
   // kinetic model: 0 linear F1 (df: [ncell][half]); 1 full distribution (df:
   // [ncell][2 half], odd then even half of f - n fhat; b_bin then holds the equilibrium
   // flux differences -(dt/dv)(-e/m)(fhat_{k+1} - fhat_{k-1}) per unit density and field)

@@ -196,14 +196,21 @@ struct fdtd_plasma {
   size_t runs_off = 0, tiles_off = 0;
   int ntiles = 0;
   std::vector<int64_t> tile_limit;   // step limit of each tile, non-increasing
-  size_t order_off = 0, queue_off = 0, status_off = 0;
-  int batch_mode = 1, batch_groups = 0, ntap = 0;   // batch default: per-step launches
+  size_t status_off = 0;
+  int batch_mode = 1, batch_groups = 0, ntap = 0;   // batch default: K-step launches
+  size_t qtiles_off = 0, qdone_off = 0, qstart_off = 0, qround_off = 0, qsegt_off = 0,
+         qctr_off = 0;                              // persistent batch launch (mode 0)
   // temporal blocking of a single FP32 1D run: time_block steps per launch (1 = off)
   int time_block = kDefaultTimeBlock;
   size_t tbtiles_off = 0;
   int ntbtiles = 0;
   int64_t tb_rows = 0;     // F1 rows one blocked pass reads (owned plus halo)
   std::vector<TbSeg> tb_seg;
+  std::vector<Tile1D> tb_host;   // the blocked tiles (host copy), per Nv group
+  // the persistent launch's tables (host copies kept while their uploads may be pending)
+  std::vector<TbQueueTile> q_tiles;
+  std::vector<int64_t> q_start;
+  std::vector<int32_t> q_round, q_segt;
   // A blocked launch reads a run's rows from one copy and writes them to the other, so
   // that no work-group reads halo rows a neighbour of the same launch has already
   // advanced: each run's second copy sits df_delta bytes after its rows (the state
@@ -263,7 +270,6 @@ size_t layout_1d(fdtd_plasma* h, const std::vector<RunSpec1D>& specs, int precis
     x.ntap = (int)specs[r].taps.size();
     x.tap_cap = specs[r].steps == INT64_MAX ? 0 : specs[r].steps;
     x.off_tap = cv.take((size_t)std::max<int64_t>(x.ntap * x.tap_cap, 1) * 2 * es);
-    x.off_chunk = cv.take(sz<int32_t>((x.nx + kBatchBlock) / kBatchBlock + 1));
     x.off_cell_node = cv.take(sz<int32_t>(std::max(x.ncell, 1)));
     x.off_tau = cv.take((size_t)std::max(x.ncell, 1) * es);
     x.off_dens = cv.take((size_t)std::max(x.ncell, 1) * es);
@@ -281,12 +287,21 @@ size_t layout_1d(fdtd_plasma* h, const std::vector<RunSpec1D>& specs, int precis
   const size_t tiles_off = cv.take(max_tiles * sizeof(Tile1D));
   // tiles of the temporally blocked kernel (single runs; never narrower than 32 nodes)
   const size_t tbtiles_off = cv.take(max_tiles * sizeof(Tile1D));
-  const size_t order_off = cv.take(sz<int32_t>(specs.size()));
-  const size_t queue_off = cv.take(sz<int32_t>(1));
+  // persistent batch launch: its tile order, per-tile block counts, segment tables, counter
+  const size_t qtiles_off = cv.take(max_tiles * sizeof(TbQueueTile));
+  const size_t qdone_off = cv.take(sz<int32_t>(max_tiles));
+  const size_t qstart_off = cv.take(sz<int64_t>(specs.size() + 1));
+  const size_t qround_off = cv.take(sz<int32_t>(specs.size()));
+  const size_t qsegt_off = cv.take(sz<int32_t>(specs.size()));
+  const size_t qctr_off = cv.take(sz<uint64_t>(1));
   const size_t status_off = cv.take(sz<int32_t>(specs.size()));
   if (h) {
-    h->order_off = order_off;
-    h->queue_off = queue_off;
+    h->qtiles_off = qtiles_off;
+    h->qdone_off = qdone_off;
+    h->qstart_off = qstart_off;
+    h->qround_off = qround_off;
+    h->qsegt_off = qsegt_off;
+    h->qctr_off = qctr_off;
     h->status_off = status_off;
     h->state_off = 0;
     h->state_bytes = state_end;
@@ -382,20 +397,8 @@ int upload_1d(fdtd_plasma* h) {
       }
     }
     x.cell_node = cn;
-    // first plasma cell of every kBatchBlock-node chunk (persistent batch kernel)
-    std::vector<int32_t> chunk;
-    {
-      int c = 0;
-      for (int n0 = 0; n0 <= x.nx; n0 += kBatchBlock) {
-        chunk.push_back(c);
-        while (c < x.ncell && cn[c] < std::min(x.nx + 1, n0 + kBatchBlock)) ++c;
-      }
-      chunk.push_back(c);
-    }
     hipError_t e;
     char* base = h->ws;
-    if ((e = hipMemcpyAsync(base + x.off_chunk, chunk.data(), chunk.size() * 4, hipMemcpyHostToDevice, h->stream)))
-      return hip_fail(e, "upload chunk offsets");
     if (x.ncell > 0) {
       if ((e = hipMemcpyAsync(base + x.off_cell_node, cn.data(), cn.size() * 4, hipMemcpyHostToDevice, h->stream)) ||
           (e = hipMemcpyAsync(base + x.off_tau, tau.data(), tau.size() * sizeof(T), hipMemcpyHostToDevice, h->stream)) ||
@@ -444,7 +447,6 @@ int upload_1d(fdtd_plasma* h) {
     R.tap_buf = reinterpret_cast<T*>(base + x.off_tap);
     R.tap_cap = x.tap_cap;
     R.status = reinterpret_cast<int32_t*>(base + h->status_off) + r;
-    R.chunk_cell = reinterpret_cast<const int32_t*>(base + x.off_chunk);
     R.model = x.model;
     R.kc = (T)kc;
     R.c_bin = reinterpret_cast<const T*>(base + x.off_c);
@@ -482,6 +484,7 @@ int build_tb_tiles(fdtd_plasma* h) {
   h->ntbtiles = 0;
   h->tb_rows = 0;
   h->tb_seg.clear();
+  h->tb_host.clear();
   const int k = h->time_block;
   if (k < 3 || h->precision != FDTD_FP32) return FDTD_OK;
   // plasma rows one work-group holds (the two-term kernel keeps two chunks per row)
@@ -552,6 +555,7 @@ int build_tb_tiles(fdtd_plasma* h) {
                                 hipMemcpyHostToDevice, h->stream);
   if (e) return hip_fail(e, "upload blocked tiles");
   h->ntbtiles = (int)tiles.size();
+  h->tb_host = std::move(tiles);
   return FDTD_OK;
 }
 
@@ -590,26 +594,95 @@ int build_tiles_1d(fdtd_plasma* h) {
   hipError_t e = hipMemcpyAsync(h->ws + h->tiles_off, tiles.data(), tiles.size() * sizeof(Tile1D),
                                 hipMemcpyHostToDevice, h->stream);
   if (e) return hip_fail(e, "upload tiles");
-  // run queue of the persistent batch kernel: most work first (steps x (F1 row bytes + node))
-  std::vector<int32_t> order(h->nruns);
-  for (int r = 0; r < h->nruns; ++r) order[r] = r;
-  auto work = [&](int r) {
-    const Host1D& x = h->h1[r];
-    const double st = h->specs[r].steps == INT64_MAX ? 1.0 : (double)h->specs[r].steps;
-    return st * ((double)x.ncell * x.row + 5.0 * (x.nx + 1));
-  };
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
-  e = hipMemcpyAsync(h->ws + h->order_off, order.data(), order.size() * 4, hipMemcpyHostToDevice,
-                     h->stream);
-  if (e) return hip_fail(e, "upload run order");
   return build_tb_tiles(h);
 }
 
+// Work-groups of the persistent batch launch: the set count, else every one that fits.
 int batch_groups(const fdtd_plasma* h) {
-  if (h->batch_groups > 0) return std::min(h->batch_groups, h->nruns);
+  if (h->batch_groups > 0) return h->batch_groups;
   int cus = 256;
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
-  return std::max(1, std::min(h->nruns, 2 * cus));
+  return std::max(1, cus * tb_queue_blocks_per_cu(h->time_block));
+}
+
+// The persistent batch launch of steps [s0, s1) (k_batch1d_queue): run r advances
+// min(its step count, s1) - s0 steps in blocks of K, then its odd rest as one block or as
+// rest - 1 and 1.  Every run's rows must sit in the first copy at the start; afterwards
+// run r's rows sit in copy (its block count) & 1.
+int run_queue(fdtd_plasma* h, int64_t s0, int64_t s1) {
+  const int kb = h->time_block, nr = h->nruns;
+  std::vector<int64_t> nblk(nr, 0), full(nr, 0), rest(nr, 0);
+  for (int r = 0; r < nr; ++r) {
+    const int64_t n = std::max<int64_t>(0, std::min(h->specs[r].steps, s1) - s0);
+    full[r] = n / kb;
+    rest[r] = n - full[r] * kb;
+    nblk[r] = full[r] + (rest[r] == 0 ? 0 : (rest[r] & 1) ? 1 : 2);
+  }
+  std::vector<int> order;
+  for (int r = 0; r < nr; ++r)
+    if (nblk[r] > 0) order.push_back(r);
+  if (order.empty()) return FDTD_OK;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nblk[a] > nblk[b]; });
+  // each run's tiles in node order (the blocked tile list keeps them so), runs most blocks first
+  std::vector<std::vector<Tile1D>> per(nr);
+  for (const Tile1D& t : h->tb_host) per[t.run].push_back(t);
+  h->q_tiles.clear();
+  std::vector<int64_t> cum;   // tiles of the runs order[0..k]
+  for (int r : order) {
+    for (const Tile1D& t : per[r]) {
+      TbQueueTile qt;
+      qt.tile = t;
+      qt.full = (int32_t)full[r];
+      qt.rest = (int32_t)rest[r];
+      qt.flags = t.node1 < h->h1[r].nx + 1 ? 1 : 0;
+      h->q_tiles.push_back(qt);
+    }
+    cum.push_back((int64_t)h->q_tiles.size());
+  }
+  // segments in round order: rounds [nblk of order[k + 1], nblk of order[k]) have the
+  // tiles of runs order[0..k] active
+  h->q_start.clear();
+  h->q_round.clear();
+  h->q_segt.clear();
+  int64_t items = 0;
+  for (int k = (int)order.size() - 1; k >= 0; --k) {
+    const int64_t lo = k + 1 < (int)order.size() ? nblk[order[k + 1]] : 0, hi = nblk[order[k]];
+    if (hi <= lo) continue;
+    h->q_start.push_back(items);
+    h->q_round.push_back((int32_t)lo);
+    h->q_segt.push_back((int32_t)cum[k]);
+    items += (hi - lo) * cum[k];
+  }
+  h->q_start.push_back(items);
+  const int ntq = (int)h->q_tiles.size();
+  hipError_t e;
+  if ((e = hipMemcpyAsync(h->ws + h->qtiles_off, h->q_tiles.data(), ntq * sizeof(TbQueueTile),
+                          hipMemcpyHostToDevice, h->stream)) ||
+      (e = hipMemcpyAsync(h->ws + h->qstart_off, h->q_start.data(), h->q_start.size() * 8,
+                          hipMemcpyHostToDevice, h->stream)) ||
+      (e = hipMemcpyAsync(h->ws + h->qround_off, h->q_round.data(), h->q_round.size() * 4,
+                          hipMemcpyHostToDevice, h->stream)) ||
+      (e = hipMemcpyAsync(h->ws + h->qsegt_off, h->q_segt.data(), h->q_segt.size() * 4,
+                          hipMemcpyHostToDevice, h->stream)) ||
+      (e = hipMemsetAsync(h->ws + h->qdone_off, 0, (size_t)ntq * 4, h->stream)) ||
+      (e = hipMemsetAsync(h->ws + h->qctr_off, 0, 8, h->stream)))
+    return hip_fail(e, "upload batch queue");
+  TbQueueArgs a;
+  a.tiles = reinterpret_cast<const TbQueueTile*>(h->ws + h->qtiles_off);
+  a.seg_start = reinterpret_cast<const int64_t*>(h->ws + h->qstart_off);
+  a.seg_round = reinterpret_cast<const int32_t*>(h->ws + h->qround_off);
+  a.seg_tiles = reinterpret_cast<const int32_t*>(h->ws + h->qsegt_off);
+  a.done = reinterpret_cast<int32_t*>(h->ws + h->qdone_off);
+  a.counter = reinterpret_cast<unsigned long long*>(h->ws + h->qctr_off);
+  a.s0 = s0;
+  a.s1 = s1;
+  a.delta = (int64_t)(h->df_delta / 4);
+  a.nseg = (int32_t)h->q_round.size();
+  a.k = kb;
+  e = launch_batch1d_queue(h->ws + h->runs_off, a, batch_groups(h), h->stream);
+  if (e) return hip_fail(e, "launch persistent batch kernel");
+  for (int r : order) h->df_cur[r] = (uint8_t)(nblk[r] & 1);
+  return FDTD_OK;
 }
 
 int finish_upload(fdtd_plasma* h) {
@@ -898,14 +971,12 @@ int fdtd_plasma_run(fdtd_plasma* h, int64_t nsteps) {
   h->started = true;
   int64_t nsteps_loop = nsteps;
   if ((e = hipEventRecord(h->ev0, h->stream))) return hip_fail(e, "hipEventRecord");
-  if (h->dims == 1 && h->nruns > 1 && h->batch_mode == 0) {
-    const int rc = rows_home(h, -1);
+  if (h->dims == 1 && h->nruns > 1 && h->batch_mode == 0 && h->ntbtiles > 0) {
+    // one persistent launch for the whole call
+    int rc = rows_home(h, -1);
     if (rc) return rc;
-    e = launch_batch1d_persistent(h->ws + h->runs_off,
-                                  reinterpret_cast<const int32_t*>(h->ws + h->order_off), h->nruns,
-                                  reinterpret_cast<int32_t*>(h->ws + h->queue_off), h->step,
-                                  h->step + nsteps, batch_groups(h), h->stream);
-    if (e) return hip_fail(e, "launch persistent batch kernel");
+    rc = run_queue(h, h->step, h->step + nsteps);
+    if (rc) return rc;
     nsteps_loop = 0;
   }
   int64_t k0 = 0;
@@ -1371,8 +1442,9 @@ int fdtd_plasma_run_status(fdtd_plasma* h, int32_t run, int32_t* status) {
     e = hipMemcpy(&v, h->ws + h->status_off + 4 * (size_t)run, 4, hipMemcpyDeviceToHost);
     if (e) return hip_fail(e, "copy status");
   }
-  *status = v ? FDTD_ENUMERIC : FDTD_OK;
-  if (v & 2) fail(FDTD_ENUMERIC, "run %d: a field broke the velocity CFL limit", run);
+  *status = (v & 4) ? FDTD_ESTATE : v ? FDTD_ENUMERIC : FDTD_OK;
+  if (v & 4) fail(FDTD_ESTATE, "run %d: a persistent batch launch gave up waiting for a tile", run);
+  else if (v & 2) fail(FDTD_ENUMERIC, "run %d: a field broke the velocity CFL limit", run);
   else if (v & 1) fail(FDTD_ENUMERIC, "run %d: non-finite field", run);
   return FDTD_OK;
 }

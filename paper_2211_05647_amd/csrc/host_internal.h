@@ -62,7 +62,7 @@ struct Host1D {
   size_t off_c = 0, off_v2h = 0;   // two-term model tables
   int ntap = 0;
   int64_t tap_cap = 0;
-  size_t off_tap = 0, off_chunk = 0;
+  size_t off_tap = 0;
 };
 
 // 1D launch (kernels1d.hip)
@@ -74,9 +74,6 @@ template <class T>
 hipError_t launch_step1d_tt(const void* runs, const void* tiles, int ntiles, int64_t step,
                             bool pending, bool flush, hipStream_t stream);
 
-hipError_t launch_batch1d_persistent(const void* runs, const int32_t* order, int nruns,
-                                     int32_t* queue, int64_t s0, int64_t s1, int groups,
-                                     hipStream_t stream);
 
 // Temporally blocked 1D launch (kernels1d_tb.hip): k steps of every tile of one FP32 run.
 constexpr int kDefaultTimeBlock = 9;
@@ -84,6 +81,22 @@ bool tb_supported(int half);             // stored bins per node the blocked ker
 int tb_block();                          // threads per work-group = largest extended range
 int tb_max_rows(int half);               // plasma rows one work-group holds
 int tb_blocks_per_cu(int k, int half);   // resident work-groups per compute unit
+// Persistent batch launch (kernels1d_tb.hip): every run of a batch through steps [s0, s1)
+// in one launch, (tile, block) items taken in order from a counter.
+struct TbQueueTile;              // common.h
+struct TbQueueArgs {
+  const TbQueueTile* tiles;     // [ntiles] runs with the most blocks first
+  const int64_t* seg_start;     // [nseg + 1]
+  const int32_t* seg_round;     // [nseg]
+  const int32_t* seg_tiles;     // [nseg]
+  int32_t* done;                // [ntiles], zero
+  unsigned long long* counter;  // zero
+  int64_t s0, s1, delta;
+  int32_t nseg, k;
+};
+int tb_queue_blocks_per_cu(int k);
+hipError_t launch_batch1d_queue(const void* runs, const TbQueueArgs& a, int groups,
+                                hipStream_t stream);
 // the same for the two-term model (half = speeds padded to a power of two)
 bool tb_tt_supported(int half);
 int tb_tt_max_rows(int half);

@@ -13,13 +13,10 @@
 // E and H are double-buffered, so halo values are re-derived from the previous
 // buffers and no work-group ever waits for another inside a step.
 //
-// Two launch forms share that step body:
-//   k_step1d             one launch per step, one work-group per tile (any number of
-//                        runs; tiles of finished runs are left out of the launch);
-//   k_batch1d_persistent one launch for a range of steps of a whole batch of runs: each
-//                        work-group pulls the next run from a longest-first queue (one
-//                        atomic add) and takes it through every step on its own, so no
-//                        work-group ever waits for another.
+// k_step1d launches it once per step, one work-group per tile (any number of runs;
+// tiles of finished runs are left out of the launch); the full-distribution and
+// two-term models have launches of their own over the same body.  Blocks of several
+// steps per launch, and the persistent batch launch, are in kernels1d_tb.hip.
 //
 // F1 layout: [cell][v > 0 bin], contiguous in the bin index.  A group of `lpc` lanes
 // covers one cell row with 16-byte loads (64 lanes x 16 B = one 1 KB row per wave
@@ -628,42 +625,6 @@ __global__ __launch_bounds__(kBlock) void k_step1d_tt(const Run1D<T>* __restrict
   step_tile<T, kBlock, 2>(R, tile, step, jloc, eloc, pending != 0, flush != 0);
 }
 
-// Persistent batch: steps [s0, s1) of every run, runs taken longest first from `order`
-// through the counter `*queue` (zero at launch).  Every work-group leaves the loop once
-// the counter passes nruns.
-template <class T>
-__global__ __launch_bounds__(kBatchBlock) void k_batch1d_persistent(
-    const Run1D<T>* __restrict__ runs, const int32_t* __restrict__ order, int nruns,
-    int32_t* queue, int64_t s0, int64_t s1) {
-  __shared__ T jloc[kBatchBlock];
-  __shared__ T eloc[kBatchBlock];
-  __shared__ int32_t next;
-  for (;;) {
-    if (threadIdx.x == 0) next = atomicAdd(queue, 1);
-    __syncthreads();
-    const int qi = next;
-    __syncthreads();
-    if (qi >= nruns) break;
-    const Run1D<T>& R = runs[order[qi]];
-    const int64_t end = s1 < R.step_limit ? s1 : R.step_limit;
-    const int nchunk = (R.nx + kBatchBlock) / kBatchBlock;
-    for (int64_t s = s0; s < end; ++s) {
-      for (int c = 0; c < nchunk; ++c) {
-        Tile1D tile;
-        tile.run = 0;
-        tile.node0 = c * kBatchBlock;
-        tile.node1 = min(R.nx + 1, tile.node0 + kBatchBlock);
-        tile.cell0 = R.chunk_cell[c];
-        tile.cell1 = R.chunk_cell[c + 1];
-        // the barrier at the end of each chunk also orders this step's global stores
-        // before the next step's loads: the whole run lives on one work-group
-        step_tile<T, kBatchBlock>(R, tile, s, jloc, eloc);
-        __syncthreads();
-      }
-    }
-  }
-}
-
 template <class T>
 hipError_t launch_step1d_tt(const void* runs, const void* tiles, int ntiles, int64_t step,
                             bool pending, bool flush, hipStream_t stream) {
@@ -686,17 +647,6 @@ hipError_t launch_step1d(const void* runs, const void* tiles, int ntiles, int64_
     hipLaunchKernelGGL(k_step1d<T>, dim3(ntiles), dim3(kBlock), 0, stream,
                        static_cast<const Run1D<T>*>(runs), static_cast<const Tile1D*>(tiles),
                        step);
-  return hipGetLastError();
-}
-
-hipError_t launch_batch1d_persistent(const void* runs, const int32_t* order, int nruns,
-                                     int32_t* queue, int64_t s0, int64_t s1, int groups,
-                                     hipStream_t stream) {
-  if (nruns <= 0 || s1 <= s0) return hipSuccess;
-  hipError_t e = hipMemsetAsync(queue, 0, sizeof(int32_t), stream);
-  if (e) return e;
-  hipLaunchKernelGGL(k_batch1d_persistent<float>, dim3(groups), dim3(kBatchBlock), 0, stream,
-                     static_cast<const Run1D<float>*>(runs), order, nruns, queue, s0, s1);
   return hipGetLastError();
 }
 

@@ -187,29 +187,45 @@ __device__ __forceinline__ void tb_coef64(float4 (&dd)[kTbIters][kTbU], float4 (
     }
 }
 
-template <int K, int LPC>
-__global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __restrict__ runs,
-                                                        const Tile1D* __restrict__ tiles,
-                                                        int64_t step, int64_t in_off,
-    int64_t out_off) {
-  __shared__ float Es[2][kTbBlock];
-  __shared__ float Hs[2][kTbBlock];
-  __shared__ float Js[kTbBlock + 1];        // + a spare slot for rows without a valid E
-  __shared__ float tauS[kTbBlock];
-  __shared__ float neS[kTbBlock];
-  __shared__ int locS[kTbBlock];
-  __shared__ float srcS[K];
+// The source sample of step n + 1 as a real call: inside the persistent launch's item
+// loop, an inlined FP64 sin / exp would have its polynomial constants hoisted out of the
+// loop and held in some forty registers for the whole launch.
+__device__ __attribute__((noinline)) float tb_source_sample(const Run1D<float>& R, int64_t n) {
+  return (float)source_wave((double)(n + 1) * R.dt, R.src_amp, R.src_w, R.src_tau, R.src_t0);
+}
 
-  const Tile1D tile = tiles[blockIdx.x];
-  const Run1D<float>& R = runs[tile.run];
-  // source samples of the K sub-steps, evaluated before the F1 rows occupy registers
-  if ((int)threadIdx.x < K)
-    srcS[threadIdx.x] = (float)source_wave((double)(step + threadIdx.x + 1) * R.dt, R.src_amp,
-                                           R.src_w, R.src_tau, R.src_t0);
+// On-chip state of one tile (LDS).
+template <int K> struct TbLds {
+  float Es[2][kTbBlock];
+  float Hs[2][kTbBlock];
+  float Js[kTbBlock + 1];        // + a spare slot for rows without a valid E
+  float tauS[kTbBlock];
+  float neS[kTbBlock];
+  int locS[kTbBlock];
+  float srcS[K];
+};
+
+// ns (odd, at most K) steps [step, step + ns) of one tile of run R by the whole work-group:
+// the fields and rows of the extended range (halo of K nodes per side) are read, the owned
+// nodes' fields go to field buffer (step & 1) ^ 1 and their rows from copy in_off to copy
+// out_off.  k is the thread's index in the work-group.  The caller orders LDS use between
+// tiles (a barrier before the next tile).
+template <int K, int LPC>
+__device__ __forceinline__ void tb_tile(const Run1D<float>& R, const Tile1D& tile, int64_t step,
+                                        int ns, int64_t in_off, int64_t out_off,
+                                        TbLds<K>& L, const int k) {
+  auto& Es = L.Es;
+  auto& Hs = L.Hs;
+  auto& Js = L.Js;
+  auto& tauS = L.tauS;
+  auto& neS = L.neS;
+  auto& locS = L.locS;
+  auto& srcS = L.srcS;
+  // source samples of the ns sub-steps, evaluated before the F1 rows occupy registers
+  if (k < ns) srcS[k] = tb_source_sample(R, step + k);
   const int nx = R.nx;
   const int x0 = tile.node0 - K > 0 ? tile.node0 - K : 0;
   const int x1 = tile.node1 + K < nx + 1 ? tile.node1 + K : nx + 1;
-  const int k = threadIdx.x;
   const int i = x0 + k;
   const int par = (int)(step & 1);
   const int ncell = tile.cell1 - tile.cell0;   // plasma nodes of the extended range
@@ -273,7 +289,7 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
       f[it][u] = cl < ncell ? dfr[(size_t)(tile.cell0 + cl) * lpc + li]
                             : make_float4(0.f, 0.f, 0.f, 0.f);
     }
-  // Crank-Nicolson coefficients of every row slot, the same for all K steps.  With one
+  // Crank-Nicolson coefficients of every row slot, the same for all sub-steps.  With one
   // row per wavefront: F1' = (F1 + d F1) + c' E, d = -2x / (2 + x), c' = (b / (2 + x)) n
   // (the row's density folded in), both kept; both FMAs update F1 in place.  With shorter rows the per-lane row scalars
   // leave room for one coefficient only (the two would need 141 VGPRs: one work-group
@@ -304,7 +320,7 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
   const int bc = R.bc, src_node = R.src_node, nprobe = R.nprobe, ntap = R.ntap;
   const float mq = R.q;
 #pragma unroll 1
-  for (int s = 0; s < K; ++s) {
+  for (int s = 0; s < ns; ++s) {
     const int p = s & 1;
     const int64_t gs = step + s;
     __syncthreads();
@@ -367,20 +383,20 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
               nprobe, ntap, gs);
     // the next sub-step's E-independent half runs while wavefront 0 updates the fields
     if constexpr (LPC == 64)
-      if (s + 1 < K) tb_drive64(f, dd);
+      if (s + 1 < ns) tb_drive64(f, dd);
     lo = nlo;
     hi = nhi;
   }
   __syncthreads();
 
   // owned nodes and their F1 rows back to HBM (the other field buffer)
-  constexpr int pf = K & 1;
+  const int pf = ns & 1;
   if (i >= tile.node0 && i < tile.node1) {
     R.E[par ^ 1][i] = Es[pf][k];
     if (i < nx) R.H[par ^ 1][i] = Hs[pf][k];
     R.J[i] = Js[k];
   }
-  // the row addresses are formed again here rather than kept live across the K steps
+  // the row addresses are formed again here rather than kept live across the sub-steps
   asm volatile("" ::: "memory");
   float4* __restrict__ dfw = reinterpret_cast<float4*>(R.df + out_off);
 #pragma unroll
@@ -395,6 +411,200 @@ __global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __re
           dfw[(size_t)(tile.cell0 + cl) * lpc + li] = f[it][u];
       }
     }
+}
+
+template <int K, int LPC>
+__global__ __launch_bounds__(kTbBlock) void k_step1d_tb(const Run1D<float>* __restrict__ runs,
+                                                        const Tile1D* __restrict__ tiles,
+                                                        int64_t step, int64_t in_off,
+                                                        int64_t out_off) {
+  __shared__ TbLds<K> L;
+  const Tile1D tile = tiles[blockIdx.x];
+  tb_tile<K, LPC>(runs[tile.run], tile, step, K, in_off, out_off, L, (int)threadIdx.x);
+}
+
+// --- persistent batch launch -------------------------------------------------------
+// One launch takes every run of a batch through steps [s0, s1) (each run to its own step
+// limit).  Work items are (tile, block) pairs: block b of a tile takes its run through
+// K steps, and at the run's end through the rest of its steps, as one block if the rest
+// is odd, else as rest - 1 steps and then 1 (a block must be odd: it reads field buffer
+// step & 1 and writes the other).  Items are numbered round by round -- block b of every
+// tile that has one, then block b + 1 -- with the runs of the most blocks first, so the
+// tiles of round b are a prefix of the tile array, and rounds with the same number of
+// active tiles form a segment (at most one per run).  Work-groups take items in order
+// from a counter.  Block b of a tile may start once the tile and its neighbours in the
+// same run have finished block b - 1: their outputs are its inputs, and they no longer
+// read the field buffer and row copy it writes.  A work-group makes every store of a
+// block visible device-wide before it records the block in `done`.  Items are handed out
+// in order, so the lowest unfinished item waits on none: the launch drains whatever the
+// number of work-groups resident.  A wait longer than kQueueSpinLimit polls gives up: it
+// sets bit 2 of the run's status (the batch's results are then void) and moves the
+// counter past the last item, so that every work-group leaves after at most its current
+// and prefetched items, rather than hang.
+struct TbQueue {
+  const TbQueueTile* tiles;     // [ntiles] runs with the most blocks first, each in node order
+  const int64_t* seg_start;     // [nseg + 1] first item of each segment; [nseg] = all items
+  const int32_t* seg_round;     // [nseg] first round of each segment
+  const int32_t* seg_tiles;     // [nseg] tiles per round in each segment
+  int32_t* done;                // [ntiles] blocks finished per tile (0 at launch)
+  unsigned long long* counter;  // next item (0 at launch)
+  int64_t s0, s1;               // steps of the launch
+  int64_t delta;                // FP32 elements from a run's rows to their second copy
+  int32_t nseg;
+};
+
+constexpr int kQueueSpinLimit = 1 << 18;
+constexpr int kQueueSegLds = 256;   // segment tables up to this size are read from LDS
+
+template <int K>
+__global__ __launch_bounds__(kTbBlock, 4) void k_batch1d_queue(const Run1D<float>* __restrict__ runs,
+                                                            TbQueue Q) {
+  __shared__ TbLds<K> L;
+  __shared__ int32_t item_t, item_b, item_ns;
+  __shared__ int64_t item_step;
+  __shared__ int64_t sg_start[kQueueSegLds + 1];
+  __shared__ int32_t sg_round[kQueueSegLds], sg_tiles[kQueueSegLds];
+  const bool sg_lds = Q.nseg <= kQueueSegLds;
+  if (sg_lds) {
+    for (int i = threadIdx.x; i <= Q.nseg; i += kTbBlock) {
+      sg_start[i] = Q.seg_start[i];
+      if (i < Q.nseg) {
+        sg_round[i] = Q.seg_round[i];
+        sg_tiles[i] = Q.seg_tiles[i];
+      }
+    }
+  }
+  __syncthreads();
+  const int64_t total = Q.seg_start[Q.nseg];
+  unsigned long long next = 0;   // thread 0: the item after the current one, fetched ahead
+  int seg = 0;                   // thread 0: segment of the current item (items only grow)
+  if (threadIdx.x == 0) next = atomicAdd(Q.counter, 1ull);
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const int64_t qi = (int64_t)next;
+      int b = -1, t = 0, ns = 0;
+      int64_t st = 0;
+      if (qi < total) {
+        next = atomicAdd(Q.counter, 1ull);
+        if (sg_lds) {
+          while (sg_start[seg + 1] <= qi) ++seg;
+        } else {
+          while (Q.seg_start[seg + 1] <= qi) ++seg;
+        }
+        const int64_t off = qi - (sg_lds ? sg_start[seg] : Q.seg_start[seg]);
+        const int nt = sg_lds ? sg_tiles[seg] : Q.seg_tiles[seg];
+        const int64_t r = off / nt;
+        b = (sg_lds ? sg_round[seg] : Q.seg_round[seg]) + (int)r;
+        t = (int)(off - r * nt);
+        const TbQueueTile qt = Q.tiles[t];
+        const int64_t q = qt.full, rest = qt.rest;
+        if (b < q) {
+          st = Q.s0 + (int64_t)b * K;
+          ns = K;
+        } else if (rest & 1) {
+          st = Q.s0 + q * K;
+          ns = (int)rest;
+        } else if (b == q) {
+          st = Q.s0 + q * K;
+          ns = (int)rest - 1;
+        } else {
+          st = Q.s0 + q * K + rest - 1;
+          ns = 1;
+        }
+        const bool left = qt.tile.node0 > 0, right = (qt.flags & 1) != 0;
+        for (int spin = 0;; ++spin) {
+          bool ok = __hip_atomic_load(Q.done + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= b;
+          if (left)
+            ok = ok && __hip_atomic_load(Q.done + t - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= b;
+          if (right)
+            ok = ok && __hip_atomic_load(Q.done + t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= b;
+          if (ok) break;
+          if (spin == kQueueSpinLimit) {
+            __hip_atomic_fetch_or(gptr(runs[qt.tile.run].status), 4, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+            atomicMax(Q.counter, 1ull << 62);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+        // one acquire for the work-group: the barrier below orders every thread's loads
+        // after it (the waves share this compute unit's caches)
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
+      item_t = t;
+      item_b = b;
+      item_ns = ns;
+      item_step = st;
+    }
+    __syncthreads();
+    const int b = __builtin_amdgcn_readfirstlane(item_b);
+    if (b < 0) break;
+    const int t = __builtin_amdgcn_readfirstlane(item_t);
+    const int ns = __builtin_amdgcn_readfirstlane(item_ns);
+    const int64_t st = item_step;
+    const Tile1D tile = Q.tiles[t].tile;
+    const Run1D<float>& R = runs[tile.run];
+    // every run starts the launch with its rows in the first copy: block b reads copy b & 1
+    const int64_t in_off = (b & 1) ? Q.delta : 0, out_off = (b & 1) ? 0 : Q.delta;
+    // the thread index passed through an empty asm, so that nothing derived from it is
+    // hoisted out of the item loop and held in registers across it
+    int k = threadIdx.x;
+    asm volatile("" : "+v"(k));
+    switch (R.half) {
+      case 32: tb_tile<K, 8>(R, tile, st, ns, in_off, out_off, L, k); break;
+      case 64: tb_tile<K, 16>(R, tile, st, ns, in_off, out_off, L, k); break;
+      case 128: tb_tile<K, 32>(R, tile, st, ns, in_off, out_off, L, k); break;
+      default: tb_tile<K, 64>(R, tile, st, ns, in_off, out_off, L, k); break;
+    }
+    // every wave waits for its own stores to complete (vmcnt 0: written to L2), then one
+    // release by thread 0 writes them back device-wide before the block is recorded
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+    if (threadIdx.x == 0)
+      __hip_atomic_store(Q.done + t, b + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <int K>
+int queue_occupancy() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch1d_queue<K>, kTbBlock, 0) != hipSuccess)
+    return 1;
+  return n > 0 ? n : 1;
+}
+
+int tb_queue_blocks_per_cu(int k) {
+  switch (k) {
+    case 3: return queue_occupancy<3>();
+    case 5: return queue_occupancy<5>();
+    case 7: return queue_occupancy<7>();
+    default: return queue_occupancy<9>();
+  }
+}
+
+hipError_t launch_batch1d_queue(const void* runs, const TbQueueArgs& a, int groups,
+                                hipStream_t stream) {
+  if (a.nseg <= 0 || groups <= 0) return hipSuccess;
+  TbQueue q;
+  q.tiles = a.tiles;
+  q.seg_start = a.seg_start;
+  q.seg_round = a.seg_round;
+  q.seg_tiles = a.seg_tiles;
+  q.done = a.done;
+  q.counter = a.counter;
+  q.s0 = a.s0;
+  q.s1 = a.s1;
+  q.delta = a.delta;
+  q.nseg = a.nseg;
+  const Run1D<float>* r = static_cast<const Run1D<float>*>(runs);
+  switch (a.k) {
+    case 3: hipLaunchKernelGGL(k_batch1d_queue<3>, dim3(groups), dim3(kTbBlock), 0, stream, r, q); break;
+    case 5: hipLaunchKernelGGL(k_batch1d_queue<5>, dim3(groups), dim3(kTbBlock), 0, stream, r, q); break;
+    case 7: hipLaunchKernelGGL(k_batch1d_queue<7>, dim3(groups), dim3(kTbBlock), 0, stream, r, q); break;
+    case 9: hipLaunchKernelGGL(k_batch1d_queue<9>, dim3(groups), dim3(kTbBlock), 0, stream, r, q); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 bool tb_supported(int half) { return half == 32 || half == 64 || half == 128 || half == 256; }

@@ -1,7 +1,7 @@
-"""GPU tests of the batched 1D path: many independent runs of uneven size in one
-persistent launch (work-groups pull whole runs longest-first from a queue), the per-step
-alternative, the training-pair taps, per-run status, and parity with solo runs and with
-the FP64 oracle."""
+"""GPU tests of the batched 1D path: many independent runs of uneven size, in K-step
+blocked launches (the default) or in one persistent launch (work-groups take (tile, block)
+items from a counter, each waiting for its neighbours' previous block), the training-pair
+taps, per-run status, and parity with solo runs and with the FP64 oracle."""
 import math
 
 import numpy as np
@@ -47,7 +47,8 @@ FIELDS = (B.F_E, B.F_H, B.F_J, B.F_DF)
 @pytest.mark.parametrize("mode,groups", [(0, 0), (0, 3), (1, 0)])
 def test_batch_equals_solo_bitwise(gpu_lib, mode, groups):
     """Run r of a batch ends bitwise equal to run r simulated alone, whatever the launch
-    form (persistent queue with one or fewer work-groups per run, or one launch per step)."""
+    form (the persistent launch with every work-group that fits or with only three, or
+    K-step blocked launches)."""
     runs = small_batch()
     _banner(f"batch == solo, mode={mode} groups={groups}")
     bat = B.Sim(runs, batch_mode=mode, groups=groups)
@@ -71,6 +72,30 @@ def test_batch_in_chunks_equals_one_call(gpu_lib):
     for r in range(len(runs)):
         for f in FIELDS:
             assert np.array_equal(a.read(f, run=r), b.read(f, run=r))
+
+
+def test_persistent_batch_in_chunks_equals_default(gpu_lib):
+    """The persistent launch over calls of uneven length (1, 7, 250, ... steps: calls that
+    end inside runs' K-step blocks, odd and even rests, runs that finish early) ends
+    bitwise where the default launch form ends in one call, also with K = 5."""
+    runs = small_batch(7, seed=17)
+    total = max(r.steps for r in runs)
+    for kb in (9, 5):
+        _banner(f"persistent batch in chunks, K={kb}")
+        a = B.Sim(runs, time_block=kb)
+        a.run(total)
+        b = B.Sim(runs, batch_mode=0, time_block=kb)
+        done = 0
+        for k in (1, 7, 250, 2, 999, 4000):
+            b.run(k)
+            done += k
+        assert done >= total
+        for r in range(len(runs)):
+            assert b.run_status(r) == B.OK
+            for f in FIELDS:
+                assert np.array_equal(a.read(f, run=r), b.read(f, run=r)), (kb, r, f)
+        a.close()
+        b.close()
 
 
 def test_batch_parity_with_oracle(gpu_lib):
