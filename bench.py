@@ -367,7 +367,8 @@ def extra_c2(B, W, torch, autotune, steps=None):
 def extra_c3(B, W, torch, reps=3, autotune=None, limit=None):
     """Batch of 256 uneven 1D runs, advanced to the last run's end in its default launch
     form (blocked launches per Nv group), with the steps per launch the autotuner stored
-    for this batch (the library default if none).  `limit` stops after that many steps
+    for this batch (the library default if none), and then in one persistent launch
+    (batch mode 0) for comparison.  `limit` stops after that many steps
     instead, with a progress line every 1000 steps (for counter collection, which
     serialises every dispatch)."""
     runs = W.c3()
@@ -398,9 +399,21 @@ def extra_c3(B, W, torch, reps=3, autotune=None, limit=None):
         walls.append(time.perf_counter() - t0)
         sim.close()
     wall = statistics.median(walls)
+    # the same batch in one persistent launch (batch mode 0), for comparison
+    pwalls = []
+    for _ in range(2):
+        sim = B.Sim(runs, time_block=kb or None, batch_mode=0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.run(tot)
+        torch.cuda.synchronize()
+        pwalls.append(time.perf_counter() - t0)
+        sim.close()
     out = dict(workload="256 independent 1D runs, Nx in [500, 20000], Nv in {64,128,256}, "
                         "2 Nx steps each",
                updates_per_s=work / wall, seconds=wall, seconds_reps=walls,
+               launch_form="K-step blocked launches per Nv group (batch mode 1)",
+               persistent_launch_seconds=min(pwalls),
                steps_per_launch=k_used,
                one_step_stream_equivalent_gbs=stream_by / wall / 1e9,
                one_step_stream_equivalent_frac=stream_by / wall / 1e9 / HBM_PEAK_GBS)
