@@ -167,6 +167,9 @@ int default_tile_1d(int half, int elem, int nx, int ncell) {
 // Owned nodes per blocked tile in a batch (capped by what the extended range allows):
 // the wider the tile, the less halo work per owned node.
 constexpr int kTbBatchWidth = 512;
+// F1 rows beyond this many bytes do not stay in the 256 MB Infinity Cache from one step to
+// the next: one-step launches then stream them with nontemporal loads and stores
+constexpr size_t kStreamRowBytes = size_t(192) << 20;
 
 // Blocked tiles of one Nv: [off, off + limit.size()) of the blocked tile list, with the
 // step limit of each tile's run (non-increasing).
@@ -196,6 +199,8 @@ struct fdtd_plasma {
   size_t runs_off = 0, tiles_off = 0;
   int ntiles = 0;
   std::vector<int64_t> tile_limit;   // step limit of each tile, non-increasing
+  int one_cpl = 0;          // one-step launches: chunks per lane of every run (0: mixed)
+  bool one_stream = false;  // one-step launches: rows streamed past the Infinity Cache
   size_t status_off = 0;
   int batch_mode = 1, batch_groups = 0, ntap = 0;   // batch default: K-step launches
   size_t qtiles_off = 0, qdone_off = 0, qstart_off = 0, qround_off = 0, qsegt_off = 0,
@@ -560,6 +565,20 @@ int build_tb_tiles(fdtd_plasma* h) {
 }
 
 int build_tiles_1d(fdtd_plasma* h) {
+  // the one-step launches' form: 16-byte chunks per lane shared by every run (0 if they
+  // differ), and whether the rows are streamed (more than the Infinity Cache keeps)
+  {
+    const int es = elem_size(h->precision), vpl = 16 / es;
+    size_t rows_bytes = 0;
+    h->one_cpl = -1;
+    for (const Host1D& x : h->h1) {
+      const int ch = x.half / vpl, cpl = ch < 64 ? 1 : ch / 64;
+      h->one_cpl = h->one_cpl < 0 || h->one_cpl == cpl ? cpl : 0;
+      rows_bytes += (size_t)x.ncell * x.row * es;
+    }
+    if (h->one_cpl < 0) h->one_cpl = 0;
+    h->one_stream = rows_bytes > kStreamRowBytes;
+  }
   std::vector<std::pair<int64_t, Tile1D>> all;
   for (int r = 0; r < h->nruns; ++r) {
     const Host1D& x = h->h1[r];
@@ -1037,7 +1056,8 @@ int fdtd_plasma_run(fdtd_plasma* h, int64_t nsteps) {
         const int p1 = count_ge(h->tile_limit, s + kb), p2 = count_ge(h->tile_limit, s + 1);
         for (int64_t ss = s; p2 > p1 && ss < s + kb; ++ss) {
           const int n = count_ge(h->tile_limit, ss + 1) - p1;
-          e = launch_step1d<float>(h->ws + h->runs_off, rt + p1, n, ss, h->stream, false);
+          e = launch_step1d<float>(h->ws + h->runs_off, rt + p1, n, ss, h->stream, false,
+                                   h->one_cpl, h->one_stream);
           if (e) return hip_fail(e, "launch step kernel");
         }
       }
@@ -1068,8 +1088,10 @@ int fdtd_plasma_run(fdtd_plasma* h, int64_t nsteps) {
       } else {
         const bool full = model == FDTD_KINETIC_FULL;
         e = h->precision == FDTD_FP64
-                ? launch_step1d<double>(h->ws + h->runs_off, h->ws + h->tiles_off, n, s, h->stream, full)
-                : launch_step1d<float>(h->ws + h->runs_off, h->ws + h->tiles_off, n, s, h->stream, full);
+                ? launch_step1d<double>(h->ws + h->runs_off, h->ws + h->tiles_off, n, s, h->stream, full,
+                                        h->one_cpl, h->one_stream)
+                : launch_step1d<float>(h->ws + h->runs_off, h->ws + h->tiles_off, n, s, h->stream, full,
+                                       h->one_cpl, h->one_stream);
       }
     } else if (h->dims == 3) {
       e = launch_step3d(h->h3, s, h->stream);

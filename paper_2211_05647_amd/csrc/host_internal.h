@@ -66,9 +66,11 @@ struct Host1D {
 };
 
 // 1D launch (kernels1d.hip)
+// cpl: 16-byte chunks per lane of every run in the launch (1, 2, 4; 0 = mixed or unknown),
+// streaming: the launch's rows exceed what the Infinity Cache keeps between steps.
 template <class T>
 hipError_t launch_step1d(const void* runs, const void* tiles, int ntiles, int64_t step,
-                         hipStream_t stream, bool full);
+                         hipStream_t stream, bool full, int cpl = 0, bool streaming = false);
 
 template <class T>
 hipError_t launch_step1d_tt(const void* runs, const void* tiles, int ntiles, int64_t step,

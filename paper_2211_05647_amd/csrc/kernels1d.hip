@@ -26,7 +26,28 @@
 
 namespace fdtdp {
 
-template <class T, int U, int NT>
+// F1 row chunks in and out: plain loads and stores, or (S, for launches whose rows do not
+// fit in the Infinity Cache and are streamed through once per step) nontemporal ones that
+// do not displace cached data.
+template <bool S, class V> __device__ __forceinline__ V row_load(const V* p) {
+  if constexpr (S) {
+    typedef int i4 __attribute__((ext_vector_type(4)));
+    const i4 x = __builtin_nontemporal_load(reinterpret_cast<const i4*>(p));
+    return __builtin_bit_cast(V, x);
+  } else {
+    return *p;
+  }
+}
+template <bool S, class V> __device__ __forceinline__ void row_store(const V& v, V* p) {
+  if constexpr (S) {
+    typedef int i4 __attribute__((ext_vector_type(4)));
+    __builtin_nontemporal_store(__builtin_bit_cast(i4, v), reinterpret_cast<i4*>(p));
+  } else {
+    *p = v;
+  }
+}
+
+template <class T, int U, int NT, bool S = false>
 __device__ __forceinline__ void kinetic_tile(const Run1D<T>& R, const T* eloc,
                                              const Tile1D& tile, T* jloc) {
   using V = typename Vec<T>::type;
@@ -70,7 +91,7 @@ __device__ __forceinline__ void kinetic_tile(const Run1D<T>& R, const T* eloc,
         const V* row = dfv + (size_t)c * ch;
 #pragma unroll
         for (int m = 0; m < CPL; ++m)
-          if (m < cpl) f[u][m] = row[li + m * lpc];
+          if (m < cpl) f[u][m] = row_load<S>(&row[li + m * lpc]);
       }
     }
     double acc[U];
@@ -119,7 +140,7 @@ __device__ __forceinline__ void kinetic_tile(const Run1D<T>& R, const T* eloc,
         V* row = dfv + (size_t)c * ch;
 #pragma unroll
         for (int m = 0; m < CPL; ++m)
-          if (m < cpl) row[li + m * lpc] = f[u][m];
+          if (m < cpl) row_store<S>(f[u][m], &row[li + m * lpc]);
       }
     }
     if (U > 1 && lpc < U) {
@@ -483,7 +504,10 @@ __device__ __forceinline__ void kinetic_tile_tt(const Run1D<T>& R, const T* eloc
 
 // One step of one tile by a work-group of NT threads (tile.node1 - tile.node0 <= NT).
 // jloc / eloc: LDS arrays of NT values.  The caller synchronises before reusing them.
-template <class T, int NT, int KIND = 0>
+// C (linear model): 0 = any row length (chosen per run at run time), else the 16-byte
+// chunks per lane of every run of the launch (1, 2 or 4), so that only that form is
+// compiled and the launch keeps the registers of that form alone; STREAM: streamed rows.
+template <class T, int NT, int KIND = 0, int C = 0, bool STREAM = false>
 __device__ __forceinline__ void step_tile(const Run1D<T>& R, const Tile1D& tile, int64_t step,
                                           T* jloc, T* eloc, bool pending = false,
                                           bool flush = false) {
@@ -525,6 +549,12 @@ __device__ __forceinline__ void step_tile(const Run1D<T>& R, const Tile1D& tile,
       const T* eprev = En + tile.node0;
       if (cpl == 1) kinetic_tile_tt<T, 1, NT>(R, eloc, eprev, tile, jloc, pending, flush);
       else kinetic_tile_tt<T, 2, NT>(R, eloc, eprev, tile, jloc, pending, flush);
+    } else if constexpr (C == 1) {
+      kinetic_tile<T, 4, NT, STREAM>(R, eloc, tile, jloc);
+    } else if constexpr (C == 2) {
+      kinetic_tile<T, 2, NT, STREAM>(R, eloc, tile, jloc);
+    } else if constexpr (C == 4) {
+      kinetic_tile<T, 1, NT, STREAM>(R, eloc, tile, jloc);
     } else if (cpl == 1) kinetic_tile<T, 4, NT>(R, eloc, tile, jloc);
     else if (cpl == 2) kinetic_tile<T, 2, NT>(R, eloc, tile, jloc);
     else kinetic_tile<T, 1, NT>(R, eloc, tile, jloc);
@@ -585,7 +615,7 @@ __device__ __forceinline__ void step_tile(const Run1D<T>& R, const Tile1D& tile,
   }
 }
 
-template <class T>
+template <class T, int C, bool S>
 __global__ __launch_bounds__(kBlock) void k_step1d(const Run1D<T>* __restrict__ runs,
                                                    const Tile1D* __restrict__ tiles,
                                                    int64_t step) {
@@ -594,7 +624,7 @@ __global__ __launch_bounds__(kBlock) void k_step1d(const Run1D<T>* __restrict__ 
   const Tile1D tile = tiles[blockIdx.x];
   const Run1D<T>& R = runs[tile.run];
   if (step >= R.step_limit) return;
-  step_tile<T, kBlock>(R, tile, step, jloc, eloc);
+  step_tile<T, kBlock, 0, C, S>(R, tile, step, jloc, eloc);
 }
 
 // The same step for runs of the full-distribution model (a kernel of its own, so the
@@ -635,25 +665,38 @@ hipError_t launch_step1d_tt(const void* runs, const void* tiles, int ntiles, int
   return hipGetLastError();
 }
 
+template <class T, int C, bool S>
+void launch_k1(const void* runs, const void* tiles, int ntiles, int64_t step, hipStream_t stream) {
+  hipLaunchKernelGGL((k_step1d<T, C, S>), dim3(ntiles), dim3(kBlock), 0, stream,
+                     static_cast<const Run1D<T>*>(runs), static_cast<const Tile1D*>(tiles), step);
+}
+
 template <class T>
 hipError_t launch_step1d(const void* runs, const void* tiles, int ntiles, int64_t step,
-                         hipStream_t stream, bool full) {
+                         hipStream_t stream, bool full, int cpl, bool streaming) {
   if (ntiles <= 0) return hipSuccess;
-  if (full)
+  if (full) {
     hipLaunchKernelGGL(k_step1d_full<T>, dim3(ntiles), dim3(kBlock), 0, stream,
                        static_cast<const Run1D<T>*>(runs), static_cast<const Tile1D*>(tiles),
                        step);
-  else
-    hipLaunchKernelGGL(k_step1d<T>, dim3(ntiles), dim3(kBlock), 0, stream,
-                       static_cast<const Run1D<T>*>(runs), static_cast<const Tile1D*>(tiles),
-                       step);
+  } else {
+    switch (cpl) {
+      case 1: streaming ? launch_k1<T, 1, true>(runs, tiles, ntiles, step, stream)
+                        : launch_k1<T, 1, false>(runs, tiles, ntiles, step, stream); break;
+      case 2: streaming ? launch_k1<T, 2, true>(runs, tiles, ntiles, step, stream)
+                        : launch_k1<T, 2, false>(runs, tiles, ntiles, step, stream); break;
+      case 4: streaming ? launch_k1<T, 4, true>(runs, tiles, ntiles, step, stream)
+                        : launch_k1<T, 4, false>(runs, tiles, ntiles, step, stream); break;
+      default: launch_k1<T, 0, false>(runs, tiles, ntiles, step, stream); break;
+    }
+  }
   return hipGetLastError();
 }
 
 template hipError_t launch_step1d<float>(const void*, const void*, int, int64_t, hipStream_t,
-                                         bool);
+                                         bool, int, bool);
 template hipError_t launch_step1d<double>(const void*, const void*, int, int64_t, hipStream_t,
-                                          bool);
+                                          bool, int, bool);
 template hipError_t launch_step1d_tt<float>(const void*, const void*, int, int64_t, bool, bool,
                                             hipStream_t);
 template hipError_t launch_step1d_tt<double>(const void*, const void*, int, int64_t, bool, bool,
