@@ -254,7 +254,7 @@ def extra_c1l(B, W, torch, autotune):
     # one step per launch on the same line: the streaming kernel beyond the Infinity Cache
     ms1, _, _ = time_steps(run, B, torch, 300, 20, reps=3, tile=tile, time_block=1)
     gbs, frac = hbm(bytes_1d(run), ms1)
-    out["one_step_per_launch"] = dict(kernel="k_step1d<float>", ms_per_step=ms1,
+    out["one_step_per_launch"] = dict(kernel="k_step1d<float, 1, true>", ms_per_step=ms1,
                                       bytes_per_launch=bytes_1d(run), hbm_gbs=gbs, hbm_frac=frac)
     return {"c1_nx2e20": out}
 
@@ -345,7 +345,7 @@ def extra_fp64(B, W, torch, steps=None):
     by = bytes_1d(run, 8)
     gbs, frac = hbm(by, ms)
     return {"c1_fp64": dict(workload=f"1D Yee + 1V kinetic, Nx=65536, Nv=512, FP64, {steps} steps",
-                            kernel="k_step1d<double>",
+                            kernel="k_step1d<double, 2, false>",
                             updates_per_s=run.plasma_cells * run.nv / (ms * 1e-3),
                             ms_per_step=ms, wall_ms_per_step=wall / steps * 1e3,
                             bytes_per_launch=by, hbm_gbs=gbs, hbm_frac=frac)}
@@ -931,7 +931,7 @@ def main():
                 "frac_of_fp32_single_issue": tflops / FP32_SINGLE_ISSUE_TFLOPS,
                 "one_step_stream_equivalent_gbs": bytes_1d(run) * kb / (launch_ms * 1e-3) / 1e9}
     else:
-        kernel = "k_step1d<float>"
+        kernel = "k_step1d<float, 1, false>"
         by = bytes_1d(run)
         launch_ms = wall / args.steps * 1e3
         achieved, frac = hbm(by, launch_ms)
