@@ -263,6 +263,27 @@ __device__ __forceinline__ T prev_lane_of_row(T v, int lpc) {
   }
 }
 
+// F1 row chunks in and out: plain loads and stores, or (S, for launches whose rows do not
+// fit in the Infinity Cache and are streamed through once per step) nontemporal ones that
+// do not displace cached data.
+template <bool S, class V> __device__ __forceinline__ V row_load(const V* p) {
+  if constexpr (S) {
+    typedef int i4 __attribute__((ext_vector_type(4)));
+    const i4 x = __builtin_nontemporal_load(reinterpret_cast<const i4*>(p));
+    return __builtin_bit_cast(V, x);
+  } else {
+    return *p;
+  }
+}
+template <bool S, class V> __device__ __forceinline__ void row_store(const V& v, V* p) {
+  if constexpr (S) {
+    typedef int i4 __attribute__((ext_vector_type(4)));
+    __builtin_nontemporal_store(__builtin_bit_cast(i4, v), reinterpret_cast<i4*>(p));
+  } else {
+    *p = v;
+  }
+}
+
 struct Tile1D {
   int32_t run, node0, node1, cell0, cell1;
 };

@@ -249,7 +249,7 @@ void set_grid(Host2D* h) {
 
 template <class T>
 hipError_t launch_step2d_t(const void* run, int half, int nbk, int nbh, int nbe, int64_t step,
-                           hipStream_t stream);
+                           hipStream_t stream, bool streaming);
 hipError_t launch_step2d_closure(const void* run, int half, int nbk, int nx, int ny, int nbe,
                                  int64_t step, hipStream_t stream, const MlpWeights& W,
                                  const MlpCells2D& C);
@@ -408,11 +408,14 @@ int upload_2d(Host2D* h, char* ws, hipStream_t stream, const std::vector<ProbeIn
 
 hipError_t launch_step2d(Host2D* h, int64_t step, hipStream_t stream) {
   const void* run = h->ws + h->off_run;
-  if (h->es == 8) return launch_step2d_t<double>(run, h->half, h->nbk, h->nbh, h->nbe, step, stream);
+  if (h->es == 8)
+    return launch_step2d_t<double>(run, h->half, h->nbk, h->nbh, h->nbe, step, stream, false);
   if (h->C.n > 0)
     return launch_step2d_closure(run, h->half, h->nbk, h->nx, h->ny, h->nbe, step, stream, h->W,
                                  h->C);
-  return launch_step2d_t<float>(run, h->half, h->nbk, h->nbh, h->nbe, step, stream);
+  // rows beyond what the 256 MB Infinity Cache keeps between steps are streamed
+  const bool streaming = (size_t)h->ncell * h->half * h->es > (size_t(192) << 20);
+  return launch_step2d_t<float>(run, h->half, h->nbk, h->nbh, h->nbe, step, stream, streaming);
 }
 
 int closure_counts_2d(const Host2D* h, int64_t* nm, int64_t* nk) {

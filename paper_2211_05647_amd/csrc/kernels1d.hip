@@ -26,27 +26,6 @@
 
 namespace fdtdp {
 
-// F1 row chunks in and out: plain loads and stores, or (S, for launches whose rows do not
-// fit in the Infinity Cache and are streamed through once per step) nontemporal ones that
-// do not displace cached data.
-template <bool S, class V> __device__ __forceinline__ V row_load(const V* p) {
-  if constexpr (S) {
-    typedef int i4 __attribute__((ext_vector_type(4)));
-    const i4 x = __builtin_nontemporal_load(reinterpret_cast<const i4*>(p));
-    return __builtin_bit_cast(V, x);
-  } else {
-    return *p;
-  }
-}
-template <bool S, class V> __device__ __forceinline__ void row_store(const V& v, V* p) {
-  if constexpr (S) {
-    typedef int i4 __attribute__((ext_vector_type(4)));
-    __builtin_nontemporal_store(__builtin_bit_cast(i4, v), reinterpret_cast<i4*>(p));
-  } else {
-    *p = v;
-  }
-}
-
 template <class T, int U, int NT, bool S = false>
 __device__ __forceinline__ void kinetic_tile(const Run1D<T>& R, const T* eloc,
                                              const Tile1D& tile, T* jloc) {

@@ -145,7 +145,7 @@ struct Kin2vCell {
   float nex, ney, tau;
 };
 
-template <int NV, int C>
+template <int NV, int C, bool S>
 __device__ __forceinline__ void kin2v_load(const Run2D<float>& R, int c, bool ok, int li,
                                            float4 (&f)[C], Kin2vCell& q) {
   constexpr int CH = NV * NV / 8, L = CH / C;
@@ -160,7 +160,7 @@ __device__ __forceinline__ void kin2v_load(const Run2D<float>& R, int c, bool ok
     q.tau = R.tau[c];
     const float4* row = reinterpret_cast<const float4*>(R.df) + (size_t)c * CH;
 #pragma unroll
-    for (int m = 0; m < C; ++m) f[m] = row[li + L * m];
+    for (int m = 0; m < C; ++m) f[m] = row_load<S>(&row[li + L * m]);
   } else {
     q.k = 0;
     q.nex = q.ney = q.tau = 0.f;
@@ -169,7 +169,9 @@ __device__ __forceinline__ void kin2v_load(const Run2D<float>& R, int c, bool ok
   }
 }
 
-template <int NV, int C, bool PF>
+// S: the rows are streamed (more of them than the Infinity Cache keeps between steps), with
+// nontemporal loads and stores.
+template <int NV, int C, bool PF, bool S>
 __device__ __forceinline__ void kinetic2v_f32(const Run2D<float>& R, int c0, int c1) {
   constexpr int CH = NV * NV / 8;
   constexpr int L = CH / C;
@@ -194,7 +196,7 @@ __device__ __forceinline__ void kinetic2v_f32(const Run2D<float>& R, int c0, int
   int base = c0 + wave * G;
   float4 f[C];
   Kin2vCell q;
-  if (PF) kin2v_load<NV, C>(R, base + g, base + g < c1, li, f, q);
+  if (PF) kin2v_load<NV, C, S>(R, base + g, base + g < c1, li, f, q);
   for (; base < c1; base += kWaves * G) {
     const int c = base + g;
     const bool ok = c < c1;
@@ -202,9 +204,9 @@ __device__ __forceinline__ void kinetic2v_f32(const Run2D<float>& R, int c0, int
     Kin2vCell qn;
     if (PF) {
       const int cn = c + kWaves * G;
-      kin2v_load<NV, C>(R, cn, cn < c1, li, fn_, qn);
+      kin2v_load<NV, C, S>(R, cn, cn < c1, li, fn_, qn);
     } else {
-      kin2v_load<NV, C>(R, c, ok, li, f, q);
+      kin2v_load<NV, C, S>(R, c, ok, li, f, q);
     }
     double ax = 0.0, ay = 0.0;
 #pragma unroll
@@ -224,7 +226,7 @@ __device__ __forceinline__ void kinetic2v_f32(const Run2D<float>& R, int c0, int
     if (ok) {
       float4* row = dfv + (size_t)c * CH;
 #pragma unroll
-      for (int m = 0; m < C; ++m) row[li + L * m] = f[m];
+      for (int m = 0; m < C; ++m) row_store<S>(f[m], &row[li + L * m]);
     }
     // reduce-scatter of (ax, ay) over the L lanes of the group
     const bool hi = (li & (L / 2)) != 0;
@@ -244,14 +246,14 @@ __device__ __forceinline__ void kinetic2v_f32(const Run2D<float>& R, int c0, int
 
 // NV > 0: FP32 with NV bins per velocity axis (the specialised kinetic path); NV = 0: any
 // bin count and precision.
-template <class T, int NV>
+template <class T, int NV, bool S = false>
 __global__ __launch_bounds__(kBlock) void k_h2d_kin(const Run2D<T>* __restrict__ rp, int64_t step) {
   const Run2D<T>& R = *rp;
   if ((int)blockIdx.x < R.nbk) {
     const int c0 = blockIdx.x * R.cells_per_block;
     const int c1 = min(R.ncell, c0 + R.cells_per_block);
     if constexpr (NV > 0) {
-      kinetic2v_f32<NV, kKin2vChunks, kKin2vPrefetch>(R, c0, c1);
+      kinetic2v_f32<NV, kKin2vChunks, kKin2vPrefetch, S>(R, c0, c1);
     } else {
       const int ch = R.half / Vec<T>::n;
       const int cpl = ch < 64 ? 1 : ch / 64;
@@ -283,23 +285,26 @@ __global__ __launch_bounds__(kBlock) void k_e2d(const Run2D<T>* __restrict__ rp,
   else e2d_rows<1>(R, i, strip, step);
 }
 
-// H + kinetic launch, picking the kinetic path by the stored bins per cell
+// H + kinetic launch, picking the kinetic path by the stored bins per cell (and, in FP32,
+// streamed rows when `streaming`)
+template <class T, int NV>
+hipError_t launch_h2d_kin_nv(const Run2D<T>* r, int grid, int64_t step, hipStream_t stream,
+                             bool streaming) {
+  if (streaming)
+    hipLaunchKernelGGL((k_h2d_kin<T, NV, true>), dim3(grid), dim3(kBlock), 0, stream, r, step);
+  else
+    hipLaunchKernelGGL((k_h2d_kin<T, NV, false>), dim3(grid), dim3(kBlock), 0, stream, r, step);
+  return hipGetLastError();
+}
+
 template <class T>
-hipError_t launch_h2d_kin(const Run2D<T>* r, int half, int grid, int64_t step, hipStream_t stream) {
+hipError_t launch_h2d_kin(const Run2D<T>* r, int half, int grid, int64_t step, hipStream_t stream,
+                          bool streaming) {
   if (grid <= 0) return hipSuccess;
   if constexpr (sizeof(T) == 4) {
-    if (half == 32) {
-      hipLaunchKernelGGL((k_h2d_kin<T, 8>), dim3(grid), dim3(kBlock), 0, stream, r, step);
-      return hipGetLastError();
-    }
-    if (half == 128) {
-      hipLaunchKernelGGL((k_h2d_kin<T, 16>), dim3(grid), dim3(kBlock), 0, stream, r, step);
-      return hipGetLastError();
-    }
-    if (half == 512) {
-      hipLaunchKernelGGL((k_h2d_kin<T, 32>), dim3(grid), dim3(kBlock), 0, stream, r, step);
-      return hipGetLastError();
-    }
+    if (half == 32) return launch_h2d_kin_nv<T, 8>(r, grid, step, stream, streaming);
+    if (half == 128) return launch_h2d_kin_nv<T, 16>(r, grid, step, stream, streaming);
+    if (half == 512) return launch_h2d_kin_nv<T, 32>(r, grid, step, stream, streaming);
   }
   hipLaunchKernelGGL((k_h2d_kin<T, 0>), dim3(grid), dim3(kBlock), 0, stream, r, step);
   return hipGetLastError();
@@ -307,9 +312,9 @@ hipError_t launch_h2d_kin(const Run2D<T>* r, int half, int grid, int64_t step, h
 
 template <class T>
 hipError_t launch_step2d_t(const void* run, int half, int nbk, int nbh, int nbe, int64_t step,
-                           hipStream_t stream) {
+                           hipStream_t stream, bool streaming) {
   const Run2D<T>* r = static_cast<const Run2D<T>*>(run);
-  hipError_t e = launch_h2d_kin(r, half, nbk + nbh, step, stream);
+  hipError_t e = launch_h2d_kin(r, half, nbk + nbh, step, stream, streaming);
   if (e) return e;
   hipLaunchKernelGGL(k_e2d<T>, dim3(nbe), dim3(kBlock), 0, stream, r, step);
   return hipGetLastError();
@@ -325,7 +330,7 @@ hipError_t launch_step2d_closure(const void* run, int half, int nbk, int nx, int
                                  int64_t step, hipStream_t stream, const MlpWeights& W,
                                  const MlpCells2D& C) {
   const Run2D<float>* r = static_cast<const Run2D<float>*>(run);
-  hipError_t e = launch_h2d_kin(r, half, nbk, step, stream);
+  hipError_t e = launch_h2d_kin(r, half, nbk, step, stream, false);
   if (e) return e;
   e = mlp_launch_cells2d(run, W, C, nx, ny, step, stream);
   if (e) return e;
@@ -333,7 +338,9 @@ hipError_t launch_step2d_closure(const void* run, int half, int nbk, int nx, int
   return hipGetLastError();
 }
 
-template hipError_t launch_step2d_t<float>(const void*, int, int, int, int, int64_t, hipStream_t);
-template hipError_t launch_step2d_t<double>(const void*, int, int, int, int, int64_t, hipStream_t);
+template hipError_t launch_step2d_t<float>(const void*, int, int, int, int, int64_t, hipStream_t,
+                                           bool);
+template hipError_t launch_step2d_t<double>(const void*, int, int, int, int, int64_t, hipStream_t,
+                                            bool);
 
 }  // namespace fdtdp
