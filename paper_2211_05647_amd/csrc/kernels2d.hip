@@ -244,6 +244,15 @@ __device__ __forceinline__ void kinetic2v_f32(const Run2D<float>& R, int c0, int
   }
 }
 
+// Work-group b of n renumbered so that the work-groups one XCD runs (the dispatcher deals
+// them out to the eight XCDs in turn) take one contiguous range: a field strip's
+// neighbouring rows are then read by the same XCD shortly before or after, from its L2,
+// instead of again from HBM by another XCD.
+__device__ __forceinline__ int xcd_contiguous(int b, int n) {
+  const int q = n >> 3, r = n & 7, x = b & 7, i = b >> 3;
+  return x * q + (x < r ? x : r) + i;
+}
+
 // NV > 0: FP32 with NV bins per velocity axis (the specialised kinetic path); NV = 0: any
 // bin count and precision.
 template <class T, int NV, bool S = false>
@@ -264,7 +273,7 @@ __global__ __launch_bounds__(kBlock) void k_h2d_kin(const Run2D<T>* __restrict__
     return;
   }
   // Hz: kBlock columns by R.hrows (1 or 4) rows per block
-  const int seg = (int)blockIdx.x - R.nbk;
+  const int seg = xcd_contiguous((int)blockIdx.x - R.nbk, (int)gridDim.x - R.nbk);
   const int spr = (R.nx + kBlock - 1) / kBlock;
   const int strip = seg / spr;
   const int i = (seg - strip * spr) * kBlock + (int)threadIdx.x;
@@ -278,8 +287,9 @@ __global__ __launch_bounds__(kBlock) void k_e2d(const Run2D<T>* __restrict__ rp,
   const Run2D<T>& R = *rp;
   // kBlock columns by R.erows (1 or 4) rows of the (nx+1) x (ny+1) lattice per block
   const int spr = (R.nx + kBlock) / kBlock;
-  const int strip = (int)blockIdx.x / spr;
-  const int i = ((int)blockIdx.x - strip * spr) * kBlock + (int)threadIdx.x;
+  const int b = xcd_contiguous((int)blockIdx.x, (int)gridDim.x);
+  const int strip = b / spr;
+  const int i = (b - strip * spr) * kBlock + (int)threadIdx.x;
   if (i > R.nx) return;
   if (R.erows == 4) e2d_rows<4>(R, i, strip * 4, step);
   else e2d_rows<1>(R, i, strip, step);
