@@ -273,8 +273,10 @@ def extra_full(B, W, torch, steps=None):
                           kernel=f"k_step1d_tb_full<{t['k']}, 64>")
         ms1, _, _ = time_steps(run, B, torch, steps, 50, reps=3, time_block=1)
         gbs, frac = hbm(bytes_1d_full(run), ms1)
-        e["one_step_per_launch"] = dict(kernel="k_step1d_full<float>", ms_per_step=ms1,
-                                        hbm_gbs=gbs, hbm_frac=frac)
+        streamed = run.plasma_cells * run.nv * 4 > (192 << 20)   # the library's threshold
+        e["one_step_per_launch"] = dict(
+            kernel=f"k_step1d_full<float, 1, {'true' if streamed else 'false'}>",
+            ms_per_step=ms1, hbm_gbs=gbs, hbm_frac=frac)
         e["workload"] = (f"1D Yee + full-distribution 1V kinetic, Nx={run.nx}, Nv={run.nv}, "
                          f"FP32, {steps} steps")
         out[key] = e

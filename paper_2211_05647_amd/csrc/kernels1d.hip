@@ -171,7 +171,7 @@ __device__ __forceinline__ void kinetic_tile(const Run1D<T>& R, const T* eloc,
 //   J = -e dv sum over both halves of v f = the linear model's moment of o'.
 // A lane group of lpc lanes holds a row in 16-byte chunks (chunk li + m lpc of each half);
 // the neighbour bins across chunk edges come from the next / previous lane by shuffles.
-template <class T, int CPL, int NT>
+template <class T, int CPL, int NT, bool S = false>
 __device__ __forceinline__ void kinetic_tile_full(const Run1D<T>& R, const T* eloc,
                                                   const Tile1D& tile, T* jloc) {
   using V = typename Vec<T>::type;
@@ -209,8 +209,8 @@ __device__ __forceinline__ void kinetic_tile_full(const Run1D<T>& R, const T* el
       const V* row = dfv + (size_t)c * (2 * ch);
 #pragma unroll
       for (int m = 0; m < CPL; ++m) {
-        o[m] = row[li + m * lpc];
-        e[m] = row[ch + li + m * lpc];
+        o[m] = row_load<S>(&row[li + m * lpc]);
+        e[m] = row_load<S>(&row[ch + li + m * lpc]);
       }
     } else {
 #pragma unroll
@@ -326,8 +326,8 @@ __device__ __forceinline__ void kinetic_tile_full(const Run1D<T>& R, const T* el
       V* row = dfv + (size_t)c * (2 * ch);
 #pragma unroll
       for (int m = 0; m < CPL; ++m) {
-        row[li + m * lpc] = on[m];
-        row[ch + li + m * lpc] = e[m];
+        row_store<S>(on[m], &row[li + m * lpc]);
+        row_store<S>(e[m], &row[ch + li + m * lpc]);
       }
     }
     const double tot = row_sum_dpp(acc, lpc, li);   // DPP rounds, as the blocked kernel
@@ -519,7 +519,10 @@ __device__ __forceinline__ void step_tile(const Run1D<T>& R, const Tile1D& tile,
     const int ch = R.half / Vec<T>::n;
     const int cpl = ch < 64 ? 1 : ch / 64;
     if constexpr (KIND == 1) {
-      if (cpl == 1) kinetic_tile_full<T, 1, NT>(R, eloc, tile, jloc);
+      if constexpr (C == 1) kinetic_tile_full<T, 1, NT, STREAM>(R, eloc, tile, jloc);
+      else if constexpr (C == 2) kinetic_tile_full<T, 2, NT, STREAM>(R, eloc, tile, jloc);
+      else if constexpr (C == 4) kinetic_tile_full<T, 4, NT, STREAM>(R, eloc, tile, jloc);
+      else if (cpl == 1) kinetic_tile_full<T, 1, NT>(R, eloc, tile, jloc);
       else if (cpl == 2) kinetic_tile_full<T, 2, NT>(R, eloc, tile, jloc);
       else kinetic_tile_full<T, 4, NT>(R, eloc, tile, jloc);
     } else if constexpr (KIND == 2) {
@@ -608,7 +611,7 @@ __global__ __launch_bounds__(kBlock) void k_step1d(const Run1D<T>* __restrict__ 
 
 // The same step for runs of the full-distribution model (a kernel of its own, so the
 // linear model's kernels keep their register budget).
-template <class T>
+template <class T, int C, bool S>
 __global__ __launch_bounds__(kBlock) void k_step1d_full(const Run1D<T>* __restrict__ runs,
                                                         const Tile1D* __restrict__ tiles,
                                                         int64_t step) {
@@ -617,7 +620,7 @@ __global__ __launch_bounds__(kBlock) void k_step1d_full(const Run1D<T>* __restri
   const Tile1D tile = tiles[blockIdx.x];
   const Run1D<T>& R = runs[tile.run];
   if (step >= R.step_limit) return;
-  step_tile<T, kBlock, 1>(R, tile, step, jloc, eloc);
+  step_tile<T, kBlock, 1, C, S>(R, tile, step, jloc, eloc);
 }
 
 // The same step for runs of the two-term model; `pending` applies the previous step's
@@ -645,29 +648,28 @@ hipError_t launch_step1d_tt(const void* runs, const void* tiles, int ntiles, int
 }
 
 template <class T, int C, bool S>
-void launch_k1(const void* runs, const void* tiles, int ntiles, int64_t step, hipStream_t stream) {
-  hipLaunchKernelGGL((k_step1d<T, C, S>), dim3(ntiles), dim3(kBlock), 0, stream,
-                     static_cast<const Run1D<T>*>(runs), static_cast<const Tile1D*>(tiles), step);
+void launch_k1(const void* runs, const void* tiles, int ntiles, int64_t step, hipStream_t stream,
+               bool full) {
+  if (full)
+    hipLaunchKernelGGL((k_step1d_full<T, C, S>), dim3(ntiles), dim3(kBlock), 0, stream,
+                       static_cast<const Run1D<T>*>(runs), static_cast<const Tile1D*>(tiles), step);
+  else
+    hipLaunchKernelGGL((k_step1d<T, C, S>), dim3(ntiles), dim3(kBlock), 0, stream,
+                       static_cast<const Run1D<T>*>(runs), static_cast<const Tile1D*>(tiles), step);
 }
 
 template <class T>
 hipError_t launch_step1d(const void* runs, const void* tiles, int ntiles, int64_t step,
                          hipStream_t stream, bool full, int cpl, bool streaming) {
   if (ntiles <= 0) return hipSuccess;
-  if (full) {
-    hipLaunchKernelGGL(k_step1d_full<T>, dim3(ntiles), dim3(kBlock), 0, stream,
-                       static_cast<const Run1D<T>*>(runs), static_cast<const Tile1D*>(tiles),
-                       step);
-  } else {
-    switch (cpl) {
-      case 1: streaming ? launch_k1<T, 1, true>(runs, tiles, ntiles, step, stream)
-                        : launch_k1<T, 1, false>(runs, tiles, ntiles, step, stream); break;
-      case 2: streaming ? launch_k1<T, 2, true>(runs, tiles, ntiles, step, stream)
-                        : launch_k1<T, 2, false>(runs, tiles, ntiles, step, stream); break;
-      case 4: streaming ? launch_k1<T, 4, true>(runs, tiles, ntiles, step, stream)
-                        : launch_k1<T, 4, false>(runs, tiles, ntiles, step, stream); break;
-      default: launch_k1<T, 0, false>(runs, tiles, ntiles, step, stream); break;
-    }
+  switch (cpl) {
+    case 1: streaming ? launch_k1<T, 1, true>(runs, tiles, ntiles, step, stream, full)
+                      : launch_k1<T, 1, false>(runs, tiles, ntiles, step, stream, full); break;
+    case 2: streaming ? launch_k1<T, 2, true>(runs, tiles, ntiles, step, stream, full)
+                      : launch_k1<T, 2, false>(runs, tiles, ntiles, step, stream, full); break;
+    case 4: streaming ? launch_k1<T, 4, true>(runs, tiles, ntiles, step, stream, full)
+                      : launch_k1<T, 4, false>(runs, tiles, ntiles, step, stream, full); break;
+    default: launch_k1<T, 0, false>(runs, tiles, ntiles, step, stream, full); break;
   }
   return hipGetLastError();
 }
