@@ -121,13 +121,14 @@ def test_batch_parity_with_oracle(gpu_lib):
         assert err <= 1e-5
 
 
-def test_taps_record_drive_and_current(gpu_lib):
+@pytest.mark.parametrize("mode", [1, 0])
+def test_taps_record_drive_and_current(gpu_lib, mode):
     """Taps hold (E^n, J^{n+1/2}) at their nodes for every step: checked against the
-    oracle stepped one step at a time."""
+    oracle stepped one step at a time, in both launch forms."""
     runs = small_batch(3, seed=31, nx_hi=500)
     taps = tap_nodes(runs, 4)
-    _banner("taps")
-    bat = B.Sim(runs, taps=taps)
+    _banner(f"taps, batch mode {mode}")
+    bat = B.Sim(runs, taps=taps, batch_mode=mode)
     bat.run(max(r.steps for r in runs))
     for r, run in enumerate(runs):
         got = bat.read_taps(r)
@@ -143,13 +144,14 @@ def test_taps_record_drive_and_current(gpu_lib):
         assert rel_l2(got[:, :, 1].T, J) <= 1e-5
 
 
-def test_nonfinite_run_is_flagged_alone(gpu_lib):
+@pytest.mark.parametrize("mode", [1, 0])
+def test_nonfinite_run_is_flagged_alone(gpu_lib, mode):
     """A run whose density overflows FP32 storage turns non-finite; only that run is
-    flagged and the others stay bitwise equal to their solo runs."""
+    flagged and the others stay bitwise equal to their solo runs, in both launch forms."""
     runs = small_batch(4, seed=41)
     runs[2].ne[runs[2].ne > 0] = 1e39
-    _banner("non-finite run")
-    bat = B.Sim(runs)
+    _banner(f"non-finite run, batch mode {mode}")
+    bat = B.Sim(runs, batch_mode=mode)
     bat.run(max(r.steps for r in runs))
     assert bat.run_status(2) == B.ENUMERIC
     with pytest.raises(B.FdtdError) as ei:
