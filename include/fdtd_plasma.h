@@ -113,7 +113,7 @@ typedef struct {
  * Maxwellian mean is nu_mean; CONST: nu = nu_mean.  closure: KINETIC, or MLP with the
  * network blob `mlp` (fdtd_mlp_blob) and the kinetic step as fallback.
  * kinetic: LINEAR is the model of section 5.2 (F0 frozen, F1 driven by E dF0/dv).
- * FULL (1D single runs only) evolves the whole f of each plasma node under
+ * FULL (1D single runs and batches of full-model runs) evolves the whole f of each plasma node under
  * df/dt - (e/m) E df/dv = C(f) (the kinetic equation of section 5.1 without the
  * streaming and magnetic terms): its even part is the l = 0 equation's F0, which heats,
  * its odd part F1.  The velocity derivative is in conservative flux form with zero flux
@@ -196,8 +196,8 @@ int fdtd_plasma_workspace_size(const fdtd_grid *grid, const fdtd_profile *profil
 int fdtd_plasma_create(const fdtd_grid *grid, const fdtd_profile *profile,
                        const fdtd_source *source, const fdtd_device *dev, fdtd_plasma **out);
 
-/* Batch of nruns independent 1D FP32 runs of uneven size (arrays of nruns structs),
- * advanced together.  steps[r] is the step count of run r: fdtd_plasma_run advances
+/* Batch of nruns independent 1D FP32 runs of uneven size (arrays of nruns structs), all of
+ * one kinetic model, LINEAR or FULL (EINVAL otherwise), advanced together.  steps[r] is the step count of run r: fdtd_plasma_run advances
  * every run to min(its own count, the batch step).  ntap (0..8) training-pair taps per
  * run record (E^n, J^{n+1/2}) at the plasma nodes tap_nodes[r * ntap + k] after every
  * step of that run (NULL when ntap = 0).  Default launch form (batch mode 1): the runs
@@ -221,7 +221,8 @@ int fdtd_plasma_create_batch(int32_t nruns, const fdtd_grid *grids,
  * (tile, K-step block) items of every run in order from a work counter, a block of a tile
  * starting once the tile and its two neighbours have finished the block before; each
  * run's last steps go as one odd block or two.  Mode 0 needs what the blocked path needs
- * (K >= 3, runs of supported Nv); otherwise the batch steps one step per launch.  Both
+ * (K >= 3, runs of supported Nv) and LINEAR runs; a FULL batch takes mode 1's launches, and
+ * a batch the blocked path cannot take steps one step per launch.  Both
  * modes give bitwise identical results.  Only before the first step. */
 int fdtd_plasma_set_batch_mode(fdtd_plasma *h, int32_t mode, int32_t groups);
 

@@ -125,8 +125,8 @@ int validate_1d(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s,
   if (p->kinetic != FDTD_KINETIC_LINEAR && p->kinetic != FDTD_KINETIC_FULL &&
       p->kinetic != FDTD_KINETIC_TWO_TERM)
     return fail(FDTD_EINVAL, "unknown kinetic model %d", p->kinetic);
-  if (batch && p->kinetic != FDTD_KINETIC_LINEAR)
-    return fail(FDTD_EINVAL, "batched runs take the linear kinetic model");
+  if (batch && p->kinetic == FDTD_KINETIC_TWO_TERM)
+    return fail(FDTD_EINVAL, "batched runs take the LINEAR or FULL kinetic model");
   if (!p->ne || !p->nu_mean) return fail(FDTD_EINVAL, "null ne or nu_mean");
   const int nx = g->nx;
   for (int i = 0; i <= nx; ++i) {
@@ -846,6 +846,8 @@ int fdtd_plasma_workspace_size_batch(int32_t nruns, const fdtd_grid* grids,
   for (int r = 0; r < nruns; ++r) {
     int rc = validate_1d(&grids[r], &profiles[r], nullptr, true);
     if (rc) return rc;
+    if (profiles[r].kinetic != profiles[0].kinetic)
+      return fail(FDTD_EINVAL, "run %d: the runs of a batch share one kinetic model", r);
     if (steps[r] < 0) return fail(FDTD_EINVAL, "run %d: negative step count", r);
     specs[r].g = grids[r];
     specs[r].p = profiles[r];
@@ -951,6 +953,8 @@ int fdtd_plasma_create_batch(int32_t nruns, const fdtd_grid* grids, const fdtd_p
   for (int r = 0; r < nruns; ++r) {
     int rc = validate_1d(&grids[r], &profiles[r], sources ? &sources[r] : nullptr, true);
     if (rc) return fail(rc, "run %d: %s", r, g_last_error.c_str());
+    if (profiles[r].kinetic != profiles[0].kinetic)
+      return fail(FDTD_EINVAL, "run %d: the runs of a batch share one kinetic model", r);
     if (steps[r] < 0) return fail(FDTD_EINVAL, "run %d: negative step count", r);
     for (int t = 0; t < ntap; ++t) {
       const int32_t nd = tap_nodes[(size_t)r * ntap + t];
@@ -990,7 +994,8 @@ int fdtd_plasma_run(fdtd_plasma* h, int64_t nsteps) {
   h->started = true;
   int64_t nsteps_loop = nsteps;
   if ((e = hipEventRecord(h->ev0, h->stream))) return hip_fail(e, "hipEventRecord");
-  if (h->dims == 1 && h->nruns > 1 && h->batch_mode == 0 && h->ntbtiles > 0) {
+  if (h->dims == 1 && h->nruns > 1 && h->batch_mode == 0 && h->ntbtiles > 0 &&
+      h->h1[0].model == FDTD_KINETIC_LINEAR) {
     // one persistent launch for the whole call
     int rc = rows_home(h, -1);
     if (rc) return rc;
@@ -1030,9 +1035,9 @@ int fdtd_plasma_run(fdtd_plasma* h, int64_t nsteps) {
         cur = h->df_cur[r];
       }
       const int64_t in_off = cur == 1 ? delta : 0, out_off = cur == 1 ? 0 : delta;
-      // two-term runs are single runs: run 0 decides (their blocked kernel leaves F0
-      // complete, so the one-step launches after it start with no l = 0 update pending)
-      // (full-model runs are single runs too)
+      // every run of a handle has one model (batches: LINEAR or FULL): run 0 decides; a
+      // two-term run's blocked kernel leaves F0 complete, so the one-step launches after it
+      // start with no l = 0 update pending
       const int model = h->h1[0].model;
       for (const TbSeg& sg : h->tb_seg) {
         const int n = count_ge(sg.limit, s + kb);
@@ -1056,8 +1061,8 @@ int fdtd_plasma_run(fdtd_plasma* h, int64_t nsteps) {
         const int p1 = count_ge(h->tile_limit, s + kb), p2 = count_ge(h->tile_limit, s + 1);
         for (int64_t ss = s; p2 > p1 && ss < s + kb; ++ss) {
           const int n = count_ge(h->tile_limit, ss + 1) - p1;
-          e = launch_step1d<float>(h->ws + h->runs_off, rt + p1, n, ss, h->stream, false,
-                                   h->one_cpl, h->one_stream);
+          e = launch_step1d<float>(h->ws + h->runs_off, rt + p1, n, ss, h->stream,
+                                   model == FDTD_KINETIC_FULL, h->one_cpl, h->one_stream);
           if (e) return hip_fail(e, "launch step kernel");
         }
       }
@@ -1077,7 +1082,7 @@ int fdtd_plasma_run(fdtd_plasma* h, int64_t nsteps) {
                                    [](int64_t v, int64_t lim) { return v >= lim; }) -
                   h->tile_limit.begin());
       }
-      // full-model and two-term runs are single runs (never batched): run 0 decides
+      // every run of a handle has one model (two-term runs are single runs): run 0 decides
       const int model = h->h1[0].model;
       if (model == FDTD_KINETIC_TWO_TERM) {
         // the l = 0 update of step s - 1 rides on step s (none pending at a call's start)

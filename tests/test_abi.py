@@ -80,6 +80,34 @@ def test_bad_problem_statements_are_rejected(mutate):
     assert len(L.fdtd_plasma_last_error()) > 0
 
 
+@pytest.mark.parametrize("models,ok", [
+    ((B.KINETIC_LINEAR, B.KINETIC_LINEAR), True),
+    ((B.KINETIC_FULL, B.KINETIC_FULL), True),
+    ((B.KINETIC_LINEAR, B.KINETIC_FULL), False),
+    ((B.KINETIC_TWO_TERM, B.KINETIC_TWO_TERM), False),
+])
+def test_batch_kinetic_models(models, ok):
+    """A batch takes runs of one kinetic model, LINEAR or FULL (checked before any device
+    is touched, by the workspace-size call)."""
+    L = B.lib()
+    run = W.c0()
+    gs, ps, keep = [], [], []
+    for m in models:
+        g, p, k = _grid_profile(run)
+        p.kinetic = m
+        gs.append(g)
+        ps.append(p)
+        keep.append(k)
+    ga = (B.Grid * len(gs))(*gs)
+    pa = (B.Profile * len(ps))(*ps)
+    steps = (C.c_int64 * len(gs))(*([100] * len(gs)))
+    n = C.c_size_t(0)
+    rc = L.fdtd_plasma_workspace_size_batch(len(gs), ga, pa, steps, 0, None, C.byref(n))
+    assert (rc == 0) == ok, (models, rc, L.fdtd_plasma_last_error())
+    if ok:
+        assert n.value > 0
+
+
 def test_plasma_at_the_ends_is_rejected():
     L = B.lib()
     run = W.c0()

@@ -87,10 +87,13 @@ def test_full_model_velocity_cfl_flagged(gpu_lib):
 
 
 def test_full_model_configurations_rejected(gpu_lib):
-    """The full model runs 1D single runs: batches and 2D runs refuse it."""
+    """The full model runs 1D single runs and batches of full-model runs: a batch that
+    mixes it with the linear model, and 2D runs, refuse it."""
     run = _strong(64)
+    lin = _strong(64)
+    lin.kinetic = "linear"
     with pytest.raises(B.FdtdError):
-        B.Sim([run, run], precision=B.FP32)
+        B.Sim([run, lin], precision=B.FP32)
     r2 = W.c2(n=64, radius=10.0, steps=10)
     r2.kinetic = "full"
     with pytest.raises(B.FdtdError):
@@ -132,6 +135,35 @@ def _long(nv, steps=600):
     run.src_amp = 3e5 * 64 / nv
     run.kinetic = "full"
     return run
+
+
+@pytest.mark.parametrize("mode", [1, 0])
+def test_full_model_batch_equals_solo_bitwise(gpu_lib, mode):
+    """A batch of full-model runs of uneven size (Nv 64, 256 and 512; runs that end inside
+    and at the end of K-step blocks) ends bitwise where each run ends alone, in either
+    batch mode (the persistent launch takes linear runs only, so a full-model batch falls
+    back to K-step launches there)."""
+    g = np.random.default_rng(5)
+    runs = []
+    for r, nv in enumerate((64, 256, 512, 64, 256)):
+        nx = int(g.integers(400, 1400))
+        run = W.slab_1d(nx, nv, int(0.3 * nx), int(0.7 * nx), 1.0, 0.2, W.F_REF, 40,
+                        int(g.integers(300, 900)), name=f"fb{r}")
+        run.src_amp = 3e5 * 64 / nv
+        run.kinetic = "full"
+        runs.append(run)
+    _banner(f"full-model batch, mode {mode}")
+    bat = B.Sim(runs, batch_mode=mode)
+    assert bat.time_block() > 1
+    bat.run(max(r.steps for r in runs) + 3)
+    for r, run in enumerate(runs):
+        assert bat.run_status(r) == B.OK
+        solo = B.Sim(run)
+        solo.run(run.steps)
+        for f in (B.F_E, B.F_H, B.F_J, B.F_DF):
+            assert np.array_equal(bat.read(f, run=r), solo.read(f)), (r, f)
+        solo.close()
+    bat.close()
 
 
 @pytest.mark.parametrize("nv", [64, 512])
