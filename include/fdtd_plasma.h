@@ -113,7 +113,7 @@ typedef struct {
  * Maxwellian mean is nu_mean; CONST: nu = nu_mean.  closure: KINETIC, or MLP with the
  * network blob `mlp` (fdtd_mlp_blob) and the kinetic step as fallback.
  * kinetic: LINEAR is the model of section 5.2 (F0 frozen, F1 driven by E dF0/dv).
- * FULL (1D single runs and batches of full-model runs) evolves the whole f of each plasma node under
+ * FULL (1D single runs and batches) evolves the whole f of each plasma node under
  * df/dt - (e/m) E df/dv = C(f) (the kinetic equation of section 5.1 without the
  * streaming and magnetic terms): its even part is the l = 0 equation's F0, which heats,
  * its odd part F1.  The velocity derivative is in conservative flux form with zero flux
@@ -121,7 +121,7 @@ typedef struct {
  * |(e/m) E dt / dv| <= 1, and a step that breaks it sets the run status (see
  * fdtd_plasma_run_status).  Temporally blocked as the LINEAR model is
  * (fdtd_plasma_set_time_block).
- * TWO_TERM (1D single runs and 3D grids): the paper's own representation, section 5.1's
+ * TWO_TERM (1D single runs and batches, 3D grids): the paper's own representation, section 5.1's
  * expansion F = F0 + (v/|v|).F1 with its l = 0 and l = 1 equations on a speed grid of nv
  * speeds (2..256; the paper uses 31) v_k = (k + 1/2) vmax / nv, F0 (f0_model) evolving
  * under the l = 0 equation without streaming (elastic collisions only: their l = 0 term,
@@ -197,7 +197,8 @@ int fdtd_plasma_create(const fdtd_grid *grid, const fdtd_profile *profile,
                        const fdtd_source *source, const fdtd_device *dev, fdtd_plasma **out);
 
 /* Batch of nruns independent 1D FP32 runs of uneven size (arrays of nruns structs), all of
- * one kinetic model, LINEAR or FULL (EINVAL otherwise), advanced together.  steps[r] is the step count of run r: fdtd_plasma_run advances
+ * one kinetic model (EINVAL otherwise), advanced together; a two-term run that stops takes
+ * its last deferred l = 0 update with it, so its state is complete from then on.  steps[r] is the step count of run r: fdtd_plasma_run advances
  * every run to min(its own count, the batch step).  ntap (0..8) training-pair taps per
  * run record (E^n, J^{n+1/2}) at the plasma nodes tap_nodes[r * ntap + k] after every
  * step of that run (NULL when ntap = 0).  Default launch form (batch mode 1): the runs
@@ -221,8 +222,8 @@ int fdtd_plasma_create_batch(int32_t nruns, const fdtd_grid *grids,
  * (tile, K-step block) items of every run in order from a work counter, a block of a tile
  * starting once the tile and its two neighbours have finished the block before; each
  * run's last steps go as one odd block or two.  Mode 0 needs what the blocked path needs
- * (K >= 3, runs of supported Nv) and LINEAR runs; a FULL batch takes mode 1's launches, and
- * a batch the blocked path cannot take steps one step per launch.  Both
+ * (K >= 3, runs of supported Nv) and LINEAR runs; a FULL or TWO_TERM batch takes mode 1's
+ * launches, and a batch the blocked path cannot take steps one step per launch.  Both
  * modes give bitwise identical results.  Only before the first step. */
 int fdtd_plasma_set_batch_mode(fdtd_plasma *h, int32_t mode, int32_t groups);
 

@@ -125,8 +125,6 @@ int validate_1d(const fdtd_grid* g, const fdtd_profile* p, const fdtd_source* s,
   if (p->kinetic != FDTD_KINETIC_LINEAR && p->kinetic != FDTD_KINETIC_FULL &&
       p->kinetic != FDTD_KINETIC_TWO_TERM)
     return fail(FDTD_EINVAL, "unknown kinetic model %d", p->kinetic);
-  if (batch && p->kinetic == FDTD_KINETIC_TWO_TERM)
-    return fail(FDTD_EINVAL, "batched runs take the LINEAR or FULL kinetic model");
   if (!p->ne || !p->nu_mean) return fail(FDTD_EINVAL, "null ne or nu_mean");
   const int nx = g->nx;
   for (int i = 0; i <= nx; ++i) {
@@ -1035,9 +1033,9 @@ int fdtd_plasma_run(fdtd_plasma* h, int64_t nsteps) {
         cur = h->df_cur[r];
       }
       const int64_t in_off = cur == 1 ? delta : 0, out_off = cur == 1 ? 0 : delta;
-      // every run of a handle has one model (batches: LINEAR or FULL): run 0 decides; a
-      // two-term run's blocked kernel leaves F0 complete, so the one-step launches after it
-      // start with no l = 0 update pending
+      // every run of a handle has one model: run 0 decides; a two-term run's blocked
+      // kernel leaves F0 complete, so the one-step launches after it start with no l = 0
+      // update pending
       const int model = h->h1[0].model;
       for (const TbSeg& sg : h->tb_seg) {
         const int n = count_ge(sg.limit, s + kb);
@@ -1060,9 +1058,16 @@ int fdtd_plasma_run(fdtd_plasma* h, int64_t nsteps) {
         if (rc) return rc;
         const int p1 = count_ge(h->tile_limit, s + kb), p2 = count_ge(h->tile_limit, s + 1);
         for (int64_t ss = s; p2 > p1 && ss < s + kb; ++ss) {
-          const int n = count_ge(h->tile_limit, ss + 1) - p1;
-          e = launch_step1d<float>(h->ws + h->runs_off, rt + p1, n, ss, h->stream,
-                                   model == FDTD_KINETIC_FULL, h->one_cpl, h->one_stream);
+          if (model == FDTD_KINETIC_TWO_TERM) {
+            // the runs still stepping, and those whose last step was ss - 1 (their flush)
+            const int n = count_ge(h->tile_limit, ss) - p1;
+            e = launch_step1d_tt<float>(h->ws + h->runs_off, rt + p1, n, ss, ss > s, false,
+                                        h->stream);
+          } else {
+            const int n = count_ge(h->tile_limit, ss + 1) - p1;
+            e = launch_step1d<float>(h->ws + h->runs_off, rt + p1, n, ss, h->stream,
+                                     model == FDTD_KINETIC_FULL, h->one_cpl, h->one_stream);
+          }
           if (e) return hip_fail(e, "launch step kernel");
         }
       }
@@ -1075,15 +1080,17 @@ int fdtd_plasma_run(fdtd_plasma* h, int64_t nsteps) {
   for (int64_t k = k0; k < nsteps_loop; ++k) {
     const int64_t s = h->step + k;
     if (h->dims == 1) {
-      // active tiles: those whose run still has steps left (limits are non-increasing)
+      // every run of a handle has one model: run 0 decides
+      const int model = h->h1[0].model;
+      // active tiles: those whose run still has steps left (limits are non-increasing);
+      // two-term runs also those whose last step was s - 1, for their flush
       int n = h->ntiles;
       if (h->nruns > 1) {
-        n = (int)(std::upper_bound(h->tile_limit.begin(), h->tile_limit.end(), s,
-                                   [](int64_t v, int64_t lim) { return v >= lim; }) -
+        const int64_t lim = model == FDTD_KINETIC_TWO_TERM ? s - 1 : s;
+        n = (int)(std::upper_bound(h->tile_limit.begin(), h->tile_limit.end(), lim,
+                                   [](int64_t v, int64_t l) { return v >= l; }) -
                   h->tile_limit.begin());
       }
-      // every run of a handle has one model (two-term runs are single runs): run 0 decides
-      const int model = h->h1[0].model;
       if (model == FDTD_KINETIC_TWO_TERM) {
         // the l = 0 update of step s - 1 rides on step s (none pending at a call's start)
         const bool pending = k > k0;
@@ -1106,11 +1113,18 @@ int fdtd_plasma_run(fdtd_plasma* h, int64_t nsteps) {
     if (e) return hip_fail(e, "launch step kernel");
   }
   if (h->dims == 1 && h->h1[0].model == FDTD_KINETIC_TWO_TERM && nsteps_loop > k0) {
-    // the last step's l = 0 update, so that the state after the call is complete
+    // the last step's l = 0 update, so that the state after the call is complete: the
+    // runs that stepped up to the call's end (a run of a batch that stopped earlier took
+    // its own flush then)
     const int64_t s = h->step + nsteps_loop;
+    int n = h->ntiles;
+    if (h->nruns > 1)
+      n = (int)(std::upper_bound(h->tile_limit.begin(), h->tile_limit.end(), s - 1,
+                                 [](int64_t v, int64_t l) { return v >= l; }) -
+                h->tile_limit.begin());
     e = h->precision == FDTD_FP64
-            ? launch_step1d_tt<double>(h->ws + h->runs_off, h->ws + h->tiles_off, h->ntiles, s, true, true, h->stream)
-            : launch_step1d_tt<float>(h->ws + h->runs_off, h->ws + h->tiles_off, h->ntiles, s, true, true, h->stream);
+            ? launch_step1d_tt<double>(h->ws + h->runs_off, h->ws + h->tiles_off, n, s, true, true, h->stream)
+            : launch_step1d_tt<float>(h->ws + h->runs_off, h->ws + h->tiles_off, n, s, true, true, h->stream);
     if (e) return hip_fail(e, "launch l = 0 flush");
   }
   if ((e = hipEventRecord(h->ev1, h->stream))) return hip_fail(e, "hipEventRecord");

@@ -633,8 +633,11 @@ __global__ __launch_bounds__(kBlock) void k_step1d_tt(const Run1D<T>* __restrict
   __shared__ T eloc[kMaxTile1D];
   const Tile1D tile = tiles[blockIdx.x];
   const Run1D<T>& R = runs[tile.run];
-  if (!flush && step >= R.step_limit) return;
-  step_tile<T, kBlock, 2>(R, tile, step, jloc, eloc, pending != 0, flush != 0);
+  // a run of a batch whose last step was step - 1 takes only that step's pending l = 0
+  // update (its flush), so that its state is complete when it stops
+  const bool fl = flush || (pending && step == R.step_limit);
+  if (!fl && step >= R.step_limit) return;
+  step_tile<T, kBlock, 2>(R, tile, step, jloc, eloc, pending != 0, fl);
 }
 
 template <class T>

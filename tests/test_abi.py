@@ -84,11 +84,12 @@ def test_bad_problem_statements_are_rejected(mutate):
     ((B.KINETIC_LINEAR, B.KINETIC_LINEAR), True),
     ((B.KINETIC_FULL, B.KINETIC_FULL), True),
     ((B.KINETIC_LINEAR, B.KINETIC_FULL), False),
-    ((B.KINETIC_TWO_TERM, B.KINETIC_TWO_TERM), False),
+    ((B.KINETIC_TWO_TERM, B.KINETIC_TWO_TERM), True),
+    ((B.KINETIC_FULL, B.KINETIC_TWO_TERM), False),
 ])
 def test_batch_kinetic_models(models, ok):
-    """A batch takes runs of one kinetic model, LINEAR or FULL (checked before any device
-    is touched, by the workspace-size call)."""
+    """A batch takes runs of one kinetic model (checked before any device is touched, by
+    the workspace-size call)."""
     L = B.lib()
     run = W.c0()
     gs, ps, keep = [], [], []

@@ -85,10 +85,18 @@ def test_call_boundaries_do_not_change_the_result(gpu_lib):
     a.close(); b.close(); c.close()
 
 
-def test_two_term_rejected_in_batches(gpu_lib):
+def test_two_term_batch_rules(gpu_lib):
+    """Two-term runs batch with each other, in FP32 only, and not with runs of another
+    model."""
     run = _run(31)
+    lin = _run(31)
+    lin.kinetic = "linear"
+    lin.nv = 64
     with pytest.raises(B.FdtdError):
-        B.Sim([run, run], precision=B.FP32)
+        B.Sim([run, lin], precision=B.FP32)
+    with pytest.raises(B.FdtdError):
+        B.Sim([run, run], precision=B.FP64)
+    B.Sim([run, run], precision=B.FP32).close()
 
 
 def test_two_term_cfl_flagged(gpu_lib):
@@ -162,3 +170,40 @@ def test_blocked_two_term_parity(gpu_lib, nv):
     _banner(f"  F0 - n F0hat rel L2 = {err0:.3e}")
     assert err0 <= 1e-5
     sim.close()
+
+
+@pytest.mark.parametrize("mode", [1, 0])
+def test_two_term_batch_equals_solo_bitwise(gpu_lib, mode):
+    """A batch of two-term runs of uneven length (31 and 64 speeds; runs that stop inside a
+    K-step pass, at its end, and after the call boundaries), advanced over calls of uneven
+    length, ends bitwise where each run ends alone: every run takes its own last deferred
+    l = 0 update when it stops (the persistent form takes linear runs only, so the batch
+    uses K-step launches in either mode)."""
+    g = np.random.default_rng(7)
+    runs = []
+    for r, nv in enumerate((31, 64, 31, 64, 31)):
+        run = _run(nv, steps=int(g.integers(200, 700)))
+        run.name = f"tb{r}"
+        runs.append(run)
+    runs[2].steps = 9 * 40          # stops at the end of a pass
+    runs[4].steps = 9 * 40 + 4      # stops inside one
+    _banner(f"two-term batch, mode {mode}")
+    bat = B.Sim(runs, batch_mode=mode)
+    assert bat.time_block() > 1
+    total = max(r.steps for r in runs) + 5
+    done = 0
+    for k in (1, 100, 7, 251, 1000):
+        k = min(k, total - done)
+        if k <= 0:
+            break
+        bat.run(k)
+        done += k
+    assert done == total
+    for r, run in enumerate(runs):
+        assert bat.run_status(r) == B.OK
+        solo = B.Sim(run)
+        solo.run(run.steps)
+        for f in (B.F_E, B.F_H, B.F_J, B.F_DF):
+            assert np.array_equal(bat.read(f, run=r), solo.read(f)), (r, f)
+        solo.close()
+    bat.close()
