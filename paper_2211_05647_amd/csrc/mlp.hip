@@ -397,21 +397,45 @@ __global__ __launch_bounds__(256) void k_mlp_grad(MlpWeights W, const float* __r
   }
 }
 
-// Sum the per-block partial gradients in block order (deterministic) into G, and the
-// loss partials into *loss (mean squared error).
-__global__ void k_mlp_reduce(const float* __restrict__ P, const float* __restrict__ lossp,
-                             int nblocks, int n, float* __restrict__ G, float* __restrict__ loss) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+// Sum the per-block partial gradients into G, and the loss partials into *loss (mean
+// squared error), each in a fixed order so that training is deterministic.  A work-group
+// takes 64 parameters: each of its four wavefronts sums one quarter of the blocks, in
+// block order, and the quarters are added in order ((q0 + q1) + (q2 + q3)).  The last
+// work-group sums the loss partials (each thread a strided run of blocks, in order, then
+// a fixed tree over the threads).
+constexpr int kReduceParams = 64;
+__global__ __launch_bounds__(256) void k_mlp_reduce(const float* __restrict__ P,
+                                                    const float* __restrict__ lossp,
+                                                    int nblocks, int n, float* __restrict__ G,
+                                                    float* __restrict__ loss) {
+  __shared__ float part[4][kReduceParams];
+  __shared__ float ls[256];
+  const int t = threadIdx.x;
+  if ((int)blockIdx.x == (int)gridDim.x - 1) {
+    float s = 0.f;
+    for (int b = t; b < nblocks; b += 256) s += lossp[b];
+    ls[t] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (t < o) ls[t] += ls[t + o];
+      __syncthreads();
+    }
+    if (t == 0) *loss = ls[0] / (float)n;
+    return;
+  }
+  const int w = t >> 6, l = t & 63;
+  const int p = blockIdx.x * kReduceParams + l;
+  const int b0 = nblocks * w / 4, b1 = nblocks * (w + 1) / 4;
+  float s = 0.f;
   if (p < kNParam) {
-    float s = 0.f;
-    for (int b = 0; b < nblocks; ++b) s += P[(size_t)b * kNParam + p];
-    G[p] = s;
+    // unrolled so that the loads of eight blocks are in flight before their adds, which
+    // still go in block order
+#pragma unroll 8
+    for (int b = b0; b < b1; ++b) s += P[(size_t)b * kNParam + p];
   }
-  if (p == 0) {
-    float s = 0.f;
-    for (int b = 0; b < nblocks; ++b) s += lossp[b];
-    *loss = s / (float)n;
-  }
+  part[w][l] = s;
+  __syncthreads();
+  if (w == 0 && p < kNParam) G[p] = (part[0][l] + part[1][l]) + (part[2][l] + part[3][l]);
 }
 
 // Adam on the FP32 master weights, then the bf16 copies the GEMM kernels read.
@@ -655,8 +679,8 @@ hipError_t mlp_launch_grad(const MlpWeights& W, const float* X, const float* T, 
   hipLaunchKernelGGL(k_mlp_grad, dim3(nb), dim3(256), 0, st, W, X, T, n, P, lossp);
   hipError_t e = hipGetLastError();
   if (e) return e;
-  hipLaunchKernelGGL(k_mlp_reduce, dim3((kNParam + 255) / 256), dim3(256), 0, st, P, lossp, nb, n,
-                     G, loss);
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((kNParam + kReduceParams - 1) / kReduceParams + 1),
+                     dim3(256), 0, st, P, lossp, nb, n, G, loss);
   return hipGetLastError();
 }
 
