@@ -98,6 +98,32 @@ def test_persistent_batch_in_chunks_equals_default(gpu_lib):
         b.close()
 
 
+def test_persistent_batch_with_many_segments(gpu_lib):
+    """300 short runs with 300 different step counts: more distinct block counts than the
+    persistent launch keeps in LDS, so its segment table is read from global memory; the
+    runs end bitwise where the default launch form takes them."""
+    g = np.random.default_rng(13)
+    runs = []
+    for r in range(300):
+        nx = int(g.integers(300, 400))
+        # 2r + 1 blocks of 9 steps, plus one odd step for odd r: 300 distinct block counts
+        run = W.slab_1d(nx, 64, int(0.4 * nx), int(0.6 * nx), 1.0, 0.1, W.F_REF, 30,
+                        18 * r + 9 + (r % 2), name=f"m{r}")
+        runs.append(run)
+    _banner("persistent batch, 300 segments")
+    total = max(r.steps for r in runs)
+    a = B.Sim(runs)
+    a.run(total)
+    b = B.Sim(runs, batch_mode=0)
+    b.run(total)
+    for r in range(0, len(runs), 7):
+        assert b.run_status(r) == B.OK
+        for f in FIELDS:
+            assert np.array_equal(a.read(f, run=r), b.read(f, run=r)), (r, f)
+    a.close()
+    b.close()
+
+
 def test_batch_parity_with_oracle(gpu_lib):
     runs = small_batch(5, seed=21, nx_hi=900)
     _banner("batch vs oracle")
