@@ -188,3 +188,40 @@ def test_blocked_launch_over_several_rounds_is_bitwise(gpu_lib):
         assert np.max(np.abs(b.read(B.F_DF))) > 0
         a.close()
         b.close()
+
+
+@pytest.mark.parametrize("k", [5, 9])
+def test_blocked_tiles_with_vacuum_gaps_are_bitwise_the_stepped_run(gpu_lib, k):
+    """A single line of Nv = 512 at K steps per launch with the plasma in seeded
+    segments of 1-80 nodes and vacuum gaps of 1-40 (rows and nodes no longer line up,
+    tiles span several gaps, some halos hold no row), probes on both sides of gaps, and
+    calls that end inside a block: against one step per launch, bit for bit."""
+    run = W.c1(nx=9000, steps=1)
+    g = np.random.default_rng(2211)
+    keep = np.zeros(run.nx + 1, bool)
+    i = 300
+    while i < run.nx - 60:
+        n = int(g.integers(1, 81))
+        keep[i:i + n] = True
+        i += n + int(g.integers(1, 41))
+    run.ne = np.where(keep, np.where(run.ne > 0, run.ne, 1e17), 0.0)
+    run.nubar = np.where(keep, np.where(run.nubar > 0, run.nubar, 1e9), 0.0)
+    steps = 1300 + k
+    probes = [run.src_node, 301, 2222, 4500, 8999]
+    _banner(f"blocked tiles with gaps, k={k}, {steps} steps")
+    sims = []
+    for tb in (1, k):
+        sim = B.Sim(run, precision=B.FP32, max_probes=len(probes) + 1, probe_capacity=steps,
+                    time_block=tb)
+        ids = [sim.add_probe(B.F_E, p) for p in probes] + [sim.add_probe(B.F_J, 2222)]
+        sims.append((sim, ids))
+    assert sims[1][0].time_block() == k
+    for sim, _ in sims:
+        sim.run(steps // 3)
+        sim.run(steps - steps // 3)
+    (a, ia), (b, ib) = sims
+    for f in (B.F_E, B.F_H, B.F_J, B.F_DF):
+        assert np.array_equal(a.read(f), b.read(f)), f
+    for p, q in zip(ia, ib):
+        assert np.array_equal(a.read_probe(p, steps), b.read_probe(q, steps))
+    assert np.max(np.abs(a.read(B.F_DF))) > 0.0
