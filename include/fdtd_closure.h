@@ -11,7 +11,7 @@
  *     y = MLP(E^n/s, ..., E^{n-15}/s, p1, p2),   s = max |E^{n-k}| (k < 16, floor 1e-30),
  *
  * p1 = omega_p dt and p2 = log10(nu_mean dt), each mapped linearly onto [-1, 1] over the
- * training box.  Network: 18 -> 128 (GELU, tanh form) -> 128 (GELU) -> 1, parameters in
+ * training box.  Network: 18 -> 128 (ReLU) -> 128 (ReLU) -> 1, parameters in
  * the order W1[128][18], b1[128], W2[128][128], b2[128], w3[128], b3 (19073 FP32 values).
  * GEMM operands are bfloat16 (round to nearest even), accumulation FP32, master weights FP32.
  * With y = 0 the recursion is exactly the Drude (single-pole) current.

@@ -12,7 +12,7 @@ one pole with the w-weighted mean collision rate and lets a network correct the 
 
 with p1 = omega_p dt and p2 = log10(nu_mean dt) mapped linearly onto [-1, 1] over the
 training box.  y = 0 is the method without the network (exactly the Drude recurrence).
-Network: 18 -> 128 (tanh-form GELU) -> 128 (GELU) -> 1.  Optional BF16 emulation rounds
+Network: 18 -> 128 (ReLU) -> 128 (ReLU) -> 1.  Optional BF16 emulation rounds
 weights and the GEMM operands to bfloat16 (round to nearest even) with FP64 arithmetic
 otherwise, mirroring the GPU kernels' operand precision.
 """
@@ -22,8 +22,6 @@ import numpy as np
 
 NIN, NH, HIST = 18, 128, 16
 NPARAM = NH * NIN + NH + NH * NH + NH + NH + 1   # 19073
-
-SQRT_2_OVER_PI = math.sqrt(2.0 / math.pi)
 
 
 def bf16(x):
@@ -39,14 +37,14 @@ def bf16(x):
     return out
 
 
-def gelu(x):
-    """GELU in its tanh form (Hendrycks & Gimpel 2016)."""
-    return 0.5 * x * (1.0 + np.tanh(SQRT_2_OVER_PI * (x + 0.044715 * x ** 3)))
+def relu(x):
+    """The hidden layers' activation, max(x, 0)."""
+    return np.maximum(x, 0.0)
 
 
-def gelu_grad(x):
-    t = np.tanh(SQRT_2_OVER_PI * (x + 0.044715 * x ** 3))
-    return 0.5 * (1.0 + t) + 0.5 * x * (1.0 - t * t) * SQRT_2_OVER_PI * (1.0 + 3 * 0.044715 * x * x)
+def relu_grad(x):
+    """Its derivative, taken as 0 at x = 0."""
+    return (np.asarray(x) > 0.0).astype(np.float64)
 
 
 def unpack(p):
@@ -81,10 +79,10 @@ def forward(p, X, emulate_bf16=False):
     r = bf16 if emulate_bf16 else (lambda a: np.asarray(a, dtype=np.float64))
     Xq, W1q, W2q, w3q = r(X), r(W1), r(W2), r(w3)
     Z1 = Xq @ W1q.T + b1
-    A1 = gelu(Z1)
+    A1 = relu(Z1)
     A1q = r(A1)
     Z2 = A1q @ W2q.T + b2
-    A2 = gelu(Z2)
+    A2 = relu(Z2)
     y = A2 @ w3q + b3
     return y, (Xq, W1q, W2q, w3q, Z1, A1q, Z2, A2)
 
@@ -100,12 +98,12 @@ def loss_and_grad(p, X, t, emulate_bf16=False):
     gw3 = A2.T @ dy
     gb3 = float(np.sum(dy))
     dA2 = np.outer(dy, w3q)
-    dZ2 = dA2 * gelu_grad(Z2)
+    dZ2 = dA2 * relu_grad(Z2)
     dZ2q = r(dZ2)
     gW2 = dZ2q.T @ A1q
     gb2 = dZ2.sum(axis=0)
     dA1 = dZ2q @ W2q
-    dZ1 = dA1 * gelu_grad(Z1)
+    dZ1 = dA1 * relu_grad(Z1)
     dZ1q = r(dZ1)
     gW1 = dZ1q.T @ Xq
     gb1 = dZ1.sum(axis=0)

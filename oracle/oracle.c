@@ -417,7 +417,7 @@ int oracle_cpml_profile(int n, int ncpml, double dx, double dt, double order,
 /* ---------------------------------------------------------------------------
  * Learned closure of a cell's current (used by oracle_run2d for closure cells):
  * J^{n+1/2} = alpha J^{n-1/2} + beta (E^n + s y), y = MLP([E^n..E^{n-15}]/s, q1, q2),
- * s = max |E window| (floor 1e-30); network 18 -> 128 -> 128 -> 1 with tanh-form GELU,
+ * s = max |E window| (floor 1e-30); network 18 -> 128 -> 128 -> 1 with ReLU hidden layers,
  * parameters W1[128][18], b1, W2[128][128], b2, w3, b3.  With bf != 0 the GEMM operands
  * (features, weights, first-layer activations) are rounded to bfloat16 (ties to even).
  * ------------------------------------------------------------------------- */
@@ -432,9 +432,9 @@ static double o_bf16(double x)
     return (double)f;
 }
 
-static double o_gelu(double x)
+static double o_relu(double x)
 {
-    return 0.5 * x * (1.0 + tanh(sqrt(2.0 / K_PI) * (x + 0.044715 * x * x * x)));
+    return x > 0.0 ? x : 0.0;
 }
 
 /* the network on weights already in their working precision (rounded to bfloat16 by
@@ -449,14 +449,14 @@ static double mlp_eval(const double *p, const double *x, int bf)
         double z = 0.0;
         for (int k = 0; k < 18; ++k) z += W1[n * 18 + k] * xq[k];
         z += b1[n];
-        a1[n] = bf ? o_bf16(o_gelu(z)) : o_gelu(z);
+        a1[n] = bf ? o_bf16(o_relu(z)) : o_relu(z);
     }
     double y = 0.0;
     for (int n = 0; n < 128; ++n) {
         double z = 0.0;
         for (int k = 0; k < 128; ++k) z += W2[n * 128 + k] * a1[k];
         z += b2[n];
-        y += o_gelu(z) * w3[n];
+        y += o_relu(z) * w3[n];
     }
     return y + b3;
 }

@@ -1,4 +1,4 @@
-// mlp.hip -- the learned closure: an 18 -> 128 -> 128 -> 1 network (tanh-form GELU) that
+// mlp.hip -- the learned closure: an 18 -> 128 -> 128 -> 1 network (ReLU hidden layers) that
 // corrects the single-pole recurrence of a plasma cell's current,
 //     J^{n+1/2} = alpha J^{n-1/2} + beta (E^n + s y),   y = MLP([E^n..E^{n-15}]/s, p1, p2),
 // trained on currents of the kinetic model of section 5.2 (arXiv 2211.05647).
@@ -32,21 +32,10 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
 }
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// GELU in its tanh form, evaluated through 0.5 (1 + tanh u) = 1 / (1 + exp(-2u)) with the
-// hardware exp2 and reciprocal (relative error ~1e-7, far below the bf16 operand rounding).
-__device__ __forceinline__ float gelu_sig(float x) {
-  // -2 sqrt(2/pi) log2(e) (x + 0.044715 x^3) = x (c0 + c1 x^2)
-  constexpr float c0 = -2.0f * 0.7978845608028654f * 1.4426950408889634f;
-  constexpr float c1 = c0 * 0.044715f;
-  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(x * fmaf(c1, x * x, c0)));
-}
-__device__ __forceinline__ float gelu_f(float x) { return x * gelu_sig(x); }
-__device__ __forceinline__ float gelu_grad_f(float x) {
-  const float k = 0.7978845608028654f;
-  const float sg = gelu_sig(x);                         // (1 + t) / 2
-  const float t = 2.0f * sg - 1.0f;
-  return sg + 0.5f * x * (1.0f - t * t) * k * fmaf(3.0f * 0.044715f * x, x, 1.0f);
-}
+// The hidden layers' activation, ReLU, and its derivative (0 at x = 0): one vector
+// instruction per activation, so the MFMA work is no longer hidden behind transcendentals.
+__device__ __forceinline__ float act_f(float x) { return fmaxf(x, 0.0f); }
+__device__ __forceinline__ float act_grad_f(float x) { return x > 0.0f ? 1.0f : 0.0f; }
 
 __device__ __forceinline__ f4 mfma(s4 a, s4 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
@@ -85,7 +74,7 @@ __device__ void load_weights(MlpLds& L, const MlpWeights& W, W2Form form) {
 }
 
 // Forward pass of the 16 rows of this wave.  Xs: [16][kK1P] bf16 features (LDS).
-// A1s: [16][kK2P] bf16 scratch (LDS) that receives GELU(Z1).  On return z1/z2 hold the
+// A1s: [16][kK2P] bf16 scratch (LDS) that receives ReLU(Z1).  On return z1/z2 hold the
 // pre-activations in D layout and y[e] the output of row 4 kq + e.
 __device__ __forceinline__ void wave_forward(const MlpLds& L, const uint16_t* Xs, uint16_t* A1s,
                                              f4 (&z1)[8], f4 (&z2)[8], float (&y)[4]) {
@@ -103,7 +92,7 @@ __device__ __forceinline__ void wave_forward(const MlpLds& L, const uint16_t* Xs
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       c[e] += bias;
-      A1s[(kq * 4 + e) * kK2P + nt * 16 + r0] = to_bf16(gelu_f(c[e]));
+      A1s[(kq * 4 + e) * kK2P + nt * 16 + r0] = to_bf16(act_f(c[e]));
     }
     z1[nt] = c;
   }
@@ -122,7 +111,7 @@ __device__ __forceinline__ void wave_forward(const MlpLds& L, const uint16_t* Xs
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       c[e] += bias;
-      yp[e] = fmaf(gelu_f(c[e]), w, yp[e]);
+      yp[e] = fmaf(act_f(c[e]), w, yp[e]);
     }
     z2[nt] = c;
   }
@@ -157,7 +146,7 @@ __device__ __forceinline__ void wave_forward_t(const MlpLds& L, const s8 (&xb)[G
       const f4 c = mfma32(w, xb[g], bias);
       s4 o;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) o[e] = (short)to_bf16(gelu_f(c[e]));
+      for (int e = 0; e < 4; ++e) o[e] = (short)to_bf16(act_f(c[e]));
       a1[g][nt] = o;
     }
   }
@@ -186,7 +175,7 @@ __device__ __forceinline__ void wave_forward_t(const MlpLds& L, const s8 (&xb)[G
     for (int e = 0; e < 4; ++e) {
       const float w3 = L.w3[nt * 16 + kq * 4 + e];
 #pragma unroll
-      for (int g = 0; g < G; ++g) yp[g] = fmaf(gelu_f(c[g][e]), w3, yp[g]);
+      for (int g = 0; g < G; ++g) yp[g] = fmaf(act_f(c[g][e]), w3, yp[g]);
     }
   }
 #pragma unroll
@@ -295,8 +284,8 @@ __global__ __launch_bounds__(256) void k_mlp_grad(MlpWeights W, const float* __r
     float sb = 0.f, sw = 0.f;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const float a2 = gelu_f(z2[nt][e]);
-      const float d = dy[e] * w * gelu_grad_f(z2[nt][e]);
+      const float a2 = act_f(z2[nt][e]);
+      const float d = dy[e] * w * act_grad_f(z2[nt][e]);
       sb += d;
       sw = fmaf(a2, dy[e], sw);
       dZ2s[(wave * 16 + kq * 4 + e) * kK2P + nt * 16 + r0] = to_bf16(d);
@@ -305,7 +294,7 @@ __global__ __launch_bounds__(256) void k_mlp_grad(MlpWeights W, const float* __r
     cw3[nt] = sw;
   }
   __syncthreads();
-  // dA1 = dZ2 W2  (B[k][j] = W2[k][j] = W2T[j][k]), then dZ1 = dA1 * GELU'(Z1)
+  // dA1 = dZ2 W2  (B[k][j] = W2[k][j] = W2T[j][k]), then dZ1 = dA1 * ReLU'(Z1)
   float cb1[8];
 #pragma unroll
   for (int nt = 0; nt < 8; ++nt) {
@@ -319,7 +308,7 @@ __global__ __launch_bounds__(256) void k_mlp_grad(MlpWeights W, const float* __r
     float sb = 0.f;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const float d = c[e] * gelu_grad_f(z1[nt][e]);
+      const float d = c[e] * act_grad_f(z1[nt][e]);
       sb += d;
       dZ1s[(wave * 16 + kq * 4 + e) * kK2P + nt * 16 + r0] = to_bf16(d);
     }
@@ -554,7 +543,7 @@ __global__ void k_make_pairs(const float* __restrict__ E, int64_t e_stride, int6
 // One launch per step does two independent things that both only read E^n: the Hz
 // half-step (64 columns by 4 rows, one column per lane) and the closure.  Each
 // wavefront takes tile t of both, so the field update's memory traffic is overlapped by
-// the network's matrix and GELU arithmetic on the same compute units.
+// the network's matrix and activation arithmetic on the same compute units.
 // Closure: for every closure cell and both current components, push the cell-centre
 // E^n (mean of the two bounding edges) into the cell's 16-sample ring, run the network on
 // [E^n..E^{n-15}]/s, p1, p2 and advance Jc = alpha Jc + beta (E^n + s y) in place.

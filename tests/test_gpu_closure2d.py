@@ -167,11 +167,9 @@ def test_trained_network_gains_on_held_out_runs(gpu_lib, trained):
 
 def test_surrogate_slab_transmission(gpu_lib, trained):
     """Slab |T| of the surrogate (network + single pole) within 1e-2 of the kinetic model at
-    two collision rates inside the training box.  At nu/w = 0.4 the network must also be
-    closer to the kinetic |T| than the single pole alone (y = 0).  At nu/w = 0.05 the
-    single pole is already close to the kinetic model (about 1e-3) and the network's
-    one-step residual (held-out MSE about 1e-4) adds more than it removes there: that case
-    is held to the 1e-2 bar only, and its margin over y = 0 is reported, not asserted."""
+    two collision rates inside the training box, and closer to the kinetic |T| than the
+    single pole alone (y = 0, the method without the network) at both.  The single pole is
+    already close at nu/w = 0.05 (about 1e-3), so that case asks for the smaller margin."""
     data, c, params, _ = trained
     blob = CL.make_blob(params, data.box, data.dt)
     zero_blob = CL.make_blob(np.zeros(B.NPARAM, dtype=np.float32), data.box, data.dt)
@@ -182,5 +180,4 @@ def test_surrogate_slab_transmission(gpu_lib, trained):
         em, ez = np.max(np.abs(Tm - Tk)), np.max(np.abs(Tz - Tk))
         _banner(f"slab nu/w={nu_ratio}: max ||T| - |T_kin||: network {em:.2e}, no network {ez:.2e}")
         assert em <= 1e-2
-        if nu_ratio >= 0.4:
-            assert em < ez, "the network should beat the single pole at nu/w = 0.4"
+        assert em < ez, f"the network should beat the single pole at nu/w = {nu_ratio}"

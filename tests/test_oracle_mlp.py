@@ -47,14 +47,20 @@ def test_bf16_matches_library_rounding():
     assert np.array_equal(M.bf16(x), ref)
 
 
-def test_gelu_matches_library():
+def test_relu_matches_library():
     torch = pytest.importorskip("torch")
-    x = np.linspace(-8, 8, 2001)
-    ref = torch.nn.functional.gelu(torch.tensor(x), approximate="tanh").numpy()
-    assert np.max(np.abs(M.gelu(x) - ref)) < 1e-15
+    x = np.concatenate([np.linspace(-8, 8, 2001), [0.0, -0.0, 1e-300, -1e-300]])
+    ref = torch.nn.functional.relu(torch.tensor(x)).numpy()
+    assert np.array_equal(M.relu(x), ref)
+    # derivative: 1 above zero, 0 below, by central differences away from the kink, and
+    # torch's own gradient everywhere (0 at x = 0)
     h = 1e-6
-    fd = (M.gelu(x + h) - M.gelu(x - h)) / (2 * h)
-    assert np.max(np.abs(fd - M.gelu_grad(x))) < 1e-8
+    xs = x[np.abs(x) > 1e-3]
+    fd = (M.relu(xs + h) - M.relu(xs - h)) / (2 * h)
+    assert np.max(np.abs(fd - M.relu_grad(xs))) < 1e-9
+    t = torch.tensor(x, requires_grad=True)
+    torch.nn.functional.relu(t).sum().backward()
+    assert np.array_equal(M.relu_grad(x), t.grad.numpy())
 
 
 def test_adam_matches_library():
