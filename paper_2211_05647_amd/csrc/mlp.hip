@@ -201,7 +201,11 @@ __device__ __forceinline__ s8 pack8(const float (&v)[8]) {
 }
 
 // --- inference on rows in global memory ----------------------------------------------
-constexpr int kInferWaves = 8;   // wavefronts per inference work-group (weights shared in LDS)
+// Wavefronts per inference work-group: all of them share one LDS copy of the bf16 weights
+// (47 KB).  Sixteen let two work-groups fill a compute unit's 32 wavefront slots within
+// its LDS, which the closure kernel, bound by the latency of each wavefront's chain of
+// gathers and matrix layers, needs (at 64 VGPRs: 8 wavefronts per SIMD).
+constexpr int kInferWaves = 16;
 constexpr int kInferG = 1;       // 16-row groups per wavefront
 constexpr int kWaveRows = 16 * kInferG;   // rows of one wavefront tile
 
@@ -550,7 +554,7 @@ __global__ void k_make_pairs(const float* __restrict__ E, int64_t e_stride, int6
 // Each wavefront takes tiles of 16 kInferG rows (8 kInferG cells x 2 components); the four lanes
 // (kq = 0..3) of row r0 stage history samples 4 kq .. 4 kq + 3 of that row, which is the
 // B-operand layout of the transposed first layer, so features go straight to registers.
-__global__ __launch_bounds__(kInferWaves * 64) void k_mlp2d(const Run2D<float>* __restrict__ rp,
+__global__ __launch_bounds__(kInferWaves * 64) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_mlp2d(const Run2D<float>* __restrict__ rp,
                                                            MlpWeights W, MlpCells2D C,
                                                            int64_t step) {
   __shared__ MlpLds L;
