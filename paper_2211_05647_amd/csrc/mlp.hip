@@ -33,7 +33,8 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // The hidden layers' activation, ReLU, and its derivative (0 at x = 0): one vector
-// instruction per activation, so the MFMA work is no longer hidden behind transcendentals.
+// instruction per activation (a tanh-form GELU takes two quarter-rate transcendentals and
+// five other instructions).
 __device__ __forceinline__ float act_f(float x) { return fmaxf(x, 0.0f); }
 __device__ __forceinline__ float act_grad_f(float x) { return x > 0.0f ? 1.0f : 0.0f; }
 
@@ -554,9 +555,8 @@ __global__ void k_make_pairs(const float* __restrict__ E, int64_t e_stride, int6
 // Each wavefront takes tiles of 16 kInferG rows (8 kInferG cells x 2 components); the four lanes
 // (kq = 0..3) of row r0 stage history samples 4 kq .. 4 kq + 3 of that row, which is the
 // B-operand layout of the transposed first layer, so features go straight to registers.
-__global__ __launch_bounds__(kInferWaves * 64) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_mlp2d(const Run2D<float>* __restrict__ rp,
-                                                           MlpWeights W, MlpCells2D C,
-                                                           int64_t step) {
+__global__ __launch_bounds__(kInferWaves * 64) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void k_mlp2d(const Run2D<float>* __restrict__ rp, MlpWeights W, MlpCells2D C, int64_t step) {
   __shared__ MlpLds L;
   load_weights(L, W, W2Form::kPermuted);
   __syncthreads();
