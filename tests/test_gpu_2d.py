@@ -126,3 +126,44 @@ def test_2d_resume_bitwise(gpu_lib):
     c.run(150)
     for f in (B.F_EX, B.F_EY, B.F_HZ, B.F_JX, B.F_DF):
         assert np.array_equal(a.read(f), c.read(f))
+
+
+def test_large_grid_fp32_parity(gpu_lib):
+    """A grid large enough for the field updates' four-rows-per-thread form (the FP32 path
+    of the large workloads): 2048 x 2050 cells with the CPML on every side, a plasma blob
+    and a point source, for 300 steps.  Ex and Ey over space and time, Hz at the end, and
+    probes next to the source, next to the PEC edges and inside the absorbing strips,
+    against the FP64 oracle."""
+    nx, ny = 2048, 2050
+    jj, ii = np.mgrid[0:ny, 0:nx]
+    blob = (ii + 0.5 - 150) ** 2 + (jj + 0.5 - 1030) ** 2 < 20 ** 2
+    ne = np.where(blob, W.density_from_ratio(1.2, W.F_REF), 0.0)
+    nu = np.where(blob, 0.1 * 2 * math.pi * W.F_REF, 0.0)
+    run = W.Run2D(name="large", nx=nx, ny=ny, nv=8, ne=ne, nubar=nu, src_kind=2,
+                  src_i=61, src_j=1025, steps=300, ncpml=8, **W.pulse(W.F_REF))
+    steps = 300
+    where = [(B.F_EY, 60, 1025), (B.F_EY, 61, 1020), (B.F_EY, 62, 1030), (B.F_EY, 63, 1025),
+             (B.F_EY, 1, 1025), (B.F_EY, nx - 1, 1025), (B.F_EY, 4, 900), (B.F_EX, 0, 1025),
+             (B.F_EX, nx - 1, 1025), (B.F_EX, 150, 1030)]
+    _banner(f"large grid fp32 {nx}x{ny}")
+    sim = B.Sim(run, precision=B.FP32, max_probes=len(where), probe_capacity=steps)
+    pids = [sim.add_probe(f, i, j) for f, i, j in where]
+    orc = oracle_2d(run)
+    opts = [(i, j) for f, i, j in where]
+    g, o, oprobe = [], [], []
+    done = 0
+    while done < steps:
+        sim.run(100)
+        done += 100
+        # the oracle's probes record Ey; Ex probes are compared through the snapshots
+        oprobe.append(orc.run(100, probes=opts))
+        g.append(np.concatenate([sim.read(B.F_EX), sim.read(B.F_EY)]))
+        o.append(np.concatenate([orc.Ex.ravel(), orc.Ey.ravel()]))
+    err = rel_l2(np.array(g), np.array(o))
+    gp = np.stack([sim.read_probe(p, steps) for p, (f, _, _) in zip(pids, where) if f == B.F_EY], axis=1)
+    op = np.concatenate(oprobe)[:, [k for k, (f, _, _) in enumerate(where) if f == B.F_EY]]
+    perr = rel_l2(gp, op)
+    _banner(f"large grid: Ex, Ey space-time rel L2 {err:.3e}, Ey probes {perr:.3e}")
+    assert err <= 1e-5 and perr <= 1e-5
+    assert rel_l2(sim.read(B.F_HZ), orc.Hz.ravel()) <= 1e-5
+    assert np.max(np.abs(sim.read(B.F_DF))) > 0.0
