@@ -651,7 +651,18 @@ hipError_t mlp_launch_cells2d(const void* run, const MlpWeights& W, const MlpCel
   const int tiles_m = (2 * C.n + kWaveRows - 1) / kWaveRows;
   const int tiles_h = ((nx + 63) / 64) * ((ny + 3) / 4);
   const int tiles = tiles_m > tiles_h ? tiles_m : tiles_h;
-  const int blocks = (tiles + kInferWaves - 1) / kInferWaves < 1024 ? (tiles + kInferWaves - 1) / kInferWaves : 1024;
+  // one work-group per resident slot (compute units x work-groups each holds): every
+  // wavefront then takes its share of the tiles in one round
+  static const int resident = [] {
+    int dev = 0, cus = 256, per = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_mlp2d, kInferWaves * 64, 0) != hipSuccess)
+      per = 1;
+    return cus * (per > 0 ? per : 1);
+  }();
+  const int need = (tiles + kInferWaves - 1) / kInferWaves;
+  const int blocks = need < resident ? need : resident;
   hipLaunchKernelGGL(k_mlp2d, dim3(blocks), dim3(kInferWaves * 64), 0, st,
                      static_cast<const Run2D<float>*>(run), W, C, step);
   return hipGetLastError();
