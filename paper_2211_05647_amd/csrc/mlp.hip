@@ -34,8 +34,14 @@ __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float(
 
 // The hidden layers' activation, ReLU, and its derivative (0 at x = 0): one vector
 // instruction per activation (a tanh-form GELU takes two quarter-rate transcendentals and
-// five other instructions).
-__device__ __forceinline__ float act_f(float x) { return fmaxf(x, 0.0f); }
+// five other instructions).  ReLU is a signed-integer max of the bit pattern with 0: a
+// negative float (-0 included) is a negative integer and becomes +0, a positive one keeps
+// its bits -- max(x, 0) for every non-NaN x, without the input canonicalisation a float
+// max adds in IEEE mode.
+__device__ __forceinline__ float act_f(float x) {
+  const int b = __float_as_int(x);
+  return __int_as_float(b > 0 ? b : 0);
+}
 __device__ __forceinline__ float act_grad_f(float x) { return x > 0.0f ? 1.0f : 0.0f; }
 
 __device__ __forceinline__ f4 mfma(s4 a, s4 b, f4 c) {
